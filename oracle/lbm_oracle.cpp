@@ -1,0 +1,536 @@
+// FP64 CPU oracle for the immersed-boundary lattice Boltzmann step.
+//
+// TEST INFRASTRUCTURE ONLY. Only the test suite, the smoke check and the
+// benchmark's CPU-baseline leg may load this library. The product path (the
+// HIP library and its Python binding) never calls, links or imports it, and
+// it shares no code, header or table with that path.
+//
+// What is computed (paper: Sec. III-A robot model, Sec. III-B "GPU-accelerated
+// localized fluid-structure interaction", Eq. (2) and Eq. (3)):
+//   * a D3Q27 lattice Boltzmann approximation of the Navier-Stokes equations
+//     of Eq. (2), BGK collision with relaxation time tau,
+//   * the fictitious body force of an accelerating, rotating frame, Eq. (3),
+//     added to the collision by Guo's forcing scheme,
+//   * open x faces by non-equilibrium extrapolation (Sec. III-B, Simulation:
+//     the domain boundary treatment taken from Zhao-Li 2002),
+//   * the immersed surface as uniformly sampled Lagrangian markers (Sec. III-B,
+//     Simulation), coupled two-way by the immersed boundary method: velocity
+//     interpolation with Peskin's 4-point smoothed delta kernel, explicit
+//     direct forcing, force spreading with the same kernel,
+//   * marker positions and velocities by linear blend skinning of bone
+//     transforms (Sec. III-A),
+//   * the fluid's force, torque and power on the body (the external
+//     generalized force of Eq. (1)).
+// The paper gives no lattice, collision, forcing or delta-kernel details; the
+// readings used here are the ones listed in the design notes of the
+// repository, and the header comments of each function say which it takes.
+//
+// Everything is double precision and deliberately plain: each stage of a step
+// is its own pass over the grid or the markers, in the order
+//   skin -> moments and unforced velocity -> interpolate -> direct forcing
+//   (-> multi-direct-forcing passes) -> spread -> collide interior nodes ->
+//   boundary planes -> stream -> wrench.
+// Lattice sweeps are parallel over z with OpenMP; per-node arithmetic does
+// not depend on the thread count. Marker sums are sequential in marker order.
+//
+// Parity pins: see tests/test_oracle_*.py. Nothing here is "parity unpinned"
+// except the fish thrust and power series, which have no closed form.
+
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+namespace {
+
+// ---------------------------------------------------------------- lattice --
+// D3Q27: velocities c_i in {-1,0,1}^3, index i = (cx+1) + 3(cy+1) + 9(cz+1).
+// Weights by |c|^2: 8/27, 2/27, 1/54, 1/216; sound speed squared 1/3.
+struct D3Q27 {
+  int c[27][3];
+  double w[27];
+  D3Q27() {
+    for (int i = 0; i < 27; ++i) {
+      c[i][0] = i % 3 - 1;
+      c[i][1] = (i / 3) % 3 - 1;
+      c[i][2] = i / 9 - 1;
+      int s = c[i][0] * c[i][0] + c[i][1] * c[i][1] + c[i][2] * c[i][2];
+      w[i] = (s == 0) ? 8.0 / 27.0 : (s == 1) ? 2.0 / 27.0 : (s == 2) ? 1.0 / 54.0 : 1.0 / 216.0;
+    }
+  }
+};
+const D3Q27 L;
+
+// Second-order equilibrium f^eq_i = w_i rho [1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u].
+void equilibrium(double rho, const double u[3], double feq[27]) {
+  double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  for (int i = 0; i < 27; ++i) {
+    double cu = L.c[i][0] * u[0] + L.c[i][1] * u[1] + L.c[i][2] * u[2];
+    feq[i] = L.w[i] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+  }
+}
+
+void cross(const double a[3], const double b[3], double out[3]) {
+  out[0] = a[1] * b[2] - a[2] * b[1];
+  out[1] = a[2] * b[0] - a[0] * b[2];
+  out[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+}  // namespace
+
+extern "C" {
+
+// ------------------------------------------------------------ C structs ----
+// Boundary codes for the two x faces. y and z are always periodic.
+enum { OR_BC_PERIODIC = 0, OR_BC_VELOCITY = 1, OR_BC_OUTFLOW = 2 };
+
+struct OrParams {
+  int32_t nx, ny, nz;
+  int32_t bc_lo, bc_hi;  // x = 0 and x = nx-1; both periodic or both open
+  int32_t mdf_iters;     // >= 1; 1 is plain explicit direct forcing
+  double tau;
+  double ib_alpha;       // direct-forcing gain
+};
+
+// Frame of reference for one step (Eq. (3)): linear acceleration of the
+// frame origin (p-double-dot), angular velocity (r-dot) and angular
+// acceleration (r-double-dot) as vectors in frame coordinates, the origin x0
+// about which x' = x - x0 is measured, and the prescribed velocity on each
+// open x face that carries a velocity condition.
+struct OrFrame {
+  double acc[3];
+  double omega[3];
+  double alpha[3];
+  double origin[3];
+  double u_lo[3];
+  double u_hi[3];
+};
+
+// Skinned marker set. Each marker follows two bones with linear blend
+// weights (Sec. III-A: linear blend skinning). Arrays are structure-of-arrays.
+struct OrMarkers {
+  int32_t n;
+  int32_t nbones;
+  const double *xrest;   // [3][n] rest-pose positions, lattice units
+  const int32_t *bone;   // [2][n]
+  const double *weight;  // [2][n]
+  const double *dv;      // [n]  marker volume (surface area share x 1 cell)
+};
+
+int or_abi_version(void) { return 1; }
+
+void or_lattice(int32_t *c, double *w) {
+  for (int i = 0; i < 27; ++i) {
+    for (int a = 0; a < 3; ++a) c[3 * i + a] = L.c[i][a];
+    w[i] = L.w[i];
+  }
+}
+
+void or_equilibrium(double rho, const double *u, double *feq) { equilibrium(rho, u, feq); }
+
+// Equilibrium populations of a whole field: rho [n], u [3][n] -> f [27][n].
+void or_equilibrium_field(const double *rho, const double *u, int64_t n, double *f) {
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k < n; ++k) {
+    double uk[3] = {u[k], u[n + k], u[2 * n + k]}, feq[27];
+    equilibrium(rho[k], uk, feq);
+    for (int i = 0; i < 27; ++i) f[i * n + k] = feq[i];
+  }
+}
+
+// Peskin's 4-point smoothed delta function (one axis). C^1, with discrete
+// partition of unity, zero first moment and sum of squares 3/8.
+double or_phi(double r) {
+  double a = std::fabs(r);
+  if (a <= 1.0) return (3.0 - 2.0 * a + std::sqrt(1.0 + 4.0 * a - 4.0 * a * a)) / 8.0;
+  if (a <= 2.0) return (5.0 - 2.0 * a - std::sqrt(-7.0 + 12.0 * a - 4.0 * a * a)) / 8.0;
+  return 0.0;
+}
+
+// Eq. (3) frame force per unit mass without its velocity-dependent Coriolis
+// part: a0(x) = -acc - alpha x x' - omega x (omega x x'), with x' = x - x0.
+void or_frame_accel_static(const OrFrame *fr, const double *x, double *a0) {
+  double xp[3] = {x[0] - fr->origin[0], x[1] - fr->origin[1], x[2] - fr->origin[2]};
+  double ax[3], wx[3], wwx[3];
+  cross(fr->alpha, xp, ax);
+  cross(fr->omega, xp, wx);
+  cross(fr->omega, wx, wwx);
+  for (int a = 0; a < 3; ++a) a0[a] = -fr->acc[a] - ax[a] - wwx[a];
+}
+
+// Fluid velocity at a node. With Guo forcing the velocity is
+//   u = (m + F/2) / rho,  F = g + rho * a_ni(x, u),
+// and a_ni (Eq. (3)) contains the Coriolis term -2 omega x u, so u is defined
+// implicitly. Writing b = m/rho + g/(2 rho) + a0/2 the definition reads
+// u + omega x u = b, a 3x3 linear system whose exact solution is
+//   u = (b - omega x b + (omega.b) omega) / (1 + |omega|^2).
+// Returns u and the total force density F used by the collision.
+void or_node_velocity(double rho, const double *m, const double *g, const OrFrame *fr,
+                      const double *x, double *u, double *F) {
+  double a0[3];
+  or_frame_accel_static(fr, x, a0);
+  double b[3];
+  for (int a = 0; a < 3; ++a) b[a] = m[a] / rho + g[a] / (2.0 * rho) + 0.5 * a0[a];
+  double wb[3];
+  cross(fr->omega, b, wb);
+  double wdotb = fr->omega[0] * b[0] + fr->omega[1] * b[1] + fr->omega[2] * b[2];
+  double w2 = fr->omega[0] * fr->omega[0] + fr->omega[1] * fr->omega[1] + fr->omega[2] * fr->omega[2];
+  for (int a = 0; a < 3; ++a) u[a] = (b[a] - wb[a] + wdotb * fr->omega[a]) / (1.0 + w2);
+  double wu[3];
+  cross(fr->omega, u, wu);
+  for (int a = 0; a < 3; ++a) F[a] = g[a] + rho * (a0[a] - 2.0 * wu[a]);
+}
+
+// BGK collision with Guo's forcing term at one node:
+//   f*_i = f_i - (f_i - f^eq_i(rho,u)) / tau
+//          + (1 - 1/(2 tau)) w_i [3 (c_i - u) + 9 (c_i.u) c_i] . F.
+void or_collide_node(const double *f, const double *g, const OrFrame *fr, const double *x, double tau,
+                     double *fout, double *u_out, double *F_out) {
+  double rho = 0.0, m[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < 27; ++i) {
+    rho += f[i];
+    for (int a = 0; a < 3; ++a) m[a] += f[i] * L.c[i][a];
+  }
+  double u[3], F[3];
+  or_node_velocity(rho, m, g, fr, x, u, F);
+  double feq[27];
+  equilibrium(rho, u, feq);
+  double pref = 1.0 - 1.0 / (2.0 * tau);
+  for (int i = 0; i < 27; ++i) {
+    double cu = L.c[i][0] * u[0] + L.c[i][1] * u[1] + L.c[i][2] * u[2];
+    double s = 0.0;
+    for (int a = 0; a < 3; ++a) s += (3.0 * (L.c[i][a] - u[a]) + 9.0 * cu * L.c[i][a]) * F[a];
+    fout[i] = f[i] - (f[i] - feq[i]) / tau + pref * L.w[i] * s;
+  }
+  if (u_out)
+    for (int a = 0; a < 3; ++a) u_out[a] = u[a];
+  if (F_out)
+    for (int a = 0; a < 3; ++a) F_out[a] = F[a];
+}
+
+// Linear blend skinning (Sec. III-A): X = sum_b w_b (R_b xrest + t_b) and
+// U = sum_b w_b (Rdot_b xrest + tdot_b). A bone pose is 24 numbers: R (3x3,
+// row-major), t (3), Rdot (3x3, row-major), tdot (3).
+void or_skin(const OrMarkers *mk, const double *poses, double *X, double *U) {
+  const int n = mk->n;
+  for (int k = 0; k < n; ++k) {
+    double xr[3] = {mk->xrest[k], mk->xrest[n + k], mk->xrest[2 * n + k]};
+    double x[3] = {0, 0, 0}, v[3] = {0, 0, 0};
+    for (int j = 0; j < 2; ++j) {
+      int b = mk->bone[j * n + k];
+      double wgt = mk->weight[j * n + k];
+      const double *P = poses + 24 * b;
+      for (int a = 0; a < 3; ++a) {
+        double px = P[3 * a] * xr[0] + P[3 * a + 1] * xr[1] + P[3 * a + 2] * xr[2] + P[9 + a];
+        double pv = P[12 + 3 * a] * xr[0] + P[12 + 3 * a + 1] * xr[1] + P[12 + 3 * a + 2] * xr[2] + P[21 + a];
+        x[a] += wgt * px;
+        v[a] += wgt * pv;
+      }
+    }
+    for (int a = 0; a < 3; ++a) {
+      X[a * n + k] = x[a];
+      U[a * n + k] = v[a];
+    }
+  }
+}
+
+}  // extern "C"
+
+namespace {
+
+inline int wrap(int i, int n) { return ((i % n) + n) % n; }
+
+struct Grid {
+  int nx, ny, nz;
+  bool xper;
+  size_t ncell() const { return (size_t)nx * ny * nz; }
+  size_t idx(int x, int y, int z) const { return (size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * z); }
+};
+
+// The 4x4x4 stencil of a marker: nodes floor(X)-1 .. floor(X)+2 per axis,
+// indices wrapped on periodic axes. Returns false if a node falls outside a
+// non-periodic axis (the caller rejects such markers beforehand).
+bool stencil(const Grid &G, const double X[3], int nodes[3][4], double wts[3][4]) {
+  int n[3] = {G.nx, G.ny, G.nz};
+  bool per[3] = {G.xper, true, true};
+  for (int a = 0; a < 3; ++a) {
+    int base = (int)std::floor(X[a]) - 1;
+    for (int s = 0; s < 4; ++s) {
+      int j = base + s;
+      wts[a][s] = or_phi(X[a] - (double)j);
+      if (per[a]) {
+        j = wrap(j, n[a]);
+      } else if (j < 0 || j >= n[a]) {
+        return false;
+      }
+      nodes[a][s] = j;
+    }
+  }
+  return true;
+}
+
+// U_k = sum over the stencil of field(x) delta_h(x - X_k), delta_h the
+// tensor product of phi. field is [ncomp][cells].
+void interpolate(const Grid &G, const double *field, int ncomp, const double *X, int n, double *out) {
+  for (int k = 0; k < n; ++k) {
+    double Xk[3] = {X[k], X[n + k], X[2 * n + k]};
+    int nodes[3][4];
+    double w[3][4];
+    stencil(G, Xk, nodes, w);
+    for (int c = 0; c < ncomp; ++c) out[c * n + k] = 0.0;
+    for (int sz = 0; sz < 4; ++sz)
+      for (int sy = 0; sy < 4; ++sy)
+        for (int sx = 0; sx < 4; ++sx) {
+          double d = w[0][sx] * w[1][sy] * w[2][sz];
+          size_t id = G.idx(nodes[0][sx], nodes[1][sy], nodes[2][sz]);
+          for (int c = 0; c < ncomp; ++c) out[c * n + k] += field[c * G.ncell() + id] * d;
+        }
+  }
+}
+
+// g(x) = sum_k Fdv_k delta_h(x - X_k), with Fdv = F_k dV_k. g is [3][cells]
+// and is overwritten.
+void spread(const Grid &G, const double *X, int n, const double *Fdv, double *g) {
+  std::memset(g, 0, sizeof(double) * 3 * G.ncell());
+  for (int k = 0; k < n; ++k) {
+    double Xk[3] = {X[k], X[n + k], X[2 * n + k]};
+    int nodes[3][4];
+    double w[3][4];
+    stencil(G, Xk, nodes, w);
+    for (int sz = 0; sz < 4; ++sz)
+      for (int sy = 0; sy < 4; ++sy)
+        for (int sx = 0; sx < 4; ++sx) {
+          double d = w[0][sx] * w[1][sy] * w[2][sz];
+          size_t id = G.idx(nodes[0][sx], nodes[1][sy], nodes[2][sz]);
+          for (int c = 0; c < 3; ++c) g[c * G.ncell() + id] += Fdv[c * n + k] * d;
+        }
+  }
+}
+
+// Density, momentum and the velocity with force field g (no g: pass zeros)
+// at every node. rho is [cells], u is [3][cells].
+void node_fields(const Grid &G, const double *f, const double *g, const OrFrame *fr, double *rho, double *u) {
+  const size_t N = G.ncell();
+#pragma omp parallel for schedule(static)
+  for (int z = 0; z < G.nz; ++z)
+    for (int y = 0; y < G.ny; ++y)
+      for (int x = 0; x < G.nx; ++x) {
+        size_t id = G.idx(x, y, z);
+        double r = 0.0, m[3] = {0, 0, 0};
+        for (int i = 0; i < 27; ++i) {
+          double fi = f[i * N + id];
+          r += fi;
+          for (int a = 0; a < 3; ++a) m[a] += fi * L.c[i][a];
+        }
+        double gg[3] = {0, 0, 0};
+        if (g)
+          for (int a = 0; a < 3; ++a) gg[a] = g[a * N + id];
+        double pos[3] = {(double)x, (double)y, (double)z};
+        double uu[3], F[3];
+        or_node_velocity(r, m, gg, fr, pos, uu, F);
+        rho[id] = r;
+        for (int a = 0; a < 3; ++a) u[a * N + id] = uu[a];
+      }
+}
+
+bool is_open_plane(const Grid &G, int x) { return !G.xper && (x == 0 || x == G.nx - 1); }
+
+}  // namespace
+
+extern "C" {
+
+// Interpolation of a [ncomp][cells] field to n markers (tests).
+int or_interpolate(const OrParams *p, const double *field, int ncomp, const double *X, int n, double *out) {
+  Grid G{p->nx, p->ny, p->nz, p->bc_lo == OR_BC_PERIODIC};
+  interpolate(G, field, ncomp, X, n, out);
+  return 0;
+}
+
+// Spreading of n marker forces Fdv = F dV onto g [3][cells] (tests).
+int or_spread(const OrParams *p, const double *X, int n, const double *Fdv, double *g) {
+  Grid G{p->nx, p->ny, p->nz, p->bc_lo == OR_BC_PERIODIC};
+  spread(G, X, n, Fdv, g);
+  return 0;
+}
+
+// Density and unforced velocity u* (frame force included, immersed-boundary
+// force excluded) of the pre-collision state f. This is the velocity field
+// the step interpolates to the markers and the one reported as "the velocity".
+int or_macros(const OrParams *p, const double *f, const OrFrame *fr, double *rho, double *u) {
+  Grid G{p->nx, p->ny, p->nz, p->bc_lo == OR_BC_PERIODIC};
+  node_fields(G, f, nullptr, fr, rho, u);
+  return 0;
+}
+
+// Advance the pre-collision populations f [27][nz][ny][nx] by nsteps steps.
+//   poses  : [nsteps][nbones][24] bone poses for each step (may be null when
+//            markers is null)
+//   frames : [nsteps]
+//   wrench : [nsteps][8] or null: force (3), torque about the frame origin
+//            (3), power, thrust-free spare slot = 0
+//   X, U, F: [3][n] or null: marker positions, velocities and direct-forcing
+//            force densities of the LAST step
+// Returns 0, or -4 when a marker's stencil leaves the domain across an open
+// face, or -1 on bad arguments.
+int or_run(const OrParams *p, double *f, const OrMarkers *mk, const double *poses, const OrFrame *frames,
+           int nsteps, double *wrench, double *Xout, double *Uout, double *Fout) {
+  if (!p || !f || p->nx < 4 || p->ny < 4 || p->nz < 4 || !(p->tau > 0.5)) return -1;
+  const bool xper = p->bc_lo == OR_BC_PERIODIC;
+  if (xper != (p->bc_hi == OR_BC_PERIODIC)) return -1;
+  if (p->mdf_iters < 1) return -1;
+  Grid G{p->nx, p->ny, p->nz, xper};
+  const size_t N = G.ncell();
+  const double tau = p->tau;
+  const int nm = mk ? mk->n : 0;
+
+  std::vector<double> fpost(27 * N), rho(N), ustar(3 * N), g(3 * N, 0.0);
+  std::vector<double> X(3 * nm), U(3 * nm), Fk(3 * nm), Fdv(3 * nm), Ustar(3 * nm), rhok(nm), Uk(3 * nm);
+  std::vector<double> ufull(3 * N);
+
+  for (int step = 0; step < nsteps; ++step) {
+    const OrFrame *fr = &frames[step];
+
+    // (1) marker positions and velocities for this step
+    if (nm > 0) {
+      or_skin(mk, poses + (size_t)step * mk->nbones * 24, X.data(), U.data());
+      if (!xper)
+        for (int k = 0; k < nm; ++k)
+          if (!(X[k] >= 2.0 && X[k] < p->nx - 3.0)) return -4;
+    }
+
+    // (2) density and unforced velocity at every node
+    node_fields(G, f, nullptr, fr, rho.data(), ustar.data());
+
+    // (3)-(5) interpolation, direct forcing, spreading
+    std::fill(g.begin(), g.end(), 0.0);
+    if (nm > 0) {
+      interpolate(G, ustar.data(), 3, X.data(), nm, Ustar.data());
+      interpolate(G, rho.data(), 1, X.data(), nm, rhok.data());
+      for (int k = 0; k < nm; ++k)
+        for (int a = 0; a < 3; ++a)
+          Fk[a * nm + k] = p->ib_alpha * 2.0 * rhok[k] * (U[a * nm + k] - Ustar[a * nm + k]);
+      for (int it = 1; it < p->mdf_iters; ++it) {
+        // multi-direct forcing: spread the current force, re-interpolate the
+        // velocity that includes it, add the remaining correction
+        for (int k = 0; k < nm; ++k)
+          for (int a = 0; a < 3; ++a) Fdv[a * nm + k] = Fk[a * nm + k] * mk->dv[k];
+        spread(G, X.data(), nm, Fdv.data(), g.data());
+        node_fields(G, f, g.data(), fr, rho.data(), ufull.data());
+        interpolate(G, ufull.data(), 3, X.data(), nm, Uk.data());
+        for (int k = 0; k < nm; ++k)
+          for (int a = 0; a < 3; ++a)
+            Fk[a * nm + k] += p->ib_alpha * 2.0 * rhok[k] * (U[a * nm + k] - Uk[a * nm + k]);
+      }
+      for (int k = 0; k < nm; ++k)
+        for (int a = 0; a < 3; ++a) Fdv[a * nm + k] = Fk[a * nm + k] * mk->dv[k];
+      spread(G, X.data(), nm, Fdv.data(), g.data());
+    }
+
+    // (6) BGK + Guo collision on every node that is not an open boundary node
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < G.nz; ++z)
+      for (int y = 0; y < G.ny; ++y)
+        for (int x = 0; x < G.nx; ++x) {
+          if (is_open_plane(G, x)) continue;
+          size_t id = G.idx(x, y, z);
+          double fl[27], fo[27];
+          for (int i = 0; i < 27; ++i) fl[i] = f[i * N + id];
+          double gg[3] = {g[id], g[N + id], g[2 * N + id]};
+          double pos[3] = {(double)x, (double)y, (double)z};
+          or_collide_node(fl, gg, fr, pos, tau, fo, nullptr, nullptr);
+          for (int i = 0; i < 27; ++i) fpost[i * N + id] = fo[i];
+        }
+
+    // (7) open faces by non-equilibrium extrapolation. Boundary node x_b
+    // takes its inward neighbour x_f's density and non-equilibrium part:
+    //   f*_i(x_b) = f^eq_i(rho_f, u_b) + (1 - 1/tau) (f_i(x_f) - f^eq_i(rho_f, u_f))
+    //               + (1 - 1/(2 tau)) w_i [3 (c_i - u_b) + 9 (c_i.u_b) c_i] . F_b
+    // u_f is x_f's fluid velocity (with its force half-term, the same
+    // definition the collision uses); u_b is the prescribed velocity
+    // (velocity face) or u_f (outflow face); F_b = rho_f a_ni(x_b, u_b) is the
+    // frame force alone (markers never reach a boundary node).
+    if (!xper) {
+      for (int side = 0; side < 2; ++side) {
+        int xb = side == 0 ? 0 : G.nx - 1;
+        int xf = side == 0 ? 1 : G.nx - 2;
+        int bc = side == 0 ? p->bc_lo : p->bc_hi;
+        const double *uface = side == 0 ? fr->u_lo : fr->u_hi;
+#pragma omp parallel for schedule(static)
+        for (int z = 0; z < G.nz; ++z)
+          for (int y = 0; y < G.ny; ++y) {
+            size_t idf = G.idx(xf, y, z), idb = G.idx(xb, y, z);
+            double fl[27], r = 0.0, m[3] = {0, 0, 0};
+            for (int i = 0; i < 27; ++i) {
+              fl[i] = f[i * N + idf];
+              r += fl[i];
+              for (int a = 0; a < 3; ++a) m[a] += fl[i] * L.c[i][a];
+            }
+            double gf[3] = {g[idf], g[N + idf], g[2 * N + idf]};
+            double posf[3] = {(double)xf, (double)y, (double)z};
+            double posb[3] = {(double)xb, (double)y, (double)z};
+            double uf[3], Ff[3];
+            or_node_velocity(r, m, gf, fr, posf, uf, Ff);
+            double ub[3];
+            for (int a = 0; a < 3; ++a) ub[a] = (bc == OR_BC_VELOCITY) ? uface[a] : uf[a];
+            double a0[3], wu[3], Fb[3];
+            or_frame_accel_static(fr, posb, a0);
+            cross(fr->omega, ub, wu);
+            for (int a = 0; a < 3; ++a) Fb[a] = r * (a0[a] - 2.0 * wu[a]);
+            double feq_b[27], feq_f[27];
+            equilibrium(r, ub, feq_b);
+            equilibrium(r, uf, feq_f);
+            double pref = 1.0 - 1.0 / (2.0 * tau);
+            for (int i = 0; i < 27; ++i) {
+              double cu = L.c[i][0] * ub[0] + L.c[i][1] * ub[1] + L.c[i][2] * ub[2];
+              double s = 0.0;
+              for (int a = 0; a < 3; ++a) s += (3.0 * (L.c[i][a] - ub[a]) + 9.0 * cu * L.c[i][a]) * Fb[a];
+              fpost[i * N + idb] = feq_b[i] + (1.0 - 1.0 / tau) * (fl[i] - feq_f[i]) + pref * L.w[i] * s;
+            }
+          }
+      }
+    }
+
+    // (8) streaming: f_i(x, n+1) = f*_i(x - c_i, n). Periodic axes wrap; a
+    // source outside an open x face is replaced by the face node itself (those
+    // values are never used: extrapolation overwrites the face nodes).
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < G.nz; ++z)
+      for (int y = 0; y < G.ny; ++y)
+        for (int x = 0; x < G.nx; ++x)
+          for (int i = 0; i < 27; ++i) {
+            int sx = x - L.c[i][0], sy = wrap(y - L.c[i][1], G.ny), sz = wrap(z - L.c[i][2], G.nz);
+            if (xper)
+              sx = wrap(sx, G.nx);
+            else
+              sx = sx < 0 ? 0 : (sx >= G.nx ? G.nx - 1 : sx);
+            f[i * N + G.idx(x, y, z)] = fpost[i * N + G.idx(sx, sy, sz)];
+          }
+
+    // (9) the fluid's force, torque and power on the body: the body exerts
+    // F_k dV_k on the fluid, so the fluid exerts the opposite on the body.
+    if (wrench) {
+      double *wr = wrench + 8 * (size_t)step;
+      for (int j = 0; j < 8; ++j) wr[j] = 0.0;
+      for (int k = 0; k < nm; ++k) {
+        double Fb[3] = {-Fdv[k], -Fdv[nm + k], -Fdv[2 * nm + k]};
+        double r[3] = {X[k] - fr->origin[0], X[nm + k] - fr->origin[1], X[2 * nm + k] - fr->origin[2]};
+        double t[3];
+        cross(r, Fb, t);
+        for (int a = 0; a < 3; ++a) {
+          wr[a] += Fb[a];
+          wr[3 + a] += t[a];
+        }
+        wr[6] += Fdv[k] * U[k] + Fdv[nm + k] * U[nm + k] + Fdv[2 * nm + k] * U[2 * nm + k];
+      }
+    }
+  }
+  if (nm > 0) {
+    if (Xout) std::memcpy(Xout, X.data(), sizeof(double) * 3 * nm);
+    if (Uout) std::memcpy(Uout, U.data(), sizeof(double) * 3 * nm);
+    if (Fout) std::memcpy(Fout, Fk.data(), sizeof(double) * 3 * nm);
+  }
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,71 @@
+"""Checks of the seeded synthetic workload generators (geometry, kinematics,
+frames). They hold no method arithmetic; these tests pin their definitions."""
+import math
+
+import numpy as np
+
+from paper_2206_01683_amd import inputs as I
+
+
+def test_fibonacci_sphere_on_radius():
+    ms = I.fibonacci_sphere(500, 6.0, (20.0, 16.0, 16.0))
+    r = np.linalg.norm(ms.xrest - np.array([[20.0], [16.0], [16.0]]), axis=0)
+    np.testing.assert_allclose(r, 6.0, atol=1e-13)
+    assert abs(ms.dv[0] - 4 * math.pi * 36 / 500) < 1e-15
+    assert np.abs(ms.xrest.mean(1) - np.array([20, 16, 16])).max() < 0.05
+
+
+def test_fish_surface_geometry():
+    L = 96.0
+    ms = I.fish_surface(12000, L, (112.0, 96.0, 96.0))
+    assert ms.n == 12000
+    # area of the elliptic-section body, about 4,000 lattice units^2
+    assert 3800 < ms.area < 4300
+    assert abs(ms.dv.sum() - ms.area) < 1e-9
+    x = ms.xrest[0]
+    assert x.min() >= 112.0 and x.max() <= 112.0 + L
+    b = I.fish_half_width((x - 112.0) / L, L)
+    ell = ((ms.xrest[1] - 96) / np.maximum(b, 1e-300)) ** 2 + ((ms.xrest[2] - 96) / np.maximum(1.5 * b, 1e-300)) ** 2
+    np.testing.assert_allclose(ell[b > 1e-6], 1.0, atol=1e-9)
+    np.testing.assert_allclose(ms.weight.sum(0), 1.0, atol=1e-15)
+    assert ms.bone.min() >= 0 and ms.bone.max() <= 9
+    assert abs(I.fish_half_width(np.array([1 / 3]), L)[0] - 0.08 * L) < 1e-12
+
+
+def test_frames_velocity_is_running_sum_of_acceleration():
+    fr = I.accelerating_frames(900, 1e-5, 400.0, (0, 0, 0))
+    a = fr[:, 0]
+    np.testing.assert_allclose(a, 1e-5 * np.sin(2 * np.pi * np.arange(900) / 400))
+    V = -fr[:, 12]
+    np.testing.assert_allclose(V[1:], np.cumsum(a)[:-1], atol=1e-18)
+    assert V[0] == 0.0
+    # a later window matches the same schedule
+    fr2 = I.accelerating_frames(100, 1e-5, 400.0, (0, 0, 0), start=500)
+    np.testing.assert_allclose(fr2, fr[500:600], atol=1e-18)
+
+
+def test_wave_kinematics_speed_bound_and_head_fixed():
+    w = I.fish_workload(nsteps=400)
+    assert w.poses.shape == (400, 10, 24)
+    X0 = I.skin_positions(w.markers, w.poses[0])
+    assert X0[0].min() > 2 and X0[0].max() < w.nx - 3
+    # the travelling wave's tail speed stays near 0.1 L 2 pi / 400 = 0.151
+    X1 = I.skin_positions(w.markers, w.poses[1])
+    assert np.abs(X1 - X0).max() < 0.2
+
+
+def test_fin_parameters_and_batch_envs():
+    th, thd = I.fin_joint_angles(I.C5_BASE, np.arange(400))
+    assert th.shape == (400, 10)
+    assert abs(np.abs(th[:, 9]).max() - 0.4) < 1e-3
+    envs = I.batch_workloads(count=4, nsteps=60)
+    for e in envs:
+        assert 64 <= e.nx <= 192 and 48 <= e.ny <= 96 and 48 <= e.nz <= 96
+        assert 2000 <= e.markers.n <= 6000
+        for s in (0, 59):
+            X = I.skin_positions(e.markers, e.poses[s])
+            for a, m in enumerate((e.nx, e.ny, e.nz)):
+                assert X[a].min() >= 2 and X[a].max() < m - 3
+    # the draw is reproducible
+    again = I.batch_workloads(count=4, nsteps=60)
+    assert [(e.nx, e.ny, e.nz, e.markers.n) for e in envs] == [(e.nx, e.ny, e.nz, e.markers.n) for e in again]

@@ -1,0 +1,165 @@
+"""Pins of the oracle's immersed-boundary coupling and skinning.
+
+* interpolation reproduces linear fields exactly (Peskin kernel moments);
+* spreading is the transpose of interpolation and conserves total force;
+* one step of direct forcing on a uniform stream removes exactly
+  2 alpha u0 sum(dV) of momentum and reports it as drag on the body;
+* linear blend skinning: identity pose gives the rest surface, a common rigid
+  motion moves every marker rigidly, velocities are the pose rates;
+* Stokes drag on a fixed sphere in a periodic array: within the IB effective
+  radius of Hasimoto's periodic-array Stokes law.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2206_01683_amd import inputs as I
+
+
+def _markers_inside(rng, n, lo, hi):
+    return np.stack([rng.uniform(lo[a], hi[a], n) for a in range(3)])
+
+
+@pytest.mark.parametrize("periodic_x", [True, False])
+def test_interpolation_of_linear_field_is_exact(periodic_x):
+    nx, ny, nz = 16, 12, 10
+    bc = oracle.BC_PERIODIC if periodic_x else oracle.BC_VELOCITY
+    prm = oracle.params(nx, ny, nz, 0.6, bc, bc)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    a = np.array([[0.3, -0.2, 0.1, 1.0], [0.05, 0.4, -0.3, -2.0]])
+    field = np.stack([a[k, 0] * x + a[k, 1] * y + a[k, 2] * z + a[k, 3] for k in range(2)])
+    rng = np.random.default_rng(0)
+    # stay where no stencil wraps, so the field is linear over every stencil
+    X = _markers_inside(rng, 200, (2.0, 2.0, 2.0), (nx - 3.0, ny - 3.0, nz - 3.0))
+    out = oracle.interpolate(prm, field, X)
+    want = np.stack([a[k, 0] * X[0] + a[k, 1] * X[1] + a[k, 2] * X[2] + a[k, 3] for k in range(2)])
+    np.testing.assert_allclose(out, want, atol=1e-12)
+
+
+def test_spread_is_transpose_of_interpolation_and_conserves_force():
+    nx, ny, nz = 12, 10, 9
+    prm = oracle.params(nx, ny, nz, 0.6)
+    rng = np.random.default_rng(1)
+    X = _markers_inside(rng, 57, (-3.0, -2.0, 0.0), (nx + 3.0, ny, nz + 1.5))  # wraps on every axis
+    Fdv = rng.standard_normal((3, 57))
+    g = oracle.spread(prm, X, Fdv)
+    np.testing.assert_allclose(g.reshape(3, -1).sum(1), Fdv.sum(1), atol=1e-12)
+    u = rng.standard_normal((3, nz, ny, nx))
+    lhs = (oracle.interpolate(prm, u, X) * Fdv).sum()
+    rhs = (u * g).sum()
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs) + 1e-13
+
+
+def test_periodic_interpolation_is_translation_invariant():
+    nx, ny, nz = 10, 9, 8
+    prm = oracle.params(nx, ny, nz, 0.6)
+    rng = np.random.default_rng(2)
+    u = rng.standard_normal((1, nz, ny, nx))
+    X = _markers_inside(rng, 40, (0, 0, 0), (nx, ny, nz))
+    shifted = np.roll(u, shift=(2, -3, 1), axis=(1, 2, 3))  # field moved by (+1 x, -3 y, +2 z)
+    Xs = X + np.array([[1.0], [-3.0], [2.0]])
+    np.testing.assert_allclose(oracle.interpolate(prm, shifted, Xs), oracle.interpolate(prm, u, X), atol=1e-13)
+
+
+@pytest.mark.parametrize("alpha", [1.0, 0.5])
+def test_direct_forcing_on_uniform_stream_one_step(alpha):
+    nx, ny, nz = 12, 10, 10
+    u0 = np.array([0.04, -0.01, 0.02])
+    f = oracle.equilibrium_field(np.ones((nz, ny, nx)), np.broadcast_to(u0.reshape(3, 1, 1, 1), (3, nz, ny, nx)))
+    ms = I.fibonacci_sphere(60, 2.0, (5.3, 4.9, 5.1))
+    c, _ = oracle.lattice()
+    P0 = np.array([(f * c[:, a].reshape(27, 1, 1, 1)).sum() for a in range(3)])
+    prm = oracle.params(nx, ny, nz, 0.6, ib_alpha=alpha)
+    res = oracle.run(prm, f, I.make_frames(1, origin=(5.3, 4.9, 5.1)), ms, I.identity_poses(1))
+    # a uniform field interpolates to itself, so F_k = 2 alpha rho (0 - u0)
+    np.testing.assert_allclose(res["F"], np.broadcast_to((-2 * alpha * u0)[:, None], (3, 60)), atol=1e-15)
+    P1 = np.array([(res["f"] * c[:, a].reshape(27, 1, 1, 1)).sum() for a in range(3)])
+    dvt = ms.dv.sum()
+    np.testing.assert_allclose(P1 - P0, -2 * alpha * u0 * dvt, atol=1e-13)
+    np.testing.assert_allclose(res["wrench"][0, 0:3], 2 * alpha * u0 * dvt, atol=1e-13)
+    # power F.U_b dV is 0 for a body at rest; with one common force per
+    # marker the torque about the frame origin is (sum_k (X_k - x0) dV_k) x F
+    assert res["wrench"][0, 6] == 0.0
+    arm = ((ms.xrest - np.array([[5.3], [4.9], [5.1]])) * ms.dv).sum(1)
+    np.testing.assert_allclose(res["wrench"][0, 3:6], np.cross(arm, 2 * alpha * u0), atol=1e-14)
+
+
+def test_marker_near_open_face_is_rejected():
+    nx, ny, nz = 16, 8, 8
+    prm = oracle.params(nx, ny, nz, 0.6, oracle.BC_VELOCITY, oracle.BC_OUTFLOW)
+    f = oracle.equilibrium_field(np.ones((nz, ny, nx)), np.zeros((3, nz, ny, nx)))
+    for xc in (2.5, nx - 3.5):  # the sphere of radius 1 crosses x = 2 or x = nx - 3
+        ms = I.fibonacci_sphere(20, 1.0, (xc, 4.0, 4.0))
+        with pytest.raises(oracle.OracleError):
+            oracle.run(prm, f.copy(), I.make_frames(1), ms, I.identity_poses(1))
+    ms = I.fibonacci_sphere(20, 1.0, (8.0, 4.0, 4.0))
+    oracle.run(prm, f.copy(), I.make_frames(1), ms, I.identity_poses(1))
+
+
+def test_skinning_identity_and_rigid_motion():
+    ms = I.fish_surface(800, 40.0, (10.0, 20.0, 20.0))
+    assert np.allclose(ms.weight.sum(0), 1.0, atol=1e-15)
+    pose = I.identity_poses(1, ms.nbones)[0]
+    X, U = oracle.skin(ms, pose)
+    np.testing.assert_allclose(X, ms.xrest, atol=1e-13, rtol=0)  # w0 x + w1 x rounds
+    np.testing.assert_array_equal(U, 0.0)
+    # the same rigid motion on every bone moves the surface rigidly
+    th = 0.3
+    R = np.array([[math.cos(th), -math.sin(th), 0], [math.sin(th), math.cos(th), 0], [0, 0, 1.0]])
+    Rd = 0.01 * np.array([[-math.sin(th), -math.cos(th), 0], [math.cos(th), -math.sin(th), 0], [0, 0, 0.0]])
+    t = np.array([1.0, -2.0, 0.5])
+    td = np.array([0.01, 0.0, -0.02])
+    pose = np.zeros((ms.nbones, 24))
+    pose[:, 0:9] = R.reshape(9)
+    pose[:, 9:12] = t
+    pose[:, 12:21] = Rd.reshape(9)
+    pose[:, 21:24] = td
+    X, U = oracle.skin(ms, pose)
+    np.testing.assert_allclose(X, R @ ms.xrest + t[:, None], atol=1e-12)
+    np.testing.assert_allclose(U, Rd @ ms.xrest + td[:, None], atol=1e-14)
+    # pairwise distances are preserved
+    d0 = np.linalg.norm(ms.xrest[:, :50, None] - ms.xrest[:, None, :50], axis=0)
+    d1 = np.linalg.norm(X[:, :50, None] - X[:, None, :50], axis=0)
+    np.testing.assert_allclose(d1, d0, atol=1e-12)
+
+
+def test_skinned_velocity_matches_position_rate_of_wave():
+    ms = I.fish_surface(500, 48.0, (40.0, 32.0, 32.0))
+    steps = np.array([99.0, 100.0, 101.0])
+    psi, psid = I.wave_headings(48.0, 10, steps)
+    poses = I.chain_poses(psi, psid, ms.joints_rest)
+    Xm, _ = oracle.skin(ms, poses[0])
+    _, U = oracle.skin(ms, poses[1])
+    Xp, _ = oracle.skin(ms, poses[2])
+    # central difference error ~ (2 pi / 400)^2 / 6 relative
+    np.testing.assert_allclose(U, (Xp - Xm) / 2.0, rtol=0, atol=1e-4 * np.abs(U).max())
+
+
+@pytest.mark.slow
+def test_stokes_drag_on_sphere_in_periodic_array():
+    """Fixed sphere (R = 3, 250 markers) in a 32^3 periodic box, tau = 1,
+    driven by a uniform body force. Quasi-steady resistance F/U against
+    Hasimoto's simple-cubic array correction of Stokes' law,
+    F = 6 pi mu R U / K, K = 1 - 1.7601 phi^(1/3) + phi - 1.5593 phi^2.
+    A diffuse-interface (IB) sphere is hydrodynamically larger than its
+    nominal radius by a fraction of the kernel width, so the check is that
+    the effective radius lies in [R, R + 1.5]."""
+    N, R, tau, G = 32, 3.0, 1.0, 1e-6
+    nu = (tau - 0.5) / 3
+    c = (N / 2 + 0.3, N / 2 + 0.1, N / 2 + 0.2)
+    ms = I.fibonacci_sphere(250, R, c)
+    prm = oracle.params(N, N, N, tau)
+    f = oracle.equilibrium_field(np.ones((N, N, N)), np.zeros((3, N, N, N)))
+    steps = 2000
+    fr = I.make_frames(steps, acc=(-G, 0, 0), origin=c)
+    res = oracle.run(prm, f, fr, ms, I.identity_poses(steps))
+    _, u = oracle.macros(prm, res["f"], fr[-1])
+    U = u[0].mean()
+    drag = res["wrench"][-1, 0]
+    phi = 4 / 3 * math.pi * R ** 3 / N ** 3
+    K = 1 - 1.7601 * phi ** (1 / 3) + phi - 1.5593 * phi ** 2
+    r_eff = R * drag / (6 * math.pi * nu * R * U / K)
+    assert drag > 0 and U > 0
+    assert R <= r_eff <= R + 1.5, r_eff
