@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""Throughput of the immersed-boundary lattice Boltzmann step on one MI355X.
+
+Workload: the single-fish, accelerating-local-frame configuration -
+384x192x192 D3Q27 lattice (tau = 0.6), a 12,000-marker synthetic fish on a
+10-joint chain of length 96 driven by a travelling body wave, frame
+acceleration a(n) = 1e-5 sin(2 pi n / 400), velocity inlet / zero-gradient
+outlet. One step = skinning, tile binning, interpolation, direct forcing,
+spreading, the fused collide-stream with the frame force and open faces, and
+the body wrench (the whole path), all through the C interface.
+
+Prints one JSON line: MLUPS (lattice updates per second / 1e6, every node
+counted), the collide kernel's achieved bandwidth against the 8 TB/s HBM peak
+from HIP events on its stream, and the FP64 oracle's throughput on the host
+cores for a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_CELL = {"f32": 216, "f16": 108, "bf16": 108}
+METRIC = "MLUPS and % of HBM roofline per GPU; adjoint/forward time ratio"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "collide_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2206_01683_amd", "csrc", f) for f in ("lattice.hpp", "fluid.hpp")]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(storage: str):
+    """HBM bytes per collide launch from the committed rocprofv3 counter
+    summary, or None when it is missing or was taken on other kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    key = f"hbm_bytes_per_launch_{storage}"
+    return float(vals[key]) if key in vals else None
+
+
+def run_gpu(storage: str, steps: int, warmup: int, block=(0, 0)):
+    import numpy as np
+    import torch
+
+    from paper_2206_01683_amd import inputs as I
+    from paper_2206_01683_amd import lbm
+
+    w = I.fish_workload(nsteps=warmup + steps)
+    sim = lbm.Simulation(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi, storage=storage, max_markers=w.markers.n,
+                         max_bones=w.markers.nbones, block=block)
+    dm = lbm.DeviceMarkers(w.markers)
+    poses = torch.as_tensor(np.ascontiguousarray(w.poses, np.float32), device="cuda")
+    wrench = torch.zeros((warmup + steps, 8), dtype=torch.float32, device="cuda")
+    if warmup:
+        sim.step(w.frames[:warmup], dm, poses[:warmup], wrench[:warmup])
+    torch.cuda.synchronize()
+    sim.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(w.frames[warmup:], dm, poses[warmup:], wrench[warmup:])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ib_ms, col_ms, timed = sim.profile_collect()
+    status = sim.check()
+    ncell = w.ncell
+    mlups = ncell * steps / wall / 1e6
+    col_avg_s = col_ms / 1000.0 / max(timed, 1)
+    alg_bytes = BYTES_PER_CELL[storage] * ncell
+    res = {
+        "workload": w, "ncell": ncell, "wall": wall, "mlups": mlups, "status": status,
+        "collide_avg_ms": col_avg_s * 1e3, "ib_avg_ms": ib_ms / max(timed, 1), "timed": timed,
+        "collide_gbs": alg_bytes / col_avg_s / 1e9, "alg_bytes": alg_bytes,
+        "wrench_last": wrench[-1].cpu().tolist(),
+    }
+    del sim
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(sample_steps: int):
+    """The FP64 oracle as it stands, on the host cores, on the first
+    sample_steps steps of the same workload (same domain, fish and frames)."""
+    import numpy as np
+
+    import oracle
+    from paper_2206_01683_amd import inputs as I
+
+    w = I.fish_workload(nsteps=sample_steps)
+    prm = oracle.params(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi)
+    f0 = oracle.equilibrium_field(np.ones((w.nz, w.ny, w.nx)), w.u0)
+    t0 = time.perf_counter()
+    oracle.run(prm, f0, w.frames, w.markers, w.poses, sample_steps)
+    dt = time.perf_counter() - t0
+    return {"value": round(w.ncell * sample_steps / dt / 1e6, 3), "unit": "MLUPS", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{sample_steps} steps of the {w.nx}x{w.ny}x{w.nz} fish workload from rest "
+                      f"({w.ncell * sample_steps} node updates, {dt:.1f} s, FP64)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--storage", default="f32", choices=sorted(BYTES_PER_CELL))
+    ap.add_argument("--cpu-steps", type=int, default=3, help="oracle sample length (0: skip)")
+    ap.add_argument("--no-forms", action="store_true", help="skip the FP16/BF16 storage forms")
+    ap.add_argument("--block", type=int, nargs=2, default=(0, 0))
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); this "
+              "build has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    main_run = run_gpu(args.storage, args.steps, args.warmup, tuple(args.block))
+    w = main_run["workload"]
+    forms = {}
+    if not args.no_forms and args.storage == "f32":
+        for st in ("f16", "bf16"):
+            r = run_gpu(st, args.steps, args.warmup, tuple(args.block))
+            forms[st] = {"mlups": round(r["mlups"], 1), "collide_GBps": round(r["collide_gbs"], 1),
+                         "collide_frac_of_hbm_peak": round(r["collide_gbs"] / HBM_PEAK_GBS, 4),
+                         "bytes_per_cell": BYTES_PER_CELL[st], "status": r["status"]}
+    traffic = measured_traffic(args.storage)
+    ach = main_run["collide_gbs"]
+    out = {
+        "metric": METRIC,
+        "value": round(main_run["mlups"], 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_run["wall"] * 1e3 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.storage,
+        "data": "synthetic",
+        "config": {"workload": f"fish-{w.nx}x{w.ny}x{w.nz}", "lattice": "D3Q27", "tau": w.tau,
+                   "markers": w.markers.n, "bones": w.markers.nbones, "storage": args.storage,
+                   "boundaries": "x: velocity inlet / zero-gradient outlet; y, z periodic",
+                   "frame": "a(n) = 1e-5 sin(2 pi n / 400) e_x"},
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic, 0),
+                     "kernel": "k_collide", "bytes_per_cell": BYTES_PER_CELL[args.storage],
+                     "cells_per_launch": main_run["ncell"],
+                     "avg_launch_ms": round(main_run["collide_avg_ms"], 5)},
+        "step_hbm_frac": round(main_run["mlups"] * 1e6 * BYTES_PER_CELL[args.storage] / (HBM_PEAK_GBS * 1e9), 4),
+        "ib_ms_per_step": round(main_run["ib_avg_ms"], 5),
+        "device_status": main_run["status"],
+        "forms": forms,
+    }
+    if args.cpu_steps > 0:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

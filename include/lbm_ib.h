@@ -1,0 +1,195 @@
+/*
+ * lbm_ib.h - C interface of the MI355X (gfx950) immersed-boundary lattice
+ * Boltzmann library.
+ *
+ * One call advances a D3Q27 lattice Boltzmann fluid, in a local frame that may
+ * accelerate and rotate, coupled two-way to a skinned surface by the immersed
+ * boundary method. This is the fluid-structure interaction module of the
+ * paper (Sec. III-B, "GPU-accelerated localized fluid-structure
+ * interaction"): Eq. (2) solved by a lattice Boltzmann method, the
+ * fictitious frame force of Eq. (3), open domain faces by non-equilibrium
+ * extrapolation (Sec. III-B, Simulation), a uniformly sampled surface
+ * (Sec. III-B, Simulation) skinned by linear blend skinning (Sec. III-A) and
+ * the fluid's force on the body, which enters Eq. (1) as the external
+ * generalized force.
+ *
+ * Method as implemented (the paper leaves these details open):
+ *   lattice      D3Q27, c_i in {-1,0,1}^3, i = (cx+1) + 3(cy+1) + 9(cz+1)
+ *   collision    BGK, relaxation time tau > 1/2, second-order equilibrium
+ *   forcing      Guo: velocity u = (m + F/2)/rho; F = g + rho a_ni(x, u),
+ *                a_ni from Eq. (3), solved exactly for the Coriolis term
+ *   streaming    pull; y and z always periodic; x periodic or open
+ *   open faces   non-equilibrium extrapolation from the inward neighbour
+ *   IB           Peskin 4-point kernel, explicit direct forcing
+ *                F_k = alpha 2 rho_k (U_k - U*_k), optional multi-direct
+ *                forcing passes, spreading g(x) = sum_k F_k dV_k delta(x - X_k)
+ *
+ * Conventions shared by every entry point:
+ *   - Every pointer is a DEVICE pointer allocated and owned by the caller,
+ *     unless its comment says [host]. The library never allocates or frees
+ *     device memory and keeps no pointer after lbm_destroy.
+ *   - Grids are x-fastest: cell (x, y, z) has index x + nx (y + ny z). A field
+ *     with components is component-major: [comp][nz][ny][nx].
+ *   - Populations in the caller's canonical layout are pre-collision values
+ *     f_i(x, n), float32, [27][nz][ny][nx].
+ *   - All device work is enqueued on the context's HIP stream. A call returns
+ *     after enqueueing; it synchronizes only where it says so.
+ *   - Every call returns an lbm_status; nothing is thrown across the boundary.
+ *     Arguments are validated on the host before any device work is queued;
+ *     on an error nothing is queued.
+ */
+#ifndef LBM_IB_H
+#define LBM_IB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_ERR_ARG = -1,          /* bad argument: null pointer, size, tau <= 1/2, ... */
+  LBM_ERR_DEVICE = -2,       /* a HIP runtime call or kernel launch failed */
+  LBM_ERR_UNSTABLE = -3,     /* device guard: non-finite value or |u| >= 0.4 seen */
+  LBM_ERR_MARKER_RANGE = -4, /* a marker came within 2 cells (3 on the high side) of an open face */
+  LBM_ERR_CAPACITY = -5,     /* more markers than max_markers or active tiles than capacity */
+  LBM_ERR_UNSUPPORTED = -6   /* valid request this build does not implement */
+} lbm_status;
+
+/* Face conditions for x = 0 (bc_lo) and x = nx-1 (bc_hi). Both periodic, or
+ * both open (each VELOCITY or OUTFLOW). */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_VELOCITY = 1, LBM_BC_OUTFLOW = 2 };
+
+/* Population storage. F32 stores f_i. F16 and BF16 store h_i = f_i - w_i
+ * (offset from the rest equilibrium) rounded to nearest even; all arithmetic
+ * and all immersed-boundary sums stay in float32. */
+enum { LBM_STORE_F32 = 0, LBM_STORE_F16 = 1, LBM_STORE_BF16 = 2 };
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* [host] Problem description. */
+typedef struct {
+  int32_t nx, ny, nz;        /* lattice size, each >= 4 */
+  int32_t bc_lo, bc_hi;      /* LBM_BC_* for the two x faces */
+  int32_t storage;           /* LBM_STORE_* */
+  int32_t max_markers;       /* capacity of the marker arrays, >= 0 */
+  int32_t max_bones;         /* capacity of a pose array, >= 1 */
+  int32_t mdf_iters;         /* direct-forcing passes, >= 1 (1 = explicit) */
+  int32_t max_active_tiles;  /* 8x8x8 tiles that may carry IB force; 0 = automatic */
+  int32_t block_x, block_y;  /* collide kernel block shape; 0 = default */
+  double tau;                /* BGK relaxation time, > 1/2 (nu = (tau - 1/2)/3) */
+  double ib_alpha;           /* direct-forcing gain, > 0 (1 = full correction) */
+} lbm_params;
+
+/* [host] Frame of one step (Eq. (3)). acc = linear acceleration of the frame
+ * origin, omega = angular velocity, alpha = angular acceleration (vectors in
+ * frame coordinates); x' = x - origin. u_lo / u_hi = velocity prescribed on
+ * the x = 0 / x = nx-1 face when that face is LBM_BC_VELOCITY. */
+typedef struct {
+  double acc[3], omega[3], alpha[3], origin[3], u_lo[3], u_hi[3];
+} lbm_frame;
+
+/* Surface markers (Sec. III-B: uniformly sampled surface; Sec. III-A: linear
+ * blend skinning). Structure-of-arrays, n entries each.
+ *   xrest  [3][n] rest-pose position          (in)
+ *   bone   [2][n] the two bones of each marker (in; 0 <= bone < nbones)
+ *   weight [2][n] their blend weights          (in)
+ *   dv     [n]    marker volume dV_k           (in)
+ *   X, U   [3][n] position and velocity        (out, written by each step)
+ *   F      [3][n] direct-forcing force density of the last step (out)
+ * A bone pose is 24 float32: R (3x3 row-major), t, dR/dt (3x3 row-major), dt/dt;
+ * X_k = sum_b w_kb (R_b xrest_k + t_b), U_k = sum_b w_kb (dR_b xrest_k + dt_b). */
+typedef struct {
+  int32_t n;
+  int32_t nbones;
+  const float *xrest;
+  const int32_t *bone;
+  const float *weight;
+  const float *dv;
+  float *X;
+  float *U;
+  float *F;
+} lbm_markers;
+
+/* Bytes of one population buffer (two are needed) and of the workspace for
+ * these parameters. 0 if the parameters are invalid. */
+size_t lbm_population_bytes(const lbm_params *p);
+size_t lbm_workspace_bytes(const lbm_params *p);
+
+/* Create a context bound to caller buffers f_a, f_b (lbm_population_bytes
+ * each), workspace (lbm_workspace_bytes, 256-byte aligned) and a HIP stream
+ * (hipStream_t, NULL = default stream), and set the initial state to the
+ * equilibrium f_i = f^eq_i(rho0, u0).
+ *   rho0 [nz][ny][nx] or NULL (rho = 1);  u0 [3][nz][ny][nx] or NULL (u = 0).
+ * *out receives the context (host memory owned by the library; release with
+ * lbm_destroy). Queues device work; does not synchronize. */
+lbm_status lbm_init(lbm_ctx **out, const lbm_params *p, void *f_a, void *f_b, void *workspace,
+                    const float *rho0, const float *u0, void *hip_stream);
+
+/* Replace the state with caller populations f [27][nz][ny][nx] (canonical
+ * pre-collision layout). */
+lbm_status lbm_load_populations(lbm_ctx *c, const float *f);
+
+/* Write the current pre-collision populations to f [27][nz][ny][nx]. Values of
+ * populations that would stream into an open-face node from outside the
+ * domain are the face node's own post-collision values (never used). */
+lbm_status lbm_read_populations(lbm_ctx *c, float *f);
+
+/* Density rho [nz][ny][nx] and fluid velocity u [3][nz][ny][nx] of the
+ * current pre-collision state: u solves u = (m + a0/2 - omega x u)/rho with
+ * a0 the frame force of Eq. (3) at that node, i.e. the velocity with the
+ * frame force but without immersed-boundary force. Either output may be NULL.
+ * frame [host] may be NULL (inertial frame). */
+lbm_status lbm_macros(lbm_ctx *c, const lbm_frame *frame, float *rho, float *u);
+
+/* Advance nsteps time steps. For step s (global step n = current + s):
+ *   skin the markers with poses[s] -> X, U; interpolate the unforced velocity
+ *   and density to the markers; direct forcing -> F; spread -> g; collide
+ *   (BGK + Guo with g and the frame force of frames[s]) and stream; open
+ *   faces by non-equilibrium extrapolation; fluid wrench into wrench[s].
+ *   m       markers (NULL or m->n == 0: no immersed body)
+ *   poses   [nsteps][m->nbones][24] (may be NULL when m is NULL)
+ *   frames  [host] [nsteps]
+ *   wrench  [nsteps][8] or NULL: fluid force on the body (3), its torque about
+ *           the frame origin (3), power delivered by the body to the fluid
+ *           sum F_k . U_k dV_k (1), 0. All float32.
+ * Markers leaving the allowed region, and unstable states, are detected on the
+ * device and reported by lbm_check. */
+lbm_status lbm_ib_step(lbm_ctx *c, const lbm_markers *m, const float *poses, const lbm_frame *frames,
+                       int32_t nsteps, float *wrench);
+
+/* Fluid force on the body from the markers' last forces F (the external
+ * generalized force of Eq. (1)). out [(1 + m->nbones)][8]: row 0 is the whole
+ * body, row 1 + b the share of bone b (each marker's force split by its blend
+ * weights); each row is force (3), torque about center (3), power (1), 0.
+ * center [host] 3 doubles. */
+lbm_status lbm_body_forces(lbm_ctx *c, const lbm_markers *m, const double *center, float *out);
+
+/* Synchronize the stream and report device-side guards: LBM_ERR_UNSTABLE,
+ * LBM_ERR_MARKER_RANGE, LBM_ERR_CAPACITY, or LBM_OK. Clears the guards. */
+lbm_status lbm_check(lbm_ctx *c);
+
+/* Measurement hook. enable != 0: every later step brackets its two phases
+ * (immersed-boundary kernels; fused collide-stream kernel) with HIP events on
+ * the context stream (event pool of 4096 steps; later steps are not timed).
+ * lbm_profile_collect synchronizes, returns the summed durations in
+ * milliseconds and the number of timed steps, and empties the pool. Either
+ * output may be NULL. */
+lbm_status lbm_profile_enable(lbm_ctx *c, int enable);
+lbm_status lbm_profile_collect(lbm_ctx *c, double *ib_ms, double *collide_ms, int64_t *steps);
+
+/* Use another HIP stream for subsequent work. */
+lbm_status lbm_set_stream(lbm_ctx *c, void *hip_stream);
+
+/* Number of steps taken since lbm_init / lbm_load_populations. */
+int64_t lbm_step_count(const lbm_ctx *c);
+
+const char *lbm_strerror(lbm_status s);
+void lbm_destroy(lbm_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_IB_H */

@@ -58,6 +58,7 @@ def lib():
         L = ctypes.CDLL(_LIB)
         dp = ctypes.c_void_p
         L.or_abi_version.restype = ctypes.c_int
+        L.or_threads.restype = ctypes.c_int
         L.or_lattice.argtypes = [dp, dp]
         L.or_equilibrium.argtypes = [ctypes.c_double, dp, dp]
         L.or_equilibrium_field.argtypes = [dp, dp, ctypes.c_int64, dp]
@@ -86,6 +87,11 @@ def _f64(a) -> np.ndarray:
 
 def params(nx, ny, nz, tau, bc_lo=BC_PERIODIC, bc_hi=BC_PERIODIC, mdf_iters=1, ib_alpha=1.0) -> _Params:
     return _Params(nx, ny, nz, bc_lo, bc_hi, mdf_iters, tau, ib_alpha)
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's lattice sweeps use."""
+    return int(lib().or_threads())
 
 
 def lattice():

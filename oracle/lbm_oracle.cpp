@@ -42,6 +42,10 @@
 #include <cstring>
 #include <vector>
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 namespace {
 
 // ---------------------------------------------------------------- lattice --
@@ -119,6 +123,15 @@ struct OrMarkers {
 };
 
 int or_abi_version(void) { return 1; }
+
+// Threads a parallel lattice sweep uses.
+int or_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 void or_lattice(int32_t *c, double *w) {
   for (int i = 0; i < 27; ++i) {

@@ -1,0 +1,299 @@
+// Lattice Boltzmann kernels: the fused pull-stream + collide step and the
+// state conversion kernels.
+//
+// State layout: two buffers of 27 population planes, each plane
+// `plane` elements long (nx*ny*nz rounded up), x fastest. A buffer holds the
+// post-collision values f*(x, n-1); the pre-collision state of step n is the
+// pull f_i(x, n) = f*_i(x - c_i, n-1). One step reads the current buffer and
+// writes the other.
+#pragma once
+
+#include "lattice.hpp"
+
+namespace lbmib {
+
+struct GridArgs {
+  int nx, ny, nz;
+  uint32_t plane;
+  int xper;       // 1: x periodic
+  int bc_lo, bc_hi;
+  int tnx, tny;   // 8^3 tile grid (x, y extents)
+};
+
+struct CollideArgs {
+  GridArgs g;
+  FrameF fr;
+  float inv_tau, omt, pref;  // 1/tau, 1 - 1/tau, 1 - 1/(2 tau)
+  int gx, gy, nblocks;       // logical block grid (x-blocks, y-blocks, total)
+};
+
+// Pull the 27 pre-collision populations of node (xs, y, z). The x neighbour
+// indices xm/xp are given by the caller (periodic wrap or interior node).
+template <class S>
+__device__ inline void pull27(const typename S::T *__restrict__ src, uint32_t plane, int nx, int ny, int xm, int xs,
+                              int xp, int ym, int y, int yp, int zm, int z, int zp, float f[Q]) {
+  const int xx[3] = {xp, xs, xm};  // indexed by cx + 1: source x = xs - cx
+  const int yy[3] = {yp, y, ym};
+  const int zz[3] = {zp, z, zm};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    uint32_t off = (uint32_t)i * plane + ((uint32_t)zz[cz_of(i) + 1] * (uint32_t)ny + (uint32_t)yy[cy_of(i) + 1]) *
+                                             (uint32_t)nx + (uint32_t)xx[cx_of(i) + 1];
+    f[i] = S::load(src + off, i);
+  }
+}
+
+__device__ inline void moments(const float f[Q], float &rho, float &mx, float &my, float &mz) {
+  rho = 0.f;
+  mx = my = mz = 0.f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    rho += f[i];
+    if (cx_of(i) == 1) mx += f[i];
+    if (cx_of(i) == -1) mx -= f[i];
+    if (cy_of(i) == 1) my += f[i];
+    if (cy_of(i) == -1) my -= f[i];
+    if (cz_of(i) == 1) mz += f[i];
+    if (cz_of(i) == -1) mz -= f[i];
+  }
+}
+
+__device__ inline float cdot(int i, float ax, float ay, float az) {
+  float r = 0.f;
+  if (cx_of(i) == 1) r += ax;
+  if (cx_of(i) == -1) r -= ax;
+  if (cy_of(i) == 1) r += ay;
+  if (cy_of(i) == -1) r -= ay;
+  if (cz_of(i) == 1) r += az;
+  if (cz_of(i) == -1) r -= az;
+  return r;
+}
+
+// Immersed-boundary force density at cell (x, y, z): zero outside active tiles.
+__device__ inline void load_g(const GridArgs &g, const int *__restrict__ tile_slot, const float *__restrict__ gbuf,
+                              int x, int y, int z, float &gx, float &gy, float &gz) {
+  gx = gy = gz = 0.f;
+  if (tile_slot == nullptr) return;
+  int t = (x >> 3) + g.tnx * ((y >> 3) + g.tny * (z >> 3));
+  int s = tile_slot[t];
+  if (s >= 0) {
+    int lc = (x & 7) | ((y & 7) << 3) | ((z & 7) << 6);
+    const float *gp = gbuf + (size_t)s * 1536;
+    gx = gp[lc];
+    gy = gp[512 + lc];
+    gz = gp[1024 + lc];
+  }
+}
+
+// One lattice Boltzmann step for every node:
+//   interior node: f*_i = f_i - (f_i - f^eq_i(rho,u))/tau + (1 - 1/(2tau)) w_i
+//                  [3(c_i - u) + 9 (c_i.u) c_i].F,  u = (m + F/2)/rho,
+//                  F = g + rho a_ni(x, u)  (Eq. (3), solved exactly)
+//   open-face node x_b with inward neighbour x_f (same y, z):
+//                  f*_i(x_b) = f^eq_i(rho_f, u_b) + (1 - 1/tau)(f_i(x_f) - f^eq_i(rho_f, u_f))
+//                  + (1 - 1/(2tau)) w_i [3(c_i - u_b) + 9 (c_i.u_b) c_i].F_b,
+//                  u_f the forced velocity at x_f, u_b the face velocity
+//                  (velocity face) or u_f (outflow), F_b = rho_f a_ni(x_b, u_b).
+// The open-face lanes reuse the interior arithmetic: replacing f_i by
+// f_i + f^eq_i(rho_f, u_b) - f^eq_i(rho_f, u_f) makes the BGK formula with
+// (rho_f, u_b, F_b) produce exactly the extrapolated values.
+// Blocks are mapped XCD-aware: hardware workgroup b runs on XCD b % 8, so the
+// logical block index gives each XCD a contiguous 1/8 of the domain (shared
+// cache lines of neighbouring blocks stay in one L2).
+template <class S, bool XPER, bool ROT>
+__global__ void __launch_bounds__(512) k_collide(const typename S::T *__restrict__ src, typename S::T *__restrict__ dst,
+                                                 CollideArgs a, const int *__restrict__ tile_slot,
+                                                 const float *__restrict__ gbuf, int *__restrict__ guard) {
+  const int b = blockIdx.x;
+  const int per = (a.nblocks + 7) >> 3;
+  const int lb = (b & 7) * per + (b >> 3);
+  if (lb >= a.nblocks) return;
+  const int bxi = lb % a.gx;
+  const int rest = lb / a.gx;
+  const int byi = rest % a.gy;
+  const int z = rest / a.gy;
+  const int x = bxi * blockDim.x + threadIdx.x;
+  const int y = byi * blockDim.y + threadIdx.y;
+  const GridArgs &g = a.g;
+  if (x >= g.nx || y >= g.ny) return;
+
+  const bool lo_face = !XPER && x == 0;
+  const bool hi_face = !XPER && x == g.nx - 1;
+  const bool face = lo_face || hi_face;
+  const int xs = lo_face ? 1 : (hi_face ? g.nx - 2 : x);
+  int xm, xp;
+  if (XPER) {
+    xm = xs == 0 ? g.nx - 1 : xs - 1;
+    xp = xs == g.nx - 1 ? 0 : xs + 1;
+  } else {
+    xm = xs - 1;
+    xp = xs + 1;
+  }
+  const int ym = y == 0 ? g.ny - 1 : y - 1;
+  const int yp = y == g.ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? g.nz - 1 : z - 1;
+  const int zp = z == g.nz - 1 ? 0 : z + 1;
+
+  float f[Q];
+  pull27<S>(src, g.plane, g.nx, g.ny, xm, xs, xp, ym, y, yp, zm, z, zp, f);
+  float rho, mx, my, mz;
+  moments(f, rho, mx, my, mz);
+  const float irho = 1.0f / rho;
+
+  float gx, gy, gz;
+  load_g(g, tile_slot, gbuf, xs, y, z, gx, gy, gz);
+  float ax, ay, az;
+  frame_a0<ROT>(a.fr, (float)xs, (float)y, (float)z, ax, ay, az);
+  float ux, uy, uz;
+  solve_coriolis<ROT>(a.fr, mx * irho + 0.5f * (gx * irho + ax), my * irho + 0.5f * (gy * irho + ay),
+                      mz * irho + 0.5f * (gz * irho + az), ux, uy, uz);
+  float Fx, Fy, Fz;
+  if (!face) {
+    float wx = 0.f, wy = 0.f, wz = 0.f;
+    if (ROT) cross3(a.fr.omg, ux, uy, uz, wx, wy, wz);
+    Fx = gx + rho * (ax - 2.0f * wx);
+    Fy = gy + rho * (ay - 2.0f * wy);
+    Fz = gz + rho * (az - 2.0f * wz);
+  } else {
+    // (ux,uy,uz) is u_f; choose u_b and shift f by f^eq(u_b) - f^eq(u_f)
+    const int bc = lo_face ? g.bc_lo : g.bc_hi;
+    const float *uf = lo_face ? a.fr.ulo : a.fr.uhi;
+    float bx = bc == 1 ? uf[0] : ux, by = bc == 1 ? uf[1] : uy, bz = bc == 1 ? uf[2] : uz;
+    const float ub2 = bx * bx + by * by + bz * bz, uf2 = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const float cb = cdot(i, bx, by, bz), cf = cdot(i, ux, uy, uz);
+      f[i] += w_of(i) * rho * (3.0f * (cb - cf) + 4.5f * (cb * cb - cf * cf) - 1.5f * (ub2 - uf2));
+    }
+    float ax2, ay2, az2;
+    frame_a0<ROT>(a.fr, (float)x, (float)y, (float)z, ax2, ay2, az2);
+    float wx = 0.f, wy = 0.f, wz = 0.f;
+    if (ROT) cross3(a.fr.omg, bx, by, bz, wx, wy, wz);
+    ux = bx;
+    uy = by;
+    uz = bz;
+    Fx = rho * (ax2 - 2.0f * wx);
+    Fy = rho * (ay2 - 2.0f * wy);
+    Fz = rho * (az2 - 2.0f * wz);
+  }
+
+  const float u2 = ux * ux + uy * uy + uz * uz;
+  if (!(u2 < 0.16f)) atomicOr(guard, (int)GUARD_UNSTABLE);
+
+  // BGK + Guo, evaluated on opposite pairs (i, 26 - i): c_j = -c_i, so the
+  // equilibrium and forcing split into parts even and odd in c.
+  const float A = 1.0f - 1.5f * u2;
+  const float uF = ux * Fx + uy * Fy + uz * Fz;
+  const float E = a.inv_tau * rho;
+  const float P = a.pref;
+  const uint32_t o = ((uint32_t)z * (uint32_t)g.ny + (uint32_t)y) * (uint32_t)g.nx + (uint32_t)x;
+  typename S::T *__restrict__ d = dst + o;
+#pragma unroll
+  for (int i = 0; i < 13; ++i) {
+    const int j = 26 - i;
+    const float w = w_of(i);
+    const float cu = cdot(i, ux, uy, uz);
+    const float cF = cdot(i, Fx, Fy, Fz);
+    const float even = (w * E) * (A + 4.5f * cu * cu) + (w * P) * (9.0f * cu * cF - 3.0f * uF);
+    const float odd = (w * E) * (3.0f * cu) + (w * P) * (3.0f * cF);
+    S::store(d + (uint32_t)i * g.plane, a.omt * f[i] + even + odd, i);
+    S::store(d + (uint32_t)j * g.plane, a.omt * f[j] + even - odd, j);
+  }
+  {
+    const float w = w_of(13);
+    S::store(d + 13u * g.plane, a.omt * f[13] + (w * E) * A - (w * P) * 3.0f * uF, 13);
+  }
+}
+
+// f_i(x) of the caller's canonical pre-collision field -> stored buffer, i.e.
+// stored_i(x) = f_i(x + c_i) (periodic wrap; clamped at open faces, where the
+// value is never read).
+template <class S>
+__global__ void k_load_canonical(const float *__restrict__ fin, typename S::T *__restrict__ dst, GridArgs g) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx) return;
+  const size_t n = (size_t)g.nx * g.ny * g.nz;
+  for (int i = 0; i < Q; ++i) {
+    int sx = x + cx_of(i), sy = wrap_idx(y + cy_of(i), g.ny), sz = wrap_idx(z + cz_of(i), g.nz);
+    sx = g.xper ? wrap_idx(sx, g.nx) : min(max(sx, 0), g.nx - 1);
+    float v = fin[(size_t)i * n + ((size_t)sz * g.ny + sy) * g.nx + sx];
+    S::store_plain(dst + (size_t)i * g.plane + ((size_t)z * g.ny + y) * g.nx + x, v, i);
+  }
+}
+
+// Equilibrium state f_i(x) = f^eq_i(rho0(x), u0(x)) written pre-shifted as above.
+template <class S>
+__global__ void k_init_equilibrium(const float *__restrict__ rho0, const float *__restrict__ u0,
+                                   typename S::T *__restrict__ dst, GridArgs g) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx) return;
+  const size_t n = (size_t)g.nx * g.ny * g.nz;
+  for (int i = 0; i < Q; ++i) {
+    int sx = x + cx_of(i), sy = wrap_idx(y + cy_of(i), g.ny), sz = wrap_idx(z + cz_of(i), g.nz);
+    sx = g.xper ? wrap_idx(sx, g.nx) : min(max(sx, 0), g.nx - 1);
+    size_t s = ((size_t)sz * g.ny + sy) * g.nx + sx;
+    float r = rho0 ? rho0[s] : 1.0f;
+    float ux = u0 ? u0[s] : 0.f, uy = u0 ? u0[n + s] : 0.f, uz = u0 ? u0[2 * n + s] : 0.f;
+    float cu = cdot(i, ux, uy, uz);
+    float v = w_of(i) * r * (1.0f + 3.0f * cu + 4.5f * cu * cu - 1.5f * (ux * ux + uy * uy + uz * uz));
+    S::store_plain(dst + (size_t)i * g.plane + ((size_t)z * g.ny + y) * g.nx + x, v, i);
+  }
+}
+
+// Stored buffer -> canonical pre-collision populations (pull with wrap/clamp).
+template <class S>
+__global__ void k_read_canonical(const typename S::T *__restrict__ src, float *__restrict__ fout, GridArgs g) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx) return;
+  const size_t n = (size_t)g.nx * g.ny * g.nz;
+  for (int i = 0; i < Q; ++i) {
+    int sx = x - cx_of(i), sy = wrap_idx(y - cy_of(i), g.ny), sz = wrap_idx(z - cz_of(i), g.nz);
+    sx = g.xper ? wrap_idx(sx, g.nx) : min(max(sx, 0), g.nx - 1);
+    fout[(size_t)i * n + ((size_t)z * g.ny + y) * g.nx + x] =
+        S::load(src + (size_t)i * g.plane + ((size_t)sz * g.ny + sy) * g.nx + sx, i);
+  }
+}
+
+// Density and frame-forced velocity (no immersed-boundary force) of the
+// pre-collision state at every node.
+template <class S, bool ROT>
+__global__ void k_macros(const typename S::T *__restrict__ src, GridArgs g, FrameF fr, float *__restrict__ rho_out,
+                         float *__restrict__ u_out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx) return;
+  const size_t n = (size_t)g.nx * g.ny * g.nz;
+  int xm = x - 1, xp = x + 1;
+  if (g.xper) {
+    xm = wrap_idx(xm, g.nx);
+    xp = wrap_idx(xp, g.nx);
+  } else {
+    xm = max(xm, 0);
+    xp = min(xp, g.nx - 1);
+  }
+  float f[Q];
+  pull27<S>(src, g.plane, g.nx, g.ny, xm, x, xp, wrap_idx(y - 1, g.ny), y, wrap_idx(y + 1, g.ny),
+            wrap_idx(z - 1, g.nz), z, wrap_idx(z + 1, g.nz), f);
+  float rho, mx, my, mz;
+  moments(f, rho, mx, my, mz);
+  float ax, ay, az;
+  frame_a0<ROT>(fr, (float)x, (float)y, (float)z, ax, ay, az);
+  float ux, uy, uz;
+  solve_coriolis<ROT>(fr, mx / rho + 0.5f * ax, my / rho + 0.5f * ay, mz / rho + 0.5f * az, ux, uy, uz);
+  size_t id = ((size_t)z * g.ny + y) * g.nx + x;
+  if (rho_out) rho_out[id] = rho;
+  if (u_out) {
+    u_out[id] = ux;
+    u_out[n + id] = uy;
+    u_out[2 * n + id] = uz;
+  }
+}
+
+}  // namespace lbmib

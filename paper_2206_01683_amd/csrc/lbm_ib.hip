@@ -1,0 +1,524 @@
+// Host side of the C interface declared in include/lbm_ib.h: argument
+// validation, workspace layout, kernel dispatch on the caller's stream.
+//
+// The library allocates no device memory: the caller hands in two population
+// buffers and one workspace, sized by lbm_population_bytes and
+// lbm_workspace_bytes. The context itself is a small host object.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/lbm_ib.h"
+#include "ib.hpp"
+
+using namespace lbmib;
+
+namespace {
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Workspace layout (all offsets 256-byte aligned).
+struct Layout {
+  int tnx, tny, tnz, ntiles, cap, maxm;
+  size_t guard, counters, tile_count, tile_slot, active, tile_off, tile_len, pairs, macro, gbuf, rec, mstate, total;
+};
+
+bool params_ok(const lbm_params *p) {
+  if (!p) return false;
+  if (p->nx < 4 || p->ny < 4 || p->nz < 4) return false;
+  if ((int64_t)p->nx * p->ny * p->nz > (int64_t)1 << 31) return false;
+  if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return false;
+  const bool lo_per = p->bc_lo == LBM_BC_PERIODIC, hi_per = p->bc_hi == LBM_BC_PERIODIC;
+  if (lo_per != hi_per) return false;
+  if (p->bc_lo < 0 || p->bc_lo > 2 || p->bc_hi < 0 || p->bc_hi > 2) return false;
+  if (p->storage < LBM_STORE_F32 || p->storage > LBM_STORE_BF16) return false;
+  if (p->max_markers < 0 || p->max_markers > (1 << 24)) return false;
+  if (p->max_bones < 1 || p->mdf_iters < 1 || p->mdf_iters > 16) return false;
+  if (p->max_active_tiles < 0) return false;
+  if (p->block_x < 0 || p->block_y < 0 || p->block_x * p->block_y > 512) return false;
+  if (p->block_x > 0 && p->block_x % 64 != 0) return false;
+  if (!(p->ib_alpha > 0.0) || !std::isfinite(p->ib_alpha)) return false;
+  return true;
+}
+
+size_t elem_bytes(int storage) { return storage == LBM_STORE_F32 ? 4 : 2; }
+
+uint32_t plane_elems(const lbm_params *p) {
+  size_t n = (size_t)p->nx * p->ny * p->nz;
+  return (uint32_t)align_up(n, 256);
+}
+
+Layout layout(const lbm_params *p) {
+  Layout L{};
+  L.tnx = (p->nx + 7) / 8;
+  L.tny = (p->ny + 7) / 8;
+  L.tnz = (p->nz + 7) / 8;
+  L.ntiles = L.tnx * L.tny * L.tnz;
+  L.maxm = std::max(p->max_markers, 1);
+  int cap = p->max_active_tiles > 0 ? p->max_active_tiles : L.ntiles;
+  cap = std::min(cap, L.ntiles);
+  if (p->max_markers == 0) cap = 1;
+  L.cap = std::max(cap, 1);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes, 256);
+    return at;
+  };
+  L.guard = take(64);
+  L.counters = take(64);
+  L.tile_count = take(sizeof(int) * L.ntiles);
+  L.tile_slot = take(sizeof(int) * L.ntiles);
+  L.active = take(sizeof(int) * L.cap);
+  L.tile_off = take(sizeof(int) * L.cap);
+  L.tile_len = take(sizeof(int) * L.cap);
+  L.pairs = take(sizeof(int) * 27 * (size_t)L.maxm);
+  L.macro = take(sizeof(float) * 4 * 512 * (size_t)L.cap);
+  L.gbuf = take(sizeof(float) * 3 * 512 * (size_t)L.cap);
+  L.rec = take(sizeof(float) * REC * (size_t)L.maxm);
+  L.mstate = take(sizeof(float) * 4 * (size_t)L.maxm);
+  L.total = o;
+  return L;
+}
+
+__global__ void k_fill_int(int *p, int v, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_params p;
+  Layout L;
+  void *f[2];
+  int cur;  // buffer holding the latest post-collision state
+  char *ws;
+  hipStream_t stream;
+  int64_t steps;
+  uint32_t plane;
+  bool slots_dirty;
+  int bx, by;
+  // measurement hook: 3 events per timed step (start, after IB, after collide)
+  bool prof;
+  std::vector<hipEvent_t> ev;
+  int prof_used;
+};
+
+static constexpr int kProfSteps = 4096;
+
+namespace {
+
+template <class T>
+T *wsp(lbm_ctx *c, size_t off) {
+  return reinterpret_cast<T *>(c->ws + off);
+}
+
+GridArgs grid_args(const lbm_ctx *c) {
+  GridArgs g;
+  g.nx = c->p.nx;
+  g.ny = c->p.ny;
+  g.nz = c->p.nz;
+  g.plane = c->plane;
+  g.xper = c->p.bc_lo == LBM_BC_PERIODIC;
+  g.bc_lo = c->p.bc_lo;
+  g.bc_hi = c->p.bc_hi;
+  g.tnx = c->L.tnx;
+  g.tny = c->L.tny;
+  return g;
+}
+
+FrameF frame_f(const lbm_frame *fr) {
+  FrameF f{};
+  if (!fr) return f;
+  for (int a = 0; a < 3; ++a) {
+    f.acc[a] = (float)fr->acc[a];
+    f.omg[a] = (float)fr->omega[a];
+    f.alp[a] = (float)fr->alpha[a];
+    f.org[a] = (float)fr->origin[a];
+    f.ulo[a] = (float)fr->u_lo[a];
+    f.uhi[a] = (float)fr->u_hi[a];
+  }
+  return f;
+}
+
+bool rotating(const lbm_frame *fr) {
+  if (!fr) return false;
+  for (int a = 0; a < 3; ++a)
+    if (fr->omega[a] != 0.0 || fr->alpha[a] != 0.0) return true;
+  return false;
+}
+
+bool frame_ok(const lbm_frame *fr) {
+  const double *d = &fr->acc[0];
+  for (int q = 0; q < 18; ++q)
+    if (!std::isfinite(d[q])) return false;
+  return true;
+}
+
+lbm_status launched() { return hipGetLastError() == hipSuccess ? LBM_OK : LBM_ERR_DEVICE; }
+
+// -------------------------------------------------------------- dispatch --
+template <class S>
+lbm_status launch_collide(lbm_ctx *c, const FrameF &fr, bool rot, bool ib) {
+  CollideArgs a;
+  a.g = grid_args(c);
+  a.fr = fr;
+  const double tau = c->p.tau;
+  a.inv_tau = (float)(1.0 / tau);
+  a.omt = (float)(1.0 - 1.0 / tau);
+  a.pref = (float)(1.0 - 0.5 / tau);
+  a.gx = (c->p.nx + c->bx - 1) / c->bx;
+  a.gy = (c->p.ny + c->by - 1) / c->by;
+  a.nblocks = a.gx * a.gy * c->p.nz;
+  const int grid = ((a.nblocks + 7) / 8) * 8;
+  using T = typename S::T;
+  const T *src = static_cast<const T *>(c->f[c->cur]);
+  T *dst = static_cast<T *>(c->f[c->cur ^ 1]);
+  const int *slots = ib ? wsp<int>(c, c->L.tile_slot) : nullptr;
+  const float *gbuf = wsp<float>(c, c->L.gbuf);
+  int *guard = wsp<int>(c, c->L.guard);
+  dim3 blk(c->bx, c->by);
+  const bool xper = a.g.xper;
+  if (xper && rot)
+    k_collide<S, true, true><<<grid, blk, 0, c->stream>>>(src, dst, a, slots, gbuf, guard);
+  else if (xper)
+    k_collide<S, true, false><<<grid, blk, 0, c->stream>>>(src, dst, a, slots, gbuf, guard);
+  else if (rot)
+    k_collide<S, false, true><<<grid, blk, 0, c->stream>>>(src, dst, a, slots, gbuf, guard);
+  else
+    k_collide<S, false, false><<<grid, blk, 0, c->stream>>>(src, dst, a, slots, gbuf, guard);
+  return launched();
+}
+
+template <class S>
+lbm_status launch_fill_macro(lbm_ctx *c, const IBArgs &a, bool rot, const float *X) {
+  using T = typename S::T;
+  const T *src = static_cast<const T *>(c->f[c->cur]);
+  const int grid = std::min(c->L.cap, 4096);
+  auto *act = wsp<int>(c, c->L.active);
+  auto *off = wsp<int>(c, c->L.tile_off);
+  auto *len = wsp<int>(c, c->L.tile_len);
+  auto *cnt = wsp<int>(c, c->L.counters);
+  auto *pairs = wsp<int>(c, c->L.pairs);
+  auto *macro = wsp<float4>(c, c->L.macro);
+  if (rot)
+    k_fill_macro<S, true><<<grid, 512, 0, c->stream>>>(src, X, act, off, len, cnt, pairs, macro, a);
+  else
+    k_fill_macro<S, false><<<grid, 512, 0, c->stream>>>(src, X, act, off, len, cnt, pairs, macro, a);
+  return launched();
+}
+
+lbm_status launch_spread(lbm_ctx *c, const IBArgs &a) {
+  const int grid = std::min(c->L.cap, 4096);
+  k_spread<<<grid, 512, 0, c->stream>>>(wsp<float>(c, c->L.rec), wsp<int>(c, c->L.active),
+                                        wsp<int>(c, c->L.tile_off), wsp<int>(c, c->L.tile_len),
+                                        wsp<int>(c, c->L.counters), wsp<int>(c, c->L.pairs),
+                                        wsp<float>(c, c->L.gbuf), a);
+  return launched();
+}
+
+lbm_status launch_interp(lbm_ctx *c, const lbm_markers *m, const IBArgs &a, bool rot, bool mdf) {
+  const int grid = (m->n + 3) / 4;
+  auto *mstate = wsp<float>(c, c->L.mstate);
+  auto *rec = wsp<float>(c, c->L.rec);
+  auto *slots = wsp<int>(c, c->L.tile_slot);
+  auto *macro = wsp<float4>(c, c->L.macro);
+  auto *gbuf = wsp<float>(c, c->L.gbuf);
+  auto *guard = wsp<int>(c, c->L.guard);
+#define LBM_INTERP(R, M) \
+  k_interp<R, M><<<grid, 256, 0, c->stream>>>(m->X, m->U, m->dv, m->F, mstate, rec, slots, macro, gbuf, a, guard)
+  if (rot && mdf)
+    LBM_INTERP(true, true);
+  else if (rot)
+    LBM_INTERP(true, false);
+  else if (mdf)
+    LBM_INTERP(false, true);
+  else
+    LBM_INTERP(false, false);
+#undef LBM_INTERP
+  return launched();
+}
+
+void prof_mark(lbm_ctx *c, int which) {
+  if (c->prof && c->prof_used < kProfSteps) (void)hipEventRecord(c->ev[3 * c->prof_used + which], c->stream);
+}
+
+template <class S>
+lbm_status step_one(lbm_ctx *c, const lbm_markers *m, const float *pose, const lbm_frame *frame, float *wrench) {
+  const FrameF fr = frame_f(frame);
+  const bool rot = rotating(frame);
+  const bool ib = m && m->n > 0;
+  lbm_status st;
+  prof_mark(c, 0);
+  if (ib) {
+    IBArgs a;
+    a.g = grid_args(c);
+    a.fr = fr;
+    a.n = m->n;
+    a.nbones = m->nbones;
+    a.alpha2 = (float)(2.0 * c->p.ib_alpha);
+    a.cap = c->L.cap;
+    auto *guard = wsp<int>(c, c->L.guard);
+    k_skin_count<<<(m->n + 255) / 256, 256, 0, c->stream>>>(m->xrest, m->bone, m->weight, pose, m->X, m->U,
+                                                             wsp<int>(c, c->L.tile_count), a, guard);
+    if ((st = launched()) != LBM_OK) return st;
+    k_tile_scan<<<1, 1024, 0, c->stream>>>(wsp<int>(c, c->L.tile_count), wsp<int>(c, c->L.tile_slot),
+                                           wsp<int>(c, c->L.active), wsp<int>(c, c->L.tile_off),
+                                           wsp<int>(c, c->L.tile_len), wsp<int>(c, c->L.counters), c->L.ntiles,
+                                           c->L.cap, guard);
+    if ((st = launched()) != LBM_OK) return st;
+    c->slots_dirty = true;
+    if ((st = launch_fill_macro<S>(c, a, rot, m->X)) != LBM_OK) return st;
+    if ((st = launch_interp(c, m, a, rot, false)) != LBM_OK) return st;
+    for (int it = 1; it < c->p.mdf_iters; ++it) {
+      if ((st = launch_spread(c, a)) != LBM_OK) return st;
+      if ((st = launch_interp(c, m, a, rot, true)) != LBM_OK) return st;
+    }
+    if ((st = launch_spread(c, a)) != LBM_OK) return st;
+  } else if (c->slots_dirty) {
+    // no body this step: clear the active-tile map so no stale force is read
+    k_fill_int<<<256, 256, 0, c->stream>>>(wsp<int>(c, c->L.tile_slot), -1, c->L.ntiles);
+    if ((st = launched()) != LBM_OK) return st;
+    c->slots_dirty = false;
+  }
+  prof_mark(c, 1);
+  if ((st = launch_collide<S>(c, fr, rot, ib)) != LBM_OK) return st;
+  prof_mark(c, 2);
+  if (c->prof && c->prof_used < kProfSteps) c->prof_used++;
+  if (ib && wrench) {
+    k_wrench<<<1, 1024, 0, c->stream>>>(m->X, m->U, m->F, m->dv, m->bone, m->weight, m->n, fr.org[0], fr.org[1],
+                                        fr.org[2], wrench);
+    if ((st = launched()) != LBM_OK) return st;
+  } else if (wrench) {
+    k_fill_int<<<1, 64, 0, c->stream>>>(reinterpret_cast<int *>(wrench), 0, 8);
+    if ((st = launched()) != LBM_OK) return st;
+  }
+  c->cur ^= 1;
+  c->steps += 1;
+  return LBM_OK;
+}
+
+template <class S>
+lbm_status init_eq(lbm_ctx *c, const float *rho0, const float *u0) {
+  GridArgs g = grid_args(c);
+  dim3 grid((c->p.nx + 63) / 64, c->p.ny, c->p.nz);
+  k_init_equilibrium<S><<<grid, 64, 0, c->stream>>>(rho0, u0, static_cast<typename S::T *>(c->f[c->cur]), g);
+  return launched();
+}
+
+template <class S>
+lbm_status load_canon(lbm_ctx *c, const float *f) {
+  GridArgs g = grid_args(c);
+  dim3 grid((c->p.nx + 63) / 64, c->p.ny, c->p.nz);
+  k_load_canonical<S><<<grid, 64, 0, c->stream>>>(f, static_cast<typename S::T *>(c->f[c->cur]), g);
+  return launched();
+}
+
+template <class S>
+lbm_status read_canon(lbm_ctx *c, float *f) {
+  GridArgs g = grid_args(c);
+  dim3 grid((c->p.nx + 63) / 64, c->p.ny, c->p.nz);
+  k_read_canonical<S><<<grid, 64, 0, c->stream>>>(static_cast<const typename S::T *>(c->f[c->cur]), f, g);
+  return launched();
+}
+
+template <class S>
+lbm_status macros(lbm_ctx *c, const lbm_frame *frame, float *rho, float *u) {
+  GridArgs g = grid_args(c);
+  dim3 grid((c->p.nx + 63) / 64, c->p.ny, c->p.nz);
+  const auto *src = static_cast<const typename S::T *>(c->f[c->cur]);
+  if (rotating(frame))
+    k_macros<S, true><<<grid, 64, 0, c->stream>>>(src, g, frame_f(frame), rho, u);
+  else
+    k_macros<S, false><<<grid, 64, 0, c->stream>>>(src, g, frame_f(frame), rho, u);
+  return launched();
+}
+
+#define LBM_BY_STORAGE(c, FN, ...)                                    \
+  ((c)->p.storage == LBM_STORE_F32   ? FN<StoreF32>(c, __VA_ARGS__)  \
+   : (c)->p.storage == LBM_STORE_F16 ? FN<StoreF16>(c, __VA_ARGS__)  \
+                                     : FN<StoreBF16>(c, __VA_ARGS__))
+
+bool markers_ok(const lbm_ctx *c, const lbm_markers *m) {
+  if (!m) return true;
+  if (m->n < 0) return false;
+  if (m->n == 0) return true;
+  if (!m->xrest || !m->bone || !m->weight || !m->dv || !m->X || !m->U || !m->F) return false;
+  if (m->nbones < 1 || m->nbones > c->p.max_bones) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_population_bytes(const lbm_params *p) {
+  if (!params_ok(p)) return 0;
+  return (size_t)27 * plane_elems(p) * elem_bytes(p->storage);
+}
+
+size_t lbm_workspace_bytes(const lbm_params *p) {
+  if (!params_ok(p)) return 0;
+  return layout(p).total;
+}
+
+lbm_status lbm_init(lbm_ctx **out, const lbm_params *p, void *f_a, void *f_b, void *workspace, const float *rho0,
+                    const float *u0, void *hip_stream) {
+  if (!out || !params_ok(p) || !f_a || !f_b || !workspace || f_a == f_b) return LBM_ERR_ARG;
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return LBM_ERR_ARG;
+  *out = nullptr;
+  lbm_ctx *c = new (std::nothrow) lbm_ctx;
+  if (!c) return LBM_ERR_ARG;
+  c->p = *p;
+  c->L = layout(p);
+  c->f[0] = f_a;
+  c->f[1] = f_b;
+  c->cur = 0;
+  c->ws = static_cast<char *>(workspace);
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->steps = 0;
+  c->plane = plane_elems(p);
+  c->slots_dirty = false;
+  c->prof = false;
+  c->prof_used = 0;
+  // collide block: 64-multiple along x covering as much of a row as fits
+  int bx = p->block_x, by = p->block_y;
+  if (bx == 0) {
+    const int chunks = (p->nx + 255) / 256;
+    bx = (int)align_up((size_t)((p->nx + chunks - 1) / chunks), 64);
+  }
+  if (by == 0) by = std::max(1, 256 / bx);
+  c->bx = bx;
+  c->by = by;
+  lbm_status st;
+  k_fill_int<<<256, 256, 0, c->stream>>>(wsp<int>(c, c->L.tile_count), 0, c->L.ntiles);
+  k_fill_int<<<256, 256, 0, c->stream>>>(wsp<int>(c, c->L.tile_slot), -1, c->L.ntiles);
+  k_fill_int<<<1, 64, 0, c->stream>>>(wsp<int>(c, c->L.guard), 0, 16);
+  k_fill_int<<<1, 64, 0, c->stream>>>(wsp<int>(c, c->L.counters), 0, 16);
+  if ((st = launched()) != LBM_OK || (st = LBM_BY_STORAGE(c, init_eq, rho0, u0)) != LBM_OK) {
+    delete c;
+    return st;
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+lbm_status lbm_load_populations(lbm_ctx *c, const float *f) {
+  if (!c || !f) return LBM_ERR_ARG;
+  c->steps = 0;
+  return LBM_BY_STORAGE(c, load_canon, f);
+}
+
+lbm_status lbm_read_populations(lbm_ctx *c, float *f) {
+  if (!c || !f) return LBM_ERR_ARG;
+  return LBM_BY_STORAGE(c, read_canon, f);
+}
+
+lbm_status lbm_macros(lbm_ctx *c, const lbm_frame *frame, float *rho, float *u) {
+  if (!c || (!rho && !u)) return LBM_ERR_ARG;
+  if (frame && !frame_ok(frame)) return LBM_ERR_ARG;
+  return LBM_BY_STORAGE(c, macros, frame, rho, u);
+}
+
+lbm_status lbm_ib_step(lbm_ctx *c, const lbm_markers *m, const float *poses, const lbm_frame *frames,
+                       int32_t nsteps, float *wrench) {
+  if (!c || nsteps < 0 || (nsteps > 0 && !frames)) return LBM_ERR_ARG;
+  if (!markers_ok(c, m)) return LBM_ERR_ARG;
+  const bool ib = m && m->n > 0;
+  if (ib && m->n > c->p.max_markers) return LBM_ERR_CAPACITY;
+  if (ib && !poses) return LBM_ERR_ARG;
+  for (int s = 0; s < nsteps; ++s)
+    if (!frame_ok(&frames[s])) return LBM_ERR_ARG;
+  for (int s = 0; s < nsteps; ++s) {
+    const float *pose = ib ? poses + (size_t)s * m->nbones * 24 : nullptr;
+    float *w = wrench ? wrench + (size_t)s * 8 : nullptr;
+    lbm_status st = LBM_BY_STORAGE(c, step_one, m, pose, &frames[s], w);
+    if (st != LBM_OK) return st;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_body_forces(lbm_ctx *c, const lbm_markers *m, const double *center, float *out) {
+  if (!c || !m || !center || !out || !markers_ok(c, m) || m->n <= 0) return LBM_ERR_ARG;
+  k_wrench<<<1 + m->nbones, 1024, 0, c->stream>>>(m->X, m->U, m->F, m->dv, m->bone, m->weight, m->n,
+                                                   (float)center[0], (float)center[1], (float)center[2], out);
+  return launched();
+}
+
+lbm_status lbm_check(lbm_ctx *c) {
+  if (!c) return LBM_ERR_ARG;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return LBM_ERR_DEVICE;
+  int guard = 0;
+  if (hipMemcpy(&guard, wsp<int>(c, c->L.guard), sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+    return LBM_ERR_DEVICE;
+  k_fill_int<<<1, 64, 0, c->stream>>>(wsp<int>(c, c->L.guard), 0, 1);
+  if (launched() != LBM_OK || hipStreamSynchronize(c->stream) != hipSuccess) return LBM_ERR_DEVICE;
+  if (guard & GUARD_UNSTABLE) return LBM_ERR_UNSTABLE;
+  if (guard & GUARD_MARKER_RANGE) return LBM_ERR_MARKER_RANGE;
+  if (guard & GUARD_CAPACITY) return LBM_ERR_CAPACITY;
+  if (guard & GUARD_BONE) return LBM_ERR_ARG;
+  return LBM_OK;
+}
+
+lbm_status lbm_profile_enable(lbm_ctx *c, int enable) {
+  if (!c) return LBM_ERR_ARG;
+  if (enable && c->ev.empty()) {
+    c->ev.resize(3 * kProfSteps);
+    for (auto &e : c->ev)
+      if (hipEventCreate(&e) != hipSuccess) return LBM_ERR_DEVICE;
+  }
+  c->prof = enable != 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_profile_collect(lbm_ctx *c, double *ib_ms, double *collide_ms, int64_t *steps) {
+  if (!c) return LBM_ERR_ARG;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return LBM_ERR_DEVICE;
+  double a = 0.0, b = 0.0;
+  for (int s = 0; s < c->prof_used; ++s) {
+    float t0 = 0.f, t1 = 0.f;
+    if (hipEventElapsedTime(&t0, c->ev[3 * s], c->ev[3 * s + 1]) != hipSuccess) return LBM_ERR_DEVICE;
+    if (hipEventElapsedTime(&t1, c->ev[3 * s + 1], c->ev[3 * s + 2]) != hipSuccess) return LBM_ERR_DEVICE;
+    a += t0;
+    b += t1;
+  }
+  if (ib_ms) *ib_ms = a;
+  if (collide_ms) *collide_ms = b;
+  if (steps) *steps = c->prof_used;
+  c->prof_used = 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_stream(lbm_ctx *c, void *hip_stream) {
+  if (!c) return LBM_ERR_ARG;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  return LBM_OK;
+}
+
+int64_t lbm_step_count(const lbm_ctx *c) { return c ? c->steps : -1; }
+
+const char *lbm_strerror(lbm_status s) {
+  switch (s) {
+    case LBM_OK: return "ok";
+    case LBM_ERR_ARG: return "invalid argument";
+    case LBM_ERR_DEVICE: return "HIP runtime or kernel launch failure";
+    case LBM_ERR_UNSTABLE: return "unstable state: non-finite value or |u| >= 0.4";
+    case LBM_ERR_MARKER_RANGE: return "marker within 2 cells (3 on the high side) of an open face";
+    case LBM_ERR_CAPACITY: return "capacity exceeded (markers or active tiles)";
+    case LBM_ERR_UNSUPPORTED: return "unsupported request";
+  }
+  return "unknown status";
+}
+
+void lbm_destroy(lbm_ctx *c) {
+  if (!c) return;
+  for (auto &e : c->ev) (void)hipEventDestroy(e);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,263 @@
+"""Python binding of the C interface in include/lbm_ib.h.
+
+Argument marshalling only: every step of the method runs in the HIP library
+(liblbmib.so, built in-tree by paper_2206_01683_amd.build). PyTorch supplies
+device memory and the stream. There is no CPU fallback: if the library is
+missing or no GPU is visible, constructing a Simulation raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbmib.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "lbm_ib.h")
+
+LBM_OK = 0
+STATUS = {0: "LBM_OK", -1: "LBM_ERR_ARG", -2: "LBM_ERR_DEVICE", -3: "LBM_ERR_UNSTABLE",
+          -4: "LBM_ERR_MARKER_RANGE", -5: "LBM_ERR_CAPACITY", -6: "LBM_ERR_UNSUPPORTED"}
+BC_PERIODIC, BC_VELOCITY, BC_OUTFLOW = 0, 1, 2
+STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("bc_lo", ctypes.c_int32), ("bc_hi", ctypes.c_int32), ("storage", ctypes.c_int32),
+                ("max_markers", ctypes.c_int32), ("max_bones", ctypes.c_int32), ("mdf_iters", ctypes.c_int32),
+                ("max_active_tiles", ctypes.c_int32), ("block_x", ctypes.c_int32), ("block_y", ctypes.c_int32),
+                ("tau", ctypes.c_double), ("ib_alpha", ctypes.c_double)]
+
+
+class Frame(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_double * 3) for name in ("acc", "omega", "alpha", "origin", "u_lo", "u_hi")]
+
+
+class Markers(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nbones", ctypes.c_int32),
+                ("xrest", ctypes.c_void_p), ("bone", ctypes.c_void_p), ("weight", ctypes.c_void_p),
+                ("dv", ctypes.c_void_p), ("X", ctypes.c_void_p), ("U", ctypes.c_void_p), ("F", ctypes.c_void_p)]
+
+
+class LBMError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        super().__init__(f"{what}: {STATUS.get(code, code)} ({strerror(code)})")
+
+
+_lib = None
+
+
+def lib():
+    """Load liblbmib.so. Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz = ctypes.c_void_p, ctypes.c_size_t
+        P = ctypes.POINTER(Params)
+        L.lbm_population_bytes.argtypes = [P]
+        L.lbm_population_bytes.restype = sz
+        L.lbm_workspace_bytes.argtypes = [P]
+        L.lbm_workspace_bytes.restype = sz
+        L.lbm_init.argtypes = [ctypes.POINTER(vp), P, vp, vp, vp, vp, vp, vp]
+        L.lbm_load_populations.argtypes = [vp, vp]
+        L.lbm_read_populations.argtypes = [vp, vp]
+        L.lbm_macros.argtypes = [vp, vp, vp, vp]
+        L.lbm_ib_step.argtypes = [vp, vp, vp, vp, ctypes.c_int32, vp]
+        L.lbm_body_forces.argtypes = [vp, vp, vp, vp]
+        L.lbm_check.argtypes = [vp]
+        L.lbm_set_stream.argtypes = [vp, vp]
+        L.lbm_profile_enable.argtypes = [vp, ctypes.c_int]
+        L.lbm_profile_collect.argtypes = [vp, vp, vp, vp]
+        L.lbm_step_count.argtypes = [vp]
+        L.lbm_step_count.restype = ctypes.c_int64
+        L.lbm_strerror.argtypes = [ctypes.c_int]
+        L.lbm_strerror.restype = ctypes.c_char_p
+        L.lbm_destroy.argtypes = [vp]
+        L.lbm_destroy.restype = None
+        for name in ("lbm_init", "lbm_load_populations", "lbm_read_populations", "lbm_macros", "lbm_ib_step",
+                     "lbm_body_forces", "lbm_check", "lbm_set_stream", "lbm_profile_enable",
+                     "lbm_profile_collect"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().lbm_strerror(int(code)).decode()
+    except Exception:
+        return "?"
+
+
+def _check(rc: int, what: str):
+    if rc != LBM_OK:
+        raise LBMError(rc, what)
+
+
+def make_params(nx, ny, nz, tau, bc_lo=BC_PERIODIC, bc_hi=BC_PERIODIC, storage="f32", max_markers=0,
+                max_bones=1, mdf_iters=1, ib_alpha=1.0, max_active_tiles=0, block=(0, 0)) -> Params:
+    return Params(nx, ny, nz, bc_lo, bc_hi, STORAGE[storage] if isinstance(storage, str) else storage,
+                  max_markers, max_bones, mdf_iters, max_active_tiles, block[0], block[1], tau, ib_alpha)
+
+
+def frames_array(frames: np.ndarray) -> np.ndarray:
+    """(nsteps, 18) float64, C-contiguous: the lbm_frame layout."""
+    fr = np.ascontiguousarray(frames, dtype=np.float64)
+    assert fr.ndim == 2 and fr.shape[1] == 18
+    return fr
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class DeviceMarkers:
+    """Marker arrays on the device in the lbm_markers layout (float32/int32)."""
+
+    def __init__(self, ms, device="cuda"):
+        dev = torch.device(device)
+        self.n = int(ms.xrest.shape[1])
+        self.nbones = int(ms.nbones)
+        self.xrest = torch.as_tensor(np.ascontiguousarray(ms.xrest, np.float32), device=dev)
+        self.bone = torch.as_tensor(np.ascontiguousarray(ms.bone, np.int32), device=dev)
+        self.weight = torch.as_tensor(np.ascontiguousarray(ms.weight, np.float32), device=dev)
+        self.dv = torch.as_tensor(np.ascontiguousarray(ms.dv, np.float32), device=dev)
+        self.X = torch.zeros((3, self.n), dtype=torch.float32, device=dev)
+        self.U = torch.zeros((3, self.n), dtype=torch.float32, device=dev)
+        self.F = torch.zeros((3, self.n), dtype=torch.float32, device=dev)
+
+    def struct(self) -> Markers:
+        return Markers(self.n, self.nbones, self.xrest.data_ptr(), self.bone.data_ptr(), self.weight.data_ptr(),
+                       self.dv.data_ptr(), self.X.data_ptr(), self.U.data_ptr(), self.F.data_ptr())
+
+
+class Simulation:
+    """One lattice with its two population buffers and workspace (torch-owned)."""
+
+    def __init__(self, nx, ny, nz, tau, bc_lo=BC_PERIODIC, bc_hi=BC_PERIODIC, storage="f32", max_markers=0,
+                 max_bones=1, mdf_iters=1, ib_alpha=1.0, rho0=None, u0=None, device="cuda", block=(0, 0),
+                 max_active_tiles=0, stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the lattice Boltzmann library runs only on the GPU")
+        L = lib()
+        self.device = torch.device(device)
+        self.shape = (nz, ny, nx)
+        self.params = make_params(nx, ny, nz, tau, bc_lo, bc_hi, storage, max_markers, max_bones, mdf_iters,
+                                  ib_alpha, max_active_tiles, block)
+        pb = L.lbm_population_bytes(ctypes.byref(self.params))
+        wb = L.lbm_workspace_bytes(ctypes.byref(self.params))
+        if pb == 0 or wb == 0:
+            raise LBMError(-1, "invalid parameters")
+        self.population_bytes = pb
+        self.workspace_bytes = wb
+        self.fa = torch.empty(pb, dtype=torch.uint8, device=self.device)
+        self.fb = torch.empty(pb, dtype=torch.uint8, device=self.device)
+        self._ws_raw = torch.empty(wb + 256, dtype=torch.uint8, device=self.device)
+        shift = (-self._ws_raw.data_ptr()) % 256
+        self.ws = self._ws_raw[shift:shift + wb]
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        rho0_t = None if rho0 is None else self._dev_f32(rho0)
+        u0_t = None if u0 is None else self._dev_f32(u0)
+        ctx = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(L.lbm_init(ctypes.byref(ctx), ctypes.byref(self.params), _ptr(self.fa), _ptr(self.fb),
+                              _ptr(self.ws), _ptr(rho0_t), _ptr(u0_t), ctypes.c_void_p(self.stream.cuda_stream)),
+                   "lbm_init")
+        self.ctx = ctx
+        self._keep = [rho0_t, u0_t]
+
+    def _dev_f32(self, a) -> torch.Tensor:
+        if isinstance(a, torch.Tensor):
+            return a.to(device=self.device, dtype=torch.float32).contiguous()
+        return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=self.device)
+
+    @property
+    def ncell(self) -> int:
+        nz, ny, nx = self.shape
+        return nx * ny * nz
+
+    def load_populations(self, f):
+        t = self._dev_f32(f)
+        assert t.numel() == 27 * self.ncell
+        _check(lib().lbm_load_populations(self.ctx, _ptr(t)), "lbm_load_populations")
+        self._keep.append(t)
+
+    def read_populations(self) -> torch.Tensor:
+        out = torch.empty((27,) + self.shape, dtype=torch.float32, device=self.device)
+        _check(lib().lbm_read_populations(self.ctx, _ptr(out)), "lbm_read_populations")
+        return out
+
+    def macros(self, frame=None):
+        rho = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        u = torch.empty((3,) + self.shape, dtype=torch.float32, device=self.device)
+        fr = None
+        if frame is not None:
+            fr = frames_array(np.asarray(frame).reshape(1, 18))
+        _check(lib().lbm_macros(self.ctx, None if fr is None else fr.ctypes.data_as(ctypes.c_void_p),
+                                _ptr(rho), _ptr(u)), "lbm_macros")
+        return rho, u
+
+    def step(self, frames, markers: Optional[DeviceMarkers] = None, poses: Optional[torch.Tensor] = None,
+             wrench: Optional[torch.Tensor] = None, nsteps: Optional[int] = None):
+        fr = frames_array(frames)
+        n = fr.shape[0] if nsteps is None else int(nsteps)
+        assert fr.shape[0] >= n
+        ms = None
+        if markers is not None:
+            ms = markers.struct()
+            assert poses is not None and poses.dtype == torch.float32 and poses.is_contiguous()
+            assert poses.shape[0] >= n and poses.shape[1] == markers.nbones and poses.shape[2] == 24
+        if wrench is not None:
+            assert wrench.dtype == torch.float32 and wrench.is_contiguous() and wrench.numel() >= 8 * n
+        _check(lib().lbm_ib_step(self.ctx, None if ms is None else ctypes.byref(ms), _ptr(poses),
+                                 fr.ctypes.data_as(ctypes.c_void_p), n, _ptr(wrench)), "lbm_ib_step")
+
+    def body_forces(self, markers: DeviceMarkers, center) -> torch.Tensor:
+        out = torch.empty((1 + markers.nbones, 8), dtype=torch.float32, device=self.device)
+        c = np.ascontiguousarray(center, dtype=np.float64)
+        ms = markers.struct()
+        _check(lib().lbm_body_forces(self.ctx, ctypes.byref(ms), c.ctypes.data_as(ctypes.c_void_p), _ptr(out)),
+               "lbm_body_forces")
+        return out
+
+    def profile(self, enable: bool = True):
+        _check(lib().lbm_profile_enable(self.ctx, 1 if enable else 0), "lbm_profile_enable")
+
+    def profile_collect(self):
+        """(ib_ms_total, collide_ms_total, timed_steps) since the last collect."""
+        a, b, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        _check(lib().lbm_profile_collect(self.ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)),
+               "lbm_profile_collect")
+        return a.value, b.value, n.value
+
+    def check(self) -> int:
+        return lib().lbm_check(self.ctx)
+
+    def step_count(self) -> int:
+        return lib().lbm_step_count(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib().lbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def header_functions(path: str = HEADER_PATH):
+    """Names of the functions declared in the public header."""
+    import re
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text)))

@@ -1,0 +1,79 @@
+"""C interface contract, checked without a GPU: the library loads, exports
+every function the header declares, validates parameters on the host and
+reports errors by status code."""
+import ctypes
+
+import pytest
+
+from paper_2206_01683_amd import lbm
+
+
+@pytest.fixture(scope="module")
+def L():
+    return lbm.lib()
+
+
+def test_every_declared_function_is_exported(L):
+    names = lbm.header_functions()
+    assert "lbm_init" in names and "lbm_ib_step" in names and "lbm_body_forces" in names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_population_and_workspace_sizes(L):
+    p = lbm.make_params(64, 32, 32, 0.6, lbm.BC_VELOCITY, lbm.BC_OUTFLOW, max_markers=500)
+    pb = L.lbm_population_bytes(ctypes.byref(p))
+    assert pb >= 27 * 64 * 32 * 32 * 4 and pb % 256 == 0
+    p16 = lbm.make_params(64, 32, 32, 0.6, storage="f16")
+    assert L.lbm_population_bytes(ctypes.byref(p16)) * 2 == L.lbm_population_bytes(
+        ctypes.byref(lbm.make_params(64, 32, 32, 0.6)))
+    assert L.lbm_workspace_bytes(ctypes.byref(p)) > 0
+
+
+@pytest.mark.parametrize("bad", [
+    dict(tau=0.5), dict(tau=0.3), dict(nx=3), dict(nz=0),
+    dict(bc_lo=lbm.BC_PERIODIC, bc_hi=lbm.BC_OUTFLOW), dict(storage=7), dict(max_bones=0),
+    dict(mdf_iters=0), dict(block=(96, 1)), dict(block=(512, 2)), dict(ib_alpha=0.0),
+])
+def test_invalid_parameters_are_rejected(L, bad):
+    kw = dict(nx=16, ny=16, nz=16, tau=0.6, bc_lo=lbm.BC_VELOCITY, bc_hi=lbm.BC_OUTFLOW)
+    kw.update(bad)
+    p = lbm.make_params(**kw)
+    assert L.lbm_population_bytes(ctypes.byref(p)) == 0
+    assert L.lbm_workspace_bytes(ctypes.byref(p)) == 0
+    ctx = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(256)
+    rc = L.lbm_init(ctypes.byref(ctx), ctypes.byref(p), dummy, ctypes.c_void_p(512), ctypes.c_void_p(1024),
+                    None, None, None)
+    assert rc == -1 and not ctx.value
+
+
+def test_init_rejects_null_or_aliased_buffers(L):
+    p = lbm.make_params(16, 16, 16, 0.6)
+    ctx = ctypes.c_void_p()
+    assert L.lbm_init(ctypes.byref(ctx), ctypes.byref(p), None, ctypes.c_void_p(512), ctypes.c_void_p(1024),
+                      None, None, None) == -1
+    assert L.lbm_init(ctypes.byref(ctx), ctypes.byref(p), ctypes.c_void_p(512), ctypes.c_void_p(512),
+                      ctypes.c_void_p(1024), None, None, None) == -1
+    # misaligned workspace
+    assert L.lbm_init(ctypes.byref(ctx), ctypes.byref(p), ctypes.c_void_p(512), ctypes.c_void_p(1024),
+                      ctypes.c_void_p(1000), None, None, None) == -1
+    assert L.lbm_init(None, ctypes.byref(p), ctypes.c_void_p(512), ctypes.c_void_p(1024),
+                      ctypes.c_void_p(1024), None, None, None) == -1
+
+
+def test_calls_on_null_context_fail_cleanly(L):
+    assert L.lbm_ib_step(None, None, None, None, 1, None) == -1
+    assert L.lbm_check(None) == -1
+    assert L.lbm_read_populations(None, None) == -1
+    assert L.lbm_macros(None, None, None, None) == -1
+    assert L.lbm_body_forces(None, None, None, None) == -1
+    assert L.lbm_step_count(None) == -1
+    L.lbm_destroy(None)
+
+
+def test_strerror_covers_every_status(L):
+    for code in lbm.STATUS:
+        s = lbm.strerror(code)
+        assert s and s != "unknown status"
+    assert lbm.strerror(42) == "unknown status"
