@@ -3,19 +3,17 @@
 //
 // The immersed force lives only in "active" 8x8x8 tiles: tiles that some
 // marker's 4x4x4 Peskin stencil touches. Each step rebuilds the active set:
-//   k_skin_count    skin markers (linear blend skinning), wrap/check range,
-//                   count markers per touched tile
-//   k_tile_scan     one workgroup: tile counts -> slots, list offsets; clears
-//                   the counts for the next step
-//   k_fill_macro    per active tile: ordered list of its markers (increasing
-//                   marker index, so spreading is deterministic) and the
-//                   density and unforced velocity of its 512 cells
+//   k_skin_mark     skin markers (linear blend skinning), wrap/check range,
+//                   flag the tiles each stencil touches
+//   k_active        compact the flags into a slot map and an active list
+//   k_macro         density and unforced velocity of every active-tile cell
 //   k_interp        one wave64 per marker, one lane per stencil node: weights,
-//                   wave-level sums -> U*_k, rho_k, direct forcing F_k
-//   k_spread        per active tile, one wave per 4x4x4 octant, marker records
-//                   staged in LDS: g(x) = sum_k F_k dV_k delta(x - X_k) with no
-//                   global atomics
-//   k_wrench        one workgroup: force, torque, power of the fluid on the body
+//                   wave-level sums -> U*_k, rho_k, direct forcing F_k, and the
+//                   body wrench reduced in workgroup order
+//   k_spread        per active tile: LDS fixed-point accumulation of the
+//                   markers touching it - order-independent (deterministic)
+//                   gather-form spreading without global atomics
+//   k_wrench        per-bone wrench for the body-forces query
 #pragma once
 
 #include "fluid.hpp"
@@ -63,16 +61,27 @@ __device__ inline bool axis_touches(int base, int n, bool per, int tile) {
   return hit;
 }
 
-// Linear blend skinning, domain handling and tile counting (one thread per marker).
-// Periodic axes: X is wrapped into [0, n). Open x: markers must satisfy
-// 2 <= X < nx - 3 so the stencil stays on nodes 1 .. nx-2; others raise the
-// range guard and are clamped so that every access stays in bounds.
-__global__ void k_skin_count(const float *__restrict__ xrest, const int *__restrict__ bone,
-                             const float *__restrict__ weight, const float *__restrict__ pose, float *__restrict__ X,
-                             float *__restrict__ U, int *__restrict__ tile_count, IBArgs a, int *__restrict__ guard) {
+// Linear blend skinning, domain handling and active-tile marking (one thread
+// per marker). Periodic axes: X is wrapped into [0, n). Open x: markers must
+// satisfy 2 <= X < nx - 3 so the stencil stays on nodes 1 .. nx-2; others
+// raise the range guard and are clamped so that every access stays in bounds.
+// Every tile a marker's stencil touches gets flag 1 (plain stores of one
+// value: no atomics). mbase[k] keeps the stencil base node per axis for the
+// spreading scan. Thread 0 also clears the active-tile counter of this step.
+// Launched with 64-thread-aligned blocks: wave c (markers 64c .. 64c+63) also
+// writes chunk_box[c], the range of tiles its markers' stencils touch per
+// axis (whole axis when a stencil wraps), so spreading can skip chunks.
+__global__ void k_skin_mark(const float *__restrict__ xrest, const int *__restrict__ bone,
+                            const float *__restrict__ weight, const float *__restrict__ pose, float *__restrict__ X,
+                            float *__restrict__ U, short4 *__restrict__ mbase, int *__restrict__ tile_flag,
+                            int4 *__restrict__ chunk_box, int *__restrict__ counters, IBArgs a,
+                            int *__restrict__ guard) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = a.n;
-  if (k >= n) return;
+  if (k == 0) counters[0] = 0;
+  const int tns[3] = {a.g.tnx, a.g.tny, (a.g.nz + 7) >> 3};
+  int lo[3] = {1 << 20, 1 << 20, 1 << 20}, hi[3] = {-1, -1, -1};
+  if (k < n) {
   const float r0 = xrest[k], r1 = xrest[n + k], r2 = xrest[2 * n + k];
   float p[3] = {0.f, 0.f, 0.f}, v[3] = {0.f, 0.f, 0.f};
 #pragma unroll
@@ -107,110 +116,88 @@ __global__ void k_skin_count(const float *__restrict__ xrest, const int *__restr
     X[ax * n + k] = p[ax];
     U[ax * n + k] = v[ax];
   }
+  const int bs[3] = {stencil_base(p[0]), stencil_base(p[1]), stencil_base(p[2])};
+  mbase[k] = make_short4((short)bs[0], (short)bs[1], (short)bs[2], 0);
   int tx[3], ty[3], tz[3];
-  const int nxt = axis_tiles(stencil_base(p[0]), a.g.nx, a.g.xper, tx);
-  const int nyt = axis_tiles(stencil_base(p[1]), a.g.ny, true, ty);
-  const int nzt = axis_tiles(stencil_base(p[2]), a.g.nz, true, tz);
+  const int nxt = axis_tiles(bs[0], a.g.nx, a.g.xper, tx);
+  const int nyt = axis_tiles(bs[1], a.g.ny, true, ty);
+  const int nzt = axis_tiles(bs[2], a.g.nz, true, tz);
   for (int i = 0; i < nzt; ++i)
     for (int j = 0; j < nyt; ++j)
-      for (int l = 0; l < nxt; ++l) atomicAdd(&tile_count[tx[l] + a.g.tnx * (ty[j] + a.g.tny * tz[i])], 1);
+      for (int l = 0; l < nxt; ++l) tile_flag[tx[l] + a.g.tnx * (ty[j] + a.g.tny * tz[i])] = 1;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    if (bs[ax] < 0 || bs[ax] + 3 >= dims[ax]) {  // wrapping stencil: whole axis
+      lo[ax] = 0;
+      hi[ax] = tns[ax] - 1;
+    } else {
+      lo[ax] = bs[ax] >> 3;
+      hi[ax] = (bs[ax] + 3) >> 3;
+    }
+  }
+  }
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      lo[ax] = min(lo[ax], __shfl_xor(lo[ax], o, 64));
+      hi[ax] = max(hi[ax], __shfl_xor(hi[ax], o, 64));
+    }
+  }
+  if ((threadIdx.x & 63) == 0 && k < n)
+    chunk_box[k >> 6] = make_int4(lo[0] | (hi[0] << 16), lo[1] | (hi[1] << 16), lo[2] | (hi[2] << 16), 0);
 }
 
-// Single workgroup: exclusive scans of (count > 0) and count over all tiles.
-// counters[0] = number of active tiles (capped), counters[1] = list entries.
-__global__ void __launch_bounds__(1024) k_tile_scan(int *__restrict__ tile_count, int *__restrict__ tile_slot,
-                                                    int *__restrict__ active, int *__restrict__ tile_off,
-                                                    int *__restrict__ tile_len, int *__restrict__ counters,
-                                                    int ntiles, int cap, int *__restrict__ guard) {
-  __shared__ int s_act[1024];
-  __shared__ int s_sum[1024];
-  const int tid = threadIdx.x;
-  const int chunk = (ntiles + 1023) / 1024;
-  const int t0 = min(tid * chunk, ntiles), t1 = min(t0 + chunk, ntiles);
-  int act = 0, sum = 0;
-  for (int t = t0; t < t1; ++t) {
-    int c = tile_count[t];
-    act += c > 0;
-    sum += c;
+// Compaction of the flagged tiles (1024 tiles per workgroup): slots in
+// workgroup order from one atomic per workgroup. Slot numbering only decides
+// storage locations, never results. Clears the flags for the next step.
+__global__ void __launch_bounds__(1024) k_active(int *__restrict__ tile_flag, int *__restrict__ tile_slot,
+                                                 int *__restrict__ active, int *__restrict__ counters, int ntiles,
+                                                 int cap, int *__restrict__ guard) {
+  __shared__ int s_w[16];
+  __shared__ int s_base;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int t = blockIdx.x * 1024 + tid;
+  int f = 0;
+  if (t < ntiles) {
+    f = tile_flag[t] != 0;
+    tile_flag[t] = 0;
   }
-  s_act[tid] = act;
-  s_sum[tid] = sum;
+  const unsigned long long bal = __ballot(f);
+  if (lane == 0) s_w[wv] = __popcll(bal);
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    int va = tid >= off ? s_act[tid - off] : 0;
-    int vs = tid >= off ? s_sum[tid - off] : 0;
-    __syncthreads();
-    s_act[tid] += va;
-    s_sum[tid] += vs;
-    __syncthreads();
+  if (tid == 0) {
+    int tot = 0;
+    for (int q = 0; q < 16; ++q) tot += s_w[q];
+    s_base = tot ? atomicAdd(&counters[0], tot) : 0;
   }
-  int slot = s_act[tid] - act, pos = s_sum[tid] - sum;
-  bool over = false;
-  for (int t = t0; t < t1; ++t) {
-    int c = tile_count[t];
-    if (c > 0) {
-      if (slot < cap) {
-        tile_slot[t] = slot;
-        active[slot] = t;
-        tile_off[slot] = pos;
-        tile_len[slot] = c;
-      } else {
-        tile_slot[t] = -1;
-        over = true;
-      }
-      ++slot;
-      pos += c;
+  __syncthreads();
+  int pre = s_base;
+  for (int q = 0; q < wv; ++q) pre += s_w[q];
+  pre += __popcll(bal & ((1ull << lane) - 1ull));
+  if (t < ntiles) {
+    if (f && pre < cap) {
+      tile_slot[t] = pre;
+      active[pre] = t;
     } else {
       tile_slot[t] = -1;
+      if (f) atomicOr(guard, (int)GUARD_CAPACITY);
     }
-    tile_count[t] = 0;
-  }
-  if (over) atomicOr(guard, (int)GUARD_CAPACITY);
-  if (tid == 1023) {
-    counters[0] = min(s_act[1023], cap);
-    counters[1] = s_sum[1023];
   }
 }
 
-// Per active tile (grid-stride over slots, 512 threads = the tile's cells):
-// (a) list of the markers touching the tile, in increasing marker index;
-// (b) density and unforced velocity u* (frame force, no IB force) per cell.
+// Density and unforced velocity u* (frame force, no IB force) of every cell
+// of every active tile (grid-stride over slots, 512 threads = the tile).
 template <class S, bool ROT>
-__global__ void __launch_bounds__(512) k_fill_macro(const typename S::T *__restrict__ src, const float *__restrict__ X,
-                                                    const int *__restrict__ active, const int *__restrict__ tile_off,
-                                                    const int *__restrict__ tile_len, const int *__restrict__ counters,
-                                                    int *__restrict__ pairs, float4 *__restrict__ macro, IBArgs a) {
-  __shared__ int s_cnt[8];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int n_active = counters[0];
+__global__ void __launch_bounds__(512) k_macro(const typename S::T *__restrict__ src, const int *__restrict__ active,
+                                               const int *__restrict__ counters, float4 *__restrict__ macro,
+                                               IBArgs a) {
+  const int tid = threadIdx.x;
+  const int n_active = min(counters[0], a.cap);
   const GridArgs &g = a.g;
   for (int slot = blockIdx.x; slot < n_active; slot += gridDim.x) {
     const int t = active[slot];
     const int tx = t % g.tnx, ty = (t / g.tnx) % g.tny, tz = t / (g.tnx * g.tny);
-    const int off = tile_off[slot], len = tile_len[slot];
-    int running = 0;
-    for (int base = 0; base < a.n; base += 512) {
-      const int k = base + tid;
-      bool hit = false;
-      if (k < a.n) {
-        hit = axis_touches(stencil_base(X[k]), g.nx, g.xper, tx) &&
-              axis_touches(stencil_base(X[a.n + k]), g.ny, true, ty) &&
-              axis_touches(stencil_base(X[2 * a.n + k]), g.nz, true, tz);
-      }
-      const unsigned long long bal = __ballot(hit);
-      if (lane == 0) s_cnt[wv] = __popcll(bal);
-      __syncthreads();
-      int woff = 0, total = 0;
-      for (int q = 0; q < 8; ++q) {
-        woff += q < wv ? s_cnt[q] : 0;
-        total += s_cnt[q];
-      }
-      const int pos = running + woff + __popcll(bal & ((1ull << lane) - 1ull));
-      if (hit && pos < len) pairs[off + pos] = k;
-      running += total;
-      __syncthreads();
-    }
-    // cell of this thread
     const int x = tx * 8 + (tid & 7), y = ty * 8 + ((tid >> 3) & 7), z = tz * 8 + (tid >> 6);
     float4 out = make_float4(1.f, 0.f, 0.f, 0.f);
     if (x < g.nx && y < g.ny && z < g.nz && (g.xper || (x > 0 && x < g.nx - 1))) {
@@ -238,154 +225,234 @@ __device__ inline float wave_sum(float v) {
   return v;
 }
 
-// One wave64 per marker; lane l is stencil node (l & 3, (l >> 2) & 3, l >> 4).
+// One wave64 per marker (16 per workgroup); lane l is stencil node
+// (l & 3, (l >> 2) & 3, l >> 4).
 // pass 0: U*_k = sum u* delta, rho_k = sum rho delta, F_k = 2 alpha rho_k (U_k - U*_k).
 // pass p > 0 (multi-direct forcing): the interpolated velocity includes the
 // current immersed force, u = u* + (I + [omega]x)^-1 g / (2 rho), and
 // F_k += 2 alpha rho_k (U_k - U_k^interp).
+// On the last pass (partials != nullptr): the fluid's force, torque about
+// the frame origin and power, summed per workgroup into partials[block][8];
+// k_spread adds them up in workgroup order.
 template <bool ROT, bool MDF>
-__global__ void __launch_bounds__(256) k_interp(const float *__restrict__ X, const float *__restrict__ U,
-                                                const float *__restrict__ dv, float *__restrict__ F,
-                                                float *__restrict__ mstate, float *__restrict__ rec,
-                                                const int *__restrict__ tile_slot, const float4 *__restrict__ macro,
-                                                const float *__restrict__ gbuf, IBArgs a, int *__restrict__ guard) {
-  const int lane = threadIdx.x & 63;
-  const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+__global__ void __launch_bounds__(1024) k_interp(const float *__restrict__ X, const float *__restrict__ U,
+                                                 const float *__restrict__ dv, float *__restrict__ F,
+                                                 float *__restrict__ mstate, float *__restrict__ rec,
+                                                 const int *__restrict__ tile_slot, const float4 *__restrict__ macro,
+                                                 const float *__restrict__ gbuf, IBArgs a, int *__restrict__ guard,
+                                                 float *__restrict__ partials) {
+  __shared__ float s_part[16][8];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int k = blockIdx.x * 16 + wv;
   const int n = a.n;
-  if (k >= n) return;
   const GridArgs &g = a.g;
-  const float Xk[3] = {X[k], X[n + k], X[2 * n + k]};
-  const int s3[3] = {lane & 3, (lane >> 2) & 3, lane >> 4};
-  const int dims[3] = {g.nx, g.ny, g.nz};
-  int base[3], node[3];
-  float w[3];
+  float part[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (k < n) {
+    const float Xk[3] = {X[k], X[n + k], X[2 * n + k]};
+    const int s3[3] = {lane & 3, (lane >> 2) & 3, lane >> 4};
+    const int dims[3] = {g.nx, g.ny, g.nz};
+    int base[3], node[3];
+    float w[3];
 #pragma unroll
-  for (int ax = 0; ax < 3; ++ax) {
-    base[ax] = stencil_base(Xk[ax]);
-    const int j = base[ax] + s3[ax];
-    w[ax] = peskin4(Xk[ax] - (float)j);
-    node[ax] = (ax > 0 || g.xper) ? wrap_idx(j, dims[ax]) : j;
-  }
-  const int t = (node[0] >> 3) + g.tnx * ((node[1] >> 3) + g.tny * (node[2] >> 3));
-  const int s = tile_slot[t];
-  float rho = 0.f, ux = 0.f, uy = 0.f, uz = 0.f;
-  if (s >= 0) {
-    const int lc = (node[0] & 7) | ((node[1] & 7) << 3) | ((node[2] & 7) << 6);
-    const float4 m = macro[(size_t)s * 512 + lc];
-    rho = m.x;
-    ux = m.y;
-    uy = m.z;
-    uz = m.w;
-    if (MDF) {
-      const float *gp = gbuf + (size_t)s * 1536;
-      const float h = 0.5f / rho;
-      float dx, dy, dz;
-      solve_coriolis<ROT>(a.fr, gp[lc] * h, gp[512 + lc] * h, gp[1024 + lc] * h, dx, dy, dz);
-      ux += dx;
-      uy += dy;
-      uz += dz;
+    for (int ax = 0; ax < 3; ++ax) {
+      base[ax] = stencil_base(Xk[ax]);
+      const int j = base[ax] + s3[ax];
+      w[ax] = peskin4(Xk[ax] - (float)j);
+      node[ax] = (ax > 0 || g.xper) ? wrap_idx(j, dims[ax]) : j;
     }
-  } else {
-    atomicOr(guard, (int)GUARD_CAPACITY);
-  }
-  const float d = w[0] * w[1] * w[2];
-  const float sr = wave_sum(rho * d), sx = wave_sum(ux * d), sy = wave_sum(uy * d), sz = wave_sum(uz * d);
-  float *r = rec + (size_t)k * REC;
-  if (lane < 4) r[lane] = w[0];                             // s3 = (lane, 0, 0)
-  if ((lane & 3) == 0 && lane < 16) r[4 + (lane >> 2)] = w[1];  // s3 = (0, lane/4, 0)
-  if ((lane & 15) == 0) r[8 + (lane >> 4)] = w[2];          // s3 = (0, 0, lane/16)
-  if (lane == 0) {
-    float rk;
-    float Fk[3];
-    const float Uk[3] = {U[k], U[n + k], U[2 * n + k]};
-    const float Ui[3] = {sx, sy, sz};
-    if (!MDF) {
-      rk = sr;
-      mstate[k] = rk;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        mstate[(c + 1) * (size_t)n + k] = Ui[c];
-        Fk[c] = a.alpha2 * rk * (Uk[c] - Ui[c]);
+    const int t = (node[0] >> 3) + g.tnx * ((node[1] >> 3) + g.tny * (node[2] >> 3));
+    const int s = tile_slot[t];
+    float rho = 0.f, ux = 0.f, uy = 0.f, uz = 0.f;
+    if (s >= 0) {
+      const int lc = (node[0] & 7) | ((node[1] & 7) << 3) | ((node[2] & 7) << 6);
+      const float4 m = macro[(size_t)s * 512 + lc];
+      rho = m.x;
+      ux = m.y;
+      uy = m.z;
+      uz = m.w;
+      if (MDF) {
+        const float *gp = gbuf + (size_t)s * 1536;
+        const float h = 0.5f / rho;
+        float dx, dy, dz;
+        solve_coriolis<ROT>(a.fr, gp[lc] * h, gp[512 + lc] * h, gp[1024 + lc] * h, dx, dy, dz);
+        ux += dx;
+        uy += dy;
+        uz += dz;
       }
     } else {
-      rk = mstate[k];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) Fk[c] = F[c * n + k] + a.alpha2 * rk * (Uk[c] - Ui[c]);
+      atomicOr(guard, (int)GUARD_CAPACITY);
     }
-    const float dvk = dv[k];
+    const float d = w[0] * w[1] * w[2];
+    const float sr = wave_sum(rho * d), sx = wave_sum(ux * d), sy = wave_sum(uy * d), sz = wave_sum(uz * d);
+    float *r = rec + (size_t)k * REC;
+    if (lane < 4) r[lane] = w[0];                                 // s3 = (lane, 0, 0)
+    if ((lane & 3) == 0 && lane < 16) r[4 + (lane >> 2)] = w[1];  // s3 = (0, lane/4, 0)
+    if ((lane & 15) == 0) r[8 + (lane >> 4)] = w[2];              // s3 = (0, 0, lane/16)
+    if (lane == 0) {
+      float rk;
+      float Fk[3];
+      const float Uk[3] = {U[k], U[n + k], U[2 * n + k]};
+      const float Ui[3] = {sx, sy, sz};
+      if (!MDF) {
+        rk = sr;
+        mstate[k] = rk;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      F[c * n + k] = Fk[c];
-      r[16 + c] = Fk[c] * dvk;
-      r[12 + c] = __int_as_float(base[c]);
+        for (int c = 0; c < 3; ++c) {
+          mstate[(c + 1) * (size_t)n + k] = Ui[c];
+          Fk[c] = a.alpha2 * rk * (Uk[c] - Ui[c]);
+        }
+      } else {
+        rk = mstate[k];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Fk[c] = F[c * n + k] + a.alpha2 * rk * (Uk[c] - Ui[c]);
+      }
+      const float dvk = dv[k];
+      float fd[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        F[c * n + k] = Fk[c];
+        fd[c] = Fk[c] * dvk;
+        r[16 + c] = fd[c];
+        r[12 + c] = __int_as_float(base[c]);
+      }
+      // fluid on body: -F dV; torque (X - x0) x (-F dV); power F.U dV
+      const float rx = Xk[0] - a.fr.org[0], ry = Xk[1] - a.fr.org[1], rz = Xk[2] - a.fr.org[2];
+      part[0] = -fd[0];
+      part[1] = -fd[1];
+      part[2] = -fd[2];
+      part[3] = -(ry * fd[2] - rz * fd[1]);
+      part[4] = -(rz * fd[0] - rx * fd[2]);
+      part[5] = -(rx * fd[1] - ry * fd[0]);
+      part[6] = fd[0] * Uk[0] + fd[1] * Uk[1] + fd[2] * Uk[2];
     }
+  }
+  if (partials == nullptr) return;  // uniform over the grid
+  if (lane == 0)
+    for (int q = 0; q < 7; ++q) s_part[wv][q] = part[q];
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    float sum = 0.f;
+    if (threadIdx.x < 7)
+      for (int q = 0; q < 16; ++q) sum += s_part[q][threadIdx.x];
+    partials[(size_t)blockIdx.x * 8 + threadIdx.x] = sum;
   }
 }
 
-// Per active tile (grid-stride over slots, 512 threads): wave w owns the
-// 4x4x4 octant (w & 1, (w >> 1) & 1, w >> 2) of the tile, lane l one cell of
-// it. The tile's marker list is staged through LDS in chunks; each wave keeps
-// the markers whose stencil meets its octant (order preserved) and every lane
-// accumulates its own cell's force in a register.
-__global__ void __launch_bounds__(512) k_spread(const float *__restrict__ rec, const int *__restrict__ active,
-                                                const int *__restrict__ tile_off, const int *__restrict__ tile_len,
-                                                const int *__restrict__ counters, const int *__restrict__ pairs,
-                                                float *__restrict__ gbuf, IBArgs a) {
-  __shared__ float s_rec[512 * REC];
-  __shared__ unsigned short s_idx[8][512];
+__device__ inline float bcast(float v, int j) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
+
+__device__ inline bool box_hits(int packed, int t) { return t >= (packed & 0xFFFF) && t <= (packed >> 16); }
+
+// Fixed-point scale of the spreading accumulator: contributions are rounded
+// to multiples of 2^-40 and summed as 64-bit integers. Integer addition is
+// associative, so the sum does not depend on the order in which waves add.
+constexpr float kFix = 1099511627776.0f;  // 2^40
+constexpr float kUnfix = 1.0f / 1099511627776.0f;
+
+// Per active tile (grid-stride over slots, 1024 threads = 16 waves):
+// gather-form spreading g(x) = sum_k F_k dV_k delta(x - X_k) over the tile's
+// 512 cells into one LDS accumulator, with no global atomics.
+// Wave w owns marker chunks w, w+16, w+32, ... (64 markers each). It loads 64
+// of its chunk boxes at once and keeps the chunks whose box meets the tile;
+// in each such chunk every lane tests its own marker and loads its record,
+// and the hits are broadcast one by one to the 64 lanes (one per stencil
+// node), which add their node's contribution with LDS atomics.
+// Workgroup 0 first adds the interpolation kernel's wrench partials in order.
+__global__ void __launch_bounds__(1024) k_spread(const float *__restrict__ rec, const short4 *__restrict__ mbase,
+                                                 const int4 *__restrict__ chunk_box,
+                                                 const int *__restrict__ active, const int *__restrict__ counters,
+                                                 float *__restrict__ gbuf, IBArgs a,
+                                                 const float *__restrict__ partials, int nparts,
+                                                 float *__restrict__ wrench) {
+  __shared__ unsigned long long s_acc[3][512];
+  __shared__ float s_red[1024];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const GridArgs &g = a.g;
-  const int n_active = counters[0];
+  const int n = a.n;
+  const int nchunks = (n + 63) >> 6;
+  if (blockIdx.x == 0 && wrench != nullptr) {
+    const int col = tid & 7, row0 = tid >> 3;
+    float acc = 0.f;
+    if (col < 7)
+      for (int b = row0; b < nparts; b += 128) acc += partials[(size_t)b * 8 + col];
+    s_red[tid] = acc;
+    __syncthreads();
+    if (tid < 8) {
+      float sum = 0.f;
+      for (int r2 = 0; r2 < 128; ++r2) sum += s_red[r2 * 8 + tid];
+      wrench[tid] = tid < 7 ? sum : 0.f;
+    }
+  }
+  const int n_active = min(counters[0], a.cap);
+  const int s3x = lane & 3, s3y = (lane >> 2) & 3, s3z = lane >> 4;
   for (int slot = blockIdx.x; slot < n_active; slot += gridDim.x) {
     const int t = active[slot];
     const int tx = t % g.tnx, ty = (t / g.tnx) % g.tny, tz = t / (g.tnx * g.tny);
-    const int ox = tx * 8 + 4 * (wv & 1), oy = ty * 8 + 4 * ((wv >> 1) & 1), oz = tz * 8 + 4 * (wv >> 2);
-    const int cx = ox + (lane & 3), cy = oy + ((lane >> 2) & 3), cz = oz + (lane >> 4);
-    const int off = tile_off[slot], len = tile_len[slot];
-    float gx = 0.f, gy = 0.f, gz = 0.f;
-    for (int c0 = 0; c0 < len; c0 += 512) {
-      const int m = min(512, len - c0);
-      if (tid < m) {
-        const float *src = rec + (size_t)pairs[off + c0 + tid] * REC;
-#pragma unroll
-        for (int q = 0; q < REC; ++q) s_rec[tid * REC + q] = src[q];
+    for (int q = tid; q < 3 * 512; q += 1024) (&s_acc[0][0])[q] = 0ull;
+    __syncthreads();
+    for (int it = 0; it * 16 * 64 < nchunks; ++it) {
+      const int cl = wv + 16 * (lane + 64 * it);  // chunk examined by this lane
+      bool pass = false;
+      if (cl < nchunks) {
+        const int4 box = chunk_box[cl];
+        pass = box_hits(box.x, tx) && box_hits(box.y, ty) && box_hits(box.z, tz);
       }
-      __syncthreads();
-      // ordered filter of the chunk for this wave's octant
-      int cnt = 0;
-      for (int e0 = 0; e0 < m; e0 += 64) {
-        const int e = e0 + lane;
+      unsigned long long cbal = __ballot(pass);
+      while (cbal) {
+        const int jc = __ffsll((long long)cbal) - 1;
+        cbal &= cbal - 1ull;
+        const int k = (wv + 16 * (jc + 64 * it)) * 64 + lane;
         bool hit = false;
-        if (e < m) {
-          const float *r = s_rec + e * REC;
-          const int bx = __float_as_int(r[12]), by = __float_as_int(r[13]), bz = __float_as_int(r[14]);
-          int dx = wrap_idx(ox - bx, g.nx), dy = wrap_idx(oy - by, g.ny), dz = wrap_idx(oz - bz, g.nz);
-          hit = (dx <= 3 || dx >= g.nx - 3) && (dy <= 3 || dy >= g.ny - 3) && (dz <= 3 || dz >= g.nz - 3);
+        float r[20];
+        if (k < n) {
+          const short4 b = mbase[k];
+          hit = axis_touches(b.x, g.nx, g.xper, tx) && axis_touches(b.y, g.ny, true, ty) &&
+                axis_touches(b.z, g.nz, true, tz);
         }
-        const unsigned long long bal = __ballot(hit);
-        if (hit) s_idx[wv][cnt + __popcll(bal & ((1ull << lane) - 1ull))] = (unsigned short)e;
-        cnt += __popcll(bal);
-      }
-      __syncthreads();
-      for (int q = 0; q < cnt; ++q) {
-        const float *r = s_rec + s_idx[wv][q] * REC;
-        int dx = wrap_idx(cx - __float_as_int(r[12]), g.nx);
-        int dy = wrap_idx(cy - __float_as_int(r[13]), g.ny);
-        int dz = wrap_idx(cz - __float_as_int(r[14]), g.nz);
-        if (dx < 4 && dy < 4 && dz < 4) {
-          const float d = r[dx] * r[4 + dy] * r[8 + dz];
-          gx += r[16] * d;
-          gy += r[17] * d;
-          gz += r[18] * d;
+        if (hit) {
+          const float4 *rp = reinterpret_cast<const float4 *>(rec + (size_t)k * REC);
+#pragma unroll
+          for (int q = 0; q < 5; ++q) {
+            const float4 v = rp[q];
+            r[4 * q] = v.x;
+            r[4 * q + 1] = v.y;
+            r[4 * q + 2] = v.z;
+            r[4 * q + 3] = v.w;
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < 20; ++q) r[q] = 0.f;
+        }
+        unsigned long long bal = __ballot(hit);
+        while (bal) {
+          const int j = __ffsll((long long)bal) - 1;
+          bal &= bal - 1ull;
+          const int bx = __float_as_int(bcast(r[12], j)), by = __float_as_int(bcast(r[13], j)),
+                    bz = __float_as_int(bcast(r[14], j));
+          int nx_ = bx + s3x, ny_ = wrap_idx(by + s3y, g.ny), nz_ = wrap_idx(bz + s3z, g.nz);
+          if (g.xper) nx_ = wrap_idx(nx_, g.nx);
+          const float wx0 = bcast(r[0], j), wx1 = bcast(r[1], j), wx2 = bcast(r[2], j), wx3 = bcast(r[3], j);
+          const float wy0 = bcast(r[4], j), wy1 = bcast(r[5], j), wy2 = bcast(r[6], j), wy3 = bcast(r[7], j);
+          const float wz0 = bcast(r[8], j), wz1 = bcast(r[9], j), wz2 = bcast(r[10], j), wz3 = bcast(r[11], j);
+          const float fx = bcast(r[16], j), fy = bcast(r[17], j), fz = bcast(r[18], j);
+          if ((nx_ >> 3) == tx && (ny_ >> 3) == ty && (nz_ >> 3) == tz) {
+            const float wx = s3x == 0 ? wx0 : s3x == 1 ? wx1 : s3x == 2 ? wx2 : wx3;
+            const float wy = s3y == 0 ? wy0 : s3y == 1 ? wy1 : s3y == 2 ? wy2 : wy3;
+            const float wz = s3z == 0 ? wz0 : s3z == 1 ? wz1 : s3z == 2 ? wz2 : wz3;
+            const float d = wx * wy * wz;
+            const int lc = (nx_ & 7) | ((ny_ & 7) << 3) | ((nz_ & 7) << 6);
+            atomicAdd(&s_acc[0][lc], (unsigned long long)__float2ll_rn(fx * d * kFix));
+            atomicAdd(&s_acc[1][lc], (unsigned long long)__float2ll_rn(fy * d * kFix));
+            atomicAdd(&s_acc[2][lc], (unsigned long long)__float2ll_rn(fz * d * kFix));
+          }
         }
       }
-      __syncthreads();
     }
-    const int lc = (cx & 7) | ((cy & 7) << 3) | ((cz & 7) << 6);
+    __syncthreads();
     float *gp = gbuf + (size_t)slot * 1536;
-    gp[lc] = gx;
-    gp[512 + lc] = gy;
-    gp[1024 + lc] = gz;
+    for (int q = tid; q < 3 * 512; q += 1024) gp[q] = (float)(long long)(&s_acc[0][0])[q] * kUnfix;
+    __syncthreads();
   }
 }
 

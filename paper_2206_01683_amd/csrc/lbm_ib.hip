@@ -25,7 +25,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // Workspace layout (all offsets 256-byte aligned).
 struct Layout {
   int tnx, tny, tnz, ntiles, cap, maxm;
-  size_t guard, counters, tile_count, tile_slot, active, tile_off, tile_len, pairs, macro, gbuf, rec, mstate, total;
+  size_t guard, counters, tile_flag, tile_slot, active, mbase, chunk_box, partials, macro, gbuf, rec, mstate, total;
 };
 
 bool params_ok(const lbm_params *p) {
@@ -48,9 +48,11 @@ bool params_ok(const lbm_params *p) {
 
 size_t elem_bytes(int storage) { return storage == LBM_STORE_F32 ? 4 : 2; }
 
+// Population plane stride: 256-element aligned plus 64 elements, so the 27
+// plane bases do not all fall on the same large power-of-two boundary.
 uint32_t plane_elems(const lbm_params *p) {
   size_t n = (size_t)p->nx * p->ny * p->nz;
-  return (uint32_t)align_up(n, 256);
+  return (uint32_t)(align_up(n, 256) + 64);
 }
 
 Layout layout(const lbm_params *p) {
@@ -72,12 +74,12 @@ Layout layout(const lbm_params *p) {
   };
   L.guard = take(64);
   L.counters = take(64);
-  L.tile_count = take(sizeof(int) * L.ntiles);
+  L.tile_flag = take(sizeof(int) * L.ntiles);
   L.tile_slot = take(sizeof(int) * L.ntiles);
   L.active = take(sizeof(int) * L.cap);
-  L.tile_off = take(sizeof(int) * L.cap);
-  L.tile_len = take(sizeof(int) * L.cap);
-  L.pairs = take(sizeof(int) * 27 * (size_t)L.maxm);
+  L.mbase = take(sizeof(short4) * (size_t)L.maxm);
+  L.chunk_box = take(sizeof(int4) * (size_t)((L.maxm + 63) / 64));
+  L.partials = take(sizeof(float) * 8 * (size_t)((L.maxm + 15) / 16));
   L.macro = take(sizeof(float) * 4 * 512 * (size_t)L.cap);
   L.gbuf = take(sizeof(float) * 3 * 512 * (size_t)L.cap);
   L.rec = take(sizeof(float) * REC * (size_t)L.maxm);
@@ -196,42 +198,42 @@ lbm_status launch_collide(lbm_ctx *c, const FrameF &fr, bool rot, bool ib) {
 }
 
 template <class S>
-lbm_status launch_fill_macro(lbm_ctx *c, const IBArgs &a, bool rot, const float *X) {
+lbm_status launch_macro(lbm_ctx *c, const IBArgs &a, bool rot) {
   using T = typename S::T;
   const T *src = static_cast<const T *>(c->f[c->cur]);
-  const int grid = std::min(c->L.cap, 4096);
+  const int grid = std::min(c->L.cap, 2048);
   auto *act = wsp<int>(c, c->L.active);
-  auto *off = wsp<int>(c, c->L.tile_off);
-  auto *len = wsp<int>(c, c->L.tile_len);
   auto *cnt = wsp<int>(c, c->L.counters);
-  auto *pairs = wsp<int>(c, c->L.pairs);
   auto *macro = wsp<float4>(c, c->L.macro);
   if (rot)
-    k_fill_macro<S, true><<<grid, 512, 0, c->stream>>>(src, X, act, off, len, cnt, pairs, macro, a);
+    k_macro<S, true><<<grid, 512, 0, c->stream>>>(src, act, cnt, macro, a);
   else
-    k_fill_macro<S, false><<<grid, 512, 0, c->stream>>>(src, X, act, off, len, cnt, pairs, macro, a);
+    k_macro<S, false><<<grid, 512, 0, c->stream>>>(src, act, cnt, macro, a);
   return launched();
 }
 
-lbm_status launch_spread(lbm_ctx *c, const IBArgs &a) {
-  const int grid = std::min(c->L.cap, 4096);
-  k_spread<<<grid, 512, 0, c->stream>>>(wsp<float>(c, c->L.rec), wsp<int>(c, c->L.active),
-                                        wsp<int>(c, c->L.tile_off), wsp<int>(c, c->L.tile_len),
-                                        wsp<int>(c, c->L.counters), wsp<int>(c, c->L.pairs),
-                                        wsp<float>(c, c->L.gbuf), a);
+// wrench != nullptr: also reduce the interpolation kernel's wrench partials.
+lbm_status launch_spread(lbm_ctx *c, const IBArgs &a, float *wrench) {
+  const int grid = std::min(c->L.cap, 2048);
+  k_spread<<<grid, 1024, 0, c->stream>>>(wsp<float>(c, c->L.rec), wsp<short4>(c, c->L.mbase),
+                                        wsp<int4>(c, c->L.chunk_box), wsp<int>(c, c->L.active),
+                                        wsp<int>(c, c->L.counters), wsp<float>(c, c->L.gbuf), a,
+                                        wsp<float>(c, c->L.partials), (a.n + 15) / 16, wrench);
   return launched();
 }
 
-lbm_status launch_interp(lbm_ctx *c, const lbm_markers *m, const IBArgs &a, bool rot, bool mdf) {
-  const int grid = (m->n + 3) / 4;
+lbm_status launch_interp(lbm_ctx *c, const lbm_markers *m, const IBArgs &a, bool rot, bool mdf, float *wrench) {
+  const int grid = (m->n + 15) / 16;
   auto *mstate = wsp<float>(c, c->L.mstate);
   auto *rec = wsp<float>(c, c->L.rec);
   auto *slots = wsp<int>(c, c->L.tile_slot);
   auto *macro = wsp<float4>(c, c->L.macro);
   auto *gbuf = wsp<float>(c, c->L.gbuf);
   auto *guard = wsp<int>(c, c->L.guard);
-#define LBM_INTERP(R, M) \
-  k_interp<R, M><<<grid, 256, 0, c->stream>>>(m->X, m->U, m->dv, m->F, mstate, rec, slots, macro, gbuf, a, guard)
+  float *part = wrench ? wsp<float>(c, c->L.partials) : nullptr;
+#define LBM_INTERP(R, M)                                                                                         \
+  k_interp<R, M><<<grid, 1024, 0, c->stream>>>(m->X, m->U, m->dv, m->F, mstate, rec, slots, macro, gbuf, a, guard, \
+                                               part)
   if (rot && mdf)
     LBM_INTERP(true, true);
   else if (rot)
@@ -264,22 +266,25 @@ lbm_status step_one(lbm_ctx *c, const lbm_markers *m, const float *pose, const l
     a.alpha2 = (float)(2.0 * c->p.ib_alpha);
     a.cap = c->L.cap;
     auto *guard = wsp<int>(c, c->L.guard);
-    k_skin_count<<<(m->n + 255) / 256, 256, 0, c->stream>>>(m->xrest, m->bone, m->weight, pose, m->X, m->U,
-                                                             wsp<int>(c, c->L.tile_count), a, guard);
+    k_skin_mark<<<(m->n + 255) / 256, 256, 0, c->stream>>>(m->xrest, m->bone, m->weight, pose, m->X, m->U,
+                                                            wsp<short4>(c, c->L.mbase), wsp<int>(c, c->L.tile_flag),
+                                                            wsp<int4>(c, c->L.chunk_box), wsp<int>(c, c->L.counters),
+                                                            a, guard);
     if ((st = launched()) != LBM_OK) return st;
-    k_tile_scan<<<1, 1024, 0, c->stream>>>(wsp<int>(c, c->L.tile_count), wsp<int>(c, c->L.tile_slot),
-                                           wsp<int>(c, c->L.active), wsp<int>(c, c->L.tile_off),
-                                           wsp<int>(c, c->L.tile_len), wsp<int>(c, c->L.counters), c->L.ntiles,
-                                           c->L.cap, guard);
+    k_active<<<(c->L.ntiles + 1023) / 1024, 1024, 0, c->stream>>>(wsp<int>(c, c->L.tile_flag),
+                                                                   wsp<int>(c, c->L.tile_slot),
+                                                                   wsp<int>(c, c->L.active),
+                                                                   wsp<int>(c, c->L.counters), c->L.ntiles,
+                                                                   c->L.cap, guard);
     if ((st = launched()) != LBM_OK) return st;
     c->slots_dirty = true;
-    if ((st = launch_fill_macro<S>(c, a, rot, m->X)) != LBM_OK) return st;
-    if ((st = launch_interp(c, m, a, rot, false)) != LBM_OK) return st;
-    for (int it = 1; it < c->p.mdf_iters; ++it) {
-      if ((st = launch_spread(c, a)) != LBM_OK) return st;
-      if ((st = launch_interp(c, m, a, rot, true)) != LBM_OK) return st;
+    if ((st = launch_macro<S>(c, a, rot)) != LBM_OK) return st;
+    const int passes = c->p.mdf_iters;
+    for (int it = 0; it < passes; ++it) {
+      if (it > 0 && (st = launch_spread(c, a, nullptr)) != LBM_OK) return st;
+      if ((st = launch_interp(c, m, a, rot, it > 0, it == passes - 1 ? wrench : nullptr)) != LBM_OK) return st;
     }
-    if ((st = launch_spread(c, a)) != LBM_OK) return st;
+    if ((st = launch_spread(c, a, wrench)) != LBM_OK) return st;
   } else if (c->slots_dirty) {
     // no body this step: clear the active-tile map so no stale force is read
     k_fill_int<<<256, 256, 0, c->stream>>>(wsp<int>(c, c->L.tile_slot), -1, c->L.ntiles);
@@ -290,11 +295,7 @@ lbm_status step_one(lbm_ctx *c, const lbm_markers *m, const float *pose, const l
   if ((st = launch_collide<S>(c, fr, rot, ib)) != LBM_OK) return st;
   prof_mark(c, 2);
   if (c->prof && c->prof_used < kProfSteps) c->prof_used++;
-  if (ib && wrench) {
-    k_wrench<<<1, 1024, 0, c->stream>>>(m->X, m->U, m->F, m->dv, m->bone, m->weight, m->n, fr.org[0], fr.org[1],
-                                        fr.org[2], wrench);
-    if ((st = launched()) != LBM_OK) return st;
-  } else if (wrench) {
+  if (!ib && wrench) {
     k_fill_int<<<1, 64, 0, c->stream>>>(reinterpret_cast<int *>(wrench), 0, 8);
     if ((st = launched()) != LBM_OK) return st;
   }
@@ -388,15 +389,12 @@ lbm_status lbm_init(lbm_ctx **out, const lbm_params *p, void *f_a, void *f_b, vo
   c->prof_used = 0;
   // collide block: 64-multiple along x covering as much of a row as fits
   int bx = p->block_x, by = p->block_y;
-  if (bx == 0) {
-    const int chunks = (p->nx + 255) / 256;
-    bx = (int)align_up((size_t)((p->nx + chunks - 1) / chunks), 64);
-  }
-  if (by == 0) by = std::max(1, 256 / bx);
+  if (bx == 0) bx = p->nx >= 128 ? 128 : 64;
+  if (by == 0) by = std::max(1, 512 / bx);
   c->bx = bx;
   c->by = by;
   lbm_status st;
-  k_fill_int<<<256, 256, 0, c->stream>>>(wsp<int>(c, c->L.tile_count), 0, c->L.ntiles);
+  k_fill_int<<<256, 256, 0, c->stream>>>(wsp<int>(c, c->L.tile_flag), 0, c->L.ntiles);
   k_fill_int<<<256, 256, 0, c->stream>>>(wsp<int>(c, c->L.tile_slot), -1, c->L.ntiles);
   k_fill_int<<<1, 64, 0, c->stream>>>(wsp<int>(c, c->L.guard), 0, 16);
   k_fill_int<<<1, 64, 0, c->stream>>>(wsp<int>(c, c->L.counters), 0, 16);
