@@ -69,19 +69,35 @@ __device__ inline float cdot(int i, float ax, float ay, float az) {
   return r;
 }
 
+// Immersed force is kept as 64-bit fixed point with 2^-40 resolution (see
+// the spreading kernel): contributions are summed as integers, so the result
+// does not depend on summation order.
+// float -> nearest multiple of 2^-40, as two's complement: adding 1.5 * 2^52
+// to the scaled value in double precision leaves the rounded integer in the
+// low mantissa bits (valid for |v| < 2^11).
+__device__ inline unsigned long long to_fix(float v) {
+  const double magic = 6755399441055744.0;  // 1.5 * 2^52
+  const double d = (double)v * 1099511627776.0 + magic;
+  return (unsigned long long)(__double_as_longlong(d) - __double_as_longlong(magic));
+}
+__device__ inline float from_fix(unsigned long long q) {
+  return (float)((double)(long long)q * (1.0 / 1099511627776.0));
+}
+
 // Immersed-boundary force density at cell (x, y, z): zero outside active tiles.
-__device__ inline void load_g(const GridArgs &g, const int *__restrict__ tile_slot, const float *__restrict__ gbuf,
-                              int x, int y, int z, float &gx, float &gy, float &gz) {
+__device__ inline void load_g(const GridArgs &g, const int *__restrict__ tile_slot,
+                              const unsigned long long *__restrict__ gfix, int x, int y, int z, float &gx, float &gy,
+                              float &gz) {
   gx = gy = gz = 0.f;
   if (tile_slot == nullptr) return;
   int t = (x >> 3) + g.tnx * ((y >> 3) + g.tny * (z >> 3));
   int s = tile_slot[t];
   if (s >= 0) {
     int lc = (x & 7) | ((y & 7) << 3) | ((z & 7) << 6);
-    const float *gp = gbuf + (size_t)s * 1536;
-    gx = gp[lc];
-    gy = gp[512 + lc];
-    gz = gp[1024 + lc];
+    const unsigned long long *gp = gfix + (size_t)s * 1536;
+    gx = from_fix(gp[lc]);
+    gy = from_fix(gp[512 + lc]);
+    gz = from_fix(gp[1024 + lc]);
   }
 }
 
@@ -103,7 +119,8 @@ __device__ inline void load_g(const GridArgs &g, const int *__restrict__ tile_sl
 template <class S, bool XPER, bool ROT>
 __global__ void __launch_bounds__(512) k_collide(const typename S::T *__restrict__ src, typename S::T *__restrict__ dst,
                                                  CollideArgs a, const int *__restrict__ tile_slot,
-                                                 const float *__restrict__ gbuf, int *__restrict__ guard) {
+                                                 const unsigned long long *__restrict__ gfix,
+                                                 int *__restrict__ guard) {
   const int b = blockIdx.x;
   const int per = (a.nblocks + 7) >> 3;
   const int lb = (b & 7) * per + (b >> 3);
@@ -141,7 +158,7 @@ __global__ void __launch_bounds__(512) k_collide(const typename S::T *__restrict
   const float irho = 1.0f / rho;
 
   float gx, gy, gz;
-  load_g(g, tile_slot, gbuf, xs, y, z, gx, gy, gz);
+  load_g(g, tile_slot, gfix, xs, y, z, gx, gy, gz);
   float ax, ay, az;
   frame_a0<ROT>(a.fr, (float)xs, (float)y, (float)z, ax, ay, az);
   float ux, uy, uz;

@@ -10,9 +10,9 @@
 //   k_interp        one wave64 per marker, one lane per stencil node: weights,
 //                   wave-level sums -> U*_k, rho_k, direct forcing F_k, and the
 //                   body wrench reduced in workgroup order
-//   k_spread        per active tile: LDS fixed-point accumulation of the
-//                   markers touching it - order-independent (deterministic)
-//                   gather-form spreading without global atomics
+//   k_spread        per (active tile, part): LDS fixed-point accumulation of
+//                   the markers touching the tile, merged into the tile's
+//                   fixed-point force - order-independent (deterministic)
 //   k_wrench        per-bone wrench for the body-forces query
 #pragma once
 
@@ -188,10 +188,11 @@ __global__ void __launch_bounds__(1024) k_active(int *__restrict__ tile_flag, in
 
 // Density and unforced velocity u* (frame force, no IB force) of every cell
 // of every active tile (grid-stride over slots, 512 threads = the tile).
+// Also clears the tile's fixed-point immersed force for this step.
 template <class S, bool ROT>
 __global__ void __launch_bounds__(512) k_macro(const typename S::T *__restrict__ src, const int *__restrict__ active,
                                                const int *__restrict__ counters, float4 *__restrict__ macro,
-                                               IBArgs a) {
+                                               unsigned long long *__restrict__ gfix, IBArgs a) {
   const int tid = threadIdx.x;
   const int n_active = min(counters[0], a.cap);
   const GridArgs &g = a.g;
@@ -216,6 +217,10 @@ __global__ void __launch_bounds__(512) k_macro(const typename S::T *__restrict__
       out = make_float4(rho, ux, uy, uz);
     }
     macro[(size_t)slot * 512 + tid] = out;
+    unsigned long long *gp = gfix + (size_t)slot * 1536;
+    gp[tid] = 0ull;
+    gp[512 + tid] = 0ull;
+    gp[1024 + tid] = 0ull;
   }
 }
 
@@ -239,8 +244,8 @@ __global__ void __launch_bounds__(1024) k_interp(const float *__restrict__ X, co
                                                  const float *__restrict__ dv, float *__restrict__ F,
                                                  float *__restrict__ mstate, float *__restrict__ rec,
                                                  const int *__restrict__ tile_slot, const float4 *__restrict__ macro,
-                                                 const float *__restrict__ gbuf, IBArgs a, int *__restrict__ guard,
-                                                 float *__restrict__ partials) {
+                                                 const unsigned long long *__restrict__ gfix, IBArgs a,
+                                                 int *__restrict__ guard, float *__restrict__ partials) {
   __shared__ float s_part[16][8];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int k = blockIdx.x * 16 + wv;
@@ -271,10 +276,11 @@ __global__ void __launch_bounds__(1024) k_interp(const float *__restrict__ X, co
       uy = m.z;
       uz = m.w;
       if (MDF) {
-        const float *gp = gbuf + (size_t)s * 1536;
+        const unsigned long long *gp = gfix + (size_t)s * 1536;
         const float h = 0.5f / rho;
         float dx, dy, dz;
-        solve_coriolis<ROT>(a.fr, gp[lc] * h, gp[512 + lc] * h, gp[1024 + lc] * h, dx, dy, dz);
+        solve_coriolis<ROT>(a.fr, from_fix(gp[lc]) * h, from_fix(gp[512 + lc]) * h, from_fix(gp[1024 + lc]) * h, dx,
+                            dy, dz);
         ux += dx;
         uy += dy;
         uz += dz;
@@ -289,8 +295,10 @@ __global__ void __launch_bounds__(1024) k_interp(const float *__restrict__ X, co
     if ((lane & 3) == 0 && lane < 16) r[4 + (lane >> 2)] = w[1];  // s3 = (0, lane/4, 0)
     if ((lane & 15) == 0) r[8 + (lane >> 4)] = w[2];              // s3 = (0, 0, lane/16)
     if (lane == 0) {
+      // inc = this pass's force; the record carries inc dV because the
+      // spreading kernel adds each pass into the step's accumulated g
       float rk;
-      float Fk[3];
+      float Fk[3], inc[3];
       const float Uk[3] = {U[k], U[n + k], U[2 * n + k]};
       const float Ui[3] = {sx, sy, sz};
       if (!MDF) {
@@ -299,12 +307,16 @@ __global__ void __launch_bounds__(1024) k_interp(const float *__restrict__ X, co
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           mstate[(c + 1) * (size_t)n + k] = Ui[c];
-          Fk[c] = a.alpha2 * rk * (Uk[c] - Ui[c]);
+          inc[c] = a.alpha2 * rk * (Uk[c] - Ui[c]);
+          Fk[c] = inc[c];
         }
       } else {
         rk = mstate[k];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) Fk[c] = F[c * n + k] + a.alpha2 * rk * (Uk[c] - Ui[c]);
+        for (int c = 0; c < 3; ++c) {
+          inc[c] = a.alpha2 * rk * (Uk[c] - Ui[c]);
+          Fk[c] = F[c * n + k] + inc[c];
+        }
       }
       const float dvk = dv[k];
       float fd[3];
@@ -312,7 +324,7 @@ __global__ void __launch_bounds__(1024) k_interp(const float *__restrict__ X, co
       for (int c = 0; c < 3; ++c) {
         F[c * n + k] = Fk[c];
         fd[c] = Fk[c] * dvk;
-        r[16 + c] = fd[c];
+        r[16 + c] = inc[c] * dvk;
         r[12 + c] = __int_as_float(base[c]);
       }
       // fluid on body: -F dV; torque (X - x0) x (-F dV); power F.U dV
@@ -344,25 +356,27 @@ __device__ inline float bcast(float v, int j) {
 
 __device__ inline bool box_hits(int packed, int t) { return t >= (packed & 0xFFFF) && t <= (packed >> 16); }
 
-// Fixed-point scale of the spreading accumulator: contributions are rounded
-// to multiples of 2^-40 and summed as 64-bit integers. Integer addition is
-// associative, so the sum does not depend on the order in which waves add.
-constexpr float kFix = 1099511627776.0f;  // 2^40
-constexpr float kUnfix = 1.0f / 1099511627776.0f;
+// Spreading accumulates in 64-bit fixed point: every contribution is rounded
+// to a multiple of 2^-40 (see fluid.hpp, to_fix / from_fix) and summed as an
+// integer. Integer addition is associative, so sums do not depend on the order
+// in which waves or workgroups add - the result is deterministic.
+constexpr int kSpreadSplit = 4;  // workgroups per active tile
 
-// Per active tile (grid-stride over slots, 1024 threads = 16 waves):
-// gather-form spreading g(x) = sum_k F_k dV_k delta(x - X_k) over the tile's
-// 512 cells into one LDS accumulator, with no global atomics.
-// Wave w owns marker chunks w, w+16, w+32, ... (64 markers each). It loads 64
-// of its chunk boxes at once and keeps the chunks whose box meets the tile;
-// in each such chunk every lane tests its own marker and loads its record,
-// and the hits are broadcast one by one to the 64 lanes (one per stencil
-// node), which add their node's contribution with LDS atomics.
+// Spreading, gather form: g(x) = sum_k F_k dV_k delta(x - X_k) over the active
+// tiles. Work item = (tile, part), kSpreadSplit parts per tile, 1024 threads.
+// Wave w of part p owns marker chunks c = 16 p + w (mod 16 kSpreadSplit)
+// (64 markers each). It loads 64 of its chunk boxes at once and keeps the
+// chunks whose box meets the tile; in each such chunk every lane tests its own
+// marker and loads its record, and the hits are broadcast one by one to the 64
+// lanes (one per stencil node), which add their node's contribution into the
+// workgroup's LDS tile with 64-bit LDS atomics. Each workgroup then adds its
+// nonzero cells into the tile's fixed-point force (one global atomic per
+// cell and component; k_macro zeroed it this step).
 // Workgroup 0 first adds the interpolation kernel's wrench partials in order.
 __global__ void __launch_bounds__(1024) k_spread(const float *__restrict__ rec, const short4 *__restrict__ mbase,
                                                  const int4 *__restrict__ chunk_box,
                                                  const int *__restrict__ active, const int *__restrict__ counters,
-                                                 float *__restrict__ gbuf, IBArgs a,
+                                                 unsigned long long *__restrict__ gfix, IBArgs a,
                                                  const float *__restrict__ partials, int nparts,
                                                  float *__restrict__ wrench) {
   __shared__ unsigned long long s_acc[3][512];
@@ -384,15 +398,17 @@ __global__ void __launch_bounds__(1024) k_spread(const float *__restrict__ rec, 
       wrench[tid] = tid < 7 ? sum : 0.f;
     }
   }
-  const int n_active = min(counters[0], a.cap);
-  const int s3x = lane & 3, s3y = (lane >> 2) & 3, s3z = lane >> 4;
-  for (int slot = blockIdx.x; slot < n_active; slot += gridDim.x) {
+  const int n_items = min(counters[0], a.cap) * kSpreadSplit;
+  const int stride = 16 * kSpreadSplit;
+  for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
+    const int slot = item / kSpreadSplit, part = item % kSpreadSplit;
     const int t = active[slot];
     const int tx = t % g.tnx, ty = (t / g.tnx) % g.tny, tz = t / (g.tnx * g.tny);
     for (int q = tid; q < 3 * 512; q += 1024) (&s_acc[0][0])[q] = 0ull;
     __syncthreads();
-    for (int it = 0; it * 16 * 64 < nchunks; ++it) {
-      const int cl = wv + 16 * (lane + 64 * it);  // chunk examined by this lane
+    const int c_first = part * 16 + wv;
+    for (int it = 0; c_first + stride * 64 * it < nchunks; ++it) {
+      const int cl = c_first + stride * (lane + 64 * it);  // chunk examined by this lane
       bool pass = false;
       if (cl < nchunks) {
         const int4 box = chunk_box[cl];
@@ -402,15 +418,17 @@ __global__ void __launch_bounds__(1024) k_spread(const float *__restrict__ rec, 
       while (cbal) {
         const int jc = __ffsll((long long)cbal) - 1;
         cbal &= cbal - 1ull;
-        const int k = (wv + 16 * (jc + 64 * it)) * 64 + lane;
+        const int k = (c_first + stride * (jc + 64 * it)) * 64 + lane;
         bool hit = false;
-        float r[20];
         if (k < n) {
           const short4 b = mbase[k];
           hit = axis_touches(b.x, g.nx, g.xper, tx) && axis_touches(b.y, g.ny, true, ty) &&
                 axis_touches(b.z, g.nz, true, tz);
         }
         if (hit) {
+          // this lane's marker: walk its 4x4x4 stencil, adding the nodes that
+          // fall in the tile
+          float r[20];
           const float4 *rp = reinterpret_cast<const float4 *>(rec + (size_t)k * REC);
 #pragma unroll
           for (int q = 0; q < 5; ++q) {
@@ -420,38 +438,43 @@ __global__ void __launch_bounds__(1024) k_spread(const float *__restrict__ rec, 
             r[4 * q + 2] = v.z;
             r[4 * q + 3] = v.w;
           }
-        } else {
+          const int bx = __float_as_int(r[12]), by = __float_as_int(r[13]), bz = __float_as_int(r[14]);
+          int lx[4], ly[4], lz[4];  // local index part per stencil node, -1 outside the tile
 #pragma unroll
-          for (int q = 0; q < 20; ++q) r[q] = 0.f;
-        }
-        unsigned long long bal = __ballot(hit);
-        while (bal) {
-          const int j = __ffsll((long long)bal) - 1;
-          bal &= bal - 1ull;
-          const int bx = __float_as_int(bcast(r[12], j)), by = __float_as_int(bcast(r[13], j)),
-                    bz = __float_as_int(bcast(r[14], j));
-          int nx_ = bx + s3x, ny_ = wrap_idx(by + s3y, g.ny), nz_ = wrap_idx(bz + s3z, g.nz);
-          if (g.xper) nx_ = wrap_idx(nx_, g.nx);
-          const float wx0 = bcast(r[0], j), wx1 = bcast(r[1], j), wx2 = bcast(r[2], j), wx3 = bcast(r[3], j);
-          const float wy0 = bcast(r[4], j), wy1 = bcast(r[5], j), wy2 = bcast(r[6], j), wy3 = bcast(r[7], j);
-          const float wz0 = bcast(r[8], j), wz1 = bcast(r[9], j), wz2 = bcast(r[10], j), wz3 = bcast(r[11], j);
-          const float fx = bcast(r[16], j), fy = bcast(r[17], j), fz = bcast(r[18], j);
-          if ((nx_ >> 3) == tx && (ny_ >> 3) == ty && (nz_ >> 3) == tz) {
-            const float wx = s3x == 0 ? wx0 : s3x == 1 ? wx1 : s3x == 2 ? wx2 : wx3;
-            const float wy = s3y == 0 ? wy0 : s3y == 1 ? wy1 : s3y == 2 ? wy2 : wy3;
-            const float wz = s3z == 0 ? wz0 : s3z == 1 ? wz1 : s3z == 2 ? wz2 : wz3;
-            const float d = wx * wy * wz;
-            const int lc = (nx_ & 7) | ((ny_ & 7) << 3) | ((nz_ & 7) << 6);
-            atomicAdd(&s_acc[0][lc], (unsigned long long)__float2ll_rn(fx * d * kFix));
-            atomicAdd(&s_acc[1][lc], (unsigned long long)__float2ll_rn(fy * d * kFix));
-            atomicAdd(&s_acc[2][lc], (unsigned long long)__float2ll_rn(fz * d * kFix));
+          for (int q = 0; q < 4; ++q) {
+            int jx = bx + q, jy = wrap_idx(by + q, g.ny), jz = wrap_idx(bz + q, g.nz);
+            if (g.xper) jx = wrap_idx(jx, g.nx);
+            lx[q] = (jx >> 3) == tx ? (jx & 7) : -1;
+            ly[q] = (jy >> 3) == ty ? ((jy & 7) << 3) : -1;
+            lz[q] = (jz >> 3) == tz ? ((jz & 7) << 6) : -1;
+          }
+#pragma unroll
+          for (int qz = 0; qz < 4; ++qz) {
+            if (lz[qz] < 0) continue;
+#pragma unroll
+            for (int qy = 0; qy < 4; ++qy) {
+              if (ly[qy] < 0) continue;
+              const float wyz = r[4 + qy] * r[8 + qz];
+#pragma unroll
+              for (int qx = 0; qx < 4; ++qx) {
+                if (lx[qx] < 0) continue;
+                const float d = r[qx] * wyz;
+                const int lc = lx[qx] | ly[qy] | lz[qz];
+                atomicAdd(&s_acc[0][lc], to_fix(r[16] * d));
+                atomicAdd(&s_acc[1][lc], to_fix(r[17] * d));
+                atomicAdd(&s_acc[2][lc], to_fix(r[18] * d));
+              }
+            }
           }
         }
       }
     }
     __syncthreads();
-    float *gp = gbuf + (size_t)slot * 1536;
-    for (int q = tid; q < 3 * 512; q += 1024) gp[q] = (float)(long long)(&s_acc[0][0])[q] * kUnfix;
+    unsigned long long *gp = gfix + (size_t)slot * 1536;
+    for (int q = tid; q < 3 * 512; q += 1024) {
+      const unsigned long long v = (&s_acc[0][0])[q];
+      if (v != 0ull) atomicAdd(&gp[q], v);
+    }
     __syncthreads();
   }
 }

@@ -81,7 +81,7 @@ Layout layout(const lbm_params *p) {
   L.chunk_box = take(sizeof(int4) * (size_t)((L.maxm + 63) / 64));
   L.partials = take(sizeof(float) * 8 * (size_t)((L.maxm + 15) / 16));
   L.macro = take(sizeof(float) * 4 * 512 * (size_t)L.cap);
-  L.gbuf = take(sizeof(float) * 3 * 512 * (size_t)L.cap);
+  L.gbuf = take(sizeof(unsigned long long) * 3 * 512 * (size_t)L.cap);
   L.rec = take(sizeof(float) * REC * (size_t)L.maxm);
   L.mstate = take(sizeof(float) * 4 * (size_t)L.maxm);
   L.total = o;
@@ -182,7 +182,7 @@ lbm_status launch_collide(lbm_ctx *c, const FrameF &fr, bool rot, bool ib) {
   const T *src = static_cast<const T *>(c->f[c->cur]);
   T *dst = static_cast<T *>(c->f[c->cur ^ 1]);
   const int *slots = ib ? wsp<int>(c, c->L.tile_slot) : nullptr;
-  const float *gbuf = wsp<float>(c, c->L.gbuf);
+  const auto *gbuf = wsp<unsigned long long>(c, c->L.gbuf);
   int *guard = wsp<int>(c, c->L.guard);
   dim3 blk(c->bx, c->by);
   const bool xper = a.g.xper;
@@ -205,19 +205,20 @@ lbm_status launch_macro(lbm_ctx *c, const IBArgs &a, bool rot) {
   auto *act = wsp<int>(c, c->L.active);
   auto *cnt = wsp<int>(c, c->L.counters);
   auto *macro = wsp<float4>(c, c->L.macro);
+  auto *gfix = wsp<unsigned long long>(c, c->L.gbuf);
   if (rot)
-    k_macro<S, true><<<grid, 512, 0, c->stream>>>(src, act, cnt, macro, a);
+    k_macro<S, true><<<grid, 512, 0, c->stream>>>(src, act, cnt, macro, gfix, a);
   else
-    k_macro<S, false><<<grid, 512, 0, c->stream>>>(src, act, cnt, macro, a);
+    k_macro<S, false><<<grid, 512, 0, c->stream>>>(src, act, cnt, macro, gfix, a);
   return launched();
 }
 
 // wrench != nullptr: also reduce the interpolation kernel's wrench partials.
 lbm_status launch_spread(lbm_ctx *c, const IBArgs &a, float *wrench) {
-  const int grid = std::min(c->L.cap, 2048);
+  const int grid = std::min(c->L.cap * kSpreadSplit, 2048);
   k_spread<<<grid, 1024, 0, c->stream>>>(wsp<float>(c, c->L.rec), wsp<short4>(c, c->L.mbase),
                                         wsp<int4>(c, c->L.chunk_box), wsp<int>(c, c->L.active),
-                                        wsp<int>(c, c->L.counters), wsp<float>(c, c->L.gbuf), a,
+                                        wsp<int>(c, c->L.counters), wsp<unsigned long long>(c, c->L.gbuf), a,
                                         wsp<float>(c, c->L.partials), (a.n + 15) / 16, wrench);
   return launched();
 }
@@ -228,7 +229,7 @@ lbm_status launch_interp(lbm_ctx *c, const lbm_markers *m, const IBArgs &a, bool
   auto *rec = wsp<float>(c, c->L.rec);
   auto *slots = wsp<int>(c, c->L.tile_slot);
   auto *macro = wsp<float4>(c, c->L.macro);
-  auto *gbuf = wsp<float>(c, c->L.gbuf);
+  auto *gbuf = wsp<unsigned long long>(c, c->L.gbuf);
   auto *guard = wsp<int>(c, c->L.guard);
   float *part = wrench ? wsp<float>(c, c->L.partials) : nullptr;
 #define LBM_INTERP(R, M)                                                                                         \
