@@ -1,0 +1,59 @@
+// Device-side description of one lattice and its immersed body ("environment").
+// Every kernel of the library works on an EnvView: the single-lattice
+// launches pass one by value, the batched launches index an array of them.
+#pragma once
+
+#include "lattice.hpp"
+
+namespace lbmib {
+
+struct GridArgs {
+  int nx, ny, nz;
+  uint32_t plane;  // elements per population plane
+  int xper;        // 1: x periodic
+  int bc_lo, bc_hi;
+  int tnx, tny;    // 8^3 tile grid (x, y extents)
+};
+
+struct EnvView {
+  GridArgs g;
+  float inv_tau, omt, pref;     // 1/tau, 1 - 1/tau, 1 - 1/(2 tau)
+  int bx, by, gx, gy, nblocks;  // collide tile shape and its block grid
+  void *f[2];                   // population buffers
+  // immersed boundary
+  int ib;                       // a body is present this step
+  int n, nbones, cap, ntiles;
+  float alpha2;                 // 2 * direct-forcing gain
+  const float *xrest, *weight, *dv;
+  const int *bone;
+  float *X, *U, *F;
+  int *tile_flag, *tile_slot, *active, *counters, *guard;
+  short4 *mbase;
+  int4 *chunk_box;
+  float *partials;
+  float4 *macro;
+  unsigned long long *gfix;
+  float *rec, *mstate;
+  // per-run device inputs of the batched forms, indexed by step
+  const float *poses;    // [nsteps][nbones][24]
+  const double *frames;  // [nsteps][18] (lbm_frame layout)
+  float *wrench;         // [nsteps][8] or null
+  int rot;               // some frame rotates
+  int cur0;              // buffer holding the state at the start of the run
+};
+
+// lbm_frame (18 doubles) -> float32 frame constants
+__device__ inline FrameF frame_from(const double *d) {
+  FrameF f;
+  for (int a = 0; a < 3; ++a) {
+    f.acc[a] = (float)d[a];
+    f.omg[a] = (float)d[3 + a];
+    f.alp[a] = (float)d[6 + a];
+    f.org[a] = (float)d[9 + a];
+    f.ulo[a] = (float)d[12 + a];
+    f.uhi[a] = (float)d[15 + a];
+  }
+  return f;
+}
+
+}  // namespace lbmib

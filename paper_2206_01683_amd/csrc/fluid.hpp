@@ -8,24 +8,9 @@
 // writes the other.
 #pragma once
 
-#include "lattice.hpp"
+#include "env.hpp"
 
 namespace lbmib {
-
-struct GridArgs {
-  int nx, ny, nz;
-  uint32_t plane;
-  int xper;       // 1: x periodic
-  int bc_lo, bc_hi;
-  int tnx, tny;   // 8^3 tile grid (x, y extents)
-};
-
-struct CollideArgs {
-  GridArgs g;
-  FrameF fr;
-  float inv_tau, omt, pref;  // 1/tau, 1 - 1/tau, 1 - 1/(2 tau)
-  int gx, gy, nblocks;       // logical block grid (x-blocks, y-blocks, total)
-};
 
 // Pull the 27 pre-collision populations of node (xs, y, z). The x neighbour
 // indices xm/xp are given by the caller (periodic wrap or interior node).
@@ -113,25 +98,21 @@ __device__ inline void load_g(const GridArgs &g, const int *__restrict__ tile_sl
 // The open-face lanes reuse the interior arithmetic: replacing f_i by
 // f_i + f^eq_i(rho_f, u_b) - f^eq_i(rho_f, u_f) makes the BGK formula with
 // (rho_f, u_b, F_b) produce exactly the extrapolated values.
-// Blocks are mapped XCD-aware: hardware workgroup b runs on XCD b % 8, so the
-// logical block index gives each XCD a contiguous 1/8 of the domain (shared
-// cache lines of neighbouring blocks stay in one L2).
+// One cell of logical block lb (tile shape e.bx x e.by), thread (tx, ty);
+// `cur` is the buffer holding f*(n-1), the other one receives f*(n).
 template <class S, bool XPER, bool ROT>
-__global__ void __launch_bounds__(512) k_collide(const typename S::T *__restrict__ src, typename S::T *__restrict__ dst,
-                                                 CollideArgs a, const int *__restrict__ tile_slot,
-                                                 const unsigned long long *__restrict__ gfix,
-                                                 int *__restrict__ guard) {
-  const int b = blockIdx.x;
-  const int per = (a.nblocks + 7) >> 3;
-  const int lb = (b & 7) * per + (b >> 3);
-  if (lb >= a.nblocks) return;
-  const int bxi = lb % a.gx;
-  const int rest = lb / a.gx;
-  const int byi = rest % a.gy;
-  const int z = rest / a.gy;
-  const int x = bxi * blockDim.x + threadIdx.x;
-  const int y = byi * blockDim.y + threadIdx.y;
-  const GridArgs &g = a.g;
+__device__ inline void collide_cell(const EnvView &e, const FrameF &fr, int cur, int lb, int tx, int ty) {
+  using T = typename S::T;
+  const T *__restrict__ src = static_cast<const T *>(e.f[cur]);
+  T *__restrict__ dst = static_cast<T *>(e.f[cur ^ 1]);
+  const int *__restrict__ tile_slot = e.ib ? e.tile_slot : nullptr;
+  const int bxi = lb % e.gx;
+  const int rest = lb / e.gx;
+  const int byi = rest % e.gy;
+  const int z = rest / e.gy;
+  const int x = bxi * e.bx + tx;
+  const int y = byi * e.by + ty;
+  const GridArgs &g = e.g;
   if (x >= g.nx || y >= g.ny) return;
 
   const bool lo_face = !XPER && x == 0;
@@ -158,23 +139,23 @@ __global__ void __launch_bounds__(512) k_collide(const typename S::T *__restrict
   const float irho = 1.0f / rho;
 
   float gx, gy, gz;
-  load_g(g, tile_slot, gfix, xs, y, z, gx, gy, gz);
+  load_g(g, tile_slot, e.gfix, xs, y, z, gx, gy, gz);
   float ax, ay, az;
-  frame_a0<ROT>(a.fr, (float)xs, (float)y, (float)z, ax, ay, az);
+  frame_a0<ROT>(fr, (float)xs, (float)y, (float)z, ax, ay, az);
   float ux, uy, uz;
-  solve_coriolis<ROT>(a.fr, mx * irho + 0.5f * (gx * irho + ax), my * irho + 0.5f * (gy * irho + ay),
+  solve_coriolis<ROT>(fr, mx * irho + 0.5f * (gx * irho + ax), my * irho + 0.5f * (gy * irho + ay),
                       mz * irho + 0.5f * (gz * irho + az), ux, uy, uz);
   float Fx, Fy, Fz;
   if (!face) {
     float wx = 0.f, wy = 0.f, wz = 0.f;
-    if (ROT) cross3(a.fr.omg, ux, uy, uz, wx, wy, wz);
+    if (ROT) cross3(fr.omg, ux, uy, uz, wx, wy, wz);
     Fx = gx + rho * (ax - 2.0f * wx);
     Fy = gy + rho * (ay - 2.0f * wy);
     Fz = gz + rho * (az - 2.0f * wz);
   } else {
     // (ux,uy,uz) is u_f; choose u_b and shift f by f^eq(u_b) - f^eq(u_f)
     const int bc = lo_face ? g.bc_lo : g.bc_hi;
-    const float *uf = lo_face ? a.fr.ulo : a.fr.uhi;
+    const float *uf = lo_face ? fr.ulo : fr.uhi;
     float bx = bc == 1 ? uf[0] : ux, by = bc == 1 ? uf[1] : uy, bz = bc == 1 ? uf[2] : uz;
     const float ub2 = bx * bx + by * by + bz * bz, uf2 = ux * ux + uy * uy + uz * uz;
 #pragma unroll
@@ -183,9 +164,9 @@ __global__ void __launch_bounds__(512) k_collide(const typename S::T *__restrict
       f[i] += w_of(i) * rho * (3.0f * (cb - cf) + 4.5f * (cb * cb - cf * cf) - 1.5f * (ub2 - uf2));
     }
     float ax2, ay2, az2;
-    frame_a0<ROT>(a.fr, (float)x, (float)y, (float)z, ax2, ay2, az2);
+    frame_a0<ROT>(fr, (float)x, (float)y, (float)z, ax2, ay2, az2);
     float wx = 0.f, wy = 0.f, wz = 0.f;
-    if (ROT) cross3(a.fr.omg, bx, by, bz, wx, wy, wz);
+    if (ROT) cross3(fr.omg, bx, by, bz, wx, wy, wz);
     ux = bx;
     uy = by;
     uz = bz;
@@ -195,14 +176,14 @@ __global__ void __launch_bounds__(512) k_collide(const typename S::T *__restrict
   }
 
   const float u2 = ux * ux + uy * uy + uz * uz;
-  if (!(u2 < 0.16f)) atomicOr(guard, (int)GUARD_UNSTABLE);
+  if (!(u2 < 0.16f)) atomicOr(e.guard, (int)GUARD_UNSTABLE);
 
   // BGK + Guo, evaluated on opposite pairs (i, 26 - i): c_j = -c_i, so the
   // equilibrium and forcing split into parts even and odd in c.
   const float A = 1.0f - 1.5f * u2;
   const float uF = ux * Fx + uy * Fy + uz * Fz;
-  const float E = a.inv_tau * rho;
-  const float P = a.pref;
+  const float E = e.inv_tau * rho;
+  const float P = e.pref;
   const uint32_t o = ((uint32_t)z * (uint32_t)g.ny + (uint32_t)y) * (uint32_t)g.nx + (uint32_t)x;
   typename S::T *__restrict__ d = dst + o;
 #pragma unroll
@@ -213,13 +194,26 @@ __global__ void __launch_bounds__(512) k_collide(const typename S::T *__restrict
     const float cF = cdot(i, Fx, Fy, Fz);
     const float even = (w * E) * (A + 4.5f * cu * cu) + (w * P) * (9.0f * cu * cF - 3.0f * uF);
     const float odd = (w * E) * (3.0f * cu) + (w * P) * (3.0f * cF);
-    S::store(d + (uint32_t)i * g.plane, a.omt * f[i] + even + odd, i);
-    S::store(d + (uint32_t)j * g.plane, a.omt * f[j] + even - odd, j);
+    S::store(d + (uint32_t)i * g.plane, e.omt * f[i] + even + odd, i);
+    S::store(d + (uint32_t)j * g.plane, e.omt * f[j] + even - odd, j);
   }
   {
     const float w = w_of(13);
-    S::store(d + 13u * g.plane, a.omt * f[13] + (w * E) * A - (w * P) * 3.0f * uF, 13);
+    S::store(d + 13u * g.plane, e.omt * f[13] + (w * E) * A - (w * P) * 3.0f * uF, 13);
   }
+}
+
+// Single-lattice launch: blockDim = (e.bx, e.by). Blocks are mapped
+// XCD-aware: hardware workgroup b runs on XCD b % 8, so the logical block
+// index gives each XCD a contiguous 1/8 of the domain (shared cache lines of
+// neighbouring blocks stay in one L2).
+template <class S, bool XPER, bool ROT>
+__global__ void __launch_bounds__(512) k_collide(EnvView e, FrameF fr, int cur) {
+  const int b = blockIdx.x;
+  const int per = (e.nblocks + 7) >> 3;
+  const int lb = (b & 7) * per + (b >> 3);
+  if (lb >= e.nblocks) return;
+  collide_cell<S, XPER, ROT>(e, fr, cur, lb, threadIdx.x, threadIdx.y);
 }
 
 // f_i(x) of the caller's canonical pre-collision field -> stored buffer, i.e.

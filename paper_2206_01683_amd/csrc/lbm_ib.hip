@@ -78,8 +78,8 @@ Layout layout(const lbm_params *p) {
   L.tile_slot = take(sizeof(int) * L.ntiles);
   L.active = take(sizeof(int) * L.cap);
   L.mbase = take(sizeof(short4) * (size_t)L.maxm);
-  L.chunk_box = take(sizeof(int4) * (size_t)((L.maxm + 63) / 64));
-  L.partials = take(sizeof(float) * 8 * (size_t)((L.maxm + 15) / 16));
+  L.chunk_box = take(sizeof(int4) * (size_t)((L.maxm + 63) / 64 + 8));
+  L.partials = take(sizeof(float) * 8 * (size_t)interp_items(L.maxm));
   L.macro = take(sizeof(float) * 4 * 512 * (size_t)L.cap);
   L.gbuf = take(sizeof(unsigned long long) * 3 * 512 * (size_t)L.cap);
   L.rec = take(sizeof(float) * REC * (size_t)L.maxm);
@@ -164,86 +164,98 @@ bool frame_ok(const lbm_frame *fr) {
 
 lbm_status launched() { return hipGetLastError() == hipSuccess ? LBM_OK : LBM_ERR_DEVICE; }
 
+// Device view of a context; the immersed-boundary fields describe `m` (may be
+// null: no body this step).
+EnvView env_view(lbm_ctx *c, const lbm_markers *m) {
+  EnvView e{};
+  e.g = grid_args(c);
+  const double tau = c->p.tau;
+  e.inv_tau = (float)(1.0 / tau);
+  e.omt = (float)(1.0 - 1.0 / tau);
+  e.pref = (float)(1.0 - 0.5 / tau);
+  e.bx = c->bx;
+  e.by = c->by;
+  e.gx = (c->p.nx + c->bx - 1) / c->bx;
+  e.gy = (c->p.ny + c->by - 1) / c->by;
+  e.nblocks = e.gx * e.gy * c->p.nz;
+  e.f[0] = c->f[0];
+  e.f[1] = c->f[1];
+  e.ib = (m && m->n > 0) ? 1 : 0;
+  e.cap = c->L.cap;
+  e.ntiles = c->L.ntiles;
+  e.alpha2 = (float)(2.0 * c->p.ib_alpha);
+  if (e.ib) {
+    e.n = m->n;
+    e.nbones = m->nbones;
+    e.xrest = m->xrest;
+    e.weight = m->weight;
+    e.dv = m->dv;
+    e.bone = m->bone;
+    e.X = m->X;
+    e.U = m->U;
+    e.F = m->F;
+  }
+  e.tile_flag = wsp<int>(c, c->L.tile_flag);
+  e.tile_slot = wsp<int>(c, c->L.tile_slot);
+  e.active = wsp<int>(c, c->L.active);
+  e.counters = wsp<int>(c, c->L.counters);
+  e.guard = wsp<int>(c, c->L.guard);
+  e.mbase = wsp<short4>(c, c->L.mbase);
+  e.chunk_box = wsp<int4>(c, c->L.chunk_box);
+  e.partials = wsp<float>(c, c->L.partials);
+  e.macro = wsp<float4>(c, c->L.macro);
+  e.gfix = wsp<unsigned long long>(c, c->L.gbuf);
+  e.rec = wsp<float>(c, c->L.rec);
+  e.mstate = wsp<float>(c, c->L.mstate);
+  e.cur0 = c->cur;
+  return e;
+}
+
 // -------------------------------------------------------------- dispatch --
 template <class S>
-lbm_status launch_collide(lbm_ctx *c, const FrameF &fr, bool rot, bool ib) {
-  CollideArgs a;
-  a.g = grid_args(c);
-  a.fr = fr;
-  const double tau = c->p.tau;
-  a.inv_tau = (float)(1.0 / tau);
-  a.omt = (float)(1.0 - 1.0 / tau);
-  a.pref = (float)(1.0 - 0.5 / tau);
-  a.gx = (c->p.nx + c->bx - 1) / c->bx;
-  a.gy = (c->p.ny + c->by - 1) / c->by;
-  a.nblocks = a.gx * a.gy * c->p.nz;
-  const int grid = ((a.nblocks + 7) / 8) * 8;
-  using T = typename S::T;
-  const T *src = static_cast<const T *>(c->f[c->cur]);
-  T *dst = static_cast<T *>(c->f[c->cur ^ 1]);
-  const int *slots = ib ? wsp<int>(c, c->L.tile_slot) : nullptr;
-  const auto *gbuf = wsp<unsigned long long>(c, c->L.gbuf);
-  int *guard = wsp<int>(c, c->L.guard);
+lbm_status launch_collide(lbm_ctx *c, const EnvView &e, const FrameF &fr, bool rot) {
+  const int grid = ((e.nblocks + 7) / 8) * 8;
   dim3 blk(c->bx, c->by);
-  const bool xper = a.g.xper;
+  const bool xper = e.g.xper;
   if (xper && rot)
-    k_collide<S, true, true><<<grid, blk, 0, c->stream>>>(src, dst, a, slots, gbuf, guard);
+    k_collide<S, true, true><<<grid, blk, 0, c->stream>>>(e, fr, c->cur);
   else if (xper)
-    k_collide<S, true, false><<<grid, blk, 0, c->stream>>>(src, dst, a, slots, gbuf, guard);
+    k_collide<S, true, false><<<grid, blk, 0, c->stream>>>(e, fr, c->cur);
   else if (rot)
-    k_collide<S, false, true><<<grid, blk, 0, c->stream>>>(src, dst, a, slots, gbuf, guard);
+    k_collide<S, false, true><<<grid, blk, 0, c->stream>>>(e, fr, c->cur);
   else
-    k_collide<S, false, false><<<grid, blk, 0, c->stream>>>(src, dst, a, slots, gbuf, guard);
+    k_collide<S, false, false><<<grid, blk, 0, c->stream>>>(e, fr, c->cur);
   return launched();
 }
 
 template <class S>
-lbm_status launch_macro(lbm_ctx *c, const IBArgs &a, bool rot) {
-  using T = typename S::T;
-  const T *src = static_cast<const T *>(c->f[c->cur]);
+lbm_status launch_macro(lbm_ctx *c, const EnvView &e, const FrameF &fr, bool rot) {
   const int grid = std::min(c->L.cap, 2048);
-  auto *act = wsp<int>(c, c->L.active);
-  auto *cnt = wsp<int>(c, c->L.counters);
-  auto *macro = wsp<float4>(c, c->L.macro);
-  auto *gfix = wsp<unsigned long long>(c, c->L.gbuf);
   if (rot)
-    k_macro<S, true><<<grid, 512, 0, c->stream>>>(src, act, cnt, macro, gfix, a);
+    k_macro<S, true><<<grid, WG, 0, c->stream>>>(e, fr, c->cur);
   else
-    k_macro<S, false><<<grid, 512, 0, c->stream>>>(src, act, cnt, macro, gfix, a);
+    k_macro<S, false><<<grid, WG, 0, c->stream>>>(e, fr, c->cur);
   return launched();
 }
 
-// wrench != nullptr: also reduce the interpolation kernel's wrench partials.
-lbm_status launch_spread(lbm_ctx *c, const IBArgs &a, float *wrench) {
+// wrench != nullptr: also sum the interpolation kernel's wrench partials.
+lbm_status launch_spread(lbm_ctx *c, const EnvView &e, float *wrench) {
   const int grid = std::min(c->L.cap * kSpreadSplit, 2048);
-  k_spread<<<grid, 1024, 0, c->stream>>>(wsp<float>(c, c->L.rec), wsp<short4>(c, c->L.mbase),
-                                        wsp<int4>(c, c->L.chunk_box), wsp<int>(c, c->L.active),
-                                        wsp<int>(c, c->L.counters), wsp<unsigned long long>(c, c->L.gbuf), a,
-                                        wsp<float>(c, c->L.partials), (a.n + 15) / 16, wrench);
+  k_spread<<<grid, WG, 0, c->stream>>>(e, wrench);
   return launched();
 }
 
-lbm_status launch_interp(lbm_ctx *c, const lbm_markers *m, const IBArgs &a, bool rot, bool mdf, float *wrench) {
-  const int grid = (m->n + 15) / 16;
-  auto *mstate = wsp<float>(c, c->L.mstate);
-  auto *rec = wsp<float>(c, c->L.rec);
-  auto *slots = wsp<int>(c, c->L.tile_slot);
-  auto *macro = wsp<float4>(c, c->L.macro);
-  auto *gbuf = wsp<unsigned long long>(c, c->L.gbuf);
-  auto *guard = wsp<int>(c, c->L.guard);
-  float *part = wrench ? wsp<float>(c, c->L.partials) : nullptr;
-#define LBM_INTERP(R, M)                                                                                         \
-  k_interp<R, M><<<grid, 1024, 0, c->stream>>>(m->X, m->U, m->dv, m->F, mstate, rec, slots, macro, gbuf, a, guard, \
-                                               part)
+lbm_status launch_interp(lbm_ctx *c, const EnvView &e, const FrameF &fr, bool rot, bool mdf, bool want_wrench) {
+  const int grid = interp_items(e.n);
+  float *part = want_wrench ? e.partials : nullptr;
   if (rot && mdf)
-    LBM_INTERP(true, true);
+    k_interp<true, true><<<grid, WG, 0, c->stream>>>(e, fr, part);
   else if (rot)
-    LBM_INTERP(true, false);
+    k_interp<true, false><<<grid, WG, 0, c->stream>>>(e, fr, part);
   else if (mdf)
-    LBM_INTERP(false, true);
+    k_interp<false, true><<<grid, WG, 0, c->stream>>>(e, fr, part);
   else
-    LBM_INTERP(false, false);
-#undef LBM_INTERP
+    k_interp<false, false><<<grid, WG, 0, c->stream>>>(e, fr, part);
   return launched();
 }
 
@@ -255,37 +267,22 @@ template <class S>
 lbm_status step_one(lbm_ctx *c, const lbm_markers *m, const float *pose, const lbm_frame *frame, float *wrench) {
   const FrameF fr = frame_f(frame);
   const bool rot = rotating(frame);
-  const bool ib = m && m->n > 0;
+  const EnvView e = env_view(c, m);
   lbm_status st;
   prof_mark(c, 0);
-  if (ib) {
-    IBArgs a;
-    a.g = grid_args(c);
-    a.fr = fr;
-    a.n = m->n;
-    a.nbones = m->nbones;
-    a.alpha2 = (float)(2.0 * c->p.ib_alpha);
-    a.cap = c->L.cap;
-    auto *guard = wsp<int>(c, c->L.guard);
-    k_skin_mark<<<(m->n + 255) / 256, 256, 0, c->stream>>>(m->xrest, m->bone, m->weight, pose, m->X, m->U,
-                                                            wsp<short4>(c, c->L.mbase), wsp<int>(c, c->L.tile_flag),
-                                                            wsp<int4>(c, c->L.chunk_box), wsp<int>(c, c->L.counters),
-                                                            a, guard);
+  if (e.ib) {
+    k_skin_mark<<<skin_items(e.n), WG, 0, c->stream>>>(e, pose);
     if ((st = launched()) != LBM_OK) return st;
-    k_active<<<(c->L.ntiles + 1023) / 1024, 1024, 0, c->stream>>>(wsp<int>(c, c->L.tile_flag),
-                                                                   wsp<int>(c, c->L.tile_slot),
-                                                                   wsp<int>(c, c->L.active),
-                                                                   wsp<int>(c, c->L.counters), c->L.ntiles,
-                                                                   c->L.cap, guard);
+    k_active<<<(e.ntiles + WG - 1) / WG, WG, 0, c->stream>>>(e);
     if ((st = launched()) != LBM_OK) return st;
     c->slots_dirty = true;
-    if ((st = launch_macro<S>(c, a, rot)) != LBM_OK) return st;
+    if ((st = launch_macro<S>(c, e, fr, rot)) != LBM_OK) return st;
     const int passes = c->p.mdf_iters;
     for (int it = 0; it < passes; ++it) {
-      if (it > 0 && (st = launch_spread(c, a, nullptr)) != LBM_OK) return st;
-      if ((st = launch_interp(c, m, a, rot, it > 0, it == passes - 1 ? wrench : nullptr)) != LBM_OK) return st;
+      if (it > 0 && (st = launch_spread(c, e, nullptr)) != LBM_OK) return st;
+      if ((st = launch_interp(c, e, fr, rot, it > 0, wrench != nullptr && it == passes - 1)) != LBM_OK) return st;
     }
-    if ((st = launch_spread(c, a, wrench)) != LBM_OK) return st;
+    if ((st = launch_spread(c, e, wrench)) != LBM_OK) return st;
   } else if (c->slots_dirty) {
     // no body this step: clear the active-tile map so no stale force is read
     k_fill_int<<<256, 256, 0, c->stream>>>(wsp<int>(c, c->L.tile_slot), -1, c->L.ntiles);
@@ -293,10 +290,10 @@ lbm_status step_one(lbm_ctx *c, const lbm_markers *m, const float *pose, const l
     c->slots_dirty = false;
   }
   prof_mark(c, 1);
-  if ((st = launch_collide<S>(c, fr, rot, ib)) != LBM_OK) return st;
+  if ((st = launch_collide<S>(c, e, fr, rot)) != LBM_OK) return st;
   prof_mark(c, 2);
   if (c->prof && c->prof_used < kProfSteps) c->prof_used++;
-  if (!ib && wrench) {
+  if (!e.ib && wrench) {
     k_fill_int<<<1, 64, 0, c->stream>>>(reinterpret_cast<int *>(wrench), 0, 8);
     if ((st = launched()) != LBM_OK) return st;
   }
