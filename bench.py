@@ -95,6 +95,40 @@ def run_gpu(storage: str, steps: int, warmup: int, block=(0, 0)):
     return res
 
 
+def run_batch(nenv: int, nsteps: int, seed: int = 4):
+    """Batched environments: nenv fish environments of uneven sizes (seeded
+    draw), nsteps steps per run, one run = one graph replay. Returns MLUPS
+    per driver with autotuned tile shapes."""
+    import numpy as np
+    import torch
+
+    from paper_2206_01683_amd import inputs as I
+    from paper_2206_01683_amd import lbm
+
+    envs = I.batch_workloads(count=nenv, seed=seed, nsteps=nsteps)
+    b = lbm.Batch(envs, nsteps)
+    shapes = b.autotune(reps=3)
+    ncell = b.ncell
+    out = {"envs": nenv, "steps_per_run": nsteps, "cells": ncell,
+           "markers": int(sum(w.markers.n for w in envs)),
+           "shapes": {f"{bx}x{by}": int(((shapes[:, 0] == bx) & (shapes[:, 1] == by)).sum())
+                      for bx, by in lbm.BATCH_SHAPES}}
+    for mode in ("persistent", "phases"):
+        b.run(nsteps, mode=mode, graph=True)  # capture + warm-up replay
+        b.synchronize()
+        t0 = time.perf_counter()
+        b.run(nsteps, mode=mode, graph=True)
+        b.synchronize()
+        dt = time.perf_counter() - t0
+        out[mode] = {"mlups": round(ncell * nsteps / dt / 1e6, 1), "ms_per_step": round(dt * 1e3 / nsteps, 4),
+                     "hbm_frac_216B": round(ncell * nsteps * 216 / dt / (HBM_PEAK_GBS * 1e9), 4)}
+    out["status"] = b.check()
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(sample_steps: int):
     """The FP64 oracle as it stands, on the host cores, on the first
     sample_steps steps of the same workload (same domain, fish and frames)."""
@@ -124,6 +158,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle sample length (0: skip)")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP16/BF16 storage forms")
     ap.add_argument("--block", type=int, nargs=2, default=(0, 0))
+    ap.add_argument("--batch-envs", type=int, default=64, help="batched form: environments (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=200, help="batched form: steps per graph replay")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -140,6 +176,8 @@ def main():
             forms[st] = {"mlups": round(r["mlups"], 1), "collide_GBps": round(r["collide_gbs"], 1),
                          "collide_frac_of_hbm_peak": round(r["collide_gbs"] / HBM_PEAK_GBS, 4),
                          "bytes_per_cell": BYTES_PER_CELL[st], "status": r["status"]}
+    if not args.no_forms and args.batch_envs > 0:
+        forms["batched"] = run_batch(args.batch_envs, args.batch_steps)
     traffic = measured_traffic(args.storage)
     ach = main_run["collide_gbs"]
     out = {

@@ -189,6 +189,63 @@ int64_t lbm_step_count(const lbm_ctx *c);
 const char *lbm_strerror(lbm_status s);
 void lbm_destroy(lbm_ctx *c);
 
+/* ---------------------------------------------------------------------------
+ * Batched environments: many lattices of different sizes, each with its own
+ * body (the many-environment setting the simulator serves for learning,
+ * Sec. III-C), advanced together by one work list per phase. Each
+ * environment is an lbm_ctx created by lbm_init with F32 storage and a
+ * collide block of block_x * block_y = 512 threads. Per-step inputs live in
+ * device arrays so that a whole run can be one launch.
+ * ------------------------------------------------------------------------- */
+typedef struct lbm_batch lbm_batch;
+
+/* [host] One environment of a batch. All pointers are device pointers valid
+ * for the lifetime of the batch; poses/frames/wrench are indexed by the step
+ * of a run (0 .. nsteps-1) and are re-read by every run. */
+typedef struct {
+  lbm_ctx *ctx;             /* initialized context (F32, 512-thread collide block) */
+  lbm_markers m;            /* n >= 1 markers, nbones <= the context's max_bones */
+  const float *poses;       /* [nsteps][m.nbones][24] */
+  const lbm_frame *frames;  /* [nsteps] device copy of the frames */
+  float *wrench;            /* [nsteps][8] or NULL */
+  int32_t rotating;         /* 0: every frame has omega = alpha = 0 (cheaper arithmetic); 1: general */
+} lbm_env;
+
+enum { LBM_BATCH_PHASES = 0,     /* one launch per phase per step */
+       LBM_BATCH_PERSISTENT = 1  /* one launch for all steps, device-wide barriers between phases */
+};
+
+/* Bytes of the device buffer a batch of nenv environments needs (descriptors,
+ * work-list prefixes, barrier state). 0 if nenv is outside [1, 512]. */
+size_t lbm_batch_bytes(int32_t nenv);
+
+/* Create a batch over envs [host, nenv entries] using the caller's device
+ * buffer dev (lbm_batch_bytes(nenv), 256-byte aligned) and HIP stream
+ * (must not be the null stream if graphs are used). All environments must
+ * use the same mdf_iters. Uploads the descriptors and synchronizes. */
+lbm_status lbm_batch_create(lbm_batch **out, const lbm_env *envs, int32_t nenv, void *dev, void *hip_stream);
+
+/* Advance every environment by nsteps steps with the given driver. graph != 0:
+ * the launches are captured once into a HIP graph (per (nsteps, mode)) and the
+ * graph is replayed; nsteps must then be even, so that every replay starts
+ * from the same population buffer. Does not synchronize. */
+lbm_status lbm_batch_run(lbm_batch *b, int32_t nsteps, int32_t mode, int32_t graph);
+
+/* Tile-shape autotuner: for every environment time the collide kernel with
+ * each 512-thread shape (64x8, 128x4, 256x2, 512x1) over reps launches and keep
+ * the fastest. The state is not advanced. shapes_out [host, nenv][2] or NULL.
+ * Synchronizes. */
+lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, int32_t *shapes_out);
+
+/* Apply shapes [host, nenv][2] (e.g. a cached autotuning result). */
+lbm_status lbm_batch_set_shapes(lbm_batch *b, const int32_t *shapes);
+
+/* Synchronize; LBM_ERR_DEVICE if a persistent run's barrier timed out,
+ * otherwise the first non-OK lbm_check of the environments. */
+lbm_status lbm_batch_check(lbm_batch *b);
+
+void lbm_batch_destroy(lbm_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,257 @@
+// Batched forms: many environments (lattices of different sizes, each with
+// its own body) advanced together.
+//
+// Every phase of a step becomes one work list over all environments: item i
+// of a phase belongs to the environment whose prefix range holds it. Static
+// item counts (markers, tiles, collide blocks) come with host-computed
+// prefixes; the active-tile counts are only known on the device, so the
+// macro and spreading phases build their prefix in LDS from the counters.
+// Two drivers use the same phase functions:
+//   kb_* kernels     one launch per phase (a step = 6+ launches), suitable for
+//                    capture into a graph of many steps;
+//   kb_persistent    one launch for all steps: each workgroup loops over the
+//                    phases, separated by a device-wide barrier. The grid is
+//                    sized to be co-resident; the barrier's wait is bounded
+//                    (a timeout sets a status bit and every workgroup exits).
+// UNI = true: every environment has open x faces and non-rotating frames,
+// so the per-environment branches on those flags compile away.
+#pragma once
+
+#include "ib.hpp"
+
+namespace lbmib {
+
+constexpr int kMaxEnvs = WG;  // one thread per environment in the LDS prefix scan
+
+struct BatchArgs {
+  const EnvView *envs;  // [nenv]
+  int nenv;
+  const int *pre;       // [4][nenv + 1] exclusive item prefixes: skin, active, interp, collide
+  int tot[4];
+  int mdf;              // direct-forcing passes
+  unsigned *bar;        // grid barrier: [0] arrivals, [1] generation
+  int *status;          // bit 0: barrier timeout
+};
+
+enum { PRE_SKIN = 0, PRE_ACTIVE = 1, PRE_INTERP = 2, PRE_COLLIDE = 3 };
+
+// Largest e with pre[e] <= item (pre non-decreasing, pre[nenv] > item).
+__device__ inline int find_env(const int *pre, int nenv, int item) {
+  int lo = 0, hi = nenv;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= item)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Exclusive prefix over environments of (active tiles x mult), in LDS.
+// Returns the total. Every thread of the workgroup must call it.
+__device__ inline int dynamic_prefix(const BatchArgs &b, int mult, int *s_pre, int tid) {
+  int v = 0;
+  if (tid < b.nenv) v = n_active_of(b.envs[tid]) * mult;
+  s_pre[tid + 1] = v;
+  if (tid == 0) s_pre[0] = 0;
+  __syncthreads();
+  for (int off = 1; off < WG; off <<= 1) {
+    const int add = tid >= off ? s_pre[tid + 1 - off] : 0;
+    __syncthreads();
+    s_pre[tid + 1] += add;
+    __syncthreads();
+  }
+  return s_pre[b.nenv];
+}
+
+__device__ inline FrameF env_frame(const EnvView &e, int s) { return frame_from(e.frames + (size_t)18 * s); }
+__device__ inline int env_cur(const EnvView &e, int s) { return e.cur0 ^ (s & 1); }
+
+// ------------------------------------------------------------ phase bodies --
+__device__ inline void phase_skin(const BatchArgs &b, int s, int item, int tid) {
+  const int ei = find_env(b.pre + PRE_SKIN * (b.nenv + 1), b.nenv, item);
+  const EnvView &e = b.envs[ei];
+  skin_item(e, e.poses + (size_t)s * e.nbones * 24, item - b.pre[PRE_SKIN * (b.nenv + 1) + ei], tid);
+}
+
+__device__ inline void phase_active(const BatchArgs &b, int item, int tid) {
+  const int ei = find_env(b.pre + PRE_ACTIVE * (b.nenv + 1), b.nenv, item);
+  active_item(b.envs[ei], item - b.pre[PRE_ACTIVE * (b.nenv + 1) + ei], tid);
+}
+
+template <bool UNI>
+__device__ inline void phase_macro(const BatchArgs &b, int s, int item, const int *s_pre, int tid) {
+  const int ei = find_env(s_pre, b.nenv, item);
+  const EnvView &e = b.envs[ei];
+  const FrameF fr = env_frame(e, s);
+  if (!UNI && e.rot)
+    macro_item<StoreF32, true>(e, fr, env_cur(e, s), item - s_pre[ei], tid);
+  else
+    macro_item<StoreF32, false>(e, fr, env_cur(e, s), item - s_pre[ei], tid);
+}
+
+template <bool UNI>
+__device__ inline void phase_interp(const BatchArgs &b, int s, int pass, int item, int tid) {
+  const int ei = find_env(b.pre + PRE_INTERP * (b.nenv + 1), b.nenv, item);
+  const EnvView &e = b.envs[ei];
+  const FrameF fr = env_frame(e, s);
+  const int local = item - b.pre[PRE_INTERP * (b.nenv + 1) + ei];
+  float *part = (e.wrench != nullptr && pass == b.mdf - 1) ? e.partials : nullptr;
+  if (!UNI && e.rot) {
+    if (pass > 0)
+      interp_item<true, true>(e, fr, local, tid, part);
+    else
+      interp_item<true, false>(e, fr, local, tid, part);
+  } else {
+    if (pass > 0)
+      interp_item<false, true>(e, fr, local, tid, part);
+    else
+      interp_item<false, false>(e, fr, local, tid, part);
+  }
+}
+
+// final: the step's last spreading pass; its first item per environment also
+// sums the wrench partials.
+__device__ inline void phase_spread(const BatchArgs &b, int s, bool final_pass, int item, const int *s_pre,
+                                    int tid) {
+  const int ei = find_env(s_pre, b.nenv, item);
+  const EnvView &e = b.envs[ei];
+  const int local = item - s_pre[ei];
+  if (final_pass && local == 0 && e.wrench != nullptr)
+    wrench_sum(e.partials, interp_items(e.n), e.wrench + (size_t)8 * s, tid);
+  spread_item(e, local, tid);
+}
+
+// Collide item -> (environment, logical block); 512 threads as e.bx x e.by.
+template <bool UNI>
+__device__ inline void phase_collide(const BatchArgs &b, int s, int item, int tid) {
+  const int ei = find_env(b.pre + PRE_COLLIDE * (b.nenv + 1), b.nenv, item);
+  const EnvView &e = b.envs[ei];
+  const FrameF fr = env_frame(e, s);
+  const int lb = item - b.pre[PRE_COLLIDE * (b.nenv + 1) + ei];
+  const int cur = env_cur(e, s);
+  const int tx = tid % e.bx, ty = tid / e.bx;
+  if (UNI) {
+    collide_cell<StoreF32, false, false>(e, fr, cur, lb, tx, ty);
+  } else if (e.g.xper) {
+    if (e.rot)
+      collide_cell<StoreF32, true, true>(e, fr, cur, lb, tx, ty);
+    else
+      collide_cell<StoreF32, true, false>(e, fr, cur, lb, tx, ty);
+  } else {
+    if (e.rot)
+      collide_cell<StoreF32, false, true>(e, fr, cur, lb, tx, ty);
+    else
+      collide_cell<StoreF32, false, false>(e, fr, cur, lb, tx, ty);
+  }
+}
+
+// Collide work item of hardware workgroup position i out of a grid of g
+// (g a multiple of 8): each XCD (i % 8) takes a contiguous eighth of the items.
+__device__ inline int xcd_item(int i, int total) {
+  const int per = (total + 7) >> 3;
+  return (i & 7) * per + (i >> 3);
+}
+
+// ------------------------------------------------------ per-phase kernels --
+__global__ void __launch_bounds__(WG) kb_skin(BatchArgs b, int s) { phase_skin(b, s, blockIdx.x, threadIdx.x); }
+
+__global__ void __launch_bounds__(WG) kb_active(BatchArgs b) { phase_active(b, blockIdx.x, threadIdx.x); }
+
+template <bool UNI>
+__global__ void __launch_bounds__(WG) kb_macro(BatchArgs b, int s) {
+  __shared__ int s_pre[kMaxEnvs + 1];
+  const int tot = dynamic_prefix(b, 1, s_pre, threadIdx.x);
+  for (int item = blockIdx.x; item < tot; item += gridDim.x) phase_macro<UNI>(b, s, item, s_pre, threadIdx.x);
+}
+
+template <bool UNI>
+__global__ void __launch_bounds__(WG) kb_interp(BatchArgs b, int s, int pass) {
+  phase_interp<UNI>(b, s, pass, blockIdx.x, threadIdx.x);
+}
+
+__global__ void __launch_bounds__(WG) kb_spread(BatchArgs b, int s, int final_pass) {
+  __shared__ int s_pre[kMaxEnvs + 1];
+  const int tot = dynamic_prefix(b, kSpreadSplit, s_pre, threadIdx.x);
+  for (int item = blockIdx.x; item < tot; item += gridDim.x)
+    phase_spread(b, s, final_pass != 0, item, s_pre, threadIdx.x);
+}
+
+template <bool UNI>
+__global__ void __launch_bounds__(WG) kb_collide(BatchArgs b, int s) {
+  const int item = xcd_item(blockIdx.x, b.tot[PRE_COLLIDE]);
+  if (item < b.tot[PRE_COLLIDE]) phase_collide<UNI>(b, s, item, threadIdx.x);
+}
+
+// --------------------------------------------------------- grid barrier ----
+constexpr long kBarrierSpins = 1L << 25;  // ~1 s of waiting: a longer wait is a failure
+
+// Device-wide barrier for a co-resident grid. Release: each workgroup's
+// writes are made visible at device scope before it arrives; acquire: after
+// the generation changes. Returns false (in every thread) after a timeout.
+__device__ inline bool grid_sync(const BatchArgs &b) {
+  __shared__ int s_ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    __threadfence();
+    const unsigned gen = __hip_atomic_load(&b.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned arrived = __hip_atomic_fetch_add(&b.bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == gridDim.x - 1) {
+      __hip_atomic_store(&b.bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&b.bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      long spins = 0;
+      while (__hip_atomic_load(&b.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kBarrierSpins) {
+          ok = 0;
+          break;
+        }
+      }
+    }
+    if (!ok) atomicOr(b.status, 1);
+    if (__hip_atomic_load(b.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1) ok = 0;
+    __threadfence();
+    s_ok = ok;
+  }
+  __syncthreads();
+  return s_ok != 0;
+}
+
+// All steps of all environments in one launch (grid: co-resident, multiple of
+// 8). At most 128 VGPRs, so that two workgroups (16 waves) share a CU.
+template <bool UNI>
+__global__ void __launch_bounds__(WG, 2) kb_persistent(BatchArgs b, int nsteps) {
+  __shared__ int s_pre[kMaxEnvs + 1];
+  const int tid = threadIdx.x;
+  for (int s = 0; s < nsteps; ++s) {
+    for (int item = blockIdx.x; item < b.tot[PRE_SKIN]; item += gridDim.x) phase_skin(b, s, item, tid);
+    if (!grid_sync(b)) return;
+    for (int item = blockIdx.x; item < b.tot[PRE_ACTIVE]; item += gridDim.x) phase_active(b, item, tid);
+    if (!grid_sync(b)) return;
+    int tot = dynamic_prefix(b, 1, s_pre, tid);
+    for (int item = blockIdx.x; item < tot; item += gridDim.x) phase_macro<UNI>(b, s, item, s_pre, tid);
+    if (!grid_sync(b)) return;
+    tot = dynamic_prefix(b, kSpreadSplit, s_pre, tid);
+    for (int pass = 0; pass < b.mdf; ++pass) {
+      if (pass > 0) {
+        for (int item = blockIdx.x; item < tot; item += gridDim.x) phase_spread(b, s, false, item, s_pre, tid);
+        if (!grid_sync(b)) return;
+      }
+      for (int item = blockIdx.x; item < b.tot[PRE_INTERP]; item += gridDim.x)
+        phase_interp<UNI>(b, s, pass, item, tid);
+      if (!grid_sync(b)) return;
+    }
+    for (int item = blockIdx.x; item < tot; item += gridDim.x) phase_spread(b, s, true, item, s_pre, tid);
+    if (!grid_sync(b)) return;
+    for (int i = blockIdx.x; i < ((b.tot[PRE_COLLIDE] + 7) & ~7); i += gridDim.x) {
+      const int item = xcd_item(i, b.tot[PRE_COLLIDE]);
+      if (item < b.tot[PRE_COLLIDE]) phase_collide<UNI>(b, s, item, tid);
+    }
+    if (!grid_sync(b)) return;
+  }
+}
+
+}  // namespace lbmib

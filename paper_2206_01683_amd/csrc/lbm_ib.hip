@@ -14,7 +14,7 @@
 #include <vector>
 
 #include "../../include/lbm_ib.h"
-#include "ib.hpp"
+#include "batch.hpp"
 
 using namespace lbmib;
 
@@ -515,6 +515,330 @@ void lbm_destroy(lbm_ctx *c) {
   if (!c) return;
   for (auto &e : c->ev) (void)hipEventDestroy(e);
   delete c;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batch --
+struct lbm_batch {
+  int nenv;
+  std::vector<lbm_env> envs;
+  std::vector<EnvView> views;  // host copy of the uploaded descriptors
+  std::vector<int> pre;        // [4][nenv + 1]
+  EnvView *d_envs;
+  int *d_pre;
+  unsigned *d_bar;
+  int *d_status;
+  int tot[4];
+  int mdf;
+  hipStream_t stream;
+  int persistent_grid[2];  // [uniform]
+  bool uniform;            // all environments open in x and non-rotating
+  bool dirty;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  int graph_nsteps, graph_mode;
+};
+
+namespace {
+
+size_t batch_layout(int nenv, size_t *o_envs, size_t *o_pre, size_t *o_bar) {
+  size_t o = 0;
+  *o_envs = o;
+  o = align_up(o + sizeof(EnvView) * (size_t)nenv, 256);
+  *o_pre = o;
+  o = align_up(o + sizeof(int) * 4 * (size_t)(nenv + 1), 256);
+  *o_bar = o;
+  o = align_up(o + 64, 256);
+  return o;
+}
+
+bool env_ok(const lbm_env &v) {
+  const lbm_ctx *c = v.ctx;
+  if (!c || c->p.storage != LBM_STORE_F32 || c->bx * c->by != WG) return false;
+  if (v.m.n < 1 || v.m.n > c->p.max_markers || !markers_ok(c, &v.m)) return false;
+  if (!v.poses || !v.frames) return false;
+  return true;
+}
+
+void batch_views(lbm_batch *b) {
+  for (int e = 0; e < b->nenv; ++e) {
+    lbm_ctx *c = b->envs[e].ctx;
+    EnvView v = env_view(c, &b->envs[e].m);
+    v.poses = b->envs[e].poses;
+    v.frames = reinterpret_cast<const double *>(b->envs[e].frames);
+    v.wrench = b->envs[e].wrench;
+    v.rot = b->envs[e].rotating ? 1 : 0;
+    v.cur0 = c->cur;
+    b->views[e] = v;
+  }
+  const int stride = b->nenv + 1;
+  for (int q = 0; q < 4; ++q) b->pre[q * stride] = 0;
+  for (int e = 0; e < b->nenv; ++e) {
+    const EnvView &v = b->views[e];
+    b->pre[0 * stride + e + 1] = b->pre[0 * stride + e] + skin_items(v.n);
+    b->pre[1 * stride + e + 1] = b->pre[1 * stride + e] + (v.ntiles + WG - 1) / WG;
+    b->pre[2 * stride + e + 1] = b->pre[2 * stride + e] + interp_items(v.n);
+    b->pre[3 * stride + e + 1] = b->pre[3 * stride + e] + v.nblocks;
+  }
+  for (int q = 0; q < 4; ++q) b->tot[q] = b->pre[q * stride + b->nenv];
+}
+
+lbm_status batch_upload(lbm_batch *b) {
+  batch_views(b);
+  if (hipMemcpyAsync(b->d_envs, b->views.data(), sizeof(EnvView) * b->nenv, hipMemcpyHostToDevice, b->stream) !=
+          hipSuccess ||
+      hipMemcpyAsync(b->d_pre, b->pre.data(), sizeof(int) * b->pre.size(), hipMemcpyHostToDevice, b->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(b->stream) != hipSuccess)
+    return LBM_ERR_DEVICE;
+  b->dirty = false;
+  return LBM_OK;
+}
+
+BatchArgs batch_args(const lbm_batch *b) {
+  BatchArgs a;
+  a.envs = b->d_envs;
+  a.nenv = b->nenv;
+  a.pre = b->d_pre;
+  for (int q = 0; q < 4; ++q) a.tot[q] = b->tot[q];
+  a.mdf = b->mdf;
+  a.bar = b->d_bar;
+  a.status = b->d_status;
+  return a;
+}
+
+template <bool UNI>
+lbm_status batch_enqueue_t(lbm_batch *b, int nsteps, int mode) {
+  const BatchArgs a = batch_args(b);
+  if (mode == LBM_BATCH_PERSISTENT) {
+    kb_persistent<UNI><<<b->persistent_grid[UNI ? 1 : 0], WG, 0, b->stream>>>(a, nsteps);
+    return launched();
+  }
+  int cap_items = 0;
+  for (int e = 0; e < b->nenv; ++e) cap_items += b->views[e].cap;
+  const int gdyn = std::max(8, std::min(cap_items * kSpreadSplit, 4096));
+  const int gcol = ((b->tot[PRE_COLLIDE] + 7) / 8) * 8;
+  for (int s = 0; s < nsteps; ++s) {
+    kb_skin<<<b->tot[PRE_SKIN], WG, 0, b->stream>>>(a, s);
+    kb_active<<<b->tot[PRE_ACTIVE], WG, 0, b->stream>>>(a);
+    kb_macro<UNI><<<gdyn, WG, 0, b->stream>>>(a, s);
+    for (int pass = 0; pass < b->mdf; ++pass) {
+      if (pass > 0) kb_spread<<<gdyn, WG, 0, b->stream>>>(a, s, 0);
+      kb_interp<UNI><<<b->tot[PRE_INTERP], WG, 0, b->stream>>>(a, s, pass);
+    }
+    kb_spread<<<gdyn, WG, 0, b->stream>>>(a, s, 1);
+    kb_collide<UNI><<<gcol, WG, 0, b->stream>>>(a, s);
+    lbm_status st = launched();
+    if (st != LBM_OK) return st;
+  }
+  return LBM_OK;
+}
+
+lbm_status batch_enqueue(lbm_batch *b, int nsteps, int mode) {
+  return b->uniform ? batch_enqueue_t<true>(b, nsteps, mode) : batch_enqueue_t<false>(b, nsteps, mode);
+}
+
+void batch_drop_graph(lbm_batch *b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->graph_nsteps = -1;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_batch_bytes(int32_t nenv) {
+  if (nenv < 1 || nenv > kMaxEnvs) return 0;
+  size_t a, p, q;
+  return batch_layout(nenv, &a, &p, &q);
+}
+
+lbm_status lbm_batch_create(lbm_batch **out, const lbm_env *envs, int32_t nenv, void *dev, void *hip_stream) {
+  if (!out || !envs || nenv < 1 || nenv > kMaxEnvs || !dev) return LBM_ERR_ARG;
+  if (reinterpret_cast<uintptr_t>(dev) % 256 != 0) return LBM_ERR_ARG;
+  *out = nullptr;
+  for (int e = 0; e < nenv; ++e) {
+    if (!env_ok(envs[e])) return LBM_ERR_ARG;
+    if (envs[e].ctx->p.mdf_iters != envs[0].ctx->p.mdf_iters) return LBM_ERR_ARG;
+    for (int f = 0; f < e; ++f)
+      if (envs[f].ctx == envs[e].ctx) return LBM_ERR_ARG;
+  }
+  lbm_batch *b = new (std::nothrow) lbm_batch;
+  if (!b) return LBM_ERR_ARG;
+  b->nenv = nenv;
+  b->envs.assign(envs, envs + nenv);
+  b->views.resize(nenv);
+  b->pre.assign(4 * (size_t)(nenv + 1), 0);
+  size_t o_envs, o_pre, o_bar;
+  batch_layout(nenv, &o_envs, &o_pre, &o_bar);
+  char *base = static_cast<char *>(dev);
+  b->d_envs = reinterpret_cast<EnvView *>(base + o_envs);
+  b->d_pre = reinterpret_cast<int *>(base + o_pre);
+  b->d_bar = reinterpret_cast<unsigned *>(base + o_bar);
+  b->d_status = reinterpret_cast<int *>(base + o_bar + 32);
+  b->mdf = envs[0].ctx->p.mdf_iters;
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  b->graph = nullptr;
+  b->exec = nullptr;
+  b->graph_nsteps = -1;
+  b->graph_mode = -1;
+  b->uniform = true;
+  for (int e = 0; e < nenv; ++e)
+    if (envs[e].rotating || envs[e].ctx->p.bc_lo == LBM_BC_PERIODIC) b->uniform = false;
+  int dev_id = 0, cus = 0, per_cu[2] = {0, 0};
+  if (hipGetDevice(&dev_id) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu[0], kb_persistent<false>, WG, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu[1], kb_persistent<true>, WG, 0) != hipSuccess ||
+      per_cu[0] < 1 || per_cu[1] < 1) {
+    delete b;
+    return LBM_ERR_DEVICE;
+  }
+  for (int u = 0; u < 2; ++u) b->persistent_grid[u] = std::max(8, (per_cu[u] * cus) / 8 * 8);
+  k_fill_int<<<1, 64, 0, b->stream>>>(reinterpret_cast<int *>(b->d_bar), 0, 16);
+  lbm_status st = launched();
+  if (st == LBM_OK) st = batch_upload(b);
+  if (st != LBM_OK) {
+    delete b;
+    return st;
+  }
+  *out = b;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_run(lbm_batch *b, int32_t nsteps, int32_t mode, int32_t graph) {
+  if (!b || nsteps < 0 || (mode != LBM_BATCH_PHASES && mode != LBM_BATCH_PERSISTENT)) return LBM_ERR_ARG;
+  if (graph && (nsteps % 2 != 0 || b->stream == nullptr)) return LBM_ERR_ARG;
+  if (nsteps == 0) return LBM_OK;
+  lbm_status st;
+  for (int e = 0; e < b->nenv; ++e)
+    if (b->views[e].cur0 != b->envs[e].ctx->cur) b->dirty = true;
+  if (b->dirty) {
+    batch_drop_graph(b);
+    if ((st = batch_upload(b)) != LBM_OK) return st;
+  }
+  if (graph) {
+    if (!b->exec || b->graph_nsteps != nsteps || b->graph_mode != mode) {
+      batch_drop_graph(b);
+      if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return LBM_ERR_DEVICE;
+      st = batch_enqueue(b, nsteps, mode);
+      hipGraph_t g = nullptr;
+      const hipError_t ce = hipStreamEndCapture(b->stream, &g);
+      if (st != LBM_OK || ce != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return LBM_ERR_DEVICE;
+      }
+      b->graph = g;
+      if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        batch_drop_graph(b);
+        return LBM_ERR_DEVICE;
+      }
+      b->graph_nsteps = nsteps;
+      b->graph_mode = mode;
+    }
+    if (hipGraphLaunch(b->exec, b->stream) != hipSuccess) return LBM_ERR_DEVICE;
+  } else if ((st = batch_enqueue(b, nsteps, mode)) != LBM_OK) {
+    return st;
+  }
+  for (int e = 0; e < b->nenv; ++e) {
+    lbm_ctx *c = b->envs[e].ctx;
+    c->cur ^= (nsteps & 1);
+    c->steps += nsteps;
+    c->slots_dirty = true;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, int32_t *shapes_out) {
+  if (!b || reps < 1) return LBM_ERR_ARG;
+  static const int cand[4][2] = {{64, 8}, {128, 4}, {256, 2}, {512, 1}};
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return LBM_ERR_DEVICE;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return LBM_ERR_DEVICE;
+  }
+  lbm_status st = LBM_OK;
+  for (int e = 0; e < b->nenv && st == LBM_OK; ++e) {
+    lbm_ctx *c = b->envs[e].ctx;
+    hipStream_t keep = c->stream;
+    c->stream = b->stream;
+    float best = 1e30f;
+    int bi = 1;
+    for (int q = 0; q < 4 && st == LBM_OK; ++q) {
+      if (cand[q][0] > (int)align_up((size_t)c->p.nx, 64) && q > 0) continue;
+      c->bx = cand[q][0];
+      c->by = cand[q][1];
+      const EnvView v = env_view(c, nullptr);
+      // the collide reads f[cur] and writes f[cur ^ 1] (scratch until the next
+      // step), so timing it leaves the state unchanged
+      st = launch_collide<StoreF32>(c, v, FrameF{}, false);
+      if (st != LBM_OK || hipEventRecord(e0, b->stream) != hipSuccess) break;
+      for (int r = 0; r < reps && st == LBM_OK; ++r) st = launch_collide<StoreF32>(c, v, FrameF{}, false);
+      float ms = 0.f;
+      if (st != LBM_OK || hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        st = LBM_ERR_DEVICE;
+        break;
+      }
+      if (ms < best) {
+        best = ms;
+        bi = q;
+      }
+    }
+    c->bx = cand[bi][0];
+    c->by = cand[bi][1];
+    c->stream = keep;
+    if (shapes_out) {
+      shapes_out[2 * e] = c->bx;
+      shapes_out[2 * e + 1] = c->by;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->dirty = true;
+  return st;
+}
+
+lbm_status lbm_batch_set_shapes(lbm_batch *b, const int32_t *shapes) {
+  if (!b || !shapes) return LBM_ERR_ARG;
+  for (int e = 0; e < b->nenv; ++e) {
+    const int bx = shapes[2 * e], by = shapes[2 * e + 1];
+    if (bx < 64 || bx % 64 != 0 || bx * by != WG) return LBM_ERR_ARG;
+  }
+  for (int e = 0; e < b->nenv; ++e) {
+    b->envs[e].ctx->bx = shapes[2 * e];
+    b->envs[e].ctx->by = shapes[2 * e + 1];
+  }
+  b->dirty = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_check(lbm_batch *b) {
+  if (!b) return LBM_ERR_ARG;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return LBM_ERR_DEVICE;
+  int status = 0;
+  if (hipMemcpy(&status, b->d_status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return LBM_ERR_DEVICE;
+  if (status & 1) return LBM_ERR_DEVICE;
+  for (int e = 0; e < b->nenv; ++e) {
+    lbm_ctx *c = b->envs[e].ctx;
+    hipStream_t keep = c->stream;
+    c->stream = b->stream;
+    const lbm_status st = lbm_check(c);
+    c->stream = keep;
+    if (st != LBM_OK) return st;
+  }
+  return LBM_OK;
+}
+
+void lbm_batch_destroy(lbm_batch *b) {
+  if (!b) return;
+  batch_drop_graph(b);
+  delete b;
 }
 
 }  // extern "C"

@@ -381,15 +381,32 @@ def fin_workload(params=C5_BASE, nsteps: int = 400, nx: int = 128, ny: int = 64,
     return w
 
 
+def _max_marker_speed(ms: MarkerSet, pose: np.ndarray) -> float:
+    """Largest skinned marker speed of one pose (rates included)."""
+    U = np.zeros((3, ms.n))
+    for j in range(2):
+        P = pose[ms.bone[j]]
+        Rd = P[:, 12:21].reshape(-1, 3, 3)
+        U += ms.weight[j] * (np.einsum('kab,bk->ak', Rd, ms.xrest) + P[:, 21:24].T)
+    return float(np.linalg.norm(U, axis=0).max())
+
+
+BATCH_MAX_MARKER_SPEED = 0.08
+
+
 def batch_workloads(count: int = 64, seed: int = 4, nsteps: int = 200):
     """Batched environments: sizes nx ~ U{64..192}, ny, nz ~ U{48..96}
     (independent integers), markers n ~ U{2000..6000}, joint-angle targets
     ~ U[-0.4, 0.4]^10, all drawn from numpy's default_rng(seed) in that order
     per environment. Fish of length round(0.4 nx) with its head at
     (0.25 nx, ny/2, nz/2); inflow (0.05, 0, 0) with a zero-gradient outlet,
-    no noise. Targets ramp in over 50 steps. A pose that brings a marker
-    within 2 cells of any face (3 on the high side) has its targets halved
-    until it fits; the number of halvings is recorded in meta."""
+    no noise. The joint angles approach their targets along a half-cosine
+    ramp. Two deterministic adjustments keep the workload valid, both
+    recorded in meta: targets are halved until every pose of the ramp keeps
+    the markers 2 cells (3 on the high side) inside the domain, and the ramp
+    is lengthened from 50 steps until the fastest marker moves at most
+    BATCH_MAX_MARKER_SPEED lattice units per step (a lattice Boltzmann fluid
+    must stay well below the lattice speed of sound, 0.577)."""
     rng = np.random.default_rng(seed)
     out = []
     u_in = np.array([0.05, 0.0, 0.0])
@@ -403,13 +420,13 @@ def batch_workloads(count: int = 64, seed: int = 4, nsteps: int = 200):
         head = (0.25 * nx, ny / 2.0, nz / 2.0)
         ms = fish_surface(n, length, head)
         halvings = 0
-        steps = np.arange(nsteps)
+        probe = np.array([0.0, 12.5, 25.0, 37.5, 50.0])  # ramp fractions 0 .. 1 for a 50-step ramp
         while True:
-            th, thd = ramp_joint_angles(targets, steps)
+            th, thd = ramp_joint_angles(targets, probe, ramp=50.0)
             psi, psid = headings_from_joint_angles(th, thd)
             poses = chain_poses(psi, psid, ms.joints_rest)
             ok = True
-            for s in range(0, nsteps, 5):
+            for s in range(len(probe)):
                 X = skin_positions(ms, poses[s])
                 for a, m in enumerate((nx, ny, nz)):
                     if X[a].min() < 2.0 or X[a].max() >= m - 3.0:
@@ -418,10 +435,19 @@ def batch_workloads(count: int = 64, seed: int = 4, nsteps: int = 200):
                 break
             targets = targets * 0.5
             halvings += 1
+        # marker speed scales as 1 / ramp length; the half-cosine rate peaks mid-ramp
+        th, thd = ramp_joint_angles(targets, np.array([25.0]), ramp=50.0)
+        psi, psid = headings_from_joint_angles(th, thd)
+        v50 = _max_marker_speed(ms, chain_poses(psi, psid, ms.joints_rest)[0])
+        ramp = float(math.ceil(50.0 * max(1.0, v50 / BATCH_MAX_MARKER_SPEED)))
+        steps = np.arange(nsteps)
+        th, thd = ramp_joint_angles(targets, steps, ramp=ramp)
+        psi, psid = headings_from_joint_angles(th, thd)
+        poses = chain_poses(psi, psid, ms.joints_rest)
         frames = make_frames(nsteps, origin=ms.xrest.mean(axis=1), u_lo=u_in, u_hi=u_in)
         u0 = np.broadcast_to(u_in.reshape(3, 1, 1, 1), (3, nz, ny, nx)).copy()
         w = Workload(f"env{e}-{nx}x{ny}x{nz}", nx, ny, nz, 0.6, BC_VELOCITY, BC_OUTFLOW, nsteps, u0, ms, poses,
                      frames, heading=np.array([-1.0, 0.0, 0.0]))
-        w.meta.update(targets=targets, halvings=halvings)
+        w.meta.update(targets=targets, halvings=halvings, ramp=ramp)
         out.append(w)
     return out

@@ -43,6 +43,15 @@ class Markers(ctypes.Structure):
                 ("dv", ctypes.c_void_p), ("X", ctypes.c_void_p), ("U", ctypes.c_void_p), ("F", ctypes.c_void_p)]
 
 
+class Env(ctypes.Structure):
+    _fields_ = [("ctx", ctypes.c_void_p), ("m", Markers), ("poses", ctypes.c_void_p), ("frames", ctypes.c_void_p),
+                ("wrench", ctypes.c_void_p), ("rotating", ctypes.c_int32)]
+
+
+BATCH_PHASES, BATCH_PERSISTENT = 0, 1
+BATCH_SHAPES = ((64, 8), (128, 4), (256, 2), (512, 1))
+
+
 class LBMError(RuntimeError):
     def __init__(self, code: int, what: str = ""):
         self.code = code
@@ -75,6 +84,15 @@ def lib():
         L.lbm_set_stream.argtypes = [vp, vp]
         L.lbm_profile_enable.argtypes = [vp, ctypes.c_int]
         L.lbm_profile_collect.argtypes = [vp, vp, vp, vp]
+        L.lbm_batch_bytes.argtypes = [ctypes.c_int32]
+        L.lbm_batch_bytes.restype = sz
+        L.lbm_batch_create.argtypes = [ctypes.POINTER(vp), vp, ctypes.c_int32, vp, vp]
+        L.lbm_batch_run.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+        L.lbm_batch_autotune.argtypes = [vp, ctypes.c_int32, vp]
+        L.lbm_batch_set_shapes.argtypes = [vp, vp]
+        L.lbm_batch_check.argtypes = [vp]
+        L.lbm_batch_destroy.argtypes = [vp]
+        L.lbm_batch_destroy.restype = None
         L.lbm_step_count.argtypes = [vp]
         L.lbm_step_count.restype = ctypes.c_int64
         L.lbm_strerror.argtypes = [ctypes.c_int]
@@ -83,7 +101,8 @@ def lib():
         L.lbm_destroy.restype = None
         for name in ("lbm_init", "lbm_load_populations", "lbm_read_populations", "lbm_macros", "lbm_ib_step",
                      "lbm_body_forces", "lbm_check", "lbm_set_stream", "lbm_profile_enable",
-                     "lbm_profile_collect"):
+                     "lbm_profile_collect", "lbm_batch_create", "lbm_batch_run", "lbm_batch_autotune",
+                     "lbm_batch_set_shapes", "lbm_batch_check"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -247,6 +266,92 @@ class Simulation:
         if getattr(self, "ctx", None):
             lib().lbm_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many workloads (inputs.Workload, each with markers) advanced together
+    by the batched kernels; every environment owns a Simulation. Per-step
+    poses, frames and wrenches live on the device for `nsteps` steps of a run
+    (a run re-reads them from step 0)."""
+
+    def __init__(self, workloads, nsteps, block=(128, 4), max_active_tiles=1024, device="cuda", keep_wrench=True):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the lattice Boltzmann library runs only on the GPU")
+        L = lib()
+        self.device = torch.device(device)
+        self.nsteps = int(nsteps)
+        self.stream = torch.cuda.Stream(self.device)  # default priority
+        self.sims, self.markers, self.poses, self.frames, self.wrench = [], [], [], [], []
+        envs = (Env * len(workloads))()
+        with torch.cuda.stream(self.stream):
+            for j, w in enumerate(workloads):
+                ntiles = ((w.nx + 7) // 8) * ((w.ny + 7) // 8) * ((w.nz + 7) // 8)
+                sim = Simulation(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi, max_markers=w.markers.n,
+                                 max_bones=w.markers.nbones, mdf_iters=w.mdf_iters, ib_alpha=w.ib_alpha,
+                                 u0=w.u0.astype(np.float32), device=self.device, block=block,
+                                 max_active_tiles=min(ntiles, max_active_tiles), stream=self.stream)
+                dm = DeviceMarkers(w.markers, self.device)
+                poses = torch.as_tensor(np.ascontiguousarray(w.poses[:self.nsteps], np.float32), device=self.device)
+                frames = torch.as_tensor(np.ascontiguousarray(w.frames[:self.nsteps], np.float64), device=self.device)
+                wr = torch.zeros((self.nsteps, 8), dtype=torch.float32, device=self.device) if keep_wrench else None
+                rot = bool(np.any(w.frames[:self.nsteps, 3:9] != 0.0))
+                envs[j] = Env(sim.ctx.value, dm.struct(), poses.data_ptr(), frames.data_ptr(),
+                              None if wr is None else wr.data_ptr(), 1 if rot else 0)
+                self.sims.append(sim)
+                self.markers.append(dm)
+                self.poses.append(poses)
+                self.frames.append(frames)
+                self.wrench.append(wr)
+            nb = L.lbm_batch_bytes(len(workloads))
+            if nb == 0:
+                raise LBMError(-1, "batch size")
+            self._dev_raw = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+            shift = (-self._dev_raw.data_ptr()) % 256
+            self._dev = self._dev_raw[shift:shift + nb]
+            b = ctypes.c_void_p()
+            _check(L.lbm_batch_create(ctypes.byref(b), envs, len(workloads), _ptr(self._dev),
+                                      ctypes.c_void_p(self.stream.cuda_stream)), "lbm_batch_create")
+        self.batch = b
+        self._envs = envs
+
+    @property
+    def ncell(self) -> int:
+        return sum(s.ncell for s in self.sims)
+
+    def run(self, nsteps=None, mode="persistent", graph=True):
+        n = self.nsteps if nsteps is None else int(nsteps)
+        assert n <= self.nsteps
+        m = BATCH_PERSISTENT if mode == "persistent" else BATCH_PHASES
+        _check(lib().lbm_batch_run(self.batch, n, m, 1 if graph else 0), "lbm_batch_run")
+
+    def autotune(self, reps=5):
+        shapes = np.zeros((len(self.sims), 2), dtype=np.int32)
+        _check(lib().lbm_batch_autotune(self.batch, int(reps), shapes.ctypes.data_as(ctypes.c_void_p)),
+               "lbm_batch_autotune")
+        return shapes
+
+    def set_shapes(self, shapes):
+        a = np.ascontiguousarray(shapes, dtype=np.int32).reshape(len(self.sims), 2)
+        _check(lib().lbm_batch_set_shapes(self.batch, a.ctypes.data_as(ctypes.c_void_p)), "lbm_batch_set_shapes")
+
+    def check(self) -> int:
+        return lib().lbm_batch_check(self.batch)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def close(self):
+        if getattr(self, "batch", None):
+            lib().lbm_batch_destroy(self.batch)
+            self.batch = None
+        for s in getattr(self, "sims", []):
+            s.close()
 
     def __del__(self):
         try:

@@ -1,0 +1,115 @@
+"""Batched environments: the batched kernels (per-phase and persistent,
+eager and graph-replayed, any autotuned tile shape) reproduce each
+environment run alone through the single-lattice path, and one environment
+matches the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2206_01683_amd import inputs as I
+from paper_2206_01683_amd import lbm
+from gpu_helpers import gpu_run, interior, oracle_run, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+NSTEPS = 20
+
+
+def _envs(count=3, seed=4):
+    return I.batch_workloads(count=count, seed=seed, nsteps=NSTEPS)
+
+
+def _read_all(batch):
+    out = []
+    with torch.cuda.stream(batch.stream):
+        for sim in batch.sims:
+            out.append(sim.read_populations())
+    batch.synchronize()
+    return [o.cpu().numpy() for o in out]
+
+
+def _alone(w, nsteps):
+    """The same environment through the single-lattice path (block 128x4)."""
+    sim = lbm.Simulation(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi, max_markers=w.markers.n,
+                         max_bones=w.markers.nbones, u0=w.u0.astype(np.float32), block=(128, 4),
+                         max_active_tiles=1024)
+    dm = lbm.DeviceMarkers(w.markers)
+    poses = torch.as_tensor(w.poses[:nsteps].astype(np.float32), device="cuda")
+    wr = torch.zeros((nsteps, 8), device="cuda")
+    sim.step(w.frames[:nsteps], dm, poses, wr)
+    torch.cuda.synchronize()
+    return sim.read_populations().cpu().numpy(), wr.cpu().numpy()
+
+
+@pytest.mark.parametrize("mode,graph", [("phases", False), ("persistent", False), ("phases", True),
+                                        ("persistent", True)])
+def test_batch_matches_environments_run_alone(mode, graph):
+    envs = _envs()
+    say("envs:", [(w.nx, w.ny, w.nz, w.markers.n) for w in envs])
+    b = lbm.Batch(envs, NSTEPS)
+    b.run(NSTEPS, mode=mode, graph=graph)
+    assert b.check() == 0
+    got = _read_all(b)
+    for j, w in enumerate(envs):
+        want, wr = _alone(w, NSTEPS)
+        d = np.abs(got[j] - want).max()
+        say(f"{mode} graph={graph} env {j} ({w.nx}x{w.ny}x{w.nz}): max |df| vs alone = {d:.3e}")
+        assert d == 0.0
+        np.testing.assert_array_equal(b.wrench[j].cpu().numpy(), wr)
+
+
+def test_graph_replays_match_eager_steps():
+    envs = _envs(count=2, seed=7)
+    a = lbm.Batch(envs, NSTEPS)
+    for _ in range(3):  # three replays of one captured graph, eager work in between
+        a.run(NSTEPS, mode="persistent", graph=True)
+        a.synchronize()
+        torch.cuda.synchronize()
+    e = lbm.Batch(envs, NSTEPS)
+    for _ in range(3):
+        e.run(NSTEPS, mode="phases", graph=False)
+    ga, ge = _read_all(a), _read_all(e)
+    for x, y in zip(ga, ge):
+        assert np.array_equal(x, y)
+    assert a.check() == 0 and e.check() == 0
+
+
+def test_autotuned_shapes_are_valid_and_do_not_change_results():
+    envs = _envs(count=3, seed=11)
+    b = lbm.Batch(envs, NSTEPS)
+    shapes = b.autotune(reps=3)
+    say("autotuned shapes:", shapes.tolist())
+    for bx, by in shapes:
+        assert (int(bx), int(by)) in lbm.BATCH_SHAPES
+    b.run(NSTEPS, mode="persistent", graph=True)
+    ref = lbm.Batch(envs, NSTEPS)
+    ref.set_shapes(np.tile(np.array([[64, 8]], np.int32), (3, 1)))
+    ref.run(NSTEPS, mode="phases", graph=False)
+    for x, y in zip(_read_all(b), _read_all(ref)):
+        assert np.array_equal(x, y)
+
+
+def test_invalid_shapes_rejected():
+    b = lbm.Batch(_envs(count=1), NSTEPS)
+    with pytest.raises(lbm.LBMError):
+        b.set_shapes(np.array([[96, 4]], np.int32))
+    with pytest.raises(lbm.LBMError):
+        b.set_shapes(np.array([[128, 2]], np.int32))
+
+
+def test_batched_environment_against_oracle():
+    w = _envs(count=1, seed=4)[0]
+    b = lbm.Batch([w], NSTEPS)
+    b.run(NSTEPS, mode="persistent", graph=False)
+    assert b.check() == 0
+    with torch.cuda.stream(b.stream):
+        _, u = b.sims[0].macros(w.frames[NSTEPS - 1])
+    b.synchronize()
+    ref = oracle_run(w, nsteps=NSTEPS)
+    _, u_ref = oracle.macros(ref["prm"], ref["f"], w.frames[NSTEPS - 1])
+    e = rel_l2(interior(u.cpu().numpy().astype(np.float64), w), interior(u_ref, w))
+    wr = b.wrench[0].cpu().numpy()
+    derr = np.abs(wr[:, 0] - ref["wrench"][:, 0]).max() / np.abs(ref["wrench"][:, 0]).max()
+    say(f"batched env {w.nx}x{w.ny}x{w.nz}, {w.markers.n} markers: velocity rel L2 {e:.3e}, force-x max rel {derr:.3e}")
+    assert e <= 1e-5 and derr <= 1e-4
