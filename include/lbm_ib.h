@@ -79,6 +79,7 @@ typedef struct {
   int32_t mdf_iters;         /* direct-forcing passes, >= 1 (1 = explicit) */
   int32_t max_active_tiles;  /* 8x8x8 tiles that may carry IB force; 0 = automatic */
   int32_t block_x, block_y;  /* collide kernel block shape; 0 = default */
+  int32_t with_adjoint;      /* nonzero: workspace also holds the adjoint buffers */
   double tau;                /* BGK relaxation time, > 1/2 (nu = (tau - 1/2)/3) */
   double ib_alpha;           /* direct-forcing gain, > 0 (1 = full correction) */
 } lbm_params;
@@ -159,6 +160,40 @@ lbm_status lbm_macros(lbm_ctx *c, const lbm_frame *frame, float *rho, float *u);
  * device and reported by lbm_check. */
 lbm_status lbm_ib_step(lbm_ctx *c, const lbm_markers *m, const float *poses, const lbm_frame *frames,
                        int32_t nsteps, float *wrench);
+
+/* Copy the current population state (the library's stored layout,
+ * lbm_population_bytes) to dst, or replace it with src (device buffers).
+ * Used for checkpoints. restore resets the step counter to step. */
+lbm_status lbm_state_save(lbm_ctx *c, void *dst);
+lbm_status lbm_state_restore(lbm_ctx *c, const void *src, int64_t step);
+
+/* Rebind the two population buffers: the next step reads f_cur and writes
+ * f_next, the step after that reads f_next and writes f_cur, and so on (the
+ * roles lbm_init gives f_a and f_b). Both are caller-owned, distinct, of
+ * lbm_population_bytes, in the stored layout; nothing is copied and the step
+ * count is unchanged. This lets a reverse sweep recompute a segment of steps
+ * straight into a ring of saved states (state n is the buffer step n reads),
+ * with no copies. A context whose buffers are rebound must not belong to a
+ * live batch (the batch keeps the pointers it was created with). */
+lbm_status lbm_bind_populations(lbm_ctx *c, void *f_cur, void *f_next);
+
+/* Discrete adjoint of one step: the exact reverse mode of the float32
+ * arithmetic of lbm_ib_step for the step that starts from `state` (stored
+ * layout) with markers m, bone poses `pose` ([m->nbones][24]) and `frame`
+ * [host]. The step's own objective term is
+ *   J_n = w[0..2] . (fluid force on the body) + w[3] * (power),
+ * w [host] 4 doubles, as reported in the step's wrench. Given
+ * lam_next = dJ/d(state after the step) it writes lam_prev = dJ/d(state
+ * before the step) (both stored layout, F32) and adds the step's
+ * dJ/d(bone pose) into pose_bar [m->nbones][24] (same layout as a pose).
+ * Supported: F32 storage, mdf_iters = 1, omega = alpha = 0, with_adjoint set
+ * (else LBM_ERR_UNSUPPORTED). The context's own state is left unchanged; m's
+ * X, U, F are overwritten with the step's values. This is the differentiation
+ * form: gradients of time-averaged thrust and power with respect to body
+ * kinematics, through skinning (Sec. III-A) and the coupled step (Sec. III-B). */
+lbm_status lbm_adjoint_step(lbm_ctx *c, const void *state, const lbm_markers *m, const float *pose,
+                            const lbm_frame *frame, const double *w, const void *lam_next, void *lam_prev,
+                            float *pose_bar);
 
 /* Fluid force on the body from the markers' last forces F (the external
  * generalized force of Eq. (1)). out [(1 + m->nbones)][8]: row 0 is the whole

@@ -1,0 +1,573 @@
+// Discrete adjoint of one immersed-boundary lattice Boltzmann step (reverse
+// mode of exactly the arithmetic of the forward step, float32 storage,
+// explicit direct forcing, non-rotating frame).
+//
+// Forward step n (state A = post-collision populations of step n-1):
+//   f = pull(A); rho, m per node; u* = m/rho + a0/2 (a0 = -frame acceleration)
+//   markers: X, U from the pose; rho_k = sum W rho, U*_k = sum W u*,
+//   F_k = 2 alpha rho_k (U_k - U*_k), g = sum_k W F_k dV_k  (W = Peskin weights)
+//   interior: u = (m + g/2)/rho + a0/2, F = g + rho a0,
+//             f*_i = (1-1/tau) f_i + f^eq_i(rho,u)/tau + S_i(u, F)
+//   open faces: f*_i(x_b) = f^eq_i(rho_f,u_b) + (1-1/tau)(f_i(x_f) - f^eq_i(rho_f,u_f)) + S_i(u_b, rho_f a0)
+//   A' = f*; per-step objective J_n = wF . F_body + wP P with F_body = -sum F_k dV_k,
+//   P = sum F_k . U_k dV_k.
+// Given lam' = dJ/dA' this computes lam = dJ/dA (for the part of J from step
+// n on) and the step's dJ/d(bone pose). Passes, with the forward IB data of
+// step n recomputed beforehand (skin, tiles, band macros, interpolation,
+// spreading):
+//   1 k_adj_gbar      gbar = dJ/dg on active-tile cells (collide + face adjoint)
+//   2 k_adj_markers   per marker: Fbar, rhobar_k, U*bar_k, Ubar_k, Xbar_k
+//                     (Xbar includes the derivative of the Peskin weights)
+//   3 k_adj_spread    spread (rhobar_k, U*bar_k) onto the band in 64-bit fixed
+//                     point (order-independent)
+//   4 k_adj_collide   every cell: fbar from the collide adjoint and the band
+//                     IB terms, push-streamed into lam (324 B per cell);
+//                     k_adj_face adds the open faces' extrapolation adjoint
+//   5 k_adj_pose      per bone: dJ/dR, dJ/dt, dJ/dRdot, dJ/dtdot
+#pragma once
+
+#include "ib.hpp"
+
+namespace lbmib {
+
+struct AdjArgs {
+  float wF[3];                        // objective weight on the fluid force on the body
+  float wP;                           // objective weight on the power
+  float a0[3];                        // frame acceleration term a0 = -acc (uniform: no rotation)
+  const float *__restrict__ lam_next;  // [27][plane]
+  float *__restrict__ lam_prev;        // [27][plane]
+  float *__restrict__ gbar;            // [cap][3][512]
+  unsigned long long *__restrict__ adjfix;  // [cap][4][512]: spread rhobar, U*bar (fixed point)
+  float *__restrict__ mbar;            // [6][n]: Xbar (3), Ubar (3)
+  float bc_u_lo[3], bc_u_hi[3];        // face velocities
+};
+
+// d phi / d r of Peskin's 4-point kernel
+__device__ inline float peskin4_d(float r) {
+  const float a = fabsf(r);
+  float d = 0.f;
+  if (a <= 1.0f) {
+    const float s = __builtin_sqrtf(fmaxf(1.0f + 4.0f * a - 4.0f * a * a, 1e-30f));
+    d = 0.125f * (-2.0f + (2.0f - 4.0f * a) / s);
+  } else if (a <= 2.0f) {
+    const float s = __builtin_sqrtf(fmaxf(-7.0f + 12.0f * a - 4.0f * a * a, 1e-30f));
+    d = 0.125f * (-2.0f - (6.0f - 4.0f * a) / s);
+  }
+  return r < 0.f ? -d : d;
+}
+
+// Moments of lam weighted with w_i, used by the BGK + Guo adjoints:
+// S0 = sum l w, S1 = sum l w c, S2 = sum l w (c.u) c, Scu = sum l w (c.u),
+// Scu2 = sum l w (c.u)^2, SF = sum l w (c.F) c.
+struct LamSums {
+  float S0, S1[3], S2[3], Scu, Scu2, SF[3];
+};
+
+__device__ inline LamSums lam_sums(const float lam[Q], float ux, float uy, float uz, float Fx, float Fy, float Fz) {
+  LamSums s{};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float lw = lam[i] * w_of(i);
+    const float cu = cdot(i, ux, uy, uz), cF = cdot(i, Fx, Fy, Fz);
+    const int c[3] = {cx_of(i), cy_of(i), cz_of(i)};
+    s.S0 += lw;
+    s.Scu += lw * cu;
+    s.Scu2 += lw * cu * cu;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (c[a] != 0) {
+        const float sg = (float)c[a];
+        s.S1[a] += sg * lw;
+        s.S2[a] += sg * lw * cu;
+        s.SF[a] += sg * lw * cF;
+      }
+    }
+  }
+  return s;
+}
+
+// Adjoint of the interior BGK + Guo collision at one node with pre-collision
+// f (moments rho, m), force g and lam = dJ/df*. Returns rhobar, mbar (the
+// parts that reach f through rho and m: fbar_j += rhobar + c_j . mbar) and
+// gbar; the direct part (1 - 1/tau) lam_j is added by the caller.
+__device__ inline void adj_collide_node(const float lam[Q], float rho, const float m[3], const float g[3],
+                                       const AdjArgs &A, float inv_tau, float pref, float &rhobar, float mbar[3],
+                                       float gbar[3]) {
+  const float ir = 1.0f / rho;
+  float u[3], F[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    u[a] = m[a] * ir + 0.5f * (g[a] * ir + A.a0[a]);
+    F[a] = g[a] + rho * A.a0[a];
+  }
+  const float u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  const LamSums s = lam_sums(lam, u[0], u[1], u[2], F[0], F[1], F[2]);
+  rhobar = inv_tau * (s.S0 * (1.0f - 1.5f * u2) + 3.0f * s.Scu + 4.5f * s.Scu2);
+  float ub[3], Fb[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    ub[a] = inv_tau * rho * (3.0f * s.S1[a] + 9.0f * s.S2[a] - 3.0f * u[a] * s.S0) +
+            pref * (-3.0f * F[a] * s.S0 + 9.0f * s.SF[a]);
+    Fb[a] = pref * (3.0f * s.S1[a] - 3.0f * u[a] * s.S0 + 9.0f * s.S2[a]);
+  }
+  float q = 0.f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    gbar[a] = Fb[a] + 0.5f * ir * ub[a];
+    rhobar += Fb[a] * A.a0[a];
+    q += ub[a] * (m[a] + 0.5f * g[a]);
+    mbar[a] = ub[a] * ir;
+  }
+  rhobar -= q * ir * ir;
+}
+
+// Adjoint of a face node's extrapolation, seen from its inward neighbour x_f
+// (moments rho, m, force g at x_f): lam_b = dJ/df*(x_b). Returns the parts of
+// fbar(x_f): direct (1 - 1/tau) lam_b is added by the caller, plus rhobar,
+// mbar, and gbar(x_f).
+__device__ inline void adj_face(const float lamb[Q], float rho, const float m[3], const float g[3],
+                                const float ubc[3], bool velocity_face, const AdjArgs &A, float omt, float pref,
+                                float &rhobar, float mbar[3], float gbar[3]) {
+  const float ir = 1.0f / rho;
+  float uf[3], ub[3], Fbd[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    uf[a] = m[a] * ir + 0.5f * (g[a] * ir + A.a0[a]);
+    ub[a] = velocity_face ? ubc[a] : uf[a];
+    Fbd[a] = rho * A.a0[a];
+  }
+  const float ub2 = ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2];
+  const float uf2 = uf[0] * uf[0] + uf[1] * uf[1] + uf[2] * uf[2];
+  const LamSums sb = lam_sums(lamb, ub[0], ub[1], ub[2], Fbd[0], Fbd[1], Fbd[2]);
+  const LamSums sf = lam_sums(lamb, uf[0], uf[1], uf[2], 0.f, 0.f, 0.f);
+  rhobar = (sb.S0 * (1.0f - 1.5f * ub2) + 3.0f * sb.Scu + 4.5f * sb.Scu2) -
+           omt * (sf.S0 * (1.0f - 1.5f * uf2) + 3.0f * sf.Scu + 4.5f * sf.Scu2);
+  float ubb[3], ufb[3], Fbb[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    Fbb[a] = pref * (3.0f * sb.S1[a] - 3.0f * ub[a] * sb.S0 + 9.0f * sb.S2[a]);
+    ubb[a] = rho * (3.0f * sb.S1[a] + 9.0f * sb.S2[a] - 3.0f * ub[a] * sb.S0) +
+             pref * (-3.0f * Fbd[a] * sb.S0 + 9.0f * sb.SF[a]);
+    ufb[a] = -omt * rho * (3.0f * sf.S1[a] + 9.0f * sf.S2[a] - 3.0f * uf[a] * sf.S0);
+    if (!velocity_face) ufb[a] += ubb[a];
+    rhobar += Fbb[a] * A.a0[a];
+  }
+  float q = 0.f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    mbar[a] = ufb[a] * ir;
+    gbar[a] = 0.5f * ir * ufb[a];
+    q += ufb[a] * (m[a] + 0.5f * g[a]);
+  }
+  rhobar -= q * ir * ir;
+}
+
+__device__ inline void load_lam(const float *__restrict__ lam, uint32_t plane, uint32_t o, float l[Q]) {
+#pragma unroll
+  for (int i = 0; i < Q; ++i) l[i] = lam[(uint32_t)i * plane + o];
+}
+
+// ------------------------------------------------------------------ pass 1 --
+// gbar on the cells of active tile `slot` (state A in e.f[0]); clears the
+// tile's fixed-point IB adjoint accumulator.
+__device__ inline void adj_gbar_item(const EnvView &e, const AdjArgs &A, int slot, int tid) {
+  const GridArgs &g = e.g;
+  const float *__restrict__ src = static_cast<const float *>(e.f[0]);
+  const int t = e.active[slot];
+  const int tx = t % g.tnx, ty = (t / g.tnx) % g.tny, tz = t / (g.tnx * g.tny);
+  const int x = tx * 8 + (tid & 7), y = ty * 8 + ((tid >> 3) & 7), z = tz * 8 + (tid >> 6);
+  float gb[3] = {0.f, 0.f, 0.f};
+  if (x < g.nx && y < g.ny && z < g.nz && (g.xper || (x > 0 && x < g.nx - 1))) {
+    const int xm = g.xper ? wrap_idx(x - 1, g.nx) : x - 1;
+    const int xp = g.xper ? wrap_idx(x + 1, g.nx) : x + 1;
+    float f[Q];
+    pull27<StoreF32>(src, g.plane, g.nx, g.ny, xm, x, xp, wrap_idx(y - 1, g.ny), y, wrap_idx(y + 1, g.ny),
+                     wrap_idx(z - 1, g.nz), z, wrap_idx(z + 1, g.nz), f);
+    float rho, m[3];
+    moments(f, rho, m[0], m[1], m[2]);
+    float gg[3];
+    load_g(g, e.tile_slot, e.gfix, x, y, z, gg[0], gg[1], gg[2]);
+    const uint32_t o = ((uint32_t)z * g.ny + y) * g.nx + x;
+    float lam[Q];
+    load_lam(A.lam_next, g.plane, o, lam);
+    float rb, mb[3];
+    adj_collide_node(lam, rho, m, gg, A, e.inv_tau, e.pref, rb, mb, gb);
+    if (!g.xper && (x == 1 || x == g.nx - 2)) {
+      const bool lo = x == 1;
+      const uint32_t ob = ((uint32_t)z * g.ny + y) * g.nx + (lo ? 0 : g.nx - 1);
+      load_lam(A.lam_next, g.plane, ob, lam);
+      float rb2, mb2[3], gb2[3];
+      adj_face(lam, rho, m, gg, lo ? A.bc_u_lo : A.bc_u_hi, (lo ? g.bc_lo : g.bc_hi) == 1, A, e.omt, e.pref, rb2,
+               mb2, gb2);
+      for (int a = 0; a < 3; ++a) gb[a] += gb2[a];
+    }
+  }
+  float *gp = A.gbar + (size_t)slot * 1536;
+  gp[tid] = gb[0];
+  gp[512 + tid] = gb[1];
+  gp[1024 + tid] = gb[2];
+  unsigned long long *ap = A.adjfix + (size_t)slot * 2048;
+  for (int q = 0; q < 4; ++q) ap[q * 512 + tid] = 0ull;
+}
+
+// ------------------------------------------------------------------ pass 2 --
+// Markers 8*item .. 8*item+7, one wave64 each, lane = stencil node. The
+// forward quantities of the step (X, U, F, rho_k, U*_k, band macros) are
+// those of the recomputed forward IB phases.
+__device__ inline void adj_marker_item(const EnvView &e, const AdjArgs &A, int item, int tid) {
+  const int lane = tid & 63, wv = tid >> 6;
+  const int k = item * kInterpPer + wv;
+  const int n = e.n;
+  if (k >= n) return;
+  const GridArgs &g = e.g;
+  const float Xk[3] = {e.X[k], e.X[n + k], e.X[2 * n + k]};
+  const int s3[3] = {lane & 3, (lane >> 2) & 3, lane >> 4};
+  const int dims[3] = {g.nx, g.ny, g.nz};
+  int base[3], node[3];
+  float w[3], dw[3];
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    base[ax] = stencil_base(Xk[ax]);
+    const int j = base[ax] + s3[ax];
+    w[ax] = peskin4(Xk[ax] - (float)j);
+    dw[ax] = peskin4_d(Xk[ax] - (float)j);  // d/dX of phi(X - j)
+    node[ax] = (ax > 0 || g.xper) ? wrap_idx(j, dims[ax]) : j;
+  }
+  const int t = (node[0] >> 3) + g.tnx * ((node[1] >> 3) + g.tny * (node[2] >> 3));
+  const int s = e.tile_slot[t];
+  float gb[3] = {0.f, 0.f, 0.f}, mac[4] = {1.f, 0.f, 0.f, 0.f};
+  if (s >= 0) {
+    const int lc = (node[0] & 7) | ((node[1] & 7) << 3) | ((node[2] & 7) << 6);
+    const float *gp = A.gbar + (size_t)s * 1536;
+    gb[0] = gp[lc];
+    gb[1] = gp[512 + lc];
+    gb[2] = gp[1024 + lc];
+    const float4 mm = e.macro[(size_t)s * 512 + lc];
+    mac[0] = mm.x;
+    mac[1] = mm.y;
+    mac[2] = mm.z;
+    mac[3] = mm.w;
+  }
+  const float W = w[0] * w[1] * w[2];
+  float G[3];
+  for (int a = 0; a < 3; ++a) G[a] = wave_sum(W * gb[a]);
+  const float dvk = e.dv[k], rk = e.mstate[k];
+  float Fk[3], Uk[3], Us[3], Fb[3], Usb[3], Ub[3];
+  float rkb = 0.f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    Fk[a] = e.F[a * n + k];
+    Uk[a] = e.U[a * n + k];
+    Us[a] = e.mstate[(a + 1) * (size_t)n + k];
+    Fb[a] = dvk * (G[a] - A.wF[a] + A.wP * Uk[a]);
+    rkb += e.alpha2 * Fb[a] * (Uk[a] - Us[a]);
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    Usb[a] = -e.alpha2 * rk * Fb[a];
+    Ub[a] = e.alpha2 * rk * Fb[a] + A.wP * Fk[a] * dvk;
+  }
+  // Xbar: sum over nodes of grad_X W times d(consumers of W)/dW
+  const float c = dvk * (Fk[0] * gb[0] + Fk[1] * gb[1] + Fk[2] * gb[2]) + mac[0] * rkb +
+                  mac[1] * Usb[0] + mac[2] * Usb[1] + mac[3] * Usb[2];
+  const float gX = wave_sum(dw[0] * w[1] * w[2] * c);
+  const float gY = wave_sum(w[0] * dw[1] * w[2] * c);
+  const float gZ = wave_sum(w[0] * w[1] * dw[2] * c);
+  float *r = e.rec + (size_t)k * REC;
+  if (lane < 4) r[lane] = w[0];
+  if ((lane & 3) == 0 && lane < 16) r[4 + (lane >> 2)] = w[1];
+  if ((lane & 15) == 0) r[8 + (lane >> 4)] = w[2];
+  if (lane == 0) {
+    r[12] = __int_as_float(base[0]);
+    r[13] = __int_as_float(base[1]);
+    r[14] = __int_as_float(base[2]);
+    r[15] = rkb;
+    r[16] = Usb[0];
+    r[17] = Usb[1];
+    r[18] = Usb[2];
+    A.mbar[k] = gX;
+    A.mbar[n + k] = gY;
+    A.mbar[2 * n + k] = gZ;
+    A.mbar[3 * n + k] = Ub[0];
+    A.mbar[4 * n + k] = Ub[1];
+    A.mbar[5 * n + k] = Ub[2];
+  }
+}
+
+// ------------------------------------------------------------------ pass 3 --
+// Spreading of (rhobar_k, U*bar_k) onto active tile (slot, part), as
+// spread_item but with four components from record slots 15..18.
+__device__ inline void adj_spread_item(const EnvView &e, const AdjArgs &A, int item, int tid) {
+  __shared__ unsigned long long s_acc[4][512];
+  const int lane = tid & 63, wv = tid >> 6;
+  const GridArgs &g = e.g;
+  const int n = e.n;
+  const int nchunks = (n + 63) >> 6;
+  const int slot = item / kSpreadSplit, part = item % kSpreadSplit;
+  const int t = e.active[slot];
+  const int tx = t % g.tnx, ty = (t / g.tnx) % g.tny, tz = t / (g.tnx * g.tny);
+  for (int q = tid; q < 4 * 512; q += WG) (&s_acc[0][0])[q] = 0ull;
+  __syncthreads();
+  const int stride = (WG / 64) * kSpreadSplit;
+  const int c_first = part * (WG / 64) + wv;
+  for (int it = 0; c_first + stride * 64 * it < nchunks; ++it) {
+    const int cl = c_first + stride * (lane + 64 * it);
+    bool pass = false;
+    if (cl < nchunks) {
+      const int4 box = e.chunk_box[cl];
+      pass = box_hits(box.x, tx) && box_hits(box.y, ty) && box_hits(box.z, tz);
+    }
+    unsigned long long cbal = __ballot(pass);
+    while (cbal) {
+      const int jc = __ffsll((long long)cbal) - 1;
+      cbal &= cbal - 1ull;
+      const int k = (c_first + stride * (jc + 64 * it)) * 64 + lane;
+      bool hit = false;
+      if (k < n) {
+        const short4 b = e.mbase[k];
+        hit = axis_touches(b.x, g.nx, g.xper, tx) && axis_touches(b.y, g.ny, true, ty) &&
+              axis_touches(b.z, g.nz, true, tz);
+      }
+      if (hit) {
+        float r[20];
+        const float4 *rp = reinterpret_cast<const float4 *>(e.rec + (size_t)k * REC);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+          const float4 v = rp[q];
+          r[4 * q] = v.x;
+          r[4 * q + 1] = v.y;
+          r[4 * q + 2] = v.z;
+          r[4 * q + 3] = v.w;
+        }
+        const int bx = __float_as_int(r[12]), by = __float_as_int(r[13]), bz = __float_as_int(r[14]);
+        int lx[4], ly[4], lz[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          int jx = bx + q, jy = wrap_idx(by + q, g.ny), jz = wrap_idx(bz + q, g.nz);
+          if (g.xper) jx = wrap_idx(jx, g.nx);
+          lx[q] = (jx >> 3) == tx ? (jx & 7) : -1;
+          ly[q] = (jy >> 3) == ty ? ((jy & 7) << 3) : -1;
+          lz[q] = (jz >> 3) == tz ? ((jz & 7) << 6) : -1;
+        }
+#pragma unroll
+        for (int qz = 0; qz < 4; ++qz) {
+          if (lz[qz] < 0) continue;
+#pragma unroll
+          for (int qy = 0; qy < 4; ++qy) {
+            if (ly[qy] < 0) continue;
+            const float wyz = r[4 + qy] * r[8 + qz];
+#pragma unroll
+            for (int qx = 0; qx < 4; ++qx) {
+              if (lx[qx] < 0) continue;
+              const float d = r[qx] * wyz;
+              const int lc = lx[qx] | ly[qy] | lz[qz];
+#pragma unroll
+              for (int cc = 0; cc < 4; ++cc) atomicAdd(&s_acc[cc][lc], to_fix(r[15 + cc] * d));
+            }
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  unsigned long long *ap = A.adjfix + (size_t)slot * 2048;
+  for (int q = tid; q < 4 * 512; q += WG) {
+    const unsigned long long v = (&s_acc[0][0])[q];
+    if (v != 0ull) atomicAdd(&ap[q], v);
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ pass 4 --
+// Every cell: fbar = (1 - 1/tau) lam + collide adjoint + the band IB terms,
+// then push-streamed: lam_prev_i(x - c_i) = fbar_i(x). Open-face nodes have
+// fbar = 0 and also clear the entries no node streams into (c_x pointing out
+// of the domain). The face extrapolation's share of fbar(x_f) is added
+// afterwards by k_adj_face.
+template <bool XPER>
+__device__ inline void adj_collide_cell(const EnvView &e, const AdjArgs &A, int lb, int tx, int ty) {
+  const GridArgs &g = e.g;
+  const float *__restrict__ src = static_cast<const float *>(e.f[0]);
+  const int bxi = lb % e.gx;
+  const int rest = lb / e.gx;
+  const int byi = rest % e.gy;
+  const int z = rest / e.gy;
+  const int x = bxi * e.bx + tx;
+  const int y = byi * e.by + ty;
+  if (x >= g.nx || y >= g.ny) return;
+  const int ym = y == 0 ? g.ny - 1 : y - 1;
+  const int yp = y == g.ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? g.nz - 1 : z - 1;
+  const int zp = z == g.nz - 1 ? 0 : z + 1;
+  const uint32_t o = ((uint32_t)z * g.ny + y) * g.nx + x;
+  float fb[Q];
+  const bool face = !XPER && (x == 0 || x == g.nx - 1);
+  if (face) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) fb[i] = 0.f;
+  } else {
+    int xm, xp;
+    if (XPER) {
+      xm = x == 0 ? g.nx - 1 : x - 1;
+      xp = x == g.nx - 1 ? 0 : x + 1;
+    } else {
+      xm = x - 1;
+      xp = x + 1;
+    }
+    float f[Q];
+    pull27<StoreF32>(src, g.plane, g.nx, g.ny, xm, x, xp, ym, y, yp, zm, z, zp, f);
+    float rho, m[3];
+    moments(f, rho, m[0], m[1], m[2]);
+    float gg[3];
+    load_g(g, e.ib ? e.tile_slot : nullptr, e.gfix, x, y, z, gg[0], gg[1], gg[2]);
+    float lam[Q];
+    load_lam(A.lam_next, g.plane, o, lam);
+    float rb, mb[3], gb[3];
+    adj_collide_node(lam, rho, m, gg, A, e.inv_tau, e.pref, rb, mb, gb);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) fb[i] = e.omt * lam[i];
+    // immersed-boundary terms: rhobar, U*bar spread onto the band reach f
+    // through u* = m/rho + a0/2 and rho
+    if (e.ib) {
+      const int t = (x >> 3) + g.tnx * ((y >> 3) + g.tny * (z >> 3));
+      const int s = e.tile_slot[t];
+      if (s >= 0) {
+        const int lc = (x & 7) | ((y & 7) << 3) | ((z & 7) << 6);
+        const unsigned long long *ap = A.adjfix + (size_t)s * 2048;
+        const float rib = from_fix(ap[lc]);
+        const float ub[3] = {from_fix(ap[512 + lc]), from_fix(ap[1024 + lc]), from_fix(ap[1536 + lc])};
+        const float ir = 1.0f / rho;
+        float q = 0.f;
+        for (int a = 0; a < 3; ++a) {
+          mb[a] += ub[a] * ir;
+          q += ub[a] * m[a];
+        }
+        rb += rib - q * ir * ir;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) fb[i] += rb + (float)cx_of(i) * mb[0] + (float)cy_of(i) * mb[1] + (float)cz_of(i) * mb[2];
+  }
+  // push: lam_prev_i(x - c_i) = fbar_i(x)
+  const int yy[3] = {yp, y, ym};  // indexed by c + 1: target y - c
+  const int zz[3] = {zp, z, zm};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    int tx_ = x - cx_of(i);
+    if (XPER) {
+      tx_ = tx_ < 0 ? tx_ + g.nx : (tx_ >= g.nx ? tx_ - g.nx : tx_);
+    } else if (tx_ < 0 || tx_ >= g.nx) {
+      continue;
+    }
+    const uint32_t ot = ((uint32_t)zz[cz_of(i) + 1] * g.ny + yy[cy_of(i) + 1]) * g.nx + tx_;
+    __builtin_nontemporal_store(fb[i], A.lam_prev + (uint32_t)i * g.plane + ot);
+  }
+  if (face) {
+    // entries of this face node pulled by no node: c_x pointing out of the domain
+    const int cxo = x == 0 ? -1 : 1;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      if (cx_of(i) == cxo) A.lam_prev[(uint32_t)i * g.plane + o] = 0.f;
+  }
+}
+
+// Face extrapolation adjoint, one thread per (y, z) of each open face
+// (blockIdx.y: 0 = x = 0 face, 1 = x = nx-1 face): adds its share of
+// fbar(x_f) into the entries x_f streamed into (each written by one thread).
+__global__ void __launch_bounds__(256) k_adj_face(EnvView e, AdjArgs A) {
+  const GridArgs &g = e.g;
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= g.ny * g.nz) return;
+  const int y = id % g.ny, z = id / g.ny;
+  const bool lo = blockIdx.y == 0;
+  const int x = lo ? 1 : g.nx - 2;
+  const float *__restrict__ src = static_cast<const float *>(e.f[0]);
+  const int ym = y == 0 ? g.ny - 1 : y - 1;
+  const int yp = y == g.ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? g.nz - 1 : z - 1;
+  const int zp = z == g.nz - 1 ? 0 : z + 1;
+  float f[Q];
+  pull27<StoreF32>(src, g.plane, g.nx, g.ny, x - 1, x, x + 1, ym, y, yp, zm, z, zp, f);
+  float rho, m[3];
+  moments(f, rho, m[0], m[1], m[2]);
+  float gg[3];
+  load_g(g, e.ib ? e.tile_slot : nullptr, e.gfix, x, y, z, gg[0], gg[1], gg[2]);
+  float lam[Q];
+  load_lam(A.lam_next, g.plane, ((uint32_t)z * g.ny + y) * g.nx + (lo ? 0 : g.nx - 1), lam);
+  float rb, mb[3], gb[3];
+  adj_face(lam, rho, m, gg, lo ? A.bc_u_lo : A.bc_u_hi, (lo ? g.bc_lo : g.bc_hi) == 1, A, e.omt, e.pref, rb, mb, gb);
+  const int yy[3] = {yp, y, ym};
+  const int zz[3] = {zp, z, zm};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float fb = e.omt * lam[i] + rb + (float)cx_of(i) * mb[0] + (float)cy_of(i) * mb[1] + (float)cz_of(i) * mb[2];
+    const uint32_t ot = ((uint32_t)zz[cz_of(i) + 1] * g.ny + yy[cy_of(i) + 1]) * g.nx + (x - cx_of(i));
+    A.lam_prev[(uint32_t)i * g.plane + ot] += fb;
+  }
+}
+
+template <bool XPER>
+__global__ void __launch_bounds__(512) k_adj_collide(EnvView e, AdjArgs A) {
+  const int b = blockIdx.x;
+  const int per = (e.nblocks + 7) >> 3;
+  const int lb = (b & 7) * per + (b >> 3);
+  if (lb >= e.nblocks) return;
+  adj_collide_cell<XPER>(e, A, lb, threadIdx.x, threadIdx.y);
+}
+
+__global__ void __launch_bounds__(WG) k_adj_gbar(EnvView e, AdjArgs A) {
+  const int na = n_active_of(e);
+  for (int slot = blockIdx.x; slot < na; slot += gridDim.x) adj_gbar_item(e, A, slot, threadIdx.x);
+}
+
+__global__ void __launch_bounds__(WG) k_adj_markers(EnvView e, AdjArgs A) {
+  adj_marker_item(e, A, blockIdx.x, threadIdx.x);
+}
+
+__global__ void __launch_bounds__(WG) k_adj_spread(EnvView e, AdjArgs A) {
+  const int items = n_active_of(e) * kSpreadSplit;
+  for (int item = blockIdx.x; item < items; item += gridDim.x) adj_spread_item(e, A, item, threadIdx.x);
+}
+
+// ------------------------------------------------------------------ pass 5 --
+// Pose adjoint of bone blockIdx.x for this step, added into pose_bar[b][24]:
+// X = sum_b w (R xrest + t), U = sum_b w (Rdot xrest + tdot).
+__global__ void __launch_bounds__(WG) k_adj_pose(EnvView e, AdjArgs A, float *__restrict__ pose_bar) {
+  __shared__ float s_red[WG / 64][24];
+  const int b = blockIdx.x;
+  const int n = e.n;
+  float acc[24];
+#pragma unroll
+  for (int q = 0; q < 24; ++q) acc[q] = 0.f;
+  for (int k = threadIdx.x; k < n; k += WG) {
+    const float wk = (e.bone[k] == b ? e.weight[k] : 0.f) + (e.bone[n + k] == b ? e.weight[n + k] : 0.f);
+    if (wk == 0.f) continue;
+    const float xr[3] = {e.xrest[k], e.xrest[n + k], e.xrest[2 * n + k]};
+    const float xb[3] = {A.mbar[k], A.mbar[n + k], A.mbar[2 * n + k]};
+    const float ub[3] = {A.mbar[3 * n + k], A.mbar[4 * n + k], A.mbar[5 * n + k]};
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        acc[3 * r + c] += wk * xb[r] * xr[c];
+        acc[12 + 3 * r + c] += wk * ub[r] * xr[c];
+      }
+      acc[9 + r] += wk * xb[r];
+      acc[21 + r] += wk * ub[r];
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < 24; ++q) {
+    const float v = wave_sum(acc[q]);
+    if (lane == 0) s_red[wv][q] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 24) {
+    float s = 0.f;
+    for (int w = 0; w < WG / 64; ++w) s += s_red[w][threadIdx.x];
+    pose_bar[b * 24 + threadIdx.x] += s;
+  }
+}
+
+}  // namespace lbmib

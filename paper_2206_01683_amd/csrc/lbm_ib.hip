@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/lbm_ib.h"
+#include "adjoint.hpp"
 #include "batch.hpp"
 
 using namespace lbmib;
@@ -25,7 +26,8 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // Workspace layout (all offsets 256-byte aligned).
 struct Layout {
   int tnx, tny, tnz, ntiles, cap, maxm;
-  size_t guard, counters, tile_flag, tile_slot, active, mbase, chunk_box, partials, macro, gbuf, rec, mstate, total;
+  size_t guard, counters, tile_flag, tile_slot, active, mbase, chunk_box, partials, macro, gbuf, rec, mstate;
+  size_t gbar, adjfix, mbar, total;
 };
 
 bool params_ok(const lbm_params *p) {
@@ -84,6 +86,12 @@ Layout layout(const lbm_params *p) {
   L.gbuf = take(sizeof(unsigned long long) * 3 * 512 * (size_t)L.cap);
   L.rec = take(sizeof(float) * REC * (size_t)L.maxm);
   L.mstate = take(sizeof(float) * 4 * (size_t)L.maxm);
+  L.gbar = L.adjfix = L.mbar = 0;
+  if (p->with_adjoint) {
+    L.gbar = take(sizeof(float) * 3 * 512 * (size_t)L.cap);
+    L.adjfix = take(sizeof(unsigned long long) * 4 * 512 * (size_t)L.cap);
+    L.mbar = take(sizeof(float) * 6 * (size_t)L.maxm);
+  }
   L.total = o;
   return L;
 }
@@ -435,6 +443,92 @@ lbm_status lbm_ib_step(lbm_ctx *c, const lbm_markers *m, const float *poses, con
     float *w = wrench ? wrench + (size_t)s * 8 : nullptr;
     lbm_status st = LBM_BY_STORAGE(c, step_one, m, pose, &frames[s], w);
     if (st != LBM_OK) return st;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_state_save(lbm_ctx *c, void *dst) {
+  if (!c || !dst) return LBM_ERR_ARG;
+  const size_t bytes = (size_t)27 * c->plane * elem_bytes(c->p.storage);
+  return hipMemcpyAsync(dst, c->f[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream) == hipSuccess ? LBM_OK
+                                                                                                  : LBM_ERR_DEVICE;
+}
+
+lbm_status lbm_state_restore(lbm_ctx *c, const void *src, int64_t step) {
+  if (!c || !src || step < 0) return LBM_ERR_ARG;
+  const size_t bytes = (size_t)27 * c->plane * elem_bytes(c->p.storage);
+  if (hipMemcpyAsync(c->f[c->cur], src, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+    return LBM_ERR_DEVICE;
+  c->steps = step;
+  return LBM_OK;
+}
+
+lbm_status lbm_bind_populations(lbm_ctx *c, void *f_cur, void *f_next) {
+  if (!c || !f_cur || !f_next || f_cur == f_next) return LBM_ERR_ARG;
+  c->f[0] = f_cur;
+  c->f[1] = f_next;
+  c->cur = 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_adjoint_step(lbm_ctx *c, const void *state, const lbm_markers *m, const float *pose,
+                            const lbm_frame *frame, const double *w, const void *lam_next, void *lam_prev,
+                            float *pose_bar) {
+  if (!c || !state || !frame || !w || !lam_next || !lam_prev || lam_next == lam_prev) return LBM_ERR_ARG;
+  if (!markers_ok(c, m) || !frame_ok(frame)) return LBM_ERR_ARG;
+  const bool ib = m && m->n > 0;
+  if (ib && (!pose || !pose_bar)) return LBM_ERR_ARG;
+  if (ib && m->n > c->p.max_markers) return LBM_ERR_CAPACITY;
+  for (int q = 0; q < 4; ++q)
+    if (!std::isfinite(w[q])) return LBM_ERR_ARG;
+  if (c->p.storage != LBM_STORE_F32 || c->p.mdf_iters != 1 || !c->p.with_adjoint || rotating(frame))
+    return LBM_ERR_UNSUPPORTED;
+  EnvView e = env_view(c, m);
+  e.f[0] = const_cast<void *>(state);
+  e.f[1] = nullptr;
+  const FrameF fr = frame_f(frame);
+  lbm_status st;
+  // forward immersed-boundary phases of this step, from `state`
+  if (ib) {
+    k_skin_mark<<<skin_items(e.n), WG, 0, c->stream>>>(e, pose);
+    k_active<<<(e.ntiles + WG - 1) / WG, WG, 0, c->stream>>>(e);
+    k_macro<StoreF32, false><<<std::min(c->L.cap, 2048), WG, 0, c->stream>>>(e, fr, 0);
+    k_interp<false, false><<<interp_items(e.n), WG, 0, c->stream>>>(e, fr, nullptr);
+    k_spread<<<std::min(c->L.cap * kSpreadSplit, 2048), WG, 0, c->stream>>>(e, nullptr);
+    if ((st = launched()) != LBM_OK) return st;
+    c->slots_dirty = true;
+  }
+  AdjArgs A{};
+  for (int a = 0; a < 3; ++a) {
+    A.wF[a] = (float)w[a];
+    A.a0[a] = -fr.acc[a];
+    A.bc_u_lo[a] = fr.ulo[a];
+    A.bc_u_hi[a] = fr.uhi[a];
+  }
+  A.wP = (float)w[3];
+  A.lam_next = static_cast<const float *>(lam_next);
+  A.lam_prev = static_cast<float *>(lam_prev);
+  A.gbar = wsp<float>(c, c->L.gbar);
+  A.adjfix = wsp<unsigned long long>(c, c->L.adjfix);
+  A.mbar = wsp<float>(c, c->L.mbar);
+  if (ib) {
+    k_adj_gbar<<<std::min(c->L.cap, 2048), WG, 0, c->stream>>>(e, A);
+    k_adj_markers<<<interp_items(e.n), WG, 0, c->stream>>>(e, A);
+    k_adj_spread<<<std::min(c->L.cap * kSpreadSplit, 2048), WG, 0, c->stream>>>(e, A);
+    if ((st = launched()) != LBM_OK) return st;
+  }
+  const int grid = ((e.nblocks + 7) / 8) * 8;
+  dim3 blk(c->bx, c->by);
+  if (e.g.xper) {
+    k_adj_collide<true><<<grid, blk, 0, c->stream>>>(e, A);
+  } else {
+    k_adj_collide<false><<<grid, blk, 0, c->stream>>>(e, A);
+    k_adj_face<<<dim3((c->p.ny * c->p.nz + 255) / 256, 2), 256, 0, c->stream>>>(e, A);
+  }
+  if ((st = launched()) != LBM_OK) return st;
+  if (ib) {
+    k_adj_pose<<<m->nbones, WG, 0, c->stream>>>(e, A, pose_bar);
+    if ((st = launched()) != LBM_OK) return st;
   }
   return LBM_OK;
 }

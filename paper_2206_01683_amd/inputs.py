@@ -196,17 +196,18 @@ def chain_poses(psi: np.ndarray, psidot: np.ndarray, joints_rest: np.ndarray) ->
     rest point xbar to R_j (xbar - Jbar_j) + J_j, with R_j the rotation by
     psi_j about z. Returns (nsteps, nbones, 24)."""
     nsteps, nb = psi.shape
+    dt = np.result_type(psi, psidot, np.float64)  # complex when differentiating by complex step
     jr = np.asarray(joints_rest, dtype=np.float64)
     h = float(jr[1, 0] - jr[0, 0]) if nb > 1 else 1.0
-    out = np.zeros((nsteps, nb, POSE_FIELDS))
-    J = np.repeat(jr[0][None, :], nsteps, axis=0)
-    Jd = np.zeros((nsteps, 3))
+    out = np.zeros((nsteps, nb, POSE_FIELDS), dtype=dt)
+    J = np.repeat(jr[0][None, :], nsteps, axis=0).astype(dt)
+    Jd = np.zeros((nsteps, 3), dtype=dt)
     for j in range(nb):
         c, s = np.cos(psi[:, j]), np.sin(psi[:, j])
         d = psidot[:, j]
-        R = np.zeros((nsteps, 3, 3))
+        R = np.zeros((nsteps, 3, 3), dtype=dt)
         R[:, 0, 0], R[:, 0, 1], R[:, 1, 0], R[:, 1, 1], R[:, 2, 2] = c, -s, s, c, 1.0
-        Rd = np.zeros((nsteps, 3, 3))
+        Rd = np.zeros((nsteps, 3, 3), dtype=dt)
         Rd[:, 0, 0], Rd[:, 0, 1], Rd[:, 1, 0], Rd[:, 1, 1] = -s * d, -c * d, c * d, -s * d
         t = J - np.einsum('nab,b->na', R, jr[j])
         td = Jd - np.einsum('nab,b->na', Rd, jr[j])
@@ -254,12 +255,13 @@ def fin_joint_angles(params, steps: np.ndarray, nbones: int = 10, period: float 
       j = 0..8 with segments {0-2}, {3-5}, {6-8} (phi1 = 0), and the tail
       theta_9(n) = At sin(2 pi f n / period - 1.8 pi + phit).
     Returns (theta, thetadot), each (nsteps, nbones)."""
-    A1, A2, A3, f, p2, p3, At, pt = [float(v) for v in params]
+    A1, A2, A3, f, p2, p3, At, pt = list(np.asarray(params).ravel())
     n = np.asarray(steps, dtype=np.float64)[:, None]
     j = np.arange(nbones)[None, :]
     seg = np.minimum(j // 3, 2)
-    A = np.choose(seg, [A1, A2, A3]).astype(np.float64)
-    ph = np.choose(seg, [0.0, p2, p3]).astype(np.float64)
+    dt = np.result_type(np.asarray(params), np.float64)
+    A = np.choose(seg, [A1, A2, A3]).astype(dt)
+    ph = np.choose(seg, [0.0, p2, p3]).astype(dt)
     w = 2 * math.pi * f / period
     arg = w * n - 2 * math.pi * j / 10.0 + ph
     th = A * np.sin(arg)
@@ -269,6 +271,26 @@ def fin_joint_angles(params, steps: np.ndarray, nbones: int = 10, period: float 
     th[:, tail] = At * np.sin(arg_t)
     thd[:, tail] = At * w * np.cos(arg_t)
     return th, thd
+
+
+def fin_poses(params, ms: MarkerSet, steps, period: float = 400.0):
+    """Bone poses of the differentiation workload for kinematics parameters."""
+    th, thd = fin_joint_angles(params, steps, ms.nbones, period)
+    psi, psid = headings_from_joint_angles(th, thd)
+    return chain_poses(psi, psid, ms.joints_rest)
+
+
+def fin_pose_jacobian(params, ms: MarkerSet, steps, period: float = 400.0, h: float = 1e-20):
+    """d(bone poses)/d(params), shape (nsteps, nbones, 24, 8), by the complex
+    step: the kinematics are analytic in the parameters, so Im(pose(p + i h
+    e_j))/h is the derivative to machine precision."""
+    p = np.asarray(params, dtype=np.float64)
+    out = np.zeros((len(steps), ms.nbones, POSE_FIELDS, p.size))
+    for j in range(p.size):
+        pc = p.astype(np.complex128)
+        pc[j] += 1j * h
+        out[..., j] = np.imag(fin_poses(pc, ms, steps, period)) / h
+    return out
 
 
 def headings_from_joint_angles(theta, thetadot):

@@ -22,6 +22,7 @@ LBM_OK = 0
 STATUS = {0: "LBM_OK", -1: "LBM_ERR_ARG", -2: "LBM_ERR_DEVICE", -3: "LBM_ERR_UNSTABLE",
           -4: "LBM_ERR_MARKER_RANGE", -5: "LBM_ERR_CAPACITY", -6: "LBM_ERR_UNSUPPORTED"}
 BC_PERIODIC, BC_VELOCITY, BC_OUTFLOW = 0, 1, 2
+OK, ERR_ARG, ERR_DEVICE, ERR_UNSTABLE, ERR_MARKER_RANGE, ERR_CAPACITY, ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 
 
@@ -30,7 +31,7 @@ class Params(ctypes.Structure):
                 ("bc_lo", ctypes.c_int32), ("bc_hi", ctypes.c_int32), ("storage", ctypes.c_int32),
                 ("max_markers", ctypes.c_int32), ("max_bones", ctypes.c_int32), ("mdf_iters", ctypes.c_int32),
                 ("max_active_tiles", ctypes.c_int32), ("block_x", ctypes.c_int32), ("block_y", ctypes.c_int32),
-                ("tau", ctypes.c_double), ("ib_alpha", ctypes.c_double)]
+                ("with_adjoint", ctypes.c_int32), ("tau", ctypes.c_double), ("ib_alpha", ctypes.c_double)]
 
 
 class Frame(ctypes.Structure):
@@ -80,6 +81,10 @@ def lib():
         L.lbm_macros.argtypes = [vp, vp, vp, vp]
         L.lbm_ib_step.argtypes = [vp, vp, vp, vp, ctypes.c_int32, vp]
         L.lbm_body_forces.argtypes = [vp, vp, vp, vp]
+        L.lbm_state_save.argtypes = [vp, vp]
+        L.lbm_state_restore.argtypes = [vp, vp, ctypes.c_int64]
+        L.lbm_adjoint_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.lbm_bind_populations.argtypes = [vp, vp, vp]
         L.lbm_check.argtypes = [vp]
         L.lbm_set_stream.argtypes = [vp, vp]
         L.lbm_profile_enable.argtypes = [vp, ctypes.c_int]
@@ -101,7 +106,9 @@ def lib():
         L.lbm_destroy.restype = None
         for name in ("lbm_init", "lbm_load_populations", "lbm_read_populations", "lbm_macros", "lbm_ib_step",
                      "lbm_body_forces", "lbm_check", "lbm_set_stream", "lbm_profile_enable",
-                     "lbm_profile_collect", "lbm_batch_create", "lbm_batch_run", "lbm_batch_autotune",
+                     "lbm_profile_collect", "lbm_state_save", "lbm_state_restore", "lbm_adjoint_step",
+                     "lbm_bind_populations",
+                     "lbm_batch_create", "lbm_batch_run", "lbm_batch_autotune",
                      "lbm_batch_set_shapes", "lbm_batch_check"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -121,9 +128,10 @@ def _check(rc: int, what: str):
 
 
 def make_params(nx, ny, nz, tau, bc_lo=BC_PERIODIC, bc_hi=BC_PERIODIC, storage="f32", max_markers=0,
-                max_bones=1, mdf_iters=1, ib_alpha=1.0, max_active_tiles=0, block=(0, 0)) -> Params:
+                max_bones=1, mdf_iters=1, ib_alpha=1.0, max_active_tiles=0, block=(0, 0), with_adjoint=False) -> Params:
     return Params(nx, ny, nz, bc_lo, bc_hi, STORAGE[storage] if isinstance(storage, str) else storage,
-                  max_markers, max_bones, mdf_iters, max_active_tiles, block[0], block[1], tau, ib_alpha)
+                  max_markers, max_bones, mdf_iters, max_active_tiles, block[0], block[1], 1 if with_adjoint else 0,
+                  tau, ib_alpha)
 
 
 def frames_array(frames: np.ndarray) -> np.ndarray:
@@ -162,14 +170,14 @@ class Simulation:
 
     def __init__(self, nx, ny, nz, tau, bc_lo=BC_PERIODIC, bc_hi=BC_PERIODIC, storage="f32", max_markers=0,
                  max_bones=1, mdf_iters=1, ib_alpha=1.0, rho0=None, u0=None, device="cuda", block=(0, 0),
-                 max_active_tiles=0, stream=None):
+                 max_active_tiles=0, stream=None, with_adjoint=False):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the lattice Boltzmann library runs only on the GPU")
         L = lib()
         self.device = torch.device(device)
         self.shape = (nz, ny, nx)
         self.params = make_params(nx, ny, nz, tau, bc_lo, bc_hi, storage, max_markers, max_bones, mdf_iters,
-                                  ib_alpha, max_active_tiles, block)
+                                  ib_alpha, max_active_tiles, block, with_adjoint)
         pb = L.lbm_population_bytes(ctypes.byref(self.params))
         wb = L.lbm_workspace_bytes(ctypes.byref(self.params))
         if pb == 0 or wb == 0:
@@ -255,6 +263,37 @@ class Simulation:
         _check(lib().lbm_profile_collect(self.ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)),
                "lbm_profile_collect")
         return a.value, b.value, n.value
+
+    def new_state(self) -> torch.Tensor:
+        """An uninitialized buffer in the stored population layout."""
+        return torch.empty(self.population_bytes, dtype=torch.uint8, device=self.device)
+
+    def save_state(self, dst: torch.Tensor):
+        _check(lib().lbm_state_save(self.ctx, _ptr(dst)), "lbm_state_save")
+
+    def restore_state(self, src: torch.Tensor, step: int = 0):
+        _check(lib().lbm_state_restore(self.ctx, _ptr(src), int(step)), "lbm_state_restore")
+
+    def bind_populations(self, cur: torch.Tensor, nxt: torch.Tensor):
+        """The next step reads `cur` and writes `nxt` (then ping-pong)."""
+        for t in (cur, nxt):
+            assert t.is_cuda and t.numel() * t.element_size() >= self.population_bytes
+        _check(lib().lbm_bind_populations(self.ctx, _ptr(cur), _ptr(nxt)), "lbm_bind_populations")
+        self._bound = (cur, nxt)
+
+    def bind_own_buffers(self):
+        """Return to the context's own two buffers; the state is not carried over."""
+        self.bind_populations(self.fa, self.fb)
+
+    def adjoint_step(self, state: torch.Tensor, markers: Optional[DeviceMarkers], pose: Optional[torch.Tensor],
+                     frame, weights, lam_next: torch.Tensor, lam_prev: torch.Tensor,
+                     pose_bar: Optional[torch.Tensor]):
+        fr = frames_array(np.asarray(frame).reshape(1, 18))
+        wts = np.ascontiguousarray(weights, dtype=np.float64).reshape(4)
+        ms = None if markers is None else markers.struct()
+        _check(lib().lbm_adjoint_step(self.ctx, _ptr(state), None if ms is None else ctypes.byref(ms), _ptr(pose),
+                                      fr.ctypes.data_as(ctypes.c_void_p), wts.ctypes.data_as(ctypes.c_void_p),
+                                      _ptr(lam_next), _ptr(lam_prev), _ptr(pose_bar)), "lbm_adjoint_step")
 
     def check(self) -> int:
         return lib().lbm_check(self.ctx)

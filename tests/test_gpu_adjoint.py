@@ -1,0 +1,191 @@
+"""Discrete adjoint of the coupled step (lbm_adjoint_step) and the
+checkpointed reverse sweep: gradients with respect to the initial state
+(dot-product test against central differences of the GPU forward), with
+respect to the kinematics parameters (against central differences of the FP64
+oracle), and invariance under the checkpoint interval."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2206_01683_amd import adjoint as AD
+from paper_2206_01683_amd import inputs as I
+from paper_2206_01683_amd import lbm
+from gpu_helpers import say
+
+pytestmark = pytest.mark.gpu
+
+NSTEPS = 12
+EVERY = 5  # segments of 5, 5 and 2 steps
+GEOM = dict(nx=48, ny=32, nz=32, length=16.0, n=600, head=(12.0, 16.0, 16.0))
+
+
+def _fin(nsteps=NSTEPS, params=I.C5_BASE):
+    return I.fin_workload(params, nsteps=nsteps, **GEOM)
+
+
+def _sim(w, with_markers=True, **kw):
+    ms = w.markers if with_markers else None
+    return lbm.Simulation(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi, max_markers=ms.n if ms else 0,
+                          max_bones=ms.nbones if ms else 1, u0=w.u0.astype(np.float32), with_adjoint=True, **kw)
+
+
+def _valid_mask(sim, ncell):
+    """Stored-layout entries that hold populations (27 planes of ncell)."""
+    plane = sim.population_bytes // 4 // 27
+    m = torch.zeros((27, plane), dtype=torch.bool, device="cuda")
+    m[:, :ncell] = True
+    return m.reshape(-1)
+
+
+def _smooth_perturbation(sim, w, state, seed, amp=1e-3):
+    """delta_i(x) = amp * f_i(x) * (a_i + b_i sin(2 pi (x/nx + y/ny) + p_i)):
+    smooth in space, random across directions, so it moves density and
+    velocity coherently near the body."""
+    rng = np.random.default_rng(seed)
+    a, b, p = rng.uniform(-1, 1, 27), rng.uniform(-1, 1, 27), rng.uniform(0, 2 * np.pi, 27)
+    z, y, x = np.meshgrid(np.arange(w.nz), np.arange(w.ny), np.arange(w.nx), indexing="ij")
+    ph = 2 * np.pi * (x / w.nx + y / w.ny)
+    plane = sim.population_bytes // 4 // 27
+    d = np.zeros((27, plane), np.float32)
+    f = state.view(torch.float32).reshape(27, plane)[:, :w.ncell].cpu().numpy()
+    for i in range(27):
+        d[i, :w.ncell] = amp * f[i] * (a[i] + b[i] * np.sin(ph + p[i])).ravel()
+    return torch.as_tensor(d.reshape(-1), device="cuda")
+
+
+def _run_J(sim, s0, dm, poses, frames, weights, c=None):
+    sim.bind_own_buffers()
+    sim.restore_state(s0, 0)
+    J, tape = AD.forward(sim, dm, poses, frames, weights, every=len(frames))
+    if c is not None:
+        J += float(torch.dot(c.double(), tape.final.view(torch.float32).double()))
+    return J
+
+
+@pytest.mark.parametrize("case", ["fin", "fluid-open", "fluid-periodic"])
+def test_state_adjoint_matches_central_differences(case):
+    """<dJ/ds0, delta> from the reverse sweep equals (J(s0 + delta) - J(s0 - delta)) / 2."""
+    w = _fin()
+    if case == "fluid-periodic":
+        w.bc_lo = w.bc_hi = I.BC_PERIODIC
+    markers = case == "fin"
+    sim = _sim(w, with_markers=markers)
+    dm = lbm.DeviceMarkers(w.markers) if markers else None
+    poses = torch.as_tensor(w.poses.astype(np.float32), device="cuda") if markers else None
+    rng = np.random.default_rng(3)
+    weights = rng.uniform(-1, 1, 4) if markers else np.zeros(4)
+    mask = _valid_mask(sim, w.ncell)
+    c = None
+    if not markers:  # terminal functional <c, s_N> with c smooth in space
+        c = _smooth_perturbation(sim, w, torch.ones(sim.population_bytes // 4, device="cuda").view(torch.uint8),
+                                 seed=9, amp=1.0)
+    s0 = sim.new_state()
+    sim.save_state(s0)
+    J0, tape = AD.forward(sim, dm, poses, w.frames, weights, every=EVERY)
+    _, lam0 = AD.backward(sim, dm, poses, w.frames, tape, lam_final=c)
+    torch.cuda.synchronize()
+    delta = _smooth_perturbation(sim, w, s0, seed=5)
+    adj = float(torch.dot(lam0[mask].double(), delta[mask].double()))
+    sp = sim.new_state()
+    sm = sim.new_state()
+    sp.view(torch.float32).copy_(s0.view(torch.float32) + delta)
+    sm.view(torch.float32).copy_(s0.view(torch.float32) - delta)
+    Jp = _run_J(sim, sp, dm, poses, w.frames, weights, c)
+    Jm = _run_J(sim, sm, dm, poses, w.frames, weights, c)
+    fd = 0.5 * (Jp - Jm)
+    err = abs(adj - fd) / abs(fd)
+    say(f"{case}: <lam0, delta> = {adj:.8e}, central difference = {fd:.8e}, rel err {err:.2e}")
+    assert np.isfinite(adj) and abs(fd) > 0
+    assert err < 2e-3
+    assert sim.check() == 0
+
+
+def test_reverse_sweep_restores_forward_state():
+    w = _fin()
+    sim = _sim(w)
+    dm = lbm.DeviceMarkers(w.markers)
+    poses = torch.as_tensor(w.poses.astype(np.float32), device="cuda")
+    _, tape = AD.forward(sim, dm, poses, w.frames, [1, 0, 0, 0.5], every=EVERY)
+    before = sim.read_populations().cpu().numpy()
+    AD.backward(sim, dm, poses, w.frames, tape)
+    after = sim.read_populations().cpu().numpy()
+    assert np.array_equal(before, after)
+    assert sim.step_count() == NSTEPS
+
+
+def test_checkpoint_interval_does_not_change_gradient():
+    """Recomputation is deterministic, so every interval gives the same bits."""
+    w = _fin()
+    sim = _sim(w)
+    dm = lbm.DeviceMarkers(w.markers)
+    poses = torch.as_tensor(w.poses.astype(np.float32), device="cuda")
+    s0 = sim.new_state()
+    sim.save_state(s0)
+    out = []
+    for every in (1, EVERY, NSTEPS):
+        sim.bind_own_buffers()
+        sim.restore_state(s0, 0)
+        _, tape = AD.forward(sim, dm, poses, w.frames, [-1, 0.3, 0, 2.0], every=every)
+        pb, lam = AD.backward(sim, dm, poses, w.frames, tape)
+        out.append((pb.cpu().numpy(), lam.cpu().numpy()))
+    for pb, lam in out[1:]:
+        assert np.array_equal(pb, out[0][0])
+        assert np.array_equal(lam, out[0][1])
+
+
+def test_parameter_gradient_against_fp64_oracle():
+    """dJ/dtheta (8 kinematics parameters) from the reverse sweep against FP64
+    central differences of the oracle (h = 1e-3), J the time-averaged thrust
+    plus a power term."""
+    weights = np.array([-1.0, 0.0, 0.0, 0.5])
+    prob = AD.FinProblem(nsteps=NSTEPS, every=EVERY, weights=weights, **GEOM)
+    theta = torch.tensor(I.C5_BASE, dtype=torch.float64, requires_grad=True)
+    J = AD.FinObjective.apply(theta, prob)
+    J.backward()
+    g = theta.grad.numpy()
+    w = prob.workload
+    prm = oracle.params(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi, 1, w.ib_alpha)
+    f0 = oracle.equilibrium_field(np.ones((w.nz, w.ny, w.nx)), w.u0.astype(np.float32).astype(np.float64))
+
+    def J_oracle(th):
+        poses = I.fin_poses(th, w.markers, np.arange(NSTEPS))
+        res = oracle.run(prm, f0, w.frames, w.markers, poses, NSTEPS)
+        return AD.objective(res["wrench"], weights / NSTEPS)
+
+    h = 1e-3
+    fd = np.zeros(8)
+    for j in range(8):
+        e = np.zeros(8)
+        e[j] = h
+        fd[j] = (J_oracle(I.C5_BASE + e) - J_oracle(I.C5_BASE - e)) / (2 * h)
+    J64 = J_oracle(np.asarray(I.C5_BASE))
+    say(f"J gpu {float(J):.8e} oracle {J64:.8e}")
+    for j in range(8):
+        say(f"  dJ/dtheta[{j}]: adjoint {g[j]: .6e}  oracle FD {fd[j]: .6e}")
+    scale = np.abs(fd).max()
+    err = np.abs(g - fd).max() / scale
+    say(f"max |adjoint - FD| / max |FD| = {err:.2e}")
+    assert abs(float(J) - J64) <= 1e-3 * abs(J64) + 1e-9
+    assert err < 5e-3
+    prob.close()
+
+
+def test_adjoint_rejects_unsupported_configurations():
+    w = _fin()
+    dm = lbm.DeviceMarkers(w.markers)
+    pose = torch.as_tensor(w.poses[0].astype(np.float32), device="cuda")
+    for kw in (dict(with_adjoint=False), dict(storage="f16"), dict(mdf_iters=2)):
+        args = dict(with_adjoint=True)
+        args.update(kw)
+        sim = lbm.Simulation(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi, max_markers=w.markers.n,
+                             max_bones=w.markers.nbones, u0=w.u0.astype(np.float32), **args)
+        s = sim.new_state()
+        sim.save_state(s)
+        lam = torch.zeros(sim.population_bytes // 4, device="cuda")
+        lam2 = torch.zeros_like(lam)
+        pb = torch.zeros_like(pose)
+        with pytest.raises(lbm.LBMError) as ei:
+            sim.adjoint_step(s, dm, pose, w.frames[0], [1, 0, 0, 0], lam, lam2, pb)
+        assert ei.value.code == lbm.ERR_UNSUPPORTED
+        sim.close()

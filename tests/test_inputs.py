@@ -69,3 +69,21 @@ def test_fin_parameters_and_batch_envs():
     # the draw is reproducible
     again = I.batch_workloads(count=4, nsteps=60)
     assert [(e.nx, e.ny, e.nz, e.markers.n) for e in envs] == [(e.nx, e.ny, e.nz, e.markers.n) for e in again]
+
+
+def test_fin_pose_jacobian_matches_central_differences():
+    """The complex-step Jacobian of the bone poses against central differences."""
+    ms = I.fish_surface(300, 16.0, (12.0, 16.0, 16.0))
+    steps = np.arange(7)
+    p = np.asarray(I.C5_BASE, dtype=np.float64)
+    J = I.fin_pose_jacobian(p, ms, steps)
+    assert J.shape == (7, ms.nbones, 24, 8)
+    np.testing.assert_array_equal(I.fin_poses(p, ms, steps), I.fin_workload(p, nsteps=7, nx=48, ny=32, nz=32,
+                                                                            length=16.0, n=300,
+                                                                            head=(12.0, 16.0, 16.0)).poses)
+    h = 1e-6
+    for j in range(8):
+        e = np.zeros(8)
+        e[j] = h
+        fd = (I.fin_poses(p + e, ms, steps) - I.fin_poses(p - e, ms, steps)) / (2 * h)
+        np.testing.assert_allclose(J[..., j], fd, atol=1e-7 * max(1.0, np.abs(J[..., j]).max()))
