@@ -129,6 +129,41 @@ def run_batch(nenv: int, nsteps: int, seed: int = 4):
     return out
 
 
+def run_adjoint(nsteps: int = 400, every: int = 20):
+    """Differentiation form: the 128x64x64 swimmer with 3,000 markers,
+    J = time-averaged thrust over nsteps steps. Forward = the steps with a
+    population checkpoint every `every` steps; backward = recompute of each
+    segment into a ring of states plus one adjoint step per step, then the
+    8-parameter gradient. Wall-clock of each, after one untimed pass."""
+    import numpy as np
+    import torch
+
+    from paper_2206_01683_amd import adjoint as AD
+    from paper_2206_01683_amd import inputs as I
+
+    prob = AD.FinProblem(nsteps=nsteps, every=every)
+    theta = np.asarray(I.C5_BASE, dtype=np.float64)
+    _, tape = prob.value(theta)
+    prob.pose_gradient(tape)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, tape = prob.value(theta)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pb = prob.pose_gradient(tape)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    g = prob.gradient(theta, tape)
+    status = prob.sim.check()
+    w = prob.workload
+    prob.close()
+    tf, tb = t1 - t0, t2 - t1
+    return {"workload": w.name, "steps": nsteps, "checkpoint_every": every, "J": J,
+            "grad_norm": float(np.linalg.norm(g)), "forward_ms_per_step": round(tf * 1e3 / nsteps, 4),
+            "backward_ms_per_step": round(tb * 1e3 / nsteps, 4), "adjoint_over_forward": round(tb / tf, 3),
+            "finite": bool(np.isfinite(pb.cpu().numpy()).all()), "status": status}
+
+
 def cpu_baseline(sample_steps: int):
     """The FP64 oracle as it stands, on the host cores, on the first
     sample_steps steps of the same workload (same domain, fish and frames)."""
@@ -155,7 +190,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f32", choices=sorted(BYTES_PER_CELL))
-    ap.add_argument("--cpu-steps", type=int, default=3, help="oracle sample length (0: skip)")
+    ap.add_argument("--cpu-steps", type=int, default=24, help="oracle sample length (0: skip)")
     ap.add_argument("--no-forms", action="store_true", help="skip the FP16/BF16 storage forms")
     ap.add_argument("--block", type=int, nargs=2, default=(0, 0))
     ap.add_argument("--batch-envs", type=int, default=64, help="batched form: environments (0: skip)")
@@ -178,6 +213,8 @@ def main():
                          "bytes_per_cell": BYTES_PER_CELL[st], "status": r["status"]}
     if not args.no_forms and args.batch_envs > 0:
         forms["batched"] = run_batch(args.batch_envs, args.batch_steps)
+    if not args.no_forms:
+        forms["adjoint"] = run_adjoint()
     traffic = measured_traffic(args.storage)
     ach = main_run["collide_gbs"]
     out = {

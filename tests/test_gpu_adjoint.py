@@ -136,7 +136,7 @@ def test_checkpoint_interval_does_not_change_gradient():
 
 def test_parameter_gradient_against_fp64_oracle():
     """dJ/dtheta (8 kinematics parameters) from the reverse sweep against FP64
-    central differences of the oracle (h = 1e-3), J the time-averaged thrust
+    central differences of the oracle (h = 1e-4), J the time-averaged thrust
     plus a power term."""
     weights = np.array([-1.0, 0.0, 0.0, 0.5])
     prob = AD.FinProblem(nsteps=NSTEPS, every=EVERY, weights=weights, **GEOM)
@@ -150,24 +150,24 @@ def test_parameter_gradient_against_fp64_oracle():
 
     def J_oracle(th):
         poses = I.fin_poses(th, w.markers, np.arange(NSTEPS))
-        res = oracle.run(prm, f0, w.frames, w.markers, poses, NSTEPS)
+        res = oracle.run(prm, f0.copy(), w.frames, w.markers, poses, NSTEPS)  # run advances f in place
         return AD.objective(res["wrench"], weights / NSTEPS)
 
-    h = 1e-3
+    h = 1e-4
     fd = np.zeros(8)
     for j in range(8):
         e = np.zeros(8)
         e[j] = h
         fd[j] = (J_oracle(I.C5_BASE + e) - J_oracle(I.C5_BASE - e)) / (2 * h)
     J64 = J_oracle(np.asarray(I.C5_BASE))
-    say(f"J gpu {float(J):.8e} oracle {J64:.8e}")
+    say(f"J gpu {J.item():.8e} oracle {J64:.8e}")
     for j in range(8):
         say(f"  dJ/dtheta[{j}]: adjoint {g[j]: .6e}  oracle FD {fd[j]: .6e}")
     scale = np.abs(fd).max()
     err = np.abs(g - fd).max() / scale
     say(f"max |adjoint - FD| / max |FD| = {err:.2e}")
-    assert abs(float(J) - J64) <= 1e-3 * abs(J64) + 1e-9
-    assert err < 5e-3
+    assert abs(J.item() - J64) <= 1e-5 * abs(J64)
+    assert err < 1e-4
     prob.close()
 
 
