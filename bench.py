@@ -191,7 +191,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f32", choices=sorted(BYTES_PER_CELL))
     ap.add_argument("--cpu-steps", type=int, default=24, help="oracle sample length (0: skip)")
-    ap.add_argument("--no-forms", action="store_true", help="skip the FP16/BF16 storage forms")
+    ap.add_argument("--forms", default="f16,bf16,batched,adjoint",
+                    help="comma-separated extra forms to measure: f16, bf16, batched, adjoint")
+    ap.add_argument("--no-forms", action="store_true", help="measure no extra form")
     ap.add_argument("--block", type=int, nargs=2, default=(0, 0))
     ap.add_argument("--batch-envs", type=int, default=64, help="batched form: environments (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=200, help="batched form: steps per graph replay")
@@ -204,16 +206,17 @@ def main():
 
     main_run = run_gpu(args.storage, args.steps, args.warmup, tuple(args.block))
     w = main_run["workload"]
+    want = set() if args.no_forms else {f.strip() for f in args.forms.split(",") if f.strip()}
     forms = {}
-    if not args.no_forms and args.storage == "f32":
-        for st in ("f16", "bf16"):
+    if args.storage == "f32":
+        for st in sorted(want & {"f16", "bf16"}):
             r = run_gpu(st, args.steps, args.warmup, tuple(args.block))
             forms[st] = {"mlups": round(r["mlups"], 1), "collide_GBps": round(r["collide_gbs"], 1),
                          "collide_frac_of_hbm_peak": round(r["collide_gbs"] / HBM_PEAK_GBS, 4),
                          "bytes_per_cell": BYTES_PER_CELL[st], "status": r["status"]}
-    if not args.no_forms and args.batch_envs > 0:
+    if "batched" in want and args.batch_envs > 0:
         forms["batched"] = run_batch(args.batch_envs, args.batch_steps)
-    if not args.no_forms:
+    if "adjoint" in want:
         forms["adjoint"] = run_adjoint()
     traffic = measured_traffic(args.storage)
     ach = main_run["collide_gbs"]
