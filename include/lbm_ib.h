@@ -267,12 +267,16 @@ lbm_status lbm_batch_create(lbm_batch **out, const lbm_env *envs, int32_t nenv, 
 lbm_status lbm_batch_run(lbm_batch *b, int32_t nsteps, int32_t mode, int32_t graph);
 
 /* Tile-shape autotuner: for every environment time the collide kernel with
- * each 512-thread shape (64x8, 128x4, 256x2, 512x1) over reps launches and keep
- * the fastest. The state is not advanced. shapes_out [host, nenv][2] or NULL.
- * Synchronizes. */
+ * each 512-thread shape over reps launches and keep the fastest. Shapes
+ * (block_x, block_y): 64x8, 128x4, 256x2 and 512x1 are 2-D blocks over
+ * (x, y) rows; (512, 0) is the linear shape, 512 consecutive cells of the
+ * x-fastest order per block with rows wrapped (no idle lanes at ragged row
+ * ends). The state is not advanced. shapes_out [host, nenv][2] or NULL.
+ * Sets the shapes the next run uses. */
 lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, int32_t *shapes_out);
 
-/* Apply shapes [host, nenv][2] (e.g. a cached autotuning result). */
+/* Apply shapes [host, nenv][2] (e.g. a cached autotuning result); any of the
+ * five autotuner shapes, else LBM_ERR_ARG. */
 lbm_status lbm_batch_set_shapes(lbm_batch *b, const int32_t *shapes);
 
 /* Synchronize; LBM_ERR_DEVICE if a persistent run's barrier timed out,

@@ -23,12 +23,15 @@
 //   4 k_adj_collide   every cell: fbar from the collide adjoint and the band
 //                     IB terms, push-streamed into lam (324 B per cell);
 //                     k_adj_face adds the open faces' extrapolation adjoint
-//   5 k_adj_pose      per bone: dJ/dR, dJ/dt, dJ/dRdot, dJ/dtdot
+//   5 k_adj_pose_part per (bone, marker range): dJ/dR, dJ/dt, dJ/dRdot,
+//     k_adj_pose_sum  dJ/dtdot partials, then their sum in a fixed order
 #pragma once
 
 #include "ib.hpp"
 
 namespace lbmib {
+
+constexpr int kPoseSplit = 16;  // workgroups per bone in the pose adjoint
 
 struct AdjArgs {
   float wF[3];                        // objective weight on the fluid force on the body
@@ -39,6 +42,7 @@ struct AdjArgs {
   float *__restrict__ gbar;            // [cap][3][512]
   unsigned long long *__restrict__ adjfix;  // [cap][4][512]: spread rhobar, U*bar (fixed point)
   float *__restrict__ mbar;            // [6][n]: Xbar (3), Ubar (3)
+  float *__restrict__ pbar;            // [nbones][kPoseSplit][24]: pose-adjoint partial sums
   float bc_u_lo[3], bc_u_hi[3];        // face velocities
 };
 
@@ -388,13 +392,8 @@ template <bool XPER>
 __device__ inline void adj_collide_cell(const EnvView &e, const AdjArgs &A, int lb, int tx, int ty) {
   const GridArgs &g = e.g;
   const float *__restrict__ src = static_cast<const float *>(e.f[0]);
-  const int bxi = lb % e.gx;
-  const int rest = lb / e.gx;
-  const int byi = rest % e.gy;
-  const int z = rest / e.gy;
-  const int x = bxi * e.bx + tx;
-  const int y = byi * e.by + ty;
-  if (x >= g.nx || y >= g.ny) return;
+  int x, y, z;
+  if (!cell_of(e, lb, tx, ty, x, y, z)) return;
   const int ym = y == 0 ? g.ny - 1 : y - 1;
   const int yp = y == g.ny - 1 ? 0 : y + 1;
   const int zm = z == 0 ? g.nz - 1 : z - 1;
@@ -474,7 +473,7 @@ __device__ inline void adj_collide_cell(const EnvView &e, const AdjArgs &A, int 
 // Face extrapolation adjoint, one thread per (y, z) of each open face
 // (blockIdx.y: 0 = x = 0 face, 1 = x = nx-1 face): adds its share of
 // fbar(x_f) into the entries x_f streamed into (each written by one thread).
-__global__ void __launch_bounds__(256) k_adj_face(EnvView e, AdjArgs A) {
+__global__ void __launch_bounds__(64) k_adj_face(EnvView e, AdjArgs A) {
   const GridArgs &g = e.g;
   const int id = blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= g.ny * g.nz) return;
@@ -498,11 +497,19 @@ __global__ void __launch_bounds__(256) k_adj_face(EnvView e, AdjArgs A) {
   adj_face(lam, rho, m, gg, lo ? A.bc_u_lo : A.bc_u_hi, (lo ? g.bc_lo : g.bc_hi) == 1, A, e.omt, e.pref, rb, mb, gb);
   const int yy[3] = {yp, y, ym};
   const int zz[3] = {zp, z, zm};
+  // all 27 reads before any write, so they are in flight together (the
+  // targets are distinct: one per direction plane)
+  float old[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const uint32_t ot = ((uint32_t)zz[cz_of(i) + 1] * g.ny + yy[cy_of(i) + 1]) * g.nx + (x - cx_of(i));
+    old[i] = A.lam_prev[(uint32_t)i * g.plane + ot];
+  }
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const float fb = e.omt * lam[i] + rb + (float)cx_of(i) * mb[0] + (float)cy_of(i) * mb[1] + (float)cz_of(i) * mb[2];
     const uint32_t ot = ((uint32_t)zz[cz_of(i) + 1] * g.ny + yy[cy_of(i) + 1]) * g.nx + (x - cx_of(i));
-    A.lam_prev[(uint32_t)i * g.plane + ot] += fb;
+    A.lam_prev[(uint32_t)i * g.plane + ot] = old[i] + fb;
   }
 }
 
@@ -530,30 +537,33 @@ __global__ void __launch_bounds__(WG) k_adj_spread(EnvView e, AdjArgs A) {
 }
 
 // ------------------------------------------------------------------ pass 5 --
-// Pose adjoint of bone blockIdx.x for this step, added into pose_bar[b][24]:
-// X = sum_b w (R xrest + t), U = sum_b w (Rdot xrest + tdot).
-__global__ void __launch_bounds__(WG) k_adj_pose(EnvView e, AdjArgs A, float *__restrict__ pose_bar) {
-  __shared__ float s_red[WG / 64][24];
-  const int b = blockIdx.x;
+// Pose adjoint: X = sum_b w (R xrest + t), U = sum_b w (Rdot xrest + tdot).
+// Workgroup (b, p) sums the terms of bone b over the p-th of kPoseSplit marker
+// ranges into pbar[b][p]; k_adj_pose_sum adds the kPoseSplit partials in
+// order into pose_bar[b] (deterministic).
+__global__ void __launch_bounds__(256) k_adj_pose_part(EnvView e, AdjArgs A) {
+  __shared__ float s_red[4][24];
+  const int b = blockIdx.x, p = blockIdx.y;
   const int n = e.n;
+  const int chunk = (n + kPoseSplit - 1) / kPoseSplit;
+  const int k0 = p * chunk, k1 = min(n, k0 + chunk);
   float acc[24];
 #pragma unroll
   for (int q = 0; q < 24; ++q) acc[q] = 0.f;
-  for (int k = threadIdx.x; k < n; k += WG) {
+  for (int k = k0 + (int)threadIdx.x; k < k1; k += 256) {
     const float wk = (e.bone[k] == b ? e.weight[k] : 0.f) + (e.bone[n + k] == b ? e.weight[n + k] : 0.f);
-    if (wk == 0.f) continue;
     const float xr[3] = {e.xrest[k], e.xrest[n + k], e.xrest[2 * n + k]};
-    const float xb[3] = {A.mbar[k], A.mbar[n + k], A.mbar[2 * n + k]};
-    const float ub[3] = {A.mbar[3 * n + k], A.mbar[4 * n + k], A.mbar[5 * n + k]};
+    const float xb[3] = {wk * A.mbar[k], wk * A.mbar[n + k], wk * A.mbar[2 * n + k]};
+    const float ub[3] = {wk * A.mbar[3 * n + k], wk * A.mbar[4 * n + k], wk * A.mbar[5 * n + k]};
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        acc[3 * r + c] += wk * xb[r] * xr[c];
-        acc[12 + 3 * r + c] += wk * ub[r] * xr[c];
+        acc[3 * r + c] += xb[r] * xr[c];
+        acc[12 + 3 * r + c] += ub[r] * xr[c];
       }
-      acc[9 + r] += wk * xb[r];
-      acc[21 + r] += wk * ub[r];
+      acc[9 + r] += xb[r];
+      acc[21 + r] += ub[r];
     }
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -563,11 +573,17 @@ __global__ void __launch_bounds__(WG) k_adj_pose(EnvView e, AdjArgs A, float *__
     if (lane == 0) s_red[wv][q] = v;
   }
   __syncthreads();
-  if (threadIdx.x < 24) {
-    float s = 0.f;
-    for (int w = 0; w < WG / 64; ++w) s += s_red[w][threadIdx.x];
-    pose_bar[b * 24 + threadIdx.x] += s;
-  }
+  if (threadIdx.x < 24)
+    A.pbar[((size_t)b * kPoseSplit + p) * 24 + threadIdx.x] =
+        ((s_red[0][threadIdx.x] + s_red[1][threadIdx.x]) + s_red[2][threadIdx.x]) + s_red[3][threadIdx.x];
+}
+
+__global__ void __launch_bounds__(64) k_adj_pose_sum(AdjArgs A, float *__restrict__ pose_bar) {
+  const int b = blockIdx.x, q = threadIdx.x;
+  if (q >= 24) return;
+  float s = 0.f;
+  for (int p = 0; p < kPoseSplit; ++p) s += A.pbar[((size_t)b * kPoseSplit + p) * 24 + q];
+  pose_bar[b * 24 + q] += s;
 }
 
 }  // namespace lbmib

@@ -18,7 +18,7 @@ struct GridArgs {
 struct EnvView {
   GridArgs g;
   float inv_tau, omt, pref;     // 1/tau, 1 - 1/tau, 1 - 1/(2 tau)
-  int bx, by, gx, gy, nblocks;  // collide tile shape and its block grid
+  int bx, by, gx, gy, nblocks;  // collide tile shape and its block grid (by = 0: linear, see cell_of)
   void *f[2];                   // population buffers
   // immersed boundary
   int ib;                       // a body is present this step
@@ -41,6 +41,29 @@ struct EnvView {
   int rot;               // some frame rotates
   int cur0;              // buffer holding the state at the start of the run
 };
+
+// Cell of thread (tx, ty) in logical collide block lb. Tile shapes bx x by
+// cover x-rows and y in 2-D blocks (z from the block index); the linear shape
+// (by = 0) gives each block bx consecutive cells of the x-fastest order, rows
+// and planes wrapped, so no lane idles at ragged row ends. False past the
+// lattice.
+__device__ inline bool cell_of(const EnvView &e, int lb, int tx, int ty, int &x, int &y, int &z) {
+  if (e.by == 0) {
+    const uint32_t cell = (uint32_t)lb * (uint32_t)e.bx + (uint32_t)tx;
+    const uint32_t row = cell / (uint32_t)e.g.nx;
+    x = (int)(cell - row * (uint32_t)e.g.nx);
+    z = (int)(row / (uint32_t)e.g.ny);
+    y = (int)(row - (uint32_t)z * (uint32_t)e.g.ny);
+    return z < e.g.nz;
+  }
+  const int bxi = lb % e.gx;
+  const int rest = lb / e.gx;
+  const int byi = rest % e.gy;
+  z = rest / e.gy;
+  x = bxi * e.bx + tx;
+  y = byi * e.by + ty;
+  return x < e.g.nx && y < e.g.ny;
+}
 
 // lbm_frame (18 doubles) -> float32 frame constants
 __device__ inline FrameF frame_from(const double *d) {

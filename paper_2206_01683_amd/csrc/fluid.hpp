@@ -98,7 +98,7 @@ __device__ inline void load_g(const GridArgs &g, const int *__restrict__ tile_sl
 // The open-face lanes reuse the interior arithmetic: replacing f_i by
 // f_i + f^eq_i(rho_f, u_b) - f^eq_i(rho_f, u_f) makes the BGK formula with
 // (rho_f, u_b, F_b) produce exactly the extrapolated values.
-// One cell of logical block lb (tile shape e.bx x e.by), thread (tx, ty);
+// One cell of logical block lb (tile shape e.bx x e.by, see cell_of), thread (tx, ty);
 // `cur` is the buffer holding f*(n-1), the other one receives f*(n).
 template <class S, bool XPER, bool ROT>
 __device__ inline void collide_cell(const EnvView &e, const FrameF &fr, int cur, int lb, int tx, int ty) {
@@ -106,14 +106,9 @@ __device__ inline void collide_cell(const EnvView &e, const FrameF &fr, int cur,
   const T *__restrict__ src = static_cast<const T *>(e.f[cur]);
   T *__restrict__ dst = static_cast<T *>(e.f[cur ^ 1]);
   const int *__restrict__ tile_slot = e.ib ? e.tile_slot : nullptr;
-  const int bxi = lb % e.gx;
-  const int rest = lb / e.gx;
-  const int byi = rest % e.gy;
-  const int z = rest / e.gy;
-  const int x = bxi * e.bx + tx;
-  const int y = byi * e.by + ty;
+  int x, y, z;
+  if (!cell_of(e, lb, tx, ty, x, y, z)) return;
   const GridArgs &g = e.g;
-  if (x >= g.nx || y >= g.ny) return;
 
   const bool lo_face = !XPER && x == 0;
   const bool hi_face = !XPER && x == g.nx - 1;

@@ -27,7 +27,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Layout {
   int tnx, tny, tnz, ntiles, cap, maxm;
   size_t guard, counters, tile_flag, tile_slot, active, mbase, chunk_box, partials, macro, gbuf, rec, mstate;
-  size_t gbar, adjfix, mbar, total;
+  size_t gbar, adjfix, mbar, pbar, total;
 };
 
 bool params_ok(const lbm_params *p) {
@@ -86,11 +86,12 @@ Layout layout(const lbm_params *p) {
   L.gbuf = take(sizeof(unsigned long long) * 3 * 512 * (size_t)L.cap);
   L.rec = take(sizeof(float) * REC * (size_t)L.maxm);
   L.mstate = take(sizeof(float) * 4 * (size_t)L.maxm);
-  L.gbar = L.adjfix = L.mbar = 0;
+  L.gbar = L.adjfix = L.mbar = L.pbar = 0;
   if (p->with_adjoint) {
     L.gbar = take(sizeof(float) * 3 * 512 * (size_t)L.cap);
     L.adjfix = take(sizeof(unsigned long long) * 4 * 512 * (size_t)L.cap);
     L.mbar = take(sizeof(float) * 6 * (size_t)L.maxm);
+    L.pbar = take(sizeof(float) * 24 * kPoseSplit * (size_t)p->max_bones);
   }
   L.total = o;
   return L;
@@ -172,6 +173,9 @@ bool frame_ok(const lbm_frame *fr) {
 
 lbm_status launched() { return hipGetLastError() == hipSuccess ? LBM_OK : LBM_ERR_DEVICE; }
 
+// Thread block of the collide launches: bx x by, or bx x 1 for the linear shape.
+dim3 collide_block(const lbm_ctx *c) { return dim3(c->bx, c->by > 0 ? c->by : 1); }
+
 // Device view of a context; the immersed-boundary fields describe `m` (may be
 // null: no body this step).
 EnvView env_view(lbm_ctx *c, const lbm_markers *m) {
@@ -183,9 +187,14 @@ EnvView env_view(lbm_ctx *c, const lbm_markers *m) {
   e.pref = (float)(1.0 - 0.5 / tau);
   e.bx = c->bx;
   e.by = c->by;
-  e.gx = (c->p.nx + c->bx - 1) / c->bx;
-  e.gy = (c->p.ny + c->by - 1) / c->by;
-  e.nblocks = e.gx * e.gy * c->p.nz;
+  if (c->by == 0) {  // linear shape: bx consecutive cells per block
+    e.gx = e.gy = 0;
+    e.nblocks = (int)(((size_t)c->p.nx * c->p.ny * c->p.nz + c->bx - 1) / c->bx);
+  } else {
+    e.gx = (c->p.nx + c->bx - 1) / c->bx;
+    e.gy = (c->p.ny + c->by - 1) / c->by;
+    e.nblocks = e.gx * e.gy * c->p.nz;
+  }
   e.f[0] = c->f[0];
   e.f[1] = c->f[1];
   e.ib = (m && m->n > 0) ? 1 : 0;
@@ -223,7 +232,7 @@ EnvView env_view(lbm_ctx *c, const lbm_markers *m) {
 template <class S>
 lbm_status launch_collide(lbm_ctx *c, const EnvView &e, const FrameF &fr, bool rot) {
   const int grid = ((e.nblocks + 7) / 8) * 8;
-  dim3 blk(c->bx, c->by);
+  const dim3 blk = collide_block(c);
   const bool xper = e.g.xper;
   if (xper && rot)
     k_collide<S, true, true><<<grid, blk, 0, c->stream>>>(e, fr, c->cur);
@@ -511,6 +520,7 @@ lbm_status lbm_adjoint_step(lbm_ctx *c, const void *state, const lbm_markers *m,
   A.gbar = wsp<float>(c, c->L.gbar);
   A.adjfix = wsp<unsigned long long>(c, c->L.adjfix);
   A.mbar = wsp<float>(c, c->L.mbar);
+  A.pbar = wsp<float>(c, c->L.pbar);
   if (ib) {
     k_adj_gbar<<<std::min(c->L.cap, 2048), WG, 0, c->stream>>>(e, A);
     k_adj_markers<<<interp_items(e.n), WG, 0, c->stream>>>(e, A);
@@ -518,16 +528,17 @@ lbm_status lbm_adjoint_step(lbm_ctx *c, const void *state, const lbm_markers *m,
     if ((st = launched()) != LBM_OK) return st;
   }
   const int grid = ((e.nblocks + 7) / 8) * 8;
-  dim3 blk(c->bx, c->by);
+  const dim3 blk = collide_block(c);
   if (e.g.xper) {
     k_adj_collide<true><<<grid, blk, 0, c->stream>>>(e, A);
   } else {
     k_adj_collide<false><<<grid, blk, 0, c->stream>>>(e, A);
-    k_adj_face<<<dim3((c->p.ny * c->p.nz + 255) / 256, 2), 256, 0, c->stream>>>(e, A);
+    k_adj_face<<<dim3((c->p.ny * c->p.nz + 63) / 64, 2), 64, 0, c->stream>>>(e, A);
   }
   if ((st = launched()) != LBM_OK) return st;
   if (ib) {
-    k_adj_pose<<<m->nbones, WG, 0, c->stream>>>(e, A, pose_bar);
+    k_adj_pose_part<<<dim3(m->nbones, kPoseSplit), 256, 0, c->stream>>>(e, A);
+    k_adj_pose_sum<<<m->nbones, 64, 0, c->stream>>>(A, pose_bar);
     if ((st = launched()) != LBM_OK) return st;
   }
   return LBM_OK;
@@ -649,7 +660,7 @@ size_t batch_layout(int nenv, size_t *o_envs, size_t *o_pre, size_t *o_bar) {
 
 bool env_ok(const lbm_env &v) {
   const lbm_ctx *c = v.ctx;
-  if (!c || c->p.storage != LBM_STORE_F32 || c->bx * c->by != WG) return false;
+  if (!c || c->p.storage != LBM_STORE_F32 || !(c->bx * c->by == WG || (c->bx == WG && c->by == 0))) return false;
   if (v.m.n < 1 || v.m.n > c->p.max_markers || !markers_ok(c, &v.m)) return false;
   if (!v.poses || !v.frames) return false;
   return true;
@@ -849,7 +860,7 @@ lbm_status lbm_batch_run(lbm_batch *b, int32_t nsteps, int32_t mode, int32_t gra
 
 lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, int32_t *shapes_out) {
   if (!b || reps < 1) return LBM_ERR_ARG;
-  static const int cand[4][2] = {{64, 8}, {128, 4}, {256, 2}, {512, 1}};
+  static const int cand[5][2] = {{64, 8}, {128, 4}, {256, 2}, {512, 1}, {512, 0}};
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return LBM_ERR_DEVICE;
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -863,8 +874,8 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, int32_t *shapes_out) {
     c->stream = b->stream;
     float best = 1e30f;
     int bi = 1;
-    for (int q = 0; q < 4 && st == LBM_OK; ++q) {
-      if (cand[q][0] > (int)align_up((size_t)c->p.nx, 64) && q > 0) continue;
+    for (int q = 0; q < 5 && st == LBM_OK; ++q) {
+      if (cand[q][1] > 0 && cand[q][0] > (int)align_up((size_t)c->p.nx, 64) && q > 0) continue;
       c->bx = cand[q][0];
       c->by = cand[q][1];
       const EnvView v = env_view(c, nullptr);
@@ -902,7 +913,7 @@ lbm_status lbm_batch_set_shapes(lbm_batch *b, const int32_t *shapes) {
   if (!b || !shapes) return LBM_ERR_ARG;
   for (int e = 0; e < b->nenv; ++e) {
     const int bx = shapes[2 * e], by = shapes[2 * e + 1];
-    if (bx < 64 || bx % 64 != 0 || bx * by != WG) return LBM_ERR_ARG;
+    if (!(bx == WG && by == 0) && (bx < 64 || bx % 64 != 0 || bx * by != WG)) return LBM_ERR_ARG;
   }
   for (int e = 0; e < b->nenv; ++e) {
     b->envs[e].ctx->bx = shapes[2 * e];

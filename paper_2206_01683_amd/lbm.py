@@ -50,7 +50,7 @@ class Env(ctypes.Structure):
 
 
 BATCH_PHASES, BATCH_PERSISTENT = 0, 1
-BATCH_SHAPES = ((64, 8), (128, 4), (256, 2), (512, 1))
+BATCH_SHAPES = ((64, 8), (128, 4), (256, 2), (512, 1), (512, 0))  # (512, 0): linear cell order
 
 
 class LBMError(RuntimeError):

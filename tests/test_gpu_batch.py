@@ -113,3 +113,19 @@ def test_batched_environment_against_oracle():
     derr = np.abs(wr[:, 0] - ref["wrench"][:, 0]).max() / np.abs(ref["wrench"][:, 0]).max()
     say(f"batched env {w.nx}x{w.ny}x{w.nz}, {w.markers.n} markers: velocity rel L2 {e:.3e}, force-x max rel {derr:.3e}")
     assert e <= 1e-5 and derr <= 1e-4
+
+
+@pytest.mark.parametrize("mode", ["phases", "persistent"])
+def test_linear_cell_order_matches_row_blocks(mode):
+    """The linear shape (512 consecutive cells per block, rows wrapped) gives
+    the same bits as 2-D row blocks."""
+    envs = _envs(count=3, seed=5)
+    a = lbm.Batch(envs, NSTEPS)
+    a.set_shapes(np.tile(np.array([[512, 0]], np.int32), (3, 1)))
+    a.run(NSTEPS, mode=mode, graph=False)
+    b = lbm.Batch(envs, NSTEPS)
+    b.set_shapes(np.tile(np.array([[64, 8]], np.int32), (3, 1)))
+    b.run(NSTEPS, mode=mode, graph=False)
+    assert a.check() == 0 and b.check() == 0
+    for x, y in zip(_read_all(a), _read_all(b)):
+        assert np.array_equal(x, y)
