@@ -2,7 +2,8 @@
 known size, repeated. Profiled with `rocprofv3 --pmc FETCH_SIZE` (then
 `WRITE_SIZE`), the counters read per copy dispatch, divided by the bytes the
 copy must move (SIZE read, SIZE written), give the factor that turns the same
-counters read on another kernel into bytes.
+counters read on another kernel into bytes. It also prints the copy's own
+read + write bandwidth, a reference ceiling for streaming kernels.
 
     python -m paper_2206_01683_amd.hbm_copy [--mib 1024] [--reps 5]
 """
@@ -21,10 +22,17 @@ def main():
     n = a.mib * (1 << 20) // 4
     src = torch.ones(n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
+    dst.copy_(src)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
     for _ in range(a.reps):
         dst.copy_(src)
+    t1.record()
     torch.cuda.synchronize()
-    print(f"copied {a.mib} MiB x {a.reps}: read {a.mib} MiB and wrote {a.mib} MiB per dispatch", flush=True)
+    ms = t0.elapsed_time(t1) / a.reps
+    gbs = 2 * a.mib * (1 << 20) / (ms * 1e-3) / 1e9
+    print(f"copied {a.mib} MiB x {a.reps}: read {a.mib} MiB and wrote {a.mib} MiB per dispatch, "
+          f"{ms:.3f} ms per copy = {gbs:.0f} GB/s read + write", flush=True)
 
 
 if __name__ == "__main__":
