@@ -73,6 +73,8 @@ def lib():
         L.or_macros.argtypes = [dp, dp, dp, dp, dp]
         L.or_run.argtypes = [dp, dp, dp, dp, dp, ctypes.c_int, dp, dp, dp, dp]
         L.or_run.restype = ctypes.c_int
+        L.or_run_tangent.argtypes = [dp, dp, dp, dp, dp, dp, dp, ctypes.c_int, dp, dp]
+        L.or_run_tangent.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -222,6 +224,30 @@ def run(prm: _Params, f: np.ndarray, frames: np.ndarray, markers=None, poses=Non
     if rc != 0:
         raise OracleError(f"oracle run failed with code {rc}")
     return {"f": f, "wrench": wrench, "X": X, "U": U, "F": F}
+
+
+def run_tangent(prm: _Params, f: np.ndarray, frames: np.ndarray, markers, poses, poses_d, nsteps=None):
+    """Forward-mode tangent of run() along a direction poses_d of the bone
+    poses (initial populations and frames fixed), in dual-number arithmetic.
+    f is advanced in place as by run(). Returns dict with f, f_d (d f), wrench
+    and wrench_d (d wrench), each of the shape run() uses."""
+    f = _f64(f)
+    frames = _f64(frames)
+    if nsteps is None:
+        nsteps = frames.shape[0]
+    keep = []
+    m = _markers(markers, keep)
+    poses = _f64(poses)
+    poses_d = _f64(poses_d)
+    assert poses.shape == poses_d.shape and poses.shape[0] >= nsteps and poses.shape[1] == markers.nbones
+    f_d = np.zeros_like(f)
+    wrench = np.zeros((nsteps, 8))
+    wrench_d = np.zeros((nsteps, 8))
+    rc = lib().or_run_tangent(ctypes.byref(prm), _p(f), _p(f_d), ctypes.byref(m), _p(poses), _p(poses_d), _p(frames),
+                              int(nsteps), _p(wrench), _p(wrench_d))
+    if rc != 0:
+        raise OracleError(f"oracle tangent run failed with code {rc}")
+    return {"f": f, "f_d": f_d, "wrench": wrench, "wrench_d": wrench_d}
 
 
 def initial_populations(rho: np.ndarray, u: np.ndarray) -> np.ndarray:

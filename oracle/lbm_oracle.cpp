@@ -39,6 +39,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -47,6 +48,39 @@
 #endif
 
 namespace {
+
+// ------------------------------------------------------- forward mode ------
+// Dual number v + d e (e^2 = 0): carrying d through every operation gives the
+// exact directional derivative of the computation (forward-mode
+// differentiation). The step below is written once over a scalar type T;
+// T = double is the oracle itself, T = Dual its tangent. Branches (stencil
+// base, kernel support, face tests) depend on values only.
+struct Dual {
+  double v, d;
+  Dual() : v(0.0), d(0.0) {}
+  Dual(double x) : v(x), d(0.0) {}
+  Dual(double x, double dx) : v(x), d(dx) {}
+};
+inline Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+inline Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+inline Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+inline Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+inline Dual operator/(Dual a, Dual b) { return Dual(a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v)); }
+inline Dual operator+(double a, Dual b) { return Dual(a) + b; }
+inline Dual operator+(Dual a, double b) { return a + Dual(b); }
+inline Dual operator-(double a, Dual b) { return Dual(a) - b; }
+inline Dual operator-(Dual a, double b) { return a - Dual(b); }
+inline Dual operator*(double a, Dual b) { return Dual(a * b.v, a * b.d); }
+inline Dual operator*(Dual a, double b) { return Dual(a.v * b, a.d * b); }
+inline Dual operator/(Dual a, double b) { return Dual(a.v / b, a.d / b); }
+inline Dual &operator+=(Dual &a, Dual b) { return a = a + b; }
+inline double val(double x) { return x; }
+inline double val(const Dual &x) { return x.v; }
+inline double tsqrt(double x) { return std::sqrt(x); }
+inline Dual tsqrt(Dual x) {
+  const double r = std::sqrt(x.v);
+  return Dual(r, x.d / (2.0 * r));
+}
 
 // ---------------------------------------------------------------- lattice --
 // D3Q27: velocities c_i in {-1,0,1}^3, index i = (cx+1) + 3(cy+1) + 9(cz+1).
@@ -67,15 +101,17 @@ struct D3Q27 {
 const D3Q27 L;
 
 // Second-order equilibrium f^eq_i = w_i rho [1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u].
-void equilibrium(double rho, const double u[3], double feq[27]) {
-  double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+template <class T>
+void equilibrium(T rho, const T u[3], T feq[27]) {
+  T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   for (int i = 0; i < 27; ++i) {
-    double cu = L.c[i][0] * u[0] + L.c[i][1] * u[1] + L.c[i][2] * u[2];
+    T cu = (double)L.c[i][0] * u[0] + (double)L.c[i][1] * u[1] + (double)L.c[i][2] * u[2];
     feq[i] = L.w[i] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
   }
 }
 
-void cross(const double a[3], const double b[3], double out[3]) {
+template <class A, class B, class C>
+void cross(const A a[3], const B b[3], C out[3]) {
   out[0] = a[1] * b[2] - a[2] * b[1];
   out[1] = a[2] * b[0] - a[0] * b[2];
   out[2] = a[0] * b[1] - a[1] * b[0];
@@ -122,7 +158,114 @@ struct OrMarkers {
   const double *dv;      // [n]  marker volume (surface area share x 1 cell)
 };
 
-int or_abi_version(void) { return 1; }
+}  // extern "C"
+
+namespace {
+
+// Peskin's 4-point smoothed delta function (one axis). C^1, with discrete
+// partition of unity, zero first moment and sum of squares 3/8.
+template <class T>
+T phi(T r) {
+  T a = val(r) < 0.0 ? -r : r;
+  if (val(a) <= 1.0) return (3.0 - 2.0 * a + tsqrt(1.0 + 4.0 * a - 4.0 * a * a)) / 8.0;
+  if (val(a) <= 2.0) return (5.0 - 2.0 * a - tsqrt(-7.0 + 12.0 * a - 4.0 * a * a)) / 8.0;
+  return T(0.0);
+}
+
+// Eq. (3) frame force per unit mass without its velocity-dependent Coriolis
+// part: a0(x) = -acc - alpha x x' - omega x (omega x x'), with x' = x - x0.
+void frame_accel_static(const OrFrame *fr, const double *x, double *a0) {
+  double xp[3] = {x[0] - fr->origin[0], x[1] - fr->origin[1], x[2] - fr->origin[2]};
+  double ax[3], wx[3], wwx[3];
+  cross(fr->alpha, xp, ax);
+  cross(fr->omega, xp, wx);
+  cross(fr->omega, wx, wwx);
+  for (int a = 0; a < 3; ++a) a0[a] = -fr->acc[a] - ax[a] - wwx[a];
+}
+
+// Fluid velocity at a node. With Guo forcing the velocity is
+//   u = (m + F/2) / rho,  F = g + rho * a_ni(x, u),
+// and a_ni (Eq. (3)) contains the Coriolis term -2 omega x u, so u is defined
+// implicitly. Writing b = m/rho + g/(2 rho) + a0/2 the definition reads
+// u + omega x u = b, a 3x3 linear system whose exact solution is
+//   u = (b - omega x b + (omega.b) omega) / (1 + |omega|^2).
+// Returns u and the total force density F used by the collision.
+template <class T>
+void node_velocity(T rho, const T *m, const T *g, const OrFrame *fr, const double *x, T *u, T *F) {
+  double a0[3];
+  frame_accel_static(fr, x, a0);
+  T b[3];
+  for (int a = 0; a < 3; ++a) b[a] = m[a] / rho + g[a] / (2.0 * rho) + 0.5 * a0[a];
+  T wb[3];
+  cross(fr->omega, b, wb);
+  T wdotb = fr->omega[0] * b[0] + fr->omega[1] * b[1] + fr->omega[2] * b[2];
+  double w2 = fr->omega[0] * fr->omega[0] + fr->omega[1] * fr->omega[1] + fr->omega[2] * fr->omega[2];
+  for (int a = 0; a < 3; ++a) u[a] = (b[a] - wb[a] + wdotb * fr->omega[a]) / (1.0 + w2);
+  T wu[3];
+  cross(fr->omega, u, wu);
+  for (int a = 0; a < 3; ++a) F[a] = g[a] + rho * (a0[a] - 2.0 * wu[a]);
+}
+
+// BGK collision with Guo's forcing term at one node:
+//   f*_i = f_i - (f_i - f^eq_i(rho,u)) / tau
+//          + (1 - 1/(2 tau)) w_i [3 (c_i - u) + 9 (c_i.u) c_i] . F.
+template <class T>
+void collide_node(const T *f, const T *g, const OrFrame *fr, const double *x, double tau, T *fout, T *u_out,
+                  T *F_out) {
+  T rho = 0.0, m[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < 27; ++i) {
+    rho += f[i];
+    for (int a = 0; a < 3; ++a) m[a] += f[i] * (double)L.c[i][a];
+  }
+  T u[3], F[3];
+  node_velocity(rho, m, g, fr, x, u, F);
+  T feq[27];
+  equilibrium(rho, u, feq);
+  double pref = 1.0 - 1.0 / (2.0 * tau);
+  for (int i = 0; i < 27; ++i) {
+    T cu = (double)L.c[i][0] * u[0] + (double)L.c[i][1] * u[1] + (double)L.c[i][2] * u[2];
+    T s = 0.0;
+    for (int a = 0; a < 3; ++a) s += (3.0 * ((double)L.c[i][a] - u[a]) + 9.0 * cu * (double)L.c[i][a]) * F[a];
+    fout[i] = f[i] - (f[i] - feq[i]) / tau + pref * L.w[i] * s;
+  }
+  if (u_out)
+    for (int a = 0; a < 3; ++a) u_out[a] = u[a];
+  if (F_out)
+    for (int a = 0; a < 3; ++a) F_out[a] = F[a];
+}
+
+// Linear blend skinning (Sec. III-A): X = sum_b w_b (R_b xrest + t_b) and
+// U = sum_b w_b (Rdot_b xrest + tdot_b). A bone pose is 24 numbers: R (3x3,
+// row-major), t (3), Rdot (3x3, row-major), tdot (3).
+template <class T>
+void skin(const OrMarkers *mk, const T *poses, T *X, T *U) {
+  const int n = mk->n;
+  for (int k = 0; k < n; ++k) {
+    double xr[3] = {mk->xrest[k], mk->xrest[n + k], mk->xrest[2 * n + k]};
+    T x[3] = {0.0, 0.0, 0.0}, v[3] = {0.0, 0.0, 0.0};
+    for (int j = 0; j < 2; ++j) {
+      int b = mk->bone[j * n + k];
+      double wgt = mk->weight[j * n + k];
+      const T *P = poses + 24 * b;
+      for (int a = 0; a < 3; ++a) {
+        T px = P[3 * a] * xr[0] + P[3 * a + 1] * xr[1] + P[3 * a + 2] * xr[2] + P[9 + a];
+        T pv = P[12 + 3 * a] * xr[0] + P[12 + 3 * a + 1] * xr[1] + P[12 + 3 * a + 2] * xr[2] + P[21 + a];
+        x[a] += wgt * px;
+        v[a] += wgt * pv;
+      }
+    }
+    for (int a = 0; a < 3; ++a) {
+      X[a * n + k] = x[a];
+      U[a * n + k] = v[a];
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int or_abi_version(void) { return 2; }
 
 // Threads a parallel lattice sweep uses.
 int or_threads(void) {
@@ -152,101 +295,21 @@ void or_equilibrium_field(const double *rho, const double *u, int64_t n, double 
   }
 }
 
-// Peskin's 4-point smoothed delta function (one axis). C^1, with discrete
-// partition of unity, zero first moment and sum of squares 3/8.
-double or_phi(double r) {
-  double a = std::fabs(r);
-  if (a <= 1.0) return (3.0 - 2.0 * a + std::sqrt(1.0 + 4.0 * a - 4.0 * a * a)) / 8.0;
-  if (a <= 2.0) return (5.0 - 2.0 * a - std::sqrt(-7.0 + 12.0 * a - 4.0 * a * a)) / 8.0;
-  return 0.0;
+double or_phi(double r) { return phi(r); }
+
+void or_frame_accel_static(const OrFrame *fr, const double *x, double *a0) { frame_accel_static(fr, x, a0); }
+
+void or_node_velocity(double rho, const double *m, const double *g, const OrFrame *fr, const double *x, double *u,
+                      double *F) {
+  node_velocity(rho, m, g, fr, x, u, F);
 }
 
-// Eq. (3) frame force per unit mass without its velocity-dependent Coriolis
-// part: a0(x) = -acc - alpha x x' - omega x (omega x x'), with x' = x - x0.
-void or_frame_accel_static(const OrFrame *fr, const double *x, double *a0) {
-  double xp[3] = {x[0] - fr->origin[0], x[1] - fr->origin[1], x[2] - fr->origin[2]};
-  double ax[3], wx[3], wwx[3];
-  cross(fr->alpha, xp, ax);
-  cross(fr->omega, xp, wx);
-  cross(fr->omega, wx, wwx);
-  for (int a = 0; a < 3; ++a) a0[a] = -fr->acc[a] - ax[a] - wwx[a];
+void or_collide_node(const double *f, const double *g, const OrFrame *fr, const double *x, double tau, double *fout,
+                     double *u_out, double *F_out) {
+  collide_node(f, g, fr, x, tau, fout, u_out, F_out);
 }
 
-// Fluid velocity at a node. With Guo forcing the velocity is
-//   u = (m + F/2) / rho,  F = g + rho * a_ni(x, u),
-// and a_ni (Eq. (3)) contains the Coriolis term -2 omega x u, so u is defined
-// implicitly. Writing b = m/rho + g/(2 rho) + a0/2 the definition reads
-// u + omega x u = b, a 3x3 linear system whose exact solution is
-//   u = (b - omega x b + (omega.b) omega) / (1 + |omega|^2).
-// Returns u and the total force density F used by the collision.
-void or_node_velocity(double rho, const double *m, const double *g, const OrFrame *fr,
-                      const double *x, double *u, double *F) {
-  double a0[3];
-  or_frame_accel_static(fr, x, a0);
-  double b[3];
-  for (int a = 0; a < 3; ++a) b[a] = m[a] / rho + g[a] / (2.0 * rho) + 0.5 * a0[a];
-  double wb[3];
-  cross(fr->omega, b, wb);
-  double wdotb = fr->omega[0] * b[0] + fr->omega[1] * b[1] + fr->omega[2] * b[2];
-  double w2 = fr->omega[0] * fr->omega[0] + fr->omega[1] * fr->omega[1] + fr->omega[2] * fr->omega[2];
-  for (int a = 0; a < 3; ++a) u[a] = (b[a] - wb[a] + wdotb * fr->omega[a]) / (1.0 + w2);
-  double wu[3];
-  cross(fr->omega, u, wu);
-  for (int a = 0; a < 3; ++a) F[a] = g[a] + rho * (a0[a] - 2.0 * wu[a]);
-}
-
-// BGK collision with Guo's forcing term at one node:
-//   f*_i = f_i - (f_i - f^eq_i(rho,u)) / tau
-//          + (1 - 1/(2 tau)) w_i [3 (c_i - u) + 9 (c_i.u) c_i] . F.
-void or_collide_node(const double *f, const double *g, const OrFrame *fr, const double *x, double tau,
-                     double *fout, double *u_out, double *F_out) {
-  double rho = 0.0, m[3] = {0.0, 0.0, 0.0};
-  for (int i = 0; i < 27; ++i) {
-    rho += f[i];
-    for (int a = 0; a < 3; ++a) m[a] += f[i] * L.c[i][a];
-  }
-  double u[3], F[3];
-  or_node_velocity(rho, m, g, fr, x, u, F);
-  double feq[27];
-  equilibrium(rho, u, feq);
-  double pref = 1.0 - 1.0 / (2.0 * tau);
-  for (int i = 0; i < 27; ++i) {
-    double cu = L.c[i][0] * u[0] + L.c[i][1] * u[1] + L.c[i][2] * u[2];
-    double s = 0.0;
-    for (int a = 0; a < 3; ++a) s += (3.0 * (L.c[i][a] - u[a]) + 9.0 * cu * L.c[i][a]) * F[a];
-    fout[i] = f[i] - (f[i] - feq[i]) / tau + pref * L.w[i] * s;
-  }
-  if (u_out)
-    for (int a = 0; a < 3; ++a) u_out[a] = u[a];
-  if (F_out)
-    for (int a = 0; a < 3; ++a) F_out[a] = F[a];
-}
-
-// Linear blend skinning (Sec. III-A): X = sum_b w_b (R_b xrest + t_b) and
-// U = sum_b w_b (Rdot_b xrest + tdot_b). A bone pose is 24 numbers: R (3x3,
-// row-major), t (3), Rdot (3x3, row-major), tdot (3).
-void or_skin(const OrMarkers *mk, const double *poses, double *X, double *U) {
-  const int n = mk->n;
-  for (int k = 0; k < n; ++k) {
-    double xr[3] = {mk->xrest[k], mk->xrest[n + k], mk->xrest[2 * n + k]};
-    double x[3] = {0, 0, 0}, v[3] = {0, 0, 0};
-    for (int j = 0; j < 2; ++j) {
-      int b = mk->bone[j * n + k];
-      double wgt = mk->weight[j * n + k];
-      const double *P = poses + 24 * b;
-      for (int a = 0; a < 3; ++a) {
-        double px = P[3 * a] * xr[0] + P[3 * a + 1] * xr[1] + P[3 * a + 2] * xr[2] + P[9 + a];
-        double pv = P[12 + 3 * a] * xr[0] + P[12 + 3 * a + 1] * xr[1] + P[12 + 3 * a + 2] * xr[2] + P[21 + a];
-        x[a] += wgt * px;
-        v[a] += wgt * pv;
-      }
-    }
-    for (int a = 0; a < 3; ++a) {
-      X[a * n + k] = x[a];
-      U[a * n + k] = v[a];
-    }
-  }
-}
+void or_skin(const OrMarkers *mk, const double *poses, double *X, double *U) { skin(mk, poses, X, U); }
 
 }  // extern "C"
 
@@ -264,14 +327,15 @@ struct Grid {
 // The 4x4x4 stencil of a marker: nodes floor(X)-1 .. floor(X)+2 per axis,
 // indices wrapped on periodic axes. Returns false if a node falls outside a
 // non-periodic axis (the caller rejects such markers beforehand).
-bool stencil(const Grid &G, const double X[3], int nodes[3][4], double wts[3][4]) {
+template <class T>
+bool stencil(const Grid &G, const T X[3], int nodes[3][4], T wts[3][4]) {
   int n[3] = {G.nx, G.ny, G.nz};
   bool per[3] = {G.xper, true, true};
   for (int a = 0; a < 3; ++a) {
-    int base = (int)std::floor(X[a]) - 1;
+    int base = (int)std::floor(val(X[a])) - 1;
     for (int s = 0; s < 4; ++s) {
       int j = base + s;
-      wts[a][s] = or_phi(X[a] - (double)j);
+      wts[a][s] = phi(X[a] - (double)j);
       if (per[a]) {
         j = wrap(j, n[a]);
       } else if (j < 0 || j >= n[a]) {
@@ -285,17 +349,18 @@ bool stencil(const Grid &G, const double X[3], int nodes[3][4], double wts[3][4]
 
 // U_k = sum over the stencil of field(x) delta_h(x - X_k), delta_h the
 // tensor product of phi. field is [ncomp][cells].
-void interpolate(const Grid &G, const double *field, int ncomp, const double *X, int n, double *out) {
+template <class T>
+void interpolate(const Grid &G, const T *field, int ncomp, const T *X, int n, T *out) {
   for (int k = 0; k < n; ++k) {
-    double Xk[3] = {X[k], X[n + k], X[2 * n + k]};
+    T Xk[3] = {X[k], X[n + k], X[2 * n + k]};
     int nodes[3][4];
-    double w[3][4];
+    T w[3][4];
     stencil(G, Xk, nodes, w);
     for (int c = 0; c < ncomp; ++c) out[c * n + k] = 0.0;
     for (int sz = 0; sz < 4; ++sz)
       for (int sy = 0; sy < 4; ++sy)
         for (int sx = 0; sx < 4; ++sx) {
-          double d = w[0][sx] * w[1][sy] * w[2][sz];
+          T d = w[0][sx] * w[1][sy] * w[2][sz];
           size_t id = G.idx(nodes[0][sx], nodes[1][sy], nodes[2][sz]);
           for (int c = 0; c < ncomp; ++c) out[c * n + k] += field[c * G.ncell() + id] * d;
         }
@@ -304,17 +369,18 @@ void interpolate(const Grid &G, const double *field, int ncomp, const double *X,
 
 // g(x) = sum_k Fdv_k delta_h(x - X_k), with Fdv = F_k dV_k. g is [3][cells]
 // and is overwritten.
-void spread(const Grid &G, const double *X, int n, const double *Fdv, double *g) {
-  std::memset(g, 0, sizeof(double) * 3 * G.ncell());
+template <class T>
+void spread(const Grid &G, const T *X, int n, const T *Fdv, T *g) {
+  std::fill(g, g + 3 * G.ncell(), T(0.0));
   for (int k = 0; k < n; ++k) {
-    double Xk[3] = {X[k], X[n + k], X[2 * n + k]};
+    T Xk[3] = {X[k], X[n + k], X[2 * n + k]};
     int nodes[3][4];
-    double w[3][4];
+    T w[3][4];
     stencil(G, Xk, nodes, w);
     for (int sz = 0; sz < 4; ++sz)
       for (int sy = 0; sy < 4; ++sy)
         for (int sx = 0; sx < 4; ++sx) {
-          double d = w[0][sx] * w[1][sy] * w[2][sz];
+          T d = w[0][sx] * w[1][sy] * w[2][sz];
           size_t id = G.idx(nodes[0][sx], nodes[1][sy], nodes[2][sz]);
           for (int c = 0; c < 3; ++c) g[c * G.ncell() + id] += Fdv[c * n + k] * d;
         }
@@ -323,25 +389,26 @@ void spread(const Grid &G, const double *X, int n, const double *Fdv, double *g)
 
 // Density, momentum and the velocity with force field g (no g: pass zeros)
 // at every node. rho is [cells], u is [3][cells].
-void node_fields(const Grid &G, const double *f, const double *g, const OrFrame *fr, double *rho, double *u) {
+template <class T>
+void node_fields(const Grid &G, const T *f, const T *g, const OrFrame *fr, T *rho, T *u) {
   const size_t N = G.ncell();
 #pragma omp parallel for schedule(static)
   for (int z = 0; z < G.nz; ++z)
     for (int y = 0; y < G.ny; ++y)
       for (int x = 0; x < G.nx; ++x) {
         size_t id = G.idx(x, y, z);
-        double r = 0.0, m[3] = {0, 0, 0};
+        T r = 0.0, m[3] = {0.0, 0.0, 0.0};
         for (int i = 0; i < 27; ++i) {
-          double fi = f[i * N + id];
+          T fi = f[i * N + id];
           r += fi;
-          for (int a = 0; a < 3; ++a) m[a] += fi * L.c[i][a];
+          for (int a = 0; a < 3; ++a) m[a] += fi * (double)L.c[i][a];
         }
-        double gg[3] = {0, 0, 0};
+        T gg[3] = {0.0, 0.0, 0.0};
         if (g)
           for (int a = 0; a < 3; ++a) gg[a] = g[a * N + id];
         double pos[3] = {(double)x, (double)y, (double)z};
-        double uu[3], F[3];
-        or_node_velocity(r, m, gg, fr, pos, uu, F);
+        T uu[3], F[3];
+        node_velocity(r, m, gg, fr, pos, uu, F);
         rho[id] = r;
         for (int a = 0; a < 3; ++a) u[a * N + id] = uu[a];
       }
@@ -372,9 +439,13 @@ int or_spread(const OrParams *p, const double *X, int n, const double *Fdv, doub
 // the step interpolates to the markers and the one reported as "the velocity".
 int or_macros(const OrParams *p, const double *f, const OrFrame *fr, double *rho, double *u) {
   Grid G{p->nx, p->ny, p->nz, p->bc_lo == OR_BC_PERIODIC};
-  node_fields(G, f, nullptr, fr, rho, u);
+  node_fields(G, f, (const double *)nullptr, fr, rho, u);
   return 0;
 }
+
+}  // extern "C"
+
+namespace {
 
 // Advance the pre-collision populations f [27][nz][ny][nx] by nsteps steps.
 //   poses  : [nsteps][nbones][24] bone poses for each step (may be null when
@@ -386,8 +457,9 @@ int or_macros(const OrParams *p, const double *f, const OrFrame *fr, double *rho
 //            force densities of the LAST step
 // Returns 0, or -4 when a marker's stencil leaves the domain across an open
 // face, or -1 on bad arguments.
-int or_run(const OrParams *p, double *f, const OrMarkers *mk, const double *poses, const OrFrame *frames,
-           int nsteps, double *wrench, double *Xout, double *Uout, double *Fout) {
+template <class T>
+int run(const OrParams *p, T *f, const OrMarkers *mk, const T *poses, const OrFrame *frames, int nsteps, T *wrench,
+        T *Xout, T *Uout, T *Fout) {
   if (!p || !f || p->nx < 4 || p->ny < 4 || p->nz < 4 || !(p->tau > 0.5)) return -1;
   const bool xper = p->bc_lo == OR_BC_PERIODIC;
   if (xper != (p->bc_hi == OR_BC_PERIODIC)) return -1;
@@ -397,26 +469,26 @@ int or_run(const OrParams *p, double *f, const OrMarkers *mk, const double *pose
   const double tau = p->tau;
   const int nm = mk ? mk->n : 0;
 
-  std::vector<double> fpost(27 * N), rho(N), ustar(3 * N), g(3 * N, 0.0);
-  std::vector<double> X(3 * nm), U(3 * nm), Fk(3 * nm), Fdv(3 * nm), Ustar(3 * nm), rhok(nm), Uk(3 * nm);
-  std::vector<double> ufull(3 * N);
+  std::vector<T> fpost(27 * N), rho(N), ustar(3 * N), g(3 * N, T(0.0));
+  std::vector<T> X(3 * nm), U(3 * nm), Fk(3 * nm), Fdv(3 * nm), Ustar(3 * nm), rhok(nm), Uk(3 * nm);
+  std::vector<T> ufull(3 * N);
 
   for (int step = 0; step < nsteps; ++step) {
     const OrFrame *fr = &frames[step];
 
     // (1) marker positions and velocities for this step
     if (nm > 0) {
-      or_skin(mk, poses + (size_t)step * mk->nbones * 24, X.data(), U.data());
+      skin(mk, poses + (size_t)step * mk->nbones * 24, X.data(), U.data());
       if (!xper)
         for (int k = 0; k < nm; ++k)
-          if (!(X[k] >= 2.0 && X[k] < p->nx - 3.0)) return -4;
+          if (!(val(X[k]) >= 2.0 && val(X[k]) < p->nx - 3.0)) return -4;
     }
 
     // (2) density and unforced velocity at every node
-    node_fields(G, f, nullptr, fr, rho.data(), ustar.data());
+    node_fields(G, (const T *)f, (const T *)nullptr, fr, rho.data(), ustar.data());
 
     // (3)-(5) interpolation, direct forcing, spreading
-    std::fill(g.begin(), g.end(), 0.0);
+    std::fill(g.begin(), g.end(), T(0.0));
     if (nm > 0) {
       interpolate(G, ustar.data(), 3, X.data(), nm, Ustar.data());
       interpolate(G, rho.data(), 1, X.data(), nm, rhok.data());
@@ -447,11 +519,11 @@ int or_run(const OrParams *p, double *f, const OrMarkers *mk, const double *pose
         for (int x = 0; x < G.nx; ++x) {
           if (is_open_plane(G, x)) continue;
           size_t id = G.idx(x, y, z);
-          double fl[27], fo[27];
+          T fl[27], fo[27];
           for (int i = 0; i < 27; ++i) fl[i] = f[i * N + id];
-          double gg[3] = {g[id], g[N + id], g[2 * N + id]};
+          T gg[3] = {g[id], g[N + id], g[2 * N + id]};
           double pos[3] = {(double)x, (double)y, (double)z};
-          or_collide_node(fl, gg, fr, pos, tau, fo, nullptr, nullptr);
+          collide_node(fl, gg, fr, pos, tau, fo, (T *)nullptr, (T *)nullptr);
           for (int i = 0; i < 27; ++i) fpost[i * N + id] = fo[i];
         }
 
@@ -473,31 +545,33 @@ int or_run(const OrParams *p, double *f, const OrMarkers *mk, const double *pose
         for (int z = 0; z < G.nz; ++z)
           for (int y = 0; y < G.ny; ++y) {
             size_t idf = G.idx(xf, y, z), idb = G.idx(xb, y, z);
-            double fl[27], r = 0.0, m[3] = {0, 0, 0};
+            T fl[27], r = 0.0, m[3] = {0.0, 0.0, 0.0};
             for (int i = 0; i < 27; ++i) {
               fl[i] = f[i * N + idf];
               r += fl[i];
-              for (int a = 0; a < 3; ++a) m[a] += fl[i] * L.c[i][a];
+              for (int a = 0; a < 3; ++a) m[a] += fl[i] * (double)L.c[i][a];
             }
-            double gf[3] = {g[idf], g[N + idf], g[2 * N + idf]};
+            T gf[3] = {g[idf], g[N + idf], g[2 * N + idf]};
             double posf[3] = {(double)xf, (double)y, (double)z};
             double posb[3] = {(double)xb, (double)y, (double)z};
-            double uf[3], Ff[3];
-            or_node_velocity(r, m, gf, fr, posf, uf, Ff);
-            double ub[3];
-            for (int a = 0; a < 3; ++a) ub[a] = (bc == OR_BC_VELOCITY) ? uface[a] : uf[a];
-            double a0[3], wu[3], Fb[3];
-            or_frame_accel_static(fr, posb, a0);
+            T uf[3], Ff[3];
+            node_velocity(r, m, gf, fr, posf, uf, Ff);
+            T ub[3];
+            for (int a = 0; a < 3; ++a) ub[a] = (bc == OR_BC_VELOCITY) ? T(uface[a]) : uf[a];
+            double a0[3];
+            T wu[3], Fb[3];
+            frame_accel_static(fr, posb, a0);
             cross(fr->omega, ub, wu);
             for (int a = 0; a < 3; ++a) Fb[a] = r * (a0[a] - 2.0 * wu[a]);
-            double feq_b[27], feq_f[27];
+            T feq_b[27], feq_f[27];
             equilibrium(r, ub, feq_b);
             equilibrium(r, uf, feq_f);
             double pref = 1.0 - 1.0 / (2.0 * tau);
             for (int i = 0; i < 27; ++i) {
-              double cu = L.c[i][0] * ub[0] + L.c[i][1] * ub[1] + L.c[i][2] * ub[2];
-              double s = 0.0;
-              for (int a = 0; a < 3; ++a) s += (3.0 * (L.c[i][a] - ub[a]) + 9.0 * cu * L.c[i][a]) * Fb[a];
+              T cu = (double)L.c[i][0] * ub[0] + (double)L.c[i][1] * ub[1] + (double)L.c[i][2] * ub[2];
+              T s = 0.0;
+              for (int a = 0; a < 3; ++a)
+                s += (3.0 * ((double)L.c[i][a] - ub[a]) + 9.0 * cu * (double)L.c[i][a]) * Fb[a];
               fpost[i * N + idb] = feq_b[i] + (1.0 - 1.0 / tau) * (fl[i] - feq_f[i]) + pref * L.w[i] * s;
             }
           }
@@ -523,12 +597,12 @@ int or_run(const OrParams *p, double *f, const OrMarkers *mk, const double *pose
     // (9) the fluid's force, torque and power on the body: the body exerts
     // F_k dV_k on the fluid, so the fluid exerts the opposite on the body.
     if (wrench) {
-      double *wr = wrench + 8 * (size_t)step;
+      T *wr = wrench + 8 * (size_t)step;
       for (int j = 0; j < 8; ++j) wr[j] = 0.0;
       for (int k = 0; k < nm; ++k) {
-        double Fb[3] = {-Fdv[k], -Fdv[nm + k], -Fdv[2 * nm + k]};
-        double r[3] = {X[k] - fr->origin[0], X[nm + k] - fr->origin[1], X[2 * nm + k] - fr->origin[2]};
-        double t[3];
+        T Fb[3] = {-Fdv[k], -Fdv[nm + k], -Fdv[2 * nm + k]};
+        T r[3] = {X[k] - fr->origin[0], X[nm + k] - fr->origin[1], X[2 * nm + k] - fr->origin[2]};
+        T t[3];
         cross(r, Fb, t);
         for (int a = 0; a < 3; ++a) {
           wr[a] += Fb[a];
@@ -539,11 +613,48 @@ int or_run(const OrParams *p, double *f, const OrMarkers *mk, const double *pose
     }
   }
   if (nm > 0) {
-    if (Xout) std::memcpy(Xout, X.data(), sizeof(double) * 3 * nm);
-    if (Uout) std::memcpy(Uout, U.data(), sizeof(double) * 3 * nm);
-    if (Fout) std::memcpy(Fout, Fk.data(), sizeof(double) * 3 * nm);
+    if (Xout) std::copy(X.begin(), X.end(), Xout);
+    if (Uout) std::copy(U.begin(), U.end(), Uout);
+    if (Fout) std::copy(Fk.begin(), Fk.end(), Fout);
   }
   return 0;
+}
+
+
+}  // namespace
+
+extern "C" {
+
+int or_run(const OrParams *p, double *f, const OrMarkers *mk, const double *poses, const OrFrame *frames,
+           int nsteps, double *wrench, double *Xout, double *Uout, double *Fout) {
+  return run(p, f, mk, poses, frames, nsteps, wrench, Xout, Uout, Fout);
+}
+
+// Forward-mode tangent of or_run with respect to the bone poses: the same
+// step in dual numbers, with the initial populations and the frames held
+// fixed. poses_d [nsteps][nbones][24] is the direction (d pose / d theta for
+// a parameter theta); f is advanced in place as by or_run, f_d [27][cells]
+// receives d f / d theta, wrench and wrench_d [nsteps][8] the wrench and its
+// derivative. Same return codes as or_run.
+int or_run_tangent(const OrParams *p, double *f, double *f_d, const OrMarkers *mk, const double *poses,
+                   const double *poses_d, const OrFrame *frames, int nsteps, double *wrench, double *wrench_d) {
+  if (!p || !f || !mk || !poses || !poses_d || !frames || nsteps < 0) return -1;
+  const size_t N = (size_t)p->nx * p->ny * p->nz;
+  const size_t np = (size_t)nsteps * mk->nbones * 24;
+  std::vector<Dual> fd(27 * N), pd(np), wd(8 * (size_t)nsteps);
+  for (size_t q = 0; q < 27 * N; ++q) fd[q] = Dual(f[q]);
+  for (size_t q = 0; q < np; ++q) pd[q] = Dual(poses[q], poses_d[q]);
+  const int rc = run(p, fd.data(), mk, pd.data(), frames, nsteps, wd.data(), (Dual *)nullptr, (Dual *)nullptr,
+                     (Dual *)nullptr);
+  for (size_t q = 0; q < 27 * N; ++q) {
+    f[q] = fd[q].v;
+    if (f_d) f_d[q] = fd[q].d;
+  }
+  for (size_t q = 0; q < 8 * (size_t)nsteps; ++q) {
+    if (wrench) wrench[q] = wd[q].v;
+    if (wrench_d) wrench_d[q] = wd[q].d;
+  }
+  return rc;
 }
 
 }  // extern "C"
