@@ -195,6 +195,30 @@ lbm_status lbm_adjoint_step(lbm_ctx *c, const void *state, const lbm_markers *m,
                             const lbm_frame *frame, const double *w, const void *lam_next, void *lam_prev,
                             float *pose_bar);
 
+/* Bytes of the immersed-boundary ring lbm_adjoint_segment needs for nseg
+ * steps: per step, the marker state, tile map and band data of the forward
+ * IB phases (sized by max_markers and the active-tile capacity). 0 on
+ * invalid parameters. */
+size_t lbm_adjoint_ring_bytes(const lbm_params *p, int32_t nseg);
+
+/* Reverse sweep over one checkpointed segment of nseg steps, natively: from
+ * ckpt (the state before the segment's first step, stored layout) the
+ * segment is recomputed into ring[0..nseg-2] (caller-owned state buffers:
+ * ring[t] receives the state after step t), keeping each step's forward IB
+ * data in ib_ring (lbm_adjoint_ring_bytes(p, nseg) bytes, 256-byte aligned);
+ * then lbm_adjoint_step's passes run for steps nseg-1 .. 0 without
+ * recomputing the IB phases. poses [nseg][nbones][24], frames [host, nseg],
+ * w [host] 4 doubles (the same weights each step), pose_bar [nseg][nbones][24]
+ * (added into). lam holds dJ/d(state after the segment) on entry and
+ * dJ/d(ckpt) on return; lam_tmp is scratch of the same size. ckpt, the ring
+ * entries, lam and lam_tmp must be distinct. The context's own state and step
+ * count are not touched. Same support as lbm_adjoint_step. The gradient is
+ * the same as that of nseg lbm_adjoint_step calls on the recomputed states
+ * (Sec. III-A skinning and Sec. III-B coupled step, differentiated). */
+lbm_status lbm_adjoint_segment(lbm_ctx *c, const void *ckpt, void *const *ring, int32_t nseg, const lbm_markers *m,
+                               const float *poses, const lbm_frame *frames, const double *w, void *lam,
+                               void *lam_tmp, float *pose_bar, void *ib_ring);
+
 /* Fluid force on the body from the markers' last forces F (the external
  * generalized force of Eq. (1)). out [(1 + m->nbones)][8]: row 0 is the whole
  * body, row 1 + b the share of bone b (each marker's force split by its blend

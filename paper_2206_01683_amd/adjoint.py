@@ -8,12 +8,12 @@ generalized force of Eq. (1) and the coupled step of Sec. III-B):
 
 `forward` runs the steps on the GPU from the simulation's current state and
 keeps a copy of the populations every `every` steps. `backward` walks the
-segments from last to first: it recomputes a segment from its checkpoint
-straight into a ring of states (the context's two population buffers are
-rebound, so nothing is copied), then applies lbm_adjoint_step in reverse,
-which carries lambda = dJ/d(state) back one step and accumulates the step's
+segments from last to first: lbm_adjoint_segment recomputes a segment from
+its checkpoint straight into a ring of states, keeping every step's forward
+immersed-boundary data, then runs the adjoint passes in reverse, which carry
+lambda = dJ/d(state) back one step at a time and accumulate each step's
 dJ/d(bone pose). Memory: ceil(nsteps / every) checkpoints, every - 1 ring
-states and two adjoint states.
+states, the IB ring of `every` steps and two adjoint states.
 
 `FinObjective` is a torch.autograd.Function from the 8 kinematics parameters
 of the swimmer to J: each step's bone poses are an analytic function of the
@@ -75,11 +75,17 @@ def forward(sim: "lbm.Simulation", markers: Optional["lbm.DeviceMarkers"], poses
 
 
 def backward(sim: "lbm.Simulation", markers: Optional["lbm.DeviceMarkers"], poses: Optional[torch.Tensor],
-             frames: np.ndarray, tape: Tape, lam_final: Optional[torch.Tensor] = None):
+             frames: np.ndarray, tape: Tape, lam_final: Optional[torch.Tensor] = None, native: bool = True):
     """Reverse sweep over the tape. Returns (pose_bar, lam0): dJ/d(pose of
     step n) as (nsteps, nbones, 24) float32 (None without markers) and
     dJ/d(initial state) in the stored layout (float32 view). The context ends
-    at the state and step count `forward` left it in."""
+    at the state and step count `forward` left it in.
+
+    native: each segment is one lbm_adjoint_segment call (recompute with the
+    forward IB data of every step kept, then the reverse passes); otherwise a
+    per-step loop here (recompute by rebinding the context's buffers, then
+    lbm_adjoint_step per step, which recomputes the step's IB data). Both
+    give the same bits."""
     frames = np.asarray(frames, dtype=np.float64).reshape(-1, 18)
     n, k = tape.nsteps, tape.every
     nfl = sim.population_bytes // 4
@@ -92,6 +98,14 @@ def backward(sim: "lbm.Simulation", markers: Optional["lbm.DeviceMarkers"], pose
     if markers is not None:
         pose_bar = torch.zeros((n, markers.nbones, 24), dtype=torch.float32, device=dev)
     ring = [sim.new_state() for _ in range(min(k, n) - 1)]
+    if native:
+        ib_ring = sim.adjoint_ring(min(k, n))
+        for j in reversed(range(len(tape.checkpoints))):
+            s, e = j * k, min(n, (j + 1) * k)
+            sim.adjoint_segment(tape.checkpoints[j], ring, markers, None if markers is None else poses[s:e],
+                                frames[s:e], tape.weights, lam, lam2, None if pose_bar is None else pose_bar[s:e],
+                                ib_ring)
+        return pose_bar, lam
     scratch = torch.zeros((1, 8), dtype=torch.float32, device=dev)
     for j in reversed(range(len(tape.checkpoints))):
         s, e = j * k, min(n, (j + 1) * k)
@@ -114,7 +128,8 @@ class FinProblem:
     from the inflow-velocity initial state, for kinematics parameters theta.
     The default weights (heading, 0) give the time-averaged thrust."""
 
-    def __init__(self, nsteps: int = 400, every: int = 20, weights=None, device="cuda", **geometry):
+    def __init__(self, nsteps: int = 400, every: int = 20, weights=None, device="cuda", max_active_tiles=256,
+                 **geometry):
         w = I.fin_workload(I.C5_BASE, nsteps=nsteps, **geometry)
         self.workload = w
         self.nsteps, self.every = nsteps, every
@@ -125,7 +140,7 @@ class FinProblem:
         ms = w.markers
         self.sim = lbm.Simulation(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi, max_markers=ms.n,
                                   max_bones=ms.nbones, u0=w.u0.astype(np.float32), device=device,
-                                  with_adjoint=True)
+                                  with_adjoint=True, max_active_tiles=max_active_tiles)
         self.s0 = self.sim.new_state()
         self.sim.save_state(self.s0)
         self.markers = lbm.DeviceMarkers(ms, device=device)

@@ -480,33 +480,38 @@ lbm_status lbm_bind_populations(lbm_ctx *c, void *f_cur, void *f_next) {
   return LBM_OK;
 }
 
-lbm_status lbm_adjoint_step(lbm_ctx *c, const void *state, const lbm_markers *m, const float *pose,
-                            const lbm_frame *frame, const double *w, const void *lam_next, void *lam_prev,
-                            float *pose_bar) {
-  if (!c || !state || !frame || !w || !lam_next || !lam_prev || lam_next == lam_prev) return LBM_ERR_ARG;
-  if (!markers_ok(c, m) || !frame_ok(frame)) return LBM_ERR_ARG;
+}  // extern "C"
+
+namespace {
+
+// Checks shared by the adjoint entry points; LBM_OK when the request is valid.
+lbm_status adjoint_request_ok(const lbm_ctx *c, const lbm_markers *m, const float *pose, const double *w,
+                              float *pose_bar) {
+  if (!markers_ok(c, m)) return LBM_ERR_ARG;
   const bool ib = m && m->n > 0;
   if (ib && (!pose || !pose_bar)) return LBM_ERR_ARG;
   if (ib && m->n > c->p.max_markers) return LBM_ERR_CAPACITY;
   for (int q = 0; q < 4; ++q)
     if (!std::isfinite(w[q])) return LBM_ERR_ARG;
-  if (c->p.storage != LBM_STORE_F32 || c->p.mdf_iters != 1 || !c->p.with_adjoint || rotating(frame))
-    return LBM_ERR_UNSUPPORTED;
-  EnvView e = env_view(c, m);
-  e.f[0] = const_cast<void *>(state);
-  e.f[1] = nullptr;
-  const FrameF fr = frame_f(frame);
-  lbm_status st;
-  // forward immersed-boundary phases of this step, from `state`
-  if (ib) {
-    k_skin_mark<<<skin_items(e.n), WG, 0, c->stream>>>(e, pose);
-    k_active<<<(e.ntiles + WG - 1) / WG, WG, 0, c->stream>>>(e);
-    k_macro<StoreF32, false><<<std::min(c->L.cap, 2048), WG, 0, c->stream>>>(e, fr, 0);
-    k_interp<false, false><<<interp_items(e.n), WG, 0, c->stream>>>(e, fr, nullptr);
-    k_spread<<<std::min(c->L.cap * kSpreadSplit, 2048), WG, 0, c->stream>>>(e, nullptr);
-    if ((st = launched()) != LBM_OK) return st;
-    c->slots_dirty = true;
-  }
+  if (c->p.storage != LBM_STORE_F32 || c->p.mdf_iters != 1 || !c->p.with_adjoint) return LBM_ERR_UNSUPPORTED;
+  return LBM_OK;
+}
+
+// Forward immersed-boundary phases of one step (one direct-forcing pass), from
+// the state in e.f[0], into the IB arrays e points at.
+lbm_status ib_forward(lbm_ctx *c, const EnvView &e, const FrameF &fr, const float *pose) {
+  k_skin_mark<<<skin_items(e.n), WG, 0, c->stream>>>(e, pose);
+  k_active<<<(e.ntiles + WG - 1) / WG, WG, 0, c->stream>>>(e);
+  k_macro<StoreF32, false><<<std::min(c->L.cap, 2048), WG, 0, c->stream>>>(e, fr, 0);
+  k_interp<false, false><<<interp_items(e.n), WG, 0, c->stream>>>(e, fr, nullptr);
+  k_spread<<<std::min(c->L.cap * kSpreadSplit, 2048), WG, 0, c->stream>>>(e, nullptr);
+  return launched();
+}
+
+// The adjoint passes of one step whose forward IB data e points at (state in
+// e.f[0]): lam_next -> lam_prev, pose_bar += the step's pose adjoint.
+lbm_status adjoint_passes(lbm_ctx *c, const EnvView &e, const FrameF &fr, const double *w, const float *lam_next,
+                          float *lam_prev, float *pose_bar) {
   AdjArgs A{};
   for (int a = 0; a < 3; ++a) {
     A.wF[a] = (float)w[a];
@@ -515,13 +520,14 @@ lbm_status lbm_adjoint_step(lbm_ctx *c, const void *state, const lbm_markers *m,
     A.bc_u_hi[a] = fr.uhi[a];
   }
   A.wP = (float)w[3];
-  A.lam_next = static_cast<const float *>(lam_next);
-  A.lam_prev = static_cast<float *>(lam_prev);
+  A.lam_next = lam_next;
+  A.lam_prev = lam_prev;
   A.gbar = wsp<float>(c, c->L.gbar);
   A.adjfix = wsp<unsigned long long>(c, c->L.adjfix);
   A.mbar = wsp<float>(c, c->L.mbar);
   A.pbar = wsp<float>(c, c->L.pbar);
-  if (ib) {
+  lbm_status st;
+  if (e.ib) {
     k_adj_gbar<<<std::min(c->L.cap, 2048), WG, 0, c->stream>>>(e, A);
     k_adj_markers<<<interp_items(e.n), WG, 0, c->stream>>>(e, A);
     k_adj_spread<<<std::min(c->L.cap * kSpreadSplit, 2048), WG, 0, c->stream>>>(e, A);
@@ -536,10 +542,146 @@ lbm_status lbm_adjoint_step(lbm_ctx *c, const void *state, const lbm_markers *m,
     k_adj_face<<<dim3((c->p.ny * c->p.nz + 63) / 64, 2), 64, 0, c->stream>>>(e, A);
   }
   if ((st = launched()) != LBM_OK) return st;
-  if (ib) {
-    k_adj_pose_part<<<dim3(m->nbones, kPoseSplit), 256, 0, c->stream>>>(e, A);
-    k_adj_pose_sum<<<m->nbones, 64, 0, c->stream>>>(A, pose_bar);
+  if (e.ib) {
+    k_adj_pose_part<<<dim3(e.nbones, kPoseSplit), 256, 0, c->stream>>>(e, A);
+    k_adj_pose_sum<<<e.nbones, 64, 0, c->stream>>>(A, pose_bar);
     if ((st = launched()) != LBM_OK) return st;
+  }
+  return LBM_OK;
+}
+
+// One slot of the adjoint IB ring: the forward IB data of one step.
+struct RingSlot {
+  size_t X, U, F, rec, mstate, mbase, chunk_box, tile_slot, active, counters, macro, gfix, total;
+};
+
+RingSlot ring_slot(const lbm_params *p) {
+  const Layout L = layout(p);
+  RingSlot r{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes, 256);
+    return at;
+  };
+  const size_t n = (size_t)L.maxm;
+  r.X = take(sizeof(float) * 3 * n);
+  r.U = take(sizeof(float) * 3 * n);
+  r.F = take(sizeof(float) * 3 * n);
+  r.rec = take(sizeof(float) * REC * n);
+  r.mstate = take(sizeof(float) * 4 * n);
+  r.mbase = take(sizeof(short4) * n);
+  r.chunk_box = take(sizeof(int4) * ((n + 63) / 64 + 8));
+  r.tile_slot = take(sizeof(int) * (size_t)L.ntiles);
+  r.active = take(sizeof(int) * (size_t)L.cap);
+  r.counters = take(64);
+  r.macro = take(sizeof(float) * 4 * 512 * (size_t)L.cap);
+  r.gfix = take(sizeof(unsigned long long) * 3 * 512 * (size_t)L.cap);
+  r.total = o;
+  return r;
+}
+
+// e with its per-step IB arrays in ring slot `base`.
+void point_at_slot(EnvView &e, const RingSlot &r, char *base) {
+  e.X = reinterpret_cast<float *>(base + r.X);
+  e.U = reinterpret_cast<float *>(base + r.U);
+  e.F = reinterpret_cast<float *>(base + r.F);
+  e.rec = reinterpret_cast<float *>(base + r.rec);
+  e.mstate = reinterpret_cast<float *>(base + r.mstate);
+  e.mbase = reinterpret_cast<short4 *>(base + r.mbase);
+  e.chunk_box = reinterpret_cast<int4 *>(base + r.chunk_box);
+  e.tile_slot = reinterpret_cast<int *>(base + r.tile_slot);
+  e.active = reinterpret_cast<int *>(base + r.active);
+  e.counters = reinterpret_cast<int *>(base + r.counters);
+  e.macro = reinterpret_cast<float4 *>(base + r.macro);
+  e.gfix = reinterpret_cast<unsigned long long *>(base + r.gfix);
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_adjoint_step(lbm_ctx *c, const void *state, const lbm_markers *m, const float *pose,
+                            const lbm_frame *frame, const double *w, const void *lam_next, void *lam_prev,
+                            float *pose_bar) {
+  if (!c || !state || !frame || !w || !lam_next || !lam_prev || lam_next == lam_prev) return LBM_ERR_ARG;
+  if (!frame_ok(frame)) return LBM_ERR_ARG;
+  lbm_status st = adjoint_request_ok(c, m, pose, w, pose_bar);
+  if (st != LBM_OK) return st;
+  if (rotating(frame)) return LBM_ERR_UNSUPPORTED;
+  EnvView e = env_view(c, m);
+  e.f[0] = const_cast<void *>(state);
+  e.f[1] = nullptr;
+  const FrameF fr = frame_f(frame);
+  if (e.ib) {
+    if ((st = ib_forward(c, e, fr, pose)) != LBM_OK) return st;
+    c->slots_dirty = true;
+  }
+  return adjoint_passes(c, e, fr, w, static_cast<const float *>(lam_next), static_cast<float *>(lam_prev),
+                        pose_bar);
+}
+
+size_t lbm_adjoint_ring_bytes(const lbm_params *p, int32_t nseg) {
+  if (!params_ok(p) || nseg < 1) return 0;
+  return ring_slot(p).total * (size_t)nseg;
+}
+
+lbm_status lbm_adjoint_segment(lbm_ctx *c, const void *ckpt, void *const *ring, int32_t nseg, const lbm_markers *m,
+                               const float *poses, const lbm_frame *frames, const double *w, void *lam,
+                               void *lam_tmp, float *pose_bar, void *ib_ring) {
+  if (!c || !ckpt || nseg < 1 || !frames || !w || !lam || !lam_tmp || lam == lam_tmp || !ib_ring) return LBM_ERR_ARG;
+  if (reinterpret_cast<uintptr_t>(ib_ring) % 256 != 0) return LBM_ERR_ARG;
+  if (nseg > 1 && !ring) return LBM_ERR_ARG;
+  for (int t = 0; t + 1 < nseg; ++t) {
+    if (!ring[t] || ring[t] == ckpt || ring[t] == lam || ring[t] == lam_tmp) return LBM_ERR_ARG;
+    for (int u = 0; u < t; ++u)
+      if (ring[u] == ring[t]) return LBM_ERR_ARG;
+  }
+  for (int t = 0; t < nseg; ++t) {
+    if (!frame_ok(&frames[t])) return LBM_ERR_ARG;
+    if (rotating(&frames[t])) return LBM_ERR_UNSUPPORTED;
+  }
+  lbm_status st = adjoint_request_ok(c, m, poses, w, pose_bar);
+  if (st != LBM_OK) return st;
+  const RingSlot rs = ring_slot(&c->p);
+  char *rbase = static_cast<char *>(ib_ring);
+  const size_t pstride = m && m->n > 0 ? (size_t)m->nbones * 24 : 0;
+  auto state_of = [&](int t) -> void * { return t == 0 ? const_cast<void *>(ckpt) : ring[t - 1]; };
+  // recompute: state t+1 from state t, keeping each step's IB data in its slot
+  for (int t = 0; t < nseg; ++t) {
+    EnvView e = env_view(c, m);
+    e.f[0] = state_of(t);
+    e.f[1] = t + 1 < nseg ? ring[t] : nullptr;
+    point_at_slot(e, rs, rbase + rs.total * (size_t)t);
+    const FrameF fr = frame_f(&frames[t]);
+    if (e.ib && (st = ib_forward(c, e, fr, poses + pstride * t)) != LBM_OK) return st;
+    if (t + 1 < nseg) {
+      const int grid = ((e.nblocks + 7) / 8) * 8;
+      const dim3 blk = collide_block(c);
+      if (e.g.xper)
+        k_collide<StoreF32, true, false><<<grid, blk, 0, c->stream>>>(e, fr, 0);
+      else
+        k_collide<StoreF32, false, false><<<grid, blk, 0, c->stream>>>(e, fr, 0);
+      if ((st = launched()) != LBM_OK) return st;
+    }
+  }
+  // reverse sweep; the result lands in `lam` (an odd count starts from a copy)
+  const size_t lam_bytes = (size_t)27 * c->plane * sizeof(float);
+  float *next = static_cast<float *>(lam), *prev = static_cast<float *>(lam_tmp);
+  if (nseg & 1) {
+    if (hipMemcpyAsync(lam_tmp, lam, lam_bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+      return LBM_ERR_DEVICE;
+    std::swap(next, prev);
+  }
+  for (int t = nseg - 1; t >= 0; --t) {
+    EnvView e = env_view(c, m);
+    e.f[0] = state_of(t);
+    e.f[1] = nullptr;
+    point_at_slot(e, rs, rbase + rs.total * (size_t)t);
+    const FrameF fr = frame_f(&frames[t]);
+    if ((st = adjoint_passes(c, e, fr, w, next, prev, pose_bar ? pose_bar + pstride * t : nullptr)) != LBM_OK)
+      return st;
+    std::swap(next, prev);
   }
   return LBM_OK;
 }

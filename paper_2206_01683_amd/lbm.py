@@ -85,6 +85,9 @@ def lib():
         L.lbm_state_restore.argtypes = [vp, vp, ctypes.c_int64]
         L.lbm_adjoint_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.lbm_bind_populations.argtypes = [vp, vp, vp]
+        L.lbm_adjoint_ring_bytes.argtypes = [P, ctypes.c_int32]
+        L.lbm_adjoint_ring_bytes.restype = sz
+        L.lbm_adjoint_segment.argtypes = [vp, vp, vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp]
         L.lbm_check.argtypes = [vp]
         L.lbm_set_stream.argtypes = [vp, vp]
         L.lbm_profile_enable.argtypes = [vp, ctypes.c_int]
@@ -107,7 +110,7 @@ def lib():
         for name in ("lbm_init", "lbm_load_populations", "lbm_read_populations", "lbm_macros", "lbm_ib_step",
                      "lbm_body_forces", "lbm_check", "lbm_set_stream", "lbm_profile_enable",
                      "lbm_profile_collect", "lbm_state_save", "lbm_state_restore", "lbm_adjoint_step",
-                     "lbm_bind_populations",
+                     "lbm_bind_populations", "lbm_adjoint_segment",
                      "lbm_batch_create", "lbm_batch_run", "lbm_batch_autotune",
                      "lbm_batch_set_shapes", "lbm_batch_check"):
             getattr(L, name).restype = ctypes.c_int
@@ -294,6 +297,33 @@ class Simulation:
         _check(lib().lbm_adjoint_step(self.ctx, _ptr(state), None if ms is None else ctypes.byref(ms), _ptr(pose),
                                       fr.ctypes.data_as(ctypes.c_void_p), wts.ctypes.data_as(ctypes.c_void_p),
                                       _ptr(lam_next), _ptr(lam_prev), _ptr(pose_bar)), "lbm_adjoint_step")
+
+    def adjoint_ring(self, nseg: int) -> torch.Tensor:
+        """Device buffer for the forward IB data of nseg steps (256-byte aligned)."""
+        nb = lib().lbm_adjoint_ring_bytes(ctypes.byref(self.params), int(nseg))
+        if nb == 0:
+            raise LBMError(-1, "invalid adjoint ring size")
+        raw = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+        shift = (-raw.data_ptr()) % 256
+        return raw[shift:shift + nb]
+
+    def adjoint_segment(self, ckpt: torch.Tensor, ring, markers: Optional[DeviceMarkers],
+                        poses: Optional[torch.Tensor], frames, weights, lam: torch.Tensor, lam_tmp: torch.Tensor,
+                        pose_bar: Optional[torch.Tensor], ib_ring: torch.Tensor):
+        """Native reverse sweep over len(frames) steps from checkpoint ckpt
+        (lbm_adjoint_segment): lam in = dJ/d(state after), out = dJ/d(ckpt)."""
+        fr = frames_array(frames)
+        nseg = fr.shape[0]
+        assert len(ring) >= nseg - 1
+        ptrs = (ctypes.c_void_p * max(1, nseg - 1))(*[t.data_ptr() for t in ring[:nseg - 1]] or [None])
+        wts = np.ascontiguousarray(weights, dtype=np.float64).reshape(4)
+        ms = None if markers is None else markers.struct()
+        if markers is not None:
+            assert poses.is_contiguous() and pose_bar.is_contiguous() and poses.shape[0] >= nseg
+        _check(lib().lbm_adjoint_segment(self.ctx, _ptr(ckpt), ptrs, nseg, None if ms is None else ctypes.byref(ms),
+                                         _ptr(poses), fr.ctypes.data_as(ctypes.c_void_p),
+                                         wts.ctypes.data_as(ctypes.c_void_p), _ptr(lam), _ptr(lam_tmp),
+                                         _ptr(pose_bar), _ptr(ib_ring)), "lbm_adjoint_segment")
 
     def check(self) -> int:
         return lib().lbm_check(self.ctx)

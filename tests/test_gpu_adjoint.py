@@ -134,6 +134,31 @@ def test_checkpoint_interval_does_not_change_gradient():
         assert np.array_equal(lam, out[0][1])
 
 
+@pytest.mark.parametrize("every", [1, EVERY, NSTEPS])
+def test_native_segment_sweep_matches_per_step_sweep(every):
+    """lbm_adjoint_segment (recompute keeping each step's IB data, then the
+    reverse passes) gives the same bits as recomputing by rebinding and
+    calling lbm_adjoint_step per step."""
+    w = _fin()
+    sim = _sim(w)
+    dm = lbm.DeviceMarkers(w.markers)
+    poses = torch.as_tensor(w.poses.astype(np.float32), device="cuda")
+    s0 = sim.new_state()
+    sim.save_state(s0)
+    c = _smooth_perturbation(sim, w, s0, seed=2, amp=1.0)
+    out = []
+    for native in (True, False):
+        sim.bind_own_buffers()
+        sim.restore_state(s0, 0)
+        _, tape = AD.forward(sim, dm, poses, w.frames, [-1, 0.3, 0.2, 2.0], every=every)
+        pb, lam = AD.backward(sim, dm, poses, w.frames, tape, lam_final=c, native=native)
+        out.append((pb.cpu().numpy(), lam.cpu().numpy(), sim.read_populations().cpu().numpy()))
+        assert sim.check() == 0
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+    assert np.array_equal(out[0][2], out[1][2])
+
+
 def test_parameter_gradient_against_fp64_oracle():
     """dJ/dtheta (8 kinematics parameters) from the reverse sweep against the
     FP64 oracle's forward-mode tangent (the exact derivative of the discrete
