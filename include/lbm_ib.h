@@ -303,8 +303,13 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, int32_t *shapes_out);
  * five autotuner shapes, else LBM_ERR_ARG. */
 lbm_status lbm_batch_set_shapes(lbm_batch *b, const int32_t *shapes);
 
-/* Synchronize; LBM_ERR_DEVICE if a persistent run's barrier timed out,
- * otherwise the first non-OK lbm_check of the environments. */
+/* Synchronize; LBM_ERR_DEVICE if a persistent run's barrier timed out (its
+ * steps stopped early, the populations are not those of a completed run; the
+ * barrier is reset so later runs can proceed), otherwise the first non-OK
+ * lbm_check of the environments. A persistent launch assumes its whole grid
+ * (sized from the occupancy of one device with nothing else running) is
+ * co-resident; every barrier wait is bounded (about a second), so a grid that
+ * is not co-resident ends with this error instead of hanging. */
 lbm_status lbm_batch_check(lbm_batch *b);
 
 void lbm_batch_destroy(lbm_batch *b);

@@ -1070,7 +1070,13 @@ lbm_status lbm_batch_check(lbm_batch *b) {
   if (hipStreamSynchronize(b->stream) != hipSuccess) return LBM_ERR_DEVICE;
   int status = 0;
   if (hipMemcpy(&status, b->d_status, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return LBM_ERR_DEVICE;
-  if (status & 1) return LBM_ERR_DEVICE;
+  if (status & 1) {
+    // a barrier timed out: the run stopped early and the barrier counters are
+    // stale; reset them (and the flag) so the next run starts clean
+    k_fill_int<<<1, 64, 0, b->stream>>>(reinterpret_cast<int *>(b->d_bar), 0, 16);
+    if (launched() != LBM_OK || hipStreamSynchronize(b->stream) != hipSuccess) return LBM_ERR_DEVICE;
+    return LBM_ERR_DEVICE;
+  }
   for (int e = 0; e < b->nenv; ++e) {
     lbm_ctx *c = b->envs[e].ctx;
     hipStream_t keep = c->stream;

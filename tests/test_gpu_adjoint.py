@@ -63,13 +63,25 @@ def _run_J(sim, s0, dm, poses, frames, weights, c=None):
     return J
 
 
-@pytest.mark.parametrize("case", ["fin", "fluid-open", "fluid-periodic"])
+ACC = (2e-4, -1e-4, 5e-5)  # a uniform frame acceleration (Eq. (3) with no rotation)
+
+
+def _accelerate(w):
+    w.frames = w.frames.copy()
+    w.frames[:, 0:3] = ACC
+    return w
+
+
+@pytest.mark.parametrize("case", ["fin", "fin-accelerating", "fin-periodic", "fluid-open", "fluid-periodic",
+                                  "fluid-open-accelerating"])
 def test_state_adjoint_matches_central_differences(case):
     """<dJ/ds0, delta> from the reverse sweep equals (J(s0 + delta) - J(s0 - delta)) / 2."""
     w = _fin()
-    if case == "fluid-periodic":
+    if "periodic" in case:
         w.bc_lo = w.bc_hi = I.BC_PERIODIC
-    markers = case == "fin"
+    if "accelerating" in case:
+        _accelerate(w)
+    markers = case.startswith("fin")
     sim = _sim(w, with_markers=markers)
     dm = lbm.DeviceMarkers(w.markers) if markers else None
     poses = torch.as_tensor(w.poses.astype(np.float32), device="cuda") if markers else None
@@ -159,13 +171,16 @@ def test_native_segment_sweep_matches_per_step_sweep(every):
     assert np.array_equal(out[0][2], out[1][2])
 
 
-def test_parameter_gradient_against_fp64_oracle():
+@pytest.mark.parametrize("accelerating", [False, True])
+def test_parameter_gradient_against_fp64_oracle(accelerating):
     """dJ/dtheta (8 kinematics parameters) from the reverse sweep against the
     FP64 oracle's forward-mode tangent (the exact derivative of the discrete
     FP64 map, one dual-number run per parameter), J the time-averaged thrust
-    plus a power term."""
+    plus a power term; inertial and uniformly accelerating frame."""
     weights = np.array([-1.0, 0.0, 0.0, 0.5])
     prob = AD.FinProblem(nsteps=NSTEPS, every=EVERY, weights=weights, **GEOM)
+    if accelerating:
+        _accelerate(prob.workload)
     theta = torch.tensor(I.C5_BASE, dtype=torch.float64, requires_grad=True)
     J = AD.FinObjective.apply(theta, prob)
     J.backward()
