@@ -15,14 +15,15 @@
 // n on) and the step's dJ/d(bone pose). Passes, with the forward IB data of
 // step n recomputed beforehand (skin, tiles, band macros, interpolation,
 // spreading):
-//   1 k_adj_gbar      gbar = dJ/dg on active-tile cells (collide + face adjoint)
+//   1 k_adj_gbar      gbar = dJ/dg on active-tile cells (collide + face adjoint);
+//                     the open faces' density and momentum adjoints at x_f
 //   2 k_adj_markers   per marker: Fbar, rhobar_k, U*bar_k, Ubar_k, Xbar_k
 //                     (Xbar includes the derivative of the Peskin weights)
 //   3 k_adj_spread    spread (rhobar_k, U*bar_k) onto the band in 64-bit fixed
 //                     point (order-independent)
 //   4 k_adj_collide   every cell: fbar from the collide adjoint and the band
 //                     IB terms, push-streamed into lam (324 B per cell);
-//                     k_adj_face adds the open faces' extrapolation adjoint
+//                     the x_f lanes add the open faces' extrapolation adjoint
 //   5 k_adj_pose_part per (bone, marker range): dJ/dR, dJ/dt, dJ/dRdot,
 //     k_adj_pose_sum  dJ/dtdot partials, then their sum in a fixed order
 #pragma once
@@ -43,6 +44,7 @@ struct AdjArgs {
   unsigned long long *__restrict__ adjfix;  // [cap][4][512]: spread rhobar, U*bar (fixed point)
   float *__restrict__ mbar;            // [6][n]: Xbar (3), Ubar (3)
   float *__restrict__ pbar;            // [nbones][kPoseSplit][24]: pose-adjoint partial sums
+  float *__restrict__ facebuf;         // [2][4][ny*nz]: open faces' rhobar, mbar (3) at x_f
   float bc_u_lo[3], bc_u_hi[3];        // face velocities
 };
 
@@ -386,8 +388,8 @@ __device__ inline void adj_spread_item(const EnvView &e, const AdjArgs &A, int i
 // Every cell: fbar = (1 - 1/tau) lam + collide adjoint + the band IB terms,
 // then push-streamed: lam_prev_i(x - c_i) = fbar_i(x). Open-face nodes have
 // fbar = 0 and also clear the entries no node streams into (c_x pointing out
-// of the domain). The face extrapolation's share of fbar(x_f) is added
-// afterwards by k_adj_face.
+// of the domain). The face extrapolation's share of fbar(x_f) is added by the
+// x_f lanes from pass 1's face results.
 template <bool XPER>
 __device__ inline void adj_collide_cell(const EnvView &e, const AdjArgs &A, int lb, int tx, int ty) {
   const GridArgs &g = e.g;
@@ -446,6 +448,19 @@ __device__ inline void adj_collide_cell(const EnvView &e, const AdjArgs &A, int 
     }
 #pragma unroll
     for (int i = 0; i < Q; ++i) fb[i] += rb + (float)cx_of(i) * mb[0] + (float)cy_of(i) * mb[1] + (float)cz_of(i) * mb[2];
+    if (!XPER && (x == 1 || x == g.nx - 2)) {
+      // the open face's extrapolation reads f(x_f): its adjoint (pass 1) plus
+      // the direct part (1 - 1/tau) lam_b of the face node
+      const int nyz = g.ny * g.nz, yz = z * g.ny + y;
+      const bool lo = x == 1;
+      const float *fp = A.facebuf + (size_t)(lo ? 0 : 1) * 4 * nyz;
+      const float rF = fp[yz], m0 = fp[nyz + yz], m1 = fp[2 * nyz + yz], m2 = fp[3 * nyz + yz];
+      const uint32_t ob = (uint32_t)yz * g.nx + (lo ? 0 : g.nx - 1);
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        fb[i] += e.omt * A.lam_next[(uint32_t)i * g.plane + ob] + rF + (float)cx_of(i) * m0 + (float)cy_of(i) * m1 +
+                 (float)cz_of(i) * m2;
+    }
   }
   // push: lam_prev_i(x - c_i) = fbar_i(x)
   const int yy[3] = {yp, y, ym};  // indexed by c + 1: target y - c
@@ -470,15 +485,17 @@ __device__ inline void adj_collide_cell(const EnvView &e, const AdjArgs &A, int 
   }
 }
 
-// Face extrapolation adjoint, one thread per (y, z) of each open face
-// (blockIdx.y: 0 = x = 0 face, 1 = x = nx-1 face): adds its share of
-// fbar(x_f) into the entries x_f streamed into (each written by one thread).
-__global__ void __launch_bounds__(64) k_adj_face(EnvView e, AdjArgs A) {
+// Face extrapolation adjoint of face node `id` (side id / (ny nz): 0 is
+// x = 0, 1 is x = nx-1), seen from its inward neighbour x_f: the parts of
+// fbar(x_f) that go through x_f's density and momentum (rhobar, mbar), stored
+// for the x_f lane of the collide adjoint, which adds them and the direct
+// part (1 - 1/tau) lam_b to its own pushes.
+__device__ inline void adj_face_item(const EnvView &e, const AdjArgs &A, int id) {
   const GridArgs &g = e.g;
-  const int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= g.ny * g.nz) return;
-  const int y = id % g.ny, z = id / g.ny;
-  const bool lo = blockIdx.y == 0;
+  const int nyz = g.ny * g.nz;
+  const int side = id / nyz, yz = id - side * nyz;
+  const int y = yz % g.ny, z = yz / g.ny;
+  const bool lo = side == 0;
   const int x = lo ? 1 : g.nx - 2;
   const float *__restrict__ src = static_cast<const float *>(e.f[0]);
   const int ym = y == 0 ? g.ny - 1 : y - 1;
@@ -492,25 +509,14 @@ __global__ void __launch_bounds__(64) k_adj_face(EnvView e, AdjArgs A) {
   float gg[3];
   load_g(g, e.ib ? e.tile_slot : nullptr, e.gfix, x, y, z, gg[0], gg[1], gg[2]);
   float lam[Q];
-  load_lam(A.lam_next, g.plane, ((uint32_t)z * g.ny + y) * g.nx + (lo ? 0 : g.nx - 1), lam);
+  load_lam(A.lam_next, g.plane, (uint32_t)yz * g.nx + (lo ? 0 : g.nx - 1), lam);
   float rb, mb[3], gb[3];
   adj_face(lam, rho, m, gg, lo ? A.bc_u_lo : A.bc_u_hi, (lo ? g.bc_lo : g.bc_hi) == 1, A, e.omt, e.pref, rb, mb, gb);
-  const int yy[3] = {yp, y, ym};
-  const int zz[3] = {zp, z, zm};
-  // all 27 reads before any write, so they are in flight together (the
-  // targets are distinct: one per direction plane)
-  float old[Q];
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const uint32_t ot = ((uint32_t)zz[cz_of(i) + 1] * g.ny + yy[cy_of(i) + 1]) * g.nx + (x - cx_of(i));
-    old[i] = A.lam_prev[(uint32_t)i * g.plane + ot];
-  }
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const float fb = e.omt * lam[i] + rb + (float)cx_of(i) * mb[0] + (float)cy_of(i) * mb[1] + (float)cz_of(i) * mb[2];
-    const uint32_t ot = ((uint32_t)zz[cz_of(i) + 1] * g.ny + yy[cy_of(i) + 1]) * g.nx + (x - cx_of(i));
-    A.lam_prev[(uint32_t)i * g.plane + ot] = old[i] + fb;
-  }
+  float *fp = A.facebuf + (size_t)side * 4 * nyz;
+  fp[yz] = rb;
+  fp[nyz + yz] = mb[0];
+  fp[2 * nyz + yz] = mb[1];
+  fp[3 * nyz + yz] = mb[2];
 }
 
 template <bool XPER>
@@ -522,9 +528,21 @@ __global__ void __launch_bounds__(512) k_adj_collide(EnvView e, AdjArgs A) {
   adj_collide_cell<XPER>(e, A, lb, threadIdx.x, threadIdx.y);
 }
 
-__global__ void __launch_bounds__(WG) k_adj_gbar(EnvView e, AdjArgs A) {
+constexpr int kFacePerBlock = 64;  // face nodes per workgroup (one wave): strided loads, spread over many CUs
+
+// Pass 1 in one launch: workgroups [0, face_blocks) take kFacePerBlock open
+// face nodes each (adj_face_item), the rest the active tiles (adj_gbar_item;
+// none without a body).
+__global__ void __launch_bounds__(WG) k_adj_gbar(EnvView e, AdjArgs A, int face_blocks) {
+  if ((int)blockIdx.x < face_blocks) {
+    const int id = blockIdx.x * kFacePerBlock + threadIdx.x;
+    if (threadIdx.x < kFacePerBlock && id < 2 * e.g.ny * e.g.nz) adj_face_item(e, A, id);
+    return;
+  }
+  if (!e.ib) return;
   const int na = n_active_of(e);
-  for (int slot = blockIdx.x; slot < na; slot += gridDim.x) adj_gbar_item(e, A, slot, threadIdx.x);
+  const int nb = gridDim.x - face_blocks;
+  for (int slot = blockIdx.x - face_blocks; slot < na; slot += nb) adj_gbar_item(e, A, slot, threadIdx.x);
 }
 
 __global__ void __launch_bounds__(WG) k_adj_markers(EnvView e, AdjArgs A) {

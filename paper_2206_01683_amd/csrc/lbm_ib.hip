@@ -27,7 +27,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Layout {
   int tnx, tny, tnz, ntiles, cap, maxm;
   size_t guard, counters, tile_flag, tile_slot, active, mbase, chunk_box, partials, macro, gbuf, rec, mstate;
-  size_t gbar, adjfix, mbar, pbar, total;
+  size_t gbar, adjfix, mbar, pbar, facebuf, total;
 };
 
 bool params_ok(const lbm_params *p) {
@@ -86,12 +86,13 @@ Layout layout(const lbm_params *p) {
   L.gbuf = take(sizeof(unsigned long long) * 3 * 512 * (size_t)L.cap);
   L.rec = take(sizeof(float) * REC * (size_t)L.maxm);
   L.mstate = take(sizeof(float) * 4 * (size_t)L.maxm);
-  L.gbar = L.adjfix = L.mbar = L.pbar = 0;
+  L.gbar = L.adjfix = L.mbar = L.pbar = L.facebuf = 0;
   if (p->with_adjoint) {
     L.gbar = take(sizeof(float) * 3 * 512 * (size_t)L.cap);
     L.adjfix = take(sizeof(unsigned long long) * 4 * 512 * (size_t)L.cap);
     L.mbar = take(sizeof(float) * 6 * (size_t)L.maxm);
     L.pbar = take(sizeof(float) * 24 * kPoseSplit * (size_t)p->max_bones);
+    L.facebuf = take(sizeof(float) * 2 * 4 * (size_t)p->ny * p->nz);
   }
   L.total = o;
   return L;
@@ -526,21 +527,25 @@ lbm_status adjoint_passes(lbm_ctx *c, const EnvView &e, const FrameF &fr, const 
   A.adjfix = wsp<unsigned long long>(c, c->L.adjfix);
   A.mbar = wsp<float>(c, c->L.mbar);
   A.pbar = wsp<float>(c, c->L.pbar);
+  A.facebuf = wsp<float>(c, c->L.facebuf);
   lbm_status st;
+  const int face_blocks = e.g.xper ? 0 : (2 * c->p.ny * c->p.nz + kFacePerBlock - 1) / kFacePerBlock;
+  const int gbar_blocks = e.ib ? std::min(c->L.cap, 2048) : 0;
+  if (face_blocks + gbar_blocks > 0) {
+    k_adj_gbar<<<face_blocks + gbar_blocks, WG, 0, c->stream>>>(e, A, face_blocks);
+    if ((st = launched()) != LBM_OK) return st;
+  }
   if (e.ib) {
-    k_adj_gbar<<<std::min(c->L.cap, 2048), WG, 0, c->stream>>>(e, A);
     k_adj_markers<<<interp_items(e.n), WG, 0, c->stream>>>(e, A);
     k_adj_spread<<<std::min(c->L.cap * kSpreadSplit, 2048), WG, 0, c->stream>>>(e, A);
     if ((st = launched()) != LBM_OK) return st;
   }
   const int grid = ((e.nblocks + 7) / 8) * 8;
   const dim3 blk = collide_block(c);
-  if (e.g.xper) {
+  if (e.g.xper)
     k_adj_collide<true><<<grid, blk, 0, c->stream>>>(e, A);
-  } else {
+  else
     k_adj_collide<false><<<grid, blk, 0, c->stream>>>(e, A);
-    k_adj_face<<<dim3((c->p.ny * c->p.nz + 63) / 64, 2), 64, 0, c->stream>>>(e, A);
-  }
   if ((st = launched()) != LBM_OK) return st;
   if (e.ib) {
     k_adj_pose_part<<<dim3(e.nbones, kPoseSplit), 256, 0, c->stream>>>(e, A);
