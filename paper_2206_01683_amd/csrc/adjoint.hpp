@@ -24,8 +24,9 @@
 //   4 k_adj_collide   every cell: fbar from the collide adjoint and the band
 //                     IB terms, push-streamed into lam (324 B per cell);
 //                     the x_f lanes add the open faces' extrapolation adjoint
-//   5 k_adj_pose_part per (bone, marker range): dJ/dR, dJ/dt, dJ/dRdot,
-//     k_adj_pose_sum  dJ/dtdot partials, then their sum in a fixed order
+//   5 k_adj_pose_part per (bone, marker range, step): dJ/dR, dJ/dt, dJ/dRdot,
+//     k_adj_pose_sum  dJ/dtdot partials, then their sum in a fixed order (per
+//                     step, or once for all steps of a segment)
 #pragma once
 
 #include "ib.hpp"
@@ -43,7 +44,6 @@ struct AdjArgs {
   float *__restrict__ gbar;            // [cap][3][512]
   unsigned long long *__restrict__ adjfix;  // [cap][4][512]: spread rhobar, U*bar (fixed point)
   float *__restrict__ mbar;            // [6][n]: Xbar (3), Ubar (3)
-  float *__restrict__ pbar;            // [nbones][kPoseSplit][24]: pose-adjoint partial sums
   float *__restrict__ facebuf;         // [2][4][ny*nz]: open faces' rhobar, mbar (3) at x_f
   float bc_u_lo[3], bc_u_hi[3];        // face velocities
 };
@@ -556,12 +556,18 @@ __global__ void __launch_bounds__(WG) k_adj_spread(EnvView e, AdjArgs A) {
 
 // ------------------------------------------------------------------ pass 5 --
 // Pose adjoint: X = sum_b w (R xrest + t), U = sum_b w (Rdot xrest + tdot).
-// Workgroup (b, p) sums the terms of bone b over the p-th of kPoseSplit marker
-// ranges into pbar[b][p]; k_adj_pose_sum adds the kPoseSplit partials in
-// order into pose_bar[b] (deterministic).
-__global__ void __launch_bounds__(256) k_adj_pose_part(EnvView e, AdjArgs A) {
+// Workgroup (b, p, t) sums the terms of bone b over the p-th of kPoseSplit
+// marker ranges of step t (marker adjoints mbar + t mstride, [6][n]) into
+// pbar + t pstride, [nbones][kPoseSplit][24]; k_adj_pose_sum adds the
+// kPoseSplit partials in order into pose_bar[t][b] (deterministic). One
+// launch covers one step, or every step of a segment.
+__global__ void __launch_bounds__(256) k_adj_pose_part(EnvView e, const float *__restrict__ mbar_base,
+                                                       size_t mstride, float *__restrict__ pbar_base,
+                                                       size_t pstride) {
   __shared__ float s_red[4][24];
   const int b = blockIdx.x, p = blockIdx.y;
+  const float *__restrict__ mbar = mbar_base + mstride * blockIdx.z;
+  float *__restrict__ pbar = pbar_base + pstride * blockIdx.z;
   const int n = e.n;
   const int chunk = (n + kPoseSplit - 1) / kPoseSplit;
   const int k0 = p * chunk, k1 = min(n, k0 + chunk);
@@ -571,8 +577,8 @@ __global__ void __launch_bounds__(256) k_adj_pose_part(EnvView e, AdjArgs A) {
   for (int k = k0 + (int)threadIdx.x; k < k1; k += 256) {
     const float wk = (e.bone[k] == b ? e.weight[k] : 0.f) + (e.bone[n + k] == b ? e.weight[n + k] : 0.f);
     const float xr[3] = {e.xrest[k], e.xrest[n + k], e.xrest[2 * n + k]};
-    const float xb[3] = {wk * A.mbar[k], wk * A.mbar[n + k], wk * A.mbar[2 * n + k]};
-    const float ub[3] = {wk * A.mbar[3 * n + k], wk * A.mbar[4 * n + k], wk * A.mbar[5 * n + k]};
+    const float xb[3] = {wk * mbar[k], wk * mbar[n + k], wk * mbar[2 * n + k]};
+    const float ub[3] = {wk * mbar[3 * n + k], wk * mbar[4 * n + k], wk * mbar[5 * n + k]};
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
 #pragma unroll
@@ -592,16 +598,23 @@ __global__ void __launch_bounds__(256) k_adj_pose_part(EnvView e, AdjArgs A) {
   }
   __syncthreads();
   if (threadIdx.x < 24)
-    A.pbar[((size_t)b * kPoseSplit + p) * 24 + threadIdx.x] =
+    pbar[((size_t)b * kPoseSplit + p) * 24 + threadIdx.x] =
         ((s_red[0][threadIdx.x] + s_red[1][threadIdx.x]) + s_red[2][threadIdx.x]) + s_red[3][threadIdx.x];
 }
 
-__global__ void __launch_bounds__(64) k_adj_pose_sum(AdjArgs A, float *__restrict__ pose_bar) {
+// grid (nbones, steps): pose_bar[t][b][q] += sum_p pbar_t[b][p][q], p in order.
+__global__ void __launch_bounds__(64) k_adj_pose_sum(const float *__restrict__ pbar_base, size_t pstride,
+                                                      float *__restrict__ pose_bar, int nbones) {
   const int b = blockIdx.x, q = threadIdx.x;
   if (q >= 24) return;
+  const float *__restrict__ pbar = pbar_base + pstride * blockIdx.y;
+  float v[kPoseSplit];
+#pragma unroll
+  for (int p = 0; p < kPoseSplit; ++p) v[p] = pbar[((size_t)b * kPoseSplit + p) * 24 + q];
   float s = 0.f;
-  for (int p = 0; p < kPoseSplit; ++p) s += A.pbar[((size_t)b * kPoseSplit + p) * 24 + q];
-  pose_bar[b * 24 + q] += s;
+#pragma unroll
+  for (int p = 0; p < kPoseSplit; ++p) s += v[p];
+  pose_bar[((size_t)blockIdx.y * nbones + b) * 24 + q] += s;
 }
 
 }  // namespace lbmib

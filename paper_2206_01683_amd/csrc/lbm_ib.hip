@@ -511,8 +511,10 @@ lbm_status ib_forward(lbm_ctx *c, const EnvView &e, const FrameF &fr, const floa
 
 // The adjoint passes of one step whose forward IB data e points at (state in
 // e.f[0]): lam_next -> lam_prev, pose_bar += the step's pose adjoint.
+// mbar: where the marker adjoints go (null: the workspace's); pose_bar null:
+// the pose reduction is left to the caller (a segment does it once).
 lbm_status adjoint_passes(lbm_ctx *c, const EnvView &e, const FrameF &fr, const double *w, const float *lam_next,
-                          float *lam_prev, float *pose_bar) {
+                          float *lam_prev, float *pose_bar, float *mbar = nullptr) {
   AdjArgs A{};
   for (int a = 0; a < 3; ++a) {
     A.wF[a] = (float)w[a];
@@ -525,8 +527,7 @@ lbm_status adjoint_passes(lbm_ctx *c, const EnvView &e, const FrameF &fr, const 
   A.lam_prev = lam_prev;
   A.gbar = wsp<float>(c, c->L.gbar);
   A.adjfix = wsp<unsigned long long>(c, c->L.adjfix);
-  A.mbar = wsp<float>(c, c->L.mbar);
-  A.pbar = wsp<float>(c, c->L.pbar);
+  A.mbar = mbar ? mbar : wsp<float>(c, c->L.mbar);
   A.facebuf = wsp<float>(c, c->L.facebuf);
   lbm_status st;
   const int face_blocks = e.g.xper ? 0 : (2 * c->p.ny * c->p.nz + kFacePerBlock - 1) / kFacePerBlock;
@@ -547,9 +548,10 @@ lbm_status adjoint_passes(lbm_ctx *c, const EnvView &e, const FrameF &fr, const 
   else
     k_adj_collide<false><<<grid, blk, 0, c->stream>>>(e, A);
   if ((st = launched()) != LBM_OK) return st;
-  if (e.ib) {
-    k_adj_pose_part<<<dim3(e.nbones, kPoseSplit), 256, 0, c->stream>>>(e, A);
-    k_adj_pose_sum<<<e.nbones, 64, 0, c->stream>>>(A, pose_bar);
+  if (e.ib && pose_bar) {
+    float *pbar = wsp<float>(c, c->L.pbar);
+    k_adj_pose_part<<<dim3(e.nbones, kPoseSplit, 1), 256, 0, c->stream>>>(e, A.mbar, 0, pbar, 0);
+    k_adj_pose_sum<<<dim3(e.nbones, 1), 64, 0, c->stream>>>(pbar, 0, pose_bar, e.nbones);
     if ((st = launched()) != LBM_OK) return st;
   }
   return LBM_OK;
@@ -557,7 +559,7 @@ lbm_status adjoint_passes(lbm_ctx *c, const EnvView &e, const FrameF &fr, const 
 
 // One slot of the adjoint IB ring: the forward IB data of one step.
 struct RingSlot {
-  size_t X, U, F, rec, mstate, mbase, chunk_box, tile_slot, active, counters, macro, gfix, total;
+  size_t X, U, F, rec, mstate, mbase, chunk_box, tile_slot, active, counters, macro, gfix, mbar, pbar, total;
 };
 
 RingSlot ring_slot(const lbm_params *p) {
@@ -582,6 +584,8 @@ RingSlot ring_slot(const lbm_params *p) {
   r.counters = take(64);
   r.macro = take(sizeof(float) * 4 * 512 * (size_t)L.cap);
   r.gfix = take(sizeof(unsigned long long) * 3 * 512 * (size_t)L.cap);
+  r.mbar = take(sizeof(float) * 6 * n);
+  r.pbar = take(sizeof(float) * 24 * kPoseSplit * (size_t)p->max_bones);
   r.total = o;
   return r;
 }
@@ -682,11 +686,23 @@ lbm_status lbm_adjoint_segment(lbm_ctx *c, const void *ckpt, void *const *ring, 
     EnvView e = env_view(c, m);
     e.f[0] = state_of(t);
     e.f[1] = nullptr;
-    point_at_slot(e, rs, rbase + rs.total * (size_t)t);
+    char *slot = rbase + rs.total * (size_t)t;
+    point_at_slot(e, rs, slot);
     const FrameF fr = frame_f(&frames[t]);
-    if ((st = adjoint_passes(c, e, fr, w, next, prev, pose_bar ? pose_bar + pstride * t : nullptr)) != LBM_OK)
+    // marker adjoints stay in the step's slot; the pose sums run once below
+    if ((st = adjoint_passes(c, e, fr, w, next, prev, nullptr, reinterpret_cast<float *>(slot + rs.mbar))) !=
+        LBM_OK)
       return st;
     std::swap(next, prev);
+  }
+  if (m && m->n > 0) {
+    const EnvView e = env_view(c, m);
+    const size_t fstride = rs.total / sizeof(float);
+    k_adj_pose_part<<<dim3(m->nbones, kPoseSplit, nseg), 256, 0, c->stream>>>(
+        e, reinterpret_cast<float *>(rbase + rs.mbar), fstride, reinterpret_cast<float *>(rbase + rs.pbar), fstride);
+    k_adj_pose_sum<<<dim3(m->nbones, nseg), 64, 0, c->stream>>>(reinterpret_cast<float *>(rbase + rs.pbar), fstride,
+                                                                 pose_bar, m->nbones);
+    if ((st = launched()) != LBM_OK) return st;
   }
   return LBM_OK;
 }
