@@ -277,6 +277,11 @@ class Simulation:
     def restore_state(self, src: torch.Tensor, step: int = 0):
         _check(lib().lbm_state_restore(self.ctx, _ptr(src), int(step)), "lbm_state_restore")
 
+    def set_stream(self, stream: torch.cuda.Stream):
+        """Enqueue all further work on `stream` (e.g. a graph-capture stream)."""
+        _check(lib().lbm_set_stream(self.ctx, ctypes.c_void_p(stream.cuda_stream)), "lbm_set_stream")
+        self.stream = stream
+
     def bind_populations(self, cur: torch.Tensor, nxt: torch.Tensor):
         """The next step reads `cur` and writes `nxt` (then ping-pong)."""
         for t in (cur, nxt):

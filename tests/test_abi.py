@@ -77,3 +77,38 @@ def test_strerror_covers_every_status(L):
         s = lbm.strerror(code)
         assert s and s != "unknown status"
     assert lbm.strerror(42) == "unknown status"
+
+
+def test_adjoint_ring_size_is_host_computed(L):
+    p = lbm.make_params(128, 64, 64, 0.6, lbm.BC_VELOCITY, lbm.BC_OUTFLOW, max_markers=3000, max_bones=10,
+                        max_active_tiles=256, with_adjoint=True)
+    one = L.lbm_adjoint_ring_bytes(ctypes.byref(p), 1)
+    assert one > 0 and one % 256 == 0
+    assert L.lbm_adjoint_ring_bytes(ctypes.byref(p), 20) == 20 * one
+    assert L.lbm_adjoint_ring_bytes(ctypes.byref(p), 0) == 0
+    big = lbm.make_params(128, 64, 64, 0.6, lbm.BC_VELOCITY, lbm.BC_OUTFLOW, max_markers=6000, max_bones=10,
+                          max_active_tiles=256, with_adjoint=True)
+    assert L.lbm_adjoint_ring_bytes(ctypes.byref(big), 1) > one
+    bad = lbm.make_params(128, 64, 64, 0.5, max_markers=3000)
+    assert L.lbm_adjoint_ring_bytes(ctypes.byref(bad), 4) == 0
+    # the adjoint buffers enlarge the workspace
+    plain = lbm.make_params(128, 64, 64, 0.6, lbm.BC_VELOCITY, lbm.BC_OUTFLOW, max_markers=3000, max_bones=10,
+                            max_active_tiles=256)
+    assert L.lbm_workspace_bytes(ctypes.byref(p)) > L.lbm_workspace_bytes(ctypes.byref(plain))
+
+
+def test_adjoint_batch_and_state_calls_on_null_handles_fail_cleanly(L):
+    w = (ctypes.c_double * 4)(0, 0, 0, 0)
+    assert L.lbm_adjoint_step(None, None, None, None, None, w, None, None, None) == -1
+    assert L.lbm_adjoint_segment(None, None, None, 1, None, None, None, w, None, None, None, None) == -1
+    assert L.lbm_bind_populations(None, None, None) == -1
+    assert L.lbm_state_save(None, None) == -1
+    assert L.lbm_state_restore(None, None, 0) == -1
+    assert L.lbm_set_stream(None, None) == -1
+    assert L.lbm_batch_bytes(0) == 0 and L.lbm_batch_bytes(100000) == 0 and L.lbm_batch_bytes(64) > 0
+    assert L.lbm_batch_create(None, None, 0, None, None) == -1
+    assert L.lbm_batch_run(None, 2, 0, 0) == -1
+    assert L.lbm_batch_autotune(None, 1, None) == -1
+    assert L.lbm_batch_set_shapes(None, None) == -1
+    assert L.lbm_batch_check(None) == -1
+    L.lbm_batch_destroy(None)
