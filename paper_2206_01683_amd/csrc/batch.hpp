@@ -147,6 +147,38 @@ __device__ inline void phase_collide(const BatchArgs &b, int s, int item, int ti
   }
 }
 
+// Collide items [i0, i1) in order, looking the environment up once per run
+// of items that belong to it (a persistent workgroup walks a contiguous range).
+template <bool UNI>
+__device__ inline void collide_range(const BatchArgs &b, int s, int i0, int i1, int tid) {
+  const int *pre = b.pre + PRE_COLLIDE * (b.nenv + 1);
+  int item = i0;
+  while (item < i1) {
+    const int ei = find_env(pre, b.nenv, item);
+    const EnvView &e = b.envs[ei];
+    const FrameF fr = env_frame(e, s);
+    const int cur = env_cur(e, s);
+    const int lo = pre[ei], hi = min(pre[ei + 1], i1);
+    const int tx = tid % e.bx, ty = tid / e.bx;
+    for (; item < hi; ++item) {
+      const int lb = item - lo;
+      if (UNI) {
+        collide_cell<StoreF32, false, false>(e, fr, cur, lb, tx, ty);
+      } else if (e.g.xper) {
+        if (e.rot)
+          collide_cell<StoreF32, true, true>(e, fr, cur, lb, tx, ty);
+        else
+          collide_cell<StoreF32, true, false>(e, fr, cur, lb, tx, ty);
+      } else {
+        if (e.rot)
+          collide_cell<StoreF32, false, true>(e, fr, cur, lb, tx, ty);
+        else
+          collide_cell<StoreF32, false, false>(e, fr, cur, lb, tx, ty);
+      }
+    }
+  }
+}
+
 // Collide work item of hardware workgroup position i out of a grid of g
 // (g a multiple of 8): each XCD (i % 8) takes a contiguous eighth of the items.
 __device__ inline int xcd_item(int i, int total) {
@@ -221,9 +253,11 @@ __device__ inline bool grid_sync(const BatchArgs &b) {
 }
 
 // All steps of all environments in one launch (grid: co-resident, multiple of
-// 8). At most 128 VGPRs, so that two workgroups (16 waves) share a CU.
+// 8). The launch bound asks for at least 4 waves per SIMD (at most 128 VGPRs),
+// so that two 512-thread workgroups share a CU; the collide phase gives each
+// workgroup a contiguous range of items.
 template <bool UNI>
-__global__ void __launch_bounds__(WG, 2) kb_persistent(BatchArgs b, int nsteps) {
+__global__ void __launch_bounds__(WG, 4) kb_persistent(BatchArgs b, int nsteps) {
   __shared__ int s_pre[kMaxEnvs + 1];
   const int tid = threadIdx.x;
   for (int s = 0; s < nsteps; ++s) {
@@ -246,9 +280,11 @@ __global__ void __launch_bounds__(WG, 2) kb_persistent(BatchArgs b, int nsteps) 
     }
     for (int item = blockIdx.x; item < tot; item += gridDim.x) phase_spread(b, s, true, item, s_pre, tid);
     if (!grid_sync(b)) return;
-    for (int i = blockIdx.x; i < ((b.tot[PRE_COLLIDE] + 7) & ~7); i += gridDim.x) {
-      const int item = xcd_item(i, b.tot[PRE_COLLIDE]);
-      if (item < b.tot[PRE_COLLIDE]) phase_collide<UNI>(b, s, item, tid);
+    {
+      const int total = b.tot[PRE_COLLIDE];
+      const int per = (total + (int)gridDim.x - 1) / (int)gridDim.x;
+      const int i0 = min(total, (int)blockIdx.x * per);
+      collide_range<UNI>(b, s, i0, min(total, i0 + per), tid);
     }
     if (!grid_sync(b)) return;
   }

@@ -98,21 +98,24 @@ __device__ inline void load_g(const GridArgs &g, const int *__restrict__ tile_sl
 // The open-face lanes reuse the interior arithmetic: replacing f_i by
 // f_i + f^eq_i(rho_f, u_b) - f^eq_i(rho_f, u_f) makes the BGK formula with
 // (rho_f, u_b, F_b) produce exactly the extrapolated values.
-// One cell of logical block lb (tile shape e.bx x e.by, see cell_of), thread (tx, ty);
-// `cur` is the buffer holding f*(n-1), the other one receives f*(n).
-template <class S, bool XPER, bool ROT>
-__device__ inline void collide_cell(const EnvView &e, const FrameF &fr, int cur, int lb, int tx, int ty) {
+//
+// A cell of the collide and, for an open-face lane, the inward neighbour
+// x_f = xs whose populations it reads.
+struct CellAt {
+  int x, y, z, xs;
+};
+
+// First half of collide_cell: locate the cell and pull its 27 populations
+// (for an open-face lane, those of x_f). False past the lattice.
+template <class S, bool XPER>
+__device__ inline bool collide_load(const EnvView &e, int cur, int lb, int tx, int ty, CellAt &c, float f[Q]) {
   using T = typename S::T;
   const T *__restrict__ src = static_cast<const T *>(e.f[cur]);
-  T *__restrict__ dst = static_cast<T *>(e.f[cur ^ 1]);
-  const int *__restrict__ tile_slot = e.ib ? e.tile_slot : nullptr;
   int x, y, z;
-  if (!cell_of(e, lb, tx, ty, x, y, z)) return;
+  if (!cell_of(e, lb, tx, ty, x, y, z)) return false;
   const GridArgs &g = e.g;
-
   const bool lo_face = !XPER && x == 0;
   const bool hi_face = !XPER && x == g.nx - 1;
-  const bool face = lo_face || hi_face;
   const int xs = lo_face ? 1 : (hi_face ? g.nx - 2 : x);
   int xm, xp;
   if (XPER) {
@@ -126,9 +129,25 @@ __device__ inline void collide_cell(const EnvView &e, const FrameF &fr, int cur,
   const int yp = y == g.ny - 1 ? 0 : y + 1;
   const int zm = z == 0 ? g.nz - 1 : z - 1;
   const int zp = z == g.nz - 1 ? 0 : z + 1;
-
-  float f[Q];
   pull27<S>(src, g.plane, g.nx, g.ny, xm, xs, xp, ym, y, yp, zm, z, zp, f);
+  c.x = x;
+  c.y = y;
+  c.z = z;
+  c.xs = xs;
+  return true;
+}
+
+// Second half: moments, forcing, BGK + Guo (or the open-face extrapolation)
+// and the 27 stores of f*(n).
+template <class S, bool XPER, bool ROT>
+__device__ inline void collide_finish(const EnvView &e, const FrameF &fr, int cur, const CellAt &c, float f[Q]) {
+  using T = typename S::T;
+  T *__restrict__ dst = static_cast<T *>(e.f[cur ^ 1]);
+  const int *__restrict__ tile_slot = e.ib ? e.tile_slot : nullptr;
+  const GridArgs &g = e.g;
+  const int x = c.x, y = c.y, z = c.z, xs = c.xs;
+  const bool lo_face = !XPER && x == 0;
+  const bool face = !XPER && (x == 0 || x == g.nx - 1);
   float rho, mx, my, mz;
   moments(f, rho, mx, my, mz);
   const float irho = 1.0f / rho;
@@ -196,6 +215,15 @@ __device__ inline void collide_cell(const EnvView &e, const FrameF &fr, int cur,
     const float w = w_of(13);
     S::store(d + 13u * g.plane, e.omt * f[13] + (w * E) * A - (w * P) * 3.0f * uF, 13);
   }
+}
+
+// One cell of logical block lb (tile shape e.bx x e.by, see cell_of), thread
+// (tx, ty); `cur` is the buffer holding f*(n-1), the other one receives f*(n).
+template <class S, bool XPER, bool ROT>
+__device__ inline void collide_cell(const EnvView &e, const FrameF &fr, int cur, int lb, int tx, int ty) {
+  CellAt c;
+  float f[Q];
+  if (collide_load<S, XPER>(e, cur, lb, tx, ty, c, f)) collide_finish<S, XPER, ROT>(e, fr, cur, c, f);
 }
 
 // Single-lattice launch: blockDim = (e.bx, e.by). Blocks are mapped
