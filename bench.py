@@ -129,6 +129,39 @@ def run_batch(nenv: int, nsteps: int, seed: int = 4):
     return out
 
 
+def run_two_fish(steps: int = 200, warmup: int = 20):
+    """Two bodies in one lattice: the 150x50x100 two-fish domain, 2 x 2,000
+    markers on 2 x 10 bones, inertial frame with inflow. MLUPS of the whole
+    step and the IB share from the library's HIP events."""
+    import numpy as np
+    import torch
+
+    from paper_2206_01683_amd import inputs as I
+    from paper_2206_01683_amd import lbm
+
+    w = I.two_fish_workload(nsteps=warmup + steps)
+    sim = lbm.Simulation(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi, max_markers=w.markers.n,
+                         max_bones=w.markers.nbones, u0=w.u0.astype(np.float32))
+    dm = lbm.DeviceMarkers(w.markers)
+    poses = torch.as_tensor(np.ascontiguousarray(w.poses, np.float32), device="cuda")
+    wrench = torch.zeros((warmup + steps, 8), dtype=torch.float32, device="cuda")
+    sim.step(w.frames[:warmup], dm, poses[:warmup], wrench[:warmup])
+    torch.cuda.synchronize()
+    sim.profile(True)
+    t0 = time.perf_counter()
+    sim.step(w.frames[warmup:], dm, poses[warmup:], wrench[warmup:])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ib_ms, col_ms, timed = sim.profile_collect()
+    status = sim.check()
+    del sim
+    torch.cuda.empty_cache()
+    return {"workload": w.name, "markers": w.markers.n, "bones": w.markers.nbones, "steps": steps,
+            "mlups": round(w.ncell * steps / wall / 1e6, 1), "ms_per_step": round(wall * 1e3 / steps, 4),
+            "ib_ms_per_step": round(ib_ms / max(timed, 1), 5),
+            "collide_GBps": round(216 * w.ncell / (col_ms / 1e3 / max(timed, 1)) / 1e9, 1), "status": status}
+
+
 def run_adjoint(nsteps: int = 400, every: int = 20):
     """Differentiation form: the 128x64x64 swimmer with 3,000 markers,
     J = time-averaged thrust over nsteps steps. Forward = the steps with a
@@ -191,8 +224,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f32", choices=sorted(BYTES_PER_CELL))
     ap.add_argument("--cpu-steps", type=int, default=24, help="oracle sample length (0: skip)")
-    ap.add_argument("--forms", default="f16,bf16,batched,adjoint",
-                    help="comma-separated extra forms to measure: f16, bf16, batched, adjoint")
+    ap.add_argument("--forms", default="f16,bf16,batched,adjoint,two_fish",
+                    help="comma-separated extra forms to measure: f16, bf16, batched, adjoint, two_fish")
     ap.add_argument("--no-forms", action="store_true", help="measure no extra form")
     ap.add_argument("--block", type=int, nargs=2, default=(0, 0))
     ap.add_argument("--batch-envs", type=int, default=64, help="batched form: environments (0: skip)")
@@ -218,6 +251,8 @@ def main():
         forms["batched"] = run_batch(args.batch_envs, args.batch_steps)
     if "adjoint" in want:
         forms["adjoint"] = run_adjoint()
+    if "two_fish" in want:
+        forms["two_fish"] = run_two_fish()
     traffic = measured_traffic(args.storage)
     ach = main_run["collide_gbs"]
     out = {

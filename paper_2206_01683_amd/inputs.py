@@ -403,6 +403,47 @@ def fin_workload(params=C5_BASE, nsteps: int = 400, nx: int = 128, ny: int = 64,
     return w
 
 
+def merge_marker_sets(sets) -> MarkerSet:
+    """One marker set of several bodies: markers concatenated in order, bone
+    indices of body j shifted by the bone counts of bodies 0 .. j-1."""
+    off = np.cumsum([0] + [m.nbones for m in sets])
+    joints = [m.joints_rest for m in sets]
+    return MarkerSet(xrest=np.concatenate([m.xrest for m in sets], axis=1),
+                     bone=np.concatenate([m.bone + off[j] for j, m in enumerate(sets)], axis=1).astype(np.int32),
+                     weight=np.concatenate([m.weight for m in sets], axis=1),
+                     dv=np.concatenate([m.dv for m in sets]), nbones=int(off[-1]),
+                     area=float(sum(m.area for m in sets)),
+                     joints_rest=None if any(j is None for j in joints) else np.concatenate(joints, axis=0))
+
+
+def two_fish_workload(nsteps: int = 400, nx: int = 150, ny: int = 50, nz: int = 100, length: float = 40.0,
+                      n: int = 2000, u_in: float = 0.04, lag: float = 0.25) -> Workload:
+    """Two swimmers in one domain (the paper's two-fish domain, 150x50x100):
+    fish of length 40 with 2,000 markers each, heads at (40, ny/2, nz/3) and
+    (50, ny/2, 2 nz/3), both bending in the x-y plane with the travelling wave
+    of fish_workload (period 400 steps), the second lagging by `lag` of a
+    period. Inertial frame, inflow u = (u_in, 0, 0) at x = 0, zero-gradient
+    outlet, fluid initially at the inflow velocity, tau = 0.6. One marker set
+    of 20 bones: fish j owns bones 10 j .. 10 j + 9 and markers
+    n j .. n j + n - 1 (meta['fish_bones'], meta['fish_markers'])."""
+    steps = np.arange(nsteps)
+    heads = [(40.0, ny / 2.0, nz / 3.0), (50.0, ny / 2.0, 2.0 * nz / 3.0)]
+    sets, poses = [], []
+    for j, head in enumerate(heads):
+        ms = fish_surface(n, length, head)
+        psi, psid = wave_headings(length, 10, steps - lag * 400.0 * j)
+        poses.append(chain_poses(psi, psid, ms.joints_rest))
+        sets.append(ms)
+    ms = merge_marker_sets(sets)
+    uv = np.array([u_in, 0.0, 0.0])
+    frames = make_frames(nsteps, origin=ms.xrest.mean(axis=1), u_lo=uv, u_hi=uv)
+    u0 = np.broadcast_to(uv.reshape(3, 1, 1, 1), (3, nz, ny, nx)).copy()
+    w = Workload(f"two-fish-{nx}x{ny}x{nz}", nx, ny, nz, 0.6, BC_VELOCITY, BC_OUTFLOW, nsteps, u0, ms,
+                 np.concatenate(poses, axis=1), frames, heading=np.array([-1.0, 0.0, 0.0]))
+    w.meta.update(fish_bones=[(0, 10), (10, 20)], fish_markers=[(0, n), (n, 2 * n)])
+    return w
+
+
 def _max_marker_speed(ms: MarkerSet, pose: np.ndarray) -> float:
     """Largest skinned marker speed of one pose (rates included)."""
     U = np.zeros((3, ms.n))

@@ -87,3 +87,23 @@ def test_fin_pose_jacobian_matches_central_differences():
         e[j] = h
         fd = (I.fin_poses(p + e, ms, steps) - I.fin_poses(p - e, ms, steps)) / (2 * h)
         np.testing.assert_allclose(J[..., j], fd, atol=1e-7 * max(1.0, np.abs(J[..., j]).max()))
+
+
+def test_two_fish_workload_structure():
+    w = I.two_fish_workload(nsteps=40)
+    ms = w.markers
+    assert (w.nx, w.ny, w.nz) == (150, 50, 100) and ms.n == 4000 and ms.nbones == 20
+    assert w.poses.shape == (40, 20, 24)
+    (b0, b1), (c0, c1) = w.meta["fish_bones"][1], w.meta["fish_markers"][1]
+    assert ms.bone[:, :c0].max() < b0 and ms.bone[:, c0:c1].min() >= b0 and ms.bone[:, c0:c1].max() < b1
+    np.testing.assert_allclose(ms.weight.sum(0), 1.0, atol=1e-15)
+    # each fish follows its own chain: the merged poses of fish 1 equal a lone fish's poses
+    lone = I.fish_surface(2000, 40.0, (50.0, 25.0, 200.0 / 3.0))
+    psi, psid = I.wave_headings(40.0, 10, np.arange(40) - 100.0)
+    np.testing.assert_allclose(w.poses[:, 10:], I.chain_poses(psi, psid, lone.joints_rest), atol=1e-12)
+    # the bodies stay apart and inside the open x faces
+    for p in w.poses[::10]:
+        X = I.skin_positions(ms, p)
+        assert X[0].min() >= 2.0 and X[0].max() < w.nx - 3.0
+        gap = np.linalg.norm(X[:, :2000, None] - X[:, None, 2000::11], axis=0).min()
+        assert gap > 10.0
