@@ -131,6 +131,8 @@ struct OrParams {
   int32_t mdf_iters;     // >= 1; 1 is plain explicit direct forcing
   double tau;
   double ib_alpha;       // direct-forcing gain
+  int32_t bc_y[2];       // y = 0 and y = ny-1 (0: periodic, the default)
+  int32_t bc_z[2];       // z = 0 and z = nz-1
 };
 
 // Frame of reference for one step (Eq. (3)): linear acceleration of the
@@ -319,26 +321,41 @@ inline int wrap(int i, int n) { return ((i % n) + n) % n; }
 
 struct Grid {
   int nx, ny, nz;
-  bool xper;
+  bool per[3];     // axis periodic; otherwise both of its faces are open
+  int bc[3][2];    // face conditions (low, high) of each open axis
   size_t ncell() const { return (size_t)nx * ny * nz; }
   size_t idx(int x, int y, int z) const { return (size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * z); }
+  int n(int a) const { return a == 0 ? nx : (a == 1 ? ny : nz); }
 };
+
+// The grid of a parameter set; false if an axis has one periodic and one open face.
+bool make_grid(const OrParams *p, Grid &G) {
+  const int32_t b[3][2] = {{p->bc_lo, p->bc_hi}, {p->bc_y[0], p->bc_y[1]}, {p->bc_z[0], p->bc_z[1]}};
+  G.nx = p->nx;
+  G.ny = p->ny;
+  G.nz = p->nz;
+  for (int a = 0; a < 3; ++a) {
+    G.per[a] = b[a][0] == OR_BC_PERIODIC;
+    if (G.per[a] != (b[a][1] == OR_BC_PERIODIC)) return false;
+    G.bc[a][0] = b[a][0];
+    G.bc[a][1] = b[a][1];
+  }
+  return true;
+}
 
 // The 4x4x4 stencil of a marker: nodes floor(X)-1 .. floor(X)+2 per axis,
 // indices wrapped on periodic axes. Returns false if a node falls outside a
 // non-periodic axis (the caller rejects such markers beforehand).
 template <class T>
 bool stencil(const Grid &G, const T X[3], int nodes[3][4], T wts[3][4]) {
-  int n[3] = {G.nx, G.ny, G.nz};
-  bool per[3] = {G.xper, true, true};
   for (int a = 0; a < 3; ++a) {
     int base = (int)std::floor(val(X[a])) - 1;
     for (int s = 0; s < 4; ++s) {
       int j = base + s;
       wts[a][s] = phi(X[a] - (double)j);
-      if (per[a]) {
-        j = wrap(j, n[a]);
-      } else if (j < 0 || j >= n[a]) {
+      if (G.per[a]) {
+        j = wrap(j, G.n(a));
+      } else if (j < 0 || j >= G.n(a)) {
         return false;
       }
       nodes[a][s] = j;
@@ -414,7 +431,38 @@ void node_fields(const Grid &G, const T *f, const T *g, const OrFrame *fr, T *rh
       }
 }
 
-bool is_open_plane(const Grid &G, int x) { return !G.xper && (x == 0 || x == G.nx - 1); }
+// Inward step of node (x, y, z) along each axis: +1 on an open low face, -1 on
+// an open high face, 0 elsewhere. A node with any nonzero step is a boundary
+// node; its inward neighbour (node + step) is the node it extrapolates from.
+bool boundary_step(const Grid &G, int x, int y, int z, int d[3]) {
+  const int c[3] = {x, y, z};
+  bool any = false;
+  for (int a = 0; a < 3; ++a) {
+    d[a] = 0;
+    if (G.per[a]) continue;
+    if (c[a] == 0) d[a] = 1;
+    else if (c[a] == G.n(a) - 1) d[a] = -1;
+    any = any || d[a] != 0;
+  }
+  return any;
+}
+
+// Face condition that sets a boundary node's velocity: its first velocity face
+// in the order x low, x high, y low, y high, z low, z high (0: none, then the
+// node is an outflow node); *face_u is that face's velocity (u_hi for the x
+// high face, u_lo for every other face: in the local moving domain every
+// open face sees the same far field).
+int boundary_velocity(const Grid &G, const OrFrame *fr, const int d[3], const double **face_u) {
+  for (int a = 0; a < 3; ++a)
+    for (int side = 0; side < 2; ++side) {
+      if (d[a] != (side == 0 ? 1 : -1)) continue;
+      if (G.bc[a][side] == OR_BC_VELOCITY) {
+        *face_u = (a == 0 && side == 1) ? fr->u_hi : fr->u_lo;
+        return 1;
+      }
+    }
+  return 0;
+}
 
 }  // namespace
 
@@ -422,14 +470,16 @@ extern "C" {
 
 // Interpolation of a [ncomp][cells] field to n markers (tests).
 int or_interpolate(const OrParams *p, const double *field, int ncomp, const double *X, int n, double *out) {
-  Grid G{p->nx, p->ny, p->nz, p->bc_lo == OR_BC_PERIODIC};
+  Grid G;
+  if (!make_grid(p, G)) return -1;
   interpolate(G, field, ncomp, X, n, out);
   return 0;
 }
 
 // Spreading of n marker forces Fdv = F dV onto g [3][cells] (tests).
 int or_spread(const OrParams *p, const double *X, int n, const double *Fdv, double *g) {
-  Grid G{p->nx, p->ny, p->nz, p->bc_lo == OR_BC_PERIODIC};
+  Grid G;
+  if (!make_grid(p, G)) return -1;
   spread(G, X, n, Fdv, g);
   return 0;
 }
@@ -438,7 +488,8 @@ int or_spread(const OrParams *p, const double *X, int n, const double *Fdv, doub
 // force excluded) of the pre-collision state f. This is the velocity field
 // the step interpolates to the markers and the one reported as "the velocity".
 int or_macros(const OrParams *p, const double *f, const OrFrame *fr, double *rho, double *u) {
-  Grid G{p->nx, p->ny, p->nz, p->bc_lo == OR_BC_PERIODIC};
+  Grid G;
+  if (!make_grid(p, G)) return -1;
   node_fields(G, f, (const double *)nullptr, fr, rho, u);
   return 0;
 }
@@ -461,10 +512,9 @@ template <class T>
 int run(const OrParams *p, T *f, const OrMarkers *mk, const T *poses, const OrFrame *frames, int nsteps, T *wrench,
         T *Xout, T *Uout, T *Fout) {
   if (!p || !f || p->nx < 4 || p->ny < 4 || p->nz < 4 || !(p->tau > 0.5)) return -1;
-  const bool xper = p->bc_lo == OR_BC_PERIODIC;
-  if (xper != (p->bc_hi == OR_BC_PERIODIC)) return -1;
+  Grid G;
+  if (!make_grid(p, G)) return -1;
   if (p->mdf_iters < 1) return -1;
-  Grid G{p->nx, p->ny, p->nz, xper};
   const size_t N = G.ncell();
   const double tau = p->tau;
   const int nm = mk ? mk->n : 0;
@@ -479,9 +529,10 @@ int run(const OrParams *p, T *f, const OrMarkers *mk, const T *poses, const OrFr
     // (1) marker positions and velocities for this step
     if (nm > 0) {
       skin(mk, poses + (size_t)step * mk->nbones * 24, X.data(), U.data());
-      if (!xper)
-        for (int k = 0; k < nm; ++k)
-          if (!(val(X[k]) >= 2.0 && val(X[k]) < p->nx - 3.0)) return -4;
+      for (int a = 0; a < 3; ++a)
+        if (!G.per[a])
+          for (int k = 0; k < nm; ++k)
+            if (!(val(X[a * nm + k]) >= 2.0 && val(X[a * nm + k]) < G.n(a) - 3.0)) return -4;
     }
 
     // (2) density and unforced velocity at every node
@@ -517,7 +568,8 @@ int run(const OrParams *p, T *f, const OrMarkers *mk, const T *poses, const OrFr
     for (int z = 0; z < G.nz; ++z)
       for (int y = 0; y < G.ny; ++y)
         for (int x = 0; x < G.nx; ++x) {
-          if (is_open_plane(G, x)) continue;
+          int d[3];
+          if (boundary_step(G, x, y, z, d)) continue;
           size_t id = G.idx(x, y, z);
           T fl[27], fo[27];
           for (int i = 0; i < 27; ++i) fl[i] = f[i * N + id];
@@ -531,20 +583,21 @@ int run(const OrParams *p, T *f, const OrMarkers *mk, const T *poses, const OrFr
     // takes its inward neighbour x_f's density and non-equilibrium part:
     //   f*_i(x_b) = f^eq_i(rho_f, u_b) + (1 - 1/tau) (f_i(x_f) - f^eq_i(rho_f, u_f))
     //               + (1 - 1/(2 tau)) w_i [3 (c_i - u_b) + 9 (c_i.u_b) c_i] . F_b
-    // u_f is x_f's fluid velocity (with its force half-term, the same
-    // definition the collision uses); u_b is the prescribed velocity
-    // (velocity face) or u_f (outflow face); F_b = rho_f a_ni(x_b, u_b) is the
-    // frame force alone (markers never reach a boundary node).
-    if (!xper) {
-      for (int side = 0; side < 2; ++side) {
-        int xb = side == 0 ? 0 : G.nx - 1;
-        int xf = side == 0 ? 1 : G.nx - 2;
-        int bc = side == 0 ? p->bc_lo : p->bc_hi;
-        const double *uface = side == 0 ? fr->u_lo : fr->u_hi;
+    // x_f is x_b moved one node inward along each open axis it lies on (a
+    // diagonal neighbour on edges and corners); u_f is x_f's fluid velocity
+    // (with its force half-term, the same definition the collision uses); u_b
+    // is the prescribed velocity of x_b's velocity face, or u_f when it lies on
+    // outflow faces only; F_b = rho_f a_ni(x_b, u_b) is the frame force alone
+    // (markers never reach a boundary node).
+    if (!(G.per[0] && G.per[1] && G.per[2])) {
 #pragma omp parallel for schedule(static)
-        for (int z = 0; z < G.nz; ++z)
-          for (int y = 0; y < G.ny; ++y) {
-            size_t idf = G.idx(xf, y, z), idb = G.idx(xb, y, z);
+      for (int z = 0; z < G.nz; ++z)
+        for (int y = 0; y < G.ny; ++y)
+          for (int x = 0; x < G.nx; ++x) {
+            int d[3];
+            if (!boundary_step(G, x, y, z, d)) continue;
+            const int xf = x + d[0], yf = y + d[1], zf = z + d[2];
+            size_t idf = G.idx(xf, yf, zf), idb = G.idx(x, y, z);
             T fl[27], r = 0.0, m[3] = {0.0, 0.0, 0.0};
             for (int i = 0; i < 27; ++i) {
               fl[i] = f[i * N + idf];
@@ -552,12 +605,14 @@ int run(const OrParams *p, T *f, const OrMarkers *mk, const T *poses, const OrFr
               for (int a = 0; a < 3; ++a) m[a] += fl[i] * (double)L.c[i][a];
             }
             T gf[3] = {g[idf], g[N + idf], g[2 * N + idf]};
-            double posf[3] = {(double)xf, (double)y, (double)z};
-            double posb[3] = {(double)xb, (double)y, (double)z};
+            double posf[3] = {(double)xf, (double)yf, (double)zf};
+            double posb[3] = {(double)x, (double)y, (double)z};
             T uf[3], Ff[3];
             node_velocity(r, m, gf, fr, posf, uf, Ff);
+            const double *uface = nullptr;
+            const int vel = boundary_velocity(G, fr, d, &uface);
             T ub[3];
-            for (int a = 0; a < 3; ++a) ub[a] = (bc == OR_BC_VELOCITY) ? T(uface[a]) : uf[a];
+            for (int a = 0; a < 3; ++a) ub[a] = vel ? T(uface[a]) : uf[a];
             double a0[3];
             T wu[3], Fb[3];
             frame_accel_static(fr, posb, a0);
@@ -575,23 +630,22 @@ int run(const OrParams *p, T *f, const OrMarkers *mk, const T *poses, const OrFr
               fpost[i * N + idb] = feq_b[i] + (1.0 - 1.0 / tau) * (fl[i] - feq_f[i]) + pref * L.w[i] * s;
             }
           }
-      }
     }
 
     // (8) streaming: f_i(x, n+1) = f*_i(x - c_i, n). Periodic axes wrap; a
-    // source outside an open x face is replaced by the face node itself (those
-    // values are never used: extrapolation overwrites the face nodes).
+    // source outside an open face is replaced by the nearest node on it (those
+    // values are never used: extrapolation overwrites the boundary nodes).
 #pragma omp parallel for schedule(static)
     for (int z = 0; z < G.nz; ++z)
       for (int y = 0; y < G.ny; ++y)
         for (int x = 0; x < G.nx; ++x)
           for (int i = 0; i < 27; ++i) {
-            int sx = x - L.c[i][0], sy = wrap(y - L.c[i][1], G.ny), sz = wrap(z - L.c[i][2], G.nz);
-            if (xper)
-              sx = wrap(sx, G.nx);
-            else
-              sx = sx < 0 ? 0 : (sx >= G.nx ? G.nx - 1 : sx);
-            f[i * N + G.idx(x, y, z)] = fpost[i * N + G.idx(sx, sy, sz)];
+            int sc[3] = {x - L.c[i][0], y - L.c[i][1], z - L.c[i][2]};
+            for (int a = 0; a < 3; ++a) {
+              const int na = G.n(a);
+              sc[a] = G.per[a] ? wrap(sc[a], na) : (sc[a] < 0 ? 0 : (sc[a] >= na ? na - 1 : sc[a]));
+            }
+            f[i * N + G.idx(x, y, z)] = fpost[i * N + G.idx(sc[0], sc[1], sc[2])];
           }
 
     // (9) the fluid's force, torque and power on the body: the body exerts

@@ -338,6 +338,8 @@ class Workload:
     mdf_iters: int = 1
     ib_alpha: float = 1.0
     meta: dict = dataclasses.field(default_factory=dict)
+    bc_y: tuple = (BC_PERIODIC, BC_PERIODIC)  # y = 0, y = ny-1
+    bc_z: tuple = (BC_PERIODIC, BC_PERIODIC)  # z = 0, z = nz-1
 
     @property
     def ncell(self) -> int:
