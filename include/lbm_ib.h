@@ -58,8 +58,14 @@ typedef enum {
   LBM_ERR_UNSUPPORTED = -6   /* valid request this build does not implement */
 } lbm_status;
 
-/* Face conditions for x = 0 (bc_lo) and x = nx-1 (bc_hi). Both periodic, or
- * both open (each VELOCITY or OUTFLOW). */
+/* Face conditions. Each axis is periodic on both faces, or open on both (each
+ * face VELOCITY or OUTFLOW): x by bc_lo (x = 0) and bc_hi (x = nx-1), y and z
+ * by bc_y[2] and bc_z[2] (low, high). An open face takes the non-equilibrium
+ * extrapolation of Sec. III-B from the node one step inward along every open
+ * axis the boundary node lies on (a diagonal neighbour on edges and corners);
+ * a node's velocity comes from its first velocity face in the order x low,
+ * x high, y low, y high, z low, z high (u_lo of the frame, u_hi for x high),
+ * or from its inward neighbour when it lies on outflow faces only. */
 enum { LBM_BC_PERIODIC = 0, LBM_BC_VELOCITY = 1, LBM_BC_OUTFLOW = 2 };
 
 /* Population storage. F32 stores f_i. F16 and BF16 store h_i = f_i - w_i
@@ -82,12 +88,14 @@ typedef struct {
   int32_t with_adjoint;      /* nonzero: workspace also holds the adjoint buffers */
   double tau;                /* BGK relaxation time, > 1/2 (nu = (tau - 1/2)/3) */
   double ib_alpha;           /* direct-forcing gain, > 0 (1 = full correction) */
+  int32_t bc_y[2], bc_z[2];  /* LBM_BC_* for the y and z faces; zeros = periodic */
 } lbm_params;
 
 /* [host] Frame of one step (Eq. (3)). acc = linear acceleration of the frame
  * origin, omega = angular velocity, alpha = angular acceleration (vectors in
  * frame coordinates); x' = x - origin. u_lo / u_hi = velocity prescribed on
- * the x = 0 / x = nx-1 face when that face is LBM_BC_VELOCITY. */
+ * the x = 0 / x = nx-1 face when that face is LBM_BC_VELOCITY; y and z
+ * velocity faces take u_lo (the far field of the local moving domain). */
 typedef struct {
   double acc[3], omega[3], alpha[3], origin[3], u_lo[3], u_hi[3];
 } lbm_frame;

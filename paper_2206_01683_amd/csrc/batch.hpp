@@ -68,6 +68,24 @@ __device__ inline int dynamic_prefix(const BatchArgs &b, int mult, int *s_pre, i
 __device__ inline FrameF env_frame(const EnvView &e, int s) { return frame_from(e.frames + (size_t)18 * s); }
 __device__ inline int env_cur(const EnvView &e, int s) { return e.cur0 ^ (s & 1); }
 
+// collide_cell for any environment: boundary kind and frame chosen at run time.
+__device__ inline void collide_any(const EnvView &e, const FrameF &fr, int cur, int lb, int tx, int ty) {
+  if (!(e.g.yper && e.g.zper)) {
+    if (e.g.xper)
+      e.rot ? collide_cell<StoreF32, true, true, true>(e, fr, cur, lb, tx, ty)
+            : collide_cell<StoreF32, true, false, true>(e, fr, cur, lb, tx, ty);
+    else
+      e.rot ? collide_cell<StoreF32, false, true, true>(e, fr, cur, lb, tx, ty)
+            : collide_cell<StoreF32, false, false, true>(e, fr, cur, lb, tx, ty);
+  } else if (e.g.xper) {
+    e.rot ? collide_cell<StoreF32, true, true>(e, fr, cur, lb, tx, ty)
+          : collide_cell<StoreF32, true, false>(e, fr, cur, lb, tx, ty);
+  } else {
+    e.rot ? collide_cell<StoreF32, false, true>(e, fr, cur, lb, tx, ty)
+          : collide_cell<StoreF32, false, false>(e, fr, cur, lb, tx, ty);
+  }
+}
+
 // ------------------------------------------------------------ phase bodies --
 __device__ inline void phase_skin(const BatchArgs &b, int s, int item, int tid) {
   const int ei = find_env(b.pre + PRE_SKIN * (b.nenv + 1), b.nenv, item);
@@ -132,19 +150,10 @@ __device__ inline void phase_collide(const BatchArgs &b, int s, int item, int ti
   const int lb = item - b.pre[PRE_COLLIDE * (b.nenv + 1) + ei];
   const int cur = env_cur(e, s);
   const int tx = tid % e.bx, ty = tid / e.bx;
-  if (UNI) {
+  if (UNI)
     collide_cell<StoreF32, false, false>(e, fr, cur, lb, tx, ty);
-  } else if (e.g.xper) {
-    if (e.rot)
-      collide_cell<StoreF32, true, true>(e, fr, cur, lb, tx, ty);
-    else
-      collide_cell<StoreF32, true, false>(e, fr, cur, lb, tx, ty);
-  } else {
-    if (e.rot)
-      collide_cell<StoreF32, false, true>(e, fr, cur, lb, tx, ty);
-    else
-      collide_cell<StoreF32, false, false>(e, fr, cur, lb, tx, ty);
-  }
+  else
+    collide_any(e, fr, cur, lb, tx, ty);
 }
 
 // Collide items [i0, i1) in order, looking the environment up once per run
@@ -162,19 +171,10 @@ __device__ inline void collide_range(const BatchArgs &b, int s, int i0, int i1, 
     const int tx = tid % e.bx, ty = tid / e.bx;
     for (; item < hi; ++item) {
       const int lb = item - lo;
-      if (UNI) {
+      if (UNI)
         collide_cell<StoreF32, false, false>(e, fr, cur, lb, tx, ty);
-      } else if (e.g.xper) {
-        if (e.rot)
-          collide_cell<StoreF32, true, true>(e, fr, cur, lb, tx, ty);
-        else
-          collide_cell<StoreF32, true, false>(e, fr, cur, lb, tx, ty);
-      } else {
-        if (e.rot)
-          collide_cell<StoreF32, false, true>(e, fr, cur, lb, tx, ty);
-        else
-          collide_cell<StoreF32, false, false>(e, fr, cur, lb, tx, ty);
-      }
+      else
+        collide_any(e, fr, cur, lb, tx, ty);
     }
   }
 }

@@ -13,6 +13,8 @@ struct GridArgs {
   int xper;        // 1: x periodic
   int bc_lo, bc_hi;
   int tnx, tny;    // 8^3 tile grid (x, y extents)
+  int yper, zper;  // 1: y (z) periodic; otherwise both faces open
+  int bc_y[2], bc_z[2];
 };
 
 struct EnvView {

@@ -99,15 +99,16 @@ __device__ inline void load_g(const GridArgs &g, const int *__restrict__ tile_sl
 // f_i + f^eq_i(rho_f, u_b) - f^eq_i(rho_f, u_f) makes the BGK formula with
 // (rho_f, u_b, F_b) produce exactly the extrapolated values.
 //
-// A cell of the collide and, for an open-face lane, the inward neighbour
-// x_f = xs whose populations it reads.
+// A cell of the collide and, for a boundary lane, the inward neighbour
+// (xs, ys, zs) whose populations it reads.
 struct CellAt {
-  int x, y, z, xs;
+  int x, y, z, xs, ys, zs;
 };
 
 // First half of collide_cell: locate the cell and pull its 27 populations
-// (for an open-face lane, those of x_f). False past the lattice.
-template <class S, bool XPER>
+// (for a boundary lane, those of its inward neighbour). False past the
+// lattice. YZ: y or z may have open faces (otherwise both are periodic).
+template <class S, bool XPER, bool YZ = false>
 __device__ inline bool collide_load(const EnvView &e, int cur, int lb, int tx, int ty, CellAt &c, float f[Q]) {
   using T = typename S::T;
   const T *__restrict__ src = static_cast<const T *>(e.f[cur]);
@@ -125,37 +126,53 @@ __device__ inline bool collide_load(const EnvView &e, int cur, int lb, int tx, i
     xm = xs - 1;
     xp = xs + 1;
   }
-  const int ym = y == 0 ? g.ny - 1 : y - 1;
-  const int yp = y == g.ny - 1 ? 0 : y + 1;
-  const int zm = z == 0 ? g.nz - 1 : z - 1;
-  const int zp = z == g.nz - 1 ? 0 : z + 1;
-  pull27<S>(src, g.plane, g.nx, g.ny, xm, xs, xp, ym, y, yp, zm, z, zp, f);
+  int ys = y, zs = z, ym, yp, zm, zp;
+  if (YZ && !g.yper) {
+    ys = y == 0 ? 1 : (y == g.ny - 1 ? g.ny - 2 : y);
+    ym = ys - 1;
+    yp = ys + 1;
+  } else {
+    ym = y == 0 ? g.ny - 1 : y - 1;
+    yp = y == g.ny - 1 ? 0 : y + 1;
+  }
+  if (YZ && !g.zper) {
+    zs = z == 0 ? 1 : (z == g.nz - 1 ? g.nz - 2 : z);
+    zm = zs - 1;
+    zp = zs + 1;
+  } else {
+    zm = z == 0 ? g.nz - 1 : z - 1;
+    zp = z == g.nz - 1 ? 0 : z + 1;
+  }
+  pull27<S>(src, g.plane, g.nx, g.ny, xm, xs, xp, ym, ys, yp, zm, zs, zp, f);
   c.x = x;
   c.y = y;
   c.z = z;
   c.xs = xs;
+  c.ys = ys;
+  c.zs = zs;
   return true;
 }
 
 // Second half: moments, forcing, BGK + Guo (or the open-face extrapolation)
 // and the 27 stores of f*(n).
-template <class S, bool XPER, bool ROT>
+template <class S, bool XPER, bool ROT, bool YZ = false>
 __device__ inline void collide_finish(const EnvView &e, const FrameF &fr, int cur, const CellAt &c, float f[Q]) {
   using T = typename S::T;
   T *__restrict__ dst = static_cast<T *>(e.f[cur ^ 1]);
   const int *__restrict__ tile_slot = e.ib ? e.tile_slot : nullptr;
   const GridArgs &g = e.g;
   const int x = c.x, y = c.y, z = c.z, xs = c.xs;
+  const int ys = YZ ? c.ys : y, zs = YZ ? c.zs : z;
   const bool lo_face = !XPER && x == 0;
-  const bool face = !XPER && (x == 0 || x == g.nx - 1);
+  const bool face = (!XPER && (x == 0 || x == g.nx - 1)) || (YZ && (ys != y || zs != z));
   float rho, mx, my, mz;
   moments(f, rho, mx, my, mz);
   const float irho = 1.0f / rho;
 
   float gx, gy, gz;
-  load_g(g, tile_slot, e.gfix, xs, y, z, gx, gy, gz);
+  load_g(g, tile_slot, e.gfix, xs, ys, zs, gx, gy, gz);
   float ax, ay, az;
-  frame_a0<ROT>(fr, (float)xs, (float)y, (float)z, ax, ay, az);
+  frame_a0<ROT>(fr, (float)xs, (float)ys, (float)zs, ax, ay, az);
   float ux, uy, uz;
   solve_coriolis<ROT>(fr, mx * irho + 0.5f * (gx * irho + ax), my * irho + 0.5f * (gy * irho + ay),
                       mz * irho + 0.5f * (gz * irho + az), ux, uy, uz);
@@ -168,8 +185,23 @@ __device__ inline void collide_finish(const EnvView &e, const FrameF &fr, int cu
     Fz = gz + rho * (az - 2.0f * wz);
   } else {
     // (ux,uy,uz) is u_f; choose u_b and shift f by f^eq(u_b) - f^eq(u_f)
-    const int bc = lo_face ? g.bc_lo : g.bc_hi;
-    const float *uf = lo_face ? fr.ulo : fr.uhi;
+    int bc;
+    const float *uf;
+    if (!YZ) {
+      bc = lo_face ? g.bc_lo : g.bc_hi;
+      uf = lo_face ? fr.ulo : fr.uhi;
+    } else {
+      // first velocity face of this node: x low, x high, y low, y high, z low, z high
+      bc = 2;
+      uf = fr.ulo;
+      if (!XPER && x != xs && (x == 0 ? g.bc_lo : g.bc_hi) == 1) {
+        bc = 1;
+        uf = x == 0 ? fr.ulo : fr.uhi;
+      } else if ((ys != y && (y == 0 ? g.bc_y[0] : g.bc_y[1]) == 1) ||
+                 (zs != z && (z == 0 ? g.bc_z[0] : g.bc_z[1]) == 1)) {
+        bc = 1;
+      }
+    }
     float bx = bc == 1 ? uf[0] : ux, by = bc == 1 ? uf[1] : uy, bz = bc == 1 ? uf[2] : uz;
     const float ub2 = bx * bx + by * by + bz * bz, uf2 = ux * ux + uy * uy + uz * uz;
 #pragma unroll
@@ -219,24 +251,24 @@ __device__ inline void collide_finish(const EnvView &e, const FrameF &fr, int cu
 
 // One cell of logical block lb (tile shape e.bx x e.by, see cell_of), thread
 // (tx, ty); `cur` is the buffer holding f*(n-1), the other one receives f*(n).
-template <class S, bool XPER, bool ROT>
+template <class S, bool XPER, bool ROT, bool YZ = false>
 __device__ inline void collide_cell(const EnvView &e, const FrameF &fr, int cur, int lb, int tx, int ty) {
   CellAt c;
   float f[Q];
-  if (collide_load<S, XPER>(e, cur, lb, tx, ty, c, f)) collide_finish<S, XPER, ROT>(e, fr, cur, c, f);
+  if (collide_load<S, XPER, YZ>(e, cur, lb, tx, ty, c, f)) collide_finish<S, XPER, ROT, YZ>(e, fr, cur, c, f);
 }
 
 // Single-lattice launch: blockDim = (e.bx, e.by). Blocks are mapped
 // XCD-aware: hardware workgroup b runs on XCD b % 8, so the logical block
 // index gives each XCD a contiguous 1/8 of the domain (shared cache lines of
 // neighbouring blocks stay in one L2).
-template <class S, bool XPER, bool ROT>
+template <class S, bool XPER, bool ROT, bool YZ = false>
 __global__ void __launch_bounds__(512) k_collide(EnvView e, FrameF fr, int cur) {
   const int b = blockIdx.x;
   const int per = (e.nblocks + 7) >> 3;
   const int lb = (b & 7) * per + (b >> 3);
   if (lb >= e.nblocks) return;
-  collide_cell<S, XPER, ROT>(e, fr, cur, lb, threadIdx.x, threadIdx.y);
+  collide_cell<S, XPER, ROT, YZ>(e, fr, cur, lb, threadIdx.x, threadIdx.y);
 }
 
 // f_i(x) of the caller's canonical pre-collision field -> stored buffer, i.e.

@@ -104,7 +104,7 @@ __device__ inline void skin_item(const EnvView &e, const float *__restrict__ pos
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
       const float nn = (float)dims[ax];
-      const bool per = ax > 0 || e.g.xper;
+      const bool per = ax == 0 ? e.g.xper != 0 : (ax == 1 ? e.g.yper != 0 : e.g.zper != 0);
       if (per) {
         float q = p[ax] - nn * floorf(p[ax] / nn);
         if (!(q >= 0.f && q < nn)) q = 0.f;
@@ -120,8 +120,8 @@ __device__ inline void skin_item(const EnvView &e, const float *__restrict__ pos
     e.mbase[k] = make_short4((short)bs[0], (short)bs[1], (short)bs[2], 0);
     int tx[3], ty[3], tz[3];
     const int nxt = axis_tiles(bs[0], e.g.nx, e.g.xper, tx);
-    const int nyt = axis_tiles(bs[1], e.g.ny, true, ty);
-    const int nzt = axis_tiles(bs[2], e.g.nz, true, tz);
+    const int nyt = axis_tiles(bs[1], e.g.ny, e.g.yper, ty);
+    const int nzt = axis_tiles(bs[2], e.g.nz, e.g.zper, tz);
     for (int i = 0; i < nzt; ++i)
       for (int j = 0; j < nyt; ++j)
         for (int l = 0; l < nxt; ++l) e.tile_flag[tx[l] + e.g.tnx * (ty[j] + e.g.tny * tz[i])] = 1;

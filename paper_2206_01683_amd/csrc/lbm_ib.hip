@@ -35,9 +35,11 @@ bool params_ok(const lbm_params *p) {
   if (p->nx < 4 || p->ny < 4 || p->nz < 4) return false;
   if ((int64_t)p->nx * p->ny * p->nz > (int64_t)1 << 31) return false;
   if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return false;
-  const bool lo_per = p->bc_lo == LBM_BC_PERIODIC, hi_per = p->bc_hi == LBM_BC_PERIODIC;
-  if (lo_per != hi_per) return false;
-  if (p->bc_lo < 0 || p->bc_lo > 2 || p->bc_hi < 0 || p->bc_hi > 2) return false;
+  const int32_t faces[3][2] = {{p->bc_lo, p->bc_hi}, {p->bc_y[0], p->bc_y[1]}, {p->bc_z[0], p->bc_z[1]}};
+  for (int a = 0; a < 3; ++a) {
+    if (faces[a][0] < 0 || faces[a][0] > 2 || faces[a][1] < 0 || faces[a][1] > 2) return false;
+    if ((faces[a][0] == LBM_BC_PERIODIC) != (faces[a][1] == LBM_BC_PERIODIC)) return false;
+  }
   if (p->storage < LBM_STORE_F32 || p->storage > LBM_STORE_BF16) return false;
   if (p->max_markers < 0 || p->max_markers > (1 << 24)) return false;
   if (p->max_bones < 1 || p->mdf_iters < 1 || p->mdf_iters > 16) return false;
@@ -141,6 +143,12 @@ GridArgs grid_args(const lbm_ctx *c) {
   g.bc_hi = c->p.bc_hi;
   g.tnx = c->L.tnx;
   g.tny = c->L.tny;
+  g.yper = c->p.bc_y[0] == LBM_BC_PERIODIC;
+  g.zper = c->p.bc_z[0] == LBM_BC_PERIODIC;
+  for (int q = 0; q < 2; ++q) {
+    g.bc_y[q] = c->p.bc_y[q];
+    g.bc_z[q] = c->p.bc_z[q];
+  }
   return g;
 }
 
@@ -235,14 +243,24 @@ lbm_status launch_collide(lbm_ctx *c, const EnvView &e, const FrameF &fr, bool r
   const int grid = ((e.nblocks + 7) / 8) * 8;
   const dim3 blk = collide_block(c);
   const bool xper = e.g.xper;
-  if (xper && rot)
+  if (!(e.g.yper && e.g.zper)) {  // open y or z faces
+    if (xper && rot)
+      k_collide<S, true, true, true><<<grid, blk, 0, c->stream>>>(e, fr, c->cur);
+    else if (xper)
+      k_collide<S, true, false, true><<<grid, blk, 0, c->stream>>>(e, fr, c->cur);
+    else if (rot)
+      k_collide<S, false, true, true><<<grid, blk, 0, c->stream>>>(e, fr, c->cur);
+    else
+      k_collide<S, false, false, true><<<grid, blk, 0, c->stream>>>(e, fr, c->cur);
+  } else if (xper && rot) {
     k_collide<S, true, true><<<grid, blk, 0, c->stream>>>(e, fr, c->cur);
-  else if (xper)
+  } else if (xper) {
     k_collide<S, true, false><<<grid, blk, 0, c->stream>>>(e, fr, c->cur);
-  else if (rot)
+  } else if (rot) {
     k_collide<S, false, true><<<grid, blk, 0, c->stream>>>(e, fr, c->cur);
-  else
+  } else {
     k_collide<S, false, false><<<grid, blk, 0, c->stream>>>(e, fr, c->cur);
+  }
   return launched();
 }
 
@@ -495,6 +513,7 @@ lbm_status adjoint_request_ok(const lbm_ctx *c, const lbm_markers *m, const floa
   for (int q = 0; q < 4; ++q)
     if (!std::isfinite(w[q])) return LBM_ERR_ARG;
   if (c->p.storage != LBM_STORE_F32 || c->p.mdf_iters != 1 || !c->p.with_adjoint) return LBM_ERR_UNSUPPORTED;
+  if (c->p.bc_y[0] != LBM_BC_PERIODIC || c->p.bc_z[0] != LBM_BC_PERIODIC) return LBM_ERR_UNSUPPORTED;
   return LBM_OK;
 }
 
@@ -955,8 +974,12 @@ lbm_status lbm_batch_create(lbm_batch **out, const lbm_env *envs, int32_t nenv, 
   b->graph_nsteps = -1;
   b->graph_mode = -1;
   b->uniform = true;
-  for (int e = 0; e < nenv; ++e)
-    if (envs[e].rotating || envs[e].ctx->p.bc_lo == LBM_BC_PERIODIC) b->uniform = false;
+  for (int e = 0; e < nenv; ++e) {
+    const lbm_params &q = envs[e].ctx->p;
+    if (envs[e].rotating || q.bc_lo == LBM_BC_PERIODIC || q.bc_y[0] != LBM_BC_PERIODIC ||
+        q.bc_z[0] != LBM_BC_PERIODIC)
+      b->uniform = false;
+  }
   int dev_id = 0, cus = 0, per_cu[2] = {0, 0};
   if (hipGetDevice(&dev_id) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id) != hipSuccess ||

@@ -31,7 +31,8 @@ class Params(ctypes.Structure):
                 ("bc_lo", ctypes.c_int32), ("bc_hi", ctypes.c_int32), ("storage", ctypes.c_int32),
                 ("max_markers", ctypes.c_int32), ("max_bones", ctypes.c_int32), ("mdf_iters", ctypes.c_int32),
                 ("max_active_tiles", ctypes.c_int32), ("block_x", ctypes.c_int32), ("block_y", ctypes.c_int32),
-                ("with_adjoint", ctypes.c_int32), ("tau", ctypes.c_double), ("ib_alpha", ctypes.c_double)]
+                ("with_adjoint", ctypes.c_int32), ("tau", ctypes.c_double), ("ib_alpha", ctypes.c_double),
+                ("bc_y", ctypes.c_int32 * 2), ("bc_z", ctypes.c_int32 * 2)]
 
 
 class Frame(ctypes.Structure):
@@ -131,10 +132,11 @@ def _check(rc: int, what: str):
 
 
 def make_params(nx, ny, nz, tau, bc_lo=BC_PERIODIC, bc_hi=BC_PERIODIC, storage="f32", max_markers=0,
-                max_bones=1, mdf_iters=1, ib_alpha=1.0, max_active_tiles=0, block=(0, 0), with_adjoint=False) -> Params:
+                max_bones=1, mdf_iters=1, ib_alpha=1.0, max_active_tiles=0, block=(0, 0), with_adjoint=False,
+                bc_y=(BC_PERIODIC, BC_PERIODIC), bc_z=(BC_PERIODIC, BC_PERIODIC)) -> Params:
     return Params(nx, ny, nz, bc_lo, bc_hi, STORAGE[storage] if isinstance(storage, str) else storage,
                   max_markers, max_bones, mdf_iters, max_active_tiles, block[0], block[1], 1 if with_adjoint else 0,
-                  tau, ib_alpha)
+                  tau, ib_alpha, (ctypes.c_int32 * 2)(*bc_y), (ctypes.c_int32 * 2)(*bc_z))
 
 
 def frames_array(frames: np.ndarray) -> np.ndarray:
@@ -173,14 +175,15 @@ class Simulation:
 
     def __init__(self, nx, ny, nz, tau, bc_lo=BC_PERIODIC, bc_hi=BC_PERIODIC, storage="f32", max_markers=0,
                  max_bones=1, mdf_iters=1, ib_alpha=1.0, rho0=None, u0=None, device="cuda", block=(0, 0),
-                 max_active_tiles=0, stream=None, with_adjoint=False):
+                 max_active_tiles=0, stream=None, with_adjoint=False, bc_y=(BC_PERIODIC, BC_PERIODIC),
+                 bc_z=(BC_PERIODIC, BC_PERIODIC)):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the lattice Boltzmann library runs only on the GPU")
         L = lib()
         self.device = torch.device(device)
         self.shape = (nz, ny, nx)
         self.params = make_params(nx, ny, nz, tau, bc_lo, bc_hi, storage, max_markers, max_bones, mdf_iters,
-                                  ib_alpha, max_active_tiles, block, with_adjoint)
+                                  ib_alpha, max_active_tiles, block, with_adjoint, bc_y, bc_z)
         pb = L.lbm_population_bytes(ctypes.byref(self.params))
         wb = L.lbm_workspace_bytes(ctypes.byref(self.params))
         if pb == 0 or wb == 0:
@@ -369,7 +372,8 @@ class Batch:
                 sim = Simulation(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi, max_markers=w.markers.n,
                                  max_bones=w.markers.nbones, mdf_iters=w.mdf_iters, ib_alpha=w.ib_alpha,
                                  u0=w.u0.astype(np.float32), device=self.device, block=block,
-                                 max_active_tiles=min(ntiles, max_active_tiles), stream=self.stream)
+                                 max_active_tiles=min(ntiles, max_active_tiles), stream=self.stream,
+                                 bc_y=w.bc_y, bc_z=w.bc_z)
                 dm = DeviceMarkers(w.markers, self.device)
                 poses = torch.as_tensor(np.ascontiguousarray(w.poses[:self.nsteps], np.float32), device=self.device)
                 frames = torch.as_tensor(np.ascontiguousarray(w.frames[:self.nsteps], np.float64), device=self.device)
