@@ -162,6 +162,41 @@ def run_two_fish(steps: int = 200, warmup: int = 20):
             "collide_GBps": round(216 * w.ncell / (col_ms / 1e3 / max(timed, 1)) / 1e9, 1), "status": status}
 
 
+def run_free_swimmer(steps: int = 100, warmup: int = 10):
+    """Two-way coupling: the 384x192x192 fish (12,000 markers) swimming freely,
+    twice as dense as the fluid, free yaw; each step the host body dynamics
+    (lbm_swimmer_*) set the poses and the frame, the GPU runs the step, and the
+    step's wrench comes back (one 32-byte device-to-host copy and a stream
+    synchronization per step). Milliseconds per coupled step."""
+    import numpy as np
+    import torch
+
+    from paper_2206_01683_amd import inputs as I
+    from paper_2206_01683_amd import lbm
+    from paper_2206_01683_amd import swim
+
+    w = I.fish_workload(nsteps=1)
+    ms = w.markers
+    n = warmup + steps
+    psi, psid = I.wave_headings(96.0, 10, np.arange(n + 1))
+    sim = lbm.Simulation(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi, max_markers=ms.n, max_bones=ms.nbones)
+    dm = lbm.DeviceMarkers(ms)
+    sw = swim.FreeSwimmer(ms, 96.0, (160.0, 96.0, 96.0), rho_body=2.0)
+    sw.init(psi[0], psid[0])
+    swim.swim(sim, dm, sw, psi[:warmup + 1], psid[:warmup + 1], warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = swim.swim(sim, dm, sw, psi[warmup:], psid[warmup:], steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    status = sim.check()
+    del sim
+    torch.cuda.empty_cache()
+    return {"workload": w.name, "steps": steps, "ms_per_step": round(wall * 1e3 / steps, 4),
+            "mlups": round(w.ncell * steps / wall / 1e6, 1), "final_velocity": [float(v) for v in out["vel"][-1]],
+            "final_heading": float(out["heading"][-1]), "status": status}
+
+
 def run_adjoint(nsteps: int = 400, every: int = 20):
     """Differentiation form: the 128x64x64 swimmer with 3,000 markers,
     J = time-averaged thrust over nsteps steps. Forward = the steps with a
@@ -224,8 +259,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f32", choices=sorted(BYTES_PER_CELL))
     ap.add_argument("--cpu-steps", type=int, default=24, help="oracle sample length (0: skip)")
-    ap.add_argument("--forms", default="f16,bf16,batched,adjoint,two_fish",
-                    help="comma-separated extra forms to measure: f16, bf16, batched, adjoint, two_fish")
+    ap.add_argument("--forms", default="f16,bf16,batched,adjoint,two_fish,free_swimmer",
+                    help="comma-separated extra forms to measure: f16, bf16, batched, adjoint, two_fish, "
+                         "free_swimmer")
     ap.add_argument("--no-forms", action="store_true", help="measure no extra form")
     ap.add_argument("--block", type=int, nargs=2, default=(0, 0))
     ap.add_argument("--batch-envs", type=int, default=64, help="batched form: environments (0: skip)")
@@ -253,6 +289,8 @@ def main():
         forms["adjoint"] = run_adjoint()
     if "two_fish" in want:
         forms["two_fish"] = run_two_fish()
+    if "free_swimmer" in want:
+        forms["free_swimmer"] = run_free_swimmer()
     traffic = measured_traffic(args.storage)
     ach = main_run["collide_gbs"]
     out = {

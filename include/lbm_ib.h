@@ -227,6 +227,71 @@ lbm_status lbm_adjoint_segment(lbm_ctx *c, const void *ckpt, void *const *ring, 
                                const float *poses, const lbm_frame *frames, const double *w, void *lam,
                                void *lam_tmp, float *pose_bar, void *ib_ring);
 
+/* ------------------------------------------------------------------------
+ * Free swimming (host functions, no device work): the articulated body of
+ * Sec. III-A with the fluid's force as the external generalized force of
+ * Eq. (1), for a planar chain of rigid links whose joint motion is prescribed.
+ * Every joint being prescribed, articulated-body dynamics leaves the floating
+ * base free, and its equations are the whole-body momentum balance
+ * M dV/dt = F (mass centre), d/dt(I_c theta' + L_s) = T (about the mass centre),
+ * I_c the chain's moment of inertia about its mass centre and L_s the angular
+ * momentum of its shape change. The local domain follows the mass centre
+ * (Sec. III-B), so the frame's velocity is the body's and its acceleration
+ * enters the fluid by Eq. (3). Unit time steps, explicit coupling:
+ *   a(n+1) = F(n)/M + r a(n),  V(n+1) = V(n) + a(n)      (translation)
+ *   L(n+1) = L(n) + T(n) + r I_c(n) (theta'(n) - theta'(n-1)),
+ *   theta'(n+1) = (L(n+1) - L_s(n+1)) / I_c(n+1),  theta(n+1) = theta(n) + theta'(n+1)
+ * with r = rho_fluid / rho_body: the direct-forcing force includes the
+ * reaction of the enclosed fluid, carried along with the body, and the r terms
+ * add it back (rigid enclosed fluid). The frame acceleration of a step is
+ * needed before its force is known, hence a(n+1) from F(n). Explicit coupling
+ * is stable only for bodies heavier than the fluid (measured: rho_body /
+ * rho_fluid >= 1.5 with free yaw on the swimmer tests; neutral buoyancy
+ * diverges). The shape of a step is the body-frame heading psi_j of every
+ * link and its rate (the chain of lbm_skin: joint j+1 = joint j + h (cos
+ * psi_j, sin psi_j)). */
+typedef struct {
+  int32_t nbones;             /* links, 1 .. 64 */
+  int32_t free_yaw;           /* 1: the body turns under the fluid's torque; 0: its heading is held */
+  double link_length;         /* h */
+  const double *mass;         /* [nbones] link masses, > 0 */
+  const double *com;          /* [nbones] distance of a link's mass centre from its proximal joint, along it */
+  const double *inertia;      /* [nbones] moment of inertia about z through the link's mass centre, > 0 */
+  const double *joints_rest;  /* [nbones][3] rest joint positions of the skin (lbm_markers' rest pose) */
+  double fluid_ratio;         /* r = rho_fluid / rho_body, >= 0 (0: no enclosed fluid) */
+  double origin[3];           /* where the mass centre sits in the local domain (the frame origin) */
+} lbm_swimmer;
+
+typedef struct {
+  double vel[2];     /* mass-centre velocity in the lab = the local frame's velocity (x, y) */
+  double acc[2];     /* the frame acceleration of the coming step */
+  double heading;    /* theta: rotation of the body frame about z */
+  double spin;       /* theta' of the coming step */
+  double spin_prev;  /* theta' of the step before */
+  double ang_mom;    /* angular momentum about the mass centre (z) */
+  double inertia;    /* I_c of the coming step */
+  double pos[2];     /* mass-centre displacement in the lab since the start */
+} lbm_swimmer_state;
+
+/* Start at mass-centre velocity vel0 [host, 2] (NULL: rest) and heading,
+ * not spinning, with the shape psi, psidot [host, nbones] of step 0. */
+lbm_status lbm_swimmer_init(const lbm_swimmer *s, lbm_swimmer_state *st, const double *vel0, double heading,
+                            const double *psi, const double *psidot);
+
+/* Bone poses [host, nbones][24] (the lbm_ib_step pose layout) and the frame
+ * [host] of the coming step from the state and that step's shape: the mass
+ * centre at s->origin, link j at heading theta + psi_j, velocities relative
+ * to the frame; the frame has the state's acceleration, no rotation, origin
+ * s->origin, and far-field face velocities -vel. */
+lbm_status lbm_swimmer_prepare(const lbm_swimmer *s, const lbm_swimmer_state *st, const double *psi,
+                               const double *psidot, float *poses, lbm_frame *frame);
+
+/* Advance the state over a step whose wrench [host, 8] (lbm_ib_step's: force
+ * (3), torque about the frame origin (3), power, 0) is known, given the shape
+ * psi, psidot of the next step. */
+lbm_status lbm_swimmer_advance(const lbm_swimmer *s, lbm_swimmer_state *st, const float *wrench,
+                               const double *psi_next, const double *psidot_next);
+
 /* Fluid force on the body from the markers' last forces F (the external
  * generalized force of Eq. (1)). out [(1 + m->nbones)][8]: row 0 is the whole
  * body, row 1 + b the share of bone b (each marker's force split by its blend

@@ -16,6 +16,7 @@
 #include "../../include/lbm_ib.h"
 #include "adjoint.hpp"
 #include "batch.hpp"
+#include "swimmer.hpp"
 
 using namespace lbmib;
 
@@ -723,6 +724,93 @@ lbm_status lbm_adjoint_segment(lbm_ctx *c, const void *ckpt, void *const *ring, 
                                                                  pose_bar, m->nbones);
     if ((st = launched()) != LBM_OK) return st;
   }
+  return LBM_OK;
+}
+
+lbm_status lbm_swimmer_init(const lbm_swimmer *s, lbm_swimmer_state *st, const double *vel0, double heading,
+                            const double *psi, const double *psidot) {
+  if (!swimmer_ok(s) || !st || !psi || !psidot || !std::isfinite(heading)) return LBM_ERR_ARG;
+  ChainShape c;
+  if (!chain_shape(s, psi, psidot, c)) return LBM_ERR_ARG;
+  for (int q = 0; q < 2; ++q) {
+    st->vel[q] = vel0 ? vel0[q] : 0.0;
+    st->acc[q] = 0.0;
+    st->pos[q] = 0.0;
+  }
+  st->heading = heading;
+  st->spin = 0.0;
+  st->spin_prev = 0.0;
+  st->ang_mom = c.Ls;
+  st->inertia = c.Ic;
+  return LBM_OK;
+}
+
+lbm_status lbm_swimmer_prepare(const lbm_swimmer *s, const lbm_swimmer_state *st, const double *psi,
+                               const double *psidot, float *poses, lbm_frame *frame) {
+  if (!swimmer_ok(s) || !st || !psi || !psidot || !poses || !frame) return LBM_ERR_ARG;
+  ChainShape c;
+  if (!chain_shape(s, psi, psidot, c)) return LBM_ERR_ARG;
+  const double th = st->heading, w = st->spin;
+  const double ct = std::cos(th), sn = std::sin(th);
+  for (int j = 0; j < s->nbones; ++j) {
+    // joint j relative to the mass centre: position and velocity in the frame
+    const double dx = c.J[j][0] - c.rc[0], dy = c.J[j][1] - c.rc[1];
+    const double vx = c.Jd[j][0] - c.rcd[0], vy = c.Jd[j][1] - c.rcd[1];
+    const double Rdx = ct * dx - sn * dy, Rdy = sn * dx + ct * dy;
+    const double P[3] = {s->origin[0] + Rdx, s->origin[1] + Rdy, s->origin[2]};
+    const double Pd[3] = {-w * Rdy + ct * vx - sn * vy, w * Rdx + sn * vx + ct * vy, 0.0};
+    const double al = th + psi[j], ca = std::cos(al), sa = std::sin(al), rate = w + psidot[j];
+    const double R[9] = {ca, -sa, 0.0, sa, ca, 0.0, 0.0, 0.0, 1.0};
+    const double Rd[9] = {-rate * sa, -rate * ca, 0.0, rate * ca, -rate * sa, 0.0, 0.0, 0.0, 0.0};
+    const double *Jr = s->joints_rest + 3 * j;
+    float *o = poses + 24 * j;
+    for (int r = 0; r < 3; ++r) {
+      double t = P[r], td = Pd[r];
+      for (int k = 0; k < 3; ++k) {
+        o[3 * r + k] = (float)R[3 * r + k];
+        o[12 + 3 * r + k] = (float)Rd[3 * r + k];
+        t -= R[3 * r + k] * Jr[k];
+        td -= Rd[3 * r + k] * Jr[k];
+      }
+      o[9 + r] = (float)t;
+      o[21 + r] = (float)td;
+    }
+  }
+  for (int q = 0; q < 3; ++q) {
+    frame->acc[q] = q < 2 ? st->acc[q] : 0.0;
+    frame->omega[q] = 0.0;
+    frame->alpha[q] = 0.0;
+    frame->origin[q] = s->origin[q];
+    frame->u_lo[q] = q < 2 ? -st->vel[q] : 0.0;
+    frame->u_hi[q] = frame->u_lo[q];
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_swimmer_advance(const lbm_swimmer *s, lbm_swimmer_state *st, const float *wrench,
+                               const double *psi_next, const double *psidot_next) {
+  if (!swimmer_ok(s) || !st || !wrench || !psi_next || !psidot_next) return LBM_ERR_ARG;
+  for (int q = 0; q < 8; ++q)
+    if (!std::isfinite(wrench[q])) return LBM_ERR_ARG;
+  ChainShape c;
+  if (!chain_shape(s, psi_next, psidot_next, c)) return LBM_ERR_ARG;
+  const double M = chain_mass(s), r = s->fluid_ratio;
+  for (int q = 0; q < 2; ++q) {
+    const double a = st->acc[q];
+    st->vel[q] += a;
+    st->pos[q] += st->vel[q];
+    st->acc[q] = (double)wrench[q] / M + r * a;
+  }
+  if (s->free_yaw) {
+    st->ang_mom += (double)wrench[5] + r * st->inertia * (st->spin - st->spin_prev);
+    st->spin_prev = st->spin;
+    st->spin = (st->ang_mom - c.Ls) / c.Ic;
+    st->heading += st->spin;
+  } else {  // heading held: a holding torque absorbs the rest
+    st->spin_prev = st->spin = 0.0;
+    st->ang_mom = c.Ls;
+  }
+  st->inertia = c.Ic;
   return LBM_OK;
 }
 

@@ -134,6 +134,26 @@ def fish_half_width(xi: np.ndarray, length: float) -> np.ndarray:
     return 0.08 * length * np.sqrt(np.clip(xi, 0.0, 1.0)) * (1.0 - xi) / peak
 
 
+def fish_link_mass(length: float, nbones: int = 10, rho: float = 1.0, nq: int = 4000):
+    """Mass properties of the fish body of fish_surface cut into nbones equal
+    links (density rho): per link its mass, the distance of its mass centre
+    from its proximal joint along the body axis, and its moment of inertia
+    about z through that centre (axial spread plus the elliptic section's
+    lateral spread b^2 / 4). Midpoint quadrature with nq points per link.
+    Also returns the body volume."""
+    h = length / nbones
+    mass, com, inertia = np.zeros(nbones), np.zeros(nbones), np.zeros(nbones)
+    for j in range(nbones):
+        s = j * h + (np.arange(nq) + 0.5) * (h / nq)
+        b = fish_half_width(s / length, length)
+        area = math.pi * b * 1.5 * b
+        dm = rho * area * (h / nq)
+        mass[j] = dm.sum()
+        com[j] = ((s - j * h) * dm).sum() / mass[j]
+        inertia[j] = (((s - j * h - com[j]) ** 2 + b * b / 4.0) * dm).sum()
+    return mass, com, inertia, float(mass.sum() / rho)
+
+
 def _ellipse_perimeter(a, b):
     # Ramanujan's second approximation
     h = ((a - b) / np.maximum(a + b, 1e-300)) ** 2

@@ -54,6 +54,18 @@ BATCH_PHASES, BATCH_PERSISTENT = 0, 1
 BATCH_SHAPES = ((64, 8), (128, 4), (256, 2), (512, 1), (512, 0))  # (512, 0): linear cell order
 
 
+class Swimmer(ctypes.Structure):
+    _fields_ = [("nbones", ctypes.c_int32), ("free_yaw", ctypes.c_int32), ("link_length", ctypes.c_double),
+                ("mass", ctypes.c_void_p), ("com", ctypes.c_void_p), ("inertia", ctypes.c_void_p),
+                ("joints_rest", ctypes.c_void_p), ("fluid_ratio", ctypes.c_double), ("origin", ctypes.c_double * 3)]
+
+
+class SwimmerState(ctypes.Structure):
+    _fields_ = [("vel", ctypes.c_double * 2), ("acc", ctypes.c_double * 2), ("heading", ctypes.c_double),
+                ("spin", ctypes.c_double), ("spin_prev", ctypes.c_double), ("ang_mom", ctypes.c_double),
+                ("inertia", ctypes.c_double), ("pos", ctypes.c_double * 2)]
+
+
 class LBMError(RuntimeError):
     def __init__(self, code: int, what: str = ""):
         self.code = code
@@ -86,6 +98,9 @@ def lib():
         L.lbm_state_restore.argtypes = [vp, vp, ctypes.c_int64]
         L.lbm_adjoint_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.lbm_bind_populations.argtypes = [vp, vp, vp]
+        L.lbm_swimmer_init.argtypes = [vp, vp, vp, ctypes.c_double, vp, vp]
+        L.lbm_swimmer_prepare.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.lbm_swimmer_advance.argtypes = [vp, vp, vp, vp, vp]
         L.lbm_adjoint_ring_bytes.argtypes = [P, ctypes.c_int32]
         L.lbm_adjoint_ring_bytes.restype = sz
         L.lbm_adjoint_segment.argtypes = [vp, vp, vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -111,7 +126,8 @@ def lib():
         for name in ("lbm_init", "lbm_load_populations", "lbm_read_populations", "lbm_macros", "lbm_ib_step",
                      "lbm_body_forces", "lbm_check", "lbm_set_stream", "lbm_profile_enable",
                      "lbm_profile_collect", "lbm_state_save", "lbm_state_restore", "lbm_adjoint_step",
-                     "lbm_bind_populations", "lbm_adjoint_segment",
+                     "lbm_bind_populations", "lbm_adjoint_segment", "lbm_swimmer_init", "lbm_swimmer_prepare",
+                     "lbm_swimmer_advance",
                      "lbm_batch_create", "lbm_batch_run", "lbm_batch_autotune",
                      "lbm_batch_set_shapes", "lbm_batch_check"):
             getattr(L, name).restype = ctypes.c_int

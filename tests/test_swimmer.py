@@ -1,0 +1,221 @@
+"""Free-swimming body dynamics (host code, no GPU): the library's
+lbm_swimmer_* functions and the FP64 oracle's independent implementation,
+each pinned to closed forms -- two identical hinged links keep their bisector
+still (zero angular momentum), a constant force and torque on a rigid shape
+give exact momentum, the posed links' mass centre sits at the frame origin,
+pose rates are the time derivatives of the poses -- and the two
+implementations agree with each other."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import swimmer as OS
+from paper_2206_01683_amd import inputs as I
+from paper_2206_01683_amd import lbm
+
+
+def _lib_body(body):
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (body.mass, body.com, body.inertia, body.joints_rest)]
+    s = lbm.Swimmer(len(body.mass), 1 if body.free_yaw else 0, body.h, *[a.ctypes.data for a in arrs],
+                    body.fluid_ratio, (ctypes.c_double * 3)(*body.origin))
+    return s, arrs
+
+
+def _lib_init(s, psi, psid, vel0=(0.0, 0.0), heading=0.0):
+    st = lbm.SwimmerState()
+    v = np.asarray(vel0, dtype=np.float64)
+    p, d = np.ascontiguousarray(psi, dtype=np.float64), np.ascontiguousarray(psid, dtype=np.float64)
+    assert lbm.lib().lbm_swimmer_init(ctypes.byref(s), ctypes.byref(st), v.ctypes.data, heading, p.ctypes.data,
+                                      d.ctypes.data) == 0
+    return st
+
+
+def _lib_advance(s, st, wrench, psi, psid):
+    w = np.ascontiguousarray(wrench, dtype=np.float32)
+    p, d = np.ascontiguousarray(psi, dtype=np.float64), np.ascontiguousarray(psid, dtype=np.float64)
+    assert lbm.lib().lbm_swimmer_advance(ctypes.byref(s), ctypes.byref(st), w.ctypes.data, p.ctypes.data,
+                                         d.ctypes.data) == 0
+
+
+def _lib_prepare(s, st, psi, psid):
+    poses = np.zeros((len(psi), 24), dtype=np.float32)
+    fr = lbm.Frame()
+    p, d = np.ascontiguousarray(psi, dtype=np.float64), np.ascontiguousarray(psid, dtype=np.float64)
+    assert lbm.lib().lbm_swimmer_prepare(ctypes.byref(s), ctypes.byref(st), p.ctypes.data, d.ctypes.data,
+                                         poses.ctypes.data, ctypes.byref(fr)) == 0
+    return poses.astype(np.float64), np.frombuffer(fr, dtype=np.float64).copy()
+
+
+def _rods(h=6.0, m=2.0):
+    return OS.Body(h, [m, m], [h / 2, h / 2], [m * h * h / 12, m * h * h / 12],
+                   [[0.0, 0.0, 0.0], [h, 0.0, 0.0]], 0.0, (10.0, 12.0, 14.0))
+
+
+def _flap(n):
+    """Joint angle phi(n) = 0.6 (1 - cos 0.07 n), split unevenly between the
+    two body-frame headings; rates zero at n = 0."""
+    t = np.arange(n, dtype=np.float64)
+    phi, phid = 0.6 * (1 - np.cos(0.07 * t)), 0.6 * 0.07 * np.sin(0.07 * t)
+    psi = np.stack([-0.3 * phi + 0.1, 0.7 * phi + 0.1], axis=1)
+    psid = np.stack([-0.3 * phid, 0.7 * phid], axis=1)
+    return psi, psid
+
+
+def test_two_hinged_rods_keep_their_bisector_still():
+    body = _rods()
+    psi, psid = _flap(60)
+    zero = np.zeros(8)
+    st_o = OS.init(body, psi[0], psid[0])
+    s, keep = _lib_body(body)
+    st_l = _lib_init(s, psi[0], psid[0])
+    for n in range(1, 60):
+        OS.advance(body, st_o, zero, psi[n], psid[n])
+        _lib_advance(s, st_l, zero, psi[n], psid[n])
+        want = -(psid[n, 0] + psid[n, 1]) / 2.0  # the bisector's world heading does not turn
+        assert abs(st_o["spin"] - want) < 1e-13
+        assert abs(st_l.spin - want) < 1e-13
+        assert abs(st_o["vel"]) == 0.0 and st_l.vel[0] == 0.0 and st_l.vel[1] == 0.0
+
+
+def test_constant_force_and_torque_on_a_rigid_body():
+    body = _rods()
+    psi = np.array([0.2, -0.4])
+    psid = np.zeros(2)
+    F, T = (0.3, -0.2), 0.05
+    wrench = np.array([F[0], F[1], 0.0, 0.0, 0.0, T, 0.0, 0.0], dtype=np.float32)
+    st_o = OS.init(body, psi, psid, vel0=(0.01, 0.02))
+    s, keep = _lib_body(body)
+    st_l = _lib_init(s, psi, psid, vel0=(0.01, 0.02))
+    *_, Ic, _ = OS.shape(body, psi, psid)
+    Ff = wrench[:2].astype(np.float64)
+    for n in range(1, 40):
+        OS.advance(body, st_o, wrench, psi, psid)
+        _lib_advance(s, st_l, wrench, psi, psid)
+        # the force of step n-1 sets the frame acceleration of step n
+        v_want = np.array([0.01, 0.02]) + (n - 1) * Ff / body.M
+        np.testing.assert_allclose([st_o["vel"].real, st_o["vel"].imag], v_want, rtol=0, atol=1e-14)
+        np.testing.assert_allclose(st_l.vel[:], v_want, rtol=0, atol=1e-14)
+        assert abs(st_o["spin"] - n * float(wrench[5]) / Ic) < 1e-14
+        assert abs(st_l.spin - n * float(wrench[5]) / Ic) < 1e-14
+
+
+def _fish_body():
+    ms = I.fish_surface(800, 24.0, (12.0, 20.0, 20.0))
+    mass, com, inertia, vol = I.fish_link_mass(24.0, 10, rho=2.0)
+    return OS.Body(2.4, mass, com, inertia, ms.joints_rest, 0.5, (30.0, 24.0, 24.0)), ms
+
+
+def test_poses_centre_the_body_and_rates_are_derivatives():
+    body, ms = _fish_body()
+    steps = np.arange(3)
+    psi, psid = I.wave_headings(24.0, 10, steps + 37.0)
+    st = OS.init(body, psi[0], psid[0], vel0=(-0.01, 0.003), heading=0.4)
+    st["spin"] = 0.02
+    poses, frame = OS.prepare(body, st, psi[0], psid[0])
+    # mass centre of the posed links at the frame origin
+    cm = np.zeros(3)
+    for j in range(10):
+        R = poses[j, :9].reshape(3, 3)
+        c_rest = body.joints_rest[j] + np.array([body.com[j], 0.0, 0.0])
+        cm += body.mass[j] * (R @ c_rest + poses[j, 9:12])
+    np.testing.assert_allclose(cm / body.M, body.origin, atol=1e-12)
+    # rates: central differences along heading + spin t, psi + psid t
+    e = 1e-6
+    sp = dict(st, heading=st["heading"] + st["spin"] * e)
+    sm = dict(st, heading=st["heading"] - st["spin"] * e)
+    pp, _ = OS.prepare(body, sp, psi[0] + psid[0] * e, psid[0])
+    pm, _ = OS.prepare(body, sm, psi[0] - psid[0] * e, psid[0])
+    fd = (pp - pm) / (2 * e)
+    np.testing.assert_allclose(fd[:, 0:9], poses[:, 12:21], atol=1e-8)
+    np.testing.assert_allclose(fd[:, 9:12], poses[:, 21:24], atol=1e-8)
+    np.testing.assert_allclose(frame[0:3], [0, 0, 0])
+    np.testing.assert_allclose(frame[12:15], [0.01, -0.003, 0.0])
+
+
+def test_library_and_oracle_swimmer_agree():
+    body, ms = _fish_body()
+    steps = np.arange(30)
+    psi, psid = I.wave_headings(24.0, 10, steps)
+    rng = np.random.default_rng(3)
+    st_o = OS.init(body, psi[0], psid[0], vel0=(-0.02, 0.001), heading=0.1)
+    s, keep = _lib_body(body)
+    st_l = _lib_init(s, psi[0], psid[0], vel0=(-0.02, 0.001), heading=0.1)
+    for n in range(29):
+        po, fo = OS.prepare(body, st_o, psi[n], psid[n])
+        pl, fl = _lib_prepare(s, st_l, psi[n], psid[n])
+        np.testing.assert_allclose(pl, po, rtol=0, atol=2e-5 * np.abs(po).max())
+        np.testing.assert_allclose(fl, fo, rtol=1e-14, atol=1e-16)
+        w = np.zeros(8, dtype=np.float32)
+        w[[0, 1, 5]] = rng.normal(0.0, [0.05, 0.05, 0.5]).astype(np.float32)
+        OS.advance(body, st_o, w, psi[n + 1], psid[n + 1])
+        _lib_advance(s, st_l, w, psi[n + 1], psid[n + 1])
+        assert abs(st_l.heading - st_o["heading"]) < 1e-12 and abs(st_l.spin_prev - st_o["spin_prev"]) < 1e-14
+        assert abs(complex(*st_l.vel[:]) - st_o["vel"]) < 1e-14
+        assert abs(complex(*st_l.acc[:]) - st_o["acc"]) < 1e-14
+
+
+def test_enclosed_fluid_terms_and_held_yaw():
+    """With fluid ratio r the force lags as a(n+1) = F(n)/M + r a(n) and a
+    spin change adds r I_c (theta'(n) - theta'(n-1)) of angular momentum; with
+    the yaw held the heading never moves, whatever the torque."""
+    base = _rods()
+    for free in (True, False):
+        body = OS.Body(base.h, base.mass, base.com, base.inertia, base.joints_rest, 0.5, base.origin, free_yaw=free)
+        s, keep = _lib_body(body)
+        psi, psid = np.array([0.2, -0.4]), np.zeros(2)
+        st_o = OS.init(body, psi, psid)
+        st_l = _lib_init(s, psi, psid)
+        *_, Ic, _ = OS.shape(body, psi, psid)
+        w = np.array([0.4, 0.0, 0, 0, 0, 0.03, 0, 0], dtype=np.float32)
+        a_want, spins = 0.0, [0.0, 0.0]
+        L = 0.0
+        for n in range(1, 12):
+            OS.advance(body, st_o, w, psi, psid)
+            _lib_advance(s, st_l, w, psi, psid)
+            a_want = float(w[0]) / body.M + 0.5 * a_want
+            assert abs(st_o["acc"].real - a_want) < 1e-15 and abs(st_l.acc[0] - a_want) < 1e-15
+            if free:
+                L += float(w[5]) + 0.5 * Ic * (spins[-1] - spins[-2])
+                spins.append(L / Ic)
+                assert abs(st_o["spin"] - spins[-1]) < 1e-14 and abs(st_l.spin - spins[-1]) < 1e-14
+            else:
+                assert st_o["heading"] == 0.0 and st_l.heading == 0.0 and st_l.spin == 0.0
+
+
+def test_swimmer_rejects_bad_bodies():
+    body = _rods()
+    s, keep = _lib_body(body)
+    st = lbm.SwimmerState()
+    z = np.zeros(2)
+    s.nbones = 0
+    assert lbm.lib().lbm_swimmer_init(ctypes.byref(s), ctypes.byref(st), None, 0.0, z.ctypes.data,
+                                      z.ctypes.data) == lbm.ERR_ARG
+    s.nbones = 2
+    s.link_length = -1.0
+    assert lbm.lib().lbm_swimmer_init(ctypes.byref(s), ctypes.byref(st), None, 0.0, z.ctypes.data,
+                                      z.ctypes.data) == lbm.ERR_ARG
+
+
+def _free_fish(rho_b, n_steps):
+    import oracle
+    nx, ny, nz, L = 64, 40, 40, 20.0
+    ms = I.fish_surface(1000, L, (20.0, 20.0, 20.0))
+    mass, com, inertia, vol = I.fish_link_mass(L, 10, rho=rho_b)
+    body = OS.Body(L / 10, mass, com, inertia, ms.joints_rest, 1.0 / rho_b, (30.0, 20.0, 20.0))
+    psi, psid = I.wave_headings(L, 10, np.arange(n_steps + 1), period=100.0)
+    prm = oracle.params(nx, ny, nz, 0.6, I.BC_VELOCITY, I.BC_OUTFLOW)
+    f = oracle.equilibrium_field(np.ones((nz, ny, nx)), np.zeros((3, nz, ny, nx)))
+    return OS.coupled_run(prm, f, ms, body, psi, psid, n_steps)
+
+
+@pytest.mark.slow
+def test_coupled_oracle_swims_stably_toward_its_heading():
+    """Twice as dense as the fluid, free yaw, 150 steps (1.5 wave periods):
+    the coupled FP64 run stays bounded, the fish drifts toward -x (its
+    heading) and recoils sideways and in yaw at the wave period."""
+    out = _free_fish(2.0, 150)
+    v, th = out["vel"], out["heading"]
+    assert np.all(np.isfinite(v)) and np.all(np.isfinite(th))
+    assert np.abs(v).max() < 0.02 and np.abs(th).max() < 0.3
+    assert v[-50:, 0].mean() < 0.0
