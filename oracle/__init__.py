@@ -25,6 +25,7 @@ _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 _lib = None
 
 BC_PERIODIC, BC_VELOCITY, BC_OUTFLOW = 0, 1, 2
+IB_DIRECT, IB_IMPLICIT = 0, 1
 
 
 def build(force: bool = True) -> str:
@@ -42,7 +43,7 @@ class _Params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("bc_lo", ctypes.c_int32), ("bc_hi", ctypes.c_int32), ("mdf_iters", ctypes.c_int32),
                 ("tau", ctypes.c_double), ("ib_alpha", ctypes.c_double),
-                ("bc_y", ctypes.c_int32 * 2), ("bc_z", ctypes.c_int32 * 2)]
+                ("bc_y", ctypes.c_int32 * 2), ("bc_z", ctypes.c_int32 * 2), ("ib_scheme", ctypes.c_int32)]
 
 
 class _Markers(ctypes.Structure):
@@ -89,11 +90,14 @@ def _f64(a) -> np.ndarray:
 
 
 def params(nx, ny, nz, tau, bc_lo=BC_PERIODIC, bc_hi=BC_PERIODIC, mdf_iters=1, ib_alpha=1.0,
-           bc_y=(BC_PERIODIC, BC_PERIODIC), bc_z=(BC_PERIODIC, BC_PERIODIC)) -> _Params:
+           bc_y=(BC_PERIODIC, BC_PERIODIC), bc_z=(BC_PERIODIC, BC_PERIODIC), ib_scheme=IB_DIRECT) -> _Params:
     """Face conditions: x by bc_lo / bc_hi, y and z by the pairs bc_y, bc_z
-    (low, high); an axis is periodic or open on both faces."""
+    (low, high); an axis is periodic or open on both faces. ib_scheme
+    IB_DIRECT: explicit direct forcing plus mdf_iters - 1 multi-direct-forcing
+    passes; IB_IMPLICIT: the implicit velocity correction, mdf_iters
+    conjugate-gradient steps."""
     return _Params(nx, ny, nz, bc_lo, bc_hi, mdf_iters, tau, ib_alpha, (ctypes.c_int32 * 2)(*bc_y),
-                   (ctypes.c_int32 * 2)(*bc_z))
+                   (ctypes.c_int32 * 2)(*bc_z), ib_scheme)
 
 
 def threads() -> int:
@@ -261,7 +265,7 @@ def initial_populations(rho: np.ndarray, u: np.ndarray) -> np.ndarray:
 
 def run_workload(w, nsteps=None, f0=None):
     """Run an inputs.Workload from its initial state f = f^eq(1, u0)."""
-    prm = params(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi, w.mdf_iters, w.ib_alpha, w.bc_y, w.bc_z)
+    prm = params(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi, w.mdf_iters, w.ib_alpha, w.bc_y, w.bc_z, w.ib_scheme)
     if f0 is None:
         f0 = equilibrium_field(np.ones((w.nz, w.ny, w.nx)), w.u0)
     return run(prm, f0, w.frames, w.markers, w.poses, nsteps or w.nsteps)

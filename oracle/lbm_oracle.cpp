@@ -122,17 +122,22 @@ void cross(const A a[3], const B b[3], C out[3]) {
 extern "C" {
 
 // ------------------------------------------------------------ C structs ----
-// Boundary codes for the two x faces. y and z are always periodic.
+// Boundary codes of a face; an axis is periodic on both faces or open on both.
 enum { OR_BC_PERIODIC = 0, OR_BC_VELOCITY = 1, OR_BC_OUTFLOW = 2 };
+// Immersed-boundary schemes: explicit direct forcing (with mdf_iters - 1
+// multi-direct-forcing passes), or the implicit velocity correction solved by
+// mdf_iters conjugate-gradient steps.
+enum { OR_IB_DIRECT = 0, OR_IB_IMPLICIT = 1 };
 
 struct OrParams {
   int32_t nx, ny, nz;
   int32_t bc_lo, bc_hi;  // x = 0 and x = nx-1; both periodic or both open
-  int32_t mdf_iters;     // >= 1; 1 is plain explicit direct forcing
+  int32_t mdf_iters;     // >= 1; direct forcing: 1 is plain explicit; implicit: CG steps
   double tau;
   double ib_alpha;       // direct-forcing gain
   int32_t bc_y[2];       // y = 0 and y = ny-1 (0: periodic, the default)
   int32_t bc_z[2];       // z = 0 and z = nz-1
+  int32_t ib_scheme;     // OR_IB_*
 };
 
 // Frame of reference for one step (Eq. (3)): linear acceleration of the
@@ -267,7 +272,7 @@ void skin(const OrMarkers *mk, const T *poses, T *X, T *U) {
 
 extern "C" {
 
-int or_abi_version(void) { return 2; }
+int or_abi_version(void) { return 3; }
 
 // Threads a parallel lattice sweep uses.
 int or_threads(void) {
@@ -498,6 +503,71 @@ int or_macros(const OrParams *p, const double *f, const OrFrame *fr, double *rho
 
 namespace {
 
+// Implicit velocity correction (the implicit immersed-boundary variant the
+// paper cites in its Introduction, Wu and Shu's velocity correction). The
+// marker forces
+// G_k = F_k dV_k are the ones whose spread force, added to the fluid velocity,
+// brings the interpolated velocity to the body velocity at every marker:
+//   interp(u*) + interp(M spread(G) / (2 rho)) = U,
+// with M = (I + [omega]x)^-1 the Coriolis solve that defines the fluid
+// velocity. M is the same 3x3 matrix at every node, so the system separates:
+//   S G = (I + [omega]x) (U - U*),   S = interp . (1 / (2 rho)) . spread,
+// one scalar system per component with the symmetric positive semidefinite
+// S (S_kl = sum_x delta(x - X_k) delta(x - X_l) / (2 rho(x))). Each component
+// is solved by `iters` steps of conjugate gradients from G = 0, with the
+// diagonal preconditioner 2 rho_k: for a uniform density the diagonal of S is
+// (3/8)^3 / (2 rho) (the 4-point kernel's squared weights sum to 3/8 along
+// each axis), and a constant factor in a preconditioner does not change the
+// iterates. Guards: alpha = 0 when p.Sp is not positive (nothing left to
+// correct), beta = 0 when the previous r.z is 0.
+//   rho [cells] node density; X, U, Ustar [3][nm]; rhok [nm]; G [3][nm] out.
+template <class T>
+void implicit_forces(const Grid &G, const T *rho, const T *X, const T *U, const T *Ustar, const T *rhok,
+                     const OrFrame *fr, int nm, int iters, T *Gout) {
+  const size_t N = G.ncell();
+  std::vector<T> r(3 * nm), z(3 * nm), p(3 * nm), q(3 * nm), g(3 * N), h(3 * N);
+  for (int k = 0; k < nm; ++k) {
+    T R[3], wR[3];
+    for (int a = 0; a < 3; ++a) R[a] = U[a * nm + k] - Ustar[a * nm + k];
+    cross(fr->omega, R, wR);
+    for (int a = 0; a < 3; ++a) r[a * nm + k] = R[a] + wR[a];
+  }
+  T rz[3];
+  for (int a = 0; a < 3; ++a) {
+    rz[a] = 0.0;
+    for (int k = 0; k < nm; ++k) {
+      const size_t i = (size_t)a * nm + k;
+      z[i] = 2.0 * rhok[k] * r[i];
+      p[i] = z[i];
+      Gout[i] = 0.0;
+      rz[a] += r[i] * z[i];
+    }
+  }
+  for (int it = 0; it < iters; ++it) {
+    // q = S p
+    spread(G, X, nm, p.data(), g.data());
+    for (int a = 0; a < 3; ++a)
+      for (size_t id = 0; id < N; ++id) h[a * N + id] = g[a * N + id] / (2.0 * rho[id]);
+    interpolate(G, h.data(), 3, X, nm, q.data());
+    for (int a = 0; a < 3; ++a) {
+      T pq = 0.0;
+      for (int k = 0; k < nm; ++k) pq += p[a * nm + k] * q[a * nm + k];
+      const T alpha = val(pq) > 0.0 ? rz[a] / pq : T(0.0);
+      T rz_new = 0.0;
+      for (int k = 0; k < nm; ++k) {
+        const size_t i = (size_t)a * nm + k;
+        Gout[i] += alpha * p[i];
+        r[i] = r[i] - alpha * q[i];
+        z[i] = 2.0 * rhok[k] * r[i];
+        rz_new += r[i] * z[i];
+      }
+      const T beta = val(rz[a]) != 0.0 ? rz_new / rz[a] : T(0.0);
+      for (int k = 0; k < nm; ++k) p[a * nm + k] = z[a * nm + k] + beta * p[a * nm + k];
+      rz[a] = rz_new;
+    }
+  }
+}
+
 // Advance the pre-collision populations f [27][nz][ny][nx] by nsteps steps.
 //   poses  : [nsteps][nbones][24] bone poses for each step (may be null when
 //            markers is null)
@@ -514,7 +584,7 @@ int run(const OrParams *p, T *f, const OrMarkers *mk, const T *poses, const OrFr
   if (!p || !f || p->nx < 4 || p->ny < 4 || p->nz < 4 || !(p->tau > 0.5)) return -1;
   Grid G;
   if (!make_grid(p, G)) return -1;
-  if (p->mdf_iters < 1) return -1;
+  if (p->mdf_iters < 1 || (p->ib_scheme != OR_IB_DIRECT && p->ib_scheme != OR_IB_IMPLICIT)) return -1;
   const size_t N = G.ncell();
   const double tau = p->tau;
   const int nm = mk ? mk->n : 0;
@@ -543,23 +613,30 @@ int run(const OrParams *p, T *f, const OrMarkers *mk, const T *poses, const OrFr
     if (nm > 0) {
       interpolate(G, ustar.data(), 3, X.data(), nm, Ustar.data());
       interpolate(G, rho.data(), 1, X.data(), nm, rhok.data());
-      for (int k = 0; k < nm; ++k)
-        for (int a = 0; a < 3; ++a)
-          Fk[a * nm + k] = p->ib_alpha * 2.0 * rhok[k] * (U[a * nm + k] - Ustar[a * nm + k]);
-      for (int it = 1; it < p->mdf_iters; ++it) {
-        // multi-direct forcing: spread the current force, re-interpolate the
-        // velocity that includes it, add the remaining correction
+      if (p->ib_scheme == OR_IB_IMPLICIT) {
+        implicit_forces(G, rho.data(), X.data(), U.data(), Ustar.data(), rhok.data(), fr, nm, p->mdf_iters,
+                        Fdv.data());
         for (int k = 0; k < nm; ++k)
-          for (int a = 0; a < 3; ++a) Fdv[a * nm + k] = Fk[a * nm + k] * mk->dv[k];
-        spread(G, X.data(), nm, Fdv.data(), g.data());
-        node_fields(G, f, g.data(), fr, rho.data(), ufull.data());
-        interpolate(G, ufull.data(), 3, X.data(), nm, Uk.data());
+          for (int a = 0; a < 3; ++a) Fk[a * nm + k] = Fdv[a * nm + k] / mk->dv[k];
+      } else {
         for (int k = 0; k < nm; ++k)
           for (int a = 0; a < 3; ++a)
-            Fk[a * nm + k] += p->ib_alpha * 2.0 * rhok[k] * (U[a * nm + k] - Uk[a * nm + k]);
+            Fk[a * nm + k] = p->ib_alpha * 2.0 * rhok[k] * (U[a * nm + k] - Ustar[a * nm + k]);
+        for (int it = 1; it < p->mdf_iters; ++it) {
+          // multi-direct forcing: spread the current force, re-interpolate the
+          // velocity that includes it, add the remaining correction
+          for (int k = 0; k < nm; ++k)
+            for (int a = 0; a < 3; ++a) Fdv[a * nm + k] = Fk[a * nm + k] * mk->dv[k];
+          spread(G, X.data(), nm, Fdv.data(), g.data());
+          node_fields(G, f, g.data(), fr, rho.data(), ufull.data());
+          interpolate(G, ufull.data(), 3, X.data(), nm, Uk.data());
+          for (int k = 0; k < nm; ++k)
+            for (int a = 0; a < 3; ++a)
+              Fk[a * nm + k] += p->ib_alpha * 2.0 * rhok[k] * (U[a * nm + k] - Uk[a * nm + k]);
+        }
+        for (int k = 0; k < nm; ++k)
+          for (int a = 0; a < 3; ++a) Fdv[a * nm + k] = Fk[a * nm + k] * mk->dv[k];
       }
-      for (int k = 0; k < nm; ++k)
-        for (int a = 0; a < 3; ++a) Fdv[a * nm + k] = Fk[a * nm + k] * mk->dv[k];
       spread(G, X.data(), nm, Fdv.data(), g.data());
     }
 

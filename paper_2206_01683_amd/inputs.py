@@ -360,6 +360,7 @@ class Workload:
     meta: dict = dataclasses.field(default_factory=dict)
     bc_y: tuple = (BC_PERIODIC, BC_PERIODIC)  # y = 0, y = ny-1
     bc_z: tuple = (BC_PERIODIC, BC_PERIODIC)  # z = 0, z = nz-1
+    ib_scheme: int = 0                        # 0 direct forcing, 1 implicit velocity correction
 
     @property
     def ncell(self) -> int:
