@@ -162,6 +162,40 @@ def run_two_fish(steps: int = 200, warmup: int = 20):
             "collide_GBps": round(216 * w.ncell / (col_ms / 1e3 / max(timed, 1)) / 1e9, 1), "status": status}
 
 
+def run_ib_schemes(steps: int = 100, warmup: int = 10):
+    """The 384x192x192 fish (12,000 markers) with each immersed-boundary
+    scheme: explicit direct forcing (1 pass), multi-direct forcing (4 passes)
+    and the implicit velocity correction (1 and 4 conjugate-gradient steps).
+    MLUPS of the whole step and the IB share from the library's HIP events."""
+    import numpy as np
+    import torch
+
+    from paper_2206_01683_amd import inputs as I
+    from paper_2206_01683_amd import lbm
+
+    w = I.fish_workload(nsteps=warmup + steps)
+    dm = lbm.DeviceMarkers(w.markers)
+    poses = torch.as_tensor(np.ascontiguousarray(w.poses, np.float32), device="cuda")
+    out = {"workload": w.name, "markers": w.markers.n, "steps": steps}
+    for name, scheme, k in (("direct_1", lbm.IB_DIRECT, 1), ("mdf_4", lbm.IB_DIRECT, 4),
+                            ("implicit_1", lbm.IB_IMPLICIT, 1), ("implicit_4", lbm.IB_IMPLICIT, 4)):
+        sim = lbm.Simulation(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi, max_markers=w.markers.n,
+                             max_bones=w.markers.nbones, u0=w.u0.astype(np.float32), mdf_iters=k, ib_scheme=scheme)
+        sim.step(w.frames[:warmup], dm, poses[:warmup])
+        torch.cuda.synchronize()
+        sim.profile(True)
+        t0 = time.perf_counter()
+        sim.step(w.frames[warmup:], dm, poses[warmup:])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ib_ms, _, timed = sim.profile_collect()
+        out[name] = {"mlups": round(w.ncell * steps / wall / 1e6, 1), "ms_per_step": round(wall * 1e3 / steps, 4),
+                     "ib_ms_per_step": round(ib_ms / max(timed, 1), 5), "status": sim.check()}
+        del sim
+        torch.cuda.empty_cache()
+    return out
+
+
 def run_free_swimmer(steps: int = 100, warmup: int = 10):
     """Two-way coupling: the 384x192x192 fish (12,000 markers) swimming freely,
     twice as dense as the fluid, free yaw; each step the host body dynamics
@@ -259,13 +293,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f32", choices=sorted(BYTES_PER_CELL))
     ap.add_argument("--cpu-steps", type=int, default=24, help="oracle sample length (0: skip)")
-    ap.add_argument("--forms", default="f16,bf16,batched,adjoint,two_fish,free_swimmer",
+    ap.add_argument("--forms", default="f16,bf16,batched,adjoint,two_fish,free_swimmer,ib_schemes",
                     help="comma-separated extra forms to measure: f16, bf16, batched, adjoint, two_fish, "
-                         "free_swimmer")
+                         "free_swimmer, ib_schemes")
     ap.add_argument("--no-forms", action="store_true", help="measure no extra form")
     ap.add_argument("--block", type=int, nargs=2, default=(0, 0))
     ap.add_argument("--batch-envs", type=int, default=64, help="batched form: environments (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=200, help="batched form: steps per graph replay")
+    ap.add_argument("--ib-steps", type=int, default=100, help="ib_schemes form: timed steps per scheme")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -291,6 +326,8 @@ def main():
         forms["two_fish"] = run_two_fish()
     if "free_swimmer" in want:
         forms["free_swimmer"] = run_free_swimmer()
+    if "ib_schemes" in want:
+        forms["ib_schemes"] = run_ib_schemes(args.ib_steps)
     traffic = measured_traffic(args.storage)
     ach = main_run["collide_gbs"]
     out = {

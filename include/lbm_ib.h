@@ -18,11 +18,12 @@
  *   collision    BGK, relaxation time tau > 1/2, second-order equilibrium
  *   forcing      Guo: velocity u = (m + F/2)/rho; F = g + rho a_ni(x, u),
  *                a_ni from Eq. (3), solved exactly for the Coriolis term
- *   streaming    pull; y and z always periodic; x periodic or open
+ *   streaming    pull; each axis periodic or open
  *   open faces   non-equilibrium extrapolation from the inward neighbour
  *   IB           Peskin 4-point kernel, explicit direct forcing
  *                F_k = alpha 2 rho_k (U_k - U*_k), optional multi-direct
- *                forcing passes, spreading g(x) = sum_k F_k dV_k delta(x - X_k)
+ *                forcing passes, spreading g(x) = sum_k F_k dV_k delta(x - X_k);
+ *                or the implicit velocity correction (LBM_IB_IMPLICIT)
  *
  * Conventions shared by every entry point:
  *   - Every pointer is a DEVICE pointer allocated and owned by the caller,
@@ -73,6 +74,26 @@ enum { LBM_BC_PERIODIC = 0, LBM_BC_VELOCITY = 1, LBM_BC_OUTFLOW = 2 };
  * and all immersed-boundary sums stay in float32. */
 enum { LBM_STORE_F32 = 0, LBM_STORE_F16 = 1, LBM_STORE_BF16 = 2 };
 
+/* Immersed-boundary schemes (lbm_params.ib_scheme).
+ * DIRECT: explicit direct forcing F_k = alpha 2 rho_k (U_k - U*_k), then
+ *   mdf_iters - 1 multi-direct-forcing passes, each adding
+ *   alpha 2 rho_k (U_k - U_k^interp) with U_k^interp the velocity including
+ *   the force so far.
+ * IMPLICIT: the implicit velocity correction (the implicit immersed boundary
+ *   the paper cites in its Introduction: Wu and Shu's velocity correction). The
+ *   marker forces G_k = F_k dV_k make the velocity with their spread force,
+ *   interpolated back, equal the body velocity at every marker:
+ *     S G = (I + [omega]x) (U - U*),  S = interp . 1/(2 rho) . spread,
+ *   (omega x: the Coriolis term of Eq. (3), which the fluid velocity solves
+ *   for exactly), one symmetric positive semidefinite system per component,
+ *   taken by mdf_iters steps of conjugate gradients from G = 0 with the
+ *   diagonal preconditioner 2 rho_k; alpha = 0 once p.Sp is not positive,
+ *   beta = 0 once r.z is 0. Each step costs one spread and one
+ *   interpolation, like a multi-direct-forcing pass; ib_alpha is not used.
+ *   Supported by lbm_ib_step only (the batched and adjoint entry points
+ *   return LBM_ERR_UNSUPPORTED). */
+enum { LBM_IB_DIRECT = 0, LBM_IB_IMPLICIT = 1 };
+
 typedef struct lbm_ctx lbm_ctx;
 
 /* [host] Problem description. */
@@ -82,13 +103,14 @@ typedef struct {
   int32_t storage;           /* LBM_STORE_* */
   int32_t max_markers;       /* capacity of the marker arrays, >= 0 */
   int32_t max_bones;         /* capacity of a pose array, >= 1 */
-  int32_t mdf_iters;         /* direct-forcing passes, >= 1 (1 = explicit) */
+  int32_t mdf_iters;         /* IB passes, 1..16: direct-forcing passes (1 = explicit), or CG steps */
   int32_t max_active_tiles;  /* 8x8x8 tiles that may carry IB force; 0 = automatic */
   int32_t block_x, block_y;  /* collide kernel block shape; 0 = default */
   int32_t with_adjoint;      /* nonzero: workspace also holds the adjoint buffers */
   double tau;                /* BGK relaxation time, > 1/2 (nu = (tau - 1/2)/3) */
   double ib_alpha;           /* direct-forcing gain, > 0 (1 = full correction) */
   int32_t bc_y[2], bc_z[2];  /* LBM_BC_* for the y and z faces; zeros = periodic */
+  int32_t ib_scheme;         /* LBM_IB_*; 0 = direct forcing */
 } lbm_params;
 
 /* [host] Frame of one step (Eq. (3)). acc = linear acceleration of the frame

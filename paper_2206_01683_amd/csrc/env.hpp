@@ -36,6 +36,10 @@ struct EnvView {
   float4 *macro;
   unsigned long long *gfix;
   float *rec, *mstate;
+  // implicit velocity correction (null with direct forcing)
+  unsigned long long *gcg;      // fixed-point spread of the search direction, as gfix
+  float *cg;                    // G, r, p, q, each [3][n]
+  float *cgpart;                // dot-product partials: p.q [interp items][4], r.z [2][cg items][4]
   // per-run device inputs of the batched forms, indexed by step
   const float *poses;    // [nsteps][nbones][24]
   const double *frames;  // [nsteps][18] (lbm_frame layout)

@@ -78,7 +78,10 @@ __device__ inline bool box_hits(int packed, int t) { return t >= (packed & 0xFFF
 __device__ inline void skin_item(const EnvView &e, const float *__restrict__ pose, int item, int tid) {
   const int k = item * WG + tid;
   const int n = e.n;
-  if (k == 0) e.counters[0] = 0;
+  if (k == 0) {
+    e.counters[0] = 0;  // active tiles of this step
+    e.counters[1] = 0;  // arrival count of the implicit correction's reductions
+  }
   const int tns[3] = {e.g.tnx, e.g.tny, (e.g.nz + 7) >> 3};
   const int dims[3] = {e.g.nx, e.g.ny, e.g.nz};
   int lo[3] = {1 << 20, 1 << 20, 1 << 20}, hi[3] = {-1, -1, -1};
@@ -223,6 +226,12 @@ __device__ inline void macro_item(const EnvView &e, const FrameF &fr, int cur, i
   gp[tid] = 0ull;
   gp[512 + tid] = 0ull;
   gp[1024 + tid] = 0ull;
+  if (e.gcg != nullptr) {  // implicit correction: its search-direction force starts at zero too
+    unsigned long long *gq = e.gcg + (size_t)slot * 1536;
+    gq[tid] = 0ull;
+    gq[512 + tid] = 0ull;
+    gq[1024 + tid] = 0ull;
+  }
 }
 
 // --------------------------------------------------------- interpolation --
@@ -370,7 +379,14 @@ __device__ inline void wrench_sum(const float *__restrict__ partials, int nparts
 // 64-bit LDS atomics (2^-40 fixed point). The workgroup then adds its nonzero
 // cells into the tile's fixed-point force, one global atomic per cell and
 // component. Integer sums make the result independent of every order.
-__device__ inline void spread_item(const EnvView &e, int item, int tid) {
+__device__ inline void cg_direction(const EnvView &e, int k, const float *beta, bool first, float p[3]);
+
+// CG = true: the spread values are the search direction of the implicit
+// correction's conjugate-gradient step (cg_direction with beta, first), not
+// the record's.
+template <bool CG>
+__device__ inline void spread_item(const EnvView &e, int item, int tid, unsigned long long *target,
+                                   const float *beta = nullptr, bool first = true) {
   __shared__ unsigned long long s_acc[3][512];
   const int lane = tid & 63, wv = tid >> 6;
   const GridArgs &g = e.g;
@@ -412,6 +428,7 @@ __device__ inline void spread_item(const EnvView &e, int item, int tid) {
           r[4 * q + 2] = v.z;
           r[4 * q + 3] = v.w;
         }
+        if (CG) cg_direction(e, k, beta, first, &r[16]);
         const int bx = __float_as_int(r[12]), by = __float_as_int(r[13]), bz = __float_as_int(r[14]);
         int lx[4], ly[4], lz[4];  // local index part per stencil node, -1 outside the tile
 #pragma unroll
@@ -444,13 +461,15 @@ __device__ inline void spread_item(const EnvView &e, int item, int tid) {
     }
   }
   __syncthreads();
-  unsigned long long *gp = e.gfix + (size_t)slot * 1536;
+  unsigned long long *gp = target + (size_t)slot * 1536;
   for (int q = tid; q < 3 * 512; q += WG) {
     const unsigned long long v = (&s_acc[0][0])[q];
     if (v != 0ull) atomicAdd(&gp[q], v);
   }
   __syncthreads();
 }
+
+__device__ inline void spread_item(const EnvView &e, int item, int tid) { spread_item<false>(e, item, tid, e.gfix); }
 
 // ----------------------------------------------- single-lattice launches --
 __global__ void __launch_bounds__(WG) k_skin_mark(EnvView e, const float *pose) {
@@ -475,6 +494,306 @@ __global__ void __launch_bounds__(WG) k_spread(EnvView e, float *wrench) {
   if (blockIdx.x == 0 && wrench != nullptr) wrench_sum(e.partials, interp_items(e.n), wrench, threadIdx.x);
   const int items = n_active_of(e) * kSpreadSplit;
   for (int item = blockIdx.x; item < items; item += gridDim.x) spread_item(e, item, threadIdx.x);
+}
+
+// ------------------------------------------- implicit velocity correction --
+// The marker forces G_k = F_k dV_k solve S G = (I + [omega]x)(U - U*) with
+// S = interp . 1/(2 rho) . spread (the implicit immersed boundary of Wu and
+// Shu, cited in the paper's Introduction): interpolating u* + M spread(G) /
+// (2 rho) then gives U at every marker, M = (I + [omega]x)^-1 the Coriolis
+// solve of the fluid velocity. M is the same at every node, so S acts on each
+// component alone and is symmetric positive semidefinite; conjugate
+// gradients with the diagonal preconditioner 2 rho_k (S's diagonal is
+// (3/8)^3 / (2 rho) for a uniform density) take mdf_iters steps from G = 0.
+// The spread and the interpolation of S use the weights of the marker record,
+// so the discrete S is exactly symmetric up to float rounding.
+//
+// Per step, after the first interpolation pass (rho_k, U*_k, record):
+//   cg_init_item     r = (I + [omega]x)(U - U*), G = 0; rz_0 = r.z, z = 2 rho_k r
+//   step j = 0, 1, ...:
+//     spread (CG)    p_j = z_j + beta_j p_{j-1} (p_0 = z_0) computed per
+//                    marker hit, spread into gcg
+//     cg_apply_item  q = S p_j from gcg; stores p_j and q; p.q rows
+//     cg_update_item alpha_j = rz_j / p_j.q; G += alpha_j p_j; r -= alpha_j q;
+//                    rz_{j+1};
+//                    beta_{j+1} = rz_{j+1} / rz_j; clears gcg; on the last
+//                    step F = G / dV, the record carries G, wrench partials
+//   then the ordinary spread of the record into gfix.
+// Each dot product is a sum of per-workgroup partial rows added in row order:
+// p.q by every update workgroup; r.z by the init or update workgroup that
+// arrives last (cg_last_arrival), which stores rz and beta for the kernels
+// that follow. Every workgroup uses the same values, and the step is
+// deterministic.
+constexpr int kCgWG = 256;     // markers per init and update workgroup
+constexpr int kCgMaxSteps = 16;
+__device__ __host__ inline int cg_items(int n) { return (n + kCgWG - 1) / kCgWG; }
+// Partial rows and scalars, 4 floats each: p.q rows (one per apply
+// workgroup), r.z rows (one per init/update workgroup), then rz_j and beta_j
+// for j = 0 .. kCgMaxSteps.
+__device__ __host__ inline size_t cg_part_floats(int n) {
+  return 4 * ((size_t)interp_items(n) + (size_t)cg_items(n) + 2 * (kCgMaxSteps + 1));
+}
+__device__ inline float *cg_pq(const EnvView &e) { return e.cgpart; }
+__device__ inline float *cg_rzp(const EnvView &e) { return e.cgpart + 4 * (size_t)interp_items(e.n); }
+__device__ inline float *cg_scal(const EnvView &e, int which, int j) {  // which: 0 rz, 1 beta
+  return cg_rzp(e) + 4 * (size_t)cg_items(e.n) + 4 * (size_t)(which * (kCgMaxSteps + 1) + j);
+}
+
+// Sums of parts[j][0..2] over j < m in row order, by the whole workgroup (a
+// multiple of 64 threads, at most 1024). Ends with a barrier.
+__device__ inline void cg_sum3(const float *__restrict__ parts, int m, float out[3]) {
+  __shared__ float s[3][16];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  float a[3] = {0.f, 0.f, 0.f};
+  for (int j = tid; j < m; j += nt)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a[c] += parts[4 * (size_t)j + c];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) a[c] = wave_sum(a[c]);
+  if ((tid & 63) == 0)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s[c][tid >> 6] = a[c];
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    float t = 0.f;
+    for (int w = 0; w < (nt >> 6); ++w) t += s[c][w];
+    out[c] = t;
+  }
+  __syncthreads();
+}
+
+// Workgroup sums of v[0..2] written to part[0..2] by thread 0. Ends with a
+// barrier.
+__device__ inline void cg_part3(const float v[3], float *__restrict__ part) {
+  __shared__ float s[3][16];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  float w[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) w[c] = wave_sum(v[c]);
+  if (lane == 0)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s[c][wv] = w[c];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float t = 0.f;
+      for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += s[c][q];
+      part[c] = t;
+    }
+  __syncthreads();
+}
+
+// Called by every thread of each of `count` workgroups after thread 0 has
+// written the workgroup's partial row: true in the workgroup that arrives
+// last, which then sees every row. That workgroup resets the counter for the
+// next kernel.
+__device__ inline bool cg_last_arrival(int *counter, int count) {
+  __shared__ int s_last;
+  if (threadIdx.x == 0) {
+    __threadfence();  // the row, visible device-wide before the arrival
+    const int prev = atomicAdd(counter, 1);
+    s_last = prev == count - 1 ? 1 : 0;
+    if (s_last) atomicExch(counter, 0);
+  }
+  __syncthreads();
+  const bool last = s_last != 0;
+  if (last) __threadfence();
+  return last;
+}
+
+// Search direction of marker k: p = z + beta p_prev, z = 2 rho_k r (p = z on
+// the first step).
+__device__ inline void cg_direction(const EnvView &e, int k, const float *beta, bool first, float p[3]) {
+  const int n = e.n;
+  const float p2 = 2.0f * e.mstate[k];
+  const float *r = e.cg + 3 * (size_t)n, *pp = e.cg + 6 * (size_t)n;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float z = p2 * r[c * n + k];
+    p[c] = first ? z : z + beta[c] * pp[c * n + k];
+  }
+}
+
+template <bool ROT>
+__device__ inline void cg_init_item(const EnvView &e, const FrameF &fr, int item) {
+  const int n = e.n, k = item * kCgWG + (int)threadIdx.x;
+  float rz[3] = {0.f, 0.f, 0.f};
+  if (k < n) {
+    float R[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) R[c] = e.U[c * n + k] - e.mstate[(c + 1) * (size_t)n + k];
+    float r[3] = {R[0], R[1], R[2]};
+    if (ROT) {
+      float wx, wy, wz;
+      cross3(fr.omg, R[0], R[1], R[2], wx, wy, wz);
+      r[0] += wx;
+      r[1] += wy;
+      r[2] += wz;
+    }
+    const float p2 = 2.0f * e.mstate[k];
+    float *G = e.cg, *rr = e.cg + 3 * (size_t)n;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      G[c * n + k] = 0.f;
+      rr[c * n + k] = r[c];
+      rz[c] = r[c] * (p2 * r[c]);
+    }
+  }
+  cg_part3(rz, cg_rzp(e) + 4 * (size_t)item);
+  if (cg_last_arrival(e.counters + 1, cg_items(n))) {
+    float t[3];
+    cg_sum3(cg_rzp(e), cg_items(n), t);
+    if (threadIdx.x < 3) cg_scal(e, 0, 0)[threadIdx.x] = t[threadIdx.x];
+  }
+}
+
+// Markers 8*item .. 8*item+7, one wave64 each, lane = stencil node (as
+// interp_item): q_k = sum_x delta(x - X_k) gcg(x) / (2 rho(x)) with gcg the
+// spread of step j's search direction, which is stored here.
+__device__ inline void cg_apply_item(const EnvView &e, int item, int tid, int j) {
+  __shared__ float s_pq[kInterpPer][3];
+  const int lane = tid & 63, wv = tid >> 6;
+  const int k = item * kInterpPer + wv;
+  const int n = e.n;
+  const GridArgs &g = e.g;
+  float pq[3] = {0.f, 0.f, 0.f};
+  if (k < n) {
+    const float *r = e.rec + (size_t)k * REC;
+    const int s3[3] = {lane & 3, (lane >> 2) & 3, lane >> 4};
+    const int dims[3] = {g.nx, g.ny, g.nz};
+    int node[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const int jj = __float_as_int(r[12 + ax]) + s3[ax];
+      node[ax] = (ax > 0 || g.xper) ? wrap_idx(jj, dims[ax]) : jj;
+    }
+    const float d = r[s3[0]] * r[4 + s3[1]] * r[8 + s3[2]];
+    const int t = (node[0] >> 3) + g.tnx * ((node[1] >> 3) + g.tny * (node[2] >> 3));
+    const int sl = e.tile_slot[t];
+    float v[3] = {0.f, 0.f, 0.f};
+    if (sl >= 0) {  // always: the first interpolation pass checked every stencil node
+      const int lc = (node[0] & 7) | ((node[1] & 7) << 3) | ((node[2] & 7) << 6);
+      const unsigned long long *gq = e.gcg + (size_t)sl * 1536;
+      const float h = 0.5f / e.macro[(size_t)sl * 512 + lc].x;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) v[c] = from_fix(gq[512 * c + lc]) * h;
+    }
+    const float qx = wave_sum(v[0] * d), qy = wave_sum(v[1] * d), qz = wave_sum(v[2] * d);
+    if (lane == 0) {
+      const float q[3] = {qx, qy, qz};
+      float p[3];
+      cg_direction(e, k, cg_scal(e, 1, j), j == 0, p);
+      float *qv = e.cg + 9 * (size_t)n, *pv = e.cg + 6 * (size_t)n;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        qv[c * n + k] = q[c];
+        pv[c * n + k] = p[c];
+        pq[c] = p[c] * q[c];
+      }
+    }
+  }
+  if (lane == 0)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s_pq[wv][c] = pq[c];
+  __syncthreads();
+  if (tid < 3) {
+    float t = 0.f;
+    for (int q = 0; q < kInterpPer; ++q) t += s_pq[q][tid];
+    cg_pq(e)[4 * (size_t)item + tid] = t;
+  }
+}
+
+// Step j of conjugate gradients for markers item*kCgWG ... On the last step
+// also the outputs: F = G / dV, the record's spread value G, and the wrench
+// partials per interpolation item (the layout wrench_sum reads).
+__device__ inline void cg_update_item(const EnvView &e, const FrameF &fr, int item, int j, bool last) {
+  const int n = e.n, k = item * kCgWG + (int)threadIdx.x;
+  float pq[3], alpha[3];
+  cg_sum3(cg_pq(e), interp_items(n), pq);  // every workgroup, in row order
+  const float *rz = cg_scal(e, 0, j);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) alpha[c] = pq[c] > 0.f ? rz[c] / pq[c] : 0.f;
+  float rzn[3] = {0.f, 0.f, 0.f}, part[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (k < n) {
+    float *G = e.cg, *r = e.cg + 3 * (size_t)n;
+    const float *p = e.cg + 6 * (size_t)n, *q = e.cg + 9 * (size_t)n;
+    const float p2 = 2.0f * e.mstate[k];
+    float Gk[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float a = alpha[c];
+      Gk[c] = G[c * n + k] + a * p[c * n + k];
+      const float rk = r[c * n + k] - a * q[c * n + k];
+      G[c * n + k] = Gk[c];
+      r[c * n + k] = rk;
+      rzn[c] = rk * (p2 * rk);
+    }
+    if (last) {
+      const float idv = 1.0f / e.dv[k];
+      float *rec = e.rec + (size_t)k * REC;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        e.F[c * n + k] = Gk[c] * idv;
+        rec[16 + c] = Gk[c];
+      }
+      const float Uk[3] = {e.U[k], e.U[n + k], e.U[2 * n + k]};
+      const float rx = e.X[k] - fr.org[0], ry = e.X[n + k] - fr.org[1], rzz = e.X[2 * n + k] - fr.org[2];
+      part[0] = -Gk[0];
+      part[1] = -Gk[1];
+      part[2] = -Gk[2];
+      part[3] = -(ry * Gk[2] - rzz * Gk[1]);
+      part[4] = -(rzz * Gk[0] - rx * Gk[2]);
+      part[5] = -(rx * Gk[1] - ry * Gk[0]);
+      part[6] = Gk[0] * Uk[0] + Gk[1] * Uk[1] + Gk[2] * Uk[2];
+    }
+  }
+  if (!last) {
+    cg_part3(rzn, cg_rzp(e) + 4 * (size_t)item);
+    if (cg_last_arrival(e.counters + 1, cg_items(n))) {
+      float t[3];
+      cg_sum3(cg_rzp(e), cg_items(n), t);
+      if (threadIdx.x < 3) {
+        const float rz0 = cg_scal(e, 0, j)[threadIdx.x];
+        cg_scal(e, 0, j + 1)[threadIdx.x] = t[threadIdx.x];
+        cg_scal(e, 1, j + 1)[threadIdx.x] = rz0 != 0.f ? t[threadIdx.x] / rz0 : 0.f;
+      }
+    }
+    return;
+  }
+  // groups of kInterpPer consecutive markers form one interpolation item
+#pragma unroll
+  for (int qd = 0; qd < 7; ++qd)
+    for (int o = kInterpPer / 2; o > 0; o >>= 1) part[qd] += __shfl_xor(part[qd], o, kInterpPer);
+  const int it = k / kInterpPer;
+  if ((k % kInterpPer) == 0 && k < n)
+#pragma unroll
+    for (int qd = 0; qd < 7; ++qd) e.partials[(size_t)it * 8 + qd] = part[qd];
+}
+
+template <bool ROT>
+__global__ void __launch_bounds__(kCgWG) k_cg_init(EnvView e, FrameF fr) { cg_init_item<ROT>(e, fr, blockIdx.x); }
+
+// Spreading of step j's search direction into gcg.
+__global__ void __launch_bounds__(WG) k_spread_cg(EnvView e, int j) {
+  const int items = n_active_of(e) * kSpreadSplit;
+  const float *beta = cg_scal(e, 1, j);
+  for (int item = blockIdx.x; item < items; item += gridDim.x)
+    spread_item<true>(e, item, threadIdx.x, e.gcg, beta, j == 0);
+}
+
+// Grid: exactly interp_items(n) workgroups (the last-arrival count).
+__global__ void __launch_bounds__(WG) k_cg_apply(EnvView e, int j) { cg_apply_item(e, blockIdx.x, threadIdx.x, j); }
+
+// Grid: at least cg_items(n) workgroups; the first cg_items(n) take the
+// markers, and all of them clear gcg for the next step's spread (not after
+// the last step: the next lattice step's macro pass clears it).
+__global__ void __launch_bounds__(kCgWG) k_cg_update(EnvView e, FrameF fr, int j, int last) {
+  if ((int)blockIdx.x < cg_items(e.n)) cg_update_item(e, fr, blockIdx.x, j, last != 0);
+  if (last) return;
+  const size_t words = (size_t)n_active_of(e) * 1536;
+  for (size_t q = (size_t)blockIdx.x * kCgWG + threadIdx.x; q < words; q += (size_t)gridDim.x * kCgWG) e.gcg[q] = 0ull;
 }
 
 // Block reduction of 8 floats over the workgroup.

@@ -28,7 +28,9 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Layout {
   int tnx, tny, tnz, ntiles, cap, maxm;
   size_t guard, counters, tile_flag, tile_slot, active, mbase, chunk_box, partials, macro, gbuf, rec, mstate;
-  size_t gbar, adjfix, mbar, pbar, facebuf, total;
+  size_t gbar, adjfix, mbar, pbar, facebuf;
+  size_t gcg, cg, cgpart;  // implicit velocity correction only
+  size_t total;
 };
 
 bool params_ok(const lbm_params *p) {
@@ -48,6 +50,7 @@ bool params_ok(const lbm_params *p) {
   if (p->block_x < 0 || p->block_y < 0 || p->block_x * p->block_y > 512) return false;
   if (p->block_x > 0 && p->block_x % 64 != 0) return false;
   if (!(p->ib_alpha > 0.0) || !std::isfinite(p->ib_alpha)) return false;
+  if (p->ib_scheme != LBM_IB_DIRECT && p->ib_scheme != LBM_IB_IMPLICIT) return false;
   return true;
 }
 
@@ -96,6 +99,12 @@ Layout layout(const lbm_params *p) {
     L.mbar = take(sizeof(float) * 6 * (size_t)L.maxm);
     L.pbar = take(sizeof(float) * 24 * kPoseSplit * (size_t)p->max_bones);
     L.facebuf = take(sizeof(float) * 2 * 4 * (size_t)p->ny * p->nz);
+  }
+  L.gcg = L.cg = L.cgpart = 0;
+  if (p->ib_scheme == LBM_IB_IMPLICIT) {
+    L.gcg = take(sizeof(unsigned long long) * 3 * 512 * (size_t)L.cap);
+    L.cg = take(sizeof(float) * 12 * (size_t)L.maxm);
+    L.cgpart = take(sizeof(float) * cg_part_floats(L.maxm));
   }
   L.total = o;
   return L;
@@ -234,6 +243,11 @@ EnvView env_view(lbm_ctx *c, const lbm_markers *m) {
   e.gfix = wsp<unsigned long long>(c, c->L.gbuf);
   e.rec = wsp<float>(c, c->L.rec);
   e.mstate = wsp<float>(c, c->L.mstate);
+  if (c->p.ib_scheme == LBM_IB_IMPLICIT) {
+    e.gcg = wsp<unsigned long long>(c, c->L.gcg);
+    e.cg = wsp<float>(c, c->L.cg);
+    e.cgpart = wsp<float>(c, c->L.cgpart);
+  }
   e.cur0 = c->cur;
   return e;
 }
@@ -296,6 +310,31 @@ lbm_status launch_interp(lbm_ctx *c, const EnvView &e, const FrameF &fr, bool ro
   return launched();
 }
 
+// Conjugate-gradient steps of the implicit velocity correction (after the
+// first interpolation pass; the final spread into gfix follows).
+lbm_status launch_implicit(lbm_ctx *c, const EnvView &e, const FrameF &fr, bool rot) {
+  lbm_status st;
+  const int items = cg_items(e.n);
+  if (rot)
+    k_cg_init<true><<<items, kCgWG, 0, c->stream>>>(e, fr);
+  else
+    k_cg_init<false><<<items, kCgWG, 0, c->stream>>>(e, fr);
+  if ((st = launched()) != LBM_OK) return st;
+  const int spread_grid = std::min(c->L.cap * kSpreadSplit, 2048);
+  const int clear_grid = std::max(items, std::min((int)(((size_t)c->L.cap * 1536 + 4 * kCgWG - 1) / (4 * kCgWG)), 1024));
+  const int steps = c->p.mdf_iters;
+  for (int j = 0; j < steps; ++j) {
+    const bool last = j == steps - 1;
+    k_spread_cg<<<spread_grid, WG, 0, c->stream>>>(e, j);
+    if ((st = launched()) != LBM_OK) return st;
+    k_cg_apply<<<interp_items(e.n), WG, 0, c->stream>>>(e, j);
+    if ((st = launched()) != LBM_OK) return st;
+    k_cg_update<<<last ? items : clear_grid, kCgWG, 0, c->stream>>>(e, fr, j, last ? 1 : 0);
+    if ((st = launched()) != LBM_OK) return st;
+  }
+  return LBM_OK;
+}
+
 void prof_mark(lbm_ctx *c, int which) {
   if (c->prof && c->prof_used < kProfSteps) (void)hipEventRecord(c->ev[3 * c->prof_used + which], c->stream);
 }
@@ -315,9 +354,14 @@ lbm_status step_one(lbm_ctx *c, const lbm_markers *m, const float *pose, const l
     c->slots_dirty = true;
     if ((st = launch_macro<S>(c, e, fr, rot)) != LBM_OK) return st;
     const int passes = c->p.mdf_iters;
-    for (int it = 0; it < passes; ++it) {
-      if (it > 0 && (st = launch_spread(c, e, nullptr)) != LBM_OK) return st;
-      if ((st = launch_interp(c, e, fr, rot, it > 0, wrench != nullptr && it == passes - 1)) != LBM_OK) return st;
+    if (c->p.ib_scheme == LBM_IB_IMPLICIT) {
+      if ((st = launch_interp(c, e, fr, rot, false, false)) != LBM_OK) return st;
+      if ((st = launch_implicit(c, e, fr, rot)) != LBM_OK) return st;
+    } else {
+      for (int it = 0; it < passes; ++it) {
+        if (it > 0 && (st = launch_spread(c, e, nullptr)) != LBM_OK) return st;
+        if ((st = launch_interp(c, e, fr, rot, it > 0, wrench != nullptr && it == passes - 1)) != LBM_OK) return st;
+      }
     }
     if ((st = launch_spread(c, e, wrench)) != LBM_OK) return st;
   } else if (c->slots_dirty) {
@@ -513,7 +557,8 @@ lbm_status adjoint_request_ok(const lbm_ctx *c, const lbm_markers *m, const floa
   if (ib && m->n > c->p.max_markers) return LBM_ERR_CAPACITY;
   for (int q = 0; q < 4; ++q)
     if (!std::isfinite(w[q])) return LBM_ERR_ARG;
-  if (c->p.storage != LBM_STORE_F32 || c->p.mdf_iters != 1 || !c->p.with_adjoint) return LBM_ERR_UNSUPPORTED;
+  if (c->p.storage != LBM_STORE_F32 || c->p.mdf_iters != 1 || c->p.ib_scheme != LBM_IB_DIRECT || !c->p.with_adjoint)
+    return LBM_ERR_UNSUPPORTED;
   if (c->p.bc_y[0] != LBM_BC_PERIODIC || c->p.bc_z[0] != LBM_BC_PERIODIC) return LBM_ERR_UNSUPPORTED;
   return LBM_OK;
 }
@@ -1039,6 +1084,7 @@ lbm_status lbm_batch_create(lbm_batch **out, const lbm_env *envs, int32_t nenv, 
   for (int e = 0; e < nenv; ++e) {
     if (!env_ok(envs[e])) return LBM_ERR_ARG;
     if (envs[e].ctx->p.mdf_iters != envs[0].ctx->p.mdf_iters) return LBM_ERR_ARG;
+    if (envs[e].ctx->p.ib_scheme != LBM_IB_DIRECT) return LBM_ERR_UNSUPPORTED;
     for (int f = 0; f < e; ++f)
       if (envs[f].ctx == envs[e].ctx) return LBM_ERR_ARG;
   }

@@ -33,7 +33,8 @@ def test_population_and_workspace_sizes(L):
 @pytest.mark.parametrize("bad", [
     dict(tau=0.5), dict(tau=0.3), dict(nx=3), dict(nz=0),
     dict(bc_lo=lbm.BC_PERIODIC, bc_hi=lbm.BC_OUTFLOW), dict(storage=7), dict(max_bones=0),
-    dict(mdf_iters=0), dict(block=(96, 1)), dict(block=(512, 2)), dict(ib_alpha=0.0),
+    dict(mdf_iters=0), dict(mdf_iters=17), dict(block=(96, 1)), dict(block=(512, 2)), dict(ib_alpha=0.0),
+    dict(ib_scheme=2), dict(ib_scheme=-1),
 ])
 def test_invalid_parameters_are_rejected(L, bad):
     kw = dict(nx=16, ny=16, nz=16, tau=0.6, bc_lo=lbm.BC_VELOCITY, bc_hi=lbm.BC_OUTFLOW)
@@ -112,3 +113,15 @@ def test_adjoint_batch_and_state_calls_on_null_handles_fail_cleanly(L):
     assert L.lbm_batch_set_shapes(None, None) == -1
     assert L.lbm_batch_check(None) == -1
     L.lbm_batch_destroy(None)
+
+
+def test_implicit_scheme_workspace_holds_its_buffers(L):
+    """The implicit velocity correction's buffers (a second fixed-point force
+    per active tile, four marker vectors, dot-product partials) are laid out
+    only when asked for."""
+    kw = dict(max_markers=3000, max_bones=10, max_active_tiles=256)
+    d = lbm.make_params(128, 64, 64, 0.6, **kw)
+    i = lbm.make_params(128, 64, 64, 0.6, ib_scheme=lbm.IB_IMPLICIT, **kw)
+    extra = L.lbm_workspace_bytes(ctypes.byref(i)) - L.lbm_workspace_bytes(ctypes.byref(d))
+    assert extra >= 256 * 1536 * 8 + 12 * 3000 * 4
+    assert extra < 256 * 1536 * 8 + 12 * 3000 * 4 + 64 * 1024
