@@ -505,9 +505,9 @@ namespace {
 
 // Implicit velocity correction (the implicit immersed-boundary variant the
 // paper cites in its Introduction, Wu and Shu's velocity correction). The
-// marker forces
-// G_k = F_k dV_k are the ones whose spread force, added to the fluid velocity,
-// brings the interpolated velocity to the body velocity at every marker:
+// marker forces G_k = F_k dV_k are the ones whose spread force, added to the
+// fluid velocity, brings the interpolated velocity to the body velocity at
+// every marker:
 //   interp(u*) + interp(M spread(G) / (2 rho)) = U,
 // with M = (I + [omega]x)^-1 the Coriolis solve that defines the fluid
 // velocity. M is the same 3x3 matrix at every node, so the system separates:
