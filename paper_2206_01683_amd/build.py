@@ -6,7 +6,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "lbm_ib.hip")
 LIB = os.path.join(HERE, "liblbmib.so")
-HEADERS = [os.path.join(HERE, "csrc", h) for h in ("lattice.hpp", "env.hpp", "fluid.hpp", "ib.hpp", "batch.hpp", "adjoint.hpp")] + [
+HEADERS = [os.path.join(HERE, "csrc", h) for h in ("lattice.hpp", "env.hpp", "fluid.hpp", "ib.hpp", "batch.hpp",
+                                                   "adjoint.hpp", "swimmer.hpp")] + [
     os.path.join(ROOT, "include", "lbm_ib.h")]
 
 HIPCC_FLAGS = [
