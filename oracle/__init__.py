@@ -26,6 +26,8 @@ _lib = None
 
 BC_PERIODIC, BC_VELOCITY, BC_OUTFLOW = 0, 1, 2
 IB_DIRECT, IB_IMPLICIT = 0, 1
+COLLIDE_BGK, COLLIDE_TRT = 0, 1
+TRT_MAGIC = 3.0 / 16.0
 
 
 def build(force: bool = True) -> str:
@@ -43,7 +45,8 @@ class _Params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("bc_lo", ctypes.c_int32), ("bc_hi", ctypes.c_int32), ("mdf_iters", ctypes.c_int32),
                 ("tau", ctypes.c_double), ("ib_alpha", ctypes.c_double),
-                ("bc_y", ctypes.c_int32 * 2), ("bc_z", ctypes.c_int32 * 2), ("ib_scheme", ctypes.c_int32)]
+                ("bc_y", ctypes.c_int32 * 2), ("bc_z", ctypes.c_int32 * 2), ("ib_scheme", ctypes.c_int32),
+                ("collision", ctypes.c_int32), ("trt_lambda", ctypes.c_double)]
 
 
 class _Markers(ctypes.Structure):
@@ -69,6 +72,7 @@ def lib():
         L.or_frame_accel_static.argtypes = [dp, dp, dp]
         L.or_node_velocity.argtypes = [ctypes.c_double, dp, dp, dp, dp, dp, dp]
         L.or_collide_node.argtypes = [dp, dp, dp, dp, ctypes.c_double, dp, dp, dp]
+        L.or_collide_node_trt.argtypes = [dp, dp, dp, dp, ctypes.c_double, ctypes.c_double, dp, dp, dp]
         L.or_skin.argtypes = [dp, dp, dp, dp]
         L.or_interpolate.argtypes = [dp, dp, ctypes.c_int, dp, ctypes.c_int, dp]
         L.or_spread.argtypes = [dp, dp, ctypes.c_int, dp, dp]
@@ -90,14 +94,16 @@ def _f64(a) -> np.ndarray:
 
 
 def params(nx, ny, nz, tau, bc_lo=BC_PERIODIC, bc_hi=BC_PERIODIC, mdf_iters=1, ib_alpha=1.0,
-           bc_y=(BC_PERIODIC, BC_PERIODIC), bc_z=(BC_PERIODIC, BC_PERIODIC), ib_scheme=IB_DIRECT) -> _Params:
+           bc_y=(BC_PERIODIC, BC_PERIODIC), bc_z=(BC_PERIODIC, BC_PERIODIC), ib_scheme=IB_DIRECT,
+           collision=COLLIDE_BGK, trt_lambda=TRT_MAGIC) -> _Params:
     """Face conditions: x by bc_lo / bc_hi, y and z by the pairs bc_y, bc_z
     (low, high); an axis is periodic or open on both faces. ib_scheme
     IB_DIRECT: explicit direct forcing plus mdf_iters - 1 multi-direct-forcing
     passes; IB_IMPLICIT: the implicit velocity correction, mdf_iters
-    conjugate-gradient steps."""
+    conjugate-gradient steps. collision COLLIDE_BGK, or COLLIDE_TRT with
+    Lambda = (tau - 1/2)(tau- - 1/2) = trt_lambda."""
     return _Params(nx, ny, nz, bc_lo, bc_hi, mdf_iters, tau, ib_alpha, (ctypes.c_int32 * 2)(*bc_y),
-                   (ctypes.c_int32 * 2)(*bc_z), ib_scheme)
+                   (ctypes.c_int32 * 2)(*bc_z), ib_scheme, collision, trt_lambda)
 
 
 def threads() -> int:
@@ -148,12 +154,17 @@ def node_velocity(rho, m, g, frame, x):
     return u, F
 
 
-def collide_node(f, g, frame, x, tau):
+def collide_node(f, g, frame, x, tau, trt_lambda=None):
+    """One node's collision: BGK, or TRT with Lambda = trt_lambda."""
     f, g, fr, x = _f64(f), _f64(g), _f64(frame), _f64(x)
     out = np.zeros(27)
     u = np.zeros(3)
     F = np.zeros(3)
-    lib().or_collide_node(_p(f), _p(g), _p(fr), _p(x), float(tau), _p(out), _p(u), _p(F))
+    if trt_lambda is None:
+        lib().or_collide_node(_p(f), _p(g), _p(fr), _p(x), float(tau), _p(out), _p(u), _p(F))
+    else:
+        lib().or_collide_node_trt(_p(f), _p(g), _p(fr), _p(x), float(tau), float(trt_lambda), _p(out), _p(u),
+                                  _p(F))
     return out, u, F
 
 
@@ -265,7 +276,8 @@ def initial_populations(rho: np.ndarray, u: np.ndarray) -> np.ndarray:
 
 def run_workload(w, nsteps=None, f0=None):
     """Run an inputs.Workload from its initial state f = f^eq(1, u0)."""
-    prm = params(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi, w.mdf_iters, w.ib_alpha, w.bc_y, w.bc_z, w.ib_scheme)
+    prm = params(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi, w.mdf_iters, w.ib_alpha, w.bc_y, w.bc_z, w.ib_scheme,
+                 w.collision, w.trt_lambda)
     if f0 is None:
         f0 = equilibrium_field(np.ones((w.nz, w.ny, w.nx)), w.u0)
     return run(prm, f0, w.frames, w.markers, w.poses, nsteps or w.nsteps)

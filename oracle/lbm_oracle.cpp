@@ -128,6 +128,8 @@ enum { OR_BC_PERIODIC = 0, OR_BC_VELOCITY = 1, OR_BC_OUTFLOW = 2 };
 // multi-direct-forcing passes), or the implicit velocity correction solved by
 // mdf_iters conjugate-gradient steps.
 enum { OR_IB_DIRECT = 0, OR_IB_IMPLICIT = 1 };
+// Collisions: BGK, or the two-relaxation-time collision (see Relax).
+enum { OR_COLLIDE_BGK = 0, OR_COLLIDE_TRT = 1 };
 
 struct OrParams {
   int32_t nx, ny, nz;
@@ -138,6 +140,8 @@ struct OrParams {
   int32_t bc_y[2];       // y = 0 and y = ny-1 (0: periodic, the default)
   int32_t bc_z[2];       // z = 0 and z = nz-1
   int32_t ib_scheme;     // OR_IB_*
+  int32_t collision;     // OR_COLLIDE_*
+  double trt_lambda;     // TRT: Lambda = (tau - 1/2)(tau- - 1/2) > 0
 };
 
 // Frame of reference for one step (Eq. (3)): linear acceleration of the
@@ -213,11 +217,63 @@ void node_velocity(T rho, const T *m, const T *g, const OrFrame *fr, const doubl
   for (int a = 0; a < 3; ++a) F[a] = g[a] + rho * (a0[a] - 2.0 * wu[a]);
 }
 
-// BGK collision with Guo's forcing term at one node:
-//   f*_i = f_i - (f_i - f^eq_i(rho,u)) / tau
-//          + (1 - 1/(2 tau)) w_i [3 (c_i - u) + 9 (c_i.u) c_i] . F.
+// Relaxation of the collision. BGK: one rate 1/tau. TRT (the two-relaxation-
+// time member of the multiple-relaxation-time family): the parts of f even
+// and odd in c relax at their own rates, omega+ = 1/tau (it sets the
+// viscosity, nu = (tau - 1/2)/3) and omega- = 1/tau- with
+// (tau - 1/2)(tau- - 1/2) = Lambda.
+struct Relax {
+  bool trt;
+  double tau;     // BGK relaxation time; TRT: tau+
+  double wp, wm;  // omega+, omega-
+};
+
+Relax relax_bgk(double tau) { return Relax{false, tau, 1.0 / tau, 1.0 / tau}; }
+Relax relax_trt(double tau, double lambda) {
+  const double tm = 0.5 + lambda / (tau - 0.5);
+  return Relax{true, tau, 1.0 / tau, 1.0 / tm};
+}
+
+// Opposite velocity: c_opp(i) = -c_i.
+int opposite(int i) {
+  for (int j = 0; j < 27; ++j)
+    if (L.c[j][0] == -L.c[i][0] && L.c[j][1] == -L.c[i][1] && L.c[j][2] == -L.c[i][2]) return j;
+  return -1;
+}
+
+// Guo's source term without its relaxation prefactor:
+//   S_i = w_i [3 (c_i - u) + 9 (c_i.u) c_i] . F.
 template <class T>
-void collide_node(const T *f, const T *g, const OrFrame *fr, const double *x, double tau, T *fout, T *u_out,
+void guo_source(const T u[3], const T F[3], T S[27]) {
+  for (int i = 0; i < 27; ++i) {
+    T cu = (double)L.c[i][0] * u[0] + (double)L.c[i][1] * u[1] + (double)L.c[i][2] * u[2];
+    T s = 0.0;
+    for (int a = 0; a < 3; ++a) s += (3.0 * ((double)L.c[i][a] - u[a]) + 9.0 * cu * (double)L.c[i][a]) * F[a];
+    S[i] = L.w[i] * s;
+  }
+}
+
+// TRT update of populations h towards e with source S: with x+_i and x-_i the
+// parts of x even and odd in c, (x_i + x_opp(i))/2 and (x_i - x_opp(i))/2,
+//   h*_i = h_i - omega+ (h+_i - e+_i) - omega- (h-_i - e-_i)
+//          + (1 - omega+/2) S+_i + (1 - omega-/2) S-_i.
+template <class T>
+void trt_update(const Relax &rx, const T *h, const T *e, const T *S, T *out) {
+  for (int i = 0; i < 27; ++i) {
+    const int j = opposite(i);
+    const T hp = 0.5 * (h[i] + h[j]), hm = 0.5 * (h[i] - h[j]);
+    const T ep = 0.5 * (e[i] + e[j]), em = 0.5 * (e[i] - e[j]);
+    const T sp = 0.5 * (S[i] + S[j]), sm = 0.5 * (S[i] - S[j]);
+    out[i] = h[i] - rx.wp * (hp - ep) - rx.wm * (hm - em) + (1.0 - 0.5 * rx.wp) * sp + (1.0 - 0.5 * rx.wm) * sm;
+  }
+}
+
+// Collision with Guo's forcing term at one node. BGK:
+//   f*_i = f_i - (f_i - f^eq_i(rho,u)) / tau
+//          + (1 - 1/(2 tau)) w_i [3 (c_i - u) + 9 (c_i.u) c_i] . F;
+// TRT: trt_update with e = f^eq(rho, u) and S = Guo's source.
+template <class T>
+void collide_node(const T *f, const T *g, const OrFrame *fr, const double *x, const Relax &rx, T *fout, T *u_out,
                   T *F_out) {
   T rho = 0.0, m[3] = {0.0, 0.0, 0.0};
   for (int i = 0; i < 27; ++i) {
@@ -228,12 +284,19 @@ void collide_node(const T *f, const T *g, const OrFrame *fr, const double *x, do
   node_velocity(rho, m, g, fr, x, u, F);
   T feq[27];
   equilibrium(rho, u, feq);
-  double pref = 1.0 - 1.0 / (2.0 * tau);
-  for (int i = 0; i < 27; ++i) {
-    T cu = (double)L.c[i][0] * u[0] + (double)L.c[i][1] * u[1] + (double)L.c[i][2] * u[2];
-    T s = 0.0;
-    for (int a = 0; a < 3; ++a) s += (3.0 * ((double)L.c[i][a] - u[a]) + 9.0 * cu * (double)L.c[i][a]) * F[a];
-    fout[i] = f[i] - (f[i] - feq[i]) / tau + pref * L.w[i] * s;
+  if (rx.trt) {
+    T S[27];
+    guo_source(u, F, S);
+    trt_update(rx, f, feq, S, fout);
+  } else {
+    const double tau = rx.tau;
+    double pref = 1.0 - 1.0 / (2.0 * tau);
+    for (int i = 0; i < 27; ++i) {
+      T cu = (double)L.c[i][0] * u[0] + (double)L.c[i][1] * u[1] + (double)L.c[i][2] * u[2];
+      T s = 0.0;
+      for (int a = 0; a < 3; ++a) s += (3.0 * ((double)L.c[i][a] - u[a]) + 9.0 * cu * (double)L.c[i][a]) * F[a];
+      fout[i] = f[i] - (f[i] - feq[i]) / tau + pref * L.w[i] * s;
+    }
   }
   if (u_out)
     for (int a = 0; a < 3; ++a) u_out[a] = u[a];
@@ -272,7 +335,7 @@ void skin(const OrMarkers *mk, const T *poses, T *X, T *U) {
 
 extern "C" {
 
-int or_abi_version(void) { return 3; }
+int or_abi_version(void) { return 4; }
 
 // Threads a parallel lattice sweep uses.
 int or_threads(void) {
@@ -313,7 +376,13 @@ void or_node_velocity(double rho, const double *m, const double *g, const OrFram
 
 void or_collide_node(const double *f, const double *g, const OrFrame *fr, const double *x, double tau, double *fout,
                      double *u_out, double *F_out) {
-  collide_node(f, g, fr, x, tau, fout, u_out, F_out);
+  collide_node(f, g, fr, x, relax_bgk(tau), fout, u_out, F_out);
+}
+
+// The TRT collision at one node (tests): tau = tau+, lambda = Lambda.
+void or_collide_node_trt(const double *f, const double *g, const OrFrame *fr, const double *x, double tau,
+                         double lambda, double *fout, double *u_out, double *F_out) {
+  collide_node(f, g, fr, x, relax_trt(tau, lambda), fout, u_out, F_out);
 }
 
 void or_skin(const OrMarkers *mk, const double *poses, double *X, double *U) { skin(mk, poses, X, U); }
@@ -587,6 +656,9 @@ int run(const OrParams *p, T *f, const OrMarkers *mk, const T *poses, const OrFr
   if (p->mdf_iters < 1 || (p->ib_scheme != OR_IB_DIRECT && p->ib_scheme != OR_IB_IMPLICIT)) return -1;
   const size_t N = G.ncell();
   const double tau = p->tau;
+  if (p->collision != OR_COLLIDE_BGK && p->collision != OR_COLLIDE_TRT) return -1;
+  if (p->collision == OR_COLLIDE_TRT && !(p->trt_lambda > 0.0 && std::isfinite(p->trt_lambda))) return -1;
+  const Relax rx = p->collision == OR_COLLIDE_TRT ? relax_trt(tau, p->trt_lambda) : relax_bgk(tau);
   const int nm = mk ? mk->n : 0;
 
   std::vector<T> fpost(27 * N), rho(N), ustar(3 * N), g(3 * N, T(0.0));
@@ -652,7 +724,7 @@ int run(const OrParams *p, T *f, const OrMarkers *mk, const T *poses, const OrFr
           for (int i = 0; i < 27; ++i) fl[i] = f[i * N + id];
           T gg[3] = {g[id], g[N + id], g[2 * N + id]};
           double pos[3] = {(double)x, (double)y, (double)z};
-          collide_node(fl, gg, fr, pos, tau, fo, (T *)nullptr, (T *)nullptr);
+          collide_node(fl, gg, fr, pos, rx, fo, (T *)nullptr, (T *)nullptr);
           for (int i = 0; i < 27; ++i) fpost[i * N + id] = fo[i];
         }
 
@@ -698,13 +770,24 @@ int run(const OrParams *p, T *f, const OrMarkers *mk, const T *poses, const OrFr
             T feq_b[27], feq_f[27];
             equilibrium(r, ub, feq_b);
             equilibrium(r, uf, feq_f);
-            double pref = 1.0 - 1.0 / (2.0 * tau);
-            for (int i = 0; i < 27; ++i) {
-              T cu = (double)L.c[i][0] * ub[0] + (double)L.c[i][1] * ub[1] + (double)L.c[i][2] * ub[2];
-              T s = 0.0;
-              for (int a = 0; a < 3; ++a)
-                s += (3.0 * ((double)L.c[i][a] - ub[a]) + 9.0 * cu * (double)L.c[i][a]) * Fb[a];
-              fpost[i * N + idb] = feq_b[i] + (1.0 - 1.0 / tau) * (fl[i] - feq_f[i]) + pref * L.w[i] * s;
+            if (rx.trt) {
+              // TRT: the non-equilibrium part's even and odd halves relax at
+              // their own rates, f*(x_b) = trt_update of h = f^eq(u_b) + f(x_f) -
+              // f^eq(u_f) towards f^eq(u_b) with the source at (u_b, F_b)
+              T h[27], Sb[27], out[27];
+              for (int i = 0; i < 27; ++i) h[i] = feq_b[i] + (fl[i] - feq_f[i]);
+              guo_source(ub, Fb, Sb);
+              trt_update(rx, h, feq_b, Sb, out);
+              for (int i = 0; i < 27; ++i) fpost[i * N + idb] = out[i];
+            } else {
+              double pref = 1.0 - 1.0 / (2.0 * tau);
+              for (int i = 0; i < 27; ++i) {
+                T cu = (double)L.c[i][0] * ub[0] + (double)L.c[i][1] * ub[1] + (double)L.c[i][2] * ub[2];
+                T s = 0.0;
+                for (int a = 0; a < 3; ++a)
+                  s += (3.0 * ((double)L.c[i][a] - ub[a]) + 9.0 * cu * (double)L.c[i][a]) * Fb[a];
+                fpost[i * N + idb] = feq_b[i] + (1.0 - 1.0 / tau) * (fl[i] - feq_f[i]) + pref * L.w[i] * s;
+              }
             }
           }
     }

@@ -361,6 +361,8 @@ class Workload:
     bc_y: tuple = (BC_PERIODIC, BC_PERIODIC)  # y = 0, y = ny-1
     bc_z: tuple = (BC_PERIODIC, BC_PERIODIC)  # z = 0, z = nz-1
     ib_scheme: int = 0                        # 0 direct forcing, 1 implicit velocity correction
+    collision: int = 0                        # 0 BGK, 1 two-relaxation-time
+    trt_lambda: float = 3.0 / 16.0            # TRT: (tau - 1/2)(tau- - 1/2)
 
     @property
     def ncell(self) -> int:
