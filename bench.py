@@ -56,7 +56,7 @@ def measured_traffic(storage: str):
     return float(vals[key]) if key in vals else None
 
 
-def run_gpu(storage: str, steps: int, warmup: int, block=(0, 0)):
+def run_gpu(storage: str, steps: int, warmup: int, block=(0, 0), collision: int = 0):
     import numpy as np
     import torch
 
@@ -65,7 +65,7 @@ def run_gpu(storage: str, steps: int, warmup: int, block=(0, 0)):
 
     w = I.fish_workload(nsteps=warmup + steps)
     sim = lbm.Simulation(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi, storage=storage, max_markers=w.markers.n,
-                         max_bones=w.markers.nbones, block=block)
+                         max_bones=w.markers.nbones, block=block, collision=collision)
     dm = lbm.DeviceMarkers(w.markers)
     poses = torch.as_tensor(np.ascontiguousarray(w.poses, np.float32), device="cuda")
     wrench = torch.zeros((warmup + steps, 8), dtype=torch.float32, device="cuda")
@@ -293,8 +293,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f32", choices=sorted(BYTES_PER_CELL))
     ap.add_argument("--cpu-steps", type=int, default=24, help="oracle sample length (0: skip)")
-    ap.add_argument("--forms", default="f16,bf16,batched,adjoint,two_fish,free_swimmer,ib_schemes",
-                    help="comma-separated extra forms to measure: f16, bf16, batched, adjoint, two_fish, "
+    ap.add_argument("--forms", default="f16,bf16,trt,batched,adjoint,two_fish,free_swimmer,ib_schemes",
+                    help="comma-separated extra forms to measure: f16, bf16, trt, batched, adjoint, two_fish, "
                          "free_swimmer, ib_schemes")
     ap.add_argument("--no-forms", action="store_true", help="measure no extra form")
     ap.add_argument("--block", type=int, nargs=2, default=(0, 0))
@@ -318,6 +318,12 @@ def main():
             forms[st] = {"mlups": round(r["mlups"], 1), "collide_GBps": round(r["collide_gbs"], 1),
                          "collide_frac_of_hbm_peak": round(r["collide_gbs"] / HBM_PEAK_GBS, 4),
                          "bytes_per_cell": BYTES_PER_CELL[st], "status": r["status"]}
+    if "trt" in want:
+        from paper_2206_01683_amd import lbm as _lbm
+        r = run_gpu(args.storage, args.steps, args.warmup, tuple(args.block), collision=_lbm.COLLIDE_TRT)
+        forms["trt"] = {"mlups": round(r["mlups"], 1), "collide_GBps": round(r["collide_gbs"], 1),
+                        "collide_frac_of_hbm_peak": round(r["collide_gbs"] / HBM_PEAK_GBS, 4),
+                        "lambda": _lbm.TRT_MAGIC, "status": r["status"]}
     if "batched" in want and args.batch_envs > 0:
         forms["batched"] = run_batch(args.batch_envs, args.batch_steps)
     if "adjoint" in want:

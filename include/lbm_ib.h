@@ -15,7 +15,8 @@
  *
  * Method as implemented (the paper leaves these details open):
  *   lattice      D3Q27, c_i in {-1,0,1}^3, i = (cx+1) + 3(cy+1) + 9(cz+1)
- *   collision    BGK, relaxation time tau > 1/2, second-order equilibrium
+ *   collision    BGK, relaxation time tau > 1/2, second-order equilibrium;
+ *                or two-relaxation-time (LBM_COLLIDE_TRT)
  *   forcing      Guo: velocity u = (m + F/2)/rho; F = g + rho a_ni(x, u),
  *                a_ni from Eq. (3), solved exactly for the Coriolis term
  *   streaming    pull; each axis periodic or open
@@ -94,6 +95,21 @@ enum { LBM_STORE_F32 = 0, LBM_STORE_F16 = 1, LBM_STORE_BF16 = 2 };
  *   return LBM_ERR_UNSUPPORTED). */
 enum { LBM_IB_DIRECT = 0, LBM_IB_IMPLICIT = 1 };
 
+/* Collisions (lbm_params.collision).
+ * BGK: f*_i = f_i - (f_i - f^eq_i)/tau + (1 - 1/(2 tau)) S_i, S_i = Guo's
+ *   source w_i [3 (c_i - u) + 9 (c_i.u) c_i].F.
+ * TRT: the two-relaxation-time collision, the smallest member of the
+ *   multiple-relaxation-time family the paper's solver family admits: with
+ *   x+_i and x-_i the parts of x even and odd in c ((x_i +- x_opp(i))/2),
+ *     f*_i = f_i - w+ (f+_i - f^eq+_i) - w- (f-_i - f^eq-_i)
+ *            + (1 - w+/2) S+_i + (1 - w-/2) S-_i,
+ *   w+ = 1/tau (the viscosity stays (tau - 1/2)/3) and w- = 1/tau- with
+ *   (tau - 1/2)(tau- - 1/2) = trt_lambda (> 0; 3/16 is the usual choice).
+ *   Open faces extrapolate as before, the non-equilibrium part's even and
+ *   odd halves relaxing at w+ and w-. Supported by lbm_ib_step; the batched
+ *   and adjoint entry points return LBM_ERR_UNSUPPORTED. */
+enum { LBM_COLLIDE_BGK = 0, LBM_COLLIDE_TRT = 1 };
+
 typedef struct lbm_ctx lbm_ctx;
 
 /* [host] Problem description. */
@@ -111,6 +127,8 @@ typedef struct {
   double ib_alpha;           /* direct-forcing gain, > 0 (1 = full correction) */
   int32_t bc_y[2], bc_z[2];  /* LBM_BC_* for the y and z faces; zeros = periodic */
   int32_t ib_scheme;         /* LBM_IB_*; 0 = direct forcing */
+  int32_t collision;         /* LBM_COLLIDE_*; 0 = BGK */
+  double trt_lambda;         /* TRT: (tau - 1/2)(tau- - 1/2) > 0; unused by BGK */
 } lbm_params;
 
 /* [host] Frame of one step (Eq. (3)). acc = linear acceleration of the frame

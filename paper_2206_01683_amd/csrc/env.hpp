@@ -17,9 +17,17 @@ struct GridArgs {
   int bc_y[2], bc_z[2];
 };
 
+// Rates of the two-relaxation-time collision: omega+, omega-, the source
+// factors 1 - omega+/2 and 1 - omega-/2, and a = 1 - (omega+ + omega-)/2,
+// b = (omega- - omega+)/2 (f*_i = a f_i + b f_opp(i) + ...).
+struct TrtRates {
+  float wp, wm, pp, pm, a, b;
+};
+
 struct EnvView {
   GridArgs g;
   float inv_tau, omt, pref;     // 1/tau, 1 - 1/tau, 1 - 1/(2 tau)
+  TrtRates trt;                 // used by the TRT collide only
   int bx, by, gx, gy, nblocks;  // collide tile shape and its block grid (by = 0: linear, see cell_of)
   void *f[2];                   // population buffers
   // immersed boundary

@@ -154,8 +154,10 @@ __device__ inline bool collide_load(const EnvView &e, int cur, int lb, int tx, i
 }
 
 // Second half: moments, forcing, BGK + Guo (or the open-face extrapolation)
-// and the 27 stores of f*(n).
-template <class S, bool XPER, bool ROT, bool YZ = false>
+// and the 27 stores of f*(n). TRT: the two-relaxation-time collision instead
+// of BGK (even and odd parts of f relax at omega+ and omega-, Guo's source
+// split the same way).
+template <class S, bool XPER, bool ROT, bool YZ = false, bool TRT = false>
 __device__ inline void collide_finish(const EnvView &e, const FrameF &fr, int cur, const CellAt &c, float f[Q]) {
   using T = typename S::T;
   T *__restrict__ dst = static_cast<T *>(e.f[cur ^ 1]);
@@ -228,47 +230,71 @@ __device__ inline void collide_finish(const EnvView &e, const FrameF &fr, int cu
   // equilibrium and forcing split into parts even and odd in c.
   const float A = 1.0f - 1.5f * u2;
   const float uF = ux * Fx + uy * Fy + uz * Fz;
-  const float E = e.inv_tau * rho;
-  const float P = e.pref;
   const uint32_t o = ((uint32_t)z * (uint32_t)g.ny + (uint32_t)y) * (uint32_t)g.nx + (uint32_t)x;
   typename S::T *__restrict__ d = dst + o;
+  if constexpr (!TRT) {
+    const float E = e.inv_tau * rho;
+    const float P = e.pref;
 #pragma unroll
-  for (int i = 0; i < 13; ++i) {
-    const int j = 26 - i;
-    const float w = w_of(i);
-    const float cu = cdot(i, ux, uy, uz);
-    const float cF = cdot(i, Fx, Fy, Fz);
-    const float even = (w * E) * (A + 4.5f * cu * cu) + (w * P) * (9.0f * cu * cF - 3.0f * uF);
-    const float odd = (w * E) * (3.0f * cu) + (w * P) * (3.0f * cF);
-    S::store(d + (uint32_t)i * g.plane, e.omt * f[i] + even + odd, i);
-    S::store(d + (uint32_t)j * g.plane, e.omt * f[j] + even - odd, j);
-  }
-  {
-    const float w = w_of(13);
-    S::store(d + 13u * g.plane, e.omt * f[13] + (w * E) * A - (w * P) * 3.0f * uF, 13);
+    for (int i = 0; i < 13; ++i) {
+      const int j = 26 - i;
+      const float w = w_of(i);
+      const float cu = cdot(i, ux, uy, uz);
+      const float cF = cdot(i, Fx, Fy, Fz);
+      const float even = (w * E) * (A + 4.5f * cu * cu) + (w * P) * (9.0f * cu * cF - 3.0f * uF);
+      const float odd = (w * E) * (3.0f * cu) + (w * P) * (3.0f * cF);
+      S::store(d + (uint32_t)i * g.plane, e.omt * f[i] + even + odd, i);
+      S::store(d + (uint32_t)j * g.plane, e.omt * f[j] + even - odd, j);
+    }
+    {
+      const float w = w_of(13);
+      S::store(d + 13u * g.plane, e.omt * f[13] + (w * E) * A - (w * P) * 3.0f * uF, 13);
+    }
+  } else {
+    // f*_i = f_i - w+ (f+_i - e+_i) - w- (f-_i - e-_i) + (1 - w+/2) S+_i + (1 - w-/2) S-_i
+    //      = a f_i + b f_j + [w+ e+_i + (1 - w+/2) S+_i] + [w- e-_i + (1 - w-/2) S-_i],
+    // a = 1 - (w+ + w-)/2, b = (w- - w+)/2; the bracketed parts are even and
+    // odd in c, as in BGK with its single rate split in two.
+    const float Ep = e.trt.wp * rho, Em = e.trt.wm * rho;
+    const float Pp = e.trt.pp, Pm = e.trt.pm, a = e.trt.a, b = e.trt.b;
+#pragma unroll
+    for (int i = 0; i < 13; ++i) {
+      const int j = 26 - i;
+      const float w = w_of(i);
+      const float cu = cdot(i, ux, uy, uz);
+      const float cF = cdot(i, Fx, Fy, Fz);
+      const float even = (w * Ep) * (A + 4.5f * cu * cu) + (w * Pp) * (9.0f * cu * cF - 3.0f * uF);
+      const float odd = (w * Em) * (3.0f * cu) + (w * Pm) * (3.0f * cF);
+      S::store(d + (uint32_t)i * g.plane, a * f[i] + b * f[j] + even + odd, i);
+      S::store(d + (uint32_t)j * g.plane, a * f[j] + b * f[i] + even - odd, j);
+    }
+    {
+      const float w = w_of(13);
+      S::store(d + 13u * g.plane, (1.0f - e.trt.wp) * f[13] + (w * Ep) * A - (w * Pp) * 3.0f * uF, 13);
+    }
   }
 }
 
 // One cell of logical block lb (tile shape e.bx x e.by, see cell_of), thread
 // (tx, ty); `cur` is the buffer holding f*(n-1), the other one receives f*(n).
-template <class S, bool XPER, bool ROT, bool YZ = false>
+template <class S, bool XPER, bool ROT, bool YZ = false, bool TRT = false>
 __device__ inline void collide_cell(const EnvView &e, const FrameF &fr, int cur, int lb, int tx, int ty) {
   CellAt c;
   float f[Q];
-  if (collide_load<S, XPER, YZ>(e, cur, lb, tx, ty, c, f)) collide_finish<S, XPER, ROT, YZ>(e, fr, cur, c, f);
+  if (collide_load<S, XPER, YZ>(e, cur, lb, tx, ty, c, f)) collide_finish<S, XPER, ROT, YZ, TRT>(e, fr, cur, c, f);
 }
 
 // Single-lattice launch: blockDim = (e.bx, e.by). Blocks are mapped
 // XCD-aware: hardware workgroup b runs on XCD b % 8, so the logical block
 // index gives each XCD a contiguous 1/8 of the domain (shared cache lines of
 // neighbouring blocks stay in one L2).
-template <class S, bool XPER, bool ROT, bool YZ = false>
+template <class S, bool XPER, bool ROT, bool YZ = false, bool TRT = false>
 __global__ void __launch_bounds__(512) k_collide(EnvView e, FrameF fr, int cur) {
   const int b = blockIdx.x;
   const int per = (e.nblocks + 7) >> 3;
   const int lb = (b & 7) * per + (b >> 3);
   if (lb >= e.nblocks) return;
-  collide_cell<S, XPER, ROT, YZ>(e, fr, cur, lb, threadIdx.x, threadIdx.y);
+  collide_cell<S, XPER, ROT, YZ, TRT>(e, fr, cur, lb, threadIdx.x, threadIdx.y);
 }
 
 // f_i(x) of the caller's canonical pre-collision field -> stored buffer, i.e.

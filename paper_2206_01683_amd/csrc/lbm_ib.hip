@@ -51,6 +51,8 @@ bool params_ok(const lbm_params *p) {
   if (p->block_x > 0 && p->block_x % 64 != 0) return false;
   if (!(p->ib_alpha > 0.0) || !std::isfinite(p->ib_alpha)) return false;
   if (p->ib_scheme != LBM_IB_DIRECT && p->ib_scheme != LBM_IB_IMPLICIT) return false;
+  if (p->collision != LBM_COLLIDE_BGK && p->collision != LBM_COLLIDE_TRT) return false;
+  if (p->collision == LBM_COLLIDE_TRT && !(p->trt_lambda > 0.0 && std::isfinite(p->trt_lambda))) return false;
   return true;
 }
 
@@ -204,6 +206,11 @@ EnvView env_view(lbm_ctx *c, const lbm_markers *m) {
   e.inv_tau = (float)(1.0 / tau);
   e.omt = (float)(1.0 - 1.0 / tau);
   e.pref = (float)(1.0 - 0.5 / tau);
+  if (c->p.collision == LBM_COLLIDE_TRT) {
+    const double wp = 1.0 / tau, wm = 1.0 / (0.5 + c->p.trt_lambda / (tau - 0.5));
+    e.trt = TrtRates{(float)wp, (float)wm, (float)(1.0 - 0.5 * wp), (float)(1.0 - 0.5 * wm),
+                     (float)(1.0 - 0.5 * (wp + wm)), (float)(0.5 * (wm - wp))};
+  }
   e.bx = c->bx;
   e.by = c->by;
   if (c->by == 0) {  // linear shape: bx consecutive cells per block
@@ -253,29 +260,38 @@ EnvView env_view(lbm_ctx *c, const lbm_markers *m) {
 }
 
 // -------------------------------------------------------------- dispatch --
+template <class S, bool TRT>
+void collide_kernels(const EnvView &e, const FrameF &fr, int cur, int grid, dim3 blk, hipStream_t s, bool xper,
+                     bool rot, bool yz) {
+  if (yz) {  // open y or z faces
+    if (xper && rot)
+      k_collide<S, true, true, true, TRT><<<grid, blk, 0, s>>>(e, fr, cur);
+    else if (xper)
+      k_collide<S, true, false, true, TRT><<<grid, blk, 0, s>>>(e, fr, cur);
+    else if (rot)
+      k_collide<S, false, true, true, TRT><<<grid, blk, 0, s>>>(e, fr, cur);
+    else
+      k_collide<S, false, false, true, TRT><<<grid, blk, 0, s>>>(e, fr, cur);
+  } else if (xper && rot) {
+    k_collide<S, true, true, false, TRT><<<grid, blk, 0, s>>>(e, fr, cur);
+  } else if (xper) {
+    k_collide<S, true, false, false, TRT><<<grid, blk, 0, s>>>(e, fr, cur);
+  } else if (rot) {
+    k_collide<S, false, true, false, TRT><<<grid, blk, 0, s>>>(e, fr, cur);
+  } else {
+    k_collide<S, false, false, false, TRT><<<grid, blk, 0, s>>>(e, fr, cur);
+  }
+}
+
 template <class S>
 lbm_status launch_collide(lbm_ctx *c, const EnvView &e, const FrameF &fr, bool rot) {
   const int grid = ((e.nblocks + 7) / 8) * 8;
   const dim3 blk = collide_block(c);
-  const bool xper = e.g.xper;
-  if (!(e.g.yper && e.g.zper)) {  // open y or z faces
-    if (xper && rot)
-      k_collide<S, true, true, true><<<grid, blk, 0, c->stream>>>(e, fr, c->cur);
-    else if (xper)
-      k_collide<S, true, false, true><<<grid, blk, 0, c->stream>>>(e, fr, c->cur);
-    else if (rot)
-      k_collide<S, false, true, true><<<grid, blk, 0, c->stream>>>(e, fr, c->cur);
-    else
-      k_collide<S, false, false, true><<<grid, blk, 0, c->stream>>>(e, fr, c->cur);
-  } else if (xper && rot) {
-    k_collide<S, true, true><<<grid, blk, 0, c->stream>>>(e, fr, c->cur);
-  } else if (xper) {
-    k_collide<S, true, false><<<grid, blk, 0, c->stream>>>(e, fr, c->cur);
-  } else if (rot) {
-    k_collide<S, false, true><<<grid, blk, 0, c->stream>>>(e, fr, c->cur);
-  } else {
-    k_collide<S, false, false><<<grid, blk, 0, c->stream>>>(e, fr, c->cur);
-  }
+  const bool yz = !(e.g.yper && e.g.zper), xper = e.g.xper != 0;
+  if (c->p.collision == LBM_COLLIDE_TRT)
+    collide_kernels<S, true>(e, fr, c->cur, grid, blk, c->stream, xper, rot, yz);
+  else
+    collide_kernels<S, false>(e, fr, c->cur, grid, blk, c->stream, xper, rot, yz);
   return launched();
 }
 
@@ -557,7 +573,8 @@ lbm_status adjoint_request_ok(const lbm_ctx *c, const lbm_markers *m, const floa
   if (ib && m->n > c->p.max_markers) return LBM_ERR_CAPACITY;
   for (int q = 0; q < 4; ++q)
     if (!std::isfinite(w[q])) return LBM_ERR_ARG;
-  if (c->p.storage != LBM_STORE_F32 || c->p.mdf_iters != 1 || c->p.ib_scheme != LBM_IB_DIRECT || !c->p.with_adjoint)
+  if (c->p.storage != LBM_STORE_F32 || c->p.mdf_iters != 1 || c->p.ib_scheme != LBM_IB_DIRECT ||
+      c->p.collision != LBM_COLLIDE_BGK || !c->p.with_adjoint)
     return LBM_ERR_UNSUPPORTED;
   if (c->p.bc_y[0] != LBM_BC_PERIODIC || c->p.bc_z[0] != LBM_BC_PERIODIC) return LBM_ERR_UNSUPPORTED;
   return LBM_OK;
@@ -1084,7 +1101,8 @@ lbm_status lbm_batch_create(lbm_batch **out, const lbm_env *envs, int32_t nenv, 
   for (int e = 0; e < nenv; ++e) {
     if (!env_ok(envs[e])) return LBM_ERR_ARG;
     if (envs[e].ctx->p.mdf_iters != envs[0].ctx->p.mdf_iters) return LBM_ERR_ARG;
-    if (envs[e].ctx->p.ib_scheme != LBM_IB_DIRECT) return LBM_ERR_UNSUPPORTED;
+    if (envs[e].ctx->p.ib_scheme != LBM_IB_DIRECT || envs[e].ctx->p.collision != LBM_COLLIDE_BGK)
+      return LBM_ERR_UNSUPPORTED;
     for (int f = 0; f < e; ++f)
       if (envs[f].ctx == envs[e].ctx) return LBM_ERR_ARG;
   }

@@ -25,6 +25,8 @@ BC_PERIODIC, BC_VELOCITY, BC_OUTFLOW = 0, 1, 2
 OK, ERR_ARG, ERR_DEVICE, ERR_UNSTABLE, ERR_MARKER_RANGE, ERR_CAPACITY, ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 IB_DIRECT, IB_IMPLICIT = 0, 1
+COLLIDE_BGK, COLLIDE_TRT = 0, 1
+TRT_MAGIC = 3.0 / 16.0
 
 
 class Params(ctypes.Structure):
@@ -33,7 +35,8 @@ class Params(ctypes.Structure):
                 ("max_markers", ctypes.c_int32), ("max_bones", ctypes.c_int32), ("mdf_iters", ctypes.c_int32),
                 ("max_active_tiles", ctypes.c_int32), ("block_x", ctypes.c_int32), ("block_y", ctypes.c_int32),
                 ("with_adjoint", ctypes.c_int32), ("tau", ctypes.c_double), ("ib_alpha", ctypes.c_double),
-                ("bc_y", ctypes.c_int32 * 2), ("bc_z", ctypes.c_int32 * 2), ("ib_scheme", ctypes.c_int32)]
+                ("bc_y", ctypes.c_int32 * 2), ("bc_z", ctypes.c_int32 * 2), ("ib_scheme", ctypes.c_int32),
+                ("collision", ctypes.c_int32), ("trt_lambda", ctypes.c_double)]
 
 
 class Frame(ctypes.Structure):
@@ -150,12 +153,15 @@ def _check(rc: int, what: str):
 
 def make_params(nx, ny, nz, tau, bc_lo=BC_PERIODIC, bc_hi=BC_PERIODIC, storage="f32", max_markers=0,
                 max_bones=1, mdf_iters=1, ib_alpha=1.0, max_active_tiles=0, block=(0, 0), with_adjoint=False,
-                bc_y=(BC_PERIODIC, BC_PERIODIC), bc_z=(BC_PERIODIC, BC_PERIODIC), ib_scheme=0) -> Params:
+                bc_y=(BC_PERIODIC, BC_PERIODIC), bc_z=(BC_PERIODIC, BC_PERIODIC), ib_scheme=0, collision=0,
+                trt_lambda=TRT_MAGIC) -> Params:
     """ib_scheme: IB_DIRECT (direct forcing, mdf_iters passes) or IB_IMPLICIT
-    (implicit velocity correction, mdf_iters conjugate-gradient steps)."""
+    (implicit velocity correction, mdf_iters conjugate-gradient steps).
+    collision: COLLIDE_BGK or COLLIDE_TRT with Lambda = trt_lambda."""
     return Params(nx, ny, nz, bc_lo, bc_hi, STORAGE[storage] if isinstance(storage, str) else storage,
                   max_markers, max_bones, mdf_iters, max_active_tiles, block[0], block[1], 1 if with_adjoint else 0,
-                  tau, ib_alpha, (ctypes.c_int32 * 2)(*bc_y), (ctypes.c_int32 * 2)(*bc_z), ib_scheme)
+                  tau, ib_alpha, (ctypes.c_int32 * 2)(*bc_y), (ctypes.c_int32 * 2)(*bc_z), ib_scheme, collision,
+                  trt_lambda)
 
 
 def frames_array(frames: np.ndarray) -> np.ndarray:
@@ -195,14 +201,15 @@ class Simulation:
     def __init__(self, nx, ny, nz, tau, bc_lo=BC_PERIODIC, bc_hi=BC_PERIODIC, storage="f32", max_markers=0,
                  max_bones=1, mdf_iters=1, ib_alpha=1.0, rho0=None, u0=None, device="cuda", block=(0, 0),
                  max_active_tiles=0, stream=None, with_adjoint=False, bc_y=(BC_PERIODIC, BC_PERIODIC),
-                 bc_z=(BC_PERIODIC, BC_PERIODIC), ib_scheme=0):
+                 bc_z=(BC_PERIODIC, BC_PERIODIC), ib_scheme=0, collision=0, trt_lambda=TRT_MAGIC):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the lattice Boltzmann library runs only on the GPU")
         L = lib()
         self.device = torch.device(device)
         self.shape = (nz, ny, nx)
         self.params = make_params(nx, ny, nz, tau, bc_lo, bc_hi, storage, max_markers, max_bones, mdf_iters,
-                                  ib_alpha, max_active_tiles, block, with_adjoint, bc_y, bc_z, ib_scheme)
+                                  ib_alpha, max_active_tiles, block, with_adjoint, bc_y, bc_z, ib_scheme,
+                                  collision, trt_lambda)
         pb = L.lbm_population_bytes(ctypes.byref(self.params))
         wb = L.lbm_workspace_bytes(ctypes.byref(self.params))
         if pb == 0 or wb == 0:
@@ -392,7 +399,8 @@ class Batch:
                                  max_bones=w.markers.nbones, mdf_iters=w.mdf_iters, ib_alpha=w.ib_alpha,
                                  u0=w.u0.astype(np.float32), device=self.device, block=block,
                                  max_active_tiles=min(ntiles, max_active_tiles), stream=self.stream,
-                                 bc_y=w.bc_y, bc_z=w.bc_z, ib_scheme=w.ib_scheme)
+                                 bc_y=w.bc_y, bc_z=w.bc_z, ib_scheme=w.ib_scheme, collision=w.collision,
+                                 trt_lambda=w.trt_lambda)
                 dm = DeviceMarkers(w.markers, self.device)
                 poses = torch.as_tensor(np.ascontiguousarray(w.poses[:self.nsteps], np.float32), device=self.device)
                 frames = torch.as_tensor(np.ascontiguousarray(w.frames[:self.nsteps], np.float64), device=self.device)
