@@ -27,6 +27,7 @@ _lib = None
 BC_PERIODIC, BC_VELOCITY, BC_OUTFLOW = 0, 1, 2
 IB_DIRECT, IB_IMPLICIT = 0, 1
 COLLIDE_BGK, COLLIDE_TRT = 0, 1
+WALL_NO_SLIP, WALL_SLIP = 0, 1
 TRT_MAGIC = 3.0 / 16.0
 
 
@@ -46,13 +47,13 @@ class _Params(ctypes.Structure):
                 ("bc_lo", ctypes.c_int32), ("bc_hi", ctypes.c_int32), ("mdf_iters", ctypes.c_int32),
                 ("tau", ctypes.c_double), ("ib_alpha", ctypes.c_double),
                 ("bc_y", ctypes.c_int32 * 2), ("bc_z", ctypes.c_int32 * 2), ("ib_scheme", ctypes.c_int32),
-                ("collision", ctypes.c_int32), ("trt_lambda", ctypes.c_double)]
+                ("collision", ctypes.c_int32), ("trt_lambda", ctypes.c_double), ("wall_mode", ctypes.c_int32)]
 
 
 class _Markers(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("nbones", ctypes.c_int32),
                 ("xrest", ctypes.c_void_p), ("bone", ctypes.c_void_p),
-                ("weight", ctypes.c_void_p), ("dv", ctypes.c_void_p)]
+                ("weight", ctypes.c_void_p), ("dv", ctypes.c_void_p), ("nrest", ctypes.c_void_p)]
 
 
 def lib():
@@ -74,6 +75,8 @@ def lib():
         L.or_collide_node.argtypes = [dp, dp, dp, dp, ctypes.c_double, dp, dp, dp]
         L.or_collide_node_trt.argtypes = [dp, dp, dp, dp, ctypes.c_double, ctypes.c_double, dp, dp, dp]
         L.or_skin.argtypes = [dp, dp, dp, dp]
+        L.or_skin_normals.argtypes = [dp, dp, dp]
+        L.or_skin_normals.restype = ctypes.c_int
         L.or_interpolate.argtypes = [dp, dp, ctypes.c_int, dp, ctypes.c_int, dp]
         L.or_spread.argtypes = [dp, dp, ctypes.c_int, dp, dp]
         L.or_macros.argtypes = [dp, dp, dp, dp, dp]
@@ -95,15 +98,17 @@ def _f64(a) -> np.ndarray:
 
 def params(nx, ny, nz, tau, bc_lo=BC_PERIODIC, bc_hi=BC_PERIODIC, mdf_iters=1, ib_alpha=1.0,
            bc_y=(BC_PERIODIC, BC_PERIODIC), bc_z=(BC_PERIODIC, BC_PERIODIC), ib_scheme=IB_DIRECT,
-           collision=COLLIDE_BGK, trt_lambda=TRT_MAGIC) -> _Params:
+           collision=COLLIDE_BGK, trt_lambda=TRT_MAGIC, wall_mode=WALL_NO_SLIP) -> _Params:
     """Face conditions: x by bc_lo / bc_hi, y and z by the pairs bc_y, bc_z
     (low, high); an axis is periodic or open on both faces. ib_scheme
     IB_DIRECT: explicit direct forcing plus mdf_iters - 1 multi-direct-forcing
     passes; IB_IMPLICIT: the implicit velocity correction, mdf_iters
     conjugate-gradient steps. collision COLLIDE_BGK, or COLLIDE_TRT with
-    Lambda = (tau - 1/2)(tau- - 1/2) = trt_lambda."""
+    Lambda = (tau - 1/2)(tau- - 1/2) = trt_lambda. wall_mode WALL_NO_SLIP, or
+    WALL_SLIP (forcing along the marker normals only; needs the marker set's
+    normals)."""
     return _Params(nx, ny, nz, bc_lo, bc_hi, mdf_iters, tau, ib_alpha, (ctypes.c_int32 * 2)(*bc_y),
-                   (ctypes.c_int32 * 2)(*bc_z), ib_scheme, collision, trt_lambda)
+                   (ctypes.c_int32 * 2)(*bc_z), ib_scheme, collision, trt_lambda, wall_mode)
 
 
 def threads() -> int:
@@ -173,8 +178,10 @@ def _markers(ms, keep):
     bone = np.ascontiguousarray(ms.bone, dtype=np.int32)
     wt = _f64(ms.weight)
     dv = _f64(ms.dv)
-    keep.extend([xr, bone, wt, dv])
-    return _Markers(xr.shape[1], int(ms.nbones), xr.ctypes.data, bone.ctypes.data, wt.ctypes.data, dv.ctypes.data)
+    nr = None if getattr(ms, "normals", None) is None else _f64(ms.normals)
+    keep.extend([xr, bone, wt, dv, nr])
+    return _Markers(xr.shape[1], int(ms.nbones), xr.ctypes.data, bone.ctypes.data, wt.ctypes.data, dv.ctypes.data,
+                    None if nr is None else nr.ctypes.data)
 
 
 def skin(ms, pose):
@@ -185,6 +192,17 @@ def skin(ms, pose):
     U = np.zeros((3, ms.n))
     lib().or_skin(ctypes.byref(m), _p(pose), _p(X), _p(U))
     return X, U
+
+
+def skin_normals(ms, pose):
+    """Skinned outward normals (3, n) of marker set ms at bone poses pose."""
+    keep = []
+    m = _markers(ms, keep)
+    pose = _f64(pose)
+    N = np.zeros((3, ms.n))
+    if lib().or_skin_normals(ctypes.byref(m), _p(pose), _p(N)) != 0:
+        raise OracleError("the marker set has no normals")
+    return N
 
 
 def interpolate(prm: _Params, field: np.ndarray, X: np.ndarray) -> np.ndarray:
@@ -277,7 +295,7 @@ def initial_populations(rho: np.ndarray, u: np.ndarray) -> np.ndarray:
 def run_workload(w, nsteps=None, f0=None):
     """Run an inputs.Workload from its initial state f = f^eq(1, u0)."""
     prm = params(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi, w.mdf_iters, w.ib_alpha, w.bc_y, w.bc_z, w.ib_scheme,
-                 w.collision, w.trt_lambda)
+                 w.collision, w.trt_lambda, w.wall_mode)
     if f0 is None:
         f0 = equilibrium_field(np.ones((w.nz, w.ny, w.nx)), w.u0)
     return run(prm, f0, w.frames, w.markers, w.poses, nsteps or w.nsteps)

@@ -130,6 +130,10 @@ enum { OR_BC_PERIODIC = 0, OR_BC_VELOCITY = 1, OR_BC_OUTFLOW = 2 };
 enum { OR_IB_DIRECT = 0, OR_IB_IMPLICIT = 1 };
 // Collisions: BGK, or the two-relaxation-time collision (see Relax).
 enum { OR_COLLIDE_BGK = 0, OR_COLLIDE_TRT = 1 };
+// Immersed-wall condition: no-slip (the marker takes the body velocity), or
+// slip (Sec. III-B: a Neumann condition, the wall only stops flow through it:
+// the forcing acts on the velocity component along the surface normal).
+enum { OR_WALL_NO_SLIP = 0, OR_WALL_SLIP = 1 };
 
 struct OrParams {
   int32_t nx, ny, nz;
@@ -142,6 +146,7 @@ struct OrParams {
   int32_t ib_scheme;     // OR_IB_*
   int32_t collision;     // OR_COLLIDE_*
   double trt_lambda;     // TRT: Lambda = (tau - 1/2)(tau- - 1/2) > 0
+  int32_t wall_mode;     // OR_WALL_*
 };
 
 // Frame of reference for one step (Eq. (3)): linear acceleration of the
@@ -167,6 +172,7 @@ struct OrMarkers {
   const int32_t *bone;   // [2][n]
   const double *weight;  // [2][n]
   const double *dv;      // [n]  marker volume (surface area share x 1 cell)
+  const double *nrest;   // [3][n] rest-pose outward unit normals (slip walls; may be null otherwise)
 };
 
 }  // extern "C"
@@ -331,11 +337,31 @@ void skin(const OrMarkers *mk, const T *poses, T *X, T *U) {
   }
 }
 
+// Skinned outward normals: n_k = N(sum_b w_kb R_b nrest_k), N() scaling to
+// unit length (the bones' rotations act on the rest normal; their
+// translations do not).
+template <class T>
+void skin_normals(const OrMarkers *mk, const T *poses, T *Nout) {
+  const int n = mk->n;
+  for (int k = 0; k < n; ++k) {
+    double nr[3] = {mk->nrest[k], mk->nrest[n + k], mk->nrest[2 * n + k]};
+    T v[3] = {0.0, 0.0, 0.0};
+    for (int j = 0; j < 2; ++j) {
+      int b = mk->bone[j * n + k];
+      double wgt = mk->weight[j * n + k];
+      const T *P = poses + 24 * b;
+      for (int a = 0; a < 3; ++a) v[a] += wgt * (P[3 * a] * nr[0] + P[3 * a + 1] * nr[1] + P[3 * a + 2] * nr[2]);
+    }
+    T len = tsqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    for (int a = 0; a < 3; ++a) Nout[a * n + k] = v[a] / len;
+  }
+}
+
 }  // namespace
 
 extern "C" {
 
-int or_abi_version(void) { return 4; }
+int or_abi_version(void) { return 5; }
 
 // Threads a parallel lattice sweep uses.
 int or_threads(void) {
@@ -386,6 +412,13 @@ void or_collide_node_trt(const double *f, const double *g, const OrFrame *fr, co
 }
 
 void or_skin(const OrMarkers *mk, const double *poses, double *X, double *U) { skin(mk, poses, X, U); }
+
+// Skinned outward normals [3][n] (tests); the marker set must carry nrest.
+int or_skin_normals(const OrMarkers *mk, const double *poses, double *N) {
+  if (!mk || !mk->nrest) return -1;
+  skin_normals(mk, poses, N);
+  return 0;
+}
 
 }  // extern "C"
 
@@ -660,10 +693,25 @@ int run(const OrParams *p, T *f, const OrMarkers *mk, const T *poses, const OrFr
   if (p->collision == OR_COLLIDE_TRT && !(p->trt_lambda > 0.0 && std::isfinite(p->trt_lambda))) return -1;
   const Relax rx = p->collision == OR_COLLIDE_TRT ? relax_trt(tau, p->trt_lambda) : relax_bgk(tau);
   const int nm = mk ? mk->n : 0;
+  if (p->wall_mode != OR_WALL_NO_SLIP && p->wall_mode != OR_WALL_SLIP) return -1;
+  const bool slip = p->wall_mode == OR_WALL_SLIP && nm > 0;
+  if (slip && (!mk->nrest || p->ib_scheme != OR_IB_DIRECT)) return -1;
 
   std::vector<T> fpost(27 * N), rho(N), ustar(3 * N), g(3 * N, T(0.0));
   std::vector<T> X(3 * nm), U(3 * nm), Fk(3 * nm), Fdv(3 * nm), Ustar(3 * nm), rhok(nm), Uk(3 * nm);
+  std::vector<T> Nk(slip ? 3 * nm : 0);
   std::vector<T> ufull(3 * N);
+  // direct-forcing increment alpha 2 rho_k (U_k - V_k) at marker k, or with a
+  // slip wall only its component along the normal, alpha 2 rho_k ((U_k - V_k).n_k) n_k
+  auto forcing = [&](const std::vector<T> &V, int k, T out[3]) {
+    T d[3];
+    for (int a = 0; a < 3; ++a) d[a] = U[a * nm + k] - V[a * nm + k];
+    if (slip) {
+      T dn = d[0] * Nk[k] + d[1] * Nk[nm + k] + d[2] * Nk[2 * nm + k];
+      for (int a = 0; a < 3; ++a) d[a] = dn * Nk[a * nm + k];
+    }
+    for (int a = 0; a < 3; ++a) out[a] = p->ib_alpha * 2.0 * rhok[k] * d[a];
+  };
 
   for (int step = 0; step < nsteps; ++step) {
     const OrFrame *fr = &frames[step];
@@ -671,6 +719,7 @@ int run(const OrParams *p, T *f, const OrMarkers *mk, const T *poses, const OrFr
     // (1) marker positions and velocities for this step
     if (nm > 0) {
       skin(mk, poses + (size_t)step * mk->nbones * 24, X.data(), U.data());
+      if (slip) skin_normals(mk, poses + (size_t)step * mk->nbones * 24, Nk.data());
       for (int a = 0; a < 3; ++a)
         if (!G.per[a])
           for (int k = 0; k < nm; ++k)
@@ -691,9 +740,11 @@ int run(const OrParams *p, T *f, const OrMarkers *mk, const T *poses, const OrFr
         for (int k = 0; k < nm; ++k)
           for (int a = 0; a < 3; ++a) Fk[a * nm + k] = Fdv[a * nm + k] / mk->dv[k];
       } else {
-        for (int k = 0; k < nm; ++k)
-          for (int a = 0; a < 3; ++a)
-            Fk[a * nm + k] = p->ib_alpha * 2.0 * rhok[k] * (U[a * nm + k] - Ustar[a * nm + k]);
+        for (int k = 0; k < nm; ++k) {
+          T inc[3];
+          forcing(Ustar, k, inc);
+          for (int a = 0; a < 3; ++a) Fk[a * nm + k] = inc[a];
+        }
         for (int it = 1; it < p->mdf_iters; ++it) {
           // multi-direct forcing: spread the current force, re-interpolate the
           // velocity that includes it, add the remaining correction
@@ -702,9 +753,11 @@ int run(const OrParams *p, T *f, const OrMarkers *mk, const T *poses, const OrFr
           spread(G, X.data(), nm, Fdv.data(), g.data());
           node_fields(G, f, g.data(), fr, rho.data(), ufull.data());
           interpolate(G, ufull.data(), 3, X.data(), nm, Uk.data());
-          for (int k = 0; k < nm; ++k)
-            for (int a = 0; a < 3; ++a)
-              Fk[a * nm + k] += p->ib_alpha * 2.0 * rhok[k] * (U[a * nm + k] - Uk[a * nm + k]);
+          for (int k = 0; k < nm; ++k) {
+            T inc[3];
+            forcing(Uk, k, inc);
+            for (int a = 0; a < 3; ++a) Fk[a * nm + k] += inc[a];
+          }
         }
         for (int k = 0; k < nm; ++k)
           for (int a = 0; a < 3; ++a) Fdv[a * nm + k] = Fk[a * nm + k] * mk->dv[k];

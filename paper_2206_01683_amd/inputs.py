@@ -107,6 +107,7 @@ class MarkerSet:
     nbones: int
     area: float
     joints_rest: Optional[np.ndarray] = None  # (nbones, 3) rest joint positions
+    normals: Optional[np.ndarray] = None      # (3, n) rest-pose outward unit normals
 
     @property
     def n(self) -> int:
@@ -124,8 +125,9 @@ def fibonacci_sphere(n: int, radius: float, center) -> MarkerSet:
     c = np.asarray(center, dtype=np.float64)
     x = np.stack([c[0] + radius * r * np.cos(ph), c[1] + radius * r * np.sin(ph), c[2] + radius * z])
     area = 4.0 * math.pi * radius * radius
+    normals = np.stack([r * np.cos(ph), r * np.sin(ph), z])
     return MarkerSet(xrest=x, bone=np.zeros((2, n), np.int32), weight=np.stack([np.ones(n), np.zeros(n)]),
-                     dv=np.full(n, area / n), nbones=1, area=area)
+                     dv=np.full(n, area / n), nbones=1, area=area, normals=normals)
 
 
 def fish_half_width(xi: np.ndarray, length: float) -> np.ndarray:
@@ -194,8 +196,15 @@ def fish_surface(n: int, length: float, head, nbones: int = 10) -> MarkerSet:
     bone = np.stack([b0c, b1c]).astype(np.int32)
     weight = np.stack([w0, w1])
     joints = np.stack([head + np.array([j * h, 0.0, 0.0]) for j in range(nbones)])
+    # outward normal of S(xi, a) = (xi L, b cos a, 1.5 b sin a): along
+    # dS/da x dS/dxi, proportional to (-1.5 b', 1.5 L cos a, L sin a), b' = db/dxi
+    peak = math.sqrt(1.0 / 3.0) * (2.0 / 3.0)
+    sq = np.sqrt(np.maximum(xik, 1e-300))
+    db = 0.08 * length / peak * ((1.0 - xik) / (2.0 * sq) - sq)
+    nv = np.stack([-1.5 * db, 1.5 * length * np.cos(ang), length * np.sin(ang)])
+    nv /= np.linalg.norm(nv, axis=0, keepdims=True)
     return MarkerSet(xrest=x, bone=bone, weight=weight, dv=np.full(n, area / n), nbones=nbones, area=area,
-                     joints_rest=joints)
+                     joints_rest=joints, normals=nv)
 
 
 # --------------------------------------------------------------------------
@@ -363,6 +372,7 @@ class Workload:
     ib_scheme: int = 0                        # 0 direct forcing, 1 implicit velocity correction
     collision: int = 0                        # 0 BGK, 1 two-relaxation-time
     trt_lambda: float = 3.0 / 16.0            # TRT: (tau - 1/2)(tau- - 1/2)
+    wall_mode: int = 0                        # 0 no-slip, 1 slip (normal component only)
 
     @property
     def ncell(self) -> int:
@@ -438,7 +448,9 @@ def merge_marker_sets(sets) -> MarkerSet:
                      weight=np.concatenate([m.weight for m in sets], axis=1),
                      dv=np.concatenate([m.dv for m in sets]), nbones=int(off[-1]),
                      area=float(sum(m.area for m in sets)),
-                     joints_rest=None if any(j is None for j in joints) else np.concatenate(joints, axis=0))
+                     joints_rest=None if any(j is None for j in joints) else np.concatenate(joints, axis=0),
+                     normals=None if any(m.normals is None for m in sets) else
+                     np.concatenate([m.normals for m in sets], axis=1))
 
 
 def two_fish_workload(nsteps: int = 400, nx: int = 150, ny: int = 50, nz: int = 100, length: float = 40.0,

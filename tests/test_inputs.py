@@ -107,3 +107,28 @@ def test_two_fish_workload_structure():
         assert X[0].min() >= 2.0 and X[0].max() < w.nx - 3.0
         gap = np.linalg.norm(X[:, :2000, None] - X[:, None, 2000::11], axis=0).min()
         assert gap > 10.0
+
+
+def test_surface_normals_are_outward_unit_and_normal_to_the_surface():
+    """Sphere and fish rest normals: unit length, pointing away from the body
+    axis, and orthogonal to the surface (the surface's own tangents, from
+    nearby markers' positions projected on the tangent plane, are short)."""
+    c = np.array([5.0, 6.0, 7.0])
+    sp = I.fibonacci_sphere(300, 2.5, c)
+    np.testing.assert_allclose(sp.normals, (sp.xrest - c[:, None]) / 2.5, rtol=0, atol=1e-14)
+    L, head = 40.0, np.array([10.0, 20.0, 20.0])
+    ms = I.fish_surface(3000, L, head)
+    n = ms.normals
+    np.testing.assert_allclose(np.linalg.norm(n, axis=0), 1.0, rtol=0, atol=1e-12)
+    xi = (ms.xrest[0] - head[0]) / L
+    mid = (xi > 0.05) & (xi < 0.95)
+    radial = ms.xrest[1:] - head[1:, None]
+    assert np.all((n[1:] * radial).sum(0)[mid] > 0)
+    # the normal of a plane fitted to each marker's 12 nearest neighbours
+    X = ms.xrest.T
+    for k in np.flatnonzero(mid)[::50]:
+        d = X - X[k]
+        near = np.argsort((d * d).sum(1))[:13]
+        P = X[near] - X[near].mean(0)
+        fit = np.linalg.svd(P)[2][-1]
+        assert abs(fit @ n[:, k]) > 0.98, (k, abs(fit @ n[:, k]))  # an x-sign error gives 0.69
