@@ -110,6 +110,18 @@ enum { LBM_IB_DIRECT = 0, LBM_IB_IMPLICIT = 1 };
  *   and adjoint entry points return LBM_ERR_UNSUPPORTED. */
 enum { LBM_COLLIDE_BGK = 0, LBM_COLLIDE_TRT = 1 };
 
+/* Immersed-wall condition (lbm_params.wall_mode).
+ * NO_SLIP: direct forcing drives the marker velocity to the body's,
+ *   F_k = alpha 2 rho_k (U_k - U*_k).
+ * SLIP: the Neumann (slipping) condition the paper applies on the immersed
+ *   solid (Sec. III-B, Formulation): only flow through the wall is stopped,
+ *   F_k = alpha 2 rho_k ((U_k - U*_k).n_k) n_k, with n_k the marker's rest
+ *   normal (lbm_markers.nrest) turned by its bones' blended rotations and
+ *   scaled to unit length; multi-direct-forcing passes project the same way.
+ *   Needs nrest; with LBM_IB_IMPLICIT, and in the adjoint, it returns
+ *   LBM_ERR_UNSUPPORTED. */
+enum { LBM_WALL_NO_SLIP = 0, LBM_WALL_SLIP = 1 };
+
 typedef struct lbm_ctx lbm_ctx;
 
 /* [host] Problem description. */
@@ -129,6 +141,7 @@ typedef struct {
   int32_t ib_scheme;         /* LBM_IB_*; 0 = direct forcing */
   int32_t collision;         /* LBM_COLLIDE_*; 0 = BGK */
   double trt_lambda;         /* TRT: (tau - 1/2)(tau- - 1/2) > 0; unused by BGK */
+  int32_t wall_mode;         /* LBM_WALL_*; 0 = no-slip */
 } lbm_params;
 
 /* [host] Frame of one step (Eq. (3)). acc = linear acceleration of the frame
@@ -148,6 +161,8 @@ typedef struct {
  *   dv     [n]    marker volume dV_k           (in)
  *   X, U   [3][n] position and velocity        (out, written by each step)
  *   F      [3][n] direct-forcing force density of the last step (out)
+ *   nrest  [3][n] rest-pose outward unit normals (in; slip walls only, may be
+ *                 NULL otherwise)
  * A bone pose is 24 float32: R (3x3 row-major), t, dR/dt (3x3 row-major), dt/dt;
  * X_k = sum_b w_kb (R_b xrest_k + t_b), U_k = sum_b w_kb (dR_b xrest_k + dt_b). */
 typedef struct {
@@ -160,6 +175,7 @@ typedef struct {
   float *X;
   float *U;
   float *F;
+  const float *nrest;
 } lbm_markers;
 
 /* Bytes of one population buffer (two are needed) and of the workspace for

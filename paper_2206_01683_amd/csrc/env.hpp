@@ -35,6 +35,9 @@ struct EnvView {
   int n, nbones, cap, ntiles;
   float alpha2;                 // 2 * direct-forcing gain
   const float *xrest, *weight, *dv;
+  int slip;                     // slip wall: force along the skinned normals Nrm only
+  const float *nrest;           // [3][n] rest normals (slip)
+  float *Nrm;                   // [3][n] skinned unit normals of this step (slip)
   const int *bone;
   float *X, *U, *F;
   int *tile_flag, *tile_slot, *active, *counters, *guard;

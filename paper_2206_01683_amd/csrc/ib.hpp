@@ -87,7 +87,13 @@ __device__ inline void skin_item(const EnvView &e, const float *__restrict__ pos
   int lo[3] = {1 << 20, 1 << 20, 1 << 20}, hi[3] = {-1, -1, -1};
   if (k < n) {
     const float r0 = e.xrest[k], r1 = e.xrest[n + k], r2 = e.xrest[2 * n + k];
-    float p[3] = {0.f, 0.f, 0.f}, v[3] = {0.f, 0.f, 0.f};
+    float p[3] = {0.f, 0.f, 0.f}, v[3] = {0.f, 0.f, 0.f}, nv[3] = {0.f, 0.f, 0.f};
+    float n0 = 0.f, n1 = 0.f, n2 = 0.f;
+    if (e.slip) {
+      n0 = e.nrest[k];
+      n1 = e.nrest[n + k];
+      n2 = e.nrest[2 * n + k];
+    }
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       int b = e.bone[j * n + k];
@@ -102,7 +108,13 @@ __device__ inline void skin_item(const EnvView &e, const float *__restrict__ pos
       for (int r = 0; r < 3; ++r) {
         p[r] += w * (P[3 * r] * r0 + P[3 * r + 1] * r1 + P[3 * r + 2] * r2 + P[9 + r]);
         v[r] += w * (P[12 + 3 * r] * r0 + P[12 + 3 * r + 1] * r1 + P[12 + 3 * r + 2] * r2 + P[21 + r]);
+        nv[r] += w * (P[3 * r] * n0 + P[3 * r + 1] * n1 + P[3 * r + 2] * n2);
       }
+    }
+    if (e.slip) {  // the rest normal turned by the blended rotations, unit length
+      const float il = rsqrtf(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+#pragma unroll
+      for (int r = 0; r < 3; ++r) e.Nrm[r * n + k] = nv[r] * il;
     }
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
@@ -300,20 +312,28 @@ __device__ inline void interp_item(const EnvView &e, const FrameF &fr, int item,
       float Fk[3], inc[3];
       const float Uk[3] = {e.U[k], e.U[n + k], e.U[2 * n + k]};
       const float Ui[3] = {sx, sy, sz};
+      // velocity to correct: U - U^interp, or on a slip wall its normal part
+      float dU[3] = {Uk[0] - Ui[0], Uk[1] - Ui[1], Uk[2] - Ui[2]};
+      if (e.slip) {
+        const float nk[3] = {e.Nrm[k], e.Nrm[n + k], e.Nrm[2 * n + k]};
+        const float dn = dU[0] * nk[0] + dU[1] * nk[1] + dU[2] * nk[2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dU[c] = dn * nk[c];
+      }
       if (!MDF) {
         rk = sr;
         e.mstate[k] = rk;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           e.mstate[(c + 1) * (size_t)n + k] = Ui[c];
-          inc[c] = e.alpha2 * rk * (Uk[c] - Ui[c]);
+          inc[c] = e.alpha2 * rk * dU[c];
           Fk[c] = inc[c];
         }
       } else {
         rk = e.mstate[k];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          inc[c] = e.alpha2 * rk * (Uk[c] - Ui[c]);
+          inc[c] = e.alpha2 * rk * dU[c];
           Fk[c] = e.F[c * n + k] + inc[c];
         }
       }

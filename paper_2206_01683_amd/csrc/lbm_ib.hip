@@ -30,6 +30,7 @@ struct Layout {
   size_t guard, counters, tile_flag, tile_slot, active, mbase, chunk_box, partials, macro, gbuf, rec, mstate;
   size_t gbar, adjfix, mbar, pbar, facebuf;
   size_t gcg, cg, cgpart;  // implicit velocity correction only
+  size_t nrm;              // slip walls only
   size_t total;
 };
 
@@ -53,6 +54,7 @@ bool params_ok(const lbm_params *p) {
   if (p->ib_scheme != LBM_IB_DIRECT && p->ib_scheme != LBM_IB_IMPLICIT) return false;
   if (p->collision != LBM_COLLIDE_BGK && p->collision != LBM_COLLIDE_TRT) return false;
   if (p->collision == LBM_COLLIDE_TRT && !(p->trt_lambda > 0.0 && std::isfinite(p->trt_lambda))) return false;
+  if (p->wall_mode != LBM_WALL_NO_SLIP && p->wall_mode != LBM_WALL_SLIP) return false;
   return true;
 }
 
@@ -102,6 +104,7 @@ Layout layout(const lbm_params *p) {
     L.pbar = take(sizeof(float) * 24 * kPoseSplit * (size_t)p->max_bones);
     L.facebuf = take(sizeof(float) * 2 * 4 * (size_t)p->ny * p->nz);
   }
+  L.nrm = p->wall_mode == LBM_WALL_SLIP ? take(sizeof(float) * 3 * (size_t)L.maxm) : 0;
   L.gcg = L.cg = L.cgpart = 0;
   if (p->ib_scheme == LBM_IB_IMPLICIT) {
     L.gcg = take(sizeof(unsigned long long) * 3 * 512 * (size_t)L.cap);
@@ -237,6 +240,11 @@ EnvView env_view(lbm_ctx *c, const lbm_markers *m) {
     e.X = m->X;
     e.U = m->U;
     e.F = m->F;
+    if (c->p.wall_mode == LBM_WALL_SLIP) {
+      e.slip = 1;
+      e.nrest = m->nrest;
+      e.Nrm = wsp<float>(c, c->L.nrm);
+    }
   }
   e.tile_flag = wsp<int>(c, c->L.tile_flag);
   e.tile_slot = wsp<int>(c, c->L.tile_slot);
@@ -445,6 +453,7 @@ bool markers_ok(const lbm_ctx *c, const lbm_markers *m) {
   if (m->n < 0) return false;
   if (m->n == 0) return true;
   if (!m->xrest || !m->bone || !m->weight || !m->dv || !m->X || !m->U || !m->F) return false;
+  if (c->p.wall_mode == LBM_WALL_SLIP && !m->nrest) return false;
   if (m->nbones < 1 || m->nbones > c->p.max_bones) return false;
   return true;
 }
@@ -525,6 +534,7 @@ lbm_status lbm_ib_step(lbm_ctx *c, const lbm_markers *m, const float *poses, con
   const bool ib = m && m->n > 0;
   if (ib && m->n > c->p.max_markers) return LBM_ERR_CAPACITY;
   if (ib && !poses) return LBM_ERR_ARG;
+  if (ib && c->p.wall_mode == LBM_WALL_SLIP && c->p.ib_scheme == LBM_IB_IMPLICIT) return LBM_ERR_UNSUPPORTED;
   for (int s = 0; s < nsteps; ++s)
     if (!frame_ok(&frames[s])) return LBM_ERR_ARG;
   for (int s = 0; s < nsteps; ++s) {
@@ -574,7 +584,7 @@ lbm_status adjoint_request_ok(const lbm_ctx *c, const lbm_markers *m, const floa
   for (int q = 0; q < 4; ++q)
     if (!std::isfinite(w[q])) return LBM_ERR_ARG;
   if (c->p.storage != LBM_STORE_F32 || c->p.mdf_iters != 1 || c->p.ib_scheme != LBM_IB_DIRECT ||
-      c->p.collision != LBM_COLLIDE_BGK || !c->p.with_adjoint)
+      c->p.collision != LBM_COLLIDE_BGK || c->p.wall_mode != LBM_WALL_NO_SLIP || !c->p.with_adjoint)
     return LBM_ERR_UNSUPPORTED;
   if (c->p.bc_y[0] != LBM_BC_PERIODIC || c->p.bc_z[0] != LBM_BC_PERIODIC) return LBM_ERR_UNSUPPORTED;
   return LBM_OK;

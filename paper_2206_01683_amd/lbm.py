@@ -26,6 +26,7 @@ OK, ERR_ARG, ERR_DEVICE, ERR_UNSTABLE, ERR_MARKER_RANGE, ERR_CAPACITY, ERR_UNSUP
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 IB_DIRECT, IB_IMPLICIT = 0, 1
 COLLIDE_BGK, COLLIDE_TRT = 0, 1
+WALL_NO_SLIP, WALL_SLIP = 0, 1
 TRT_MAGIC = 3.0 / 16.0
 
 
@@ -36,7 +37,7 @@ class Params(ctypes.Structure):
                 ("max_active_tiles", ctypes.c_int32), ("block_x", ctypes.c_int32), ("block_y", ctypes.c_int32),
                 ("with_adjoint", ctypes.c_int32), ("tau", ctypes.c_double), ("ib_alpha", ctypes.c_double),
                 ("bc_y", ctypes.c_int32 * 2), ("bc_z", ctypes.c_int32 * 2), ("ib_scheme", ctypes.c_int32),
-                ("collision", ctypes.c_int32), ("trt_lambda", ctypes.c_double)]
+                ("collision", ctypes.c_int32), ("trt_lambda", ctypes.c_double), ("wall_mode", ctypes.c_int32)]
 
 
 class Frame(ctypes.Structure):
@@ -46,7 +47,8 @@ class Frame(ctypes.Structure):
 class Markers(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("nbones", ctypes.c_int32),
                 ("xrest", ctypes.c_void_p), ("bone", ctypes.c_void_p), ("weight", ctypes.c_void_p),
-                ("dv", ctypes.c_void_p), ("X", ctypes.c_void_p), ("U", ctypes.c_void_p), ("F", ctypes.c_void_p)]
+                ("dv", ctypes.c_void_p), ("X", ctypes.c_void_p), ("U", ctypes.c_void_p), ("F", ctypes.c_void_p),
+                ("nrest", ctypes.c_void_p)]
 
 
 class Env(ctypes.Structure):
@@ -154,14 +156,15 @@ def _check(rc: int, what: str):
 def make_params(nx, ny, nz, tau, bc_lo=BC_PERIODIC, bc_hi=BC_PERIODIC, storage="f32", max_markers=0,
                 max_bones=1, mdf_iters=1, ib_alpha=1.0, max_active_tiles=0, block=(0, 0), with_adjoint=False,
                 bc_y=(BC_PERIODIC, BC_PERIODIC), bc_z=(BC_PERIODIC, BC_PERIODIC), ib_scheme=0, collision=0,
-                trt_lambda=TRT_MAGIC) -> Params:
+                trt_lambda=TRT_MAGIC, wall_mode=0) -> Params:
     """ib_scheme: IB_DIRECT (direct forcing, mdf_iters passes) or IB_IMPLICIT
     (implicit velocity correction, mdf_iters conjugate-gradient steps).
-    collision: COLLIDE_BGK or COLLIDE_TRT with Lambda = trt_lambda."""
+    collision: COLLIDE_BGK or COLLIDE_TRT with Lambda = trt_lambda.
+    wall_mode: WALL_NO_SLIP or WALL_SLIP (normal component only)."""
     return Params(nx, ny, nz, bc_lo, bc_hi, STORAGE[storage] if isinstance(storage, str) else storage,
                   max_markers, max_bones, mdf_iters, max_active_tiles, block[0], block[1], 1 if with_adjoint else 0,
                   tau, ib_alpha, (ctypes.c_int32 * 2)(*bc_y), (ctypes.c_int32 * 2)(*bc_z), ib_scheme, collision,
-                  trt_lambda)
+                  trt_lambda, wall_mode)
 
 
 def frames_array(frames: np.ndarray) -> np.ndarray:
@@ -189,10 +192,13 @@ class DeviceMarkers:
         self.X = torch.zeros((3, self.n), dtype=torch.float32, device=dev)
         self.U = torch.zeros((3, self.n), dtype=torch.float32, device=dev)
         self.F = torch.zeros((3, self.n), dtype=torch.float32, device=dev)
+        nr = getattr(ms, "normals", None)  # rest normals, needed by slip walls only
+        self.nrest = None if nr is None else torch.as_tensor(np.ascontiguousarray(nr, np.float32), device=dev)
 
     def struct(self) -> Markers:
         return Markers(self.n, self.nbones, self.xrest.data_ptr(), self.bone.data_ptr(), self.weight.data_ptr(),
-                       self.dv.data_ptr(), self.X.data_ptr(), self.U.data_ptr(), self.F.data_ptr())
+                       self.dv.data_ptr(), self.X.data_ptr(), self.U.data_ptr(), self.F.data_ptr(),
+                       None if self.nrest is None else self.nrest.data_ptr())
 
 
 class Simulation:
@@ -201,7 +207,7 @@ class Simulation:
     def __init__(self, nx, ny, nz, tau, bc_lo=BC_PERIODIC, bc_hi=BC_PERIODIC, storage="f32", max_markers=0,
                  max_bones=1, mdf_iters=1, ib_alpha=1.0, rho0=None, u0=None, device="cuda", block=(0, 0),
                  max_active_tiles=0, stream=None, with_adjoint=False, bc_y=(BC_PERIODIC, BC_PERIODIC),
-                 bc_z=(BC_PERIODIC, BC_PERIODIC), ib_scheme=0, collision=0, trt_lambda=TRT_MAGIC):
+                 bc_z=(BC_PERIODIC, BC_PERIODIC), ib_scheme=0, collision=0, trt_lambda=TRT_MAGIC, wall_mode=0):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the lattice Boltzmann library runs only on the GPU")
         L = lib()
@@ -209,7 +215,7 @@ class Simulation:
         self.shape = (nz, ny, nx)
         self.params = make_params(nx, ny, nz, tau, bc_lo, bc_hi, storage, max_markers, max_bones, mdf_iters,
                                   ib_alpha, max_active_tiles, block, with_adjoint, bc_y, bc_z, ib_scheme,
-                                  collision, trt_lambda)
+                                  collision, trt_lambda, wall_mode)
         pb = L.lbm_population_bytes(ctypes.byref(self.params))
         wb = L.lbm_workspace_bytes(ctypes.byref(self.params))
         if pb == 0 or wb == 0:
@@ -400,7 +406,7 @@ class Batch:
                                  u0=w.u0.astype(np.float32), device=self.device, block=block,
                                  max_active_tiles=min(ntiles, max_active_tiles), stream=self.stream,
                                  bc_y=w.bc_y, bc_z=w.bc_z, ib_scheme=w.ib_scheme, collision=w.collision,
-                                 trt_lambda=w.trt_lambda)
+                                 trt_lambda=w.trt_lambda, wall_mode=w.wall_mode)
                 dm = DeviceMarkers(w.markers, self.device)
                 poses = torch.as_tensor(np.ascontiguousarray(w.poses[:self.nsteps], np.float32), device=self.device)
                 frames = torch.as_tensor(np.ascontiguousarray(w.frames[:self.nsteps], np.float64), device=self.device)

@@ -24,7 +24,7 @@ def gpu_sim(w, storage="f32", f0=None, block=(0, 0), mdf_iters=None, max_active_
                          rho0=None if f0 is not None else np.ones((w.nz, w.ny, w.nx), np.float32),
                          u0=None if f0 is not None else w.u0.astype(np.float32), block=block,
                          max_active_tiles=max_active_tiles, bc_y=w.bc_y, bc_z=w.bc_z, ib_scheme=w.ib_scheme,
-                         collision=w.collision, trt_lambda=w.trt_lambda)
+                         collision=w.collision, trt_lambda=w.trt_lambda, wall_mode=w.wall_mode)
     if f0 is not None:
         sim.load_populations(f0)
     return sim
@@ -47,7 +47,7 @@ def gpu_run(w, nsteps=None, storage="f32", f0=None, block=(0, 0), mdf_iters=None
 
 def oracle_run(w, nsteps=None, f0=None, mdf_iters=None):
     prm = oracle.params(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi, mdf_iters or w.mdf_iters, w.ib_alpha, w.bc_y,
-                        w.bc_z, w.ib_scheme, w.collision, w.trt_lambda)
+                        w.bc_z, w.ib_scheme, w.collision, w.trt_lambda, w.wall_mode)
     if f0 is None:
         f0 = oracle.equilibrium_field(np.ones((w.nz, w.ny, w.nx)), w.u0.astype(np.float32).astype(np.float64))
     res = oracle.run(prm, np.array(f0, dtype=np.float64), w.frames, w.markers, w.poses, nsteps or w.nsteps)

@@ -35,7 +35,7 @@ def test_population_and_workspace_sizes(L):
     dict(bc_lo=lbm.BC_PERIODIC, bc_hi=lbm.BC_OUTFLOW), dict(storage=7), dict(max_bones=0),
     dict(mdf_iters=0), dict(mdf_iters=17), dict(block=(96, 1)), dict(block=(512, 2)), dict(ib_alpha=0.0),
     dict(ib_scheme=2), dict(ib_scheme=-1), dict(collision=2), dict(collision=1, trt_lambda=0.0),
-    dict(collision=1, trt_lambda=float("nan")),
+    dict(collision=1, trt_lambda=float("nan")), dict(wall_mode=2),
 ])
 def test_invalid_parameters_are_rejected(L, bad):
     kw = dict(nx=16, ny=16, nz=16, tau=0.6, bc_lo=lbm.BC_VELOCITY, bc_hi=lbm.BC_OUTFLOW)
