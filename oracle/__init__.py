@@ -82,6 +82,8 @@ def lib():
         L.or_macros.argtypes = [dp, dp, dp, dp, dp]
         L.or_run.argtypes = [dp, dp, dp, dp, dp, ctypes.c_int, dp, dp, dp, dp]
         L.or_run.restype = ctypes.c_int
+        L.or_run_forced.argtypes = [dp, dp, dp, ctypes.c_int, dp]
+        L.or_run_forced.restype = ctypes.c_int
         L.or_run_tangent.argtypes = [dp, dp, dp, dp, dp, dp, dp, ctypes.c_int, dp, dp]
         L.or_run_tangent.restype = ctypes.c_int
         _lib = L
@@ -262,6 +264,19 @@ def run(prm: _Params, f: np.ndarray, frames: np.ndarray, markers=None, poses=Non
     if rc != 0:
         raise OracleError(f"oracle run failed with code {rc}")
     return {"f": f, "wrench": wrench, "X": X, "U": U, "F": F}
+
+
+def run_forced(prm: _Params, f: np.ndarray, g: np.ndarray, nsteps: int, frame=None) -> np.ndarray:
+    """nsteps steps of the fluid alone with a constant body-force density
+    field g (3, nz, ny, nx) added at every node; returns the advanced f."""
+    f = _f64(f)
+    g = _f64(g)
+    frames = _f64(np.repeat(np.asarray(frame if frame is not None else np.zeros(18), np.float64).reshape(1, 18),
+                            nsteps, axis=0))
+    rc = lib().or_run_forced(ctypes.byref(prm), _p(f), _p(frames), int(nsteps), _p(g))
+    if rc != 0:
+        raise OracleError(f"oracle run failed with code {rc}")
+    return f
 
 
 def run_tangent(prm: _Params, f: np.ndarray, frames: np.ndarray, markers, poses, poses_d, nsteps=None):

@@ -682,7 +682,7 @@ void implicit_forces(const Grid &G, const T *rho, const T *X, const T *U, const 
 // face, or -1 on bad arguments.
 template <class T>
 int run(const OrParams *p, T *f, const OrMarkers *mk, const T *poses, const OrFrame *frames, int nsteps, T *wrench,
-        T *Xout, T *Uout, T *Fout) {
+        T *Xout, T *Uout, T *Fout, const double *gext = nullptr) {
   if (!p || !f || p->nx < 4 || p->ny < 4 || p->nz < 4 || !(p->tau > 0.5)) return -1;
   Grid G;
   if (!make_grid(p, G)) return -1;
@@ -764,6 +764,9 @@ int run(const OrParams *p, T *f, const OrMarkers *mk, const T *poses, const OrFr
       }
       spread(G, X.data(), nm, Fdv.data(), g.data());
     }
+    // a prescribed body-force density field, added to the immersed force (tests)
+    if (gext)
+      for (size_t i = 0; i < 3 * N; ++i) g[i] += gext[i];
 
     // (6) BGK + Guo collision on every node that is not an open boundary node
 #pragma omp parallel for schedule(static)
@@ -895,6 +898,13 @@ extern "C" {
 int or_run(const OrParams *p, double *f, const OrMarkers *mk, const double *poses, const OrFrame *frames,
            int nsteps, double *wrench, double *Xout, double *Uout, double *Fout) {
   return run(p, f, mk, poses, frames, nsteps, wrench, Xout, Uout, Fout);
+}
+
+// nsteps steps with no body and a constant body-force density field
+// g [3][cells] added at every node (tests of the bulk forcing).
+int or_run_forced(const OrParams *p, double *f, const OrFrame *frames, int nsteps, const double *g) {
+  return run(p, f, (const OrMarkers *)nullptr, (const double *)nullptr, frames, nsteps, (double *)nullptr,
+             (double *)nullptr, (double *)nullptr, (double *)nullptr, g);
 }
 
 // Forward-mode tangent of or_run with respect to the bone poses: the same
