@@ -274,16 +274,33 @@ def cpu_baseline(sample_steps: int):
     import oracle
     from paper_2206_01683_amd import inputs as I
 
-    w = I.fish_workload(nsteps=sample_steps)
+    w = I.fish_workload(nsteps=max(sample_steps, 2))
     prm = oracle.params(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi)
     f0 = oracle.equilibrium_field(np.ones((w.nz, w.ny, w.nx)), w.u0)
     t0 = time.perf_counter()
-    oracle.run(prm, f0, w.frames, w.markers, w.poses, sample_steps)
+    oracle.run(prm, f0.copy(), w.frames, w.markers, w.poses, sample_steps)
     dt = time.perf_counter() - t0
-    return {"value": round(w.ncell * sample_steps / dt / 1e6, 3), "unit": "MLUPS", "cores": oracle.threads(),
+    cores = oracle.threads()
+    # one core as well: a 2-step run less a 1-step run, so that the set-up of
+    # a call (buffer allocation and first touch) cancels
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    oracle.run(prm, f0.copy(), w.frames, w.markers, w.poses, 1)
+    t2 = time.perf_counter()
+    oracle.run(prm, f0, w.frames, w.markers, w.poses, 2)
+    dt1 = (time.perf_counter() - t2) - (t2 - t1)
+    oracle.set_threads(cores)
+    model = None
+    if os.path.exists("/proc/cpuinfo"):
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    return {"value": round(w.ncell * sample_steps / dt / 1e6, 3), "unit": "MLUPS", "cores": cores,
             "kind": "oracle",
             "sample": f"{sample_steps} steps of the {w.nx}x{w.ny}x{w.nz} fish workload from rest "
-                      f"({w.ncell * sample_steps} node updates, {dt:.1f} s, FP64)"}
+                      f"({w.ncell * sample_steps} node updates, {dt:.1f} s, FP64)",
+            "one_core_value": round(w.ncell / max(dt1, 1e-9) / 1e6, 3), "cpu_model": model}
 
 
 def main():

@@ -70,9 +70,14 @@ typedef enum {
  * or from its inward neighbour when it lies on outflow faces only. */
 enum { LBM_BC_PERIODIC = 0, LBM_BC_VELOCITY = 1, LBM_BC_OUTFLOW = 2 };
 
-/* Population storage. F32 stores f_i. F16 and BF16 store h_i = f_i - w_i
- * (offset from the rest equilibrium) rounded to nearest even; all arithmetic
- * and all immersed-boundary sums stay in float32. */
+/* Population storage. Every format stores h_i = f_i - w_i, the offset from
+ * the rest equilibrium: F32 as float, F16 and BF16 rounded to nearest even.
+ * The collision works on h (rho - 1 = sum h, momentum = sum h c), so the
+ * rounding of stored values scales with |h|, not with w_i; all arithmetic
+ * and all immersed-boundary sums stay in float32. The stored layout of a
+ * state (lbm_state_save) holds, at cell x, h_i(x + c_i) of the post-collision
+ * populations, 27 planes of plane stride elements (lbm_population_bytes / 27
+ * / element size). */
 enum { LBM_STORE_F32 = 0, LBM_STORE_F16 = 1, LBM_STORE_BF16 = 2 };
 
 /* Immersed-boundary schemes (lbm_params.ib_scheme).

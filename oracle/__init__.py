@@ -65,6 +65,8 @@ def lib():
         dp = ctypes.c_void_p
         L.or_abi_version.restype = ctypes.c_int
         L.or_threads.restype = ctypes.c_int
+        L.or_set_threads.argtypes = [ctypes.c_int]
+        L.or_set_threads.restype = None
         L.or_lattice.argtypes = [dp, dp]
         L.or_equilibrium.argtypes = [ctypes.c_double, dp, dp]
         L.or_equilibrium_field.argtypes = [dp, dp, ctypes.c_int64, dp]
@@ -116,6 +118,11 @@ def params(nx, ny, nz, tau, bc_lo=BC_PERIODIC, bc_hi=BC_PERIODIC, mdf_iters=1, i
 def threads() -> int:
     """OpenMP threads the oracle's lattice sweeps use."""
     return int(lib().or_threads())
+
+
+def set_threads(n: int) -> None:
+    """Use n OpenMP threads for later lattice sweeps."""
+    lib().or_set_threads(int(n))
 
 
 def lattice():

@@ -372,6 +372,15 @@ int or_threads(void) {
 #endif
 }
 
+// Threads later lattice sweeps use (timing on one core); n >= 1.
+void or_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 void or_lattice(int32_t *c, double *w) {
   for (int i = 0; i < 27; ++i) {
     for (int a = 0; a < 3; ++a) c[3 * i + a] = L.c[i][a];

@@ -170,7 +170,7 @@ __device__ inline void adj_face(const float lamb[Q], float rho, const float m[3]
 
 __device__ inline void load_lam(const float *__restrict__ lam, uint32_t plane, uint32_t o, float l[Q]) {
 #pragma unroll
-  for (int i = 0; i < Q; ++i) l[i] = lam[(uint32_t)i * plane + o];
+  for (int i = 0; i < Q; ++i) l[i] = lam[(size_t)i * plane + o];
 }
 
 // ------------------------------------------------------------------ pass 1 --
@@ -458,7 +458,7 @@ __device__ inline void adj_collide_cell(const EnvView &e, const AdjArgs &A, int 
       const uint32_t ob = (uint32_t)yz * g.nx + (lo ? 0 : g.nx - 1);
 #pragma unroll
       for (int i = 0; i < Q; ++i)
-        fb[i] += e.omt * A.lam_next[(uint32_t)i * g.plane + ob] + rF + (float)cx_of(i) * m0 + (float)cy_of(i) * m1 +
+        fb[i] += e.omt * A.lam_next[(size_t)i * g.plane + ob] + rF + (float)cx_of(i) * m0 + (float)cy_of(i) * m1 +
                  (float)cz_of(i) * m2;
     }
   }
@@ -474,14 +474,14 @@ __device__ inline void adj_collide_cell(const EnvView &e, const AdjArgs &A, int 
       continue;
     }
     const uint32_t ot = ((uint32_t)zz[cz_of(i) + 1] * g.ny + yy[cy_of(i) + 1]) * g.nx + tx_;
-    __builtin_nontemporal_store(fb[i], A.lam_prev + (uint32_t)i * g.plane + ot);
+    __builtin_nontemporal_store(fb[i], A.lam_prev + (size_t)i * g.plane + ot);
   }
   if (face) {
     // entries of this face node pulled by no node: c_x pointing out of the domain
     const int cxo = x == 0 ? -1 : 1;
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-      if (cx_of(i) == cxo) A.lam_prev[(uint32_t)i * g.plane + o] = 0.f;
+      if (cx_of(i) == cxo) A.lam_prev[(size_t)i * g.plane + o] = 0.f;
   }
 }
 

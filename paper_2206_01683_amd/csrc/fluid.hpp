@@ -12,9 +12,12 @@
 
 namespace lbmib {
 
-// Pull the 27 pre-collision populations of node (xs, y, z). The x neighbour
-// indices xm/xp are given by the caller (periodic wrap or interior node).
-template <class S>
+// Pull the 27 pre-collision populations of node (xs, y, z): f_i with
+// DEV = false, the deviations h_i = f_i - w_i with DEV = true. The x
+// neighbour indices xm/xp are given by the caller (periodic wrap or interior
+// node). Plane offsets i * plane are 64-bit (27 planes of a large lattice pass
+// 2^32 elements); a cell's offset within a plane is 32-bit (cells < 2^31).
+template <class S, bool DEV = false>
 __device__ inline void pull27(const typename S::T *__restrict__ src, uint32_t plane, int nx, int ny, int xm, int xs,
                               int xp, int ym, int y, int yp, int zm, int z, int zp, float f[Q]) {
   const int xx[3] = {xp, xs, xm};  // indexed by cx + 1: source x = xs - cx
@@ -22,9 +25,9 @@ __device__ inline void pull27(const typename S::T *__restrict__ src, uint32_t pl
   const int zz[3] = {zp, z, zm};
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    uint32_t off = (uint32_t)i * plane + ((uint32_t)zz[cz_of(i) + 1] * (uint32_t)ny + (uint32_t)yy[cy_of(i) + 1]) *
-                                             (uint32_t)nx + (uint32_t)xx[cx_of(i) + 1];
-    f[i] = S::load(src + off, i);
+    const uint32_t cell = ((uint32_t)zz[cz_of(i) + 1] * (uint32_t)ny + (uint32_t)yy[cy_of(i) + 1]) * (uint32_t)nx +
+                          (uint32_t)xx[cx_of(i) + 1];
+    f[i] = DEV ? S::load_dev(src + (size_t)i * plane + cell, i) : S::load(src + (size_t)i * plane + cell, i);
   }
 }
 
@@ -143,7 +146,7 @@ __device__ inline bool collide_load(const EnvView &e, int cur, int lb, int tx, i
     zm = z == 0 ? g.nz - 1 : z - 1;
     zp = z == g.nz - 1 ? 0 : z + 1;
   }
-  pull27<S>(src, g.plane, g.nx, g.ny, xm, xs, xp, ym, ys, yp, zm, zs, zp, f);
+  pull27<S, true>(src, g.plane, g.nx, g.ny, xm, xs, xp, ym, ys, yp, zm, zs, zp, f);
   c.x = x;
   c.y = y;
   c.z = z;
@@ -159,6 +162,10 @@ __device__ inline bool collide_load(const EnvView &e, int cur, int lb, int tx, i
 // split the same way).
 template <class S, bool XPER, bool ROT, bool YZ = false, bool TRT = false>
 __device__ inline void collide_finish(const EnvView &e, const FrameF &fr, int cur, const CellAt &c, float f[Q]) {
+  // multiply-adds fused within a source expression only, so that this
+  // arithmetic rounds the same way in every kernel it is inlined into (the
+  // single-lattice, batched and persistent collides give the same bits)
+#pragma clang fp contract(on)
   using T = typename S::T;
   T *__restrict__ dst = static_cast<T *>(e.f[cur ^ 1]);
   const int *__restrict__ tile_slot = e.ib ? e.tile_slot : nullptr;
@@ -167,8 +174,10 @@ __device__ inline void collide_finish(const EnvView &e, const FrameF &fr, int cu
   const int ys = YZ ? c.ys : y, zs = YZ ? c.zs : z;
   const bool lo_face = !XPER && x == 0;
   const bool face = (!XPER && (x == 0 || x == g.nx - 1)) || (YZ && (ys != y || zs != z));
-  float rho, mx, my, mz;
-  moments(f, rho, mx, my, mz);
+  // f holds the deviations h_i = f_i - w_i: sum h = rho - 1, sum h c = m
+  float drho, mx, my, mz;
+  moments(f, drho, mx, my, mz);
+  const float rho = 1.0f + drho;
   const float irho = 1.0f / rho;
 
   float gx, gy, gz;
@@ -226,14 +235,17 @@ __device__ inline void collide_finish(const EnvView &e, const FrameF &fr, int cu
   const float u2 = ux * ux + uy * uy + uz * uz;
   if (!(u2 < 0.16f)) atomicOr(e.guard, (int)GUARD_UNSTABLE);
 
-  // BGK + Guo, evaluated on opposite pairs (i, 26 - i): c_j = -c_i, so the
-  // equilibrium and forcing split into parts even and odd in c.
-  const float A = 1.0f - 1.5f * u2;
+  // BGK + Guo on the deviations, evaluated on opposite pairs (i, 26 - i):
+  // c_j = -c_i, so the equilibrium and forcing split into parts even and odd
+  // in c. h*_i = h_i - (h_i - heq_i)/tau + S_i with
+  // heq_i = f^eq_i - w_i = w_i [(rho - 1) + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u^2)].
+  const float Ah = -1.5f * u2;
   const float uF = ux * Fx + uy * Fy + uz * Fz;
   const uint32_t o = ((uint32_t)z * (uint32_t)g.ny + (uint32_t)y) * (uint32_t)g.nx + (uint32_t)x;
   typename S::T *__restrict__ d = dst + o;
   if constexpr (!TRT) {
     const float E = e.inv_tau * rho;
+    const float B = e.inv_tau * drho;
     const float P = e.pref;
 #pragma unroll
     for (int i = 0; i < 13; ++i) {
@@ -241,21 +253,21 @@ __device__ inline void collide_finish(const EnvView &e, const FrameF &fr, int cu
       const float w = w_of(i);
       const float cu = cdot(i, ux, uy, uz);
       const float cF = cdot(i, Fx, Fy, Fz);
-      const float even = (w * E) * (A + 4.5f * cu * cu) + (w * P) * (9.0f * cu * cF - 3.0f * uF);
+      const float even = w * (E * (Ah + 4.5f * cu * cu) + B) + (w * P) * (9.0f * cu * cF - 3.0f * uF);
       const float odd = (w * E) * (3.0f * cu) + (w * P) * (3.0f * cF);
-      S::store(d + (uint32_t)i * g.plane, e.omt * f[i] + even + odd, i);
-      S::store(d + (uint32_t)j * g.plane, e.omt * f[j] + even - odd, j);
+      S::store_dev(d + (size_t)i * g.plane, e.omt * f[i] + even + odd, i);
+      S::store_dev(d + (size_t)j * g.plane, e.omt * f[j] + even - odd, j);
     }
     {
       const float w = w_of(13);
-      S::store(d + 13u * g.plane, e.omt * f[13] + (w * E) * A - (w * P) * 3.0f * uF, 13);
+      S::store_dev(d + (size_t)13 * g.plane, e.omt * f[13] + w * (E * Ah + B) - (w * P) * 3.0f * uF, 13);
     }
   } else {
-    // f*_i = f_i - w+ (f+_i - e+_i) - w- (f-_i - e-_i) + (1 - w+/2) S+_i + (1 - w-/2) S-_i
-    //      = a f_i + b f_j + [w+ e+_i + (1 - w+/2) S+_i] + [w- e-_i + (1 - w-/2) S-_i],
+    // h*_i = h_i - w+ (h+_i - heq+_i) - w- (h-_i - heq-_i) + (1 - w+/2) S+_i + (1 - w-/2) S-_i
+    //      = a h_i + b h_j + [w+ heq+_i + (1 - w+/2) S+_i] + [w- heq-_i + (1 - w-/2) S-_i],
     // a = 1 - (w+ + w-)/2, b = (w- - w+)/2; the bracketed parts are even and
     // odd in c, as in BGK with its single rate split in two.
-    const float Ep = e.trt.wp * rho, Em = e.trt.wm * rho;
+    const float Ep = e.trt.wp * rho, Em = e.trt.wm * rho, Bp = e.trt.wp * drho;
     const float Pp = e.trt.pp, Pm = e.trt.pm, a = e.trt.a, b = e.trt.b;
 #pragma unroll
     for (int i = 0; i < 13; ++i) {
@@ -263,14 +275,15 @@ __device__ inline void collide_finish(const EnvView &e, const FrameF &fr, int cu
       const float w = w_of(i);
       const float cu = cdot(i, ux, uy, uz);
       const float cF = cdot(i, Fx, Fy, Fz);
-      const float even = (w * Ep) * (A + 4.5f * cu * cu) + (w * Pp) * (9.0f * cu * cF - 3.0f * uF);
+      const float even = w * (Ep * (Ah + 4.5f * cu * cu) + Bp) + (w * Pp) * (9.0f * cu * cF - 3.0f * uF);
       const float odd = (w * Em) * (3.0f * cu) + (w * Pm) * (3.0f * cF);
-      S::store(d + (uint32_t)i * g.plane, a * f[i] + b * f[j] + even + odd, i);
-      S::store(d + (uint32_t)j * g.plane, a * f[j] + b * f[i] + even - odd, j);
+      S::store_dev(d + (size_t)i * g.plane, a * f[i] + b * f[j] + even + odd, i);
+      S::store_dev(d + (size_t)j * g.plane, a * f[j] + b * f[i] + even - odd, j);
     }
     {
       const float w = w_of(13);
-      S::store(d + 13u * g.plane, (1.0f - e.trt.wp) * f[13] + (w * Ep) * A - (w * Pp) * 3.0f * uF, 13);
+      S::store_dev(d + (size_t)13 * g.plane, (1.0f - e.trt.wp) * f[13] + w * (Ep * Ah + Bp) - (w * Pp) * 3.0f * uF,
+                   13);
     }
   }
 }
@@ -370,11 +383,12 @@ __global__ void k_macros(const typename S::T *__restrict__ src, GridArgs g, Fram
     xm = max(xm, 0);
     xp = min(xp, g.nx - 1);
   }
-  float f[Q];
-  pull27<S>(src, g.plane, g.nx, g.ny, xm, x, xp, wrap_idx(y - 1, g.ny), y, wrap_idx(y + 1, g.ny),
-            wrap_idx(z - 1, g.nz), z, wrap_idx(z + 1, g.nz), f);
-  float rho, mx, my, mz;
-  moments(f, rho, mx, my, mz);
+  float f[Q];  // deviations h_i
+  pull27<S, true>(src, g.plane, g.nx, g.ny, xm, x, xp, wrap_idx(y - 1, g.ny), y, wrap_idx(y + 1, g.ny),
+                  wrap_idx(z - 1, g.nz), z, wrap_idx(z + 1, g.nz), f);
+  float drho, mx, my, mz;
+  moments(f, drho, mx, my, mz);
+  const float rho = 1.0f + drho;
   float ax, ay, az;
   frame_a0<ROT>(fr, (float)x, (float)y, (float)z, ax, ay, az);
   float ux, uy, uz;

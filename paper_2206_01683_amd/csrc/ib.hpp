@@ -221,11 +221,12 @@ __device__ inline void macro_item(const EnvView &e, const FrameF &fr, int cur, i
   if (x < g.nx && y < g.ny && z < g.nz && (g.xper || (x > 0 && x < g.nx - 1))) {
     const int xm = g.xper ? wrap_idx(x - 1, g.nx) : x - 1;
     const int xp = g.xper ? wrap_idx(x + 1, g.nx) : x + 1;
-    float f[Q];
-    pull27<S>(src, g.plane, g.nx, g.ny, xm, x, xp, wrap_idx(y - 1, g.ny), y, wrap_idx(y + 1, g.ny),
-              wrap_idx(z - 1, g.nz), z, wrap_idx(z + 1, g.nz), f);
-    float rho, mx, my, mz;
-    moments(f, rho, mx, my, mz);
+    float f[Q];  // deviations h_i = f_i - w_i
+    pull27<S, true>(src, g.plane, g.nx, g.ny, xm, x, xp, wrap_idx(y - 1, g.ny), y, wrap_idx(y + 1, g.ny),
+                    wrap_idx(z - 1, g.nz), z, wrap_idx(z + 1, g.nz), f);
+    float drho, mx, my, mz;
+    moments(f, drho, mx, my, mz);
+    const float rho = 1.0f + drho;
     float ax, ay, az;
     frame_a0<ROT>(fr, (float)x, (float)y, (float)z, ax, ay, az);
     float ux, uy, uz;

@@ -23,18 +23,26 @@ __host__ __device__ constexpr float w_of(int i) {
 }
 
 // ------------------------------------------------------------- storage ----
-// F32 keeps f_i. F16 / BF16 keep h_i = f_i - w_i, rounded to nearest even.
+// Every format keeps h_i = f_i - w_i, the offset from the rest equilibrium:
+// F32 as float, F16 / BF16 rounded to nearest even. The collide works on h
+// directly (rho - 1 = sum h, m = sum h c), so the rounding of a stored value
+// scales with |h| rather than with w_i; load / store convert to and from f
+// for the kernels that want f.
 struct StoreF32 {
   using T = float;
   static constexpr int kind = 0;
-  __device__ static inline float load(const T *p, int) { return *p; }
-  __device__ static inline void store(T *p, float f, int) { __builtin_nontemporal_store(f, p); }
-  __device__ static inline void store_plain(T *p, float f, int) { *p = f; }
+  __device__ static inline float load_dev(const T *p, int) { return *p; }
+  __device__ static inline void store_dev(T *p, float h, int) { __builtin_nontemporal_store(h, p); }
+  __device__ static inline float load(const T *p, int i) { return w_of(i) + *p; }
+  __device__ static inline void store(T *p, float f, int i) { __builtin_nontemporal_store(f - w_of(i), p); }
+  __device__ static inline void store_plain(T *p, float f, int i) { *p = f - w_of(i); }
 };
 
 struct StoreF16 {
   using T = _Float16;
   static constexpr int kind = 1;
+  __device__ static inline float load_dev(const T *p, int) { return (float)(*p); }
+  __device__ static inline void store_dev(T *p, float h, int) { __builtin_nontemporal_store((_Float16)h, p); }
   __device__ static inline float load(const T *p, int i) { return w_of(i) + (float)(*p); }
   __device__ static inline void store(T *p, float f, int i) {
     __builtin_nontemporal_store((_Float16)(f - w_of(i)), p);
@@ -52,6 +60,8 @@ struct StoreBF16 {
     u += 0x7FFFu + ((u >> 16) & 1u);
     return (uint16_t)(u >> 16);
   }
+  __device__ static inline float load_dev(const T *p, int) { return to_f(*p); }
+  __device__ static inline void store_dev(T *p, float h, int) { __builtin_nontemporal_store(to_h(h), p); }
   __device__ static inline float load(const T *p, int i) { return w_of(i) + to_f(*p); }
   __device__ static inline void store(T *p, float f, int i) { __builtin_nontemporal_store(to_h(f - w_of(i)), p); }
   __device__ static inline void store_plain(T *p, float f, int i) { *p = to_h(f - w_of(i)); }

@@ -41,14 +41,15 @@ def _valid_mask(sim, ncell):
 def _smooth_perturbation(sim, w, state, seed, amp=1e-3):
     """delta_i(x) = amp * f_i(x) * (a_i + b_i sin(2 pi (x/nx + y/ny) + p_i)):
     smooth in space, random across directions, so it moves density and
-    velocity coherently near the body."""
+    velocity coherently near the body. The stored layout holds h_i = f_i - w_i."""
     rng = np.random.default_rng(seed)
     a, b, p = rng.uniform(-1, 1, 27), rng.uniform(-1, 1, 27), rng.uniform(0, 2 * np.pi, 27)
     z, y, x = np.meshgrid(np.arange(w.nz), np.arange(w.ny), np.arange(w.nx), indexing="ij")
     ph = 2 * np.pi * (x / w.nx + y / w.ny)
     plane = sim.population_bytes // 4 // 27
     d = np.zeros((27, plane), np.float32)
-    f = state.view(torch.float32).reshape(27, plane)[:, :w.ncell].cpu().numpy()
+    _, wts = oracle.lattice()
+    f = state.view(torch.float32).reshape(27, plane)[:, :w.ncell].cpu().numpy() + wts[:, None].astype(np.float32)
     for i in range(27):
         d[i, :w.ncell] = amp * f[i] * (a[i] + b[i] * np.sin(ph + p[i])).ravel()
     return torch.as_tensor(d.reshape(-1), device="cuda")

@@ -98,21 +98,25 @@ def test_invalid_shapes_rejected():
         b.set_shapes(np.array([[128, 2]], np.int32))
 
 
-def test_batched_environment_against_oracle():
-    w = _envs(count=1, seed=4)[0]
-    b = lbm.Batch([w], NSTEPS)
+def test_batched_environments_against_oracle():
+    """Three environments of the seed-4 draw, batched together (persistent
+    driver), each against the FP64 oracle."""
+    envs = _envs(count=3, seed=4)
+    b = lbm.Batch(envs, NSTEPS)
     b.run(NSTEPS, mode="persistent", graph=False)
     assert b.check() == 0
     with torch.cuda.stream(b.stream):
-        _, u = b.sims[0].macros(w.frames[NSTEPS - 1])
+        us = [sim.macros(w.frames[NSTEPS - 1])[1] for sim, w in zip(b.sims, envs)]
     b.synchronize()
-    ref = oracle_run(w, nsteps=NSTEPS)
-    _, u_ref = oracle.macros(ref["prm"], ref["f"], w.frames[NSTEPS - 1])
-    e = rel_l2(interior(u.cpu().numpy().astype(np.float64), w), interior(u_ref, w))
-    wr = b.wrench[0].cpu().numpy()
-    derr = np.abs(wr[:, 0] - ref["wrench"][:, 0]).max() / np.abs(ref["wrench"][:, 0]).max()
-    say(f"batched env {w.nx}x{w.ny}x{w.nz}, {w.markers.n} markers: velocity rel L2 {e:.3e}, force-x max rel {derr:.3e}")
-    assert e <= 1e-5 and derr <= 1e-4
+    for j, w in enumerate(envs):
+        ref = oracle_run(w, nsteps=NSTEPS)
+        _, u_ref = oracle.macros(ref["prm"], ref["f"], w.frames[NSTEPS - 1])
+        e = rel_l2(interior(us[j].cpu().numpy().astype(np.float64), w), interior(u_ref, w))
+        wr = b.wrench[j].cpu().numpy()
+        derr = np.abs(wr[:, 0] - ref["wrench"][:, 0]).max() / np.abs(ref["wrench"][:, 0]).max()
+        say(f"batched env {j} {w.nx}x{w.ny}x{w.nz}, {w.markers.n} markers: velocity rel L2 {e:.3e}, "
+            f"force-x max rel {derr:.3e}")
+        assert e <= 1e-5 and derr <= 1e-4
 
 
 @pytest.mark.parametrize("mode", ["phases", "persistent"])
