@@ -75,6 +75,7 @@ def test_fish_long_run_precision_report():
         report[st] = (errs, t_err)
         say(f"{st}: velocity rel L2 at steps {MARKS}: " + ", ".join(f"{x:.2e}" for x in errs) +
             f"; mean thrust over the last 400 steps rel err {t_err:.2e} (oracle mean thrust {t_ref:.4e})")
-    assert report["f32"][0][0] <= 1e-5
+    # measured on one MI355X, 1,000 steps: FP32 1.4e-6 / 5.6e-6 / 8.8e-6, mean thrust 3e-5
+    assert max(report["f32"][0]) <= 2e-5 and report["f32"][1] <= 2e-4
     for j in range(len(MARKS)):
         assert report["f32"][0][j] < report["f16"][0][j] < report["bf16"][0][j]
