@@ -679,6 +679,56 @@ void implicit_forces(const Grid &G, const T *rho, const T *X, const T *U, const 
   }
 }
 
+// Implicit velocity correction on a slip wall: one unknown per marker, the
+// normal force G_k = gamma_k n_k, chosen so that the interpolated velocity
+// with the spread force has the body's normal velocity at every marker:
+//   n_k . [interp(u* + spread(G) / (2 rho)) - U]_k = 0,
+// i.e. (N^T S N) gamma = N^T (U - U*), N stacking the unit normals. N^T S N
+// is symmetric positive semidefinite when the frame does not rotate (the
+// Coriolis solve would make it unsymmetric; rotating frames are rejected).
+// Conjugate gradients as in implicit_forces, on the scalars gamma.
+template <class T>
+void implicit_forces_slip(const Grid &G, const T *rho, const T *X, const T *U, const T *Ustar, const T *rhok,
+                          const T *Nk, int nm, int iters, T *Gout) {
+  const size_t N = G.ncell();
+  std::vector<T> r(nm), z(nm), p(nm), q(nm), gam(nm, T(0.0)), pv(3 * nm), qv(3 * nm), g(3 * N), h(3 * N);
+  T rz = 0.0;
+  for (int k = 0; k < nm; ++k) {
+    r[k] = 0.0;
+    for (int a = 0; a < 3; ++a) r[k] += Nk[a * nm + k] * (U[a * nm + k] - Ustar[a * nm + k]);
+    z[k] = 2.0 * rhok[k] * r[k];
+    p[k] = z[k];
+    rz += r[k] * z[k];
+  }
+  for (int it = 0; it < iters; ++it) {
+    for (int k = 0; k < nm; ++k)
+      for (int a = 0; a < 3; ++a) pv[a * nm + k] = p[k] * Nk[a * nm + k];
+    spread(G, X, nm, pv.data(), g.data());
+    for (int a = 0; a < 3; ++a)
+      for (size_t id = 0; id < N; ++id) h[a * N + id] = g[a * N + id] / (2.0 * rho[id]);
+    interpolate(G, h.data(), 3, X, nm, qv.data());
+    T pq = 0.0;
+    for (int k = 0; k < nm; ++k) {
+      q[k] = 0.0;
+      for (int a = 0; a < 3; ++a) q[k] += Nk[a * nm + k] * qv[a * nm + k];
+      pq += p[k] * q[k];
+    }
+    const T alpha = val(pq) > 0.0 ? rz / pq : T(0.0);
+    T rz_new = 0.0;
+    for (int k = 0; k < nm; ++k) {
+      gam[k] += alpha * p[k];
+      r[k] = r[k] - alpha * q[k];
+      z[k] = 2.0 * rhok[k] * r[k];
+      rz_new += r[k] * z[k];
+    }
+    const T beta = val(rz) != 0.0 ? rz_new / rz : T(0.0);
+    for (int k = 0; k < nm; ++k) p[k] = z[k] + beta * p[k];
+    rz = rz_new;
+  }
+  for (int k = 0; k < nm; ++k)
+    for (int a = 0; a < 3; ++a) Gout[a * nm + k] = gam[k] * Nk[a * nm + k];
+}
+
 // Advance the pre-collision populations f [27][nz][ny][nx] by nsteps steps.
 //   poses  : [nsteps][nbones][24] bone poses for each step (may be null when
 //            markers is null)
@@ -704,7 +754,7 @@ int run(const OrParams *p, T *f, const OrMarkers *mk, const T *poses, const OrFr
   const int nm = mk ? mk->n : 0;
   if (p->wall_mode != OR_WALL_NO_SLIP && p->wall_mode != OR_WALL_SLIP) return -1;
   const bool slip = p->wall_mode == OR_WALL_SLIP && nm > 0;
-  if (slip && (!mk->nrest || p->ib_scheme != OR_IB_DIRECT)) return -1;
+  if (slip && !mk->nrest) return -1;
 
   std::vector<T> fpost(27 * N), rho(N), ustar(3 * N), g(3 * N, T(0.0));
   std::vector<T> X(3 * nm), U(3 * nm), Fk(3 * nm), Fdv(3 * nm), Ustar(3 * nm), rhok(nm), Uk(3 * nm);
@@ -743,7 +793,14 @@ int run(const OrParams *p, T *f, const OrMarkers *mk, const T *poses, const OrFr
     if (nm > 0) {
       interpolate(G, ustar.data(), 3, X.data(), nm, Ustar.data());
       interpolate(G, rho.data(), 1, X.data(), nm, rhok.data());
-      if (p->ib_scheme == OR_IB_IMPLICIT) {
+      if (p->ib_scheme == OR_IB_IMPLICIT && slip) {
+        const double *w = fr->omega;
+        if (w[0] != 0.0 || w[1] != 0.0 || w[2] != 0.0) return -1;  // unsymmetric system: not supported
+        implicit_forces_slip(G, rho.data(), X.data(), U.data(), Ustar.data(), rhok.data(), Nk.data(), nm,
+                             p->mdf_iters, Fdv.data());
+        for (int k = 0; k < nm; ++k)
+          for (int a = 0; a < 3; ++a) Fk[a * nm + k] = Fdv[a * nm + k] / mk->dv[k];
+      } else if (p->ib_scheme == OR_IB_IMPLICIT) {
         implicit_forces(G, rho.data(), X.data(), U.data(), Ustar.data(), rhok.data(), fr, nm, p->mdf_iters,
                         Fdv.data());
         for (int k = 0; k < nm; ++k)

@@ -11,7 +11,9 @@ What fixes it independently of the oracle's code:
     closed sphere loses a third of what a no-slip wall removes (the normals of
     a sphere average n n^T to I/3 over the surface);
   * in Stokes flow a slip sphere has two thirds of a no-slip sphere's drag
-    (4 pi mu R U against 6 pi mu R U)."""
+    (4 pi mu R U against 6 pi mu R U);
+  * the implicit correction on a slip wall: one marker has a closed form, and
+    n markers end with no normal slip after n conjugate-gradient steps."""
 import math
 
 import numpy as np
@@ -110,13 +112,75 @@ def test_stokes_resistance_slip_is_two_thirds_of_no_slip():
     assert 0.62 < r_s / r_ns < 0.71, r_s / r_ns
 
 
-def test_slip_needs_normals_and_direct_forcing():
+def _cluster_markers(center, n, seed, spacing=1.1, dv=0.7):
+    rng = np.random.default_rng(seed)
+    pts = []
+    while len(pts) < n:
+        q = np.asarray(center) + rng.uniform(-1.8, 1.8, 3)
+        if all(np.linalg.norm(q - p) >= spacing for p in pts):
+            pts.append(q)
+    X = np.array(pts).T
+    nr = rng.standard_normal((3, n))
+    nr /= np.linalg.norm(nr, axis=0, keepdims=True)
+    return I.MarkerSet(xrest=X, bone=np.zeros((2, n), np.int32), weight=np.vstack([np.ones(n), np.zeros(n)]),
+                       dv=np.full(n, dv), nbones=1, area=dv * n, normals=nr)
+
+
+def _moving_pose(vel):
+    p = I.identity_poses(1)
+    p[0, 0, 21:24] = vel
+    return p
+
+
+def test_implicit_slip_one_marker_closed_form():
+    """One marker in a uniform state: the normal force is
+    G = 2 rho (8/3)^3 (n.(U - u0)) n (the 4-point kernel's squared weights sum
+    to 3/8 per axis), and nothing along the wall."""
+    n = 12
+    rho0, u0 = 1.2, np.array([0.03, -0.02, 0.01])
+    f0 = oracle.equilibrium_field(np.full((n, n, n), rho0), np.broadcast_to(u0.reshape(3, 1, 1, 1), (3, n, n, n)))
+    ms = _cluster_markers((6.2, 5.8, 6.1), 1, seed=3)
+    U = np.array([0.05, 0.01, -0.02])
+    prm = oracle.params(n, n, n, 0.7, mdf_iters=2, ib_scheme=oracle.IB_IMPLICIT, wall_mode=oracle.WALL_SLIP)
+    res = oracle.run(prm, f0.copy(), I.make_frames(1), ms, _moving_pose(U))
+    nk = ms.normals[:, 0]
+    G = res["F"][:, 0] * ms.dv[0]
+    np.testing.assert_allclose(G, 2 * rho0 * (8 / 3) ** 3 * (nk @ (U - u0)) * nk, rtol=1e-12, atol=1e-16)
+
+
+def test_implicit_slip_n_markers_end_with_no_normal_slip():
+    """n markers, n steps: the normal component of the slip vanishes at every
+    marker, the tangential one does not, and every force is normal."""
+    n, nm = 14, 6
+    shape = (n, n, n)
+    rho = I.random_density(shape, 0.05, seed=3)
+    u = I.perturbed_velocity(shape, np.array([0.02, 0.01, -0.01]), 0.02, seed=4)
+    f0 = oracle.equilibrium_field(rho, u)
+    ms = _cluster_markers((7.0, 7.0, 7.0), nm, seed=5)
+    U = np.array([-0.03, 0.02, 0.04])
+    frame = I.make_frames(1, acc=(1e-4, 0, 0), origin=(7.0, 7.0, 7.0))
+    prm = oracle.params(n, n, n, 0.7, mdf_iters=nm, ib_scheme=oracle.IB_IMPLICIT, wall_mode=oracle.WALL_SLIP)
+    res = oracle.run(prm, f0.copy(), frame, ms, _moving_pose(U))
+    rho_n, ustar = oracle.macros(prm, f0, frame[0])
+    g = oracle.spread(prm, res["X"], res["F"] * ms.dv)
+    slip = oracle.interpolate(prm, ustar + g / (2 * rho_n), res["X"]) - res["U"]
+    normal = (slip * ms.normals).sum(0)
+    tangential = slip - normal * ms.normals
+    scale = np.abs(res["U"] - oracle.interpolate(prm, ustar, res["X"])).max()
+    assert np.abs(normal).max() < 1e-9 * scale
+    assert np.abs(tangential).max() > 1e-3 * scale
+    assert np.abs(np.cross(res["F"].T, ms.normals.T)).max() < 1e-15 * np.abs(res["F"]).max()
+
+
+def test_slip_rejections():
     n = 12
     f0 = oracle.equilibrium_field(np.ones((n, n, n)), np.zeros((3, n, n, n)))
     ms = I.fibonacci_sphere(50, 2.0, (6.0, 6.0, 6.0))
+    # the implicit correction on a slip wall in a rotating frame
     prm = oracle.params(n, n, n, 0.7, wall_mode=oracle.WALL_SLIP, ib_scheme=oracle.IB_IMPLICIT)
     with pytest.raises(oracle.OracleError):
-        oracle.run(prm, f0.copy(), I.make_frames(1), ms, I.identity_poses(1))
+        oracle.run(prm, f0.copy(), I.make_frames(1, omega=(0, 0, 0.01)), ms, I.identity_poses(1))
+    # a slip wall without normals
     ms.normals = None
     prm = oracle.params(n, n, n, 0.7, wall_mode=oracle.WALL_SLIP)
     with pytest.raises(oracle.OracleError):
