@@ -123,7 +123,10 @@ enum { LBM_COLLIDE_BGK = 0, LBM_COLLIDE_TRT = 1 };
  *   F_k = alpha 2 rho_k ((U_k - U*_k).n_k) n_k, with n_k the marker's rest
  *   normal (lbm_markers.nrest) turned by its bones' blended rotations and
  *   scaled to unit length; multi-direct-forcing passes project the same way.
- *   Needs nrest; with LBM_IB_IMPLICIT, and in the adjoint, it returns
+ *   With LBM_IB_IMPLICIT the unknown is one normal force gamma_k n_k per
+ *   marker, (N^T S N) gamma = N^T (U - U*), in frames that do not rotate (a
+ *   rotating frame returns LBM_ERR_UNSUPPORTED: the Coriolis solve makes
+ *   that system unsymmetric). Needs nrest; the adjoint returns
  *   LBM_ERR_UNSUPPORTED. */
 enum { LBM_WALL_NO_SLIP = 0, LBM_WALL_SLIP = 1 };
 

@@ -449,7 +449,15 @@ __device__ inline void spread_item(const EnvView &e, int item, int tid, unsigned
           r[4 * q + 2] = v.z;
           r[4 * q + 3] = v.w;
         }
-        if (CG) cg_direction(e, k, beta, first, &r[16]);
+        if (CG) {
+          cg_direction(e, k, beta, first, &r[16]);
+          if (e.slip) {  // the search direction is a normal force p n
+            const float p0 = r[16];
+            r[16] = p0 * e.Nrm[k];
+            r[17] = p0 * e.Nrm[n + k];
+            r[18] = p0 * e.Nrm[2 * (size_t)n + k];
+          }
+        }
         const int bx = __float_as_int(r[12]), by = __float_as_int(r[13]), bz = __float_as_int(r[14]);
         int lx[4], ly[4], lz[4];  // local index part per stencil node, -1 outside the tile
 #pragma unroll
@@ -527,7 +535,11 @@ __global__ void __launch_bounds__(WG) k_spread(EnvView e, float *wrench) {
 // gradients with the diagonal preconditioner 2 rho_k (S's diagonal is
 // (3/8)^3 / (2 rho) for a uniform density) take mdf_iters steps from G = 0.
 // The spread and the interpolation of S use the weights of the marker record,
-// so the discrete S is exactly symmetric up to float rounding.
+// so the discrete S is exactly symmetric up to float rounding. On a slip wall
+// the unknown is one normal force gamma_k n_k per marker: the vectors keep it
+// in component 0 (the others stay zero, and their guarded alpha and beta
+// vanish), the spread takes p n and the apply the normal part of S p n,
+// (N^T S N) gamma = N^T (U - U*); the frame must not rotate.
 //
 // Per step, after the first interpolation pass (rho_k, U*_k, record):
 //   cg_init_item     r = (I + [omega]x)(U - U*), G = 0; rz_0 = r.z, z = 2 rho_k r
@@ -653,6 +665,10 @@ __device__ inline void cg_init_item(const EnvView &e, const FrameF &fr, int item
       r[1] += wy;
       r[2] += wz;
     }
+    if (e.slip) {  // one unknown per marker, the normal force: r = n.(U - U*) in component 0
+      r[0] = e.Nrm[k] * R[0] + e.Nrm[n + k] * R[1] + e.Nrm[2 * (size_t)n + k] * R[2];
+      r[1] = r[2] = 0.f;
+    }
     const float p2 = 2.0f * e.mstate[k];
     float *G = e.cg, *rr = e.cg + 3 * (size_t)n;
 #pragma unroll
@@ -703,7 +719,11 @@ __device__ inline void cg_apply_item(const EnvView &e, int item, int tid, int j)
     }
     const float qx = wave_sum(v[0] * d), qy = wave_sum(v[1] * d), qz = wave_sum(v[2] * d);
     if (lane == 0) {
-      const float q[3] = {qx, qy, qz};
+      float q[3] = {qx, qy, qz};
+      if (e.slip) {  // n . (S p n)
+        q[0] = e.Nrm[k] * qx + e.Nrm[n + k] * qy + e.Nrm[2 * (size_t)n + k] * qz;
+        q[1] = q[2] = 0.f;
+      }
       float p[3];
       cg_direction(e, k, cg_scal(e, 1, j), j == 0, p);
       float *qv = e.cg + 9 * (size_t)n, *pv = e.cg + 6 * (size_t)n;
@@ -752,6 +772,12 @@ __device__ inline void cg_update_item(const EnvView &e, const FrameF &fr, int it
       rzn[c] = rk * (p2 * rk);
     }
     if (last) {
+      if (e.slip) {  // the normal force gamma n
+        const float gam = Gk[0];
+        Gk[0] = gam * e.Nrm[k];
+        Gk[1] = gam * e.Nrm[n + k];
+        Gk[2] = gam * e.Nrm[2 * (size_t)n + k];
+      }
       const float idv = 1.0f / e.dv[k];
       float *rec = e.rec + (size_t)k * REC;
 #pragma unroll

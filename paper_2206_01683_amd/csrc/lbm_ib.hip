@@ -534,9 +534,12 @@ lbm_status lbm_ib_step(lbm_ctx *c, const lbm_markers *m, const float *poses, con
   const bool ib = m && m->n > 0;
   if (ib && m->n > c->p.max_markers) return LBM_ERR_CAPACITY;
   if (ib && !poses) return LBM_ERR_ARG;
-  if (ib && c->p.wall_mode == LBM_WALL_SLIP && c->p.ib_scheme == LBM_IB_IMPLICIT) return LBM_ERR_UNSUPPORTED;
   for (int s = 0; s < nsteps; ++s)
     if (!frame_ok(&frames[s])) return LBM_ERR_ARG;
+  // the implicit correction on a slip wall needs a frame that does not rotate
+  if (ib && c->p.wall_mode == LBM_WALL_SLIP && c->p.ib_scheme == LBM_IB_IMPLICIT)
+    for (int s = 0; s < nsteps; ++s)
+      if (rotating(&frames[s])) return LBM_ERR_UNSUPPORTED;
   for (int s = 0; s < nsteps; ++s) {
     const float *pose = ib ? poses + (size_t)s * m->nbones * 24 : nullptr;
     float *w = wrench ? wrench + (size_t)s * 8 : nullptr;

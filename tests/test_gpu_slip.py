@@ -105,15 +105,35 @@ def test_batched_slip_environments_match_a_lone_run():
         assert d == 0.0
 
 
+@pytest.mark.parametrize("iters", [1, 3])
+def test_implicit_correction_on_a_slip_wall(iters):
+    """One normal force per marker by conjugate gradients, against the
+    oracle's scalar solve; forces normal to the wall."""
+    w = _slip(I.sphere_workload(nsteps=1))
+    w.ib_scheme = lbm.IB_IMPLICIT
+    F = _one_step(w, 44, mdf=iters)
+    nrm = w.markers.normals
+    assert np.abs(np.cross(F.T, nrm.T)).max() < 1e-5 * np.abs(F).max()
+
+
+def test_implicit_correction_on_a_slip_wall_fish():
+    w = _slip(I.fin_workload(nsteps=160))
+    w.ib_scheme = lbm.IB_IMPLICIT
+    w.poses = w.poses[157:158]
+    w.frames = w.frames[157:158]
+    w.nsteps = 1
+    _one_step(w, 45, mdf=2)
+
+
 def test_slip_rejections():
     w = _slip(I.sphere_workload(nsteps=1))
-    # implicit correction with a slip wall
+    # implicit correction with a slip wall in a rotating frame
     w.ib_scheme = lbm.IB_IMPLICIT
     sim = gpu_sim(w)
     dm = lbm.DeviceMarkers(w.markers)
     poses = torch.as_tensor(w.poses.astype(np.float32), device="cuda")
     with pytest.raises(lbm.LBMError) as ei:
-        sim.step(w.frames, dm, poses)
+        sim.step(I.make_frames(1, omega=(0.0, 0.0, 0.002), origin=(20.0, 16.0, 16.0)), dm, poses)
     assert ei.value.code == lbm.ERR_UNSUPPORTED
     # no normals
     w.ib_scheme = lbm.IB_DIRECT
