@@ -3,9 +3,9 @@
 //
 // State layout: two buffers of 27 population planes, each plane
 // `plane` elements long (nx*ny*nz rounded up), x fastest. A buffer holds the
-// post-collision values f*(x, n-1); the pre-collision state of step n is the
-// pull f_i(x, n) = f*_i(x - c_i, n-1). One step reads the current buffer and
-// writes the other.
+// post-collision values f*(x, n-1), stored as deviations f* - w_i; the
+// pre-collision state of step n is the pull f_i(x, n) = f*_i(x - c_i, n-1).
+// One step reads the current buffer and writes the other.
 #pragma once
 
 #include "env.hpp"
@@ -311,8 +311,8 @@ __global__ void __launch_bounds__(512) k_collide(EnvView e, FrameF fr, int cur) 
 }
 
 // f_i(x) of the caller's canonical pre-collision field -> stored buffer, i.e.
-// stored_i(x) = f_i(x + c_i) (periodic wrap; clamped at open faces, where the
-// value is never read).
+// stored_i(x) = f_i(x + c_i) - w_i (periodic wrap; clamped at open faces,
+// where the value is never read).
 template <class S>
 __global__ void k_load_canonical(const float *__restrict__ fin, typename S::T *__restrict__ dst, GridArgs g) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -328,7 +328,8 @@ __global__ void k_load_canonical(const float *__restrict__ fin, typename S::T *_
   }
 }
 
-// Equilibrium state f_i(x) = f^eq_i(rho0(x), u0(x)) written pre-shifted as above.
+// Equilibrium state f_i(x) = f^eq_i(rho0(x), u0(x)) written pre-shifted (and as
+// deviations) as above.
 template <class S>
 __global__ void k_init_equilibrium(const float *__restrict__ rho0, const float *__restrict__ u0,
                                    typename S::T *__restrict__ dst, GridArgs g) {
