@@ -249,17 +249,19 @@ lbm_status lbm_state_restore(lbm_ctx *c, const void *src, int64_t step);
  * live batch (the batch keeps the pointers it was created with). */
 lbm_status lbm_bind_populations(lbm_ctx *c, void *f_cur, void *f_next);
 
-/* Discrete adjoint of one step: the exact reverse mode of the float32
- * arithmetic of lbm_ib_step for the step that starts from `state` (stored
- * layout) with markers m, bone poses `pose` ([m->nbones][24]) and `frame`
- * [host]. The step's own objective term is
+/* Discrete adjoint of one step: the reverse mode, in float32, of
+ * lbm_ib_step for the step that starts from `state` (stored layout) with
+ * markers m, bone poses `pose` ([m->nbones][24]) and `frame` [host]. It
+ * linearises the collision around f = w + h of the stored deviations h (the
+ * forward collide works on h; the two agree to float32 rounding). The step's own objective term is
  *   J_n = w[0..2] . (fluid force on the body) + w[3] * (power),
  * w [host] 4 doubles, as reported in the step's wrench. Given
  * lam_next = dJ/d(state after the step) it writes lam_prev = dJ/d(state
  * before the step) (both stored layout, F32) and adds the step's
  * dJ/d(bone pose) into pose_bar [m->nbones][24] (same layout as a pose).
- * Supported: F32 storage, mdf_iters = 1, omega = alpha = 0, with_adjoint set
- * (else LBM_ERR_UNSUPPORTED). The context's own state is left unchanged; m's
+ * Supported: F32 storage, BGK, direct forcing with mdf_iters = 1 on a
+ * no-slip wall, omega = alpha = 0, with_adjoint set (else
+ * LBM_ERR_UNSUPPORTED). The context's own state is left unchanged; m's
  * X, U, F are overwritten with the step's values. This is the differentiation
  * form: gradients of time-averaged thrust and power with respect to body
  * kinematics, through skinning (Sec. III-A) and the coupled step (Sec. III-B). */
