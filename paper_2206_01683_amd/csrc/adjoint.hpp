@@ -521,9 +521,7 @@ __device__ inline void adj_face_item(const EnvView &e, const AdjArgs &A, int id)
 
 template <bool XPER>
 __global__ void __launch_bounds__(512) k_adj_collide(EnvView e, AdjArgs A) {
-  const int b = blockIdx.x;
-  const int per = (e.nblocks + 7) >> 3;
-  const int lb = (b & 7) * per + (b >> 3);
+  const int lb = blockIdx.x;
   if (lb >= e.nblocks) return;
   adj_collide_cell<XPER>(e, A, lb, threadIdx.x, threadIdx.y);
 }

@@ -179,13 +179,6 @@ __device__ inline void collide_range(const BatchArgs &b, int s, int i0, int i1, 
   }
 }
 
-// Collide work item of hardware workgroup position i out of a grid of g
-// (g a multiple of 8): each XCD (i % 8) takes a contiguous eighth of the items.
-__device__ inline int xcd_item(int i, int total) {
-  const int per = (total + 7) >> 3;
-  return (i & 7) * per + (i >> 3);
-}
-
 // ------------------------------------------------------ per-phase kernels --
 __global__ void __launch_bounds__(WG) kb_skin(BatchArgs b, int s) { phase_skin(b, s, blockIdx.x, threadIdx.x); }
 
@@ -210,9 +203,11 @@ __global__ void __launch_bounds__(WG) kb_spread(BatchArgs b, int s, int final_pa
     phase_spread(b, s, final_pass != 0, item, s_pre, threadIdx.x);
 }
 
+// One collide work item per workgroup, in launch order (the same mapping
+// as the single-lattice collide).
 template <bool UNI>
 __global__ void __launch_bounds__(WG) kb_collide(BatchArgs b, int s) {
-  const int item = xcd_item(blockIdx.x, b.tot[PRE_COLLIDE]);
+  const int item = blockIdx.x;
   if (item < b.tot[PRE_COLLIDE]) phase_collide<UNI>(b, s, item, threadIdx.x);
 }
 

@@ -297,15 +297,14 @@ __device__ inline void collide_cell(const EnvView &e, const FrameF &fr, int cur,
   if (collide_load<S, XPER, YZ>(e, cur, lb, tx, ty, c, f)) collide_finish<S, XPER, ROT, YZ, TRT>(e, fr, cur, c, f);
 }
 
-// Single-lattice launch: blockDim = (e.bx, e.by). Blocks are mapped
-// XCD-aware: hardware workgroup b runs on XCD b % 8, so the logical block
-// index gives each XCD a contiguous 1/8 of the domain (shared cache lines of
-// neighbouring blocks stay in one L2).
+// Single-lattice launch: blockDim = (e.bx, e.by), logical block = hardware
+// workgroup index. (Mapping blocks so that each XCD, which takes workgroups
+// b with b % 8 equal, sweeps a contiguous eighth of the domain measured 3%
+// slower on the fish: consecutive workgroups then share no lines in L2, and
+// interleaving them over the XCDs spreads each plane's traffic evenly.)
 template <class S, bool XPER, bool ROT, bool YZ = false, bool TRT = false>
 __global__ void __launch_bounds__(512) k_collide(EnvView e, FrameF fr, int cur) {
-  const int b = blockIdx.x;
-  const int per = (e.nblocks + 7) >> 3;
-  const int lb = (b & 7) * per + (b >> 3);
+  const int lb = blockIdx.x;
   if (lb >= e.nblocks) return;
   collide_cell<S, XPER, ROT, YZ, TRT>(e, fr, cur, lb, threadIdx.x, threadIdx.y);
 }

@@ -293,7 +293,7 @@ void collide_kernels(const EnvView &e, const FrameF &fr, int cur, int grid, dim3
 
 template <class S>
 lbm_status launch_collide(lbm_ctx *c, const EnvView &e, const FrameF &fr, bool rot) {
-  const int grid = ((e.nblocks + 7) / 8) * 8;
+  const int grid = e.nblocks;
   const dim3 blk = collide_block(c);
   const bool yz = !(e.g.yper && e.g.zper), xper = e.g.xper != 0;
   if (c->p.collision == LBM_COLLIDE_TRT)
@@ -636,7 +636,7 @@ lbm_status adjoint_passes(lbm_ctx *c, const EnvView &e, const FrameF &fr, const 
     k_adj_spread<<<std::min(c->L.cap * kSpreadSplit, 2048), WG, 0, c->stream>>>(e, A);
     if ((st = launched()) != LBM_OK) return st;
   }
-  const int grid = ((e.nblocks + 7) / 8) * 8;
+  const int grid = e.nblocks;
   const dim3 blk = collide_block(c);
   if (e.g.xper)
     k_adj_collide<true><<<grid, blk, 0, c->stream>>>(e, A);
@@ -760,7 +760,7 @@ lbm_status lbm_adjoint_segment(lbm_ctx *c, const void *ckpt, void *const *ring, 
     const FrameF fr = frame_f(&frames[t]);
     if (e.ib && (st = ib_forward(c, e, fr, poses + pstride * t)) != LBM_OK) return st;
     if (t + 1 < nseg) {
-      const int grid = ((e.nblocks + 7) / 8) * 8;
+      const int grid = e.nblocks;
       const dim3 blk = collide_block(c);
       if (e.g.xper)
         k_collide<StoreF32, true, false><<<grid, blk, 0, c->stream>>>(e, fr, 0);
@@ -1068,7 +1068,7 @@ lbm_status batch_enqueue_t(lbm_batch *b, int nsteps, int mode) {
   int cap_items = 0;
   for (int e = 0; e < b->nenv; ++e) cap_items += b->views[e].cap;
   const int gdyn = std::max(8, std::min(cap_items * kSpreadSplit, 4096));
-  const int gcol = ((b->tot[PRE_COLLIDE] + 7) / 8) * 8;
+  const int gcol = b->tot[PRE_COLLIDE];
   for (int s = 0; s < nsteps; ++s) {
     kb_skin<<<b->tot[PRE_SKIN], WG, 0, b->stream>>>(a, s);
     kb_active<<<b->tot[PRE_ACTIVE], WG, 0, b->stream>>>(a);
