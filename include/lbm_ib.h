@@ -111,8 +111,9 @@ enum { LBM_IB_DIRECT = 0, LBM_IB_IMPLICIT = 1 };
  *   w+ = 1/tau (the viscosity stays (tau - 1/2)/3) and w- = 1/tau- with
  *   (tau - 1/2)(tau- - 1/2) = trt_lambda (> 0; 3/16 is the usual choice).
  *   Open faces extrapolate as before, the non-equilibrium part's even and
- *   odd halves relaxing at w+ and w-. Supported by lbm_ib_step; the batched
- *   and adjoint entry points return LBM_ERR_UNSUPPORTED. */
+ *   odd halves relaxing at w+ and w-. Supported by lbm_ib_step and the
+ *   batched entry points; the adjoint entry points return
+ *   LBM_ERR_UNSUPPORTED. */
 enum { LBM_COLLIDE_BGK = 0, LBM_COLLIDE_TRT = 1 };
 
 /* Immersed-wall condition (lbm_params.wall_mode).
@@ -420,7 +421,10 @@ size_t lbm_batch_bytes(int32_t nenv);
 /* Create a batch over envs [host, nenv entries] using the caller's device
  * buffer dev (lbm_batch_bytes(nenv), 256-byte aligned) and HIP stream
  * (must not be the null stream if graphs are used). All environments must
- * use the same mdf_iters. Uploads the descriptors and synchronizes. */
+ * use the same mdf_iters. Each environment keeps its own collision (BGK or
+ * TRT), wall mode and faces; an environment with ib_scheme
+ * LBM_IB_IMPLICIT returns LBM_ERR_UNSUPPORTED. Uploads the descriptors and
+ * synchronizes. */
 lbm_status lbm_batch_create(lbm_batch **out, const lbm_env *envs, int32_t nenv, void *dev, void *hip_stream);
 
 /* Advance every environment by nsteps steps with the given driver. graph != 0:

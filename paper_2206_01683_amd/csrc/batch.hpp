@@ -68,22 +68,33 @@ __device__ inline int dynamic_prefix(const BatchArgs &b, int mult, int *s_pre, i
 __device__ inline FrameF env_frame(const EnvView &e, int s) { return frame_from(e.frames + (size_t)18 * s); }
 __device__ inline int env_cur(const EnvView &e, int s) { return e.cur0 ^ (s & 1); }
 
-// collide_cell for any environment: boundary kind and frame chosen at run time.
-__device__ inline void collide_any(const EnvView &e, const FrameF &fr, int cur, int lb, int tx, int ty) {
+// collide_cell for any environment of one collision kind: boundary kind and
+// frame chosen at run time.
+template <bool TRT>
+__device__ inline void collide_any_t(const EnvView &e, const FrameF &fr, int cur, int lb, int tx, int ty) {
   if (!(e.g.yper && e.g.zper)) {
     if (e.g.xper)
-      e.rot ? collide_cell<StoreF32, true, true, true>(e, fr, cur, lb, tx, ty)
-            : collide_cell<StoreF32, true, false, true>(e, fr, cur, lb, tx, ty);
+      e.rot ? collide_cell<StoreF32, true, true, true, TRT>(e, fr, cur, lb, tx, ty)
+            : collide_cell<StoreF32, true, false, true, TRT>(e, fr, cur, lb, tx, ty);
     else
-      e.rot ? collide_cell<StoreF32, false, true, true>(e, fr, cur, lb, tx, ty)
-            : collide_cell<StoreF32, false, false, true>(e, fr, cur, lb, tx, ty);
+      e.rot ? collide_cell<StoreF32, false, true, true, TRT>(e, fr, cur, lb, tx, ty)
+            : collide_cell<StoreF32, false, false, true, TRT>(e, fr, cur, lb, tx, ty);
   } else if (e.g.xper) {
-    e.rot ? collide_cell<StoreF32, true, true>(e, fr, cur, lb, tx, ty)
-          : collide_cell<StoreF32, true, false>(e, fr, cur, lb, tx, ty);
+    e.rot ? collide_cell<StoreF32, true, true, false, TRT>(e, fr, cur, lb, tx, ty)
+          : collide_cell<StoreF32, true, false, false, TRT>(e, fr, cur, lb, tx, ty);
   } else {
-    e.rot ? collide_cell<StoreF32, false, true>(e, fr, cur, lb, tx, ty)
-          : collide_cell<StoreF32, false, false>(e, fr, cur, lb, tx, ty);
+    e.rot ? collide_cell<StoreF32, false, true, false, TRT>(e, fr, cur, lb, tx, ty)
+          : collide_cell<StoreF32, false, false, false, TRT>(e, fr, cur, lb, tx, ty);
   }
+}
+
+// Any environment: boundary kind, rotation and collision (BGK or TRT) from
+// its view, each uniform over a workgroup.
+__device__ inline void collide_any(const EnvView &e, const FrameF &fr, int cur, int lb, int tx, int ty) {
+  if (e.two_rate)
+    collide_any_t<true>(e, fr, cur, lb, tx, ty);
+  else
+    collide_any_t<false>(e, fr, cur, lb, tx, ty);
 }
 
 // ------------------------------------------------------------ phase bodies --

@@ -209,7 +209,8 @@ EnvView env_view(lbm_ctx *c, const lbm_markers *m) {
   e.inv_tau = (float)(1.0 / tau);
   e.omt = (float)(1.0 - 1.0 / tau);
   e.pref = (float)(1.0 - 0.5 / tau);
-  if (c->p.collision == LBM_COLLIDE_TRT) {
+  e.two_rate = c->p.collision == LBM_COLLIDE_TRT ? 1 : 0;
+  if (e.two_rate) {
     const double wp = 1.0 / tau, wm = 1.0 / (0.5 + c->p.trt_lambda / (tau - 0.5));
     e.trt = TrtRates{(float)wp, (float)wm, (float)(1.0 - 0.5 * wp), (float)(1.0 - 0.5 * wm),
                      (float)(1.0 - 0.5 * (wp + wm)), (float)(0.5 * (wm - wp))};
@@ -1114,8 +1115,7 @@ lbm_status lbm_batch_create(lbm_batch **out, const lbm_env *envs, int32_t nenv, 
   for (int e = 0; e < nenv; ++e) {
     if (!env_ok(envs[e])) return LBM_ERR_ARG;
     if (envs[e].ctx->p.mdf_iters != envs[0].ctx->p.mdf_iters) return LBM_ERR_ARG;
-    if (envs[e].ctx->p.ib_scheme != LBM_IB_DIRECT || envs[e].ctx->p.collision != LBM_COLLIDE_BGK)
-      return LBM_ERR_UNSUPPORTED;
+    if (envs[e].ctx->p.ib_scheme != LBM_IB_DIRECT) return LBM_ERR_UNSUPPORTED;
     for (int f = 0; f < e; ++f)
       if (envs[f].ctx == envs[e].ctx) return LBM_ERR_ARG;
   }
@@ -1142,7 +1142,7 @@ lbm_status lbm_batch_create(lbm_batch **out, const lbm_env *envs, int32_t nenv, 
   for (int e = 0; e < nenv; ++e) {
     const lbm_params &q = envs[e].ctx->p;
     if (envs[e].rotating || q.bc_lo == LBM_BC_PERIODIC || q.bc_y[0] != LBM_BC_PERIODIC ||
-        q.bc_z[0] != LBM_BC_PERIODIC)
+        q.bc_z[0] != LBM_BC_PERIODIC || q.collision != LBM_COLLIDE_BGK)
       b->uniform = false;
   }
   int dev_id = 0, cus = 0, per_cu[2] = {0, 0};

@@ -95,11 +95,42 @@ def test_equal_rates_match_bgk():
     assert d <= 1e-7
 
 
-def test_batch_and_adjoint_reject_trt():
+@pytest.mark.parametrize("mode", ["phases", "persistent"])
+def test_batched_trt_environments(mode):
+    """A batch mixing TRT (two values of Lambda) and BGK environments: the
+    general batched kernels pick each environment's collision at run time.
+    Each environment agrees with its lone single-lattice run to float32
+    rounding, and the TRT ones with the FP64 oracle."""
+    n = 10
+    envs = I.batch_workloads(count=3, seed=13, nsteps=n)
+    _trt(envs[0])
+    _trt(envs[1], 0.25)
+    b = lbm.Batch(envs, n)
+    b.run(n, mode=mode, graph=False)
+    assert b.check() == 0
+    with torch.cuda.stream(b.stream):
+        got = [s.read_populations() for s in b.sims]
+        us = [s.macros(w.frames[n - 1])[1] for s, w in zip(b.sims, envs)]
+    b.synchronize()
+    for j, w in enumerate(envs):
+        sim, _, wr = gpu_run(w, n, block=(128, 4))
+        want = sim.read_populations()
+        torch.cuda.synchronize()
+        d = (got[j] - want).abs().max().item()
+        dw = np.abs(b.wrench[j].cpu().numpy() - wr).max()
+        msg = f"{mode} env {j} collision {w.collision} lambda {w.trt_lambda}: max |df| vs alone {d:.3e}, wrench {dw:.3e}"
+        if w.collision == lbm.COLLIDE_TRT:
+            ref = oracle_run(w, n)
+            _, u_ref = oracle.macros(ref["prm"], ref["f"], w.frames[n - 1])
+            e = rel_l2(interior(us[j].cpu().numpy().astype(np.float64), w), interior(u_ref, w))
+            msg += f", velocity rel L2 vs oracle {e:.3e}"
+            assert e <= 1e-5
+        say(msg)
+        assert d < 1e-6 and dw < 1e-6
+
+
+def test_adjoint_rejects_trt():
     w = _trt(I.sphere_workload(nsteps=4))
-    with pytest.raises(lbm.LBMError) as ei:
-        lbm.Batch([w, I.sphere_workload(nsteps=4)], 4)
-    assert ei.value.code == lbm.ERR_UNSUPPORTED
     sim = lbm.Simulation(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi, max_markers=w.markers.n, max_bones=1,
                          u0=w.u0.astype(np.float32), with_adjoint=True, collision=lbm.COLLIDE_TRT)
     dm = lbm.DeviceMarkers(w.markers)
