@@ -27,6 +27,7 @@ struct BatchArgs {
   const EnvView *envs;  // [nenv]
   int nenv;
   const int *pre;       // [4][nenv + 1] exclusive item prefixes: skin, active, interp, collide
+  const int *corder;    // [nenv] environment at each position of the collide prefix (grouped by kind)
   int tot[4];
   int mdf;              // direct-forcing passes
   unsigned *bar;        // grid barrier: [0] arrivals, [1] generation
@@ -97,6 +98,24 @@ __device__ inline void collide_any(const EnvView &e, const FrameF &fr, int cur, 
     collide_any_t<false>(e, fr, cur, lb, tx, ty);
 }
 
+// Collide kind of an environment: bit 0 periodic x, bit 1 rotating frame,
+// bit 2 an open y or z face, bit 3 TRT. Kind 0 (open x, no rotation,
+// periodic y and z, BGK) is the common case.
+enum { kCollideKinds = 16 };
+__host__ __device__ inline int collide_kind(const EnvView &e) {
+  return (e.g.xper ? 1 : 0) | (e.rot ? 2 : 0) | (e.g.yper && e.g.zper ? 0 : 4) | (e.two_rate ? 8 : 0);
+}
+
+// K >= 0: the environment is of kind K (one specialised collide, registers
+// of that variant only); K < 0: any kind, chosen at run time.
+template <int K>
+__device__ inline void collide_item(const EnvView &e, const FrameF &fr, int cur, int lb, int tx, int ty) {
+  if constexpr (K < 0)
+    collide_any(e, fr, cur, lb, tx, ty);
+  else
+    collide_cell<StoreF32, (K & 1) != 0, (K & 2) != 0, (K & 4) != 0, (K & 8) != 0>(e, fr, cur, lb, tx, ty);
+}
+
 // ------------------------------------------------------------ phase bodies --
 __device__ inline void phase_skin(const BatchArgs &b, int s, int item, int tid) {
   const int ei = find_env(b.pre + PRE_SKIN * (b.nenv + 1), b.nenv, item);
@@ -153,18 +172,17 @@ __device__ inline void phase_spread(const BatchArgs &b, int s, bool final_pass, 
 }
 
 // Collide item -> (environment, logical block); 512 threads as e.bx x e.by.
-template <bool UNI>
+// Collide items are numbered over the environments in kind order (corder).
+template <int K>
 __device__ inline void phase_collide(const BatchArgs &b, int s, int item, int tid) {
-  const int ei = find_env(b.pre + PRE_COLLIDE * (b.nenv + 1), b.nenv, item);
-  const EnvView &e = b.envs[ei];
+  const int *pre = b.pre + PRE_COLLIDE * (b.nenv + 1);
+  const int pos = find_env(pre, b.nenv, item);
+  const EnvView &e = b.envs[b.corder[pos]];
   const FrameF fr = env_frame(e, s);
-  const int lb = item - b.pre[PRE_COLLIDE * (b.nenv + 1) + ei];
+  const int lb = item - pre[pos];
   const int cur = env_cur(e, s);
   const int tx = tid % e.bx, ty = tid / e.bx;
-  if (UNI)
-    collide_cell<StoreF32, false, false>(e, fr, cur, lb, tx, ty);
-  else
-    collide_any(e, fr, cur, lb, tx, ty);
+  collide_item<K>(e, fr, cur, lb, tx, ty);
 }
 
 // Collide items [i0, i1) in order, looking the environment up once per run
@@ -174,19 +192,13 @@ __device__ inline void collide_range(const BatchArgs &b, int s, int i0, int i1, 
   const int *pre = b.pre + PRE_COLLIDE * (b.nenv + 1);
   int item = i0;
   while (item < i1) {
-    const int ei = find_env(pre, b.nenv, item);
-    const EnvView &e = b.envs[ei];
+    const int pos = find_env(pre, b.nenv, item);
+    const EnvView &e = b.envs[b.corder[pos]];
     const FrameF fr = env_frame(e, s);
     const int cur = env_cur(e, s);
-    const int lo = pre[ei], hi = min(pre[ei + 1], i1);
+    const int lo = pre[pos], hi = min(pre[pos + 1], i1);
     const int tx = tid % e.bx, ty = tid / e.bx;
-    for (; item < hi; ++item) {
-      const int lb = item - lo;
-      if (UNI)
-        collide_cell<StoreF32, false, false>(e, fr, cur, lb, tx, ty);
-      else
-        collide_any(e, fr, cur, lb, tx, ty);
-    }
+    for (; item < hi; ++item) collide_item<UNI ? 0 : -1>(e, fr, cur, item - lo, tx, ty);
   }
 }
 
@@ -214,12 +226,13 @@ __global__ void __launch_bounds__(WG) kb_spread(BatchArgs b, int s, int final_pa
     phase_spread(b, s, final_pass != 0, item, s_pre, threadIdx.x);
 }
 
-// One collide work item per workgroup, in launch order (the same mapping
-// as the single-lattice collide).
-template <bool UNI>
-__global__ void __launch_bounds__(WG) kb_collide(BatchArgs b, int s) {
-  const int item = blockIdx.x;
-  if (item < b.tot[PRE_COLLIDE]) phase_collide<UNI>(b, s, item, threadIdx.x);
+// Collide items item0 .. item0 + gridDim.x - 1, all of environments of kind
+// K, one per workgroup in launch order (the same mapping as the
+// single-lattice collide). One launch per kind present.
+template <int K>
+__global__ void __launch_bounds__(WG) kb_collide(BatchArgs b, int s, int item0) {
+  const int item = item0 + blockIdx.x;
+  if (item < b.tot[PRE_COLLIDE]) phase_collide<K>(b, s, item, threadIdx.x);
 }
 
 // --------------------------------------------------------- grid barrier ----

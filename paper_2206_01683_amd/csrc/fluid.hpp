@@ -195,25 +195,29 @@ __device__ inline void collide_finish(const EnvView &e, const FrameF &fr, int cu
     Fy = gy + rho * (ay - 2.0f * wy);
     Fz = gz + rho * (az - 2.0f * wz);
   } else {
-    // (ux,uy,uz) is u_f; choose u_b and shift f by f^eq(u_b) - f^eq(u_f)
+    // (ux,uy,uz) is u_f; choose u_b and shift f by f^eq(u_b) - f^eq(u_f).
+    // The inlet velocity is picked by value (fr.uhi or fr.ulo), never through
+    // a pointer into fr: where fr is a local, that would put it in scratch.
     int bc;
-    const float *uf;
+    bool use_hi;
     if (!YZ) {
       bc = lo_face ? g.bc_lo : g.bc_hi;
-      uf = lo_face ? fr.ulo : fr.uhi;
+      use_hi = !lo_face;
     } else {
       // first velocity face of this node: x low, x high, y low, y high, z low, z high
       bc = 2;
-      uf = fr.ulo;
+      use_hi = false;
       if (!XPER && x != xs && (x == 0 ? g.bc_lo : g.bc_hi) == 1) {
         bc = 1;
-        uf = x == 0 ? fr.ulo : fr.uhi;
+        use_hi = x != 0;
       } else if ((ys != y && (y == 0 ? g.bc_y[0] : g.bc_y[1]) == 1) ||
                  (zs != z && (z == 0 ? g.bc_z[0] : g.bc_z[1]) == 1)) {
         bc = 1;
       }
     }
-    float bx = bc == 1 ? uf[0] : ux, by = bc == 1 ? uf[1] : uy, bz = bc == 1 ? uf[2] : uz;
+    const float ufx = use_hi ? fr.uhi[0] : fr.ulo[0], ufy = use_hi ? fr.uhi[1] : fr.ulo[1],
+                ufz = use_hi ? fr.uhi[2] : fr.ulo[2];
+    float bx = bc == 1 ? ufx : ux, by = bc == 1 ? ufy : uy, bz = bc == 1 ? ufz : uz;
     const float ub2 = bx * bx + by * by + bz * bz, uf2 = ux * ux + uy * uy + uz * uz;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {

@@ -8,9 +8,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "../../include/lbm_ib.h"
@@ -975,7 +977,9 @@ struct lbm_batch {
   int nenv;
   std::vector<lbm_env> envs;
   std::vector<EnvView> views;  // host copy of the uploaded descriptors
-  std::vector<int> pre;        // [4][nenv + 1]
+  std::vector<int> pre;        // [4][nenv + 1] prefixes, then [nenv + 1] collide order (corder)
+  int kind_lo[kCollideKinds];  // collide items of kind k: [kind_lo[k], kind_lo[k] + kind_n[k])
+  int kind_n[kCollideKinds];
   EnvView *d_envs;
   int *d_pre;
   unsigned *d_bar;
@@ -998,7 +1002,7 @@ size_t batch_layout(int nenv, size_t *o_envs, size_t *o_pre, size_t *o_bar) {
   *o_envs = o;
   o = align_up(o + sizeof(EnvView) * (size_t)nenv, 256);
   *o_pre = o;
-  o = align_up(o + sizeof(int) * 4 * (size_t)(nenv + 1), 256);
+  o = align_up(o + sizeof(int) * 5 * (size_t)(nenv + 1), 256);
   *o_bar = o;
   o = align_up(o + 64, 256);
   return o;
@@ -1030,8 +1034,21 @@ void batch_views(lbm_batch *b) {
     b->pre[0 * stride + e + 1] = b->pre[0 * stride + e] + skin_items(v.n);
     b->pre[1 * stride + e + 1] = b->pre[1 * stride + e] + (v.ntiles + WG - 1) / WG;
     b->pre[2 * stride + e + 1] = b->pre[2 * stride + e] + interp_items(v.n);
-    b->pre[3 * stride + e + 1] = b->pre[3 * stride + e] + v.nblocks;
   }
+  // collide items: environments grouped by collide kind, each group one launch
+  int *corder = &b->pre[4 * stride];
+  int pos = 0;
+  for (int k = 0; k < kCollideKinds; ++k) {
+    b->kind_lo[k] = b->pre[3 * stride + pos];
+    for (int e = 0; e < b->nenv; ++e) {
+      if (collide_kind(b->views[e]) != k) continue;
+      corder[pos] = e;
+      b->pre[3 * stride + pos + 1] = b->pre[3 * stride + pos] + b->views[e].nblocks;
+      ++pos;
+    }
+    b->kind_n[k] = b->pre[3 * stride + pos] - b->kind_lo[k];
+  }
+  corder[b->nenv] = 0;
   for (int q = 0; q < 4; ++q) b->tot[q] = b->pre[q * stride + b->nenv];
 }
 
@@ -1052,11 +1069,30 @@ BatchArgs batch_args(const lbm_batch *b) {
   a.envs = b->d_envs;
   a.nenv = b->nenv;
   a.pre = b->d_pre;
+  a.corder = b->d_pre + 4 * (b->nenv + 1);
   for (int q = 0; q < 4; ++q) a.tot[q] = b->tot[q];
   a.mdf = b->mdf;
   a.bar = b->d_bar;
   a.status = b->d_status;
   return a;
+}
+
+template <int K>
+void launch_kb_collide(const BatchArgs &a, int s, int item0, int n, hipStream_t st) {
+  kb_collide<K><<<n, WG, 0, st>>>(a, s, item0);
+}
+
+template <int... K>
+constexpr std::array<void (*)(const BatchArgs &, int, int, int, hipStream_t), sizeof...(K)> kb_collide_table(
+    std::integer_sequence<int, K...>) {
+  return {&launch_kb_collide<K>...};
+}
+
+// One collide launch per kind present, each kernel specialised to its kind.
+void batch_collide(const lbm_batch *b, const BatchArgs &a, int s) {
+  static constexpr auto table = kb_collide_table(std::make_integer_sequence<int, kCollideKinds>{});
+  for (int k = 0; k < kCollideKinds; ++k)
+    if (b->kind_n[k] > 0) table[k](a, s, b->kind_lo[k], b->kind_n[k], b->stream);
 }
 
 template <bool UNI>
@@ -1069,7 +1105,6 @@ lbm_status batch_enqueue_t(lbm_batch *b, int nsteps, int mode) {
   int cap_items = 0;
   for (int e = 0; e < b->nenv; ++e) cap_items += b->views[e].cap;
   const int gdyn = std::max(8, std::min(cap_items * kSpreadSplit, 4096));
-  const int gcol = b->tot[PRE_COLLIDE];
   for (int s = 0; s < nsteps; ++s) {
     kb_skin<<<b->tot[PRE_SKIN], WG, 0, b->stream>>>(a, s);
     kb_active<<<b->tot[PRE_ACTIVE], WG, 0, b->stream>>>(a);
@@ -1079,7 +1114,7 @@ lbm_status batch_enqueue_t(lbm_batch *b, int nsteps, int mode) {
       kb_interp<UNI><<<b->tot[PRE_INTERP], WG, 0, b->stream>>>(a, s, pass);
     }
     kb_spread<<<gdyn, WG, 0, b->stream>>>(a, s, 1);
-    kb_collide<UNI><<<gcol, WG, 0, b->stream>>>(a, s);
+    batch_collide(b, a, s);
     lbm_status st = launched();
     if (st != LBM_OK) return st;
   }
@@ -1124,7 +1159,7 @@ lbm_status lbm_batch_create(lbm_batch **out, const lbm_env *envs, int32_t nenv, 
   b->nenv = nenv;
   b->envs.assign(envs, envs + nenv);
   b->views.resize(nenv);
-  b->pre.assign(4 * (size_t)(nenv + 1), 0);
+  b->pre.assign(5 * (size_t)(nenv + 1), 0);
   size_t o_envs, o_pre, o_bar;
   batch_layout(nenv, &o_envs, &o_pre, &o_bar);
   char *base = static_cast<char *>(dev);
