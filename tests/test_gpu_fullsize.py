@@ -75,3 +75,51 @@ def test_reduced_storage_sphere_100_steps_error_report():
     assert errs["f32"][0] <= 1e-5
     assert errs["f32"][0] < errs["f16"][0] < errs["bf16"][0]
     assert errs["f16"][0] < 5e-3 and errs["bf16"][0] < 5e-2
+
+
+@pytest.mark.timeout(600)
+def test_full_size_batched_64_environments():
+    """The batched form at the benchmark's size and launch configuration: the
+    64 fish environments of the seed-4 draw (44.2M cells, 262,073 markers),
+    autotuned tile shapes, the per-phase driver replayed from a HIP graph,
+    two steps from rest; every environment's populations against the FP64
+    oracle's, and the persistent driver bit for bit equal to the per-phase
+    one."""
+    from paper_2206_01683_amd import lbm
+    n = 2
+    envs = I.batch_workloads(count=64, seed=4, nsteps=n)
+    b = lbm.Batch(envs, n)
+    shapes = b.autotune(reps=1)
+    say("full-size batch: shapes", {f"{bx}x{by}": int(((shapes[:, 0] == bx) & (shapes[:, 1] == by)).sum())
+                                    for bx, by in lbm.BATCH_SHAPES})
+    b.run(n, mode="phases", graph=True)
+    assert b.check() == 0
+    p = lbm.Batch(envs, n)
+    p.set_shapes(shapes)
+    p.run(n, mode="persistent", graph=True)
+    assert p.check() == 0
+    worst = 0.0
+    for j, w in enumerate(envs):
+        with torch.cuda.stream(b.stream):
+            got = b.sims[j].read_populations()
+        b.synchronize()
+        with torch.cuda.stream(p.stream):
+            other = p.sims[j].read_populations()
+        p.synchronize()
+        assert torch.equal(got, other)
+        got = got.cpu().numpy()
+        ref = oracle_run(w, nsteps=n)
+        err = max(np.abs(interior(got[i].astype(np.float64), w) - interior(ref["f"][i], w)).max() for i in range(27))
+        scale = max(np.abs(ref["f"][i]).max() for i in range(27))
+        wr = b.wrench[j].cpu().numpy()
+        assert np.array_equal(wr, p.wrench[j].cpu().numpy())
+        fx = np.abs(wr[:, 0] - ref["wrench"][:, 0]).max() / np.abs(ref["wrench"][:, 0]).max()
+        worst = max(worst, err / scale)
+        if j % 16 == 0:
+            say(f"full-size batch env {j} ({w.nx}x{w.ny}x{w.nz}, {w.markers.n} markers): max |df| {err:.3e} "
+                f"(scale {scale:.3f}), force-x max rel {fx:.3e}")
+        assert err < 1e-6 * scale
+        assert fx <= 1e-4
+    say(f"full-size batch: worst max |df| / scale over 64 environments {worst:.3e}")
+    b.close()
+    p.close()
