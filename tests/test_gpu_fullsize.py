@@ -123,3 +123,34 @@ def test_full_size_batched_64_environments():
     say(f"full-size batch: worst max |df| / scale over 64 environments {worst:.3e}")
     b.close()
     p.close()
+
+
+@pytest.mark.timeout(600)
+def test_full_size_adjoint_gradient():
+    """The differentiation form at the benchmark's geometry and checkpoint
+    interval: the 128x64x64 fin with 3,000 markers, J the time-averaged
+    thrust, 40 steps in two checkpoint segments of 20. The 8-parameter
+    gradient from the native reverse sweep against the FP64 oracle's
+    forward-mode tangent (one dual-number run per parameter)."""
+    from paper_2206_01683_amd import adjoint as AD
+    n, every = 40, 20
+    prob = AD.FinProblem(nsteps=n, every=every)
+    theta = np.asarray(I.C5_BASE, dtype=np.float64)
+    J, tape = prob.value(theta)
+    g = prob.gradient(theta, tape)
+    w = prob.workload
+    prm = oracle.params(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi, 1, w.ib_alpha)
+    f0 = oracle.equilibrium_field(np.ones((w.nz, w.ny, w.nx)), w.u0.astype(np.float32).astype(np.float64))
+    poses = I.fin_poses(theta, w.markers, np.arange(n))
+    jac = I.fin_pose_jacobian(theta, w.markers, np.arange(n))
+    tan = np.zeros(8)
+    for j in range(8):
+        r = oracle.run_tangent(prm, f0.copy(), w.frames, w.markers, poses, jac[..., j], n)
+        tan[j] = AD.objective(r["wrench_d"], prob.weights)
+        say(f"full-size adjoint: dJ/dtheta[{j}] adjoint {g[j]: .6e}  oracle tangent {tan[j]: .6e}")
+    J64 = AD.objective(r["wrench"], prob.weights)
+    err = np.abs(g - tan).max() / np.abs(tan).max()
+    say(f"full-size adjoint: J gpu {J:.8e} oracle {J64:.8e}; max |adjoint - tangent| / max |tangent| = {err:.2e}")
+    assert abs(J - J64) <= 1e-5 * abs(J64)
+    assert err < 1e-4
+    prob.close()
