@@ -268,6 +268,9 @@ __device__ inline void interp_item(const EnvView &e, const FrameF &fr, int item,
   float part[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (k < n) {
     const float Xk[3] = {e.X[k], e.X[n + k], e.X[2 * n + k]};
+    // loaded now, used after the stencil gather: off the dependent chain
+    const float Uk[3] = {e.U[k], e.U[n + k], e.U[2 * n + k]};
+    const float dvk = e.dv[k];
     const int s3[3] = {lane & 3, (lane >> 2) & 3, lane >> 4};
     const int dims[3] = {g.nx, g.ny, g.nz};
     int base[3], node[3];
@@ -311,7 +314,6 @@ __device__ inline void interp_item(const EnvView &e, const FrameF &fr, int item,
     if (lane == 0) {
       float rk;
       float Fk[3], inc[3];
-      const float Uk[3] = {e.U[k], e.U[n + k], e.U[2 * n + k]};
       const float Ui[3] = {sx, sy, sz};
       // velocity to correct: U - U^interp, or on a slip wall its normal part
       float dU[3] = {Uk[0] - Ui[0], Uk[1] - Ui[1], Uk[2] - Ui[2]};
@@ -338,7 +340,6 @@ __device__ inline void interp_item(const EnvView &e, const FrameF &fr, int item,
           Fk[c] = e.F[c * n + k] + inc[c];
         }
       }
-      const float dvk = e.dv[k];
       float fd[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
