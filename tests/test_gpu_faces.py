@@ -75,10 +75,10 @@ def test_marker_range_guard_on_open_y_face():
 
 
 def test_batched_environments_with_open_faces():
-    """Environments with open y or z faces take the general batched kernels
-    (boundary kinds chosen at run time), compiled apart from the
-    single-lattice ones, so they agree with a lone run to float32 rounding
-    rather than bit for bit; both agree with the oracle."""
+    """Environments with open y or z faces in a batch: the per-phase driver
+    launches a collide specialised to their kind. Each agrees with its lone
+    run (bit for bit as measured; the bound allows float32 rounding) and with
+    the oracle."""
     n = 10
     envs = I.batch_workloads(count=2, seed=9, nsteps=n)
     envs[0].bc_y = (V, O)

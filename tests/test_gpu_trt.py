@@ -98,9 +98,10 @@ def test_equal_rates_match_bgk():
 @pytest.mark.parametrize("mode", ["phases", "persistent"])
 def test_batched_trt_environments(mode):
     """A batch mixing TRT (two values of Lambda) and BGK environments: the
-    general batched kernels pick each environment's collision at run time.
-    Each environment agrees with its lone single-lattice run to float32
-    rounding, and the TRT ones with the FP64 oracle."""
+    per-phase driver launches one collide per collision kind, the persistent
+    kernel picks each environment's collision at run time. Each environment
+    agrees with its lone single-lattice run (bit for bit as measured; the
+    bound allows float32 rounding), and the TRT ones with the FP64 oracle."""
     n = 10
     envs = I.batch_workloads(count=3, seed=13, nsteps=n)
     _trt(envs[0])
