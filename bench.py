@@ -98,7 +98,8 @@ def run_gpu(storage: str, steps: int, warmup: int, block=(0, 0), collision: int 
 def run_batch(nenv: int, nsteps: int, seed: int = 4):
     """Batched environments: nenv fish environments of uneven sizes (seeded
     draw), nsteps steps per run, one run = one graph replay. Returns MLUPS
-    per driver with autotuned tile shapes."""
+    per driver with autotuned tile shapes, F32 storage, and of the per-phase
+    driver with FP16 and BF16 storage."""
     import numpy as np
     import torch
 
@@ -126,6 +127,22 @@ def run_batch(nenv: int, nsteps: int, seed: int = 4):
     b.close()
     del b
     torch.cuda.empty_cache()
+    # 2-byte storage (108 B per cell), per-phase driver: same environments
+    for fmt in ("f16", "bf16"):
+        b = lbm.Batch(envs, nsteps, storage=fmt)
+        b.autotune(reps=3)
+        b.run(nsteps, mode="phases", graph=True)
+        b.synchronize()
+        t0 = time.perf_counter()
+        b.run(nsteps, mode="phases", graph=True)
+        b.synchronize()
+        dt = time.perf_counter() - t0
+        out[f"phases_{fmt}"] = {"mlups": round(ncell * nsteps / dt / 1e6, 1), "ms_per_step": round(dt * 1e3 / nsteps, 4),
+                                "hbm_frac_108B": round(ncell * nsteps * 108 / dt / (HBM_PEAK_GBS * 1e9), 4),
+                                "status": b.check()}
+        b.close()
+        del b
+        torch.cuda.empty_cache()
     return out
 
 

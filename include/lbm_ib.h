@@ -402,7 +402,7 @@ typedef struct lbm_batch lbm_batch;
  * for the lifetime of the batch; poses/frames/wrench are indexed by the step
  * of a run (0 .. nsteps-1) and are re-read by every run. */
 typedef struct {
-  lbm_ctx *ctx;             /* initialized context (F32, 512-thread collide block) */
+  lbm_ctx *ctx;             /* initialized context (any storage, 512-thread collide block) */
   lbm_markers m;            /* n >= 1 markers, nbones <= the context's max_bones */
   const float *poses;       /* [nsteps][m.nbones][24] */
   const lbm_frame *frames;  /* [nsteps] device copy of the frames */
@@ -430,7 +430,10 @@ lbm_status lbm_batch_create(lbm_batch **out, const lbm_env *envs, int32_t nenv, 
 /* Advance every environment by nsteps steps with the given driver. graph != 0:
  * the launches are captured once into a HIP graph (per (nsteps, mode)) and the
  * graph is replayed; nsteps must then be even, so that every replay starts
- * from the same population buffer. Does not synchronize. */
+ * from the same population buffer. The persistent driver takes F32 storage
+ * only: with an FP16 or BF16 environment it returns LBM_ERR_UNSUPPORTED (the
+ * per-phase driver takes every storage, one collide launch per kind and
+ * format). Does not synchronize. */
 lbm_status lbm_batch_run(lbm_batch *b, int32_t nsteps, int32_t mode, int32_t graph);
 
 /* Tile-shape autotuner: for every environment time the collide kernel with

@@ -99,21 +99,28 @@ __device__ inline void collide_any(const EnvView &e, const FrameF &fr, int cur, 
 }
 
 // Collide kind of an environment: bit 0 periodic x, bit 1 rotating frame,
-// bit 2 an open y or z face, bit 3 TRT. Kind 0 (open x, no rotation,
-// periodic y and z, BGK) is the common case.
-enum { kCollideKinds = 16 };
+// bit 2 an open y or z face, bit 3 TRT; bits 4-5 the population format
+// (Store*::kind). Kind 0 (open x, no rotation, periodic y and z, BGK, F32)
+// is the common case.
+enum { kCollideKinds = 48 };
 __host__ __device__ inline int collide_kind(const EnvView &e) {
-  return (e.g.xper ? 1 : 0) | (e.rot ? 2 : 0) | (e.g.yper && e.g.zper ? 0 : 4) | (e.two_rate ? 8 : 0);
+  return (e.g.xper ? 1 : 0) | (e.rot ? 2 : 0) | (e.g.yper && e.g.zper ? 0 : 4) | (e.two_rate ? 8 : 0) |
+         (e.storage << 4);
 }
 
+template <int SK> struct StoreOf { using type = StoreF32; };
+template <> struct StoreOf<1> { using type = StoreF16; };
+template <> struct StoreOf<2> { using type = StoreBF16; };
+
 // K >= 0: the environment is of kind K (one specialised collide, registers
-// of that variant only); K < 0: any kind, chosen at run time.
+// of that variant only); K < 0: any F32 kind, chosen at run time.
 template <int K>
 __device__ inline void collide_item(const EnvView &e, const FrameF &fr, int cur, int lb, int tx, int ty) {
   if constexpr (K < 0)
     collide_any(e, fr, cur, lb, tx, ty);
   else
-    collide_cell<StoreF32, (K & 1) != 0, (K & 2) != 0, (K & 4) != 0, (K & 8) != 0>(e, fr, cur, lb, tx, ty);
+    collide_cell<typename StoreOf<(K >> 4)>::type, (K & 1) != 0, (K & 2) != 0, (K & 4) != 0, (K & 8) != 0>(
+        e, fr, cur, lb, tx, ty);
 }
 
 // ------------------------------------------------------------ phase bodies --
@@ -128,15 +135,28 @@ __device__ inline void phase_active(const BatchArgs &b, int item, int tid) {
   active_item(b.envs[ei], item - b.pre[PRE_ACTIVE * (b.nenv + 1) + ei], tid);
 }
 
-template <bool UNI>
+template <class S, bool UNI>
+__device__ inline void macro_rot(const EnvView &e, const FrameF &fr, int cur, int slot, int tid) {
+  if (!UNI && e.rot)
+    macro_item<S, true>(e, fr, cur, slot, tid);
+  else
+    macro_item<S, false>(e, fr, cur, slot, tid);
+}
+
+// ANYS: environments may store 2-byte populations (per-phase driver); the
+// persistent kernel takes F32 only.
+template <bool UNI, bool ANYS = false>
 __device__ inline void phase_macro(const BatchArgs &b, int s, int item, const int *s_pre, int tid) {
   const int ei = find_env(s_pre, b.nenv, item);
   const EnvView &e = b.envs[ei];
   const FrameF fr = env_frame(e, s);
-  if (!UNI && e.rot)
-    macro_item<StoreF32, true>(e, fr, env_cur(e, s), item - s_pre[ei], tid);
+  const int cur = env_cur(e, s), slot = item - s_pre[ei];
+  if (!UNI && ANYS && e.storage == StoreF16::kind)
+    macro_rot<StoreF16, UNI>(e, fr, cur, slot, tid);
+  else if (!UNI && ANYS && e.storage == StoreBF16::kind)
+    macro_rot<StoreBF16, UNI>(e, fr, cur, slot, tid);
   else
-    macro_item<StoreF32, false>(e, fr, env_cur(e, s), item - s_pre[ei], tid);
+    macro_rot<StoreF32, UNI>(e, fr, cur, slot, tid);
 }
 
 template <bool UNI>
@@ -211,7 +231,7 @@ template <bool UNI>
 __global__ void __launch_bounds__(WG) kb_macro(BatchArgs b, int s) {
   __shared__ int s_pre[kMaxEnvs + 1];
   const int tot = dynamic_prefix(b, 1, s_pre, threadIdx.x);
-  for (int item = blockIdx.x; item < tot; item += gridDim.x) phase_macro<UNI>(b, s, item, s_pre, threadIdx.x);
+  for (int item = blockIdx.x; item < tot; item += gridDim.x) phase_macro<UNI, true>(b, s, item, s_pre, threadIdx.x);
 }
 
 template <bool UNI>

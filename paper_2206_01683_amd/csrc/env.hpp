@@ -29,6 +29,7 @@ struct EnvView {
   float inv_tau, omt, pref;     // 1/tau, 1 - 1/tau, 1 - 1/(2 tau)
   TrtRates trt;                 // used by the TRT collide only
   int two_rate;                 // collision: 1 TRT (rates in trt), 0 BGK
+  int storage;                  // population format: Store*::kind (0 F32, 1 F16, 2 BF16)
   int bx, by, gx, gy, nblocks;  // collide tile shape and its block grid (by = 0: linear, see cell_of)
   void *f[2];                   // population buffers
   // immersed boundary

@@ -212,6 +212,9 @@ EnvView env_view(lbm_ctx *c, const lbm_markers *m) {
   e.omt = (float)(1.0 - 1.0 / tau);
   e.pref = (float)(1.0 - 0.5 / tau);
   e.two_rate = c->p.collision == LBM_COLLIDE_TRT ? 1 : 0;
+  e.storage = c->p.storage == LBM_STORE_F16 ? StoreF16::kind
+              : c->p.storage == LBM_STORE_BF16 ? StoreBF16::kind
+                                               : StoreF32::kind;
   if (e.two_rate) {
     const double wp = 1.0 / tau, wm = 1.0 / (0.5 + c->p.trt_lambda / (tau - 0.5));
     e.trt = TrtRates{(float)wp, (float)wm, (float)(1.0 - 0.5 * wp), (float)(1.0 - 0.5 * wm),
@@ -988,7 +991,8 @@ struct lbm_batch {
   int mdf;
   hipStream_t stream;
   int persistent_grid[2];  // [uniform]
-  bool uniform;            // all environments open in x and non-rotating
+  bool uniform;            // every environment of collide kind 0 (open x, non-rotating, periodic y/z, BGK, F32)
+  bool two_byte;           // some environment stores 2-byte populations (per-phase driver only)
   bool dirty;
   hipGraph_t graph;
   hipGraphExec_t exec;
@@ -1010,7 +1014,7 @@ size_t batch_layout(int nenv, size_t *o_envs, size_t *o_pre, size_t *o_bar) {
 
 bool env_ok(const lbm_env &v) {
   const lbm_ctx *c = v.ctx;
-  if (!c || c->p.storage != LBM_STORE_F32 || !(c->bx * c->by == WG || (c->bx == WG && c->by == 0))) return false;
+  if (!c || !(c->bx * c->by == WG || (c->bx == WG && c->by == 0))) return false;
   if (v.m.n < 1 || v.m.n > c->p.max_markers || !markers_ok(c, &v.m)) return false;
   if (!v.poses || !v.frames) return false;
   return true;
@@ -1174,11 +1178,13 @@ lbm_status lbm_batch_create(lbm_batch **out, const lbm_env *envs, int32_t nenv, 
   b->graph_nsteps = -1;
   b->graph_mode = -1;
   b->uniform = true;
+  b->two_byte = false;
   for (int e = 0; e < nenv; ++e) {
     const lbm_params &q = envs[e].ctx->p;
     if (envs[e].rotating || q.bc_lo == LBM_BC_PERIODIC || q.bc_y[0] != LBM_BC_PERIODIC ||
-        q.bc_z[0] != LBM_BC_PERIODIC || q.collision != LBM_COLLIDE_BGK)
+        q.bc_z[0] != LBM_BC_PERIODIC || q.collision != LBM_COLLIDE_BGK || q.storage != LBM_STORE_F32)
       b->uniform = false;
+    if (q.storage != LBM_STORE_F32) b->two_byte = true;
   }
   int dev_id = 0, cus = 0, per_cu[2] = {0, 0};
   if (hipGetDevice(&dev_id) != hipSuccess ||
@@ -1204,6 +1210,7 @@ lbm_status lbm_batch_create(lbm_batch **out, const lbm_env *envs, int32_t nenv, 
 lbm_status lbm_batch_run(lbm_batch *b, int32_t nsteps, int32_t mode, int32_t graph) {
   if (!b || nsteps < 0 || (mode != LBM_BATCH_PHASES && mode != LBM_BATCH_PERSISTENT)) return LBM_ERR_ARG;
   if (graph && (nsteps % 2 != 0 || b->stream == nullptr)) return LBM_ERR_ARG;
+  if (mode == LBM_BATCH_PERSISTENT && b->two_byte) return LBM_ERR_UNSUPPORTED;
   if (nsteps == 0) return LBM_OK;
   lbm_status st;
   for (int e = 0; e < b->nenv; ++e)
@@ -1267,9 +1274,9 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, int32_t *shapes_out) {
       const EnvView v = env_view(c, nullptr);
       // the collide reads f[cur] and writes f[cur ^ 1] (scratch until the next
       // step), so timing it leaves the state unchanged
-      st = launch_collide<StoreF32>(c, v, FrameF{}, false);
+      st = LBM_BY_STORAGE(c, launch_collide, v, FrameF{}, false);
       if (st != LBM_OK || hipEventRecord(e0, b->stream) != hipSuccess) break;
-      for (int r = 0; r < reps && st == LBM_OK; ++r) st = launch_collide<StoreF32>(c, v, FrameF{}, false);
+      for (int r = 0; r < reps && st == LBM_OK; ++r) st = LBM_BY_STORAGE(c, launch_collide, v, FrameF{}, false);
       float ms = 0.f;
       if (st != LBM_OK || hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
           hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {

@@ -387,9 +387,12 @@ class Batch:
     """Many workloads (inputs.Workload, each with markers) advanced together
     by the batched kernels; every environment owns a Simulation. Per-step
     poses, frames and wrenches live on the device for `nsteps` steps of a run
-    (a run re-reads them from step 0)."""
+    (a run re-reads them from step 0). storage: one population format for
+    every environment ("f32", "f16", "bf16") or a sequence, one per
+    environment; the persistent driver takes "f32" only."""
 
-    def __init__(self, workloads, nsteps, block=(128, 4), max_active_tiles=1024, device="cuda", keep_wrench=True):
+    def __init__(self, workloads, nsteps, block=(128, 4), max_active_tiles=1024, device="cuda", keep_wrench=True,
+                 storage="f32"):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the lattice Boltzmann library runs only on the GPU")
         L = lib()
@@ -399,9 +402,11 @@ class Batch:
         self.sims, self.markers, self.poses, self.frames, self.wrench = [], [], [], [], []
         envs = (Env * len(workloads))()
         with torch.cuda.stream(self.stream):
+            formats = [storage] * len(workloads) if isinstance(storage, str) else list(storage)
+            assert len(formats) == len(workloads)
             for j, w in enumerate(workloads):
                 ntiles = ((w.nx + 7) // 8) * ((w.ny + 7) // 8) * ((w.nz + 7) // 8)
-                sim = Simulation(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi, max_markers=w.markers.n,
+                sim = Simulation(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi, storage=formats[j], max_markers=w.markers.n,
                                  max_bones=w.markers.nbones, mdf_iters=w.mdf_iters, ib_alpha=w.ib_alpha,
                                  u0=w.u0.astype(np.float32), device=self.device, block=block,
                                  max_active_tiles=min(ntiles, max_active_tiles), stream=self.stream,

@@ -169,3 +169,31 @@ def test_mixed_collide_kinds_match_environments_run_alone(mode):
         dw = np.abs(b.wrench[j].cpu().numpy() - wr).max()
         say(f"{mode} env {j} ({w.nx}x{w.ny}x{w.nz}): max |df| vs alone {d:.3e}, wrench {dw:.3e}")
         assert d < 1e-6 and dw < 1e-6
+
+
+def test_two_byte_environments_match_lone_runs():
+    """FP16, BF16 and F32 environments in one batch (per-phase driver,
+    autotuned shapes, eager and graph-replayed): one collide launch per kind
+    and format, each environment equal to its lone run with the same
+    storage. The persistent driver takes F32 only and refuses the batch."""
+    from gpu_helpers import gpu_run
+    n = 10
+    envs = I.batch_workloads(count=3, seed=17, nsteps=n)
+    formats = ["f16", "bf16", "f32"]
+    for graph in (False, True):
+        b = lbm.Batch(envs, n, storage=formats)
+        b.autotune(reps=1)
+        b.run(n, mode="phases", graph=graph)
+        assert b.check() == 0
+        got = _read_all(b)
+        for j, w in enumerate(envs):
+            sim, _, wr = gpu_run(w, n, storage=formats[j], block=(128, 4))
+            want = sim.read_populations().cpu().numpy()
+            d = np.abs(got[j] - want).max()
+            dw = np.abs(b.wrench[j].cpu().numpy() - wr).max()
+            say(f"graph={graph} env {j} storage {formats[j]}: max |df| vs alone {d:.3e}, wrench {dw:.3e}")
+            assert d == 0.0 and dw == 0.0
+        with pytest.raises(lbm.LBMError) as ei:
+            b.run(n, mode="persistent", graph=graph)
+        assert ei.value.code == lbm.ERR_UNSUPPORTED
+        b.close()
