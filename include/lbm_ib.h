@@ -96,8 +96,9 @@ enum { LBM_STORE_F32 = 0, LBM_STORE_F16 = 1, LBM_STORE_BF16 = 2 };
  *   diagonal preconditioner 2 rho_k; alpha = 0 once p.Sp is not positive,
  *   beta = 0 once r.z is 0. Each step costs one spread and one
  *   interpolation, like a multi-direct-forcing pass; ib_alpha is not used.
- *   Supported by lbm_ib_step only (the batched and adjoint entry points
- *   return LBM_ERR_UNSUPPORTED). */
+ *   Supported by lbm_ib_step and by the batched per-phase driver when every
+ *   environment of the batch uses it; the persistent driver and the adjoint
+ *   entry points return LBM_ERR_UNSUPPORTED. */
 enum { LBM_IB_DIRECT = 0, LBM_IB_IMPLICIT = 1 };
 
 /* Collisions (lbm_params.collision).
@@ -421,19 +422,19 @@ size_t lbm_batch_bytes(int32_t nenv);
 /* Create a batch over envs [host, nenv entries] using the caller's device
  * buffer dev (lbm_batch_bytes(nenv), 256-byte aligned) and HIP stream
  * (must not be the null stream if graphs are used). All environments must
- * use the same mdf_iters. Each environment keeps its own collision (BGK or
- * TRT), wall mode and faces; an environment with ib_scheme
- * LBM_IB_IMPLICIT returns LBM_ERR_UNSUPPORTED. Uploads the descriptors and
- * synchronizes. */
+ * use the same mdf_iters and the same ib_scheme (else LBM_ERR_UNSUPPORTED;
+ * also for the implicit correction on a slip wall in a rotating frame, as
+ * lbm_ib_step). Each environment keeps its own collision (BGK or TRT),
+ * storage, wall mode and faces. Uploads the descriptors and synchronizes. */
 lbm_status lbm_batch_create(lbm_batch **out, const lbm_env *envs, int32_t nenv, void *dev, void *hip_stream);
 
 /* Advance every environment by nsteps steps with the given driver. graph != 0:
  * the launches are captured once into a HIP graph (per (nsteps, mode)) and the
  * graph is replayed; nsteps must then be even, so that every replay starts
  * from the same population buffer. The persistent driver takes F32 storage
- * only: with an FP16 or BF16 environment it returns LBM_ERR_UNSUPPORTED (the
- * per-phase driver takes every storage, one collide launch per kind and
- * format). Does not synchronize. */
+ * and direct forcing only: with an FP16 or BF16 environment or the implicit
+ * correction it returns LBM_ERR_UNSUPPORTED (the per-phase driver takes
+ * both, one collide launch per kind and format). Does not synchronize. */
 lbm_status lbm_batch_run(lbm_batch *b, int32_t nsteps, int32_t mode, int32_t graph);
 
 /* Tile-shape autotuner: for every environment time the collide kernel with

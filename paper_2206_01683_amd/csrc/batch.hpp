@@ -34,7 +34,9 @@ struct BatchArgs {
   int *status;          // bit 0: barrier timeout
 };
 
-enum { PRE_SKIN = 0, PRE_ACTIVE = 1, PRE_INTERP = 2, PRE_COLLIDE = 3 };
+// Rows of BatchArgs::pre: per-environment exclusive item prefixes (row 4 holds
+// the collide order, corder); PRE_CG counts conjugate-gradient items.
+enum { PRE_SKIN = 0, PRE_ACTIVE = 1, PRE_INTERP = 2, PRE_COLLIDE = 3, PRE_CG = 5, PRE_ROWS = 6 };
 
 // Largest e with pre[e] <= item (pre non-decreasing, pre[nenv] > item).
 __device__ inline int find_env(const int *pre, int nenv, int item) {
@@ -219,6 +221,59 @@ __device__ inline void collide_range(const BatchArgs &b, int s, int i0, int i1, 
     const int lo = pre[pos], hi = min(pre[pos + 1], i1);
     const int tx = tid % e.bx, ty = tid / e.bx;
     for (; item < hi; ++item) collide_item<UNI ? 0 : -1>(e, fr, cur, item - lo, tx, ty);
+  }
+}
+
+// ------------------------------------- implicit velocity correction, batched --
+// Each environment's conjugate gradients, as in the single-lattice kernels:
+// every environment counts the last-arrival of its own items (its own
+// counters), so one launch covers the items of all environments. The batch
+// runs them when every environment uses LBM_IB_IMPLICIT (per-phase driver).
+__global__ void __launch_bounds__(kCgWG) kb_cg_init(BatchArgs b, int s) {
+  const int *pre = b.pre + PRE_CG * (b.nenv + 1);
+  const int ei = find_env(pre, b.nenv, blockIdx.x);
+  const EnvView &e = b.envs[ei];
+  const FrameF fr = env_frame(e, s);
+  if (e.rot)
+    cg_init_item<true>(e, fr, blockIdx.x - pre[ei]);
+  else
+    cg_init_item<false>(e, fr, blockIdx.x - pre[ei]);
+}
+
+// Spreading of CG step j's search direction into each environment's gcg.
+__global__ void __launch_bounds__(WG) kb_spread_cg(BatchArgs b, int j) {
+  __shared__ int s_pre[kMaxEnvs + 1];
+  const int tot = dynamic_prefix(b, kSpreadSplit, s_pre, threadIdx.x);
+  for (int item = blockIdx.x; item < tot; item += gridDim.x) {
+    const int ei = find_env(s_pre, b.nenv, item);
+    const EnvView &e = b.envs[ei];
+    spread_item<true>(e, item - s_pre[ei], threadIdx.x, e.gcg, cg_scal(e, 1, j), j == 0);
+  }
+}
+
+// Grid: the total of PRE_INTERP (each environment's interpolation items).
+__global__ void __launch_bounds__(WG) kb_cg_apply(BatchArgs b, int j) {
+  const int *pre = b.pre + PRE_INTERP * (b.nenv + 1);
+  const int ei = find_env(pre, b.nenv, blockIdx.x);
+  cg_apply_item(b.envs[ei], blockIdx.x - pre[ei], threadIdx.x, j);
+}
+
+// Grid: the total of PRE_CG.
+__global__ void __launch_bounds__(kCgWG) kb_cg_update(BatchArgs b, int s, int j, int last) {
+  const int *pre = b.pre + PRE_CG * (b.nenv + 1);
+  const int ei = find_env(pre, b.nenv, blockIdx.x);
+  const EnvView &e = b.envs[ei];
+  cg_update_item(e, env_frame(e, s), blockIdx.x - pre[ei], j, last != 0);
+}
+
+// Clears gcg of every active tile before the next CG step's spreading.
+__global__ void __launch_bounds__(WG) kb_cg_clear(BatchArgs b) {
+  __shared__ int s_pre[kMaxEnvs + 1];
+  const int tot = dynamic_prefix(b, 1, s_pre, threadIdx.x);
+  for (int item = blockIdx.x; item < tot; item += gridDim.x) {
+    const int ei = find_env(s_pre, b.nenv, item);
+    unsigned long long *gq = b.envs[ei].gcg + (size_t)(item - s_pre[ei]) * 1536;
+    for (int q = threadIdx.x; q < 1536; q += WG) gq[q] = 0ull;
   }
 }
 

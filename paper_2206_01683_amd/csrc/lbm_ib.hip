@@ -980,7 +980,7 @@ struct lbm_batch {
   int nenv;
   std::vector<lbm_env> envs;
   std::vector<EnvView> views;  // host copy of the uploaded descriptors
-  std::vector<int> pre;        // [4][nenv + 1] prefixes, then [nenv + 1] collide order (corder)
+  std::vector<int> pre;        // [PRE_ROWS][nenv + 1]: item prefixes, collide order (row 4), CG items (PRE_CG)
   int kind_lo[kCollideKinds];  // collide items of kind k: [kind_lo[k], kind_lo[k] + kind_n[k])
   int kind_n[kCollideKinds];
   EnvView *d_envs;
@@ -993,6 +993,8 @@ struct lbm_batch {
   int persistent_grid[2];  // [uniform]
   bool uniform;            // every environment of collide kind 0 (open x, non-rotating, periodic y/z, BGK, F32)
   bool two_byte;           // some environment stores 2-byte populations (per-phase driver only)
+  bool implicit;           // every environment uses the implicit correction (per-phase driver only)
+  int tot_cg;              // conjugate-gradient items over all environments
   bool dirty;
   hipGraph_t graph;
   hipGraphExec_t exec;
@@ -1006,7 +1008,7 @@ size_t batch_layout(int nenv, size_t *o_envs, size_t *o_pre, size_t *o_bar) {
   *o_envs = o;
   o = align_up(o + sizeof(EnvView) * (size_t)nenv, 256);
   *o_pre = o;
-  o = align_up(o + sizeof(int) * 5 * (size_t)(nenv + 1), 256);
+  o = align_up(o + sizeof(int) * PRE_ROWS * (size_t)(nenv + 1), 256);
   *o_bar = o;
   o = align_up(o + 64, 256);
   return o;
@@ -1033,12 +1035,15 @@ void batch_views(lbm_batch *b) {
   }
   const int stride = b->nenv + 1;
   for (int q = 0; q < 4; ++q) b->pre[q * stride] = 0;
+  b->pre[PRE_CG * stride] = 0;
   for (int e = 0; e < b->nenv; ++e) {
     const EnvView &v = b->views[e];
     b->pre[0 * stride + e + 1] = b->pre[0 * stride + e] + skin_items(v.n);
     b->pre[1 * stride + e + 1] = b->pre[1 * stride + e] + (v.ntiles + WG - 1) / WG;
     b->pre[2 * stride + e + 1] = b->pre[2 * stride + e] + interp_items(v.n);
+    b->pre[PRE_CG * stride + e + 1] = b->pre[PRE_CG * stride + e] + cg_items(v.n);
   }
+  b->tot_cg = b->pre[PRE_CG * stride + b->nenv];
   // collide items: environments grouped by collide kind, each group one launch
   int *corder = &b->pre[4 * stride];
   int pos = 0;
@@ -1113,9 +1118,21 @@ lbm_status batch_enqueue_t(lbm_batch *b, int nsteps, int mode) {
     kb_skin<<<b->tot[PRE_SKIN], WG, 0, b->stream>>>(a, s);
     kb_active<<<b->tot[PRE_ACTIVE], WG, 0, b->stream>>>(a);
     kb_macro<UNI><<<gdyn, WG, 0, b->stream>>>(a, s);
-    for (int pass = 0; pass < b->mdf; ++pass) {
-      if (pass > 0) kb_spread<<<gdyn, WG, 0, b->stream>>>(a, s, 0);
-      kb_interp<UNI><<<b->tot[PRE_INTERP], WG, 0, b->stream>>>(a, s, pass);
+    if (b->implicit) {  // mdf = conjugate-gradient steps
+      kb_interp<UNI><<<b->tot[PRE_INTERP], WG, 0, b->stream>>>(a, s, 0);
+      kb_cg_init<<<b->tot_cg, kCgWG, 0, b->stream>>>(a, s);
+      for (int j = 0; j < b->mdf; ++j) {
+        const bool last = j == b->mdf - 1;
+        kb_spread_cg<<<gdyn, WG, 0, b->stream>>>(a, j);
+        kb_cg_apply<<<b->tot[PRE_INTERP], WG, 0, b->stream>>>(a, j);
+        kb_cg_update<<<b->tot_cg, kCgWG, 0, b->stream>>>(a, s, j, last ? 1 : 0);
+        if (!last) kb_cg_clear<<<gdyn, WG, 0, b->stream>>>(a);
+      }
+    } else {
+      for (int pass = 0; pass < b->mdf; ++pass) {
+        if (pass > 0) kb_spread<<<gdyn, WG, 0, b->stream>>>(a, s, 0);
+        kb_interp<UNI><<<b->tot[PRE_INTERP], WG, 0, b->stream>>>(a, s, pass);
+      }
     }
     kb_spread<<<gdyn, WG, 0, b->stream>>>(a, s, 1);
     batch_collide(b, a, s);
@@ -1154,7 +1171,11 @@ lbm_status lbm_batch_create(lbm_batch **out, const lbm_env *envs, int32_t nenv, 
   for (int e = 0; e < nenv; ++e) {
     if (!env_ok(envs[e])) return LBM_ERR_ARG;
     if (envs[e].ctx->p.mdf_iters != envs[0].ctx->p.mdf_iters) return LBM_ERR_ARG;
-    if (envs[e].ctx->p.ib_scheme != LBM_IB_DIRECT) return LBM_ERR_UNSUPPORTED;
+    if (envs[e].ctx->p.ib_scheme != envs[0].ctx->p.ib_scheme) return LBM_ERR_UNSUPPORTED;
+    // as lbm_ib_step: the slip-wall correction's system is unsymmetric in a rotating frame
+    if (envs[e].ctx->p.ib_scheme == LBM_IB_IMPLICIT && envs[e].ctx->p.wall_mode == LBM_WALL_SLIP &&
+        envs[e].rotating)
+      return LBM_ERR_UNSUPPORTED;
     for (int f = 0; f < e; ++f)
       if (envs[f].ctx == envs[e].ctx) return LBM_ERR_ARG;
   }
@@ -1163,7 +1184,7 @@ lbm_status lbm_batch_create(lbm_batch **out, const lbm_env *envs, int32_t nenv, 
   b->nenv = nenv;
   b->envs.assign(envs, envs + nenv);
   b->views.resize(nenv);
-  b->pre.assign(5 * (size_t)(nenv + 1), 0);
+  b->pre.assign(PRE_ROWS * (size_t)(nenv + 1), 0);
   size_t o_envs, o_pre, o_bar;
   batch_layout(nenv, &o_envs, &o_pre, &o_bar);
   char *base = static_cast<char *>(dev);
@@ -1179,6 +1200,7 @@ lbm_status lbm_batch_create(lbm_batch **out, const lbm_env *envs, int32_t nenv, 
   b->graph_mode = -1;
   b->uniform = true;
   b->two_byte = false;
+  b->implicit = envs[0].ctx->p.ib_scheme == LBM_IB_IMPLICIT;
   for (int e = 0; e < nenv; ++e) {
     const lbm_params &q = envs[e].ctx->p;
     if (envs[e].rotating || q.bc_lo == LBM_BC_PERIODIC || q.bc_y[0] != LBM_BC_PERIODIC ||
@@ -1210,7 +1232,7 @@ lbm_status lbm_batch_create(lbm_batch **out, const lbm_env *envs, int32_t nenv, 
 lbm_status lbm_batch_run(lbm_batch *b, int32_t nsteps, int32_t mode, int32_t graph) {
   if (!b || nsteps < 0 || (mode != LBM_BATCH_PHASES && mode != LBM_BATCH_PERSISTENT)) return LBM_ERR_ARG;
   if (graph && (nsteps % 2 != 0 || b->stream == nullptr)) return LBM_ERR_ARG;
-  if (mode == LBM_BATCH_PERSISTENT && b->two_byte) return LBM_ERR_UNSUPPORTED;
+  if (mode == LBM_BATCH_PERSISTENT && (b->two_byte || b->implicit)) return LBM_ERR_UNSUPPORTED;
   if (nsteps == 0) return LBM_OK;
   lbm_status st;
   for (int e = 0; e < b->nenv; ++e)

@@ -112,7 +112,43 @@ def test_determinism_bitwise():
     assert np.array_equal(wa, wb)
 
 
-def test_batch_and_adjoint_reject_the_implicit_scheme():
+@pytest.mark.parametrize("graph", [False, True])
+def test_batched_implicit_environments_match_lone_runs(graph):
+    """Three environments with the implicit correction (3 CG steps; one in a
+    rotating frame, one with FP16 storage) batched by the per-phase driver:
+    every environment equal to its lone single-lattice run, populations and
+    wrench. The persistent driver refuses implicit batches."""
+    n = 10
+    envs = I.batch_workloads(count=3, seed=23, nsteps=n)
+    for w in envs:
+        w.ib_scheme = lbm.IB_IMPLICIT
+        w.mdf_iters = 3
+    w = envs[1]
+    w.frames[:, 3:6] = (0.0, 0.0, 1e-3)
+    w.frames[:, 9:12] = (w.nx / 2.0, w.ny / 2.0, w.nz / 2.0)
+    formats = ["f32", "f32", "f16"]
+    b = lbm.Batch(envs, n, storage=formats)
+    b.run(n, mode="phases", graph=graph)
+    assert b.check() == 0
+    with torch.cuda.stream(b.stream):
+        got = [s.read_populations() for s in b.sims]
+    b.synchronize()
+    for j, w in enumerate(envs):
+        sim, _, wr = gpu_run(w, n, storage=formats[j], block=(128, 4))
+        want = sim.read_populations()
+        torch.cuda.synchronize()
+        d = (got[j] - want).abs().max().item()
+        dw = np.abs(b.wrench[j].cpu().numpy() - wr).max()
+        say(f"graph={graph} implicit env {j} ({w.nx}x{w.ny}x{w.nz}, {formats[j]}): max |df| vs alone {d:.3e}, "
+            f"wrench {dw:.3e}")
+        assert d == 0.0 and dw == 0.0
+    with pytest.raises(lbm.LBMError) as ei:
+        b.run(n, mode="persistent", graph=graph)
+    assert ei.value.code == lbm.ERR_UNSUPPORTED
+    b.close()
+
+
+def test_batch_mixing_schemes_and_adjoint_reject_the_implicit_scheme():
     w = I.sphere_workload(nsteps=4)
     w.ib_scheme = lbm.IB_IMPLICIT
     with pytest.raises(lbm.LBMError) as ei:
