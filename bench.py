@@ -56,7 +56,8 @@ def measured_traffic(storage: str):
     return float(vals[key]) if key in vals else None
 
 
-def run_gpu(storage: str, steps: int, warmup: int, block=(0, 0), collision: int = 0):
+def run_gpu(storage: str, steps: int, warmup: int, block=(0, 0), collision: int = 0, variant=None):
+    """The fish workload; variant (optional) edits it first (faces, frames)."""
     import numpy as np
     import torch
 
@@ -64,8 +65,10 @@ def run_gpu(storage: str, steps: int, warmup: int, block=(0, 0), collision: int 
     from paper_2206_01683_amd import lbm
 
     w = I.fish_workload(nsteps=warmup + steps)
+    if variant is not None:
+        variant(w)
     sim = lbm.Simulation(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi, storage=storage, max_markers=w.markers.n,
-                         max_bones=w.markers.nbones, block=block, collision=collision)
+                         max_bones=w.markers.nbones, block=block, collision=collision, bc_y=w.bc_y, bc_z=w.bc_z)
     dm = lbm.DeviceMarkers(w.markers)
     poses = torch.as_tensor(np.ascontiguousarray(w.poses, np.float32), device="cuda")
     wrench = torch.zeros((warmup + steps, 8), dtype=torch.float32, device="cuda")
@@ -327,9 +330,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f32", choices=sorted(BYTES_PER_CELL))
     ap.add_argument("--cpu-steps", type=int, default=24, help="oracle sample length (0: skip)")
-    ap.add_argument("--forms", default="f16,bf16,trt,batched,adjoint,two_fish,free_swimmer,ib_schemes",
-                    help="comma-separated extra forms to measure: f16, bf16, trt, batched, adjoint, two_fish, "
-                         "free_swimmer, ib_schemes")
+    ap.add_argument("--forms", default="f16,bf16,trt,faces_frames,batched,adjoint,two_fish,free_swimmer,ib_schemes",
+                    help="comma-separated extra forms to measure: f16, bf16, trt, faces_frames, batched, adjoint, "
+                         "two_fish, free_swimmer, ib_schemes")
     ap.add_argument("--no-forms", action="store_true", help="measure no extra form")
     ap.add_argument("--block", type=int, nargs=2, default=(0, 0))
     ap.add_argument("--batch-envs", type=int, default=64, help="batched form: environments (0: skip)")
@@ -358,6 +361,22 @@ def main():
         forms["trt"] = {"mlups": round(r["mlups"], 1), "collide_GBps": round(r["collide_gbs"], 1),
                         "collide_frac_of_hbm_peak": round(r["collide_gbs"] / HBM_PEAK_GBS, 4),
                         "lambda": _lbm.TRT_MAGIC, "status": r["status"]}
+    if "faces_frames" in want:
+        from paper_2206_01683_amd import inputs as _I
+
+        def open_faces(w):  # far field entering through every face
+            w.bc_y = (_I.BC_VELOCITY, _I.BC_VELOCITY)
+            w.bc_z = (_I.BC_VELOCITY, _I.BC_VELOCITY)
+
+        def rotating(w):  # the frame also turns about z through its origin (the fish's centre)
+            w.frames[:, 3:6] = (0.0, 0.0, 2e-4)
+
+        forms["faces_frames"] = {}
+        for name, fn in (("open_faces", open_faces), ("rotating_frame", rotating)):
+            r = run_gpu(args.storage, args.steps, args.warmup, tuple(args.block), variant=fn)
+            forms["faces_frames"][name] = {"mlups": round(r["mlups"], 1), "collide_GBps": round(r["collide_gbs"], 1),
+                                           "collide_frac_of_hbm_peak": round(r["collide_gbs"] / HBM_PEAK_GBS, 4),
+                                           "ib_ms_per_step": round(r["ib_avg_ms"], 5), "status": r["status"]}
     if "batched" in want and args.batch_envs > 0:
         forms["batched"] = run_batch(args.batch_envs, args.batch_steps)
     if "adjoint" in want:
