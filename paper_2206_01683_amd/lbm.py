@@ -389,7 +389,9 @@ class Batch:
     poses, frames and wrenches live on the device for `nsteps` steps of a run
     (a run re-reads them from step 0). storage: one population format for
     every environment ("f32", "f16", "bf16") or a sequence, one per
-    environment; the persistent driver takes "f32" only."""
+    environment; the persistent driver takes "f32" and direct forcing only
+    (the per-phase driver also takes the implicit correction, when every
+    environment uses it)."""
 
     def __init__(self, workloads, nsteps, block=(128, 4), max_active_tiles=1024, device="cuda", keep_wrench=True,
                  storage="f32"):
