@@ -381,6 +381,11 @@ def main():
         forms["batched"] = run_batch(args.batch_envs, args.batch_steps)
     if "adjoint" in want:
         forms["adjoint"] = run_adjoint()
+        # the same run keeping every step's state (400 x 56.6 MB = 22.6 GB of HBM): no collide recompute
+        a1 = run_adjoint(every=1)
+        forms["adjoint"]["store_every_step"] = {k: a1[k] for k in ("checkpoint_every", "forward_ms_per_step",
+                                                                     "backward_ms_per_step", "adjoint_over_forward",
+                                                                     "grad_norm", "finite", "status")}
     if "two_fish" in want:
         forms["two_fish"] = run_two_fish()
     if "free_swimmer" in want:
