@@ -7,14 +7,18 @@
 // prefixes; the active-tile counts are only known on the device, so the
 // macro and spreading phases build their prefix in LDS from the counters.
 // Two drivers use the same phase functions:
-//   kb_* kernels     one launch per phase (a step = 6+ launches), suitable for
-//                    capture into a graph of many steps;
+//   kb_* kernels     one launch per phase (a step = 6+ launches; the collide
+//                    one launch per collide kind present, each specialised),
+//                    suitable for capture into a graph of many steps; they
+//                    also take 2-byte storage and the implicit correction;
 //   kb_persistent    one launch for all steps: each workgroup loops over the
 //                    phases, separated by a device-wide barrier. The grid is
 //                    sized to be co-resident; the barrier's wait is bounded
 //                    (a timeout sets a status bit and every workgroup exits).
-// UNI = true: every environment has open x faces and non-rotating frames,
-// so the per-environment branches on those flags compile away.
+//                    F32 storage and direct forcing only.
+// UNI = true: every environment is of collide kind 0 (open x faces, no
+// rotation, periodic y and z, BGK, F32), so the per-environment branches on
+// those flags compile away.
 #pragma once
 
 #include "ib.hpp"
@@ -26,7 +30,7 @@ constexpr int kMaxEnvs = WG;  // one thread per environment in the LDS prefix sc
 struct BatchArgs {
   const EnvView *envs;  // [nenv]
   int nenv;
-  const int *pre;       // [4][nenv + 1] exclusive item prefixes: skin, active, interp, collide
+  const int *pre;       // [PRE_ROWS][nenv + 1] exclusive item prefixes (rows named by PRE_*)
   const int *corder;    // [nenv] environment at each position of the collide prefix (grouped by kind)
   int tot[4];
   int mdf;              // direct-forcing passes
