@@ -295,6 +295,30 @@ lbm_status lbm_adjoint_segment(lbm_ctx *c, const void *ckpt, void *const *ring, 
                                const float *poses, const lbm_frame *frames, const double *w, void *lam,
                                void *lam_tmp, float *pose_bar, void *ib_ring);
 
+/* The forward half of lbm_adjoint_segment, for callers that keep every state
+ * of a horizon (the HBM of one device holds hundreds of states of a
+ * 128x64x64 lattice): from ckpt, nseg steps are run with ring[t] receiving
+ * the state after step t (t = 0 .. nseg-1; ring[nseg-1] may be NULL, which
+ * skips the last collide), each step's forward IB data kept in ib_ring
+ * (lbm_adjoint_ring_bytes(p, nseg) bytes, 256-byte aligned), and each step's
+ * wrench row (force, torque, power, 0; as lbm_ib_step writes it) in wrench
+ * [nseg][8] (device, or NULL). The states, IB data and wrench are those of
+ * nseg lbm_ib_step calls from ckpt, bit for bit. Then lbm_adjoint_sweep with
+ * the same ckpt, ring, ib_ring, markers, poses and frames gives the gradient
+ * with no recompute. ckpt and the ring entries must be distinct. The
+ * context's own state and step count are not touched. Same support as
+ * lbm_adjoint_step. */
+lbm_status lbm_adjoint_record(lbm_ctx *c, const void *ckpt, void *const *ring, int32_t nseg, const lbm_markers *m,
+                              const float *poses, const lbm_frame *frames, void *ib_ring, float *wrench);
+
+/* The reverse half of lbm_adjoint_segment: its reverse passes over a segment
+ * that lbm_adjoint_record (or lbm_adjoint_segment) has left in ring (entries
+ * 0 .. nseg-2 are read) and ib_ring, with the same ckpt, markers, poses and
+ * frames. Arguments, errors and results as lbm_adjoint_segment. */
+lbm_status lbm_adjoint_sweep(lbm_ctx *c, const void *ckpt, void *const *ring, int32_t nseg, const lbm_markers *m,
+                             const float *poses, const lbm_frame *frames, const double *w, void *lam, void *lam_tmp,
+                             float *pose_bar, void *ib_ring);
+
 /* ------------------------------------------------------------------------
  * Free swimming (host functions, no device work): the articulated body of
  * Sec. III-A with the fluid's force as the external generalized force of

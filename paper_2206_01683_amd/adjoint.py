@@ -15,6 +15,12 @@ lambda = dJ/d(state) back one step at a time and accumulate each step's
 dJ/d(bone pose). Memory: ceil(nsteps / every) checkpoints, every - 1 ring
 states, the IB ring of `every` steps and two adjoint states.
 
+With record=True, `forward` keeps every state of the horizon instead
+(lbm_adjoint_record: nsteps states and the IB ring of nsteps steps, e.g.
+400 x 56.6 MB for the 128x64x64 fin), and `backward` runs the reverse passes
+alone (lbm_adjoint_sweep), with no recompute. The gradient is the same, bit
+for bit.
+
 `FinObjective` is a torch.autograd.Function from the 8 kinematics parameters
 of the swimmer to J: each step's bone poses are an analytic function of the
 parameters (inputs.fin_poses, the prescribed body motion of Sec. III-A), and
@@ -40,6 +46,8 @@ class Tape:
     checkpoints: List[torch.Tensor]  # state before step j * every
     final: torch.Tensor             # state after the last step
     wrench: torch.Tensor            # (nsteps, 8) float32, device
+    ring: Optional[List[torch.Tensor]] = None  # record: state after step t, t < nsteps - 1
+    ib_ring: Optional[torch.Tensor] = None     # record: every step's forward IB data
 
 
 def objective(wrench, weights) -> float:
@@ -51,8 +59,9 @@ def objective(wrench, weights) -> float:
 
 
 def forward(sim: "lbm.Simulation", markers: Optional["lbm.DeviceMarkers"], poses: Optional[torch.Tensor],
-            frames: np.ndarray, weights, every: int = 20):
-    """Run len(frames) steps with checkpoints; returns (J, tape)."""
+            frames: np.ndarray, weights, every: int = 20, record: bool = False):
+    """Run len(frames) steps with checkpoints (or, record=True, keeping
+    every state); returns (J, tape)."""
     frames = np.asarray(frames, dtype=np.float64).reshape(-1, 18)
     n = frames.shape[0]
     if n < 1 or every < 1:
@@ -61,6 +70,17 @@ def forward(sim: "lbm.Simulation", markers: Optional["lbm.DeviceMarkers"], poses
         raise ValueError("poses must cover every step")
     start = sim.step_count()
     wr = torch.zeros((n, 8), dtype=torch.float32, device=sim.device)
+    w4 = np.asarray(weights, dtype=np.float64).reshape(4)
+    if record:
+        ck = sim.new_state()
+        sim.save_state(ck)
+        ring = [sim.new_state() for _ in range(n)]
+        ib_ring = sim.adjoint_ring(n)
+        sim.adjoint_record(ck, ring, markers, None if markers is None else poses[:n].contiguous(), frames,
+                           ib_ring, wr)
+        sim.restore_state(ring[-1], start + n)  # the context ends after the run, as with checkpoints
+        tape = Tape(start, n, n, w4, [ck], ring[-1], wr, ring=ring[:-1], ib_ring=ib_ring)
+        return objective(wr.cpu().numpy(), tape.weights), tape
     cks = []
     for s in range(0, n, every):
         e = min(n, s + every)
@@ -70,7 +90,7 @@ def forward(sim: "lbm.Simulation", markers: Optional["lbm.DeviceMarkers"], poses
         sim.step(frames[s:e], markers, None if markers is None else poses[s:e], wr[s:e])
     final = sim.new_state()
     sim.save_state(final)
-    tape = Tape(start, n, every, np.asarray(weights, dtype=np.float64).reshape(4), cks, final, wr)
+    tape = Tape(start, n, every, w4, cks, final, wr)
     return objective(wr.cpu().numpy(), tape.weights), tape
 
 
@@ -97,6 +117,10 @@ def backward(sim: "lbm.Simulation", markers: Optional["lbm.DeviceMarkers"], pose
     pose_bar = None
     if markers is not None:
         pose_bar = torch.zeros((n, markers.nbones, 24), dtype=torch.float32, device=dev)
+    if tape.ring is not None:  # recorded: the reverse passes alone
+        sim.adjoint_segment(tape.checkpoints[0], tape.ring, markers, None if markers is None else poses[:n],
+                            frames[:n], tape.weights, lam, lam2, pose_bar, tape.ib_ring, sweep_only=True)
+        return pose_bar, lam
     ring = [sim.new_state() for _ in range(min(k, n) - 1)]
     if native:
         ib_ring = sim.adjoint_ring(min(k, n))
@@ -129,9 +153,10 @@ class FinProblem:
     The default weights (heading, 0) give the time-averaged thrust."""
 
     def __init__(self, nsteps: int = 400, every: int = 20, weights=None, device="cuda", max_active_tiles=256,
-                 **geometry):
+                 record: bool = False, **geometry):
         w = I.fin_workload(I.C5_BASE, nsteps=nsteps, **geometry)
         self.workload = w
+        self.record = record  # keep every state (forward(record=True)) instead of checkpoints
         self.nsteps, self.every = nsteps, every
         if weights is None:
             weights = np.concatenate([w.heading, [0.0]])
@@ -153,7 +178,8 @@ class FinProblem:
         self.sim.bind_own_buffers()
         self.sim.restore_state(self.s0, 0)
         poses = torch.as_tensor(self.poses(theta).astype(np.float32), device=self.sim.device)
-        J, tape = forward(self.sim, self.markers, poses, self.workload.frames, self.weights, self.every)
+        J, tape = forward(self.sim, self.markers, poses, self.workload.frames, self.weights, self.every,
+                          record=self.record)
         tape.poses = poses
         return J, tape
 

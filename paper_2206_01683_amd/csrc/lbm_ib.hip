@@ -584,11 +584,12 @@ lbm_status lbm_bind_populations(lbm_ctx *c, void *f_cur, void *f_next) {
 namespace {
 
 // Checks shared by the adjoint entry points; LBM_OK when the request is valid.
+// need_pose_bar false: a forward-only request (lbm_adjoint_record).
 lbm_status adjoint_request_ok(const lbm_ctx *c, const lbm_markers *m, const float *pose, const double *w,
-                              float *pose_bar) {
+                              float *pose_bar, bool need_pose_bar = true) {
   if (!markers_ok(c, m)) return LBM_ERR_ARG;
   const bool ib = m && m->n > 0;
-  if (ib && (!pose || !pose_bar)) return LBM_ERR_ARG;
+  if (ib && (!pose || (need_pose_bar && !pose_bar))) return LBM_ERR_ARG;
   if (ib && m->n > c->p.max_markers) return LBM_ERR_CAPACITY;
   for (int q = 0; q < 4; ++q)
     if (!std::isfinite(w[q])) return LBM_ERR_ARG;
@@ -601,12 +602,13 @@ lbm_status adjoint_request_ok(const lbm_ctx *c, const lbm_markers *m, const floa
 
 // Forward immersed-boundary phases of one step (one direct-forcing pass), from
 // the state in e.f[0], into the IB arrays e points at.
-lbm_status ib_forward(lbm_ctx *c, const EnvView &e, const FrameF &fr, const float *pose) {
+// wrench != null: also the step's wrench row, as lbm_ib_step writes it.
+lbm_status ib_forward(lbm_ctx *c, const EnvView &e, const FrameF &fr, const float *pose, float *wrench = nullptr) {
   k_skin_mark<<<skin_items(e.n), WG, 0, c->stream>>>(e, pose);
   k_active<<<(e.ntiles + WG - 1) / WG, WG, 0, c->stream>>>(e);
   k_macro<StoreF32, false><<<std::min(c->L.cap, 2048), WG, 0, c->stream>>>(e, fr, 0);
-  k_interp<false, false><<<interp_items(e.n), WG, 0, c->stream>>>(e, fr, nullptr);
-  k_spread<<<std::min(c->L.cap * kSpreadSplit, 2048), WG, 0, c->stream>>>(e, nullptr);
+  k_interp<false, false><<<interp_items(e.n), WG, 0, c->stream>>>(e, fr, wrench ? e.partials : nullptr);
+  k_spread<<<std::min(c->L.cap * kSpreadSplit, 2048), WG, 0, c->stream>>>(e, wrench);
   return launched();
 }
 
@@ -736,14 +738,24 @@ size_t lbm_adjoint_ring_bytes(const lbm_params *p, int32_t nseg) {
   return ring_slot(p).total * (size_t)nseg;
 }
 
-lbm_status lbm_adjoint_segment(lbm_ctx *c, const void *ckpt, void *const *ring, int32_t nseg, const lbm_markers *m,
-                               const float *poses, const lbm_frame *frames, const double *w, void *lam,
-                               void *lam_tmp, float *pose_bar, void *ib_ring) {
-  if (!c || !ckpt || nseg < 1 || !frames || !w || !lam || !lam_tmp || lam == lam_tmp || !ib_ring) return LBM_ERR_ARG;
+}  // extern "C"
+
+namespace {
+
+// Arguments shared by the segment entry points. ring: nring entries, the
+// last one may be null when last_optional.
+lbm_status segment_args_ok(lbm_ctx *c, const void *ckpt, void *const *ring, int32_t nseg, int32_t nring,
+                           bool last_optional, const lbm_frame *frames, const void *lam, const void *lam_tmp,
+                           const void *ib_ring) {
+  if (!c || !ckpt || nseg < 1 || !frames || !ib_ring) return LBM_ERR_ARG;
   if (reinterpret_cast<uintptr_t>(ib_ring) % 256 != 0) return LBM_ERR_ARG;
-  if (nseg > 1 && !ring) return LBM_ERR_ARG;
-  for (int t = 0; t + 1 < nseg; ++t) {
-    if (!ring[t] || ring[t] == ckpt || ring[t] == lam || ring[t] == lam_tmp) return LBM_ERR_ARG;
+  if (nring > 0 && !ring) return LBM_ERR_ARG;
+  for (int t = 0; t < nring; ++t) {
+    if (!ring[t]) {
+      if (last_optional && t == nring - 1) continue;
+      return LBM_ERR_ARG;
+    }
+    if (ring[t] == ckpt || (lam && ring[t] == lam) || (lam_tmp && ring[t] == lam_tmp)) return LBM_ERR_ARG;
     for (int u = 0; u < t; ++u)
       if (ring[u] == ring[t]) return LBM_ERR_ARG;
   }
@@ -751,21 +763,32 @@ lbm_status lbm_adjoint_segment(lbm_ctx *c, const void *ckpt, void *const *ring, 
     if (!frame_ok(&frames[t])) return LBM_ERR_ARG;
     if (rotating(&frames[t])) return LBM_ERR_UNSUPPORTED;
   }
-  lbm_status st = adjoint_request_ok(c, m, poses, w, pose_bar);
-  if (st != LBM_OK) return st;
+  return LBM_OK;
+}
+
+// Forward over a segment from ckpt: state t+1 into ring[t] (skipped where
+// t + 1 == nseg and ring has no such entry), each step's IB data in its slot
+// of ib_ring, wrench rows if wrench != null.
+lbm_status segment_record(lbm_ctx *c, const void *ckpt, void *const *ring, int32_t nseg, int32_t nring,
+                          const lbm_markers *m, const float *poses, const lbm_frame *frames, void *ib_ring,
+                          float *wrench) {
   const RingSlot rs = ring_slot(&c->p);
   char *rbase = static_cast<char *>(ib_ring);
   const size_t pstride = m && m->n > 0 ? (size_t)m->nbones * 24 : 0;
-  auto state_of = [&](int t) -> void * { return t == 0 ? const_cast<void *>(ckpt) : ring[t - 1]; };
-  // recompute: state t+1 from state t, keeping each step's IB data in its slot
+  lbm_status st;
   for (int t = 0; t < nseg; ++t) {
     EnvView e = env_view(c, m);
-    e.f[0] = state_of(t);
-    e.f[1] = t + 1 < nseg ? ring[t] : nullptr;
+    e.f[0] = t == 0 ? const_cast<void *>(ckpt) : ring[t - 1];
+    e.f[1] = t < nring ? ring[t] : nullptr;
     point_at_slot(e, rs, rbase + rs.total * (size_t)t);
     const FrameF fr = frame_f(&frames[t]);
-    if (e.ib && (st = ib_forward(c, e, fr, poses + pstride * t)) != LBM_OK) return st;
-    if (t + 1 < nseg) {
+    float *wr = wrench ? wrench + 8 * (size_t)t : nullptr;
+    if (e.ib && (st = ib_forward(c, e, fr, poses + pstride * t, wr)) != LBM_OK) return st;
+    if (!e.ib && wr) {
+      k_fill_int<<<1, 64, 0, c->stream>>>(reinterpret_cast<int *>(wr), 0, 8);
+      if ((st = launched()) != LBM_OK) return st;
+    }
+    if (e.f[1]) {
       const int grid = e.nblocks;
       const dim3 blk = collide_block(c);
       if (e.g.xper)
@@ -775,7 +798,18 @@ lbm_status lbm_adjoint_segment(lbm_ctx *c, const void *ckpt, void *const *ring, 
       if ((st = launched()) != LBM_OK) return st;
     }
   }
-  // reverse sweep; the result lands in `lam` (an odd count starts from a copy)
+  return LBM_OK;
+}
+
+// Reverse passes over a recorded segment; the result lands in `lam` (an odd
+// count starts from a copy).
+lbm_status segment_sweep(lbm_ctx *c, const void *ckpt, void *const *ring, int32_t nseg, const lbm_markers *m,
+                         const lbm_frame *frames, const double *w, void *lam, void *lam_tmp, float *pose_bar,
+                         void *ib_ring) {
+  const RingSlot rs = ring_slot(&c->p);
+  char *rbase = static_cast<char *>(ib_ring);
+  lbm_status st;
+  auto state_of = [&](int t) -> void * { return t == 0 ? const_cast<void *>(ckpt) : ring[t - 1]; };
   const size_t lam_bytes = (size_t)27 * c->plane * sizeof(float);
   float *next = static_cast<float *>(lam), *prev = static_cast<float *>(lam_tmp);
   if (nseg & 1) {
@@ -806,6 +840,40 @@ lbm_status lbm_adjoint_segment(lbm_ctx *c, const void *ckpt, void *const *ring, 
     if ((st = launched()) != LBM_OK) return st;
   }
   return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_adjoint_segment(lbm_ctx *c, const void *ckpt, void *const *ring, int32_t nseg, const lbm_markers *m,
+                               const float *poses, const lbm_frame *frames, const double *w, void *lam,
+                               void *lam_tmp, float *pose_bar, void *ib_ring) {
+  if (!w || !lam || !lam_tmp || lam == lam_tmp) return LBM_ERR_ARG;
+  lbm_status st = segment_args_ok(c, ckpt, ring, nseg, nseg - 1, false, frames, lam, lam_tmp, ib_ring);
+  if (st != LBM_OK) return st;
+  if ((st = adjoint_request_ok(c, m, poses, w, pose_bar)) != LBM_OK) return st;
+  if ((st = segment_record(c, ckpt, ring, nseg, nseg - 1, m, poses, frames, ib_ring, nullptr)) != LBM_OK) return st;
+  return segment_sweep(c, ckpt, ring, nseg, m, frames, w, lam, lam_tmp, pose_bar, ib_ring);
+}
+
+lbm_status lbm_adjoint_record(lbm_ctx *c, const void *ckpt, void *const *ring, int32_t nseg, const lbm_markers *m,
+                              const float *poses, const lbm_frame *frames, void *ib_ring, float *wrench) {
+  lbm_status st = segment_args_ok(c, ckpt, ring, nseg, nseg, true, frames, nullptr, nullptr, ib_ring);
+  if (st != LBM_OK) return st;
+  static const double kNoWeights[4] = {0.0, 0.0, 0.0, 0.0};
+  if ((st = adjoint_request_ok(c, m, poses, kNoWeights, nullptr, false)) != LBM_OK) return st;
+  return segment_record(c, ckpt, ring, nseg, nseg, m, poses, frames, ib_ring, wrench);
+}
+
+lbm_status lbm_adjoint_sweep(lbm_ctx *c, const void *ckpt, void *const *ring, int32_t nseg, const lbm_markers *m,
+                             const float *poses, const lbm_frame *frames, const double *w, void *lam, void *lam_tmp,
+                             float *pose_bar, void *ib_ring) {
+  if (!w || !lam || !lam_tmp || lam == lam_tmp) return LBM_ERR_ARG;
+  lbm_status st = segment_args_ok(c, ckpt, ring, nseg, nseg - 1, false, frames, lam, lam_tmp, ib_ring);
+  if (st != LBM_OK) return st;
+  if ((st = adjoint_request_ok(c, m, poses, w, pose_bar)) != LBM_OK) return st;
+  return segment_sweep(c, ckpt, ring, nseg, m, frames, w, lam, lam_tmp, pose_bar, ib_ring);
 }
 
 lbm_status lbm_swimmer_init(const lbm_swimmer *s, lbm_swimmer_state *st, const double *vel0, double heading,

@@ -110,6 +110,8 @@ def lib():
         L.lbm_adjoint_ring_bytes.argtypes = [P, ctypes.c_int32]
         L.lbm_adjoint_ring_bytes.restype = sz
         L.lbm_adjoint_segment.argtypes = [vp, vp, vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.lbm_adjoint_sweep.argtypes = [vp, vp, vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.lbm_adjoint_record.argtypes = [vp, vp, vp, ctypes.c_int32, vp, vp, vp, vp, vp]
         L.lbm_check.argtypes = [vp]
         L.lbm_set_stream.argtypes = [vp, vp]
         L.lbm_profile_enable.argtypes = [vp, ctypes.c_int]
@@ -132,7 +134,8 @@ def lib():
         for name in ("lbm_init", "lbm_load_populations", "lbm_read_populations", "lbm_macros", "lbm_ib_step",
                      "lbm_body_forces", "lbm_check", "lbm_set_stream", "lbm_profile_enable",
                      "lbm_profile_collect", "lbm_state_save", "lbm_state_restore", "lbm_adjoint_step",
-                     "lbm_bind_populations", "lbm_adjoint_segment", "lbm_swimmer_init", "lbm_swimmer_prepare",
+                     "lbm_bind_populations", "lbm_adjoint_segment", "lbm_adjoint_sweep", "lbm_adjoint_record",
+                     "lbm_swimmer_init", "lbm_swimmer_prepare",
                      "lbm_swimmer_advance",
                      "lbm_batch_create", "lbm_batch_run", "lbm_batch_autotune",
                      "lbm_batch_set_shapes", "lbm_batch_check"):
@@ -349,9 +352,11 @@ class Simulation:
 
     def adjoint_segment(self, ckpt: torch.Tensor, ring, markers: Optional[DeviceMarkers],
                         poses: Optional[torch.Tensor], frames, weights, lam: torch.Tensor, lam_tmp: torch.Tensor,
-                        pose_bar: Optional[torch.Tensor], ib_ring: torch.Tensor):
+                        pose_bar: Optional[torch.Tensor], ib_ring: torch.Tensor, sweep_only: bool = False):
         """Native reverse sweep over len(frames) steps from checkpoint ckpt
-        (lbm_adjoint_segment): lam in = dJ/d(state after), out = dJ/d(ckpt)."""
+        (lbm_adjoint_segment): lam in = dJ/d(state after), out = dJ/d(ckpt).
+        sweep_only: the segment was recorded by adjoint_record into ring and
+        ib_ring (lbm_adjoint_sweep, no recompute)."""
         fr = frames_array(frames)
         nseg = fr.shape[0]
         assert len(ring) >= nseg - 1
@@ -360,10 +365,30 @@ class Simulation:
         ms = None if markers is None else markers.struct()
         if markers is not None:
             assert poses.is_contiguous() and pose_bar.is_contiguous() and poses.shape[0] >= nseg
-        _check(lib().lbm_adjoint_segment(self.ctx, _ptr(ckpt), ptrs, nseg, None if ms is None else ctypes.byref(ms),
-                                         _ptr(poses), fr.ctypes.data_as(ctypes.c_void_p),
-                                         wts.ctypes.data_as(ctypes.c_void_p), _ptr(lam), _ptr(lam_tmp),
-                                         _ptr(pose_bar), _ptr(ib_ring)), "lbm_adjoint_segment")
+        fn = lib().lbm_adjoint_sweep if sweep_only else lib().lbm_adjoint_segment
+        _check(fn(self.ctx, _ptr(ckpt), ptrs, nseg, None if ms is None else ctypes.byref(ms), _ptr(poses),
+                  fr.ctypes.data_as(ctypes.c_void_p), wts.ctypes.data_as(ctypes.c_void_p), _ptr(lam), _ptr(lam_tmp),
+                  _ptr(pose_bar), _ptr(ib_ring)), "lbm_adjoint_sweep" if sweep_only else "lbm_adjoint_segment")
+
+    def adjoint_record(self, ckpt: torch.Tensor, ring, markers: Optional[DeviceMarkers],
+                       poses: Optional[torch.Tensor], frames, ib_ring: torch.Tensor,
+                       wrench: Optional[torch.Tensor] = None):
+        """Forward over len(frames) steps from ckpt keeping every state
+        (ring[t] = state after step t; len(ring) == nsteps, the last entry may
+        be None) and every step's IB data in ib_ring (lbm_adjoint_record);
+        wrench (nsteps, 8) receives the step wrenches."""
+        fr = frames_array(frames)
+        nseg = fr.shape[0]
+        assert len(ring) == nseg
+        ptrs = (ctypes.c_void_p * nseg)(*[None if t is None else t.data_ptr() for t in ring])
+        ms = None if markers is None else markers.struct()
+        if markers is not None:
+            assert poses.is_contiguous() and poses.shape[0] >= nseg
+        if wrench is not None:
+            assert wrench.is_contiguous() and wrench.dtype == torch.float32 and wrench.shape[0] >= nseg
+        _check(lib().lbm_adjoint_record(self.ctx, _ptr(ckpt), ptrs, nseg, None if ms is None else ctypes.byref(ms),
+                                        _ptr(poses), fr.ctypes.data_as(ctypes.c_void_p), _ptr(ib_ring),
+                                        _ptr(wrench)), "lbm_adjoint_record")
 
     def check(self) -> int:
         return lib().lbm_check(self.ctx)

@@ -228,3 +228,27 @@ def test_adjoint_rejects_unsupported_configurations():
             sim.adjoint_step(s, dm, pose, w.frames[0], [1, 0, 0, 0], lam, lam2, pb)
         assert ei.value.code == lbm.ERR_UNSUPPORTED
         sim.close()
+
+
+def test_recorded_forward_and_sweep_match_checkpointed_run():
+    """Keeping every state (lbm_adjoint_record, then lbm_adjoint_sweep with
+    no recompute) against checkpoints every 5 steps with the segment
+    recompute: the same wrench rows, J, pose gradient, initial-state adjoint
+    and final context state, bit for bit."""
+    th = np.asarray(I.C5_BASE, dtype=np.float64)
+    a = AD.FinProblem(nsteps=NSTEPS, every=EVERY, **GEOM)
+    b = AD.FinProblem(nsteps=NSTEPS, every=EVERY, record=True, **GEOM)
+    Ja, ta = a.value(th)
+    Jb, tb = b.value(th)
+    say(f"J checkpointed {Ja:.10e} recorded {Jb:.10e}")
+    assert Ja == Jb
+    assert torch.equal(ta.wrench, tb.wrench)
+    assert torch.equal(a.sim.read_populations(), b.sim.read_populations())
+    pa, la = AD.backward(a.sim, a.markers, ta.poses, a.workload.frames, ta)
+    pb, lb = AD.backward(b.sim, b.markers, tb.poses, b.workload.frames, tb)
+    torch.cuda.synchronize()
+    say(f"pose gradient max |diff| {(pa - pb).abs().max().item():.3e}, lambda_0 max |diff| "
+        f"{(la - lb).abs().max().item():.3e}")
+    assert torch.equal(pa, pb) and torch.equal(la, lb)
+    a.close()
+    b.close()
