@@ -103,6 +103,8 @@ def test_adjoint_batch_and_state_calls_on_null_handles_fail_cleanly(L):
     w = (ctypes.c_double * 4)(0, 0, 0, 0)
     assert L.lbm_adjoint_step(None, None, None, None, None, w, None, None, None) == -1
     assert L.lbm_adjoint_segment(None, None, None, 1, None, None, None, w, None, None, None, None) == -1
+    assert L.lbm_adjoint_sweep(None, None, None, 1, None, None, None, w, None, None, None, None) == -1
+    assert L.lbm_adjoint_record(None, None, None, 1, None, None, None, None, None) == -1
     assert L.lbm_bind_populations(None, None, None) == -1
     assert L.lbm_state_save(None, None) == -1
     assert L.lbm_state_restore(None, None, 0) == -1
