@@ -252,3 +252,29 @@ def test_recorded_forward_and_sweep_match_checkpointed_run():
     assert torch.equal(pa, pb) and torch.equal(la, lb)
     a.close()
     b.close()
+
+
+def test_recorded_fluid_only_run_matches_checkpointed_run():
+    """No body (zero wrench rows, a terminal functional <c, s_N>): the
+    recorded forward and sweep give the checkpointed run's final state and
+    initial-state adjoint bit for bit."""
+    w = _fin()
+    sim = _sim(w, with_markers=False)
+    c = _smooth_perturbation(sim, w, torch.ones(sim.population_bytes // 4, device="cuda").view(torch.uint8),
+                             seed=9, amp=1.0)
+    s0 = sim.new_state()
+    sim.save_state(s0)
+    out = {}
+    for record in (False, True):
+        sim.bind_own_buffers()
+        sim.restore_state(s0, 0)
+        J, tape = AD.forward(sim, None, None, w.frames, np.zeros(4), every=EVERY, record=record)
+        final = sim.read_populations()
+        _, lam0 = AD.backward(sim, None, None, w.frames, tape, lam_final=c)
+        torch.cuda.synchronize()
+        out[record] = (J, tape.wrench.clone(), final, lam0.clone())
+    assert out[False][0] == out[True][0] == 0.0
+    assert torch.equal(out[False][1], out[True][1]) and not out[True][1].any()
+    assert torch.equal(out[False][2], out[True][2])
+    assert torch.equal(out[False][3], out[True][3])
+    sim.close()
