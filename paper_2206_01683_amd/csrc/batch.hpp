@@ -18,7 +18,8 @@
 //                    F32 storage and direct forcing only.
 // UNI = true: every environment is of collide kind 0 (open x faces, no
 // rotation, periodic y and z, BGK, F32), so the per-environment branches on
-// those flags compile away.
+// those flags compile away. The interpolation branches on rotation only, so
+// the per-phase driver takes its UNI template whenever no frame rotates.
 #pragma once
 
 #include "ib.hpp"

@@ -1062,6 +1062,7 @@ struct lbm_batch {
   bool uniform;            // every environment of collide kind 0 (open x, non-rotating, periodic y/z, BGK, F32)
   bool two_byte;           // some environment stores 2-byte populations (per-phase driver only)
   bool implicit;           // every environment uses the implicit correction (per-phase driver only)
+  bool still;              // no environment's frame rotates (the interpolation's only per-kind branch)
   int tot_cg;              // conjugate-gradient items over all environments
   bool dirty;
   hipGraph_t graph;
@@ -1182,12 +1183,19 @@ lbm_status batch_enqueue_t(lbm_batch *b, int nsteps, int mode) {
   int cap_items = 0;
   for (int e = 0; e < b->nenv; ++e) cap_items += b->views[e].cap;
   const int gdyn = std::max(8, std::min(cap_items * kSpreadSplit, 4096));
+  // interpolation branches per environment only on rotation
+  auto interp = [&](const BatchArgs &args, int s, int pass) {
+    if (UNI || b->still)
+      kb_interp<true><<<b->tot[PRE_INTERP], WG, 0, b->stream>>>(args, s, pass);
+    else
+      kb_interp<false><<<b->tot[PRE_INTERP], WG, 0, b->stream>>>(args, s, pass);
+  };
   for (int s = 0; s < nsteps; ++s) {
     kb_skin<<<b->tot[PRE_SKIN], WG, 0, b->stream>>>(a, s);
     kb_active<<<b->tot[PRE_ACTIVE], WG, 0, b->stream>>>(a);
     kb_macro<UNI><<<gdyn, WG, 0, b->stream>>>(a, s);
     if (b->implicit) {  // mdf = conjugate-gradient steps
-      kb_interp<UNI><<<b->tot[PRE_INTERP], WG, 0, b->stream>>>(a, s, 0);
+      interp(a, s, 0);
       kb_cg_init<<<b->tot_cg, kCgWG, 0, b->stream>>>(a, s);
       for (int j = 0; j < b->mdf; ++j) {
         const bool last = j == b->mdf - 1;
@@ -1199,7 +1207,7 @@ lbm_status batch_enqueue_t(lbm_batch *b, int nsteps, int mode) {
     } else {
       for (int pass = 0; pass < b->mdf; ++pass) {
         if (pass > 0) kb_spread<<<gdyn, WG, 0, b->stream>>>(a, s, 0);
-        kb_interp<UNI><<<b->tot[PRE_INTERP], WG, 0, b->stream>>>(a, s, pass);
+        interp(a, s, pass);
       }
     }
     kb_spread<<<gdyn, WG, 0, b->stream>>>(a, s, 1);
@@ -1269,12 +1277,14 @@ lbm_status lbm_batch_create(lbm_batch **out, const lbm_env *envs, int32_t nenv, 
   b->uniform = true;
   b->two_byte = false;
   b->implicit = envs[0].ctx->p.ib_scheme == LBM_IB_IMPLICIT;
+  b->still = true;
   for (int e = 0; e < nenv; ++e) {
     const lbm_params &q = envs[e].ctx->p;
     if (envs[e].rotating || q.bc_lo == LBM_BC_PERIODIC || q.bc_y[0] != LBM_BC_PERIODIC ||
         q.bc_z[0] != LBM_BC_PERIODIC || q.collision != LBM_COLLIDE_BGK || q.storage != LBM_STORE_F32)
       b->uniform = false;
     if (q.storage != LBM_STORE_F32) b->two_byte = true;
+    if (envs[e].rotating) b->still = false;
   }
   int dev_id = 0, cus = 0, per_cu[2] = {0, 0};
   if (hipGetDevice(&dev_id) != hipSuccess ||
