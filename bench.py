@@ -29,7 +29,8 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL = {"f32": 216, "f16": 108, "bf16": 108}
 METRIC = "MLUPS and % of HBM roofline per GPU; adjoint/forward time ratio"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "collide_traffic.txt")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2206_01683_amd", "csrc", f) for f in ("lattice.hpp", "fluid.hpp")]
+# the sources k_collide is compiled from (its lattice, storage, view of the context, and the kernel itself)
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2206_01683_amd", "csrc", f) for f in ("lattice.hpp", "env.hpp", "fluid.hpp")]
 
 
 def kernel_source_hash() -> str:
