@@ -131,7 +131,8 @@ def test_full_size_adjoint_gradient():
     interval: the 128x64x64 fin with 3,000 markers, J the time-averaged
     thrust, 40 steps in two checkpoint segments of 20. The 8-parameter
     gradient from the native reverse sweep against the FP64 oracle's
-    forward-mode tangent (one dual-number run per parameter)."""
+    forward-mode tangent (one dual-number run per parameter); and the run
+    recording every state (no recompute) bit for bit equal to it."""
     from paper_2206_01683_amd import adjoint as AD
     n, every = 40, 20
     prob = AD.FinProblem(nsteps=n, every=every)
@@ -154,3 +155,10 @@ def test_full_size_adjoint_gradient():
     assert abs(J - J64) <= 1e-5 * abs(J64)
     assert err < 1e-4
     prob.close()
+    # the same horizon recorded whole in HBM (no recompute): the same J and gradient, bit for bit
+    rec = AD.FinProblem(nsteps=n, every=every, record=True)
+    Jr, tr = rec.value(theta)
+    gr = rec.gradient(theta, tr)
+    say(f"full-size adjoint, recorded: J {Jr:.8e}; max |gradient - checkpointed| {np.abs(gr - g).max():.3e}")
+    assert Jr == J and np.array_equal(gr, g)
+    rec.close()
