@@ -278,3 +278,49 @@ def test_recorded_fluid_only_run_matches_checkpointed_run():
     assert torch.equal(out[False][2], out[True][2])
     assert torch.equal(out[False][3], out[True][3])
     sim.close()
+
+
+def test_record_and_sweep_reject_bad_arguments():
+    """Host-side checks of lbm_adjoint_record / lbm_adjoint_sweep, before any
+    launch: aliased ring entries, a ring entry that is the checkpoint, an
+    unaligned IB ring, a rotating frame, and configurations the adjoint does
+    not support."""
+    w = _fin(nsteps=4)
+    sim = _sim(w)
+    dm = lbm.DeviceMarkers(w.markers)
+    poses = torch.as_tensor(w.poses[:4].astype(np.float32), device="cuda")
+    ck = sim.new_state()
+    sim.save_state(ck)
+    ring = [sim.new_state() for _ in range(4)]
+    ib = sim.adjoint_ring(4)
+    lam = torch.zeros(sim.population_bytes // 4, device="cuda")
+    lam2 = torch.zeros_like(lam)
+    pb = torch.zeros((4, w.markers.nbones, 24), device="cuda")
+    bad = [
+        (lambda: sim.adjoint_record(ck, [ring[0], ring[0], ring[2], ring[3]], dm, poses, w.frames[:4], ib),
+         lbm.ERR_ARG),
+        (lambda: sim.adjoint_record(ck, [ring[0], ck, ring[2], None], dm, poses, w.frames[:4], ib), lbm.ERR_ARG),
+        (lambda: sim.adjoint_record(ck, [ring[0], ring[1], ring[2], None], dm, poses, w.frames[:4], ib[1:]),
+         lbm.ERR_ARG),
+        (lambda: sim.adjoint_segment(ck, [ring[0], ring[0], ring[2]], dm, poses, w.frames[:4], [1, 0, 0, 0], lam,
+                                     lam2, pb, ib, sweep_only=True), lbm.ERR_ARG),
+    ]
+    spin = w.frames[:4].copy()
+    spin[:, 3:6] = (0.0, 0.0, 1e-3)
+    bad.append((lambda: sim.adjoint_record(ck, ring, dm, poses, spin, ib), lbm.ERR_UNSUPPORTED))
+    bad.append((lambda: sim.adjoint_segment(ck, ring[:3], dm, poses, spin, [1, 0, 0, 0], lam, lam2, pb, ib,
+                                            sweep_only=True), lbm.ERR_UNSUPPORTED))
+    for j, (call, code) in enumerate(bad):
+        with pytest.raises(lbm.LBMError) as ei:
+            call()
+        assert ei.value.code == code, j
+    torch.cuda.synchronize()
+    assert sim.check() == 0
+    sim.close()
+    f16 = _sim(w, storage="f16")
+    s16 = f16.new_state()
+    f16.save_state(s16)
+    with pytest.raises(lbm.LBMError) as ei:
+        f16.adjoint_record(s16, [f16.new_state() for _ in range(4)], dm, poses, w.frames[:4], f16.adjoint_ring(4))
+    assert ei.value.code == lbm.ERR_UNSUPPORTED
+    f16.close()
