@@ -33,8 +33,10 @@
 // Lattice sweeps are parallel over z with OpenMP; per-node arithmetic does
 // not depend on the thread count. Marker sums are sequential in marker order.
 //
-// Parity pins: see tests/test_oracle_*.py. Nothing here is "parity unpinned"
-// except the fish thrust and power series, which have no closed form.
+// Parity pins: see tests/test_oracle_*.py (the power term and the open faces'
+// outflow and density extrapolation in tests/test_oracle_pins.py). Nothing
+// here is "parity unpinned" except the fish thrust and power series, which
+// have no closed form.
 
 #include <cmath>
 #include <cstdint>
