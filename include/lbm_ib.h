@@ -203,6 +203,28 @@ size_t lbm_workspace_bytes(const lbm_params *p);
 lbm_status lbm_init(lbm_ctx **out, const lbm_params *p, void *f_a, void *f_b, void *workspace,
                     const float *rho0, const float *u0, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): lbm_init
+ * without a caller workspace. The context's workspace is a fixed array of
+ * LBM_STATIC_WORKSPACE_BYTES (64 MiB) that the library holds on each device
+ * it runs on until the process ends; the context itself is a per-device slot
+ * of the library, so this call allocates no memory of any kind. Arguments as
+ * lbm_init (f_a, f_b, rho0, u0, hip_stream) on the current device.
+ * Errors: LBM_ERR_CAPACITY if lbm_workspace_bytes(p) exceeds
+ * LBM_STATIC_WORKSPACE_BYTES (lower max_markers or max_active_tiles);
+ * LBM_ERR_ARG as lbm_init; LBM_ERR_DEVICE if the runtime cannot resolve the
+ * array on this device.
+ * Sharing: every context created this way on one device is the same slot and
+ * uses the same workspace. A second call on a device re-initialises that slot
+ * for its own problem (the earlier handle then refers to the new one), and
+ * calls that overlap in time on one device race. The workspace keeps the
+ * last call's contents; this call clears every part of it that must start
+ * cleared. lbm_destroy on such a context frees nothing. All other entry
+ * points accept it as any context. */
+#define LBM_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+lbm_status lbm_init_static(lbm_ctx **out, const lbm_params *p, void *f_a, void *f_b, const float *rho0,
+                           const float *u0, void *hip_stream);
+
 /* Replace the state with caller populations f [27][nz][ny][nx] (canonical
  * pre-collision layout). */
 lbm_status lbm_load_populations(lbm_ctx *c, const float *f);

@@ -11,6 +11,7 @@
 #include <array>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <utility>
 #include <vector>
@@ -135,6 +136,7 @@ struct lbm_ctx {
   int64_t steps;
   uint32_t plane;
   bool slots_dirty;
+  bool is_static;  // created by lbm_init_static: workspace in `scratch`, not freed by lbm_destroy
   int bx, by;
   // measurement hook: 3 events per timed step (start, after IB, after collide)
   bool prof;
@@ -466,6 +468,66 @@ bool markers_ok(const lbm_ctx *c, const lbm_markers *m) {
   return true;
 }
 
+// Fill a context for parameters p (already validated) bound to the caller's
+// population buffers and to workspace ws, and queue the initial state.
+lbm_status setup_ctx(lbm_ctx *c, const lbm_params *p, void *f_a, void *f_b, char *ws, const float *rho0,
+                     const float *u0, void *hip_stream) {
+  c->p = *p;
+  c->L = layout(p);
+  c->f[0] = f_a;
+  c->f[1] = f_b;
+  c->cur = 0;
+  c->ws = ws;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->steps = 0;
+  c->plane = plane_elems(p);
+  c->slots_dirty = false;
+  c->is_static = false;
+  c->prof = false;
+  c->prof_used = 0;
+  // collide block: 64-multiple along x covering as much of a row as fits
+  int bx = p->block_x, by = p->block_y;
+  if (bx == 0) bx = p->nx >= 128 ? 128 : 64;
+  if (by == 0) by = std::max(1, 512 / bx);
+  c->bx = bx;
+  c->by = by;
+  // every workspace field that must start cleared, by kernels (no memset
+  // nodes, so the sequence can sit in a captured graph)
+  k_fill_int<<<256, 256, 0, c->stream>>>(wsp<int>(c, c->L.tile_flag), 0, c->L.ntiles);
+  k_fill_int<<<256, 256, 0, c->stream>>>(wsp<int>(c, c->L.tile_slot), -1, c->L.ntiles);
+  k_fill_int<<<1, 64, 0, c->stream>>>(wsp<int>(c, c->L.guard), 0, 16);
+  k_fill_int<<<1, 64, 0, c->stream>>>(wsp<int>(c, c->L.counters), 0, 16);
+  lbm_status st = launched();
+  if (st != LBM_OK) return st;
+  return LBM_BY_STORAGE(c, init_eq, rho0, u0);
+}
+
+// Workspace of the contexts lbm_init_static creates: one array per device
+// (each GPU the library runs on holds its own copy until the process ends),
+// shared by every such context on that device. Host code reaches it only
+// through the address hipGetSymbolAddress returns for the current device;
+// the array's name in host code is not a device address.
+constexpr size_t kStaticWorkspaceBytes = LBM_STATIC_WORKSPACE_BYTES;
+constexpr int kMaxStaticDevices = 64;
+__device__ __align__(256) char scratch[kStaticWorkspaceBytes];
+
+char *g_scratch_ptr[kMaxStaticDevices];
+lbm_ctx g_static_ctx[kMaxStaticDevices];
+std::mutex g_scratch_mu;
+
+// Device address of `scratch` on device dev (the current device), looked up
+// once per device; null if the runtime cannot resolve it.
+char *static_workspace(int dev) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    if (reinterpret_cast<uintptr_t>(ptr) % 256 != 0) return nullptr;
+    g_scratch_ptr[dev] = static_cast<char *>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 extern "C" {
@@ -487,33 +549,29 @@ lbm_status lbm_init(lbm_ctx **out, const lbm_params *p, void *f_a, void *f_b, vo
   *out = nullptr;
   lbm_ctx *c = new (std::nothrow) lbm_ctx;
   if (!c) return LBM_ERR_ARG;
-  c->p = *p;
-  c->L = layout(p);
-  c->f[0] = f_a;
-  c->f[1] = f_b;
-  c->cur = 0;
-  c->ws = static_cast<char *>(workspace);
-  c->stream = static_cast<hipStream_t>(hip_stream);
-  c->steps = 0;
-  c->plane = plane_elems(p);
-  c->slots_dirty = false;
-  c->prof = false;
-  c->prof_used = 0;
-  // collide block: 64-multiple along x covering as much of a row as fits
-  int bx = p->block_x, by = p->block_y;
-  if (bx == 0) bx = p->nx >= 128 ? 128 : 64;
-  if (by == 0) by = std::max(1, 512 / bx);
-  c->bx = bx;
-  c->by = by;
-  lbm_status st;
-  k_fill_int<<<256, 256, 0, c->stream>>>(wsp<int>(c, c->L.tile_flag), 0, c->L.ntiles);
-  k_fill_int<<<256, 256, 0, c->stream>>>(wsp<int>(c, c->L.tile_slot), -1, c->L.ntiles);
-  k_fill_int<<<1, 64, 0, c->stream>>>(wsp<int>(c, c->L.guard), 0, 16);
-  k_fill_int<<<1, 64, 0, c->stream>>>(wsp<int>(c, c->L.counters), 0, 16);
-  if ((st = launched()) != LBM_OK || (st = LBM_BY_STORAGE(c, init_eq, rho0, u0)) != LBM_OK) {
+  const lbm_status st = setup_ctx(c, p, f_a, f_b, static_cast<char *>(workspace), rho0, u0, hip_stream);
+  if (st != LBM_OK) {
     delete c;
     return st;
   }
+  *out = c;
+  return LBM_OK;
+}
+
+lbm_status lbm_init_static(lbm_ctx **out, const lbm_params *p, void *f_a, void *f_b, const float *rho0,
+                           const float *u0, void *hip_stream) {
+  if (!out || !params_ok(p) || !f_a || !f_b || f_a == f_b) return LBM_ERR_ARG;
+  *out = nullptr;
+  if (layout(p).total > kStaticWorkspaceBytes) return LBM_ERR_CAPACITY;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return LBM_ERR_DEVICE;
+  if (dev < 0 || dev >= kMaxStaticDevices) return LBM_ERR_UNSUPPORTED;
+  char *ws = static_workspace(dev);
+  if (!ws) return LBM_ERR_DEVICE;
+  lbm_ctx *c = &g_static_ctx[dev];
+  const lbm_status st = setup_ctx(c, p, f_a, f_b, ws, rho0, u0, hip_stream);
+  c->is_static = true;
+  if (st != LBM_OK) return st;
   *out = c;
   return LBM_OK;
 }
@@ -1039,6 +1097,10 @@ const char *lbm_strerror(lbm_status s) {
 
 void lbm_destroy(lbm_ctx *c) {
   if (!c) return;
+  if (c->is_static) {  // a per-device slot: keep it (and its events) for the next lbm_init_static
+    c->prof = false;
+    return;
+  }
   for (auto &e : c->ev) (void)hipEventDestroy(e);
   delete c;
 }

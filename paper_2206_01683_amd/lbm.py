@@ -24,6 +24,7 @@ STATUS = {0: "LBM_OK", -1: "LBM_ERR_ARG", -2: "LBM_ERR_DEVICE", -3: "LBM_ERR_UNS
 BC_PERIODIC, BC_VELOCITY, BC_OUTFLOW = 0, 1, 2
 OK, ERR_ARG, ERR_DEVICE, ERR_UNSTABLE, ERR_MARKER_RANGE, ERR_CAPACITY, ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
+STATIC_WORKSPACE_BYTES = 64 << 20  # LBM_STATIC_WORKSPACE_BYTES
 IB_DIRECT, IB_IMPLICIT = 0, 1
 COLLIDE_BGK, COLLIDE_TRT = 0, 1
 WALL_NO_SLIP, WALL_SLIP = 0, 1
@@ -95,6 +96,7 @@ def lib():
         L.lbm_workspace_bytes.argtypes = [P]
         L.lbm_workspace_bytes.restype = sz
         L.lbm_init.argtypes = [ctypes.POINTER(vp), P, vp, vp, vp, vp, vp, vp]
+        L.lbm_init_static.argtypes = [ctypes.POINTER(vp), P, vp, vp, vp, vp, vp]
         L.lbm_load_populations.argtypes = [vp, vp]
         L.lbm_read_populations.argtypes = [vp, vp]
         L.lbm_macros.argtypes = [vp, vp, vp, vp]
@@ -131,8 +133,8 @@ def lib():
         L.lbm_strerror.restype = ctypes.c_char_p
         L.lbm_destroy.argtypes = [vp]
         L.lbm_destroy.restype = None
-        for name in ("lbm_init", "lbm_load_populations", "lbm_read_populations", "lbm_macros", "lbm_ib_step",
-                     "lbm_body_forces", "lbm_check", "lbm_set_stream", "lbm_profile_enable",
+        for name in ("lbm_init", "lbm_init_static", "lbm_load_populations", "lbm_read_populations", "lbm_macros",
+                     "lbm_ib_step", "lbm_body_forces", "lbm_check", "lbm_set_stream", "lbm_profile_enable",
                      "lbm_profile_collect", "lbm_state_save", "lbm_state_restore", "lbm_adjoint_step",
                      "lbm_bind_populations", "lbm_adjoint_segment", "lbm_adjoint_sweep", "lbm_adjoint_record",
                      "lbm_swimmer_init", "lbm_swimmer_prepare",
@@ -205,12 +207,18 @@ class DeviceMarkers:
 
 
 class Simulation:
-    """One lattice with its two population buffers and workspace (torch-owned)."""
+    """One lattice with its two population buffers and workspace (torch-owned).
+
+    static_workspace=True creates the context with lbm_init_static: no
+    workspace tensor; the library's per-device static workspace is used
+    (shared by every such Simulation on the device, so only the latest one
+    is usable)."""
 
     def __init__(self, nx, ny, nz, tau, bc_lo=BC_PERIODIC, bc_hi=BC_PERIODIC, storage="f32", max_markers=0,
                  max_bones=1, mdf_iters=1, ib_alpha=1.0, rho0=None, u0=None, device="cuda", block=(0, 0),
                  max_active_tiles=0, stream=None, with_adjoint=False, bc_y=(BC_PERIODIC, BC_PERIODIC),
-                 bc_z=(BC_PERIODIC, BC_PERIODIC), ib_scheme=0, collision=0, trt_lambda=TRT_MAGIC, wall_mode=0):
+                 bc_z=(BC_PERIODIC, BC_PERIODIC), ib_scheme=0, collision=0, trt_lambda=TRT_MAGIC, wall_mode=0,
+                 static_workspace=False):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the lattice Boltzmann library runs only on the GPU")
         L = lib()
@@ -227,17 +235,26 @@ class Simulation:
         self.workspace_bytes = wb
         self.fa = torch.empty(pb, dtype=torch.uint8, device=self.device)
         self.fb = torch.empty(pb, dtype=torch.uint8, device=self.device)
-        self._ws_raw = torch.empty(wb + 256, dtype=torch.uint8, device=self.device)
-        shift = (-self._ws_raw.data_ptr()) % 256
-        self.ws = self._ws_raw[shift:shift + wb]
+        self.static_workspace = bool(static_workspace)
+        if self.static_workspace:
+            self.ws = None
+        else:
+            self._ws_raw = torch.empty(wb + 256, dtype=torch.uint8, device=self.device)
+            shift = (-self._ws_raw.data_ptr()) % 256
+            self.ws = self._ws_raw[shift:shift + wb]
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         rho0_t = None if rho0 is None else self._dev_f32(rho0)
         u0_t = None if u0 is None else self._dev_f32(u0)
         ctx = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            _check(L.lbm_init(ctypes.byref(ctx), ctypes.byref(self.params), _ptr(self.fa), _ptr(self.fb),
-                              _ptr(self.ws), _ptr(rho0_t), _ptr(u0_t), ctypes.c_void_p(self.stream.cuda_stream)),
-                   "lbm_init")
+            if self.static_workspace:
+                _check(L.lbm_init_static(ctypes.byref(ctx), ctypes.byref(self.params), _ptr(self.fa),
+                                         _ptr(self.fb), _ptr(rho0_t), _ptr(u0_t),
+                                         ctypes.c_void_p(self.stream.cuda_stream)), "lbm_init_static")
+            else:
+                _check(L.lbm_init(ctypes.byref(ctx), ctypes.byref(self.params), _ptr(self.fa), _ptr(self.fb),
+                                  _ptr(self.ws), _ptr(rho0_t), _ptr(u0_t), ctypes.c_void_p(self.stream.cuda_stream)),
+                       "lbm_init")
         self.ctx = ctx
         self._keep = [rho0_t, u0_t]
 

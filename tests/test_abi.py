@@ -128,3 +128,28 @@ def test_implicit_scheme_workspace_holds_its_buffers(L):
     extra = L.lbm_workspace_bytes(ctypes.byref(i)) - L.lbm_workspace_bytes(ctypes.byref(d))
     assert extra >= 256 * 1536 * 8 + 12 * 3000 * 4
     assert extra < 256 * 1536 * 8 + 12 * 3000 * 4 + 64 * 1024
+
+
+def test_static_init_validates_on_the_host(L):
+    """lbm_init_static (no caller workspace) refuses bad arguments, and a
+    problem whose workspace exceeds the static array, before any device call."""
+    ctx = ctypes.c_void_p()
+    bad = lbm.make_params(16, 16, 16, 0.5)
+    assert L.lbm_init_static(ctypes.byref(ctx), ctypes.byref(bad), ctypes.c_void_p(512), ctypes.c_void_p(1024),
+                             None, None, None) == -1
+    ok = lbm.make_params(16, 16, 16, 0.6)
+    assert L.lbm_init_static(ctypes.byref(ctx), ctypes.byref(ok), None, ctypes.c_void_p(1024), None, None,
+                             None) == -1
+    assert L.lbm_init_static(ctypes.byref(ctx), ctypes.byref(ok), ctypes.c_void_p(512), ctypes.c_void_p(512),
+                             None, None, None) == -1
+    assert L.lbm_init_static(None, ctypes.byref(ok), ctypes.c_void_p(512), ctypes.c_void_p(1024), None, None,
+                             None) == -1
+    big = lbm.make_params(384, 192, 192, 0.6, lbm.BC_VELOCITY, lbm.BC_OUTFLOW, max_markers=12000, max_bones=10)
+    assert L.lbm_workspace_bytes(ctypes.byref(big)) > lbm.STATIC_WORKSPACE_BYTES
+    assert L.lbm_init_static(ctypes.byref(ctx), ctypes.byref(big), ctypes.c_void_p(512), ctypes.c_void_p(1024),
+                             None, None, None) == lbm.ERR_CAPACITY
+    assert not ctx.value
+    # the fish fits once its active tiles are bounded
+    fish = lbm.make_params(384, 192, 192, 0.6, lbm.BC_VELOCITY, lbm.BC_OUTFLOW, max_markers=12000, max_bones=10,
+                           max_active_tiles=1024)
+    assert L.lbm_workspace_bytes(ctypes.byref(fish)) <= lbm.STATIC_WORKSPACE_BYTES
