@@ -76,8 +76,7 @@ enum { LBM_BC_PERIODIC = 0, LBM_BC_VELOCITY = 1, LBM_BC_OUTFLOW = 2 };
  * rounding of stored values scales with |h|, not with w_i; all arithmetic
  * and all immersed-boundary sums stay in float32. The stored layout of a
  * state (lbm_state_save) holds, at cell x, h_i(x + c_i) of the post-collision
- * populations, 27 planes of plane stride elements (lbm_population_bytes / 27
- * / element size). */
+ * populations, arranged as lbm_params.layout says (LBM_LAYOUT_*). */
 enum { LBM_STORE_F32 = 0, LBM_STORE_F16 = 1, LBM_STORE_BF16 = 2 };
 
 /* Immersed-boundary schemes (lbm_params.ib_scheme).
@@ -132,6 +131,18 @@ enum { LBM_COLLIDE_BGK = 0, LBM_COLLIDE_TRT = 1 };
  *   LBM_ERR_UNSUPPORTED. */
 enum { LBM_WALL_NO_SLIP = 0, LBM_WALL_SLIP = 1 };
 
+/* Stored population layout (lbm_params.layout). Population i of cell
+ * (x, y, z) sits at element (z ny + y) rs + i ps + x of a population buffer;
+ * lbm_population_strides gives ps and rs.
+ * PLANES: [27][nz][ny][nx], each population a plane of its own
+ *   (ps = plane stride, rs = nx).
+ * ROWS: [nz][ny][27][nx], the 27 populations of one (y, z) row side by side
+ *   (ps = nx, rs = 27 nx). A step then touches 9 source rows and 1 target
+ *   row per cell instead of 27 + 27 planes, which streams faster from HBM.
+ * AUTO: ROWS when nx is a multiple of 32 (every row starts on a 128-byte
+ *   line), else PLANES. */
+enum { LBM_LAYOUT_AUTO = 0, LBM_LAYOUT_PLANES = 1, LBM_LAYOUT_ROWS = 2 };
+
 typedef struct lbm_ctx lbm_ctx;
 
 /* [host] Problem description. */
@@ -143,7 +154,10 @@ typedef struct {
   int32_t max_bones;         /* capacity of a pose array, >= 1 */
   int32_t mdf_iters;         /* IB passes, 1..16: direct-forcing passes (1 = explicit), or CG steps */
   int32_t max_active_tiles;  /* 8x8x8 tiles that may carry IB force; 0 = automatic */
-  int32_t block_x, block_y;  /* collide kernel block shape; 0 = default */
+  int32_t block_x, block_y;  /* collide block: block_x (a multiple of 64) by block_y cells, or block_x
+                                consecutive cells of the x-fastest order when block_y = -1;
+                                0, 0 = default (256 consecutive cells with LBM_LAYOUT_ROWS,
+                                else 128 x 4 or 64 x 8) */
   int32_t with_adjoint;      /* nonzero: workspace also holds the adjoint buffers */
   double tau;                /* BGK relaxation time, > 1/2 (nu = (tau - 1/2)/3) */
   double ib_alpha;           /* direct-forcing gain, > 0 (1 = full correction) */
@@ -152,6 +166,7 @@ typedef struct {
   int32_t collision;         /* LBM_COLLIDE_*; 0 = BGK */
   double trt_lambda;         /* TRT: (tau - 1/2)(tau- - 1/2) > 0; unused by BGK */
   int32_t wall_mode;         /* LBM_WALL_*; 0 = no-slip */
+  int32_t layout;            /* LBM_LAYOUT_*; 0 = automatic */
 } lbm_params;
 
 /* [host] Frame of one step (Eq. (3)). acc = linear acceleration of the frame
@@ -192,6 +207,11 @@ typedef struct {
  * these parameters. 0 if the parameters are invalid. */
 size_t lbm_population_bytes(const lbm_params *p);
 size_t lbm_workspace_bytes(const lbm_params *p);
+
+/* [host] strides[0] = ps, strides[1] = rs (elements) of the stored layout
+ * these parameters select (see LBM_LAYOUT_*); strides[2] = 1 for ROWS, 0 for
+ * PLANES. LBM_ERR_ARG if the parameters are invalid or strides is NULL. */
+lbm_status lbm_population_strides(const lbm_params *p, int64_t *strides);
 
 /* Create a context bound to caller buffers f_a, f_b (lbm_population_bytes
  * each), workspace (lbm_workspace_bytes, 256-byte aligned) and a HIP stream

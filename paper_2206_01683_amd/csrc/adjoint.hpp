@@ -39,8 +39,8 @@ struct AdjArgs {
   float wF[3];                        // objective weight on the fluid force on the body
   float wP;                           // objective weight on the power
   float a0[3];                        // frame acceleration term a0 = -acc (uniform: no rotation)
-  const float *__restrict__ lam_next;  // [27][plane]
-  float *__restrict__ lam_prev;        // [27][plane]
+  const float *__restrict__ lam_next;  // in the population layout (GridArgs)
+  float *__restrict__ lam_prev;        // in the population layout
   float *__restrict__ gbar;            // [cap][3][512]
   unsigned long long *__restrict__ adjfix;  // [cap][4][512]: spread rhobar, U*bar (fixed point)
   float *__restrict__ mbar;            // [6][n]: Xbar (3), Ubar (3)
@@ -168,9 +168,11 @@ __device__ inline void adj_face(const float lamb[Q], float rho, const float m[3]
   rhobar -= q * ir * ir;
 }
 
-__device__ inline void load_lam(const float *__restrict__ lam, uint32_t plane, uint32_t o, float l[Q]) {
+// lam (in the population layout) of every direction at x in row `row`
+__device__ inline void load_lam(const float *__restrict__ lam, const GridArgs &g, uint32_t row, int x, float l[Q]) {
+  const float *__restrict__ p = lam + pop_idx(g, 0, row, (uint32_t)x);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) l[i] = lam[(size_t)i * plane + o];
+  for (int i = 0; i < Q; ++i) l[i] = p[(size_t)i * g.ps];
 }
 
 // ------------------------------------------------------------------ pass 1 --
@@ -187,21 +189,20 @@ __device__ inline void adj_gbar_item(const EnvView &e, const AdjArgs &A, int slo
     const int xm = g.xper ? wrap_idx(x - 1, g.nx) : x - 1;
     const int xp = g.xper ? wrap_idx(x + 1, g.nx) : x + 1;
     float f[Q];
-    pull27<StoreF32>(src, g.plane, g.nx, g.ny, xm, x, xp, wrap_idx(y - 1, g.ny), y, wrap_idx(y + 1, g.ny),
+    pull27<StoreF32>(src, g, xm, x, xp, wrap_idx(y - 1, g.ny), y, wrap_idx(y + 1, g.ny),
                      wrap_idx(z - 1, g.nz), z, wrap_idx(z + 1, g.nz), f);
     float rho, m[3];
     moments(f, rho, m[0], m[1], m[2]);
     float gg[3];
     load_g(g, e.tile_slot, e.gfix, x, y, z, gg[0], gg[1], gg[2]);
-    const uint32_t o = ((uint32_t)z * g.ny + y) * g.nx + x;
+    const uint32_t row = (uint32_t)z * g.ny + y;
     float lam[Q];
-    load_lam(A.lam_next, g.plane, o, lam);
+    load_lam(A.lam_next, g, row, x, lam);
     float rb, mb[3];
     adj_collide_node(lam, rho, m, gg, A, e.inv_tau, e.pref, rb, mb, gb);
     if (!g.xper && (x == 1 || x == g.nx - 2)) {
       const bool lo = x == 1;
-      const uint32_t ob = ((uint32_t)z * g.ny + y) * g.nx + (lo ? 0 : g.nx - 1);
-      load_lam(A.lam_next, g.plane, ob, lam);
+      load_lam(A.lam_next, g, row, lo ? 0 : g.nx - 1, lam);
       float rb2, mb2[3], gb2[3];
       adj_face(lam, rho, m, gg, lo ? A.bc_u_lo : A.bc_u_hi, (lo ? g.bc_lo : g.bc_hi) == 1, A, e.omt, e.pref, rb2,
                mb2, gb2);
@@ -400,7 +401,7 @@ __device__ inline void adj_collide_cell(const EnvView &e, const AdjArgs &A, int 
   const int yp = y == g.ny - 1 ? 0 : y + 1;
   const int zm = z == 0 ? g.nz - 1 : z - 1;
   const int zp = z == g.nz - 1 ? 0 : z + 1;
-  const uint32_t o = ((uint32_t)z * g.ny + y) * g.nx + x;
+  const uint32_t row = (uint32_t)z * g.ny + y;
   float fb[Q];
   const bool face = !XPER && (x == 0 || x == g.nx - 1);
   if (face) {
@@ -416,13 +417,13 @@ __device__ inline void adj_collide_cell(const EnvView &e, const AdjArgs &A, int 
       xp = x + 1;
     }
     float f[Q];
-    pull27<StoreF32>(src, g.plane, g.nx, g.ny, xm, x, xp, ym, y, yp, zm, z, zp, f);
+    pull27<StoreF32>(src, g, xm, x, xp, ym, y, yp, zm, z, zp, f);
     float rho, m[3];
     moments(f, rho, m[0], m[1], m[2]);
     float gg[3];
     load_g(g, e.ib ? e.tile_slot : nullptr, e.gfix, x, y, z, gg[0], gg[1], gg[2]);
     float lam[Q];
-    load_lam(A.lam_next, g.plane, o, lam);
+    load_lam(A.lam_next, g, row, x, lam);
     float rb, mb[3], gb[3];
     adj_collide_node(lam, rho, m, gg, A, e.inv_tau, e.pref, rb, mb, gb);
 #pragma unroll
@@ -455,10 +456,10 @@ __device__ inline void adj_collide_cell(const EnvView &e, const AdjArgs &A, int 
       const bool lo = x == 1;
       const float *fp = A.facebuf + (size_t)(lo ? 0 : 1) * 4 * nyz;
       const float rF = fp[yz], m0 = fp[nyz + yz], m1 = fp[2 * nyz + yz], m2 = fp[3 * nyz + yz];
-      const uint32_t ob = (uint32_t)yz * g.nx + (lo ? 0 : g.nx - 1);
+      const float *__restrict__ lb_ = A.lam_next + pop_idx(g, 0, (uint32_t)yz, lo ? 0 : g.nx - 1);
 #pragma unroll
       for (int i = 0; i < Q; ++i)
-        fb[i] += e.omt * A.lam_next[(size_t)i * g.plane + ob] + rF + (float)cx_of(i) * m0 + (float)cy_of(i) * m1 +
+        fb[i] += e.omt * lb_[(size_t)i * g.ps] + rF + (float)cx_of(i) * m0 + (float)cy_of(i) * m1 +
                  (float)cz_of(i) * m2;
     }
   }
@@ -473,15 +474,15 @@ __device__ inline void adj_collide_cell(const EnvView &e, const AdjArgs &A, int 
     } else if (tx_ < 0 || tx_ >= g.nx) {
       continue;
     }
-    const uint32_t ot = ((uint32_t)zz[cz_of(i) + 1] * g.ny + yy[cy_of(i) + 1]) * g.nx + tx_;
-    __builtin_nontemporal_store(fb[i], A.lam_prev + (size_t)i * g.plane + ot);
+    const uint32_t trow = (uint32_t)zz[cz_of(i) + 1] * g.ny + yy[cy_of(i) + 1];
+    __builtin_nontemporal_store(fb[i], A.lam_prev + pop_idx(g, i, trow, (uint32_t)tx_));
   }
   if (face) {
     // entries of this face node pulled by no node: c_x pointing out of the domain
     const int cxo = x == 0 ? -1 : 1;
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-      if (cx_of(i) == cxo) A.lam_prev[(size_t)i * g.plane + o] = 0.f;
+      if (cx_of(i) == cxo) A.lam_prev[pop_idx(g, i, row, (uint32_t)x)] = 0.f;
   }
 }
 
@@ -503,13 +504,13 @@ __device__ inline void adj_face_item(const EnvView &e, const AdjArgs &A, int id)
   const int zm = z == 0 ? g.nz - 1 : z - 1;
   const int zp = z == g.nz - 1 ? 0 : z + 1;
   float f[Q];
-  pull27<StoreF32>(src, g.plane, g.nx, g.ny, x - 1, x, x + 1, ym, y, yp, zm, z, zp, f);
+  pull27<StoreF32>(src, g, x - 1, x, x + 1, ym, y, yp, zm, z, zp, f);
   float rho, m[3];
   moments(f, rho, m[0], m[1], m[2]);
   float gg[3];
   load_g(g, e.ib ? e.tile_slot : nullptr, e.gfix, x, y, z, gg[0], gg[1], gg[2]);
   float lam[Q];
-  load_lam(A.lam_next, g.plane, (uint32_t)yz * g.nx + (lo ? 0 : g.nx - 1), lam);
+  load_lam(A.lam_next, g, (uint32_t)yz, lo ? 0 : g.nx - 1, lam);
   float rb, mb[3], gb[3];
   adj_face(lam, rho, m, gg, lo ? A.bc_u_lo : A.bc_u_hi, (lo ? g.bc_lo : g.bc_hi) == 1, A, e.omt, e.pref, rb, mb, gb);
   float *fp = A.facebuf + (size_t)side * 4 * nyz;

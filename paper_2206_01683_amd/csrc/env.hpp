@@ -9,7 +9,12 @@ namespace lbmib {
 
 struct GridArgs {
   int nx, ny, nz;
-  uint32_t plane;  // elements per population plane
+  uint32_t plane;  // a population buffer holds 27 * plane elements
+  // Population layout: element (i, x, y, z) at row * rs + i * ps + x with
+  // row = z * ny + y. Planes: ps = plane, rs = nx ([27][nz][ny][nx], each
+  // population a plane of its own). Rows: ps = nx, rs = 27 * nx
+  // ([nz][ny][27][nx], the 27 populations of one (y, z) row side by side).
+  uint32_t ps, rs;
   int xper;        // 1: x periodic
   int bc_lo, bc_hi;
   int tnx, tny;    // 8^3 tile grid (x, y extents)
@@ -60,6 +65,11 @@ struct EnvView {
   int rot;               // some frame rotates
   int cur0;              // buffer holding the state at the start of the run
 };
+
+// Element offset of population i at x in row `row` (= z * ny + y).
+__device__ inline size_t pop_idx(const GridArgs &g, int i, uint32_t row, uint32_t x) {
+  return (size_t)row * g.rs + (size_t)i * g.ps + x;
+}
 
 // Cell of thread (tx, ty) in logical collide block lb. Tile shapes bx x by
 // cover x-rows and y in 2-D blocks (z from the block index); the linear shape

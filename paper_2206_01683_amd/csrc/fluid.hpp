@@ -1,11 +1,11 @@
 // Lattice Boltzmann kernels: the fused pull-stream + collide step and the
 // state conversion kernels.
 //
-// State layout: two buffers of 27 population planes, each plane
-// `plane` elements long (nx*ny*nz rounded up), x fastest. A buffer holds the
-// post-collision values f*(x, n-1), stored as deviations f* - w_i; the
-// pre-collision state of step n is the pull f_i(x, n) = f*_i(x - c_i, n-1).
-// One step reads the current buffer and writes the other.
+// State layout: two buffers of 27 populations per cell (planes or rows, see
+// GridArgs), x fastest. A buffer holds the post-collision values f*(x, n-1),
+// stored as deviations f* - w_i; the pre-collision state of step n is the
+// pull f_i(x, n) = f*_i(x - c_i, n-1). One step reads the current buffer and
+// writes the other.
 #pragma once
 
 #include "env.hpp"
@@ -15,19 +15,19 @@ namespace lbmib {
 // Pull the 27 pre-collision populations of node (xs, y, z): f_i with
 // DEV = false, the deviations h_i = f_i - w_i with DEV = true. The x
 // neighbour indices xm/xp are given by the caller (periodic wrap or interior
-// node). Plane offsets i * plane are 64-bit (27 planes of a large lattice pass
-// 2^32 elements); a cell's offset within a plane is 32-bit (cells < 2^31).
+// node). Offsets are 64-bit (27 populations of a large lattice pass 2^32
+// elements).
 template <class S, bool DEV = false>
-__device__ inline void pull27(const typename S::T *__restrict__ src, uint32_t plane, int nx, int ny, int xm, int xs,
-                              int xp, int ym, int y, int yp, int zm, int z, int zp, float f[Q]) {
+__device__ inline void pull27(const typename S::T *__restrict__ src, const GridArgs &g, int xm, int xs, int xp,
+                              int ym, int y, int yp, int zm, int z, int zp, float f[Q]) {
   const int xx[3] = {xp, xs, xm};  // indexed by cx + 1: source x = xs - cx
   const int yy[3] = {yp, y, ym};
   const int zz[3] = {zp, z, zm};
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const uint32_t cell = ((uint32_t)zz[cz_of(i) + 1] * (uint32_t)ny + (uint32_t)yy[cy_of(i) + 1]) * (uint32_t)nx +
-                          (uint32_t)xx[cx_of(i) + 1];
-    f[i] = DEV ? S::load_dev(src + (size_t)i * plane + cell, i) : S::load(src + (size_t)i * plane + cell, i);
+    const uint32_t row = (uint32_t)zz[cz_of(i) + 1] * (uint32_t)g.ny + (uint32_t)yy[cy_of(i) + 1];
+    const size_t at = pop_idx(g, i, row, (uint32_t)xx[cx_of(i) + 1]);
+    f[i] = DEV ? S::load_dev(src + at, i) : S::load(src + at, i);
   }
 }
 
@@ -146,7 +146,7 @@ __device__ inline bool collide_load(const EnvView &e, int cur, int lb, int tx, i
     zm = z == 0 ? g.nz - 1 : z - 1;
     zp = z == g.nz - 1 ? 0 : z + 1;
   }
-  pull27<S, true>(src, g.plane, g.nx, g.ny, xm, xs, xp, ym, ys, yp, zm, zs, zp, f);
+  pull27<S, true>(src, g, xm, xs, xp, ym, ys, yp, zm, zs, zp, f);
   c.x = x;
   c.y = y;
   c.z = z;
@@ -245,8 +245,7 @@ __device__ inline void collide_finish(const EnvView &e, const FrameF &fr, int cu
   // heq_i = f^eq_i - w_i = w_i [(rho - 1) + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u^2)].
   const float Ah = -1.5f * u2;
   const float uF = ux * Fx + uy * Fy + uz * Fz;
-  const uint32_t o = ((uint32_t)z * (uint32_t)g.ny + (uint32_t)y) * (uint32_t)g.nx + (uint32_t)x;
-  typename S::T *__restrict__ d = dst + o;
+  typename S::T *__restrict__ d = dst + pop_idx(g, 0, (uint32_t)z * (uint32_t)g.ny + (uint32_t)y, (uint32_t)x);
   if constexpr (!TRT) {
     const float E = e.inv_tau * rho;
     const float B = e.inv_tau * drho;
@@ -259,12 +258,12 @@ __device__ inline void collide_finish(const EnvView &e, const FrameF &fr, int cu
       const float cF = cdot(i, Fx, Fy, Fz);
       const float even = w * (E * (Ah + 4.5f * cu * cu) + B) + (w * P) * (9.0f * cu * cF - 3.0f * uF);
       const float odd = (w * E) * (3.0f * cu) + (w * P) * (3.0f * cF);
-      S::store_dev(d + (size_t)i * g.plane, e.omt * f[i] + even + odd, i);
-      S::store_dev(d + (size_t)j * g.plane, e.omt * f[j] + even - odd, j);
+      S::store_dev(d + (size_t)i * g.ps, e.omt * f[i] + even + odd, i);
+      S::store_dev(d + (size_t)j * g.ps, e.omt * f[j] + even - odd, j);
     }
     {
       const float w = w_of(13);
-      S::store_dev(d + (size_t)13 * g.plane, e.omt * f[13] + w * (E * Ah + B) - (w * P) * 3.0f * uF, 13);
+      S::store_dev(d + (size_t)13 * g.ps, e.omt * f[13] + w * (E * Ah + B) - (w * P) * 3.0f * uF, 13);
     }
   } else {
     // h*_i = h_i - w+ (h+_i - heq+_i) - w- (h-_i - heq-_i) + (1 - w+/2) S+_i + (1 - w-/2) S-_i
@@ -281,12 +280,12 @@ __device__ inline void collide_finish(const EnvView &e, const FrameF &fr, int cu
       const float cF = cdot(i, Fx, Fy, Fz);
       const float even = w * (Ep * (Ah + 4.5f * cu * cu) + Bp) + (w * Pp) * (9.0f * cu * cF - 3.0f * uF);
       const float odd = (w * Em) * (3.0f * cu) + (w * Pm) * (3.0f * cF);
-      S::store_dev(d + (size_t)i * g.plane, a * f[i] + b * f[j] + even + odd, i);
-      S::store_dev(d + (size_t)j * g.plane, a * f[j] + b * f[i] + even - odd, j);
+      S::store_dev(d + (size_t)i * g.ps, a * f[i] + b * f[j] + even + odd, i);
+      S::store_dev(d + (size_t)j * g.ps, a * f[j] + b * f[i] + even - odd, j);
     }
     {
       const float w = w_of(13);
-      S::store_dev(d + (size_t)13 * g.plane, (1.0f - e.trt.wp) * f[13] + w * (Ep * Ah + Bp) - (w * Pp) * 3.0f * uF,
+      S::store_dev(d + (size_t)13 * g.ps, (1.0f - e.trt.wp) * f[13] + w * (Ep * Ah + Bp) - (w * Pp) * 3.0f * uF,
                    13);
     }
   }
@@ -327,7 +326,7 @@ __global__ void k_load_canonical(const float *__restrict__ fin, typename S::T *_
     int sx = x + cx_of(i), sy = wrap_idx(y + cy_of(i), g.ny), sz = wrap_idx(z + cz_of(i), g.nz);
     sx = g.xper ? wrap_idx(sx, g.nx) : min(max(sx, 0), g.nx - 1);
     float v = fin[(size_t)i * n + ((size_t)sz * g.ny + sy) * g.nx + sx];
-    S::store_plain(dst + (size_t)i * g.plane + ((size_t)z * g.ny + y) * g.nx + x, v, i);
+    S::store_plain(dst + pop_idx(g, i, (uint32_t)z * g.ny + y, x), v, i);
   }
 }
 
@@ -349,7 +348,7 @@ __global__ void k_init_equilibrium(const float *__restrict__ rho0, const float *
     float ux = u0 ? u0[s] : 0.f, uy = u0 ? u0[n + s] : 0.f, uz = u0 ? u0[2 * n + s] : 0.f;
     float cu = cdot(i, ux, uy, uz);
     float v = w_of(i) * r * (1.0f + 3.0f * cu + 4.5f * cu * cu - 1.5f * (ux * ux + uy * uy + uz * uz));
-    S::store_plain(dst + (size_t)i * g.plane + ((size_t)z * g.ny + y) * g.nx + x, v, i);
+    S::store_plain(dst + pop_idx(g, i, (uint32_t)z * g.ny + y, x), v, i);
   }
 }
 
@@ -365,7 +364,7 @@ __global__ void k_read_canonical(const typename S::T *__restrict__ src, float *_
     int sx = x - cx_of(i), sy = wrap_idx(y - cy_of(i), g.ny), sz = wrap_idx(z - cz_of(i), g.nz);
     sx = g.xper ? wrap_idx(sx, g.nx) : min(max(sx, 0), g.nx - 1);
     fout[(size_t)i * n + ((size_t)z * g.ny + y) * g.nx + x] =
-        S::load(src + (size_t)i * g.plane + ((size_t)sz * g.ny + sy) * g.nx + sx, i);
+        S::load(src + pop_idx(g, i, (uint32_t)sz * g.ny + sy, sx), i);
   }
 }
 
@@ -388,7 +387,7 @@ __global__ void k_macros(const typename S::T *__restrict__ src, GridArgs g, Fram
     xp = min(xp, g.nx - 1);
   }
   float f[Q];  // deviations h_i
-  pull27<S, true>(src, g.plane, g.nx, g.ny, xm, x, xp, wrap_idx(y - 1, g.ny), y, wrap_idx(y + 1, g.ny),
+  pull27<S, true>(src, g, xm, x, xp, wrap_idx(y - 1, g.ny), y, wrap_idx(y + 1, g.ny),
                   wrap_idx(z - 1, g.nz), z, wrap_idx(z + 1, g.nz), f);
   float drho, mx, my, mz;
   moments(f, drho, mx, my, mz);

@@ -222,7 +222,7 @@ __device__ inline void macro_item(const EnvView &e, const FrameF &fr, int cur, i
     const int xm = g.xper ? wrap_idx(x - 1, g.nx) : x - 1;
     const int xp = g.xper ? wrap_idx(x + 1, g.nx) : x + 1;
     float f[Q];  // deviations h_i = f_i - w_i
-    pull27<S, true>(src, g.plane, g.nx, g.ny, xm, x, xp, wrap_idx(y - 1, g.ny), y, wrap_idx(y + 1, g.ny),
+    pull27<S, true>(src, g, xm, x, xp, wrap_idx(y - 1, g.ny), y, wrap_idx(y + 1, g.ny),
                     wrap_idx(z - 1, g.nz), z, wrap_idx(z + 1, g.nz), f);
     float drho, mx, my, mz;
     moments(f, drho, mx, my, mz);

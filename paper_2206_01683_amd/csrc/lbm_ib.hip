@@ -51,13 +51,15 @@ bool params_ok(const lbm_params *p) {
   if (p->max_markers < 0 || p->max_markers > (1 << 24)) return false;
   if (p->max_bones < 1 || p->mdf_iters < 1 || p->mdf_iters > 16) return false;
   if (p->max_active_tiles < 0) return false;
-  if (p->block_x < 0 || p->block_y < 0 || p->block_x * p->block_y > 512) return false;
+  if (p->block_x < 0 || p->block_y < -1 || p->block_x > 512 || p->block_x * p->block_y > 512) return false;
   if (p->block_x > 0 && p->block_x % 64 != 0) return false;
+  if (p->block_y == -1 && p->block_x == 0) return false;
   if (!(p->ib_alpha > 0.0) || !std::isfinite(p->ib_alpha)) return false;
   if (p->ib_scheme != LBM_IB_DIRECT && p->ib_scheme != LBM_IB_IMPLICIT) return false;
   if (p->collision != LBM_COLLIDE_BGK && p->collision != LBM_COLLIDE_TRT) return false;
   if (p->collision == LBM_COLLIDE_TRT && !(p->trt_lambda > 0.0 && std::isfinite(p->trt_lambda))) return false;
   if (p->wall_mode != LBM_WALL_NO_SLIP && p->wall_mode != LBM_WALL_SLIP) return false;
+  if (p->layout != LBM_LAYOUT_AUTO && p->layout != LBM_LAYOUT_PLANES && p->layout != LBM_LAYOUT_ROWS) return false;
   return true;
 }
 
@@ -70,6 +72,22 @@ size_t elem_bytes(int storage) { return storage == LBM_STORE_F32 ? 4 : 2; }
 uint32_t plane_elems(const lbm_params *p) {
   size_t n = (size_t)p->nx * p->ny * p->nz;
   return (uint32_t)(align_up(n, 256) + 192);
+}
+
+// Row layout ([nz][ny][27][nx]) for these parameters, else planes.
+bool rows_layout(const lbm_params *p) {
+  return p->layout == LBM_LAYOUT_ROWS || (p->layout == LBM_LAYOUT_AUTO && p->nx % 32 == 0);
+}
+
+// Population and row strides (elements) of the stored layout.
+void pop_strides(const lbm_params *p, uint32_t &ps, uint32_t &rs) {
+  if (rows_layout(p)) {
+    ps = (uint32_t)p->nx;
+    rs = 27u * (uint32_t)p->nx;
+  } else {
+    ps = plane_elems(p);
+    rs = (uint32_t)p->nx;
+  }
 }
 
 Layout layout(const lbm_params *p) {
@@ -135,6 +153,7 @@ struct lbm_ctx {
   hipStream_t stream;
   int64_t steps;
   uint32_t plane;
+  uint32_t ps, rs;  // population and row strides of the stored layout
   bool slots_dirty;
   bool is_static;  // created by lbm_init_static: workspace in `scratch`, not freed by lbm_destroy
   int bx, by;
@@ -159,6 +178,8 @@ GridArgs grid_args(const lbm_ctx *c) {
   g.ny = c->p.ny;
   g.nz = c->p.nz;
   g.plane = c->plane;
+  g.ps = c->ps;
+  g.rs = c->rs;
   g.xper = c->p.bc_lo == LBM_BC_PERIODIC;
   g.bc_lo = c->p.bc_lo;
   g.bc_hi = c->p.bc_hi;
@@ -481,14 +502,23 @@ lbm_status setup_ctx(lbm_ctx *c, const lbm_params *p, void *f_a, void *f_b, char
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->steps = 0;
   c->plane = plane_elems(p);
+  pop_strides(p, c->ps, c->rs);
   c->slots_dirty = false;
   c->is_static = false;
   c->prof = false;
   c->prof_used = 0;
-  // collide block: 64-multiple along x covering as much of a row as fits
+  // collide block: bx x by cells (by = 0: bx consecutive cells of the
+  // x-fastest order). Default: 256 consecutive cells with the row layout;
+  // with planes a 64-multiple along x covering as much of a row as fits.
   int bx = p->block_x, by = p->block_y;
-  if (bx == 0) bx = p->nx >= 128 ? 128 : 64;
-  if (by == 0) by = std::max(1, 512 / bx);
+  if (bx == 0 && by == 0 && rows_layout(p)) {
+    bx = 256;
+  } else if (by == -1) {
+    by = 0;
+  } else {
+    if (bx == 0) bx = p->nx >= 128 ? 128 : 64;
+    if (by == 0) by = std::max(1, 512 / bx);
+  }
   c->bx = bx;
   c->by = by;
   // every workspace field that must start cleared, by kernels (no memset
@@ -540,6 +570,16 @@ size_t lbm_population_bytes(const lbm_params *p) {
 size_t lbm_workspace_bytes(const lbm_params *p) {
   if (!params_ok(p)) return 0;
   return layout(p).total;
+}
+
+lbm_status lbm_population_strides(const lbm_params *p, int64_t *strides) {
+  if (!params_ok(p) || !strides) return LBM_ERR_ARG;
+  uint32_t ps, rs;
+  pop_strides(p, ps, rs);
+  strides[0] = ps;
+  strides[1] = rs;
+  strides[2] = rows_layout(p) ? 1 : 0;
+  return LBM_OK;
 }
 
 lbm_status lbm_init(lbm_ctx **out, const lbm_params *p, void *f_a, void *f_b, void *workspace, const float *rho0,

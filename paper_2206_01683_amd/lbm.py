@@ -27,6 +27,7 @@ STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 STATIC_WORKSPACE_BYTES = 64 << 20  # LBM_STATIC_WORKSPACE_BYTES
 IB_DIRECT, IB_IMPLICIT = 0, 1
 COLLIDE_BGK, COLLIDE_TRT = 0, 1
+LAYOUT_AUTO, LAYOUT_PLANES, LAYOUT_ROWS = 0, 1, 2
 WALL_NO_SLIP, WALL_SLIP = 0, 1
 TRT_MAGIC = 3.0 / 16.0
 
@@ -38,7 +39,8 @@ class Params(ctypes.Structure):
                 ("max_active_tiles", ctypes.c_int32), ("block_x", ctypes.c_int32), ("block_y", ctypes.c_int32),
                 ("with_adjoint", ctypes.c_int32), ("tau", ctypes.c_double), ("ib_alpha", ctypes.c_double),
                 ("bc_y", ctypes.c_int32 * 2), ("bc_z", ctypes.c_int32 * 2), ("ib_scheme", ctypes.c_int32),
-                ("collision", ctypes.c_int32), ("trt_lambda", ctypes.c_double), ("wall_mode", ctypes.c_int32)]
+                ("collision", ctypes.c_int32), ("trt_lambda", ctypes.c_double), ("wall_mode", ctypes.c_int32),
+                ("layout", ctypes.c_int32)]
 
 
 class Frame(ctypes.Structure):
@@ -95,6 +97,7 @@ def lib():
         L.lbm_population_bytes.restype = sz
         L.lbm_workspace_bytes.argtypes = [P]
         L.lbm_workspace_bytes.restype = sz
+        L.lbm_population_strides.argtypes = [P, vp]
         L.lbm_init.argtypes = [ctypes.POINTER(vp), P, vp, vp, vp, vp, vp, vp]
         L.lbm_init_static.argtypes = [ctypes.POINTER(vp), P, vp, vp, vp, vp, vp]
         L.lbm_load_populations.argtypes = [vp, vp]
@@ -133,8 +136,9 @@ def lib():
         L.lbm_strerror.restype = ctypes.c_char_p
         L.lbm_destroy.argtypes = [vp]
         L.lbm_destroy.restype = None
-        for name in ("lbm_init", "lbm_init_static", "lbm_load_populations", "lbm_read_populations", "lbm_macros",
-                     "lbm_ib_step", "lbm_body_forces", "lbm_check", "lbm_set_stream", "lbm_profile_enable",
+        for name in ("lbm_init", "lbm_init_static", "lbm_population_strides", "lbm_load_populations",
+                     "lbm_read_populations", "lbm_macros", "lbm_ib_step", "lbm_body_forces", "lbm_check",
+                     "lbm_set_stream", "lbm_profile_enable",
                      "lbm_profile_collect", "lbm_state_save", "lbm_state_restore", "lbm_adjoint_step",
                      "lbm_bind_populations", "lbm_adjoint_segment", "lbm_adjoint_sweep", "lbm_adjoint_record",
                      "lbm_swimmer_init", "lbm_swimmer_prepare",
@@ -161,15 +165,17 @@ def _check(rc: int, what: str):
 def make_params(nx, ny, nz, tau, bc_lo=BC_PERIODIC, bc_hi=BC_PERIODIC, storage="f32", max_markers=0,
                 max_bones=1, mdf_iters=1, ib_alpha=1.0, max_active_tiles=0, block=(0, 0), with_adjoint=False,
                 bc_y=(BC_PERIODIC, BC_PERIODIC), bc_z=(BC_PERIODIC, BC_PERIODIC), ib_scheme=0, collision=0,
-                trt_lambda=TRT_MAGIC, wall_mode=0) -> Params:
+                trt_lambda=TRT_MAGIC, wall_mode=0, layout=LAYOUT_AUTO) -> Params:
     """ib_scheme: IB_DIRECT (direct forcing, mdf_iters passes) or IB_IMPLICIT
     (implicit velocity correction, mdf_iters conjugate-gradient steps).
     collision: COLLIDE_BGK or COLLIDE_TRT with Lambda = trt_lambda.
-    wall_mode: WALL_NO_SLIP or WALL_SLIP (normal component only)."""
+    wall_mode: WALL_NO_SLIP or WALL_SLIP (normal component only).
+    layout: LAYOUT_AUTO, LAYOUT_PLANES or LAYOUT_ROWS (stored populations).
+    block: collide block (bx, by); (bx, -1) is bx consecutive cells."""
     return Params(nx, ny, nz, bc_lo, bc_hi, STORAGE[storage] if isinstance(storage, str) else storage,
                   max_markers, max_bones, mdf_iters, max_active_tiles, block[0], block[1], 1 if with_adjoint else 0,
                   tau, ib_alpha, (ctypes.c_int32 * 2)(*bc_y), (ctypes.c_int32 * 2)(*bc_z), ib_scheme, collision,
-                  trt_lambda, wall_mode)
+                  trt_lambda, wall_mode, layout)
 
 
 def frames_array(frames: np.ndarray) -> np.ndarray:
@@ -218,7 +224,7 @@ class Simulation:
                  max_bones=1, mdf_iters=1, ib_alpha=1.0, rho0=None, u0=None, device="cuda", block=(0, 0),
                  max_active_tiles=0, stream=None, with_adjoint=False, bc_y=(BC_PERIODIC, BC_PERIODIC),
                  bc_z=(BC_PERIODIC, BC_PERIODIC), ib_scheme=0, collision=0, trt_lambda=TRT_MAGIC, wall_mode=0,
-                 static_workspace=False):
+                 static_workspace=False, layout=LAYOUT_AUTO):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the lattice Boltzmann library runs only on the GPU")
         L = lib()
@@ -226,13 +232,16 @@ class Simulation:
         self.shape = (nz, ny, nx)
         self.params = make_params(nx, ny, nz, tau, bc_lo, bc_hi, storage, max_markers, max_bones, mdf_iters,
                                   ib_alpha, max_active_tiles, block, with_adjoint, bc_y, bc_z, ib_scheme,
-                                  collision, trt_lambda, wall_mode)
+                                  collision, trt_lambda, wall_mode, layout)
         pb = L.lbm_population_bytes(ctypes.byref(self.params))
         wb = L.lbm_workspace_bytes(ctypes.byref(self.params))
         if pb == 0 or wb == 0:
             raise LBMError(-1, "invalid parameters")
         self.population_bytes = pb
         self.workspace_bytes = wb
+        st = (ctypes.c_int64 * 3)()
+        _check(L.lbm_population_strides(ctypes.byref(self.params), st), "lbm_population_strides")
+        self.pop_stride, self.row_stride, self.rows_layout = int(st[0]), int(st[1]), bool(st[2])
         self.fa = torch.empty(pb, dtype=torch.uint8, device=self.device)
         self.fb = torch.empty(pb, dtype=torch.uint8, device=self.device)
         self.static_workspace = bool(static_workspace)
@@ -321,6 +330,13 @@ class Simulation:
         _check(lib().lbm_profile_collect(self.ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)),
                "lbm_profile_collect")
         return a.value, b.value, n.value
+
+    def stored_view(self, state: torch.Tensor) -> torch.Tensor:
+        """[27][nz][ny][nx] strided view of a float32 buffer in the stored
+        population layout (a state, or an adjoint buffer of the same layout)."""
+        nz, ny, nx = self.shape
+        flat = state.view(torch.float32) if state.dtype != torch.float32 else state
+        return flat.as_strided((27, nz, ny, nx), (self.pop_stride, ny * self.row_stride, self.row_stride, 1))
 
     def new_state(self) -> torch.Tensor:
         """An uninitialized buffer in the stored population layout."""

@@ -153,3 +153,32 @@ def test_static_init_validates_on_the_host(L):
     fish = lbm.make_params(384, 192, 192, 0.6, lbm.BC_VELOCITY, lbm.BC_OUTFLOW, max_markers=12000, max_bones=10,
                            max_active_tiles=1024)
     assert L.lbm_workspace_bytes(ctypes.byref(fish)) <= lbm.STATIC_WORKSPACE_BYTES
+
+
+def test_population_layout_strides(L):
+    """Rows ([nz][ny][27][nx]) by default when nx is a multiple of 32, planes
+    otherwise or on request; the strides address element (i, x, y, z) at
+    (z ny + y) rs + i ps + x inside lbm_population_bytes."""
+    st = (ctypes.c_int64 * 3)()
+    for nx, layout, want_rows in ((384, lbm.LAYOUT_AUTO, True), (48, lbm.LAYOUT_AUTO, False),
+                                  (384, lbm.LAYOUT_PLANES, False), (37, lbm.LAYOUT_ROWS, True)):
+        for storage in ("f32", "f16"):
+            p = lbm.make_params(nx, 20, 12, 0.6, storage=storage, layout=layout)
+            assert L.lbm_population_strides(ctypes.byref(p), st) == 0
+            ps, rs, rows = st[0], st[1], st[2]
+            assert rows == (1 if want_rows else 0)
+            if want_rows:
+                assert (ps, rs) == (nx, 27 * nx)
+            else:
+                assert rs == nx and ps >= nx * 20 * 12
+            # the last element of the last population fits in the buffer
+            last = (12 * 20 - 1) * rs + 26 * ps + nx - 1
+            assert (last + 1) * (4 if storage == "f32" else 2) <= L.lbm_population_bytes(ctypes.byref(p))
+    bad = lbm.make_params(64, 16, 16, 0.6, layout=3)
+    assert L.lbm_population_strides(ctypes.byref(bad), st) == -1
+    assert L.lbm_population_bytes(ctypes.byref(bad)) == 0
+    assert L.lbm_population_strides(ctypes.byref(lbm.make_params(64, 16, 16, 0.6)), None) == -1
+    # block (bx, -1): bx consecutive cells; needs bx
+    assert L.lbm_population_bytes(ctypes.byref(lbm.make_params(64, 16, 16, 0.6, block=(256, -1)))) > 0
+    assert L.lbm_population_bytes(ctypes.byref(lbm.make_params(64, 16, 16, 0.6, block=(0, -1)))) == 0
+    assert L.lbm_population_bytes(ctypes.byref(lbm.make_params(64, 16, 16, 0.6, block=(576, -1)))) == 0

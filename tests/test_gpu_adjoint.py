@@ -31,11 +31,11 @@ def _sim(w, with_markers=True, **kw):
 
 
 def _valid_mask(sim, ncell):
-    """Stored-layout entries that hold populations (27 planes of ncell)."""
-    plane = sim.population_bytes // 4 // 27
-    m = torch.zeros((27, plane), dtype=torch.bool, device="cuda")
-    m[:, :ncell] = True
-    return m.reshape(-1)
+    """Stored-layout entries that hold populations (27 per cell; the rest of
+    the buffer is padding)."""
+    m = torch.zeros(sim.population_bytes // 4, dtype=torch.float32, device="cuda")
+    sim.stored_view(m).fill_(1.0)
+    return m != 0
 
 
 def _smooth_perturbation(sim, w, state, seed, amp=1e-3):
@@ -46,13 +46,14 @@ def _smooth_perturbation(sim, w, state, seed, amp=1e-3):
     a, b, p = rng.uniform(-1, 1, 27), rng.uniform(-1, 1, 27), rng.uniform(0, 2 * np.pi, 27)
     z, y, x = np.meshgrid(np.arange(w.nz), np.arange(w.ny), np.arange(w.nx), indexing="ij")
     ph = 2 * np.pi * (x / w.nx + y / w.ny)
-    plane = sim.population_bytes // 4 // 27
-    d = np.zeros((27, plane), np.float32)
     _, wts = oracle.lattice()
-    f = state.view(torch.float32).reshape(27, plane)[:, :w.ncell].cpu().numpy() + wts[:, None].astype(np.float32)
+    f = sim.stored_view(state).cpu().numpy() + wts[:, None, None, None].astype(np.float32)
+    d = np.zeros((27, w.nz, w.ny, w.nx), np.float32)
     for i in range(27):
-        d[i, :w.ncell] = amp * f[i] * (a[i] + b[i] * np.sin(ph + p[i])).ravel()
-    return torch.as_tensor(d.reshape(-1), device="cuda")
+        d[i] = amp * f[i] * (a[i] + b[i] * np.sin(ph + p[i]))
+    out = torch.zeros(sim.population_bytes // 4, dtype=torch.float32, device="cuda")
+    sim.stored_view(out).copy_(torch.as_tensor(d, device="cuda"))
+    return out
 
 
 def _run_J(sim, s0, dm, poses, frames, weights, c=None):
