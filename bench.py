@@ -92,7 +92,7 @@ def run_gpu(storage: str, steps: int, warmup: int, block=(0, 0), collision: int 
         "workload": w, "ncell": ncell, "wall": wall, "mlups": mlups, "status": status,
         "collide_avg_ms": col_avg_s * 1e3, "ib_avg_ms": ib_ms / max(timed, 1), "timed": timed,
         "collide_gbs": alg_bytes / col_avg_s / 1e9, "alg_bytes": alg_bytes,
-        "wrench_last": wrench[-1].cpu().tolist(),
+        "wrench_last": wrench[-1].cpu().tolist(), "rows_layout": sim.rows_layout,
     }
     del sim
     torch.cuda.empty_cache()
@@ -332,9 +332,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f32", choices=sorted(BYTES_PER_CELL))
     ap.add_argument("--cpu-steps", type=int, default=24, help="oracle sample length (0: skip)")
-    ap.add_argument("--forms", default="f16,bf16,trt,faces_frames,batched,adjoint,two_fish,free_swimmer,ib_schemes",
-                    help="comma-separated extra forms to measure: f16, bf16, trt, faces_frames, batched, adjoint, "
-                         "two_fish, free_swimmer, ib_schemes")
+    ap.add_argument("--forms",
+                    default="ceiling,f16,bf16,trt,faces_frames,batched,adjoint,two_fish,free_swimmer,ib_schemes",
+                    help="comma-separated extra forms to measure: ceiling, f16, bf16, trt, faces_frames, batched, "
+                         "adjoint, two_fish, free_swimmer, ib_schemes")
     ap.add_argument("--no-forms", action="store_true", help="measure no extra form")
     ap.add_argument("--block", type=int, nargs=2, default=(0, 0))
     ap.add_argument("--batch-envs", type=int, default=64, help="batched form: environments (0: skip)")
@@ -351,6 +352,14 @@ def main():
     w = main_run["workload"]
     want = set() if args.no_forms else {f.strip() for f in args.forms.split(",") if f.strip()}
     forms = {}
+    if "ceiling" in want:
+        # the practical ceiling: reference streaming kernels on the fish's sizes
+        from paper_2206_01683_amd import hbm_ceiling
+        c = hbm_ceiling.measure(w.nx, w.ny, w.nz)
+        c["collide_over_pull27_same_layout"] = round(
+            main_run["collide_gbs"] / c["pull27_rows" if main_run["rows_layout"] else "pull27_planes"]["GBps"], 4)
+        c["collide_over_copy"] = round(main_run["collide_gbs"] / c["copy"]["GBps"], 4)
+        forms["ceiling"] = c
     if args.storage == "f32":
         for st in sorted(want & {"f16", "bf16"}):
             r = run_gpu(st, args.steps, args.warmup, tuple(args.block))

@@ -2,10 +2,13 @@
 every function the header declares, validates parameters on the host and
 reports errors by status code."""
 import ctypes
+import os
 
 import pytest
 
 from paper_2206_01683_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 @pytest.fixture(scope="module")
@@ -182,3 +185,26 @@ def test_population_layout_strides(L):
     assert L.lbm_population_bytes(ctypes.byref(lbm.make_params(64, 16, 16, 0.6, block=(256, -1)))) > 0
     assert L.lbm_population_bytes(ctypes.byref(lbm.make_params(64, 16, 16, 0.6, block=(0, -1)))) == 0
     assert L.lbm_population_bytes(ctypes.byref(lbm.make_params(64, 16, 16, 0.6, block=(576, -1)))) == 0
+
+
+def test_ceiling_library_exports_and_validates():
+    """The reference streaming kernels (include/hbm_ceiling.h): every declared
+    function is exported, and bad arguments are refused before any launch."""
+    import re
+
+    from paper_2206_01683_amd import hbm_ceiling
+    C = hbm_ceiling.lib()
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "hbm_ceiling.h")).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(hbm_[a-z_0-9]+)\s*\(", text)))
+    assert names == ["hbm_copy", "hbm_pull27", "hbm_read"]
+    for n in names:
+        assert hasattr(C, n), n
+    p, q = ctypes.c_void_p(4096), ctypes.c_void_p(8192)
+    assert C.hbm_copy(p, q, 100, None) == -1          # not a multiple of 16
+    assert C.hbm_copy(ctypes.c_void_p(4100), q, 160, None) == -1  # misaligned
+    assert C.hbm_copy(None, q, 160, None) == -1
+    assert C.hbm_read(p, 0, q, None) == -1
+    assert C.hbm_pull27(p, p, 8, 8, 8, 8, 216, None) == -1      # aliased
+    assert C.hbm_pull27(p, q, 8, 8, 8, 8, 64, None) == -1       # rows need rs = 27 nx
+    assert C.hbm_pull27(p, q, 8, 8, 8, 100, 8, None) == -1      # planes need ps >= cells
+    assert C.hbm_pull27(p, q, 0, 8, 8, 8, 216, None) == -1
