@@ -288,9 +288,37 @@ def run_adjoint(nsteps: int = 400, every: int = 20, record: bool = False):
             "finite": bool(np.isfinite(pb.cpu().numpy()).all()), "status": status}
 
 
+def _precision_vs_oracle(w, f_ref, prm, nsteps: int) -> dict:
+    """Velocity relative L2 (non-face nodes) of the GPU after nsteps steps of
+    workload w, per storage format, against the oracle's populations f_ref."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2206_01683_amd import lbm
+
+    _, u_ref = oracle.macros(prm, f_ref, w.frames[nsteps - 1])
+    u_ref = u_ref[..., 1:-1]
+    out = {"steps": nsteps, "metric": "velocity relative L2 over the non-face nodes"}
+    for st in ("f32", "f16", "bf16"):
+        sim = lbm.Simulation(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi, storage=st, max_markers=w.markers.n,
+                             max_bones=w.markers.nbones, rho0=np.ones((w.nz, w.ny, w.nx), np.float32),
+                             u0=w.u0.astype(np.float32))
+        dm = lbm.DeviceMarkers(w.markers)
+        poses = torch.as_tensor(np.ascontiguousarray(w.poses[:nsteps], np.float32), device="cuda")
+        sim.step(w.frames[:nsteps], dm, poses)
+        _, u = sim.macros(w.frames[nsteps - 1])
+        u = u.cpu().numpy().astype(np.float64)[..., 1:-1]
+        out[st] = float(np.linalg.norm((u - u_ref).ravel()) / np.linalg.norm(u_ref.ravel()))
+        sim.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(sample_steps: int):
     """The FP64 oracle as it stands, on the host cores, on the first
-    sample_steps steps of the same workload (same domain, fish and frames)."""
+    sample_steps steps of the same workload (same domain, fish and frames);
+    then the GPU's velocity error against that sample's end state."""
     import numpy as np
 
     import oracle
@@ -300,7 +328,7 @@ def cpu_baseline(sample_steps: int):
     prm = oracle.params(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi)
     f0 = oracle.equilibrium_field(np.ones((w.nz, w.ny, w.nx)), w.u0)
     t0 = time.perf_counter()
-    oracle.run(prm, f0.copy(), w.frames, w.markers, w.poses, sample_steps)
+    ref = oracle.run(prm, f0.copy(), w.frames, w.markers, w.poses, sample_steps)
     dt = time.perf_counter() - t0
     cores = oracle.threads()
     # one core as well: a 2-step run less a 1-step run, so that the set-up of
@@ -318,11 +346,19 @@ def cpu_baseline(sample_steps: int):
             if line.startswith("model name"):
                 model = line.split(":", 1)[1].strip()
                 break
+    try:
+        import psutil
+        physical = psutil.cpu_count(logical=False)
+    except Exception:
+        physical = None
     return {"value": round(w.ncell * sample_steps / dt / 1e6, 3), "unit": "MLUPS", "cores": cores,
             "kind": "oracle",
             "sample": f"{sample_steps} steps of the {w.nx}x{w.ny}x{w.nz} fish workload from rest "
                       f"({w.ncell * sample_steps} node updates, {dt:.1f} s, FP64)",
-            "one_core_value": round(w.ncell / max(dt1, 1e-9) / 1e6, 3), "cpu_model": model}
+            "one_core_value": round(w.ncell / max(dt1, 1e-9) / 1e6, 3), "cpu_model": model,
+            "openmp_threads": cores, "physical_cores_visible": physical,
+            "logical_cpus_usable": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
+            "gpu_precision_vs_oracle": _precision_vs_oracle(w, ref["f"], prm, sample_steps)}
 
 
 def main():
