@@ -35,9 +35,23 @@ struct BatchArgs {
   const int *corder;    // [nenv] environment at each position of the collide prefix (grouped by kind)
   int tot[4];
   int mdf;              // direct-forcing passes
-  unsigned *bar;        // grid barrier: [0] arrivals, [1] generation
-  int *status;          // bit 0: barrier timeout
+  unsigned *bar;        // grid barrier words and the collide work queue (BAR_*, kBarWords)
 };
+
+// Barrier words, each on its own 128-byte line (indices into BatchArgs::bar):
+// the top arrival count, the generation, the collide work queue, the status
+// word, then one arrival count per group of kBarGroup workgroups.
+constexpr int kBarLine = 32;
+enum : int {
+  BAR_TOP = 0,
+  BAR_GEN = kBarLine,
+  BAR_QUEUE = 2 * kBarLine,
+  BAR_STATUS = 3 * kBarLine,
+  BAR_GROUPS = 4 * kBarLine
+};
+constexpr int kBarGroup = 32;      // workgroups per first-level arrival count
+constexpr int kBarMaxGroups = 64;  // so at most 2048 workgroups
+constexpr int kBarWords = BAR_GROUPS + kBarMaxGroups * kBarLine;
 
 // Rows of BatchArgs::pre: per-environment exclusive item prefixes (row 4 holds
 // the collide order, corder); PRE_CG counts conjugate-gradient items.
@@ -73,7 +87,22 @@ __device__ inline int dynamic_prefix(const BatchArgs &b, int mult, int *s_pre, i
   return s_pre[b.nenv];
 }
 
-__device__ inline FrameF env_frame(const EnvView &e, int s) { return frame_from(e.frames + (size_t)18 * s); }
+// Step s's frame of environment e. The values are uniform over the
+// workgroup: moving them to scalar registers keeps 18 vector registers free
+// for the collide.
+__device__ inline float uniform_f(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+__device__ inline FrameF env_frame(const EnvView &e, int s) {
+  FrameF f = frame_from(e.frames + (size_t)18 * s);
+  for (int a = 0; a < 3; ++a) {
+    f.acc[a] = uniform_f(f.acc[a]);
+    f.omg[a] = uniform_f(f.omg[a]);
+    f.alp[a] = uniform_f(f.alp[a]);
+    f.org[a] = uniform_f(f.org[a]);
+    f.ulo[a] = uniform_f(f.ulo[a]);
+    f.uhi[a] = uniform_f(f.uhi[a]);
+  }
+  return f;
+}
 __device__ inline int env_cur(const EnvView &e, int s) { return e.cur0 ^ (s & 1); }
 
 // collide_cell for any environment of one collision kind: boundary kind and
@@ -201,10 +230,11 @@ __device__ inline void phase_spread(const BatchArgs &b, int s, bool final_pass, 
 // Collide item -> (environment, logical block); 512 threads as e.bx x e.by.
 // Collide items are numbered over the environments in kind order (corder).
 template <int K>
-__device__ inline void phase_collide(const BatchArgs &b, int s, int item, int tid) {
-  const int *pre = b.pre + PRE_COLLIDE * (b.nenv + 1);
+__device__ inline void phase_collide(const BatchArgs &b, const EnvView *__restrict__ envs, const int *__restrict__ pre0,
+                                     const int *__restrict__ corder, int s, int item, int tid) {
+  const int *pre = pre0 + PRE_COLLIDE * (b.nenv + 1);
   const int pos = find_env(pre, b.nenv, item);
-  const EnvView &e = b.envs[b.corder[pos]];
+  const EnvView &e = envs[corder[pos]];
   const FrameF fr = env_frame(e, s);
   const int lb = item - pre[pos];
   const int cur = env_cur(e, s);
@@ -212,20 +242,28 @@ __device__ inline void phase_collide(const BatchArgs &b, int s, int item, int ti
   collide_item<K>(e, fr, cur, lb, tx, ty);
 }
 
-// Collide items [i0, i1) in order, looking the environment up once per run
-// of items that belong to it (a persistent workgroup walks a contiguous range).
+// Collide items handed out in launch order by a device-wide ticket counter
+// (bar[BAR_QUEUE], cleared at every grid barrier), so that the resident workgroups
+// sweep a compact, moving window of the lattices as the hardware's dispatch
+// of a per-phase launch does (workgroups that each walked a contiguous range
+// of their own streamed from hundreds of distant regions at once). Each
+// workgroup fetches its next ticket while the current item runs.
 template <bool UNI>
-__device__ inline void collide_range(const BatchArgs &b, int s, int i0, int i1, int tid) {
+__device__ inline void collide_queue(const BatchArgs &b, int s, int tid) {
+  __shared__ int s_ticket[2];
+  const int total = b.tot[PRE_COLLIDE];
   const int *pre = b.pre + PRE_COLLIDE * (b.nenv + 1);
-  int item = i0;
-  while (item < i1) {
+  if (tid == 0) s_ticket[0] = (int)atomicAdd(&b.bar[BAR_QUEUE], 1u);
+  __syncthreads();
+  for (int k = 0;; k ^= 1) {
+    const int item = s_ticket[k];
+    if (item >= total) break;  // the same value in every thread
+    if (tid == 0) s_ticket[k ^ 1] = (int)atomicAdd(&b.bar[BAR_QUEUE], 1u);
     const int pos = find_env(pre, b.nenv, item);
     const EnvView &e = b.envs[b.corder[pos]];
-    const FrameF fr = env_frame(e, s);
-    const int cur = env_cur(e, s);
-    const int lo = pre[pos], hi = min(pre[pos + 1], i1);
     const int tx = tid % e.bx, ty = tid / e.bx;
-    for (; item < hi; ++item) collide_item<UNI ? 0 : -1>(e, fr, cur, item - lo, tx, ty);
+    collide_item<UNI ? 0 : -1>(e, env_frame(e, s), env_cur(e, s), item - pre[pos], tx, ty);
+    __syncthreads();  // the next ticket is visible; this one was read by every thread
   }
 }
 
@@ -310,80 +348,138 @@ __global__ void __launch_bounds__(WG) kb_spread(BatchArgs b, int s, int final_pa
 // K, one per workgroup in launch order (the same mapping as the
 // single-lattice collide). One launch per kind present.
 template <int K>
-__global__ void __launch_bounds__(WG) kb_collide(BatchArgs b, int s, int item0) {
+__global__ void __launch_bounds__(WG) kb_collide(BatchArgs b, const EnvView *__restrict__ envs,
+                                                 const int *__restrict__ pre, const int *__restrict__ corder, int s,
+                                                 int item0) {
   const int item = item0 + blockIdx.x;
-  if (item < b.tot[PRE_COLLIDE]) phase_collide<K>(b, s, item, threadIdx.x);
+  if (item < b.tot[PRE_COLLIDE]) phase_collide<K>(b, envs, pre, corder, s, item, threadIdx.x);
 }
 
 // --------------------------------------------------------- grid barrier ----
-constexpr long kBarrierSpins = 1L << 25;  // ~1 s of waiting: a longer wait is a failure
+constexpr long kBarrierSpins = 1L << 24;  // ~1 s of waiting: a longer wait is a failure
 
-// Device-wide barrier for a co-resident grid. Release: each workgroup's
-// writes are made visible at device scope before it arrives; acquire: after
-// the generation changes. Returns false (in every thread) after a timeout.
+// Device-wide barrier for a co-resident grid, in two levels: a workgroup
+// arrives on its group's count; the last of a group arrives on the top count;
+// the last of those clears the work queue and advances the generation, which
+// the others wait for. Spreading the arrivals over lines cuts the chain of
+// serialized device-scope atomics from one per workgroup to about
+// kBarGroup + groups.
+// Memory ordering: each arrival is an acquire-release read-modify-write at
+// device scope (it writes this workgroup's L2 lines back before it counts),
+// and a waiter polls the generation with relaxed loads and acquires once when
+// it changes. An acquiring poll would invalidate its XCD's L2 on every
+// iteration, under the feet of the workgroups still busy in the phase.
+// Returns false (in every thread) after a timeout.
 __device__ inline bool grid_sync(const BatchArgs &b) {
   __shared__ int s_ok;
   __syncthreads();
   if (threadIdx.x == 0) {
     int ok = 1;
-    __threadfence();
-    const unsigned gen = __hip_atomic_load(&b.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned arrived = __hip_atomic_fetch_add(&b.bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (arrived == gridDim.x - 1) {
-      __hip_atomic_store(&b.bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&b.bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned gen = __hip_atomic_load(&b.bar[BAR_GEN], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned nwg = gridDim.x;
+    const unsigned grp = blockIdx.x / kBarGroup;
+    const unsigned ngrp = (nwg + kBarGroup - 1) / kBarGroup;
+    const unsigned in_grp = min((unsigned)kBarGroup, nwg - grp * kBarGroup);
+    unsigned *gc = &b.bar[BAR_GROUPS + grp * kBarLine];
+    bool last = false;
+    if (__hip_atomic_fetch_add(gc, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == in_grp - 1) {
+      __hip_atomic_store(gc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      last = __hip_atomic_fetch_add(&b.bar[BAR_TOP], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == ngrp - 1;
+    }
+    if (last) {
+      __hip_atomic_store(&b.bar[BAR_TOP], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&b.bar[BAR_QUEUE], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // empty work queue
+      __hip_atomic_fetch_add(&b.bar[BAR_GEN], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       long spins = 0;
-      while (__hip_atomic_load(&b.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-        __builtin_amdgcn_s_sleep(1);
+      while (__hip_atomic_load(&b.bar[BAR_GEN], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        __builtin_amdgcn_s_sleep(2);
         if (++spins > kBarrierSpins) {
           ok = 0;
           break;
         }
       }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    if (!ok) atomicOr(b.status, 1);
-    if (__hip_atomic_load(b.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1) ok = 0;
-    __threadfence();
+    int *status = reinterpret_cast<int *>(&b.bar[BAR_STATUS]);
+    if (!ok) atomicOr(status, 1);
+    if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1) ok = 0;
     s_ok = ok;
   }
   __syncthreads();
   return s_ok != 0;
 }
 
+// Thread index for one phase of the persistent kernel. It passes through an
+// empty asm so that the index arithmetic of each phase stays inside that
+// phase: hoisted out of the step loop, every phase's per-thread addresses
+// would stay live across all the others and spill.
+__device__ inline int phase_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+// The workgroup index and grid size likewise (scalar registers).
+__device__ inline int phase_blk() {
+  int t = blockIdx.x;
+  asm volatile("" : "+s"(t));
+  return t;
+}
+__device__ inline int phase_grid() {
+  int t = gridDim.x;
+  asm volatile("" : "+s"(t));
+  return t;
+}
+
 // All steps of all environments in one launch (grid: co-resident, multiple of
-// 8). The launch bound asks for at least 4 waves per SIMD (at most 128 VGPRs),
-// so that two 512-thread workgroups share a CU; the collide phase gives each
-// workgroup a contiguous range of items.
+// 8). The launch bound asks for at least 6 waves per SIMD (at most 80 VGPRs):
+// three 512-thread workgroups per CU. The collide phase takes its items from
+// a work queue in launch order.
 template <bool UNI>
-__global__ void __launch_bounds__(WG, 4) kb_persistent(BatchArgs b, int nsteps) {
+__global__ void __launch_bounds__(WG, 6) kb_persistent(BatchArgs b, int nsteps) {
   __shared__ int s_pre[kMaxEnvs + 1];
-  const int tid = threadIdx.x;
   for (int s = 0; s < nsteps; ++s) {
-    for (int item = blockIdx.x; item < b.tot[PRE_SKIN]; item += gridDim.x) phase_skin(b, s, item, tid);
-    if (!grid_sync(b)) return;
-    for (int item = blockIdx.x; item < b.tot[PRE_ACTIVE]; item += gridDim.x) phase_active(b, item, tid);
-    if (!grid_sync(b)) return;
-    int tot = dynamic_prefix(b, 1, s_pre, tid);
-    for (int item = blockIdx.x; item < tot; item += gridDim.x) phase_macro<UNI>(b, s, item, s_pre, tid);
-    if (!grid_sync(b)) return;
-    tot = dynamic_prefix(b, kSpreadSplit, s_pre, tid);
-    for (int pass = 0; pass < b.mdf; ++pass) {
-      if (pass > 0) {
-        for (int item = blockIdx.x; item < tot; item += gridDim.x) phase_spread(b, s, false, item, s_pre, tid);
-        if (!grid_sync(b)) return;
-      }
-      for (int item = blockIdx.x; item < b.tot[PRE_INTERP]; item += gridDim.x)
-        phase_interp<UNI>(b, s, pass, item, tid);
-      if (!grid_sync(b)) return;
+    {
+      const int tid = phase_tid(), blk = phase_blk(), grid = phase_grid();
+      for (int item = blk; item < b.tot[PRE_SKIN]; item += grid) phase_skin(b, s, item, tid);
     }
-    for (int item = blockIdx.x; item < tot; item += gridDim.x) phase_spread(b, s, true, item, s_pre, tid);
     if (!grid_sync(b)) return;
     {
-      const int total = b.tot[PRE_COLLIDE];
-      const int per = (total + (int)gridDim.x - 1) / (int)gridDim.x;
-      const int i0 = min(total, (int)blockIdx.x * per);
-      collide_range<UNI>(b, s, i0, min(total, i0 + per), tid);
+      const int tid = phase_tid(), blk = phase_blk(), grid = phase_grid();
+      for (int item = blk; item < b.tot[PRE_ACTIVE]; item += grid) phase_active(b, item, tid);
+    }
+    if (!grid_sync(b)) return;
+    {
+      const int tid = phase_tid(), blk = phase_blk(), grid = phase_grid();
+      const int tot = dynamic_prefix(b, 1, s_pre, tid);
+      for (int item = blk; item < tot; item += grid) phase_macro<UNI>(b, s, item, s_pre, tid);
+    }
+    if (!grid_sync(b)) return;
+    int tot;
+    {
+      const int tid = phase_tid();
+      tot = dynamic_prefix(b, kSpreadSplit, s_pre, tid);
+    }
+    for (int pass = 0; pass < b.mdf; ++pass) {
+      if (pass > 0) {
+        const int tid = phase_tid(), blk = phase_blk(), grid = phase_grid();
+        for (int item = blk; item < tot; item += grid) phase_spread(b, s, false, item, s_pre, tid);
+        if (!grid_sync(b)) return;
+      }
+      {
+        const int tid = phase_tid(), blk = phase_blk(), grid = phase_grid();
+        for (int item = blk; item < b.tot[PRE_INTERP]; item += grid)
+          phase_interp<UNI>(b, s, pass, item, tid);
+      }
+      if (!grid_sync(b)) return;
+    }
+    {
+      const int tid = phase_tid(), blk = phase_blk(), grid = phase_grid();
+      for (int item = blk; item < tot; item += grid) phase_spread(b, s, true, item, s_pre, tid);
+    }
+    if (!grid_sync(b)) return;
+    {
+      collide_queue<UNI>(b, s, phase_tid());
     }
     if (!grid_sync(b)) return;
   }

@@ -33,20 +33,19 @@ constexpr int kInterpPer = WG / 64;  // markers per interpolation item
 
 __device__ inline int stencil_base(float X) { return (int)floorf(X) - 1; }
 
-// Distinct tiles along one axis touched by nodes base..base+3 (wrapped when
-// periodic). At most 3.
-__device__ inline int axis_tiles(int base, int n, bool per, int out[3]) {
-  int cnt = 0;
+// Tiles of the nodes base..base+3 along one axis (wrapped when periodic),
+// one per node; first[s] is false when node s's tile repeats an earlier
+// node's. Fixed-size and fully unrolled, so everything stays in registers.
+__device__ inline void axis_node_tiles(int base, int n, bool per, int t[4], bool first[4]) {
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     int j = base + s;
     if (per) j = wrap_idx(j, n);
-    int t = j >> 3;
-    bool dup = false;
-    for (int q = 0; q < cnt; ++q) dup |= out[q] == t;
-    if (!dup && cnt < 3) out[cnt++] = t;
+    t[s] = j >> 3;
+    first[s] = true;
+#pragma unroll
+    for (int q = 0; q < s; ++q) first[s] = first[s] && t[q] != t[s];
   }
-  return cnt;
 }
 
 __device__ inline bool axis_touches(int base, int n, bool per, int tile) {
@@ -60,9 +59,21 @@ __device__ inline bool axis_touches(int base, int n, bool per, int tile) {
   return hit;
 }
 
+// Value of lane (this lane ^ o) of the wave (ds_bpermute). The lane id
+// passes through an empty asm so that its arithmetic is redone where it is
+// used: in the persistent kernel, hoisting it out of the step loop would hold
+// one register per offset across every phase.
+__device__ inline int xor_lane_addr(int o) {
+  int lane = __lane_id();
+  asm volatile("" : "+v"(lane));
+  return (lane ^ o) << 2;
+}
+__device__ inline int shfl_xor_i(int v, int o) { return __builtin_amdgcn_ds_bpermute(xor_lane_addr(o), v); }
+__device__ inline float shfl_xor_f(float v, int o) { return __int_as_float(shfl_xor_i(__float_as_int(v), o)); }
+
 __device__ inline float wave_sum(float v) {
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  for (int o = 32; o > 0; o >>= 1) v += shfl_xor_f(v, o);
   return v;
 }
 
@@ -110,6 +121,9 @@ __device__ inline void skin_item(const EnvView &e, const float *__restrict__ pos
         v[r] += w * (P[12 + 3 * r] * r0 + P[12 + 3 * r + 1] * r1 + P[12 + 3 * r + 2] * r2 + P[21 + r]);
         nv[r] += w * (P[3 * r] * n0 + P[3 * r + 1] * n1 + P[3 * r + 2] * n2);
       }
+      // one bone's 24 pose values live at a time: keeps the phase within the
+      // register budget of the kernels it is inlined into
+      __builtin_amdgcn_sched_barrier(0);
     }
     if (e.slip) {  // the rest normal turned by the blended rotations, unit length
       const float il = rsqrtf(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
@@ -133,13 +147,18 @@ __device__ inline void skin_item(const EnvView &e, const float *__restrict__ pos
     }
     const int bs[3] = {stencil_base(p[0]), stencil_base(p[1]), stencil_base(p[2])};
     e.mbase[k] = make_short4((short)bs[0], (short)bs[1], (short)bs[2], 0);
-    int tx[3], ty[3], tz[3];
-    const int nxt = axis_tiles(bs[0], e.g.nx, e.g.xper, tx);
-    const int nyt = axis_tiles(bs[1], e.g.ny, e.g.yper, ty);
-    const int nzt = axis_tiles(bs[2], e.g.nz, e.g.zper, tz);
-    for (int i = 0; i < nzt; ++i)
-      for (int j = 0; j < nyt; ++j)
-        for (int l = 0; l < nxt; ++l) e.tile_flag[tx[l] + e.g.tnx * (ty[j] + e.g.tny * tz[i])] = 1;
+    int tx[4], ty[4], tz[4];
+    bool fx[4], fy[4], fz[4];
+    axis_node_tiles(bs[0], e.g.nx, e.g.xper, tx, fx);
+    axis_node_tiles(bs[1], e.g.ny, e.g.yper, ty, fy);
+    axis_node_tiles(bs[2], e.g.nz, e.g.zper, tz, fz);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int l = 0; l < 4; ++l)
+          if (fz[i] && fy[j] && fx[l]) e.tile_flag[tx[l] + e.g.tnx * (ty[j] + e.g.tny * tz[i])] = 1;
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
       if (bs[ax] < 0 || bs[ax] + 3 >= dims[ax]) {  // wrapping stencil: whole axis
@@ -155,8 +174,8 @@ __device__ inline void skin_item(const EnvView &e, const float *__restrict__ pos
   for (int ax = 0; ax < 3; ++ax) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
-      lo[ax] = min(lo[ax], __shfl_xor(lo[ax], o, 64));
-      hi[ax] = max(hi[ax], __shfl_xor(hi[ax], o, 64));
+      lo[ax] = min(lo[ax], shfl_xor_i(lo[ax], o));
+      hi[ax] = max(hi[ax], shfl_xor_i(hi[ax], o));
     }
   }
   if ((tid & 63) == 0 && k < n)
@@ -813,7 +832,7 @@ __device__ inline void cg_update_item(const EnvView &e, const FrameF &fr, int it
   // groups of kInterpPer consecutive markers form one interpolation item
 #pragma unroll
   for (int qd = 0; qd < 7; ++qd)
-    for (int o = kInterpPer / 2; o > 0; o >>= 1) part[qd] += __shfl_xor(part[qd], o, kInterpPer);
+    for (int o = kInterpPer / 2; o > 0; o >>= 1) part[qd] += shfl_xor_f(part[qd], o);
   const int it = k / kInterpPer;
   if ((k % kInterpPer) == 0 && k < n)
 #pragma unroll

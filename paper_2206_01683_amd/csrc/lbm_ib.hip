@@ -1183,7 +1183,7 @@ size_t batch_layout(int nenv, size_t *o_envs, size_t *o_pre, size_t *o_bar) {
   *o_pre = o;
   o = align_up(o + sizeof(int) * PRE_ROWS * (size_t)(nenv + 1), 256);
   *o_bar = o;
-  o = align_up(o + 64, 256);
+  o = align_up(o + sizeof(unsigned) * kBarWords, 256);
   return o;
 }
 
@@ -1255,13 +1255,12 @@ BatchArgs batch_args(const lbm_batch *b) {
   for (int q = 0; q < 4; ++q) a.tot[q] = b->tot[q];
   a.mdf = b->mdf;
   a.bar = b->d_bar;
-  a.status = b->d_status;
   return a;
 }
 
 template <int K>
 void launch_kb_collide(const BatchArgs &a, int s, int item0, int n, hipStream_t st) {
-  kb_collide<K><<<n, WG, 0, st>>>(a, s, item0);
+  kb_collide<K><<<n, WG, 0, st>>>(a, a.envs, a.pre, a.corder, s, item0);
 }
 
 template <int... K>
@@ -1371,7 +1370,7 @@ lbm_status lbm_batch_create(lbm_batch **out, const lbm_env *envs, int32_t nenv, 
   b->d_envs = reinterpret_cast<EnvView *>(base + o_envs);
   b->d_pre = reinterpret_cast<int *>(base + o_pre);
   b->d_bar = reinterpret_cast<unsigned *>(base + o_bar);
-  b->d_status = reinterpret_cast<int *>(base + o_bar + 32);
+  b->d_status = reinterpret_cast<int *>(b->d_bar + BAR_STATUS);
   b->mdf = envs[0].ctx->p.mdf_iters;
   b->stream = static_cast<hipStream_t>(hip_stream);
   b->graph = nullptr;
@@ -1399,8 +1398,9 @@ lbm_status lbm_batch_create(lbm_batch **out, const lbm_env *envs, int32_t nenv, 
     delete b;
     return LBM_ERR_DEVICE;
   }
-  for (int u = 0; u < 2; ++u) b->persistent_grid[u] = std::max(8, (per_cu[u] * cus) / 8 * 8);
-  k_fill_int<<<1, 64, 0, b->stream>>>(reinterpret_cast<int *>(b->d_bar), 0, 16);
+  for (int u = 0; u < 2; ++u)
+    b->persistent_grid[u] = std::min(kBarGroup * kBarMaxGroups, std::max(8, (per_cu[u] * cus) / 8 * 8));
+  k_fill_int<<<8, 256, 0, b->stream>>>(reinterpret_cast<int *>(b->d_bar), 0, kBarWords);
   lbm_status st = launched();
   if (st == LBM_OK) st = batch_upload(b);
   if (st != LBM_OK) {
@@ -1528,7 +1528,7 @@ lbm_status lbm_batch_check(lbm_batch *b) {
   if (status & 1) {
     // a barrier timed out: the run stopped early and the barrier counters are
     // stale; reset them (and the flag) so the next run starts clean
-    k_fill_int<<<1, 64, 0, b->stream>>>(reinterpret_cast<int *>(b->d_bar), 0, 16);
+    k_fill_int<<<8, 256, 0, b->stream>>>(reinterpret_cast<int *>(b->d_bar), 0, kBarWords);
     if (launched() != LBM_OK || hipStreamSynchronize(b->stream) != hipSuccess) return LBM_ERR_DEVICE;
     return LBM_ERR_DEVICE;
   }
