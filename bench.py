@@ -31,6 +31,7 @@ METRIC = "MLUPS and % of HBM roofline per GPU; adjoint/forward time ratio"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "collide_traffic.txt")
 # the sources k_collide is compiled from (its lattice, storage, view of the context, and the kernel itself)
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2206_01683_amd", "csrc", f) for f in ("lattice.hpp", "env.hpp", "fluid.hpp")]
+MAIN_KERNEL = "k_collide"
 
 
 def kernel_source_hash() -> str:
@@ -57,7 +58,8 @@ def measured_traffic(storage: str):
     return float(vals[key]) if key in vals else None
 
 
-def run_gpu(storage: str, steps: int, warmup: int, block=(0, 0), collision: int = 0, variant=None):
+def run_gpu(storage: str, steps: int, warmup: int, block=(0, 0), collision: int = 0, variant=None,
+            ib_workgroups: int = 0):
     """The fish workload; variant (optional) edits it first (faces, frames)."""
     import numpy as np
     import torch
@@ -69,7 +71,8 @@ def run_gpu(storage: str, steps: int, warmup: int, block=(0, 0), collision: int 
     if variant is not None:
         variant(w)
     sim = lbm.Simulation(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi, storage=storage, max_markers=w.markers.n,
-                         max_bones=w.markers.nbones, block=block, collision=collision, bc_y=w.bc_y, bc_z=w.bc_z)
+                         max_bones=w.markers.nbones, block=block, collision=collision, bc_y=w.bc_y, bc_z=w.bc_z,
+                         ib_workgroups=ib_workgroups)
     dm = lbm.DeviceMarkers(w.markers)
     poses = torch.as_tensor(np.ascontiguousarray(w.poses, np.float32), device="cuda")
     wrench = torch.zeros((warmup + steps, 8), dtype=torch.float32, device="cuda")
@@ -369,9 +372,10 @@ def main():
     ap.add_argument("--storage", default="f32", choices=sorted(BYTES_PER_CELL))
     ap.add_argument("--cpu-steps", type=int, default=24, help="oracle sample length (0: skip)")
     ap.add_argument("--forms",
-                    default="ceiling,f16,bf16,trt,faces_frames,batched,adjoint,two_fish,free_swimmer,ib_schemes",
-                    help="comma-separated extra forms to measure: ceiling, f16, bf16, trt, faces_frames, batched, "
-                         "adjoint, two_fish, free_swimmer, ib_schemes")
+                    default="ceiling,f16,bf16,overlap,trt,faces_frames,batched,adjoint,two_fish,free_swimmer,"
+                            "ib_schemes",
+                    help="comma-separated extra forms to measure: ceiling, f16, bf16, overlap, trt, faces_frames, "
+                         "batched, adjoint, two_fish, free_swimmer, ib_schemes")
     ap.add_argument("--no-forms", action="store_true", help="measure no extra form")
     ap.add_argument("--block", type=int, nargs=2, default=(0, 0))
     ap.add_argument("--batch-envs", type=int, default=64, help="batched form: environments (0: skip)")
@@ -402,6 +406,13 @@ def main():
             forms[st] = {"mlups": round(r["mlups"], 1), "collide_GBps": round(r["collide_gbs"], 1),
                          "collide_frac_of_hbm_peak": round(r["collide_gbs"] / HBM_PEAK_GBS, 4),
                          "bytes_per_cell": BYTES_PER_CELL[st], "status": r["status"]}
+    if "overlap" in want:
+        # the IB chain beside the collide in one launch (k_step_overlap, 64 chain workgroups)
+        r = run_gpu(args.storage, args.steps, args.warmup, tuple(args.block), ib_workgroups=64)
+        forms["overlap"] = {"mlups": round(r["mlups"], 1), "ib_workgroups": 64,
+                            "skin_binning_ms_per_step": round(r["ib_avg_ms"], 5),
+                            "main_launch_ms": round(r["collide_avg_ms"], 5),
+                            "main_launch_GBps_216B": round(r["collide_gbs"], 1), "status": r["status"]}
     if "trt" in want:
         from paper_2206_01683_amd import lbm as _lbm
         r = run_gpu(args.storage, args.steps, args.warmup, tuple(args.block), collision=_lbm.COLLIDE_TRT)
@@ -462,7 +473,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic, 0),
-                     "kernel": "k_collide", "bytes_per_cell": BYTES_PER_CELL[args.storage],
+                     "kernel": MAIN_KERNEL, "bytes_per_cell": BYTES_PER_CELL[args.storage],
                      "cells_per_launch": main_run["ncell"],
                      "avg_launch_ms": round(main_run["collide_avg_ms"], 5)},
         "step_hbm_frac": round(main_run["mlups"] * 1e6 * BYTES_PER_CELL[args.storage] / (HBM_PEAK_GBS * 1e9), 4),

@@ -53,6 +53,7 @@ struct EnvView {
   float *partials;
   float4 *macro;
   unsigned long long *gfix;
+  unsigned *sched;              // scheduling words of the overlapped step (single lattice), or null
   float *rec, *mstate;
   // implicit velocity correction (null with direct forcing)
   unsigned long long *gcg;      // fixed-point spread of the search direction, as gfix

@@ -31,6 +31,13 @@ constexpr int REC = 20;              // floats per marker record: w[12], base[3]
 constexpr int kSpreadSplit = 4;      // spreading work items per active tile
 constexpr int kInterpPer = WG / 64;  // markers per interpolation item
 
+// Scheduling words of the overlapped step (step.hpp), each on its own
+// 128-byte line, in the workspace (EnvView::sched): the chain's barrier
+// arrival count and generation, and the count of chain workgroups that have
+// finished. active_item clears the arrival and done counts each step.
+constexpr int kSchedLine = 32;
+enum : int { SCHED_ARRIVE = 0, SCHED_GEN = kSchedLine, SCHED_DONE = 2 * kSchedLine, SCHED_WORDS = 3 * kSchedLine };
+
 __device__ inline int stencil_base(float X) { return (int)floorf(X) - 1; }
 
 // Tiles of the nodes base..base+3 along one axis (wrapped when periodic),
@@ -193,6 +200,10 @@ __device__ inline void active_item(const EnvView &e, int item, int tid) {
   __shared__ int s_base;
   const int lane = tid & 63, wv = tid >> 6;
   const int t = item * WG + tid;
+  if (item == 0 && tid == 0 && e.sched != nullptr) {
+    e.sched[SCHED_ARRIVE] = 0u;
+    e.sched[SCHED_DONE] = 0u;
+  }
   int f = 0;
   if (t < e.ntiles) {
     f = e.tile_flag[t] != 0;

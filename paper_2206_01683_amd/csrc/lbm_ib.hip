@@ -19,6 +19,7 @@
 #include "../../include/lbm_ib.h"
 #include "adjoint.hpp"
 #include "batch.hpp"
+#include "step.hpp"
 #include "swimmer.hpp"
 
 using namespace lbmib;
@@ -29,6 +30,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Workspace layout (all offsets 256-byte aligned).
 struct Layout {
+  size_t sched;             // scheduling words of the overlapped step
   int tnx, tny, tnz, ntiles, cap, maxm;
   size_t guard, counters, tile_flag, tile_slot, active, mbase, chunk_box, partials, macro, gbuf, rec, mstate;
   size_t gbar, adjfix, mbar, pbar, facebuf;
@@ -60,6 +62,7 @@ bool params_ok(const lbm_params *p) {
   if (p->collision == LBM_COLLIDE_TRT && !(p->trt_lambda > 0.0 && std::isfinite(p->trt_lambda))) return false;
   if (p->wall_mode != LBM_WALL_NO_SLIP && p->wall_mode != LBM_WALL_SLIP) return false;
   if (p->layout != LBM_LAYOUT_AUTO && p->layout != LBM_LAYOUT_PLANES && p->layout != LBM_LAYOUT_ROWS) return false;
+  if (p->ib_workgroups < -1 || p->ib_workgroups > 1024) return false;
   return true;
 }
 
@@ -109,6 +112,7 @@ Layout layout(const lbm_params *p) {
   };
   L.guard = take(64);
   L.counters = take(64);
+  L.sched = take(sizeof(unsigned) * SCHED_WORDS);
   L.tile_flag = take(sizeof(int) * L.ntiles);
   L.tile_slot = take(sizeof(int) * L.ntiles);
   L.active = take(sizeof(int) * L.cap);
@@ -282,6 +286,7 @@ EnvView env_view(lbm_ctx *c, const lbm_markers *m) {
   e.active = wsp<int>(c, c->L.active);
   e.counters = wsp<int>(c, c->L.counters);
   e.guard = wsp<int>(c, c->L.guard);
+  e.sched = wsp<unsigned>(c, c->L.sched);
   e.mbase = wsp<short4>(c, c->L.mbase);
   e.chunk_box = wsp<int4>(c, c->L.chunk_box);
   e.partials = wsp<float>(c, c->L.partials);
@@ -331,6 +336,63 @@ lbm_status launch_collide(lbm_ctx *c, const EnvView &e, const FrameF &fr, bool r
     collide_kernels<S, true>(e, fr, c->cur, grid, blk, c->stream, xper, rot, yz);
   else
     collide_kernels<S, false>(e, fr, c->cur, grid, blk, c->stream, xper, rot, yz);
+  return launched();
+}
+
+template <class S, bool TRT>
+void step_overlap_kernels(const EnvView &e, const FrameF &fr, int cur, int grid, int nib, int passes, float *wrench,
+                          hipStream_t s, bool xper, bool rot, bool yz) {
+  if (yz) {  // open y or z faces
+    if (xper && rot)
+      k_step_overlap<S, true, true, true, TRT><<<grid, WG, 0, s>>>(e, fr, cur, nib, passes, wrench);
+    else if (xper)
+      k_step_overlap<S, true, false, true, TRT><<<grid, WG, 0, s>>>(e, fr, cur, nib, passes, wrench);
+    else if (rot)
+      k_step_overlap<S, false, true, true, TRT><<<grid, WG, 0, s>>>(e, fr, cur, nib, passes, wrench);
+    else
+      k_step_overlap<S, false, false, true, TRT><<<grid, WG, 0, s>>>(e, fr, cur, nib, passes, wrench);
+  } else if (xper && rot) {
+    k_step_overlap<S, true, true, false, TRT><<<grid, WG, 0, s>>>(e, fr, cur, nib, passes, wrench);
+  } else if (xper) {
+    k_step_overlap<S, true, false, false, TRT><<<grid, WG, 0, s>>>(e, fr, cur, nib, passes, wrench);
+  } else if (rot) {
+    k_step_overlap<S, false, true, false, TRT><<<grid, WG, 0, s>>>(e, fr, cur, nib, passes, wrench);
+  } else {
+    k_step_overlap<S, false, false, false, TRT><<<grid, WG, 0, s>>>(e, fr, cur, nib, passes, wrench);
+  }
+}
+
+// Whether the immersed-boundary chain runs beside the collide this step: on
+// request only (ib_workgroups > 0 chain workgroups, direct forcing). Under the
+// collide's load the chain's dependent accesses slow several-fold, so the band
+// blocks often end up waiting for it. Measured on the 384x192x192 fish: 8, 16,
+// 32, 64, 128 and 256 chain workgroups gave a 1251, 857, 664, 549, 553 and
+// 577 us launch, against 50 + 522 us for the chain's own launches followed by
+// the collide; the launch then moves 5.5 TB/s where the collide alone moves
+// 5.9. With 2-byte storage (367 against 314 us per step), four forcing passes,
+// or lattices small for their markers (the 150x50x100 two-fish domain, the
+// 128x64x64 fin: 1.5-2x slower) it loses.
+bool overlap_chain(const lbm_ctx *c) { return c->p.ib_scheme == LBM_IB_DIRECT && c->p.ib_workgroups > 0; }
+
+// The band macros, interpolation and spreading beside the collide, in one
+// launch (k_step_overlap); the collide blocks take 512 cells each (the
+// context's 2-D shape if it has 512 cells, else 512 consecutive cells).
+template <class S>
+lbm_status launch_step_overlap(lbm_ctx *c, const EnvView &e0, const FrameF &fr, bool rot, float *wrench) {
+  EnvView e = e0;
+  if (!(c->by > 0 && c->bx * c->by == WG)) {
+    e.bx = WG;
+    e.by = 0;
+    e.gx = e.gy = 0;
+    e.nblocks = (int)(((size_t)c->p.nx * c->p.ny * c->p.nz + WG - 1) / WG);
+  }
+  const int nib = c->p.ib_workgroups;
+  const int grid = nib + e.nblocks;
+  const bool yz = !(e.g.yper && e.g.zper), xper = e.g.xper != 0;
+  if (c->p.collision == LBM_COLLIDE_TRT)
+    step_overlap_kernels<S, true>(e, fr, c->cur, grid, nib, c->p.mdf_iters, wrench, c->stream, xper, rot, yz);
+  else
+    step_overlap_kernels<S, false>(e, fr, c->cur, grid, nib, c->p.mdf_iters, wrench, c->stream, xper, rot, yz);
   return launched();
 }
 
@@ -407,6 +469,16 @@ lbm_status step_one(lbm_ctx *c, const lbm_markers *m, const float *pose, const l
     k_active<<<(e.ntiles + WG - 1) / WG, WG, 0, c->stream>>>(e);
     if ((st = launched()) != LBM_OK) return st;
     c->slots_dirty = true;
+    if (overlap_chain(c)) {
+      // the rest of the chain beside the collide, in one launch
+      prof_mark(c, 1);
+      if ((st = launch_step_overlap<S>(c, e, fr, rot, wrench)) != LBM_OK) return st;
+      prof_mark(c, 2);
+      if (c->prof && c->prof_used < kProfSteps) c->prof_used++;
+      c->cur ^= 1;
+      c->steps += 1;
+      return LBM_OK;
+    }
     if ((st = launch_macro<S>(c, e, fr, rot)) != LBM_OK) return st;
     const int passes = c->p.mdf_iters;
     if (c->p.ib_scheme == LBM_IB_IMPLICIT) {

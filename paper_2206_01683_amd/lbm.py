@@ -40,7 +40,7 @@ class Params(ctypes.Structure):
                 ("with_adjoint", ctypes.c_int32), ("tau", ctypes.c_double), ("ib_alpha", ctypes.c_double),
                 ("bc_y", ctypes.c_int32 * 2), ("bc_z", ctypes.c_int32 * 2), ("ib_scheme", ctypes.c_int32),
                 ("collision", ctypes.c_int32), ("trt_lambda", ctypes.c_double), ("wall_mode", ctypes.c_int32),
-                ("layout", ctypes.c_int32)]
+                ("layout", ctypes.c_int32), ("ib_workgroups", ctypes.c_int32)]
 
 
 class Frame(ctypes.Structure):
@@ -165,17 +165,19 @@ def _check(rc: int, what: str):
 def make_params(nx, ny, nz, tau, bc_lo=BC_PERIODIC, bc_hi=BC_PERIODIC, storage="f32", max_markers=0,
                 max_bones=1, mdf_iters=1, ib_alpha=1.0, max_active_tiles=0, block=(0, 0), with_adjoint=False,
                 bc_y=(BC_PERIODIC, BC_PERIODIC), bc_z=(BC_PERIODIC, BC_PERIODIC), ib_scheme=0, collision=0,
-                trt_lambda=TRT_MAGIC, wall_mode=0, layout=LAYOUT_AUTO) -> Params:
+                trt_lambda=TRT_MAGIC, wall_mode=0, layout=LAYOUT_AUTO, ib_workgroups=0) -> Params:
     """ib_scheme: IB_DIRECT (direct forcing, mdf_iters passes) or IB_IMPLICIT
     (implicit velocity correction, mdf_iters conjugate-gradient steps).
     collision: COLLIDE_BGK or COLLIDE_TRT with Lambda = trt_lambda.
     wall_mode: WALL_NO_SLIP or WALL_SLIP (normal component only).
     layout: LAYOUT_AUTO, LAYOUT_PLANES or LAYOUT_ROWS (stored populations).
+    ib_workgroups: workgroups running the IB phases beside the collide (0
+    automatic); -1 runs them before the collide in launches of their own.
     block: collide block (bx, by); (bx, -1) is bx consecutive cells."""
     return Params(nx, ny, nz, bc_lo, bc_hi, STORAGE[storage] if isinstance(storage, str) else storage,
                   max_markers, max_bones, mdf_iters, max_active_tiles, block[0], block[1], 1 if with_adjoint else 0,
                   tau, ib_alpha, (ctypes.c_int32 * 2)(*bc_y), (ctypes.c_int32 * 2)(*bc_z), ib_scheme, collision,
-                  trt_lambda, wall_mode, layout)
+                  trt_lambda, wall_mode, layout, ib_workgroups)
 
 
 def frames_array(frames: np.ndarray) -> np.ndarray:
@@ -224,7 +226,7 @@ class Simulation:
                  max_bones=1, mdf_iters=1, ib_alpha=1.0, rho0=None, u0=None, device="cuda", block=(0, 0),
                  max_active_tiles=0, stream=None, with_adjoint=False, bc_y=(BC_PERIODIC, BC_PERIODIC),
                  bc_z=(BC_PERIODIC, BC_PERIODIC), ib_scheme=0, collision=0, trt_lambda=TRT_MAGIC, wall_mode=0,
-                 static_workspace=False, layout=LAYOUT_AUTO):
+                 static_workspace=False, layout=LAYOUT_AUTO, ib_workgroups=0):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the lattice Boltzmann library runs only on the GPU")
         L = lib()
@@ -232,7 +234,7 @@ class Simulation:
         self.shape = (nz, ny, nx)
         self.params = make_params(nx, ny, nz, tau, bc_lo, bc_hi, storage, max_markers, max_bones, mdf_iters,
                                   ib_alpha, max_active_tiles, block, with_adjoint, bc_y, bc_z, ib_scheme,
-                                  collision, trt_lambda, wall_mode, layout)
+                                  collision, trt_lambda, wall_mode, layout, ib_workgroups)
         pb = L.lbm_population_bytes(ctypes.byref(self.params))
         wb = L.lbm_workspace_bytes(ctypes.byref(self.params))
         if pb == 0 or wb == 0:

@@ -208,3 +208,10 @@ def test_ceiling_library_exports_and_validates():
     assert C.hbm_pull27(p, q, 8, 8, 8, 8, 64, None) == -1       # rows need rs = 27 nx
     assert C.hbm_pull27(p, q, 8, 8, 8, 100, 8, None) == -1      # planes need ps >= cells
     assert C.hbm_pull27(p, q, 0, 8, 8, 8, 216, None) == -1
+
+
+def test_ib_workgroups_parameter_is_validated(L):
+    for v in (-1, 0, 1, 64, 1024):
+        assert L.lbm_population_bytes(ctypes.byref(lbm.make_params(64, 16, 16, 0.6, ib_workgroups=v))) > 0
+    for v in (-2, 1025):
+        assert L.lbm_population_bytes(ctypes.byref(lbm.make_params(64, 16, 16, 0.6, ib_workgroups=v))) == 0
