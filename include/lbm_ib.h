@@ -220,7 +220,10 @@ lbm_status lbm_population_strides(const lbm_params *p, int64_t *strides);
 /* Create a context bound to caller buffers f_a, f_b (lbm_population_bytes
  * each), workspace (lbm_workspace_bytes, 256-byte aligned) and a HIP stream
  * (hipStream_t, NULL = default stream), and set the initial state to the
- * equilibrium f_i = f^eq_i(rho0, u0).
+ * equilibrium f_i = f^eq_i(rho0, u0). This sets up the paper's local fluid
+ * domain (Sec. III-B, Simulation: a grid of given resolution around the
+ * body, fluid density and viscosity as the relaxation time tau) for the
+ * lattice Boltzmann solution of Eq. (2).
  *   rho0 [nz][ny][nx] or NULL (rho = 1);  u0 [3][nz][ny][nx] or NULL (u = 0).
  * *out receives the context (host memory owned by the library; release with
  * lbm_destroy). Queues device work; does not synchronize. */
@@ -259,13 +262,18 @@ lbm_status lbm_load_populations(lbm_ctx *c, const float *f);
 lbm_status lbm_read_populations(lbm_ctx *c, float *f);
 
 /* Density rho [nz][ny][nx] and fluid velocity u [3][nz][ny][nx] of the
- * current pre-collision state: u solves u = (m + a0/2 - omega x u)/rho with
- * a0 the frame force of Eq. (3) at that node, i.e. the velocity with the
- * frame force but without immersed-boundary force. Either output may be NULL.
- * frame [host] may be NULL (inertial frame). */
+ * current pre-collision state (the macroscopic fields of Eq. (2)): u solves
+ * u = (m + a0/2 - omega x u)/rho with a0 the frame force of Eq. (3) at that
+ * node, i.e. the velocity with the frame force but without immersed-boundary
+ * force. Either output may be NULL. frame [host] may be NULL (inertial
+ * frame). */
 lbm_status lbm_macros(lbm_ctx *c, const lbm_frame *frame, float *rho, float *u);
 
-/* Advance nsteps time steps. For step s (global step n = current + s):
+/* Advance nsteps time steps of the paper's coupled fluid-structure step
+ * (Sec. III-B: the lattice Boltzmann solution of Eq. (2) in the local frame,
+ * with the fictitious body force of Eq. (3), the immersed boundary of the
+ * skinned surface of Sec. III-A, and the open-domain faces of Sec. III-B,
+ * Simulation). For step s (global step n = current + s):
  *   skin the markers with poses[s] -> X, U; interpolate the unforced velocity
  *   and density to the markers; direct forcing -> F; spread -> g; collide
  *   (BGK + Guo with g and the frame force of frames[s]) and stream; open
