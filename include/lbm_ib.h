@@ -389,19 +389,26 @@ lbm_status lbm_adjoint_sweep(lbm_ctx *c, const void *ckpt, void *const *ring, in
  * I_c the chain's moment of inertia about its mass centre and L_s the angular
  * momentum of its shape change. The local domain follows the mass centre
  * (Sec. III-B), so the frame's velocity is the body's and its acceleration
- * enters the fluid by Eq. (3). Unit time steps, explicit coupling:
- *   a(n+1) = F(n)/M + r a(n),  V(n+1) = V(n) + a(n)      (translation)
- *   L(n+1) = L(n) + T(n) + r I_c(n) (theta'(n) - theta'(n-1)),
- *   theta'(n+1) = (L(n+1) - L_s(n+1)) / I_c(n+1),  theta(n+1) = theta(n) + theta'(n+1)
+ * enters the fluid by Eq. (3). Unit time steps, with k = added_mass:
+ *   (1 + k) a(n+1) = F(n)/M + (r + k) a(n),  V(n+1) = V(n) + a(n)     (translation)
+ *   (1 + k) I_c(n+1) theta'(n+1) = L(n) + T(n) + (r I_c(n) + k I_c(n+1)) theta''(n)
+ *                                  - L_s(n+1) + k I_c(n+1) theta'(n),
+ *   L(n+1) = I_c(n+1) theta'(n+1) + L_s(n+1),  theta(n+1) = theta(n) + theta'(n+1),
+ *   theta''(n) = theta'(n) - theta'(n-1)
  * with r = rho_fluid / rho_body: the direct-forcing force includes the
  * reaction of the enclosed fluid, carried along with the body, and the r terms
  * add it back (rigid enclosed fluid). The frame acceleration of a step is
- * needed before its force is known, hence a(n+1) from F(n). Explicit coupling
- * is stable only for bodies heavier than the fluid (measured: rho_body /
- * rho_fluid >= 1.5 with free yaw on the swimmer tests; neutral buoyancy
- * diverges). The shape of a step is the body-frame heading psi_j of every
- * link and its rate (the chain of lbm_skin: joint j+1 = joint j + h (cos
- * psi_j, sin psi_j)). */
+ * needed before its force is known, hence a(n+1) from F(n). k = 0 is plain
+ * explicit coupling: if the fluid's force holds a reaction -m_a a(n) to the
+ * body's acceleration (added mass m_a, plus the enclosed fluid), a(n+1)
+ * carries -(m_a / M) a(n), which grows when m_a > M: bodies near neutral
+ * buoyancy diverge (measured: explicit coupling needs rho_body / rho_fluid >=
+ * 1.5 on the swimmer tests). k > 0 adds an artificial added mass k M (and
+ * inertia k I_c) to both sides: the factor becomes (k M - m_a) / (M + k M),
+ * of modulus below one whenever k > (m_a / M - 1) / 2, and a steady
+ * acceleration is unchanged ((M + m_a) a = F_ext). The shape of a step is the
+ * body-frame heading psi_j of every link and its rate (the chain of lbm_skin:
+ * joint j+1 = joint j + h (cos psi_j, sin psi_j)). */
 typedef struct {
   int32_t nbones;             /* links, 1 .. 64 */
   int32_t free_yaw;           /* 1: the body turns under the fluid's torque; 0: its heading is held */
@@ -412,6 +419,7 @@ typedef struct {
   const double *joints_rest;  /* [nbones][3] rest joint positions of the skin (lbm_markers' rest pose) */
   double fluid_ratio;         /* r = rho_fluid / rho_body, >= 0 (0: no enclosed fluid) */
   double origin[3];           /* where the mass centre sits in the local domain (the frame origin) */
+  double added_mass;          /* k >= 0: artificial added mass k M and inertia k I_c (0: explicit coupling) */
 } lbm_swimmer;
 
 typedef struct {

@@ -7,10 +7,15 @@ Model (the articulated body of Sec. III-A with every joint prescribed, the
 fluid force as the external generalized force of Eq. (1), the local domain of
 Sec. III-B following the body's mass centre):
   M dV/dt = F,   d/dt (I_c theta' + L_s) = T   (about the mass centre),
-stepped with r = rho_fluid / rho_body (the enclosed fluid's share) as
-  a(n+1) = F(n) / M + r a(n),   V(n+1) = V(n) + a(n),
-  L(n+1) = L(n) + T(n) + r I_c(n) (theta'(n) - theta'(n-1)),
-  theta'(n+1) = (L(n+1) - L_s(n+1)) / I_c(n+1),  theta(n+1) = theta(n) + theta'(n+1);
+stepped with r = rho_fluid / rho_body (the enclosed fluid's share) and an
+artificial added mass k (a multiple of the body's mass and inertia, put on
+both sides of the update; k = 0 is explicit coupling). Translation: the body
+with the extra mass k M, driven by the step's force plus the extra mass times
+the previous acceleration,
+  (M + k M) a(n+1) = F(n) + (r M + k M) a(n),   V(n+1) = V(n) + a(n);
+rotation: the angular momentum of the body and the extra inertia k I_c,
+  L(n+1) + k I_c' (theta'(n+1) - theta'(n)) = L(n) + T(n) + (r I_c + k I_c') (theta'(n) - theta'(n-1)),
+  L = I_c theta' + L_s (I_c' the next shape's), theta(n+1) = theta(n) + theta'(n+1);
 with the yaw held, theta' = 0 and L = L_s.
 Planar vectors are complex numbers here: rotation is multiplication by
 exp(i theta) and the z cross product is Im(conj(a) b)."""
@@ -20,7 +25,7 @@ from . import run as _fluid_run
 
 
 class Body:
-    def __init__(self, h, mass, com, inertia, joints_rest, fluid_ratio, origin, free_yaw=True):
+    def __init__(self, h, mass, com, inertia, joints_rest, fluid_ratio, origin, free_yaw=True, added_mass=0.0):
         self.h = float(h)
         self.mass = np.asarray(mass, dtype=np.float64)
         self.com = np.asarray(com, dtype=np.float64)
@@ -29,6 +34,7 @@ class Body:
         self.fluid_ratio = float(fluid_ratio)
         self.origin = np.asarray(origin, dtype=np.float64)
         self.free_yaw = bool(free_yaw)
+        self.added_mass = float(added_mass)
         self.M = float(self.mass.sum())
 
 
@@ -87,17 +93,21 @@ def prepare(body, st, psi, psid):
 
 def advance(body, st, wrench, psi_next, psid_next):
     F = complex(wrench[0], wrench[1])
-    r = body.fluid_ratio
+    r, k, M = body.fluid_ratio, body.added_mass, body.M
     a = st["acc"]
     st["vel"] = st["vel"] + a
     st["pos"] = st["pos"] + st["vel"]
-    st["acc"] = F / body.M + r * a
+    st["acc"] = (F + (r * M + k * M) * a) / (M + k * M)
     *_, Ic, Ls = shape(body, psi_next, psid_next)
     if body.free_yaw:
-        st["ang_mom"] = st["ang_mom"] + float(wrench[5]) + r * st["inertia"] * (st["spin"] - st["spin_prev"])
+        # unknown w = theta'(n+1): Ic w + Ls + k Ic (w - theta'(n)) = L(n) + T(n) + (r I_c(n) + k Ic) theta''(n)
+        dw = st["spin"] - st["spin_prev"]
+        budget = st["ang_mom"] + float(wrench[5]) + (r * st["inertia"] + k * Ic) * dw
+        w = (budget - Ls + k * Ic * st["spin"]) / (Ic + k * Ic)
         st["spin_prev"] = st["spin"]
-        st["spin"] = (st["ang_mom"] - Ls) / Ic
-        st["heading"] = st["heading"] + st["spin"]
+        st["spin"] = w
+        st["ang_mom"] = Ic * w + Ls
+        st["heading"] = st["heading"] + w
     else:
         st["spin"] = st["spin_prev"] = 0.0
         st["ang_mom"] = Ls

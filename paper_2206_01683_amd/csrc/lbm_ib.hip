@@ -1115,17 +1115,19 @@ lbm_status lbm_swimmer_advance(const lbm_swimmer *s, lbm_swimmer_state *st, cons
     if (!std::isfinite(wrench[q])) return LBM_ERR_ARG;
   ChainShape c;
   if (!chain_shape(s, psi_next, psidot_next, c)) return LBM_ERR_ARG;
-  const double M = chain_mass(s), r = s->fluid_ratio;
+  const double M = chain_mass(s), r = s->fluid_ratio, k = s->added_mass;
   for (int q = 0; q < 2; ++q) {
     const double a = st->acc[q];
     st->vel[q] += a;
     st->pos[q] += st->vel[q];
-    st->acc[q] = (double)wrench[q] / M + r * a;
+    st->acc[q] = ((double)wrench[q] / M + (r + k) * a) / (1.0 + k);
   }
   if (s->free_yaw) {
-    st->ang_mom += (double)wrench[5] + r * st->inertia * (st->spin - st->spin_prev);
+    const double dspin = st->spin - st->spin_prev, Ik = k * c.Ic;
+    const double rhs = st->ang_mom + (double)wrench[5] + (r * st->inertia + Ik) * dspin - c.Ls + Ik * st->spin;
     st->spin_prev = st->spin;
-    st->spin = (st->ang_mom - c.Ls) / c.Ic;
+    st->spin = rhs / (c.Ic + Ik);
+    st->ang_mom = c.Ic * st->spin + c.Ls;
     st->heading += st->spin;
   } else {  // heading held: a holding torque absorbs the rest
     st->spin_prev = st->spin = 0.0;

@@ -11,17 +11,21 @@
 // (Sec. III-B: the frame translates with the body), so the frame's velocity is
 // V and its acceleration enters the fluid through Eq. (3).
 //
-// Time stepping (unit steps, r = rho_fluid / rho_body):
-//   a(n+1) = F(n)/M + r a(n),  V(n+1) = V(n) + a(n),
-//   L(n+1) = L(n) + T(n) + r I_c(n) (theta'(n) - theta'(n-1)),
-//   theta'(n+1) = (L(n+1) - L_s(n+1)) / I_c(n+1),  theta(n+1) = theta(n) + theta'(n+1).
+// Time stepping (unit steps, r = rho_fluid / rho_body, k the artificial added
+// mass as a multiple of the body's):
+//   (1 + k) a(n+1) = F(n)/M + (r + k) a(n),  V(n+1) = V(n) + a(n),
+//   (1 + k) I_c(n+1) theta'(n+1) = L(n) + T(n) + (r I_c(n) + k I_c(n+1)) theta''(n)
+//                                  - L_s(n+1) + k I_c(n+1) theta'(n),
+//   L(n+1) = I_c(n+1) theta'(n+1) + L_s(n+1),  theta(n+1) = theta(n) + theta'(n+1).
 // The frame acceleration of step n is needed before step n's force is known,
 // hence a(n+1) from F(n). The direct-forcing force includes the reaction of
 // the fluid the body encloses, carried along with it; the r terms add it back
-// (enclosed fluid moving rigidly: mass r M, inertia r I_c). Measured on the
-// swimmer tests: with them the coupling is stable down to rho_body / rho_fluid
-// = 1.5 with free yaw; at neutral buoyancy explicit coupling diverges with or
-// without them (that would take sub-iterations or an implicit coupling).
+// (enclosed fluid moving rigidly: mass r M, inertia r I_c). With k = 0 this is
+// explicit coupling, stable on the swimmer tests down to rho_body / rho_fluid
+// = 1.5: a reaction -m_a a(n) in the force feeds back as -(m_a / M) a(n). The
+// k terms, added to both sides, turn that factor into (k M - m_a)/(M + k M),
+// so a k of order one keeps neutrally buoyant bodies stable, and leave a
+// steady acceleration unchanged.
 //
 // Host code only (no device work).
 #pragma once
@@ -88,6 +92,7 @@ inline double chain_mass(const lbm_swimmer *s) {
 inline bool swimmer_ok(const lbm_swimmer *s) {
   if (!s || s->nbones < 1 || s->nbones > 64 || !s->mass || !s->com || !s->inertia || !s->joints_rest) return false;
   if (!(s->link_length > 0.0) || !(s->fluid_ratio >= 0.0) || !std::isfinite(s->fluid_ratio)) return false;
+  if (!(s->added_mass >= 0.0) || !std::isfinite(s->added_mass)) return false;
   if (s->free_yaw != 0 && s->free_yaw != 1) return false;
   for (int j = 0; j < s->nbones; ++j)
     if (!(s->mass[j] > 0.0) || !(s->inertia[j] > 0.0) || !std::isfinite(s->com[j])) return false;

@@ -66,7 +66,8 @@ BATCH_SHAPES = ((64, 8), (128, 4), (256, 2), (512, 1), (512, 0))  # (512, 0): li
 class Swimmer(ctypes.Structure):
     _fields_ = [("nbones", ctypes.c_int32), ("free_yaw", ctypes.c_int32), ("link_length", ctypes.c_double),
                 ("mass", ctypes.c_void_p), ("com", ctypes.c_void_p), ("inertia", ctypes.c_void_p),
-                ("joints_rest", ctypes.c_void_p), ("fluid_ratio", ctypes.c_double), ("origin", ctypes.c_double * 3)]
+                ("joints_rest", ctypes.c_void_p), ("fluid_ratio", ctypes.c_double), ("origin", ctypes.c_double * 3),
+                ("added_mass", ctypes.c_double)]
 
 
 class SwimmerState(ctypes.Structure):

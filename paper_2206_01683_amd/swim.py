@@ -21,17 +21,20 @@ class FreeSwimmer:
     """Host dynamics of a planar chain (lbm_swimmer_*) with the mass
     properties of the fish body of length `length` (inputs.fish_link_mass)
     at density rho_body, enclosing fluid of density rho_fluid; its mass centre
-    sits at `origin` in the local domain. Explicit coupling needs rho_body
-    somewhat above rho_fluid (1.5 and up with free yaw on the tests)."""
+    sits at `origin` in the local domain. added_mass = 0 is explicit
+    coupling, which needs rho_body somewhat above rho_fluid (1.5 and up with
+    free yaw on the tests); an artificial added mass of order one (a multiple
+    of the body's mass and inertia, on both sides of the update) keeps a
+    neutrally buoyant body stable."""
 
-    def __init__(self, markers, length, origin, rho_body=2.0, rho_fluid=1.0, free_yaw=True):
+    def __init__(self, markers, length, origin, rho_body=2.0, rho_fluid=1.0, free_yaw=True, added_mass=0.0):
         nb = markers.nbones
         mass, com, inertia, volume = I.fish_link_mass(length, nb, rho_body)
         self._arrays = [np.ascontiguousarray(a, dtype=np.float64) for a in
                         (mass, com, inertia, np.asarray(markers.joints_rest, dtype=np.float64).reshape(nb, 3))]
         ptr = [a.ctypes.data for a in self._arrays]
         self.s = lbm.Swimmer(nb, 1 if free_yaw else 0, length / nb, ptr[0], ptr[1], ptr[2], ptr[3],
-                             rho_fluid / rho_body, (ctypes.c_double * 3)(*origin))
+                             rho_fluid / rho_body, (ctypes.c_double * 3)(*origin), float(added_mass))
         self.st = lbm.SwimmerState()
         self.nbones = nb
         self.mass = float(mass.sum())

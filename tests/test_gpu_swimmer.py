@@ -1,8 +1,9 @@
 """Free swimming on the GPU against the FP64 oracle: the body's rigid motion
 driven by the fluid's force (library host dynamics lbm_swimmer_*), the local
 domain following it, step by step. 40 coupled steps of a 1,000-marker fish
-twice as dense as the fluid with free yaw: velocity, heading and wrench
-series and the final flow agree."""
+with free yaw, twice as dense as the fluid with explicit coupling, and as
+dense as the fluid with an artificial added mass equal to its own: velocity,
+heading and wrench series and the final flow agree."""
 import numpy as np
 import pytest
 import torch
@@ -20,21 +21,22 @@ NX, NY, NZ, L, NM = 64, 40, 40, 20.0, 1000
 ORIGIN = (30.0, 20.0, 20.0)
 
 
-def test_free_swimmer_against_oracle():
+@pytest.mark.parametrize("rho_b,k", [(2.0, 0.0), (1.0, 1.0)])
+def test_free_swimmer_against_oracle(rho_b, k):
     n = 40
     ms = I.fish_surface(NM, L, (20.0, 20.0, 20.0))
     psi, psid = I.wave_headings(L, 10, np.arange(n + 1), period=100.0)
     sim = lbm.Simulation(NX, NY, NZ, 0.6, I.BC_VELOCITY, I.BC_OUTFLOW, max_markers=NM, max_bones=10)
     dm = lbm.DeviceMarkers(ms)
-    sw = swim.FreeSwimmer(ms, L, ORIGIN, rho_body=2.0)
+    sw = swim.FreeSwimmer(ms, L, ORIGIN, rho_body=rho_b, added_mass=k)
     sw.init(psi[0], psid[0])
     got = swim.swim(sim, dm, sw, psi, psid, n)
     _, u = sim.macros(got["frames"][-1])
     torch.cuda.synchronize()
     assert sim.check() == 0
 
-    mass, com, inertia, vol = I.fish_link_mass(L, 10, rho=2.0)
-    body = OS.Body(L / 10, mass, com, inertia, ms.joints_rest, 0.5, ORIGIN)
+    mass, com, inertia, vol = I.fish_link_mass(L, 10, rho=rho_b)
+    body = OS.Body(L / 10, mass, com, inertia, ms.joints_rest, 1.0 / rho_b, ORIGIN, added_mass=k)
     prm = oracle.params(NX, NY, NZ, 0.6, I.BC_VELOCITY, I.BC_OUTFLOW)
     f0 = oracle.equilibrium_field(np.ones((NZ, NY, NX)), np.zeros((3, NZ, NY, NX)))
     ref = OS.coupled_run(prm, f0, ms, body, psi, psid, n)
@@ -46,7 +48,8 @@ def test_free_swimmer_against_oracle():
     ug = u.cpu().numpy().astype(np.float64)[..., 1:-1]
     eu = rel_l2(ug, u_ref[..., 1:-1])
     em = np.abs(ug - u_ref[..., 1:-1]).max() / np.abs(u_ref[..., 1:-1]).max()
-    say(f"free swimmer: velocity {ev:.2e}, heading {eh:.2e}, force {ew:.2e}, flow rel L2 {eu:.2e} "
+    say(f"free swimmer (rho_b {rho_b}, added mass {k}): velocity {ev:.2e}, heading {eh:.2e}, force {ew:.2e}, "
+        f"flow rel L2 {eu:.2e} "
         f"(max {em:.2e} of the peak); final velocity {got['vel'][-1]}, heading {got['heading'][-1]:.5f}")
     # The flow is the small field the fish makes from rest (the frame's far
     # field is about 1e-3), and the float32 run's body trajectory differs

@@ -18,7 +18,7 @@ from paper_2206_01683_amd import lbm
 def _lib_body(body):
     arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (body.mass, body.com, body.inertia, body.joints_rest)]
     s = lbm.Swimmer(len(body.mass), 1 if body.free_yaw else 0, body.h, *[a.ctypes.data for a in arrs],
-                    body.fluid_ratio, (ctypes.c_double * 3)(*body.origin))
+                    body.fluid_ratio, (ctypes.c_double * 3)(*body.origin), body.added_mass)
     return s, arrs
 
 
@@ -183,6 +183,74 @@ def test_enclosed_fluid_terms_and_held_yaw():
                 assert st_o["heading"] == 0.0 and st_l.heading == 0.0 and st_l.spin == 0.0
 
 
+@pytest.mark.parametrize("k", [0.0, 1.0, 2.0])
+def test_artificial_added_mass_against_a_linear_reaction(k):
+    """The fluid's force on a body it holds back: F(n) = F_e - (m_a + r M) a(n),
+    T(n) = T_e - (I_a + r I_c) theta''(n), the reaction to the body's own
+    acceleration (added mass m_a, inertia I_a) and to its enclosed fluid's.
+    Closed form of the update: a(n+1) - a* = q (a(n) - a*) with
+    a* = F_e / (M + m_a) and q = (k M - m_a) / (M + k M), and likewise for the
+    spin rate with q = (k I_c - I_a) / (I_c + k I_c). With m_a = 2 M explicit
+    coupling (k = 0, q = -2) doubles each step's error; k = 1 (q = -1/2) and
+    k = 2 (q = 0) converge to the steady values (M + m_a) a* = F_e,
+    (I_c + I_a) theta''* = T_e. Library and oracle both."""
+    base = _rods()
+    r = 0.7
+    body = OS.Body(base.h, base.mass, base.com, base.inertia, base.joints_rest, r, base.origin, added_mass=k)
+    s, keep = _lib_body(body)
+    psi, psid = np.array([0.2, -0.4]), np.zeros(2)
+    *_, Ic, _ = OS.shape(body, psi, psid)
+    M = body.M
+    ma, Ia = 2.0 * M, 2.0 * Ic
+    Fe, Te = 0.3, 0.02
+    a_star, w2_star = Fe / (M + ma), Te / (Ic + Ia)
+    q_a, q_w = (k * M - ma) / (M + k * M), (k * Ic - Ia) / (Ic + k * Ic)
+    st_o = OS.init(body, psi, psid)
+    st_l = _lib_init(s, psi, psid)
+    for n in range(40):
+        a_o, wdd_o = st_o["acc"].real, st_o["spin"] - st_o["spin_prev"]
+        a_l, wdd_l = st_l.acc[0], st_l.spin - st_l.spin_prev
+        applied = []
+        for st_a, st_w, adv in ((a_o, wdd_o, lambda w: OS.advance(body, st_o, w, psi, psid)),
+                                (a_l, wdd_l, lambda w: _lib_advance(s, st_l, w, psi, psid))):
+            w = np.zeros(8)
+            w[0] = Fe - (ma + r * M) * st_a
+            w[5] = Te - (Ia + r * Ic) * st_w
+            applied.append(w)
+            adv(w.astype(np.float32))
+        for st_a, st_w, a_new, w_new, w in ((a_o, wdd_o, st_o["acc"].real, st_o["spin"] - st_o["spin_prev"],
+                                             applied[0]),
+                                            (a_l, wdd_l, st_l.acc[0], st_l.spin - st_l.spin_prev, applied[1])):
+            # float32 wrench: the force is rounded to 24 bits before the update
+            assert abs((a_new - a_star) - q_a * (st_a - a_star)) <= 1e-7 * abs(w[0]) / M + 1e-15
+            assert abs((w_new - w2_star) - q_w * (st_w - w2_star)) <= 1e-7 * abs(w[5]) / Ic + 1e-15
+    err_a, err_w = abs(st_l.acc[0] - a_star), abs(st_l.spin - st_l.spin_prev - w2_star)
+    if k == 0.0:
+        assert err_a > 1e6 * a_star and err_w > 1e6 * w2_star  # |q| = 2
+    else:
+        assert err_a < 1e-5 * a_star and err_w < 1e-5 * w2_star
+
+
+def test_library_and_oracle_agree_with_added_mass():
+    body0, ms = _fish_body()
+    body = OS.Body(body0.h, body0.mass, body0.com, body0.inertia, body0.joints_rest, 1.0, body0.origin,
+                   added_mass=1.0)
+    steps = np.arange(30)
+    psi, psid = I.wave_headings(24.0, 10, steps)
+    rng = np.random.default_rng(5)
+    st_o = OS.init(body, psi[0], psid[0], vel0=(-0.02, 0.001), heading=0.1)
+    s, keep = _lib_body(body)
+    st_l = _lib_init(s, psi[0], psid[0], vel0=(-0.02, 0.001), heading=0.1)
+    for n in range(29):
+        w = np.zeros(8, dtype=np.float32)
+        w[[0, 1, 5]] = rng.normal(0.0, [0.05, 0.05, 0.5]).astype(np.float32)
+        OS.advance(body, st_o, w, psi[n + 1], psid[n + 1])
+        _lib_advance(s, st_l, w, psi[n + 1], psid[n + 1])
+        assert abs(st_l.heading - st_o["heading"]) < 1e-12 and abs(st_l.spin - st_o["spin"]) < 1e-13
+        assert abs(st_l.ang_mom - st_o["ang_mom"]) < 1e-11 * max(1.0, abs(st_o["ang_mom"]))
+        assert abs(complex(*st_l.acc[:]) - st_o["acc"]) < 1e-14
+
+
 def test_swimmer_rejects_bad_bodies():
     body = _rods()
     s, keep = _lib_body(body)
@@ -195,14 +263,19 @@ def test_swimmer_rejects_bad_bodies():
     s.link_length = -1.0
     assert lbm.lib().lbm_swimmer_init(ctypes.byref(s), ctypes.byref(st), None, 0.0, z.ctypes.data,
                                       z.ctypes.data) == lbm.ERR_ARG
+    s.link_length = 6.0
+    s.added_mass = -0.5
+    assert lbm.lib().lbm_swimmer_init(ctypes.byref(s), ctypes.byref(st), None, 0.0, z.ctypes.data,
+                                      z.ctypes.data) == lbm.ERR_ARG
 
 
-def _free_fish(rho_b, n_steps):
+def _free_fish(rho_b, n_steps, added_mass=0.0):
     import oracle
     nx, ny, nz, L = 64, 40, 40, 20.0
     ms = I.fish_surface(1000, L, (20.0, 20.0, 20.0))
     mass, com, inertia, vol = I.fish_link_mass(L, 10, rho=rho_b)
-    body = OS.Body(L / 10, mass, com, inertia, ms.joints_rest, 1.0 / rho_b, (30.0, 20.0, 20.0))
+    body = OS.Body(L / 10, mass, com, inertia, ms.joints_rest, 1.0 / rho_b, (30.0, 20.0, 20.0),
+                   added_mass=added_mass)
     psi, psid = I.wave_headings(L, 10, np.arange(n_steps + 1), period=100.0)
     prm = oracle.params(nx, ny, nz, 0.6, I.BC_VELOCITY, I.BC_OUTFLOW)
     f = oracle.equilibrium_field(np.ones((nz, ny, nx)), np.zeros((3, nz, ny, nx)))
@@ -219,3 +292,23 @@ def test_coupled_oracle_swims_stably_toward_its_heading():
     assert np.all(np.isfinite(v)) and np.all(np.isfinite(th))
     assert np.abs(v).max() < 0.02 and np.abs(th).max() < 0.3
     assert v[-50:, 0].mean() < 0.0
+
+
+@pytest.mark.slow
+def test_coupled_oracle_neutrally_buoyant_with_added_mass():
+    """As dense as the fluid (the paper's fish), free yaw, 150 steps: explicit
+    coupling runs away, the artificial added mass (k = 1) keeps the coupled
+    FP64 run bounded and swimming toward its heading."""
+    out = _free_fish(1.0, 150, added_mass=1.0)
+    v, th = out["vel"], out["heading"]
+    assert np.all(np.isfinite(v)) and np.all(np.isfinite(th))
+    assert np.abs(v).max() < 0.02 and np.abs(th).max() < 0.3
+    assert v[-50:, 0].mean() < 0.0
+    import oracle
+    try:
+        bad = _free_fish(1.0, 150, added_mass=0.0)
+        ran_away = not (np.all(np.isfinite(bad["vel"])) and np.abs(bad["vel"]).max() < 0.02 and
+                        np.abs(bad["heading"]).max() < 0.3)
+    except oracle.OracleError:  # the body left the domain (marker range)
+        ran_away = True
+    assert ran_away
