@@ -7,12 +7,17 @@ Workload: the single-fish, accelerating-local-frame configuration -
 acceleration a(n) = 1e-5 sin(2 pi n / 400), velocity inlet / zero-gradient
 outlet. One step = skinning, tile binning, interpolation, direct forcing,
 spreading, the fused collide-stream with the frame force and open faces, and
-the body wrench (the whole path), all through the C interface.
+the body wrench (the whole path), all through the C interface. The headline
+step runs skinning and binning in launches of their own and the rest in one
+launch (k_step_overlap): 48 workgroups take the immersed-boundary chain while
+the others stream the collide; the "sequential" form runs every phase in its
+own launch (k_collide alone).
 
 Prints one JSON line: MLUPS (lattice updates per second / 1e6, every node
-counted), the collide kernel's achieved bandwidth against the 8 TB/s HBM peak
-from HIP events on its stream, and the FP64 oracle's throughput on the host
-cores for a bounded sample of the same workload.
+counted), the main launch's achieved bandwidth (the collide's 216 B per cell
+over the launch's average duration, from HIP events on its stream) against
+the 8 TB/s HBM peak, and the FP64 oracle's throughput on the host cores for a
+bounded sample of the same workload.
 """
 import argparse
 import hashlib
@@ -28,31 +33,46 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL = {"f32": 216, "f16": 108, "bf16": 108}
 METRIC = "MLUPS and % of HBM roofline per GPU; adjoint/forward time ratio"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "collide_traffic.txt")
-# the sources k_collide is compiled from (its lattice, storage, view of the context, and the kernel itself)
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2206_01683_amd", "csrc", f) for f in ("lattice.hpp", "env.hpp", "fluid.hpp")]
-MAIN_KERNEL = "k_collide"
+# The headline step runs the immersed-boundary phases after the tile binning
+# in this many workgroups beside the collide, in one launch (k_step_overlap);
+# 0 runs them in launches of their own before the collide (k_collide).
+HEADLINE_IB_WORKGROUPS = 48
+_CSRC = os.path.join(ROOT, "paper_2206_01683_amd", "csrc")
+# the sources each main kernel is compiled from, and its committed HBM traffic summary
+KERNEL_SOURCES = {
+    "k_collide": [os.path.join(_CSRC, f) for f in ("lattice.hpp", "env.hpp", "fluid.hpp")],
+    "k_step_overlap": [os.path.join(_CSRC, f) for f in ("lattice.hpp", "env.hpp", "fluid.hpp", "ib.hpp", "step.hpp")],
+}
+TRAFFIC_FILES = {
+    "k_collide": os.path.join(ROOT, "profiles", "collide_traffic.txt"),
+    "k_step_overlap": os.path.join(ROOT, "profiles", "step_overlap_traffic.txt"),
+}
 
 
-def kernel_source_hash() -> str:
+def main_kernel(ib_workgroups: int) -> str:
+    return "k_step_overlap" if ib_workgroups > 0 else "k_collide"
+
+
+def kernel_source_hash(kernel: str) -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in KERNEL_SOURCES[kernel]:
         with open(p, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(storage: str):
-    """HBM bytes per collide launch from the committed rocprofv3 counter
+def measured_traffic(storage: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary, or None when it is missing or was taken on other kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+    path = TRAFFIC_FILES[kernel]
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash(kernel):
         return None
     key = f"hbm_bytes_per_launch_{storage}"
     return float(vals[key]) if key in vals else None
@@ -102,6 +122,9 @@ def run_gpu(storage: str, steps: int, warmup: int, block=(0, 0), collision: int 
     return res
 
 
+BATCH_GROUPS = 2  # concurrent groups of the per-phase driver
+
+
 def run_batch(nenv: int, nsteps: int, seed: int = 4):
     """Batched environments: nenv fish environments of uneven sizes (seeded
     draw), nsteps steps per run, one run = one graph replay. Returns MLUPS
@@ -121,15 +144,21 @@ def run_batch(nenv: int, nsteps: int, seed: int = 4):
            "markers": int(sum(w.markers.n for w in envs)),
            "shapes": {f"{bx}x{by}": int(((shapes[:, 0] == bx) & (shapes[:, 1] == by)).sum())
                       for bx, by in lbm.BATCH_SHAPES}}
-    for mode in ("persistent", "phases"):
+    def timed(b, mode, bytes_per_cell):
         b.run(nsteps, mode=mode, graph=True)  # capture + warm-up replay
         b.synchronize()
         t0 = time.perf_counter()
         b.run(nsteps, mode=mode, graph=True)
         b.synchronize()
         dt = time.perf_counter() - t0
-        out[mode] = {"mlups": round(ncell * nsteps / dt / 1e6, 1), "ms_per_step": round(dt * 1e3 / nsteps, 4),
-                     "hbm_frac_216B": round(ncell * nsteps * 216 / dt / (HBM_PEAK_GBS * 1e9), 4)}
+        return {"mlups": round(ncell * nsteps / dt / 1e6, 1), "ms_per_step": round(dt * 1e3 / nsteps, 4),
+                f"hbm_frac_{bytes_per_cell}B": round(ncell * nsteps * bytes_per_cell / dt / (HBM_PEAK_GBS * 1e9), 4)}
+
+    for mode in ("persistent", "phases"):
+        out[mode] = timed(b, mode, 216)
+    # the per-phase driver as concurrent cell-balanced groups, one stream each
+    b.set_groups(BATCH_GROUPS)
+    out[f"phases_groups{BATCH_GROUPS}"] = timed(b, "phases", 216)
     out["status"] = b.check()
     b.close()
     del b
@@ -138,15 +167,10 @@ def run_batch(nenv: int, nsteps: int, seed: int = 4):
     for fmt in ("f16", "bf16"):
         b = lbm.Batch(envs, nsteps, storage=fmt)
         b.autotune(reps=3)
-        b.run(nsteps, mode="phases", graph=True)
-        b.synchronize()
-        t0 = time.perf_counter()
-        b.run(nsteps, mode="phases", graph=True)
-        b.synchronize()
-        dt = time.perf_counter() - t0
-        out[f"phases_{fmt}"] = {"mlups": round(ncell * nsteps / dt / 1e6, 1), "ms_per_step": round(dt * 1e3 / nsteps, 4),
-                                "hbm_frac_108B": round(ncell * nsteps * 108 / dt / (HBM_PEAK_GBS * 1e9), 4),
-                                "status": b.check()}
+        out[f"phases_{fmt}"] = timed(b, "phases", 108)
+        b.set_groups(BATCH_GROUPS)
+        out[f"phases_{fmt}_groups{BATCH_GROUPS}"] = timed(b, "phases", 108)
+        out[f"phases_{fmt}"]["status"] = b.check()
         b.close()
         del b
         torch.cuda.empty_cache()
@@ -374,15 +398,17 @@ def main():
     ap.add_argument("--storage", default="f32", choices=sorted(BYTES_PER_CELL))
     ap.add_argument("--cpu-steps", type=int, default=24, help="oracle sample length (0: skip)")
     ap.add_argument("--forms",
-                    default="ceiling,f16,bf16,overlap,trt,faces_frames,batched,adjoint,two_fish,free_swimmer,"
+                    default="sequential,ceiling,f16,bf16,trt,faces_frames,batched,adjoint,two_fish,free_swimmer,"
                             "ib_schemes",
-                    help="comma-separated extra forms to measure: ceiling, f16, bf16, overlap, trt, faces_frames, "
+                    help="comma-separated extra forms to measure: sequential, ceiling, f16, bf16, trt, faces_frames, "
                          "batched, adjoint, two_fish, free_swimmer, ib_schemes")
     ap.add_argument("--no-forms", action="store_true", help="measure no extra form")
     ap.add_argument("--block", type=int, nargs=2, default=(0, 0))
     ap.add_argument("--batch-envs", type=int, default=64, help="batched form: environments (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=200, help="batched form: steps per graph replay")
     ap.add_argument("--ib-steps", type=int, default=100, help="ib_schemes form: timed steps per scheme")
+    ap.add_argument("--ib-workgroups", type=int, default=HEADLINE_IB_WORKGROUPS,
+                    help="headline step: immersed-boundary workgroups beside the collide (0: launches of their own)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -390,17 +416,31 @@ def main():
               "build has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
-    main_run = run_gpu(args.storage, args.steps, args.warmup, tuple(args.block))
+    nib = max(0, args.ib_workgroups)
+    kernel = main_kernel(nib)
+    main_run = run_gpu(args.storage, args.steps, args.warmup, tuple(args.block), ib_workgroups=nib)
     w = main_run["workload"]
     want = set() if args.no_forms else {f.strip() for f in args.forms.split(",") if f.strip()}
     forms = {}
+    seq = main_run if nib == 0 else None
+    if nib > 0 and want & {"sequential", "ceiling"}:
+        # the same step with the immersed-boundary phases in launches of their own before the collide: the
+        # collide kernel alone against the roofline and the practical ceiling
+        seq = run_gpu(args.storage, args.steps, args.warmup, tuple(args.block), ib_workgroups=0)
+        t = measured_traffic(args.storage, "k_collide")
+        forms["sequential"] = {"mlups": round(seq["mlups"], 1), "kernel": "k_collide",
+                               "collide_avg_ms": round(seq["collide_avg_ms"], 5),
+                               "collide_GBps": round(seq["collide_gbs"], 1),
+                               "collide_frac_of_hbm_peak": round(seq["collide_gbs"] / HBM_PEAK_GBS, 4),
+                               "collide_traffic": None if t is None else round(t, 0),
+                               "ib_ms_per_step": round(seq["ib_avg_ms"], 5), "status": seq["status"]}
     if "ceiling" in want:
         # the practical ceiling: reference streaming kernels on the fish's sizes
         from paper_2206_01683_amd import hbm_ceiling
         c = hbm_ceiling.measure(w.nx, w.ny, w.nz)
         c["collide_over_pull27_same_layout"] = round(
-            main_run["collide_gbs"] / c["pull27_rows" if main_run["rows_layout"] else "pull27_planes"]["GBps"], 4)
-        c["collide_over_copy"] = round(main_run["collide_gbs"] / c["copy"]["GBps"], 4)
+            seq["collide_gbs"] / c["pull27_rows" if seq["rows_layout"] else "pull27_planes"]["GBps"], 4)
+        c["collide_over_copy"] = round(seq["collide_gbs"] / c["copy"]["GBps"], 4)
         forms["ceiling"] = c
     if args.storage == "f32":
         for st in sorted(want & {"f16", "bf16"}):
@@ -408,13 +448,6 @@ def main():
             forms[st] = {"mlups": round(r["mlups"], 1), "collide_GBps": round(r["collide_gbs"], 1),
                          "collide_frac_of_hbm_peak": round(r["collide_gbs"] / HBM_PEAK_GBS, 4),
                          "bytes_per_cell": BYTES_PER_CELL[st], "status": r["status"]}
-    if "overlap" in want:
-        # the IB chain beside the collide in one launch (k_step_overlap, 64 chain workgroups)
-        r = run_gpu(args.storage, args.steps, args.warmup, tuple(args.block), ib_workgroups=64)
-        forms["overlap"] = {"mlups": round(r["mlups"], 1), "ib_workgroups": 64,
-                            "skin_binning_ms_per_step": round(r["ib_avg_ms"], 5),
-                            "main_launch_ms": round(r["collide_avg_ms"], 5),
-                            "main_launch_GBps_216B": round(r["collide_gbs"], 1), "status": r["status"]}
     if "trt" in want:
         from paper_2206_01683_amd import lbm as _lbm
         r = run_gpu(args.storage, args.steps, args.warmup, tuple(args.block), collision=_lbm.COLLIDE_TRT)
@@ -453,7 +486,7 @@ def main():
         forms["free_swimmer"] = run_free_swimmer()
     if "ib_schemes" in want:
         forms["ib_schemes"] = run_ib_schemes(args.ib_steps)
-    traffic = measured_traffic(args.storage)
+    traffic = measured_traffic(args.storage, kernel)
     ach = main_run["collide_gbs"]
     out = {
         "metric": METRIC,
@@ -475,11 +508,13 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic, 0),
-                     "kernel": MAIN_KERNEL, "bytes_per_cell": BYTES_PER_CELL[args.storage],
+                     "kernel": kernel, "bytes_per_cell": BYTES_PER_CELL[args.storage],
                      "cells_per_launch": main_run["ncell"],
                      "avg_launch_ms": round(main_run["collide_avg_ms"], 5)},
         "step_hbm_frac": round(main_run["mlups"] * 1e6 * BYTES_PER_CELL[args.storage] / (HBM_PEAK_GBS * 1e9), 4),
-        "ib_ms_per_step": round(main_run["ib_avg_ms"], 5),
+        "ib_workgroups": nib,
+        # launches before the main one: every immersed-boundary phase (nib = 0), or skinning and tile binning
+        "pre_launch_ms_per_step": round(main_run["ib_avg_ms"], 5),
         "device_status": main_run["status"],
         "forms": forms,
     }

@@ -542,6 +542,30 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, int32_t *shapes_out);
  * five autotuner shapes, else LBM_ERR_ARG. */
 lbm_status lbm_batch_set_shapes(lbm_batch *b, const int32_t *shapes);
 
+/* Concurrent groups for the per-phase driver, which otherwise leaves the
+ * device part idle at every phase boundary of every step (each phase is a
+ * launch that waits for the previous one). ngroups in [2, LBM_BATCH_MAX_GROUPS]
+ * and at most nenv: the environments are split into ngroups groups of about
+ * equal cell count (largest lattice first, each to the group with the fewest
+ * cells; each group keeps the batch's order), and each group becomes a batch
+ * of its own on streams[g] [host array of ngroups distinct HIP streams, owned
+ * by the caller and alive while the groups are set]. A per-phase run then
+ * waits for the work queued on the batch's stream, runs the groups
+ * concurrently (one graph per group when graph != 0), and makes the batch's
+ * stream wait for all of them; lbm_batch_check covers the groups. Each
+ * environment's arithmetic is independent of the others, so the populations
+ * and wrenches are bit for bit those of the ungrouped run. The persistent
+ * driver always runs the whole batch in one launch. dev: device buffer of
+ * lbm_batch_group_bytes(nenv, ngroups) bytes, 256-byte aligned, owned by the
+ * caller and alive while the groups are set. ngroups = 1 drops the groups
+ * (streams and dev may be NULL). Synchronizes the batch's stream. Returns
+ * LBM_ERR_ARG for a count outside the range, a NULL or repeated stream or a
+ * misaligned buffer. lbm_batch_group_bytes is 0 if nenv is outside
+ * [1, 512] or ngroups outside [2, min(nenv, LBM_BATCH_MAX_GROUPS)]. */
+enum { LBM_BATCH_MAX_GROUPS = 8 };
+size_t lbm_batch_group_bytes(int32_t nenv, int32_t ngroups);
+lbm_status lbm_batch_set_groups(lbm_batch *b, int32_t ngroups, void *const *streams, void *dev);
+
 /* Synchronize; LBM_ERR_DEVICE if a persistent run's barrier timed out (its
  * steps stopped early, the populations are not those of a completed run; the
  * barrier is reset so later runs can proceed), otherwise the first non-OK

@@ -10,7 +10,7 @@ SRC = os.path.join(HERE, "csrc", "lbm_ib.hip")
 LIB = os.path.join(HERE, "liblbmib.so")
 CEIL_SRC = os.path.join(HERE, "csrc", "hbm_ceiling.hip")
 CEIL_LIB = os.path.join(HERE, "libhbmceiling.so")
-HEADERS = [os.path.join(HERE, "csrc", h) for h in ("lattice.hpp", "env.hpp", "fluid.hpp", "ib.hpp", "batch.hpp",
+HEADERS = [os.path.join(HERE, "csrc", h) for h in ("lattice.hpp", "env.hpp", "fluid.hpp", "ib.hpp", "batch.hpp", "step.hpp",
                                                    "adjoint.hpp", "swimmer.hpp")] + [
     os.path.join(ROOT, "include", "lbm_ib.h")]
 

@@ -223,7 +223,7 @@ __device__ inline void adj_gbar_item(const EnvView &e, const AdjArgs &A, int slo
 // those of the recomputed forward IB phases.
 __device__ inline void adj_marker_item(const EnvView &e, const AdjArgs &A, int item, int tid) {
   const int lane = tid & 63, wv = tid >> 6;
-  const int k = item * kInterpPer + wv;
+  const int k = item * kWavePer + wv;
   const int n = e.n;
   if (k >= n) return;
   const GridArgs &g = e.g;

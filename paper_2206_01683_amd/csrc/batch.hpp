@@ -328,8 +328,8 @@ __global__ void __launch_bounds__(WG) kb_active(BatchArgs b) { phase_active(b, b
 template <bool UNI>
 __global__ void __launch_bounds__(WG) kb_macro(BatchArgs b, int s) {
   __shared__ int s_pre[kMaxEnvs + 1];
-  const int tot = dynamic_prefix(b, 1, s_pre, threadIdx.x);
-  for (int item = blockIdx.x; item < tot; item += gridDim.x) phase_macro<UNI, true>(b, s, item, s_pre, threadIdx.x);
+  const XcdWalk w = xcd_walk(dynamic_prefix(b, 1, s_pre, threadIdx.x));
+  for (int item = w.first; item < w.end; item += w.step) phase_macro<UNI, true>(b, s, item, s_pre, threadIdx.x);
 }
 
 template <bool UNI>
@@ -452,7 +452,8 @@ __global__ void __launch_bounds__(WG, 6) kb_persistent(BatchArgs b, int nsteps) 
     {
       const int tid = phase_tid(), blk = phase_blk(), grid = phase_grid();
       const int tot = dynamic_prefix(b, 1, s_pre, tid);
-      for (int item = blk; item < tot; item += grid) phase_macro<UNI>(b, s, item, s_pre, tid);
+      const XcdWalk w = xcd_walk(tot, blk, grid);
+      for (int item = w.first; item < w.end; item += w.step) phase_macro<UNI>(b, s, item, s_pre, tid);
     }
     if (!grid_sync(b)) return;
     int tot;

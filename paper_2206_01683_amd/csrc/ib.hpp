@@ -12,9 +12,9 @@
 //   active_item   512 tiles: compact the flags into slots and an active list
 //   macro_item    one active tile: density and unforced velocity of its 512
 //                 cells; clears the tile's fixed-point force
-//   interp_item   8 markers, one wave64 each, one lane per stencil node:
-//                 wave-level sums -> U*_k, rho_k, direct forcing F_k, marker
-//                 record, wrench partials
+//   interp_item   32 markers, 16 lanes each, one lane per x-row of 4
+//                 stencil nodes: row sums, then 16-lane sums -> U*_k, rho_k,
+//                 direct forcing F_k, marker record, wrench partials
 //   spread_item   (active tile, part): the markers whose stencils touch the
 //                 tile add their stencil nodes into an LDS tile in 64-bit fixed
 //                 point (order-independent, so deterministic), merged into the
@@ -29,7 +29,8 @@ namespace lbmib {
 constexpr int WG = 512;              // threads per workgroup in every IB phase
 constexpr int REC = 20;              // floats per marker record: w[12], base[3], pad, fdv[3], pad
 constexpr int kSpreadSplit = 4;      // spreading work items per active tile
-constexpr int kInterpPer = WG / 64;  // markers per interpolation item
+constexpr int kWavePer = WG / 64;    // markers per item of the one-wave-per-marker kernels (adjoint)
+constexpr int kInterpMk = WG / 16;   // markers per interpolation (and CG apply) item, 16 lanes each
 
 // Scheduling words of the overlapped step (step.hpp), each on its own
 // 128-byte line, in the workspace (EnvView::sched): the chain's barrier
@@ -236,6 +237,28 @@ __device__ inline void active_item(const EnvView &e, int item, int tid) {
 __device__ inline int active_items(const EnvView &e) { return (e.ntiles + WG - 1) / WG; }
 __device__ inline int n_active_of(const EnvView &e) { return min(e.counters[0], e.cap); }
 
+// XCD-contiguous walk over work items 0 .. tot-1. The dispatcher hands
+// workgroup b to XCD b % kXcds, and each XCD has its own L2; an active tile's
+// x-rows are 8 cells (32 bytes at F32) of 128-byte lines that it shares with
+// its x-neighbours, which hold the next slots. Giving each XCD one contiguous
+// range of items makes those neighbours meet in one L2 instead of fetching
+// each line once per XCD. Every item is visited exactly once for any grid;
+// workgroups past the last multiple of kXcds take no items.
+constexpr int kXcds = 8;
+struct XcdWalk {
+  int first, end, step;
+};
+__device__ inline XcdWalk xcd_walk(int tot, int blk, int grid) {
+  const int per = grid / kXcds;
+  if (per == 0) return {blk, tot, grid};  // small grid: plain stride
+  const int x = blk % kXcds, r = blk / kXcds;
+  if (r >= per) return {0, 0, 1};
+  const int chunk = (tot + kXcds - 1) / kXcds;
+  const int lo = x * chunk, hi = min(tot, lo + chunk);
+  return {lo + r, hi, per};
+}
+__device__ inline XcdWalk xcd_walk(int tot) { return xcd_walk(tot, (int)blockIdx.x, (int)gridDim.x); }
+
 // ----------------------------------------------------------- band macros --
 // Density and unforced velocity u* (frame force, no IB force) of every cell
 // of active tile `slot`; also clears the tile's fixed-point immersed force.
@@ -278,8 +301,12 @@ __device__ inline void macro_item(const EnvView &e, const FrameF &fr, int cur, i
 }
 
 // --------------------------------------------------------- interpolation --
-// Markers 8*item .. 8*item+7, one wave64 each; lane l is stencil node
-// (l & 3, (l >> 2) & 3, l >> 4).
+// Markers 32*item .. 32*item+31, four per wave, 16 lanes each. Lane
+// sub = lane & 15 of a marker's group holds the x-row of stencil nodes
+// (0..3, sub & 3, sub >> 2): it issues the row's four gathers together, sums
+// the row, and a 16-lane butterfly (every lane of the group ends with the
+// same bits) completes the 64-node sums. Node weight delta = wx (wy wz),
+// the product the spreading uses.
 // pass 0: U*_k = sum u* delta, rho_k = sum rho delta, F_k = 2 alpha rho_k (U_k - U*_k).
 // pass p > 0 (multi-direct forcing): the interpolated velocity includes the
 // current immersed force, u = u* + (I + [omega]x)^-1 g / (2 rho), and
@@ -288,60 +315,113 @@ __device__ inline void macro_item(const EnvView &e, const FrameF &fr, int cur, i
 // pass into the step's force). With partials != nullptr: the fluid's force,
 // torque about the frame origin and power, summed per item into
 // partials[item][8].
+__device__ inline float group16_sum(float v) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) v += shfl_xor_f(v, o);
+  return v;
+}
+
+// Stencil geometry of marker position X for row lane sub: the base node per
+// axis, the four x weights, the row's y and z weights, and per x node of the
+// row its tile index and its cell index within the tile.
+struct StencilRow {
+  int base[3];
+  float wx[4], wy, wz;
+  int tile[4], lc[4];
+};
+
+__device__ inline StencilRow stencil_row(const GridArgs &g, const float X[3], int sub) {
+  StencilRow r;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) r.base[ax] = stencil_base(X[ax]);
+  const int jy = r.base[1] + (sub & 3), jz = r.base[2] + (sub >> 2);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) r.wx[i] = peskin4(X[0] - (float)(r.base[0] + i));
+  r.wy = peskin4(X[1] - (float)jy);
+  r.wz = peskin4(X[2] - (float)jz);
+  const int yn = wrap_idx(jy, g.ny), zn = wrap_idx(jz, g.nz);
+  const int trow = g.tnx * ((yn >> 3) + g.tny * (zn >> 3));
+  const int lrow = ((yn & 7) << 3) | ((zn & 7) << 6);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int xn = g.xper ? wrap_idx(r.base[0] + i, g.nx) : r.base[0] + i;
+    r.tile[i] = (xn >> 3) + trow;
+    r.lc[i] = (xn & 7) | lrow;
+  }
+  return r;
+}
+
 template <bool ROT, bool MDF>
 __device__ inline void interp_item(const EnvView &e, const FrameF &fr, int item, int tid, float *partials) {
-  __shared__ float s_part[kInterpPer][8];
-  const int lane = tid & 63, wv = tid >> 6;
-  const int k = item * kInterpPer + wv;
+  // multiply-adds fuse only within one expression, never across statements,
+  // so every kernel that inlines this item rounds its outputs identically
+#pragma clang fp contract(on)
+  __shared__ float s_part[kInterpMk][8];
+  const int sub = tid & 15, mk = tid >> 4;
+  const int k = item * kInterpMk + mk;
   const int n = e.n;
   const GridArgs &g = e.g;
+  const bool live = k < n;
   float part[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  if (k < n) {
-    const float Xk[3] = {e.X[k], e.X[n + k], e.X[2 * n + k]};
-    // loaded now, used after the stencil gather: off the dependent chain
-    const float Uk[3] = {e.U[k], e.U[n + k], e.U[2 * n + k]};
-    const float dvk = e.dv[k];
-    const int s3[3] = {lane & 3, (lane >> 2) & 3, lane >> 4};
-    const int dims[3] = {g.nx, g.ny, g.nz};
-    int base[3], node[3];
-    float w[3];
+  float Xk[3] = {0.f, 0.f, 0.f}, Uk[3] = {0.f, 0.f, 0.f}, dvk = 0.f;
+  StencilRow st{};
+  float sr = 0.f, sx = 0.f, sy = 0.f, sz = 0.f;
+  if (live) {
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      base[ax] = stencil_base(Xk[ax]);
-      const int j = base[ax] + s3[ax];
-      w[ax] = peskin4(Xk[ax] - (float)j);
-      node[ax] = (ax > 0 || g.xper) ? wrap_idx(j, dims[ax]) : j;
+      Xk[ax] = e.X[ax * n + k];
+      // loaded now, used after the stencil gather: off the dependent chain
+      Uk[ax] = e.U[ax * n + k];
     }
-    const int t = (node[0] >> 3) + g.tnx * ((node[1] >> 3) + g.tny * (node[2] >> 3));
-    const int s = e.tile_slot[t];
-    float rho = 0.f, ux = 0.f, uy = 0.f, uz = 0.f;
-    if (s >= 0) {
-      const int lc = (node[0] & 7) | ((node[1] & 7) << 3) | ((node[2] & 7) << 6);
-      const float4 m = e.macro[(size_t)s * 512 + lc];
-      rho = m.x;
-      ux = m.y;
-      uy = m.z;
-      uz = m.w;
-      if (MDF) {
-        const unsigned long long *gp = e.gfix + (size_t)s * 1536;
-        const float h = 0.5f / rho;
+    dvk = e.dv[k];
+    st = stencil_row(g, Xk, sub);
+    int sl[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sl[i] = e.tile_slot[st.tile[i]];
+    float4 m[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      m[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (sl[i] >= 0)
+        m[i] = e.macro[(size_t)sl[i] * 512 + st.lc[i]];
+      else
+        atomicOr(e.guard, (int)GUARD_CAPACITY);
+    }
+    if (MDF) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (sl[i] < 0) continue;
+        const unsigned long long *gp = e.gfix + (size_t)sl[i] * 1536;
+        const float h = 0.5f / m[i].x;
         float dx, dy, dz;
-        solve_coriolis<ROT>(fr, from_fix(gp[lc]) * h, from_fix(gp[512 + lc]) * h, from_fix(gp[1024 + lc]) * h, dx,
-                            dy, dz);
-        ux += dx;
-        uy += dy;
-        uz += dz;
+        solve_coriolis<ROT>(fr, from_fix(gp[st.lc[i]]) * h, from_fix(gp[512 + st.lc[i]]) * h,
+                            from_fix(gp[1024 + st.lc[i]]) * h, dx, dy, dz);
+        m[i].y += dx;
+        m[i].z += dy;
+        m[i].w += dz;
       }
-    } else {
-      atomicOr(e.guard, (int)GUARD_CAPACITY);
     }
-    const float d = w[0] * w[1] * w[2];
-    const float sr = wave_sum(rho * d), sx = wave_sum(ux * d), sy = wave_sum(uy * d), sz = wave_sum(uz * d);
+    const float wyz = st.wy * st.wz;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float d = st.wx[i] * wyz;
+      sr += m[i].x * d;
+      sx += m[i].y * d;
+      sy += m[i].z * d;
+      sz += m[i].w * d;
+    }
+  }
+  // every lane takes part (a group of 16 is all live or all not)
+  sr = group16_sum(sr);
+  sx = group16_sum(sx);
+  sy = group16_sum(sy);
+  sz = group16_sum(sz);
+  if (live) {
     float *r = e.rec + (size_t)k * REC;
-    if (lane < 4) r[lane] = w[0];                                 // s3 = (lane, 0, 0)
-    if ((lane & 3) == 0 && lane < 16) r[4 + (lane >> 2)] = w[1];  // s3 = (0, lane/4, 0)
-    if ((lane & 15) == 0) r[8 + (lane >> 4)] = w[2];              // s3 = (0, 0, lane/16)
-    if (lane == 0) {
+    if (sub == 0) *reinterpret_cast<float4 *>(r) = make_float4(st.wx[0], st.wx[1], st.wx[2], st.wx[3]);
+    if (sub < 4) r[4 + sub] = st.wy;                // row (sy, 0)
+    if ((sub & 3) == 0) r[8 + (sub >> 2)] = st.wz;  // row (0, sz)
+    if (sub == 0) {
       float rk;
       float Fk[3], inc[3];
       const float Ui[3] = {sx, sy, sz};
@@ -376,7 +456,7 @@ __device__ inline void interp_item(const EnvView &e, const FrameF &fr, int item,
         e.F[c * n + k] = Fk[c];
         fd[c] = Fk[c] * dvk;
         r[16 + c] = inc[c] * dvk;
-        r[12 + c] = __int_as_float(base[c]);
+        r[12 + c] = __int_as_float(st.base[c]);
       }
       // fluid on body: -F dV; torque (X - x0) x (-F dV); power F.U dV
       const float rx = Xk[0] - fr.org[0], ry = Xk[1] - fr.org[1], rz = Xk[2] - fr.org[2];
@@ -390,19 +470,20 @@ __device__ inline void interp_item(const EnvView &e, const FrameF &fr, int item,
     }
   }
   if (partials == nullptr) return;  // uniform over the workgroup
-  if (lane == 0)
-    for (int q = 0; q < 7; ++q) s_part[wv][q] = part[q];
+  if (sub == 0)
+    for (int q = 0; q < 7; ++q) s_part[mk][q] = part[q];
   __syncthreads();
   if (tid < 8) {
     float sum = 0.f;
     if (tid < 7)
-      for (int q = 0; q < kInterpPer; ++q) sum += s_part[q][tid];
+      for (int q = 0; q < kInterpMk; ++q) sum += s_part[q][tid];
     partials[(size_t)item * 8 + tid] = sum;
   }
   __syncthreads();
 }
 
-__device__ __host__ inline int interp_items(int n) { return (n + kInterpPer - 1) / kInterpPer; }
+__device__ __host__ inline int interp_items(int n) { return (n + kInterpMk - 1) / kInterpMk; }
+__device__ __host__ inline int wave_items(int n) { return (n + kWavePer - 1) / kWavePer; }
 
 // Wrench of the step: the interpolation partials summed in item order.
 __device__ inline void wrench_sum(const float *__restrict__ partials, int nparts, float *__restrict__ wrench, int tid) {
@@ -540,8 +621,8 @@ __global__ void __launch_bounds__(WG) k_active(EnvView e) { active_item(e, block
 
 template <class S, bool ROT>
 __global__ void __launch_bounds__(WG) k_macro(EnvView e, FrameF fr, int cur) {
-  const int na = n_active_of(e);
-  for (int slot = blockIdx.x; slot < na; slot += gridDim.x) macro_item<S, ROT>(e, fr, cur, slot, threadIdx.x);
+  const XcdWalk w = xcd_walk(n_active_of(e));
+  for (int slot = w.first; slot < w.end; slot += w.step) macro_item<S, ROT>(e, fr, cur, slot, threadIdx.x);
 }
 
 template <bool ROT, bool MDF>
@@ -717,62 +798,70 @@ __device__ inline void cg_init_item(const EnvView &e, const FrameF &fr, int item
   }
 }
 
-// Markers 8*item .. 8*item+7, one wave64 each, lane = stencil node (as
-// interp_item): q_k = sum_x delta(x - X_k) gcg(x) / (2 rho(x)) with gcg the
-// spread of step j's search direction, which is stored here.
+// Markers 32*item .. 32*item+31, 16 lanes each, lane = x-row of stencil
+// nodes (as interp_item): q_k = sum_x delta(x - X_k) gcg(x) / (2 rho(x)) with
+// gcg the spread of step j's search direction, which is stored here. The
+// weights are the record's, multiplied as the spreading multiplies them, so
+// the discrete S is symmetric.
 __device__ inline void cg_apply_item(const EnvView &e, int item, int tid, int j) {
-  __shared__ float s_pq[kInterpPer][3];
-  const int lane = tid & 63, wv = tid >> 6;
-  const int k = item * kInterpPer + wv;
+#pragma clang fp contract(on)  // as interp_item
+  __shared__ float s_pq[kInterpMk][3];
+  const int sub = tid & 15, mk = tid >> 4;
+  const int k = item * kInterpMk + mk;
   const int n = e.n;
   const GridArgs &g = e.g;
+  const bool live = k < n;
   float pq[3] = {0.f, 0.f, 0.f};
-  if (k < n) {
+  float v[3] = {0.f, 0.f, 0.f};
+  if (live) {
     const float *r = e.rec + (size_t)k * REC;
-    const int s3[3] = {lane & 3, (lane >> 2) & 3, lane >> 4};
-    const int dims[3] = {g.nx, g.ny, g.nz};
-    int node[3];
+    const int jy = __float_as_int(r[13]) + (sub & 3), jz = __float_as_int(r[14]) + (sub >> 2);
+    const int bx = __float_as_int(r[12]);
+    const float wyz = r[4 + (sub & 3)] * r[8 + (sub >> 2)];
+    const int yn = wrap_idx(jy, g.ny), zn = wrap_idx(jz, g.nz);
+    const int trow = g.tnx * ((yn >> 3) + g.tny * (zn >> 3));
+    const int lrow = ((yn & 7) << 3) | ((zn & 7) << 6);
+    int sl[4], lc[4];
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      const int jj = __float_as_int(r[12 + ax]) + s3[ax];
-      node[ax] = (ax > 0 || g.xper) ? wrap_idx(jj, dims[ax]) : jj;
+    for (int i = 0; i < 4; ++i) {
+      const int xn = g.xper ? wrap_idx(bx + i, g.nx) : bx + i;
+      sl[i] = e.tile_slot[(xn >> 3) + trow];
+      lc[i] = (xn & 7) | lrow;
     }
-    const float d = r[s3[0]] * r[4 + s3[1]] * r[8 + s3[2]];
-    const int t = (node[0] >> 3) + g.tnx * ((node[1] >> 3) + g.tny * (node[2] >> 3));
-    const int sl = e.tile_slot[t];
-    float v[3] = {0.f, 0.f, 0.f};
-    if (sl >= 0) {  // always: the first interpolation pass checked every stencil node
-      const int lc = (node[0] & 7) | ((node[1] & 7) << 3) | ((node[2] & 7) << 6);
-      const unsigned long long *gq = e.gcg + (size_t)sl * 1536;
-      const float h = 0.5f / e.macro[(size_t)sl * 512 + lc].x;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) v[c] = from_fix(gq[512 * c + lc]) * h;
-    }
-    const float qx = wave_sum(v[0] * d), qy = wave_sum(v[1] * d), qz = wave_sum(v[2] * d);
-    if (lane == 0) {
-      float q[3] = {qx, qy, qz};
-      if (e.slip) {  // n . (S p n)
-        q[0] = e.Nrm[k] * qx + e.Nrm[n + k] * qy + e.Nrm[2 * (size_t)n + k] * qz;
-        q[1] = q[2] = 0.f;
-      }
-      float p[3];
-      cg_direction(e, k, cg_scal(e, 1, j), j == 0, p);
-      float *qv = e.cg + 9 * (size_t)n, *pv = e.cg + 6 * (size_t)n;
+    for (int i = 0; i < 4; ++i) {
+      if (sl[i] < 0) continue;  // never: the first interpolation pass checked every stencil node
+      const unsigned long long *gq = e.gcg + (size_t)sl[i] * 1536;
+      const float h = 0.5f / e.macro[(size_t)sl[i] * 512 + lc[i]].x;
+      const float d = r[i] * wyz;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        qv[c * n + k] = q[c];
-        pv[c * n + k] = p[c];
-        pq[c] = p[c] * q[c];
-      }
+      for (int c = 0; c < 3; ++c) v[c] += (from_fix(gq[512 * c + lc[i]]) * h) * d;
     }
   }
-  if (lane == 0)
+  const float qx = group16_sum(v[0]), qy = group16_sum(v[1]), qz = group16_sum(v[2]);
+  if (live && sub == 0) {
+    float q[3] = {qx, qy, qz};
+    if (e.slip) {  // n . (S p n)
+      q[0] = e.Nrm[k] * qx + e.Nrm[n + k] * qy + e.Nrm[2 * (size_t)n + k] * qz;
+      q[1] = q[2] = 0.f;
+    }
+    float p[3];
+    cg_direction(e, k, cg_scal(e, 1, j), j == 0, p);
+    float *qv = e.cg + 9 * (size_t)n, *pv = e.cg + 6 * (size_t)n;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) s_pq[wv][c] = pq[c];
+    for (int c = 0; c < 3; ++c) {
+      qv[c * n + k] = q[c];
+      pv[c * n + k] = p[c];
+      pq[c] = p[c] * q[c];
+    }
+  }
+  if (sub == 0)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s_pq[mk][c] = pq[c];
   __syncthreads();
   if (tid < 3) {
     float t = 0.f;
-    for (int q = 0; q < kInterpPer; ++q) t += s_pq[q][tid];
+    for (int q = 0; q < kInterpMk; ++q) t += s_pq[q][tid];
     cg_pq(e)[4 * (size_t)item + tid] = t;
   }
 }
@@ -781,6 +870,7 @@ __device__ inline void cg_apply_item(const EnvView &e, int item, int tid, int j)
 // also the outputs: F = G / dV, the record's spread value G, and the wrench
 // partials per interpolation item (the layout wrench_sum reads).
 __device__ inline void cg_update_item(const EnvView &e, const FrameF &fr, int item, int j, bool last) {
+#pragma clang fp contract(on)  // as interp_item
   const int n = e.n, k = item * kCgWG + (int)threadIdx.x;
   float pq[3], alpha[3];
   cg_sum3(cg_pq(e), interp_items(n), pq);  // every workgroup, in row order
@@ -840,12 +930,13 @@ __device__ inline void cg_update_item(const EnvView &e, const FrameF &fr, int it
     }
     return;
   }
-  // groups of kInterpPer consecutive markers form one interpolation item
+  // groups of kInterpMk consecutive markers (aligned lanes of one wave) form
+  // one interpolation item
 #pragma unroll
   for (int qd = 0; qd < 7; ++qd)
-    for (int o = kInterpPer / 2; o > 0; o >>= 1) part[qd] += shfl_xor_f(part[qd], o);
-  const int it = k / kInterpPer;
-  if ((k % kInterpPer) == 0 && k < n)
+    for (int o = kInterpMk / 2; o > 0; o >>= 1) part[qd] += shfl_xor_f(part[qd], o);
+  const int it = k / kInterpMk;
+  if ((k % kInterpMk) == 0 && k < n)
 #pragma unroll
     for (int qd = 0; qd < 7; ++qd) e.partials[(size_t)it * 8 + qd] = part[qd];
 }

@@ -812,7 +812,7 @@ lbm_status adjoint_passes(lbm_ctx *c, const EnvView &e, const FrameF &fr, const 
     if ((st = launched()) != LBM_OK) return st;
   }
   if (e.ib) {
-    k_adj_markers<<<interp_items(e.n), WG, 0, c->stream>>>(e, A);
+    k_adj_markers<<<wave_items(e.n), WG, 0, c->stream>>>(e, A);
     k_adj_spread<<<std::min(c->L.cap * kSpreadSplit, 2048), WG, 0, c->stream>>>(e, A);
     if ((st = launched()) != LBM_OK) return st;
   }
@@ -1246,6 +1246,11 @@ struct lbm_batch {
   hipGraph_t graph;
   hipGraphExec_t exec;
   int graph_nsteps, graph_mode;
+  // Concurrent groups of the per-phase driver (empty: one group). Each group
+  // is a batch of its own over a subset of the environments, run on its own
+  // stream between a fork and a join event on this batch's stream.
+  std::vector<lbm_batch *> sub;
+  std::vector<hipEvent_t> sub_ev;  // [0] fork, [1 + g] join of group g
 };
 
 namespace {
@@ -1407,6 +1412,44 @@ void batch_drop_graph(lbm_batch *b) {
   b->graph_nsteps = -1;
 }
 
+void batch_drop_groups(lbm_batch *b);
+
+// Cell-balanced split of the environments into ngroups groups: largest
+// lattice first, each to the group with the fewest cells so far (ties to the
+// lower group); within a group the environments keep the batch's order.
+std::vector<std::vector<int>> batch_partition(const lbm_batch *b, int ngroups) {
+  std::vector<int> order(b->nenv);
+  for (int e = 0; e < b->nenv; ++e) order[e] = e;
+  auto cells = [&](int e) {
+    const lbm_params &q = b->envs[e].ctx->p;
+    return (int64_t)q.nx * q.ny * q.nz;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cells(x) > cells(y); });
+  std::vector<int64_t> load(ngroups, 0);
+  std::vector<int> owner(b->nenv, 0);
+  for (int e : order) {
+    int g = 0;
+    for (int h = 1; h < ngroups; ++h)
+      if (load[h] < load[g]) g = h;
+    owner[e] = g;
+    load[g] += cells(e);
+  }
+  std::vector<std::vector<int>> groups(ngroups);
+  for (int e = 0; e < b->nenv; ++e) groups[owner[e]].push_back(e);
+  return groups;
+}
+
+void batch_drop_groups(lbm_batch *b) {
+  for (lbm_batch *s : b->sub) {
+    (void)hipStreamSynchronize(s->stream);
+    lbm_batch_destroy(s);
+  }
+  for (hipEvent_t ev : b->sub_ev)
+    if (ev) (void)hipEventDestroy(ev);
+  b->sub.clear();
+  b->sub_ev.clear();
+}
+
 }  // namespace
 
 extern "C" {
@@ -1491,6 +1534,20 @@ lbm_status lbm_batch_run(lbm_batch *b, int32_t nsteps, int32_t mode, int32_t gra
   if (mode == LBM_BATCH_PERSISTENT && (b->two_byte || b->implicit)) return LBM_ERR_UNSUPPORTED;
   if (nsteps == 0) return LBM_OK;
   lbm_status st;
+  if (mode == LBM_BATCH_PHASES && !b->sub.empty()) {
+    // groups run concurrently, each on its own stream, after the work already
+    // queued on this batch's stream; this stream then waits for all of them
+    if (hipEventRecord(b->sub_ev[0], b->stream) != hipSuccess) return LBM_ERR_DEVICE;
+    for (size_t g = 0; g < b->sub.size(); ++g) {
+      lbm_batch *s = b->sub[g];
+      if (hipStreamWaitEvent(s->stream, b->sub_ev[0], 0) != hipSuccess) return LBM_ERR_DEVICE;
+      if ((st = lbm_batch_run(s, nsteps, mode, graph)) != LBM_OK) return st;
+      if (hipEventRecord(b->sub_ev[1 + g], s->stream) != hipSuccess ||
+          hipStreamWaitEvent(b->stream, b->sub_ev[1 + g], 0) != hipSuccess)
+        return LBM_ERR_DEVICE;
+    }
+    return LBM_OK;
+  }
   for (int e = 0; e < b->nenv; ++e)
     if (b->views[e].cur0 != b->envs[e].ctx->cur) b->dirty = true;
   if (b->dirty) {
@@ -1577,6 +1634,7 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int32_t reps, int32_t *shapes_out) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   b->dirty = true;
+  for (lbm_batch *s : b->sub) s->dirty = true;
   return st;
 }
 
@@ -1591,6 +1649,7 @@ lbm_status lbm_batch_set_shapes(lbm_batch *b, const int32_t *shapes) {
     b->envs[e].ctx->by = shapes[2 * e + 1];
   }
   b->dirty = true;
+  for (lbm_batch *s : b->sub) s->dirty = true;
   return LBM_OK;
 }
 
@@ -1617,8 +1676,48 @@ lbm_status lbm_batch_check(lbm_batch *b) {
   return LBM_OK;
 }
 
+size_t lbm_batch_group_bytes(int32_t nenv, int32_t ngroups) {
+  if (nenv < 1 || nenv > kMaxEnvs || ngroups < 2 || ngroups > LBM_BATCH_MAX_GROUPS || ngroups > nenv) return 0;
+  // every group holds at most nenv - ngroups + 1 environments
+  return (size_t)ngroups * lbm_batch_bytes(nenv - ngroups + 1);
+}
+
+lbm_status lbm_batch_set_groups(lbm_batch *b, int32_t ngroups, void *const *streams, void *dev) {
+  if (!b || ngroups < 1 || ngroups > LBM_BATCH_MAX_GROUPS || ngroups > b->nenv) return LBM_ERR_ARG;
+  if (ngroups == 1) {
+    batch_drop_groups(b);
+    return LBM_OK;
+  }
+  if (!streams || !dev || reinterpret_cast<uintptr_t>(dev) % 256 != 0) return LBM_ERR_ARG;
+  for (int g = 0; g < ngroups; ++g) {
+    if (!streams[g]) return LBM_ERR_ARG;
+    for (int h = 0; h < g; ++h)
+      if (streams[h] == streams[g]) return LBM_ERR_ARG;
+  }
+  // the work queued on the groups' old streams and tables ends before they change
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return LBM_ERR_DEVICE;
+  batch_drop_groups(b);
+  const std::vector<std::vector<int>> groups = batch_partition(b, ngroups);
+  const size_t slice = lbm_batch_bytes(b->nenv - ngroups + 1);
+  lbm_status st = LBM_OK;
+  b->sub_ev.assign(ngroups + 1, nullptr);
+  for (int k = 0; k <= ngroups && st == LBM_OK; ++k)
+    if (hipEventCreateWithFlags(&b->sub_ev[k], hipEventDisableTiming) != hipSuccess) st = LBM_ERR_DEVICE;
+  for (int g = 0; g < ngroups && st == LBM_OK; ++g) {
+    std::vector<lbm_env> part;
+    for (int e : groups[g]) part.push_back(b->envs[e]);
+    lbm_batch *s = nullptr;
+    st = lbm_batch_create(&s, part.data(), (int32_t)part.size(), static_cast<char *>(dev) + g * slice,
+                          streams[g]);
+    if (st == LBM_OK) b->sub.push_back(s);
+  }
+  if (st != LBM_OK) batch_drop_groups(b);
+  return st;
+}
+
 void lbm_batch_destroy(lbm_batch *b) {
   if (!b) return;
+  batch_drop_groups(b);
   batch_drop_graph(b);
   delete b;
 }

@@ -129,6 +129,9 @@ def lib():
         L.lbm_batch_autotune.argtypes = [vp, ctypes.c_int32, vp]
         L.lbm_batch_set_shapes.argtypes = [vp, vp]
         L.lbm_batch_check.argtypes = [vp]
+        L.lbm_batch_group_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+        L.lbm_batch_group_bytes.restype = sz
+        L.lbm_batch_set_groups.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(vp), vp]
         L.lbm_batch_destroy.argtypes = [vp]
         L.lbm_batch_destroy.restype = None
         L.lbm_step_count.argtypes = [vp]
@@ -145,7 +148,7 @@ def lib():
                      "lbm_swimmer_init", "lbm_swimmer_prepare",
                      "lbm_swimmer_advance",
                      "lbm_batch_create", "lbm_batch_run", "lbm_batch_autotune",
-                     "lbm_batch_set_shapes", "lbm_batch_check"):
+                     "lbm_batch_set_shapes", "lbm_batch_set_groups", "lbm_batch_check"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -519,6 +522,26 @@ class Batch:
         a = np.ascontiguousarray(shapes, dtype=np.int32).reshape(len(self.sims), 2)
         _check(lib().lbm_batch_set_shapes(self.batch, a.ctypes.data_as(ctypes.c_void_p)), "lbm_batch_set_shapes")
 
+    def set_groups(self, ngroups):
+        """Run the per-phase driver as `ngroups` concurrent, cell-balanced
+        groups, each on a stream of its own (default priority); 1 drops them."""
+        L = lib()
+        n = int(ngroups)
+        if n == 1:
+            _check(L.lbm_batch_set_groups(self.batch, 1, None, None), "lbm_batch_set_groups")
+            self._groups = None
+            return
+        nb = L.lbm_batch_group_bytes(len(self.sims), n)
+        if nb == 0:
+            raise LBMError(-1, "group count")
+        raw = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+        shift = (-raw.data_ptr()) % 256
+        streams = [torch.cuda.Stream(self.device) for _ in range(n)]  # default priority
+        arr = (ctypes.c_void_p * n)(*[s.cuda_stream for s in streams])
+        _check(L.lbm_batch_set_groups(self.batch, n, arr, ctypes.c_void_p(raw.data_ptr() + shift)),
+               "lbm_batch_set_groups")
+        self._groups = (raw, streams)
+
     def check(self) -> int:
         return lib().lbm_batch_check(self.batch)
 
@@ -529,6 +552,7 @@ class Batch:
         if getattr(self, "batch", None):
             lib().lbm_batch_destroy(self.batch)
             self.batch = None
+        self._groups = None
         for s in getattr(self, "sims", []):
             s.close()
 

@@ -15,7 +15,7 @@ def say(*a):
     sys.stdout.flush()
 
 
-def gpu_sim(w, storage="f32", f0=None, block=(0, 0), mdf_iters=None, max_active_tiles=0):
+def gpu_sim(w, storage="f32", f0=None, block=(0, 0), mdf_iters=None, max_active_tiles=0, ib_workgroups=0):
     """A context for workload w (its faces, IB scheme and passes)."""
     nb = w.markers.nbones if w.markers is not None else 1
     nm = w.markers.n if w.markers is not None else 0
@@ -24,16 +24,17 @@ def gpu_sim(w, storage="f32", f0=None, block=(0, 0), mdf_iters=None, max_active_
                          rho0=None if f0 is not None else np.ones((w.nz, w.ny, w.nx), np.float32),
                          u0=None if f0 is not None else w.u0.astype(np.float32), block=block,
                          max_active_tiles=max_active_tiles, bc_y=w.bc_y, bc_z=w.bc_z, ib_scheme=w.ib_scheme,
-                         collision=w.collision, trt_lambda=w.trt_lambda, wall_mode=w.wall_mode)
+                         collision=w.collision, trt_lambda=w.trt_lambda, wall_mode=w.wall_mode,
+                         ib_workgroups=ib_workgroups)
     if f0 is not None:
         sim.load_populations(f0)
     return sim
 
 
-def gpu_run(w, nsteps=None, storage="f32", f0=None, block=(0, 0), mdf_iters=None, chunk=None):
+def gpu_run(w, nsteps=None, storage="f32", f0=None, block=(0, 0), mdf_iters=None, chunk=None, ib_workgroups=0):
     """Returns (sim, markers-or-None, wrench (nsteps, 8) numpy)."""
     nsteps = nsteps or w.nsteps
-    sim = gpu_sim(w, storage, f0, block, mdf_iters)
+    sim = gpu_sim(w, storage, f0, block, mdf_iters, ib_workgroups=ib_workgroups)
     dm = lbm.DeviceMarkers(w.markers) if w.markers is not None else None
     poses = torch.as_tensor(np.ascontiguousarray(w.poses[:nsteps], np.float32), device="cuda") if dm else None
     wrench = torch.zeros((nsteps, 8), dtype=torch.float32, device="cuda")

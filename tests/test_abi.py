@@ -118,7 +118,21 @@ def test_adjoint_batch_and_state_calls_on_null_handles_fail_cleanly(L):
     assert L.lbm_batch_autotune(None, 1, None) == -1
     assert L.lbm_batch_set_shapes(None, None) == -1
     assert L.lbm_batch_check(None) == -1
+    assert L.lbm_batch_set_groups(None, 2, None, None) == -1
     L.lbm_batch_destroy(None)
+
+
+def test_batch_group_bytes_cover_every_group(L):
+    """Each of g groups holds at most nenv - g + 1 environments (the split
+    gives every group one), so g such slices cover any split; counts outside
+    [2, min(nenv, 8)] are refused."""
+    for nenv in (2, 5, 64, 512):
+        for g in range(2, min(nenv, 8) + 1):
+            assert L.lbm_batch_group_bytes(nenv, g) == g * L.lbm_batch_bytes(nenv - g + 1)
+    assert L.lbm_batch_group_bytes(64, 1) == 0
+    assert L.lbm_batch_group_bytes(64, 9) == 0
+    assert L.lbm_batch_group_bytes(3, 4) == 0
+    assert L.lbm_batch_group_bytes(0, 2) == 0
 
 
 def test_implicit_scheme_workspace_holds_its_buffers(L):

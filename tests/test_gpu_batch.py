@@ -197,3 +197,42 @@ def test_two_byte_environments_match_lone_runs():
             b.run(n, mode="persistent", graph=graph)
         assert ei.value.code == lbm.ERR_UNSUPPORTED
         b.close()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_concurrent_groups_match_one_group(graph):
+    """Five environments split into three cell-balanced groups, each on its
+    own stream: every population and wrench equals the one-group per-phase
+    run, also when grouped and ungrouped runs alternate (each run continues
+    from the state the previous one left) and after the shapes change."""
+    n = 10
+    envs = I.batch_workloads(count=5, seed=31, nsteps=n)
+    ref = lbm.Batch(envs, n)
+    b = lbm.Batch(envs, n)
+    b.set_groups(3)
+    for rnd, grouped in enumerate((True, False, True)):
+        if rnd == 2:
+            shapes = b.autotune(reps=1)
+            ref.set_shapes(shapes)
+        if not grouped:
+            b.set_groups(1)
+        b.run(n, mode="phases", graph=graph)
+        ref.run(n, mode="phases", graph=graph)
+        assert b.check() == 0 and ref.check() == 0
+        for j, (x, y) in enumerate(zip(_read_all(b), _read_all(ref))):
+            d = np.abs(x - y).max()
+            say(f"graph={graph} run {rnd} grouped={grouped} env {j}: max |df| vs one group {d:.3e}")
+            assert d == 0.0
+            assert np.array_equal(b.wrench[j].cpu().numpy(), ref.wrench[j].cpu().numpy())
+        if not grouped:
+            b.set_groups(3)
+    b.close()
+    ref.close()
+
+
+def test_group_counts_outside_range_rejected():
+    b = lbm.Batch(_envs(count=3), NSTEPS)
+    for g in (0, 4, 9):
+        with pytest.raises(lbm.LBMError):
+            b.set_groups(g)
+    b.close()

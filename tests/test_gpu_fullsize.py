@@ -15,7 +15,13 @@ from gpu_helpers import gpu_run, interior, oracle_run, random_state, rel_l2, say
 pytestmark = pytest.mark.gpu
 
 
+HEADLINE_IB_WORKGROUPS = 48  # bench.py's headline launch configuration
+
+
 def test_full_size_fish_one_step():
+    """Also the headline's launch configuration (the immersed-boundary chain
+    in 48 workgroups beside the collide, one launch): bit for bit the step
+    with every phase in its own launch."""
     w = I.fish_workload(nsteps=1, start=123)
     say("full size: generating state")
     f0 = random_state(w, 11, du=0.02, noise=5e-5)
@@ -24,6 +30,13 @@ def test_full_size_fish_one_step():
     got = sim.read_populations().cpu().numpy()
     X, U, F = dm.X.cpu().numpy(), dm.U.cpu().numpy(), dm.F.cpu().numpy()
     assert sim.check() == 0
+    del sim
+    torch.cuda.empty_cache()
+    say("full size: GPU step, immersed boundary beside the collide")
+    sim, dm2, wr2 = gpu_run(w, nsteps=1, f0=f0, ib_workgroups=HEADLINE_IB_WORKGROUPS)
+    assert sim.check() == 0
+    assert np.array_equal(sim.read_populations().cpu().numpy(), got)
+    assert np.array_equal(dm2.F.cpu().numpy(), F) and np.array_equal(wr2, wr)
     del sim
     torch.cuda.empty_cache()
     say("full size: oracle step")

@@ -1,6 +1,7 @@
 """The immersed-boundary phases beside the collide in one launch
-(k_step_overlap, the default with direct forcing) against the same phases in
-launches of their own before the collide (lbm_params.ib_workgroups = -1):
+(k_step_overlap, lbm_params.ib_workgroups > 0, the benchmark's headline
+configuration) against the same phases in launches of their own before the
+collide (ib_workgroups = 0 or -1):
 the arithmetic is the same inline code, so every result must agree bit for
 bit, for any number of chain workgroups, with multi-direct forcing passes,
 2-byte storage, TRT, open y/z faces, a rotating frame and a body across the
