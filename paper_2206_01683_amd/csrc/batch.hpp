@@ -71,10 +71,26 @@ __device__ inline int find_env(const int *pre, int nenv, int item) {
 }
 
 // Exclusive prefix over environments of (active tiles x mult), in LDS.
-// Returns the total. Every thread of the workgroup must call it.
+// Returns the total. Every thread of the workgroup must call it. Up to 64
+// environments the first wave scans them with lane shuffles (one barrier);
+// more take the workgroup-wide scan.
 __device__ inline int dynamic_prefix(const BatchArgs &b, int mult, int *s_pre, int tid) {
   int v = 0;
   if (tid < b.nenv) v = n_active_of(b.envs[tid]) * mult;
+  if (b.nenv <= 64) {
+    if (tid < 64) {
+      const int lane = tid;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int up = __builtin_amdgcn_ds_bpermute((lane >= off ? lane - off : lane) << 2, v);
+        if (lane >= off) v += up;
+      }
+      s_pre[tid + 1] = v;
+      if (tid == 0) s_pre[0] = 0;
+    }
+    __syncthreads();
+    return s_pre[b.nenv];
+  }
   s_pre[tid + 1] = v;
   if (tid == 0) s_pre[0] = 0;
   __syncthreads();
@@ -224,7 +240,7 @@ __device__ inline void phase_spread(const BatchArgs &b, int s, bool final_pass, 
   const int local = item - s_pre[ei];
   if (final_pass && local == 0 && e.wrench != nullptr)
     wrench_sum(e.partials, interp_items(e.n), e.wrench + (size_t)8 * s, tid);
-  spread_item(e, local, tid);
+  spread_item<kBatchSpreadSplit>(e, local, tid);
 }
 
 // Collide item -> (environment, logical block); 512 threads as e.bx x e.by.
@@ -286,19 +302,20 @@ __global__ void __launch_bounds__(kCgWG) kb_cg_init(BatchArgs b, int s) {
 // Spreading of CG step j's search direction into each environment's gcg.
 __global__ void __launch_bounds__(WG) kb_spread_cg(BatchArgs b, int j) {
   __shared__ int s_pre[kMaxEnvs + 1];
-  const int tot = dynamic_prefix(b, kSpreadSplit, s_pre, threadIdx.x);
+  const int tot = dynamic_prefix(b, kBatchSpreadSplit, s_pre, threadIdx.x);
   for (int item = blockIdx.x; item < tot; item += gridDim.x) {
     const int ei = find_env(s_pre, b.nenv, item);
     const EnvView &e = b.envs[ei];
-    spread_item<true>(e, item - s_pre[ei], threadIdx.x, e.gcg, cg_scal(e, 1, j), j == 0);
+    spread_item<true, kBatchSpreadSplit>(e, item - s_pre[ei], threadIdx.x, e.gcg, cg_scal(e, 1, j), j == 0);
   }
 }
 
 // Grid: the total of PRE_INTERP (each environment's interpolation items).
 __global__ void __launch_bounds__(WG) kb_cg_apply(BatchArgs b, int j) {
   const int *pre = b.pre + PRE_INTERP * (b.nenv + 1);
-  const int ei = find_env(pre, b.nenv, blockIdx.x);
-  cg_apply_item(b.envs[ei], blockIdx.x - pre[ei], threadIdx.x, j);
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  const int ei = find_env(pre, b.nenv, item);
+  cg_apply_item(b.envs[ei], item - pre[ei], threadIdx.x, j);
 }
 
 // Grid: the total of PRE_CG.
@@ -334,12 +351,14 @@ __global__ void __launch_bounds__(WG) kb_macro(BatchArgs b, int s) {
 
 template <bool UNI>
 __global__ void __launch_bounds__(WG) kb_interp(BatchArgs b, int s, int pass) {
-  phase_interp<UNI>(b, s, pass, blockIdx.x, threadIdx.x);
+  // grid = every environment's interpolation items; each XCD takes consecutive
+  // items (the markers of a few environments), so its L2 holds their band macros
+  phase_interp<UNI>(b, s, pass, xcd_item(blockIdx.x, gridDim.x), threadIdx.x);
 }
 
 __global__ void __launch_bounds__(WG) kb_spread(BatchArgs b, int s, int final_pass) {
   __shared__ int s_pre[kMaxEnvs + 1];
-  const int tot = dynamic_prefix(b, kSpreadSplit, s_pre, threadIdx.x);
+  const int tot = dynamic_prefix(b, kBatchSpreadSplit, s_pre, threadIdx.x);
   for (int item = blockIdx.x; item < tot; item += gridDim.x)
     phase_spread(b, s, final_pass != 0, item, s_pre, threadIdx.x);
 }
@@ -459,7 +478,7 @@ __global__ void __launch_bounds__(WG, 6) kb_persistent(BatchArgs b, int nsteps) 
     int tot;
     {
       const int tid = phase_tid();
-      tot = dynamic_prefix(b, kSpreadSplit, s_pre, tid);
+      tot = dynamic_prefix(b, kBatchSpreadSplit, s_pre, tid);
     }
     for (int pass = 0; pass < b.mdf; ++pass) {
       if (pass > 0) {

@@ -28,7 +28,8 @@ namespace lbmib {
 
 constexpr int WG = 512;              // threads per workgroup in every IB phase
 constexpr int REC = 20;              // floats per marker record: w[12], base[3], pad, fdv[3], pad
-constexpr int kSpreadSplit = 4;      // spreading work items per active tile
+constexpr int kSpreadSplit = 4;      // spreading work items per active tile (single lattice)
+constexpr int kBatchSpreadSplit = 2; // the same in the batched forms, whose many tiles need less splitting
 constexpr int kWavePer = WG / 64;    // markers per item of the one-wave-per-marker kernels (adjoint)
 constexpr int kInterpMk = WG / 16;   // markers per interpolation (and CG apply) item, 16 lanes each
 
@@ -258,6 +259,15 @@ __device__ inline XcdWalk xcd_walk(int tot, int blk, int grid) {
   return {lo + r, hi, per};
 }
 __device__ inline XcdWalk xcd_walk(int tot) { return xcd_walk(tot, (int)blockIdx.x, (int)gridDim.x); }
+
+// Item of workgroup blk in a grid of exactly `grid` workgroups, one item each,
+// XCD-contiguous: with grid = 8q + m, XCD x (workgroups x, x + 8, ...) takes
+// the q + (x < m) consecutive items from x q + min(x, m) on. A bijection of
+// 0 .. grid-1, so every item runs once.
+__device__ inline int xcd_item(int blk, int grid) {
+  const int q = grid / kXcds, m = grid % kXcds, x = blk % kXcds;
+  return x * q + min(x, m) + blk / kXcds;
+}
 
 // ----------------------------------------------------------- band macros --
 // Density and unforced velocity u* (frame force, no IB force) of every cell
@@ -517,7 +527,7 @@ __device__ inline void cg_direction(const EnvView &e, int k, const float *beta, 
 // CG = true: the spread values are the search direction of the implicit
 // correction's conjugate-gradient step (cg_direction with beta, first), not
 // the record's.
-template <bool CG>
+template <bool CG, int SPLIT = kSpreadSplit>
 __device__ inline void spread_item(const EnvView &e, int item, int tid, unsigned long long *target,
                                    const float *beta = nullptr, bool first = true) {
   __shared__ unsigned long long s_acc[3][512];
@@ -525,12 +535,12 @@ __device__ inline void spread_item(const EnvView &e, int item, int tid, unsigned
   const GridArgs &g = e.g;
   const int n = e.n;
   const int nchunks = (n + 63) >> 6;
-  const int slot = item / kSpreadSplit, part = item % kSpreadSplit;
+  const int slot = item / SPLIT, part = item % SPLIT;
   const int t = e.active[slot];
   const int tx = t % g.tnx, ty = (t / g.tnx) % g.tny, tz = t / (g.tnx * g.tny);
   for (int q = tid; q < 3 * 512; q += WG) (&s_acc[0][0])[q] = 0ull;
   __syncthreads();
-  const int stride = (WG / 64) * kSpreadSplit;
+  const int stride = (WG / 64) * SPLIT;
   const int c_first = part * (WG / 64) + wv;
   for (int it = 0; c_first + stride * 64 * it < nchunks; ++it) {
     const int cl = c_first + stride * (lane + 64 * it);  // chunk examined by this lane
@@ -610,7 +620,10 @@ __device__ inline void spread_item(const EnvView &e, int item, int tid, unsigned
   __syncthreads();
 }
 
-__device__ inline void spread_item(const EnvView &e, int item, int tid) { spread_item<false>(e, item, tid, e.gfix); }
+template <int SPLIT = kSpreadSplit>
+__device__ inline void spread_item(const EnvView &e, int item, int tid) {
+  spread_item<false, SPLIT>(e, item, tid, e.gfix);
+}
 
 // ----------------------------------------------- single-lattice launches --
 __global__ void __launch_bounds__(WG) k_skin_mark(EnvView e, const float *pose) {
@@ -625,9 +638,11 @@ __global__ void __launch_bounds__(WG) k_macro(EnvView e, FrameF fr, int cur) {
   for (int slot = w.first; slot < w.end; slot += w.step) macro_item<S, ROT>(e, fr, cur, slot, threadIdx.x);
 }
 
+// Grid: exactly interp_items(n) workgroups. The markers of one XCD are
+// consecutive, so its L2 holds the band macros of their stretch of body.
 template <bool ROT, bool MDF>
 __global__ void __launch_bounds__(WG) k_interp(EnvView e, FrameF fr, float *partials) {
-  interp_item<ROT, MDF>(e, fr, blockIdx.x, threadIdx.x, partials);
+  interp_item<ROT, MDF>(e, fr, xcd_item(blockIdx.x, gridDim.x), threadIdx.x, partials);
 }
 
 // wrench != nullptr: workgroup 0 first sums the interpolation partials.
@@ -953,7 +968,9 @@ __global__ void __launch_bounds__(WG) k_spread_cg(EnvView e, int j) {
 }
 
 // Grid: exactly interp_items(n) workgroups (the last-arrival count).
-__global__ void __launch_bounds__(WG) k_cg_apply(EnvView e, int j) { cg_apply_item(e, blockIdx.x, threadIdx.x, j); }
+__global__ void __launch_bounds__(WG) k_cg_apply(EnvView e, int j) {
+  cg_apply_item(e, xcd_item(blockIdx.x, gridDim.x), threadIdx.x, j);
+}
 
 // Grid: at least cg_items(n) workgroups; the first cg_items(n) take the
 // markers, and all of them clear gcg for the next step's spread (not after
