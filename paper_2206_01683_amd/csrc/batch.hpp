@@ -108,7 +108,7 @@ __device__ inline int dynamic_prefix(const BatchArgs &b, int mult, int *s_pre, i
 // for the collide.
 __device__ inline float uniform_f(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
 __device__ inline FrameF env_frame(const EnvView &e, int s) {
-  FrameF f = frame_from(e.frames + (size_t)18 * s);
+  FrameF f = frame_from((const gmem<double> *)e.frames + (size_t)18 * s);
   for (int a = 0; a < 3; ++a) {
     f.acc[a] = uniform_f(f.acc[a]);
     f.omg[a] = uniform_f(f.omg[a]);

@@ -96,7 +96,8 @@ __device__ inline bool cell_of(const EnvView &e, int lb, int tx, int ty, int &x,
 }
 
 // lbm_frame (18 doubles) -> float32 frame constants
-__device__ inline FrameF frame_from(const double *d) {
+template <class P>
+__device__ inline FrameF frame_from(P d) {
   FrameF f;
   for (int a = 0; a < 3; ++a) {
     f.acc[a] = (float)d[a];

@@ -17,9 +17,9 @@ namespace lbmib {
 // neighbour indices xm/xp are given by the caller (periodic wrap or interior
 // node). Offsets are 64-bit (27 populations of a large lattice pass 2^32
 // elements).
-template <class S, bool DEV = false>
-__device__ inline void pull27(const typename S::T *__restrict__ src, const GridArgs &g, int xm, int xs, int xp,
-                              int ym, int y, int yp, int zm, int z, int zp, float f[Q]) {
+template <class S, bool DEV = false, class P>
+__device__ inline void pull27(P src, const GridArgs &g, int xm, int xs, int xp, int ym, int y, int yp, int zm, int z,
+                              int zp, float f[Q]) {
   const int xx[3] = {xp, xs, xm};  // indexed by cx + 1: source x = xs - cx
   const int yy[3] = {yp, y, ym};
   const int zz[3] = {zp, z, zm};
@@ -79,10 +79,10 @@ __device__ inline void load_g(const GridArgs &g, const int *__restrict__ tile_sl
   gx = gy = gz = 0.f;
   if (tile_slot == nullptr) return;
   int t = (x >> 3) + g.tnx * ((y >> 3) + g.tny * (z >> 3));
-  int s = tile_slot[t];
+  int s = ((const gmem<int> *)tile_slot)[t];
   if (s >= 0) {
     int lc = (x & 7) | ((y & 7) << 3) | ((z & 7) << 6);
-    const unsigned long long *gp = gfix + (size_t)s * 1536;
+    const gmem<unsigned long long> *gp = (const gmem<unsigned long long> *)gfix + (size_t)s * 1536;
     gx = from_fix(gp[lc]);
     gy = from_fix(gp[512 + lc]);
     gz = from_fix(gp[1024 + lc]);
@@ -114,7 +114,7 @@ struct CellAt {
 template <class S, bool XPER, bool YZ = false>
 __device__ inline bool collide_load(const EnvView &e, int cur, int lb, int tx, int ty, CellAt &c, float f[Q]) {
   using T = typename S::T;
-  const T *__restrict__ src = static_cast<const T *>(e.f[cur]);
+  const gmem<T> *__restrict__ src = (const gmem<T> *)e.f[cur];
   int x, y, z;
   if (!cell_of(e, lb, tx, ty, x, y, z)) return false;
   const GridArgs &g = e.g;
@@ -167,7 +167,7 @@ __device__ inline void collide_finish(const EnvView &e, const FrameF &fr, int cu
   // single-lattice, batched and persistent collides give the same bits)
 #pragma clang fp contract(on)
   using T = typename S::T;
-  T *__restrict__ dst = static_cast<T *>(e.f[cur ^ 1]);
+  gmem<T> *__restrict__ dst = (gmem<T> *)e.f[cur ^ 1];
   const int *__restrict__ tile_slot = e.ib ? e.tile_slot : nullptr;
   const GridArgs &g = e.g;
   const int x = c.x, y = c.y, z = c.z, xs = c.xs;
@@ -245,7 +245,7 @@ __device__ inline void collide_finish(const EnvView &e, const FrameF &fr, int cu
   // heq_i = f^eq_i - w_i = w_i [(rho - 1) + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u^2)].
   const float Ah = -1.5f * u2;
   const float uF = ux * Fx + uy * Fy + uz * Fz;
-  typename S::T *__restrict__ d = dst + pop_idx(g, 0, (uint32_t)z * (uint32_t)g.ny + (uint32_t)y, (uint32_t)x);
+  gmem<T> *__restrict__ d = dst + pop_idx(g, 0, (uint32_t)z * (uint32_t)g.ny + (uint32_t)y, (uint32_t)x);
   if constexpr (!TRT) {
     const float E = e.inv_tau * rho;
     const float B = e.inv_tau * drho;

@@ -275,9 +275,9 @@ __device__ inline int xcd_item(int blk, int grid) {
 template <class S, bool ROT>
 __device__ inline void macro_item(const EnvView &e, const FrameF &fr, int cur, int slot, int tid) {
   using T = typename S::T;
-  const T *__restrict__ src = static_cast<const T *>(e.f[cur]);
+  const gmem<T> *__restrict__ src = (const gmem<T> *)e.f[cur];
   const GridArgs &g = e.g;
-  const int t = e.active[slot];
+  const int t = ((const gmem<int> *)e.active)[slot];
   const int tx = t % g.tnx, ty = (t / g.tnx) % g.tny, tz = t / (g.tnx * g.tny);
   const int x = tx * 8 + (tid & 7), y = ty * 8 + ((tid >> 3) & 7), z = tz * 8 + (tid >> 6);
   float4 out = make_float4(1.f, 0.f, 0.f, 0.f);
@@ -297,13 +297,13 @@ __device__ inline void macro_item(const EnvView &e, const FrameF &fr, int cur, i
     solve_coriolis<ROT>(fr, mx * ir + 0.5f * ax, my * ir + 0.5f * ay, mz * ir + 0.5f * az, ux, uy, uz);
     out = make_float4(rho, ux, uy, uz);
   }
-  e.macro[(size_t)slot * 512 + tid] = out;
-  unsigned long long *gp = e.gfix + (size_t)slot * 1536;
+  ((gmem<vfloat4> *)e.macro)[(size_t)slot * 512 + tid] = vfloat4{out.x, out.y, out.z, out.w};
+  gmem<unsigned long long> *gp = (gmem<unsigned long long> *)e.gfix + (size_t)slot * 1536;
   gp[tid] = 0ull;
   gp[512 + tid] = 0ull;
   gp[1024 + tid] = 0ull;
   if (e.gcg != nullptr) {  // implicit correction: its search-direction force starts at zero too
-    unsigned long long *gq = e.gcg + (size_t)slot * 1536;
+    gmem<unsigned long long> *gq = (gmem<unsigned long long> *)e.gcg + (size_t)slot * 1536;
     gq[tid] = 0ull;
     gq[512 + tid] = 0ull;
     gq[1024 + tid] = 0ull;
@@ -372,6 +372,11 @@ __device__ inline void interp_item(const EnvView &e, const FrameF &fr, int item,
   const int n = e.n;
   const GridArgs &g = e.g;
   const bool live = k < n;
+  // the environment's arrays through global pointers (see gmem)
+  const gmem<float> *X = (const gmem<float> *)e.X, *U = (const gmem<float> *)e.U;
+  const gmem<int> *tile_slot = (const gmem<int> *)e.tile_slot;
+  const gmem<vfloat4> *macro = (const gmem<vfloat4> *)e.macro;
+  gmem<float> *F = (gmem<float> *)e.F, *mstate = (gmem<float> *)e.mstate;
   float part[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   float Xk[3] = {0.f, 0.f, 0.f}, Uk[3] = {0.f, 0.f, 0.f}, dvk = 0.f;
   StencilRow st{};
@@ -379,29 +384,30 @@ __device__ inline void interp_item(const EnvView &e, const FrameF &fr, int item,
   if (live) {
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      Xk[ax] = e.X[ax * n + k];
+      Xk[ax] = X[ax * n + k];
       // loaded now, used after the stencil gather: off the dependent chain
-      Uk[ax] = e.U[ax * n + k];
+      Uk[ax] = U[ax * n + k];
     }
-    dvk = e.dv[k];
+    dvk = ((const gmem<float> *)e.dv)[k];
     st = stencil_row(g, Xk, sub);
     int sl[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) sl[i] = e.tile_slot[st.tile[i]];
+    for (int i = 0; i < 4; ++i) sl[i] = tile_slot[st.tile[i]];
     float4 m[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       m[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (sl[i] >= 0)
-        m[i] = e.macro[(size_t)sl[i] * 512 + st.lc[i]];
-      else
+      if (sl[i] >= 0) {
+        const vfloat4 v = macro[(size_t)sl[i] * 512 + st.lc[i]];
+        m[i] = make_float4(v.x, v.y, v.z, v.w);
+      } else
         atomicOr(e.guard, (int)GUARD_CAPACITY);
     }
     if (MDF) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         if (sl[i] < 0) continue;
-        const unsigned long long *gp = e.gfix + (size_t)sl[i] * 1536;
+        const gmem<unsigned long long> *gp = (const gmem<unsigned long long> *)e.gfix + (size_t)sl[i] * 1536;
         const float h = 0.5f / m[i].x;
         float dx, dy, dz;
         solve_coriolis<ROT>(fr, from_fix(gp[st.lc[i]]) * h, from_fix(gp[512 + st.lc[i]]) * h,
@@ -427,8 +433,8 @@ __device__ inline void interp_item(const EnvView &e, const FrameF &fr, int item,
   sy = group16_sum(sy);
   sz = group16_sum(sz);
   if (live) {
-    float *r = e.rec + (size_t)k * REC;
-    if (sub == 0) *reinterpret_cast<float4 *>(r) = make_float4(st.wx[0], st.wx[1], st.wx[2], st.wx[3]);
+    gmem<float> *r = (gmem<float> *)e.rec + (size_t)k * REC;
+    if (sub == 0) *(gmem<vfloat4> *)r = vfloat4{st.wx[0], st.wx[1], st.wx[2], st.wx[3]};
     if (sub < 4) r[4 + sub] = st.wy;                // row (sy, 0)
     if ((sub & 3) == 0) r[8 + (sub >> 2)] = st.wz;  // row (0, sz)
     if (sub == 0) {
@@ -445,25 +451,25 @@ __device__ inline void interp_item(const EnvView &e, const FrameF &fr, int item,
       }
       if (!MDF) {
         rk = sr;
-        e.mstate[k] = rk;
+        mstate[k] = rk;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          e.mstate[(c + 1) * (size_t)n + k] = Ui[c];
+          mstate[(c + 1) * (size_t)n + k] = Ui[c];
           inc[c] = e.alpha2 * rk * dU[c];
           Fk[c] = inc[c];
         }
       } else {
-        rk = e.mstate[k];
+        rk = mstate[k];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           inc[c] = e.alpha2 * rk * dU[c];
-          Fk[c] = e.F[c * n + k] + inc[c];
+          Fk[c] = F[c * n + k] + inc[c];
         }
       }
       float fd[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        e.F[c * n + k] = Fk[c];
+        F[c * n + k] = Fk[c];
         fd[c] = Fk[c] * dvk;
         r[16 + c] = inc[c] * dvk;
         r[12 + c] = __int_as_float(st.base[c]);
@@ -536,7 +542,7 @@ __device__ inline void spread_item(const EnvView &e, int item, int tid, unsigned
   const int n = e.n;
   const int nchunks = (n + 63) >> 6;
   const int slot = item / SPLIT, part = item % SPLIT;
-  const int t = e.active[slot];
+  const int t = ((const gmem<int> *)e.active)[slot];
   const int tx = t % g.tnx, ty = (t / g.tnx) % g.tny, tz = t / (g.tnx * g.tny);
   for (int q = tid; q < 3 * 512; q += WG) (&s_acc[0][0])[q] = 0ull;
   __syncthreads();
@@ -546,7 +552,8 @@ __device__ inline void spread_item(const EnvView &e, int item, int tid, unsigned
     const int cl = c_first + stride * (lane + 64 * it);  // chunk examined by this lane
     bool pass = false;
     if (cl < nchunks) {
-      const int4 box = e.chunk_box[cl];
+      const gmem<int> *bp = (const gmem<int> *)e.chunk_box + 4 * (size_t)cl;
+      const int4 box = make_int4(bp[0], bp[1], bp[2], bp[3]);
       pass = box_hits(box.x, tx) && box_hits(box.y, ty) && box_hits(box.z, tz);
     }
     unsigned long long cbal = __ballot(pass);
@@ -556,16 +563,17 @@ __device__ inline void spread_item(const EnvView &e, int item, int tid, unsigned
       const int k = (c_first + stride * (jc + 64 * it)) * 64 + lane;
       bool hit = false;
       if (k < n) {
-        const short4 b = e.mbase[k];
+        const gmem<short> *mb = (const gmem<short> *)e.mbase + 4 * (size_t)k;
+        const short4 b = make_short4(mb[0], mb[1], mb[2], mb[3]);
         hit = axis_touches(b.x, g.nx, g.xper, tx) && axis_touches(b.y, g.ny, true, ty) &&
               axis_touches(b.z, g.nz, true, tz);
       }
       if (hit) {
         float r[20];
-        const float4 *rp = reinterpret_cast<const float4 *>(e.rec + (size_t)k * REC);
+        const gmem<vfloat4> *rp = (const gmem<vfloat4> *)e.rec + (size_t)k * (REC / 4);
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-          const float4 v = rp[q];
+          const vfloat4 v = rp[q];
           r[4 * q] = v.x;
           r[4 * q + 1] = v.y;
           r[4 * q + 2] = v.z;
@@ -612,10 +620,10 @@ __device__ inline void spread_item(const EnvView &e, int item, int tid, unsigned
     }
   }
   __syncthreads();
-  unsigned long long *gp = target + (size_t)slot * 1536;
+  gmem<unsigned long long> *gp = (gmem<unsigned long long> *)target + (size_t)slot * 1536;
   for (int q = tid; q < 3 * 512; q += WG) {
     const unsigned long long v = (&s_acc[0][0])[q];
-    if (v != 0ull) atomicAdd(&gp[q], v);
+    if (v != 0ull) __hip_atomic_fetch_add(&gp[q], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
 }

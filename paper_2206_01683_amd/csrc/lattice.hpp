@@ -22,6 +22,16 @@ __host__ __device__ constexpr float w_of(int i) {
   return c2_of(i) == 0 ? 8.0f / 27.0f : c2_of(i) == 1 ? 2.0f / 27.0f : c2_of(i) == 2 ? 1.0f / 54.0f : 1.0f / 216.0f;
 }
 
+// Device memory seen through the global address space. A pointer read from
+// memory (an EnvView in the batched forms' descriptor array) carries no
+// address space, and the compiler then accesses it with flat instructions,
+// which also count against the wait counter of LDS and scalar loads, so a
+// wait for one of those waits for every population load in flight. The hot
+// loads and stores go through pointers cast to this space instead.
+template <class T>
+using gmem = __attribute__((address_space(1))) T;
+typedef float vfloat4 __attribute__((ext_vector_type(4)));  // float4 as a native vector (stores through gmem)
+
 // ------------------------------------------------------------- storage ----
 // Every format keeps h_i = f_i - w_i, the offset from the rest equilibrium:
 // F32 as float, F16 / BF16 rounded to nearest even. The collide works on h
@@ -31,23 +41,33 @@ __host__ __device__ constexpr float w_of(int i) {
 struct StoreF32 {
   using T = float;
   static constexpr int kind = 0;
-  __device__ static inline float load_dev(const T *p, int) { return *p; }
-  __device__ static inline void store_dev(T *p, float h, int) { __builtin_nontemporal_store(h, p); }
-  __device__ static inline float load(const T *p, int i) { return w_of(i) + *p; }
-  __device__ static inline void store(T *p, float f, int i) { __builtin_nontemporal_store(f - w_of(i), p); }
-  __device__ static inline void store_plain(T *p, float f, int i) { *p = f - w_of(i); }
+  template <class P>
+  __device__ static inline float load_dev(P p, int) { return *p; }
+  template <class P>
+  __device__ static inline void store_dev(P p, float h, int) { __builtin_nontemporal_store(h, p); }
+  template <class P>
+  __device__ static inline float load(P p, int i) { return w_of(i) + *p; }
+  template <class P>
+  __device__ static inline void store(P p, float f, int i) { __builtin_nontemporal_store(f - w_of(i), p); }
+  template <class P>
+  __device__ static inline void store_plain(P p, float f, int i) { *p = f - w_of(i); }
 };
 
 struct StoreF16 {
   using T = _Float16;
   static constexpr int kind = 1;
-  __device__ static inline float load_dev(const T *p, int) { return (float)(*p); }
-  __device__ static inline void store_dev(T *p, float h, int) { __builtin_nontemporal_store((_Float16)h, p); }
-  __device__ static inline float load(const T *p, int i) { return w_of(i) + (float)(*p); }
-  __device__ static inline void store(T *p, float f, int i) {
+  template <class P>
+  __device__ static inline float load_dev(P p, int) { return (float)(*p); }
+  template <class P>
+  __device__ static inline void store_dev(P p, float h, int) { __builtin_nontemporal_store((_Float16)h, p); }
+  template <class P>
+  __device__ static inline float load(P p, int i) { return w_of(i) + (float)(*p); }
+  template <class P>
+  __device__ static inline void store(P p, float f, int i) {
     __builtin_nontemporal_store((_Float16)(f - w_of(i)), p);
   }
-  __device__ static inline void store_plain(T *p, float f, int i) { *p = (_Float16)(f - w_of(i)); }
+  template <class P>
+  __device__ static inline void store_plain(P p, float f, int i) { *p = (_Float16)(f - w_of(i)); }
 };
 
 struct StoreBF16 {
@@ -60,11 +80,16 @@ struct StoreBF16 {
     u += 0x7FFFu + ((u >> 16) & 1u);
     return (uint16_t)(u >> 16);
   }
-  __device__ static inline float load_dev(const T *p, int) { return to_f(*p); }
-  __device__ static inline void store_dev(T *p, float h, int) { __builtin_nontemporal_store(to_h(h), p); }
-  __device__ static inline float load(const T *p, int i) { return w_of(i) + to_f(*p); }
-  __device__ static inline void store(T *p, float f, int i) { __builtin_nontemporal_store(to_h(f - w_of(i)), p); }
-  __device__ static inline void store_plain(T *p, float f, int i) { *p = to_h(f - w_of(i)); }
+  template <class P>
+  __device__ static inline float load_dev(P p, int) { return to_f(*p); }
+  template <class P>
+  __device__ static inline void store_dev(P p, float h, int) { __builtin_nontemporal_store(to_h(h), p); }
+  template <class P>
+  __device__ static inline float load(P p, int i) { return w_of(i) + to_f(*p); }
+  template <class P>
+  __device__ static inline void store(P p, float f, int i) { __builtin_nontemporal_store(to_h(f - w_of(i)), p); }
+  template <class P>
+  __device__ static inline void store_plain(P p, float f, int i) { *p = to_h(f - w_of(i)); }
 };
 
 // ------------------------------------------------------------- frames -----
