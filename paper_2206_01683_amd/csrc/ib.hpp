@@ -105,25 +105,31 @@ __device__ inline void skin_item(const EnvView &e, const float *__restrict__ pos
   const int tns[3] = {e.g.tnx, e.g.tny, (e.g.nz + 7) >> 3};
   const int dims[3] = {e.g.nx, e.g.ny, e.g.nz};
   int lo[3] = {1 << 20, 1 << 20, 1 << 20}, hi[3] = {-1, -1, -1};
+  // the environment's arrays through global pointers (see gmem)
+  const gmem<float> *xrest = (const gmem<float> *)e.xrest, *nrest = (const gmem<float> *)e.nrest;
+  const gmem<float> *weight = (const gmem<float> *)e.weight, *gpose = (const gmem<float> *)pose;
+  const gmem<int> *bone = (const gmem<int> *)e.bone;
+  gmem<float> *X = (gmem<float> *)e.X, *U = (gmem<float> *)e.U;
+  gmem<int> *tile_flag = (gmem<int> *)e.tile_flag;
   if (k < n) {
-    const float r0 = e.xrest[k], r1 = e.xrest[n + k], r2 = e.xrest[2 * n + k];
+    const float r0 = xrest[k], r1 = xrest[n + k], r2 = xrest[2 * n + k];
     float p[3] = {0.f, 0.f, 0.f}, v[3] = {0.f, 0.f, 0.f}, nv[3] = {0.f, 0.f, 0.f};
     float n0 = 0.f, n1 = 0.f, n2 = 0.f;
     if (e.slip) {
-      n0 = e.nrest[k];
-      n1 = e.nrest[n + k];
-      n2 = e.nrest[2 * n + k];
+      n0 = nrest[k];
+      n1 = nrest[n + k];
+      n2 = nrest[2 * n + k];
     }
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      int b = e.bone[j * n + k];
-      float w = e.weight[j * n + k];
+      int b = bone[j * n + k];
+      float w = weight[j * n + k];
       if ((unsigned)b >= (unsigned)e.nbones) {
         atomicOr(e.guard, (int)GUARD_BONE);
         b = 0;
         w = 0.f;
       }
-      const float *P = pose + 24 * b;
+      const gmem<float> *P = gpose + 24 * b;
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
         p[r] += w * (P[3 * r] * r0 + P[3 * r + 1] * r1 + P[3 * r + 2] * r2 + P[9 + r]);
@@ -137,7 +143,7 @@ __device__ inline void skin_item(const EnvView &e, const float *__restrict__ pos
     if (e.slip) {  // the rest normal turned by the blended rotations, unit length
       const float il = rsqrtf(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
 #pragma unroll
-      for (int r = 0; r < 3; ++r) e.Nrm[r * n + k] = nv[r] * il;
+      for (int r = 0; r < 3; ++r) ((gmem<float> *)e.Nrm)[r * n + k] = nv[r] * il;
     }
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
@@ -151,11 +157,15 @@ __device__ inline void skin_item(const EnvView &e, const float *__restrict__ pos
         atomicOr(e.guard, (int)GUARD_MARKER_RANGE);
         p[ax] = (p[ax] >= 2.0f) ? nn - 3.5f : 2.0f;
       }
-      e.X[ax * n + k] = p[ax];
-      e.U[ax * n + k] = v[ax];
+      X[ax * n + k] = p[ax];
+      U[ax * n + k] = v[ax];
     }
     const int bs[3] = {stencil_base(p[0]), stencil_base(p[1]), stencil_base(p[2])};
-    e.mbase[k] = make_short4((short)bs[0], (short)bs[1], (short)bs[2], 0);
+    gmem<short> *mb = (gmem<short> *)e.mbase + 4 * (size_t)k;
+    mb[0] = (short)bs[0];
+    mb[1] = (short)bs[1];
+    mb[2] = (short)bs[2];
+    mb[3] = 0;
     int tx[4], ty[4], tz[4];
     bool fx[4], fy[4], fz[4];
     axis_node_tiles(bs[0], e.g.nx, e.g.xper, tx, fx);
@@ -167,7 +177,7 @@ __device__ inline void skin_item(const EnvView &e, const float *__restrict__ pos
       for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int l = 0; l < 4; ++l)
-          if (fz[i] && fy[j] && fx[l]) e.tile_flag[tx[l] + e.g.tnx * (ty[j] + e.g.tny * tz[i])] = 1;
+          if (fz[i] && fy[j] && fx[l]) tile_flag[tx[l] + e.g.tnx * (ty[j] + e.g.tny * tz[i])] = 1;
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
       if (bs[ax] < 0 || bs[ax] + 3 >= dims[ax]) {  // wrapping stencil: whole axis
@@ -187,8 +197,13 @@ __device__ inline void skin_item(const EnvView &e, const float *__restrict__ pos
       hi[ax] = max(hi[ax], shfl_xor_i(hi[ax], o));
     }
   }
-  if ((tid & 63) == 0 && k < n)
-    e.chunk_box[k >> 6] = make_int4(lo[0] | (hi[0] << 16), lo[1] | (hi[1] << 16), lo[2] | (hi[2] << 16), 0);
+  if ((tid & 63) == 0 && k < n) {
+    gmem<int> *cb = (gmem<int> *)e.chunk_box + 4 * (size_t)(k >> 6);
+    cb[0] = lo[0] | (hi[0] << 16);
+    cb[1] = lo[1] | (hi[1] << 16);
+    cb[2] = lo[2] | (hi[2] << 16);
+    cb[3] = 0;
+  }
 }
 
 __device__ __host__ inline int skin_items(int n) { return (n + WG - 1) / WG; }
