@@ -8,10 +8,10 @@ acceleration a(n) = 1e-5 sin(2 pi n / 400), velocity inlet / zero-gradient
 outlet. One step = skinning, tile binning, interpolation, direct forcing,
 spreading, the fused collide-stream with the frame force and open faces, and
 the body wrench (the whole path), all through the C interface. The headline
-step runs skinning and binning in launches of their own and the rest in one
-launch (k_step_overlap): 48 workgroups take the immersed-boundary chain while
-the others stream the collide; the "sequential" form runs every phase in its
-own launch (k_collide alone).
+step is one launch (k_step_overlap): 48 workgroups take the immersed-boundary
+chain (macros, interpolation, forcing, spreading, then the next step's
+skinning and tile binning) while the others stream the collide; the
+"sequential" form runs every phase in its own launch (k_collide alone).
 
 Prints one JSON line: MLUPS (lattice updates per second / 1e6, every node
 counted), the main launch's achieved bandwidth (the collide's 216 B per cell
@@ -513,7 +513,8 @@ def main():
                      "avg_launch_ms": round(main_run["collide_avg_ms"], 5)},
         "step_hbm_frac": round(main_run["mlups"] * 1e6 * BYTES_PER_CELL[args.storage] / (HBM_PEAK_GBS * 1e9), 4),
         "ib_workgroups": nib,
-        # launches before the main one: every immersed-boundary phase (nib = 0), or skinning and tile binning
+        # launches before the main one per step: every immersed-boundary phase (nib = 0); with the chain beside
+        # the collide, only the first step's skinning and tile binning, over all timed steps
         "pre_launch_ms_per_step": round(main_run["ib_avg_ms"], 5),
         "device_status": main_run["status"],
         "forms": forms,

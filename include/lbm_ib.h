@@ -167,10 +167,9 @@ typedef struct {
   double trt_lambda;         /* TRT: (tau - 1/2)(tau- - 1/2) > 0; unused by BGK */
   int32_t wall_mode;         /* LBM_WALL_*; 0 = no-slip */
   int32_t layout;            /* LBM_LAYOUT_*; 0 = automatic */
-  int32_t ib_workgroups;     /* direct forcing: > 0 runs the immersed-boundary phases after the tile
-                                binning in that many workgroups beside the collide, in one launch with it;
-                                0 or -1 runs them before the collide in launches of their own (see
-                                lbm_ib_step) */
+  int32_t ib_workgroups;     /* direct forcing: > 0 runs the immersed-boundary phases in that many
+                                workgroups beside the collide, one launch per step (see lbm_ib_step);
+                                0 or -1 runs them before the collide in launches of their own */
 } lbm_params;
 
 /* [host] Frame of one step (Eq. (3)). acc = linear acceleration of the frame
@@ -287,11 +286,13 @@ lbm_status lbm_macros(lbm_ctx *c, const lbm_frame *frame, float *rho, float *u);
  * Markers leaving the allowed region, and unstable states, are detected on the
  * device and reported by lbm_check.
  * Scheduling (lbm_params.ib_workgroups > 0): with direct forcing and a body
- * present, the band macros, interpolation and spreading can run in the same
- * launch as the collide (the collide blocks whose cells lie in active tiles
- * wait for them), so the collide's streaming overlaps them; by default they
- * run in launches of their own before it. The results are the same bits
- * either way. */
+ * present, each step is one launch: ib_workgroups workgroups run the band
+ * macros, interpolation and spreading, then skin and bin the next step's
+ * markers, while the others run the collide (the collide blocks whose cells
+ * lie in active tiles wait for the spreading), so the collide's streaming
+ * overlaps them; the first step's skinning and binning run in launches of
+ * their own. By default every phase runs in a launch of its own before the
+ * collide. The results are the same bits either way. */
 lbm_status lbm_ib_step(lbm_ctx *c, const lbm_markers *m, const float *poses, const lbm_frame *frames,
                        int32_t nsteps, float *wrench);
 

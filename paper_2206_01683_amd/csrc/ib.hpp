@@ -94,8 +94,11 @@ __device__ inline bool box_hits(int packed, int t) { return t >= (packed & 0xFFF
 // (dR_b xrest + dt_b). Periodic axes: X wrapped into [0, n). Open x: markers
 // must satisfy 2 <= X < nx - 3 so the stencil stays on nodes 1 .. nx-2; others
 // raise the range guard and are clamped so that every access stays in bounds.
-// Item 0 also clears the active-tile counter of this step.
-__device__ inline void skin_item(const EnvView &e, const float *__restrict__ pose, int item, int tid) {
+// Item 0 also clears the active-tile counter of this step. (Always inlined:
+// called as a function, its call would hold the persistent kernel's registers
+// across it and push that kernel past its budget.)
+__device__ __attribute__((always_inline)) inline void skin_item(const EnvView &e, const float *__restrict__ pose,
+                                                                int item, int tid) {
   const int k = item * WG + tid;
   const int n = e.n;
   if (k == 0) {
@@ -211,16 +214,20 @@ __device__ __host__ inline int skin_items(int n) { return (n + WG - 1) / WG; }
 // ---------------------------------------------------------- active tiles --
 // Tiles 512*item .. 512*item+511: slots in workgroup order from one atomic per
 // workgroup. Slot numbering only decides storage locations, never results.
-// Clears the flags for the next step.
-__device__ inline void active_item(const EnvView &e, int item, int tid) {
+// Clears the flags for the next step. slots: the tile map to write (null:
+// e.tile_slot). reset_sched: item 0 also clears the overlapped step's counts
+// (not when the overlapped step itself bins the next step's tiles).
+__device__ inline void active_item(const EnvView &e, int item, int tid, bool reset_sched = true,
+                                   int *slots = nullptr) {
   __shared__ int s_w[WG / 64];
   __shared__ int s_base;
   const int lane = tid & 63, wv = tid >> 6;
   const int t = item * WG + tid;
-  if (item == 0 && tid == 0 && e.sched != nullptr) {
+  if (item == 0 && tid == 0 && e.sched != nullptr && reset_sched) {
     e.sched[SCHED_ARRIVE] = 0u;
     e.sched[SCHED_DONE] = 0u;
   }
+  int *tile_slot = slots != nullptr ? slots : e.tile_slot;
   int f = 0;
   if (t < e.ntiles) {
     f = e.tile_flag[t] != 0;
@@ -240,10 +247,10 @@ __device__ inline void active_item(const EnvView &e, int item, int tid) {
   pre += __popcll(bal & ((1ull << lane) - 1ull));
   if (t < e.ntiles) {
     if (f && pre < e.cap) {
-      e.tile_slot[t] = pre;
+      tile_slot[t] = pre;
       e.active[pre] = t;
     } else {
-      e.tile_slot[t] = -1;
+      tile_slot[t] = -1;
       if (f) atomicOr(e.guard, (int)GUARD_CAPACITY);
     }
   }

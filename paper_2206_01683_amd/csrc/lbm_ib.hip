@@ -32,7 +32,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Layout {
   size_t sched;             // scheduling words of the overlapped step
   int tnx, tny, tnz, ntiles, cap, maxm;
-  size_t guard, counters, tile_flag, tile_slot, active, mbase, chunk_box, partials, macro, gbuf, rec, mstate;
+  size_t guard, counters, tile_flag, tile_slot, tile_slot2, active, mbase, chunk_box, partials, macro, gbuf, rec, mstate;
   size_t gbar, adjfix, mbar, pbar, facebuf;
   size_t gcg, cg, cgpart;  // implicit velocity correction only
   size_t nrm;              // slip walls only
@@ -115,6 +115,7 @@ Layout layout(const lbm_params *p) {
   L.sched = take(sizeof(unsigned) * SCHED_WORDS);
   L.tile_flag = take(sizeof(int) * L.ntiles);
   L.tile_slot = take(sizeof(int) * L.ntiles);
+  L.tile_slot2 = take(sizeof(int) * L.ntiles);  // the one-launch step's second tile map
   L.active = take(sizeof(int) * L.cap);
   L.mbase = take(sizeof(short4) * (size_t)L.maxm);
   L.chunk_box = take(sizeof(int4) * (size_t)((L.maxm + 63) / 64 + 8));
@@ -161,9 +162,12 @@ struct lbm_ctx {
   bool slots_dirty;
   bool is_static;  // created by lbm_init_static: workspace in `scratch`, not freed by lbm_destroy
   int bx, by;
-  // measurement hook: 3 events per timed step (start, after IB, after collide)
+  // measurement hook: up to 3 events per timed step (start, after IB, after
+  // collide); prof_chained[s]: step s of a one-launch run records only its
+  // end, and starts at the previous step's end (no IB before its launch)
   bool prof;
   std::vector<hipEvent_t> ev;
+  std::vector<unsigned char> prof_chained;
   int prof_used;
 };
 
@@ -341,44 +345,52 @@ lbm_status launch_collide(lbm_ctx *c, const EnvView &e, const FrameF &fr, bool r
 
 template <class S, bool TRT>
 void step_overlap_kernels(const EnvView &e, const FrameF &fr, int cur, int grid, int nib, int passes, float *wrench,
-                          hipStream_t s, bool xper, bool rot, bool yz) {
+                          const float *next_pose, int *next_slots, unsigned target, hipStream_t s, bool xper, bool rot,
+                          bool yz) {
+#define LBM_STEP_OVERLAP(XP, RT, YZ_)                                                                           \
+  k_step_overlap<S, XP, RT, YZ_, TRT><<<grid, WG, 0, s>>>(e, fr, cur, nib, passes, wrench, next_pose, next_slots, \
+                                                         target)
   if (yz) {  // open y or z faces
     if (xper && rot)
-      k_step_overlap<S, true, true, true, TRT><<<grid, WG, 0, s>>>(e, fr, cur, nib, passes, wrench);
+      LBM_STEP_OVERLAP(true, true, true);
     else if (xper)
-      k_step_overlap<S, true, false, true, TRT><<<grid, WG, 0, s>>>(e, fr, cur, nib, passes, wrench);
+      LBM_STEP_OVERLAP(true, false, true);
     else if (rot)
-      k_step_overlap<S, false, true, true, TRT><<<grid, WG, 0, s>>>(e, fr, cur, nib, passes, wrench);
+      LBM_STEP_OVERLAP(false, true, true);
     else
-      k_step_overlap<S, false, false, true, TRT><<<grid, WG, 0, s>>>(e, fr, cur, nib, passes, wrench);
+      LBM_STEP_OVERLAP(false, false, true);
   } else if (xper && rot) {
-    k_step_overlap<S, true, true, false, TRT><<<grid, WG, 0, s>>>(e, fr, cur, nib, passes, wrench);
+    LBM_STEP_OVERLAP(true, true, false);
   } else if (xper) {
-    k_step_overlap<S, true, false, false, TRT><<<grid, WG, 0, s>>>(e, fr, cur, nib, passes, wrench);
+    LBM_STEP_OVERLAP(true, false, false);
   } else if (rot) {
-    k_step_overlap<S, false, true, false, TRT><<<grid, WG, 0, s>>>(e, fr, cur, nib, passes, wrench);
+    LBM_STEP_OVERLAP(false, true, false);
   } else {
-    k_step_overlap<S, false, false, false, TRT><<<grid, WG, 0, s>>>(e, fr, cur, nib, passes, wrench);
+    LBM_STEP_OVERLAP(false, false, false);
   }
+#undef LBM_STEP_OVERLAP
 }
 
-// Whether the immersed-boundary chain runs beside the collide this step: on
-// request only (ib_workgroups > 0 chain workgroups, direct forcing). Under the
-// collide's load the chain's dependent accesses slow several-fold, so the band
-// blocks often end up waiting for it. Measured on the 384x192x192 fish: 8, 16,
-// 32, 64, 128 and 256 chain workgroups gave a 1251, 857, 664, 549, 553 and
-// 577 us launch, against 50 + 522 us for the chain's own launches followed by
-// the collide; the launch then moves 5.5 TB/s where the collide alone moves
-// 5.9. With 2-byte storage (367 against 314 us per step), four forcing passes,
-// or lattices small for their markers (the 150x50x100 two-fish domain, the
-// 128x64x64 fin: 1.5-2x slower) it loses.
+// Whether the immersed-boundary chain runs beside the collide, one launch per
+// step: on request only (ib_workgroups > 0 chain workgroups, direct forcing).
+// Under the collide's load the chain's dependent accesses slow several-fold,
+// so it pays only where the collide is long enough to hide it. On the
+// 384x192x192 fish at F32 with 32-64 chain workgroups a step takes 0.553 ms
+// against 0.583 ms in separate launches (one box; 96 and more take slots
+// from the collide, 16 and fewer leave the band blocks waiting); with 2-byte
+// storage (the collide takes 257 us), four forcing passes, or lattices small
+// for their markers (the 150x50x100 two-fish domain, the 128x64x64 fin) it
+// loses.
 bool overlap_chain(const lbm_ctx *c) { return c->p.ib_scheme == LBM_IB_DIRECT && c->p.ib_workgroups > 0; }
 
-// The band macros, interpolation and spreading beside the collide, in one
-// launch (k_step_overlap); the collide blocks take 512 cells each (the
-// context's 2-D shape if it has 512 cells, else 512 consecutive cells).
+// The band macros, interpolation and spreading beside the collide, and the
+// next step's skinning and binning (next_pose != null) into next_slots, in one
+// launch (k_step_overlap) with e0.tile_slot this step's tile map; the collide
+// blocks take 512 cells each (the context's 2-D shape if it has 512 cells,
+// else 512 consecutive cells).
 template <class S>
-lbm_status launch_step_overlap(lbm_ctx *c, const EnvView &e0, const FrameF &fr, bool rot, float *wrench) {
+lbm_status launch_step_overlap(lbm_ctx *c, const EnvView &e0, const FrameF &fr, bool rot, float *wrench,
+                               const float *next_pose, int *next_slots, unsigned target) {
   EnvView e = e0;
   if (!(c->by > 0 && c->bx * c->by == WG)) {
     e.bx = WG;
@@ -390,9 +402,11 @@ lbm_status launch_step_overlap(lbm_ctx *c, const EnvView &e0, const FrameF &fr, 
   const int grid = nib + e.nblocks;
   const bool yz = !(e.g.yper && e.g.zper), xper = e.g.xper != 0;
   if (c->p.collision == LBM_COLLIDE_TRT)
-    step_overlap_kernels<S, true>(e, fr, c->cur, grid, nib, c->p.mdf_iters, wrench, c->stream, xper, rot, yz);
+    step_overlap_kernels<S, true>(e, fr, c->cur, grid, nib, c->p.mdf_iters, wrench, next_pose, next_slots, target,
+                                  c->stream, xper, rot, yz);
   else
-    step_overlap_kernels<S, false>(e, fr, c->cur, grid, nib, c->p.mdf_iters, wrench, c->stream, xper, rot, yz);
+    step_overlap_kernels<S, false>(e, fr, c->cur, grid, nib, c->p.mdf_iters, wrench, next_pose, next_slots, target,
+                                   c->stream, xper, rot, yz);
   return launched();
 }
 
@@ -456,6 +470,13 @@ void prof_mark(lbm_ctx *c, int which) {
   if (c->prof && c->prof_used < kProfSteps) (void)hipEventRecord(c->ev[3 * c->prof_used + which], c->stream);
 }
 
+// Ends a timed step. chained: only its end event was recorded (see prof_chained).
+void prof_step(lbm_ctx *c, bool chained) {
+  if (!c->prof || c->prof_used >= kProfSteps) return;
+  c->prof_chained[c->prof_used] = chained ? 1 : 0;
+  c->prof_used++;
+}
+
 template <class S>
 lbm_status step_one(lbm_ctx *c, const lbm_markers *m, const float *pose, const lbm_frame *frame, float *wrench) {
   const FrameF fr = frame_f(frame);
@@ -469,16 +490,6 @@ lbm_status step_one(lbm_ctx *c, const lbm_markers *m, const float *pose, const l
     k_active<<<(e.ntiles + WG - 1) / WG, WG, 0, c->stream>>>(e);
     if ((st = launched()) != LBM_OK) return st;
     c->slots_dirty = true;
-    if (overlap_chain(c)) {
-      // the rest of the chain beside the collide, in one launch
-      prof_mark(c, 1);
-      if ((st = launch_step_overlap<S>(c, e, fr, rot, wrench)) != LBM_OK) return st;
-      prof_mark(c, 2);
-      if (c->prof && c->prof_used < kProfSteps) c->prof_used++;
-      c->cur ^= 1;
-      c->steps += 1;
-      return LBM_OK;
-    }
     if ((st = launch_macro<S>(c, e, fr, rot)) != LBM_OK) return st;
     const int passes = c->p.mdf_iters;
     if (c->p.ib_scheme == LBM_IB_IMPLICIT) {
@@ -500,13 +511,55 @@ lbm_status step_one(lbm_ctx *c, const lbm_markers *m, const float *pose, const l
   prof_mark(c, 1);
   if ((st = launch_collide<S>(c, e, fr, rot)) != LBM_OK) return st;
   prof_mark(c, 2);
-  if (c->prof && c->prof_used < kProfSteps) c->prof_used++;
+  prof_step(c, false);
   if (!e.ib && wrench) {
     k_fill_int<<<1, 64, 0, c->stream>>>(reinterpret_cast<int *>(wrench), 0, 8);
     if ((st = launched()) != LBM_OK) return st;
   }
   c->cur ^= 1;
   c->steps += 1;
+  return LBM_OK;
+}
+
+// nsteps steps with the immersed-boundary chain beside the collide
+// (overlap_chain): the first step's skinning and binning in launches of their
+// own, then one launch per step, each skinning and binning the next step. The
+// tile maps alternate between steps, starting so that the last step uses the
+// context's own map (L.tile_slot), which the other paths read.
+template <class S>
+lbm_status step_fused(lbm_ctx *c, const lbm_markers *m, const float *poses, const lbm_frame *frames, int nsteps,
+                      float *wrench) {
+  if (nsteps == 0) return LBM_OK;
+  EnvView e = env_view(c, m);
+  int *maps[2] = {wsp<int>(c, c->L.tile_slot), wsp<int>(c, c->L.tile_slot2)};
+  const int first = (nsteps - 1) & 1;
+  const size_t pose_stride = (size_t)m->nbones * 24;
+  lbm_status st;
+  prof_mark(c, 0);
+  e.tile_slot = maps[first];
+  k_skin_mark<<<skin_items(e.n), WG, 0, c->stream>>>(e, poses);
+  if ((st = launched()) != LBM_OK) return st;
+  k_active<<<(e.ntiles + WG - 1) / WG, WG, 0, c->stream>>>(e);  // also zeroes the done count
+  if ((st = launched()) != LBM_OK) return st;
+  c->slots_dirty = true;
+  const unsigned nib = (unsigned)c->p.ib_workgroups;
+  for (int s = 0; s < nsteps; ++s) {
+    // one event per step after the first (each launch directly follows the
+    // previous one, whose end event is its start): event packets between
+    // launches cost the step a few microseconds each
+    const bool chained = s > 0 && c->prof_used > 0;
+    if (!chained) prof_mark(c, 1);
+    e.tile_slot = maps[(first + s) & 1];
+    const float *next_pose = s + 1 < nsteps ? poses + (size_t)(s + 1) * pose_stride : nullptr;
+    st = launch_step_overlap<S>(c, e, frame_f(&frames[s]), rotating(&frames[s]),
+                                wrench ? wrench + (size_t)s * 8 : nullptr, next_pose, maps[(first + s + 1) & 1],
+                                nib * (unsigned)(s + 1));
+    if (st != LBM_OK) return st;
+    prof_mark(c, 2);
+    prof_step(c, chained);
+    c->cur ^= 1;
+    c->steps += 1;
+  }
   return LBM_OK;
 }
 
@@ -596,6 +649,7 @@ lbm_status setup_ctx(lbm_ctx *c, const lbm_params *p, void *f_a, void *f_b, char
   // every workspace field that must start cleared, by kernels (no memset
   // nodes, so the sequence can sit in a captured graph)
   k_fill_int<<<256, 256, 0, c->stream>>>(wsp<int>(c, c->L.tile_flag), 0, c->L.ntiles);
+  k_fill_int<<<256, 256, 0, c->stream>>>(wsp<int>(c, c->L.tile_slot2), -1, c->L.ntiles);
   k_fill_int<<<256, 256, 0, c->stream>>>(wsp<int>(c, c->L.tile_slot), -1, c->L.ntiles);
   k_fill_int<<<1, 64, 0, c->stream>>>(wsp<int>(c, c->L.guard), 0, 16);
   k_fill_int<<<1, 64, 0, c->stream>>>(wsp<int>(c, c->L.counters), 0, 16);
@@ -718,6 +772,7 @@ lbm_status lbm_ib_step(lbm_ctx *c, const lbm_markers *m, const float *poses, con
   if (ib && c->p.wall_mode == LBM_WALL_SLIP && c->p.ib_scheme == LBM_IB_IMPLICIT)
     for (int s = 0; s < nsteps; ++s)
       if (rotating(&frames[s])) return LBM_ERR_UNSUPPORTED;
+  if (ib && overlap_chain(c)) return LBM_BY_STORAGE(c, step_fused, m, poses, frames, nsteps, wrench);
   for (int s = 0; s < nsteps; ++s) {
     const float *pose = ib ? poses + (size_t)s * m->nbones * 24 : nullptr;
     float *w = wrench ? wrench + (size_t)s * 8 : nullptr;
@@ -1163,6 +1218,7 @@ lbm_status lbm_profile_enable(lbm_ctx *c, int enable) {
   if (!c) return LBM_ERR_ARG;
   if (enable && c->ev.empty()) {
     c->ev.resize(3 * kProfSteps);
+    c->prof_chained.assign(kProfSteps, 0);
     for (auto &e : c->ev)
       if (hipEventCreate(&e) != hipSuccess) return LBM_ERR_DEVICE;
   }
@@ -1176,8 +1232,12 @@ lbm_status lbm_profile_collect(lbm_ctx *c, double *ib_ms, double *collide_ms, in
   double a = 0.0, b = 0.0;
   for (int s = 0; s < c->prof_used; ++s) {
     float t0 = 0.f, t1 = 0.f;
-    if (hipEventElapsedTime(&t0, c->ev[3 * s], c->ev[3 * s + 1]) != hipSuccess) return LBM_ERR_DEVICE;
-    if (hipEventElapsedTime(&t1, c->ev[3 * s + 1], c->ev[3 * s + 2]) != hipSuccess) return LBM_ERR_DEVICE;
+    if (c->prof_chained[s]) {  // from the previous step's end
+      if (hipEventElapsedTime(&t1, c->ev[3 * (s - 1) + 2], c->ev[3 * s + 2]) != hipSuccess) return LBM_ERR_DEVICE;
+    } else {
+      if (hipEventElapsedTime(&t0, c->ev[3 * s], c->ev[3 * s + 1]) != hipSuccess) return LBM_ERR_DEVICE;
+      if (hipEventElapsedTime(&t1, c->ev[3 * s + 1], c->ev[3 * s + 2]) != hipSuccess) return LBM_ERR_DEVICE;
+    }
     a += t0;
     b += t1;
   }
