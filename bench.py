@@ -8,10 +8,11 @@ acceleration a(n) = 1e-5 sin(2 pi n / 400), velocity inlet / zero-gradient
 outlet. One step = skinning, tile binning, interpolation, direct forcing,
 spreading, the fused collide-stream with the frame force and open faces, and
 the body wrench (the whole path), all through the C interface. The headline
-step is one launch (k_step_overlap): 48 workgroups take the immersed-boundary
-chain (macros, interpolation, forcing, spreading, then the next step's
-skinning and tile binning) while the others stream the collide; the
-"sequential" form runs every phase in its own launch (k_collide alone).
+step is one launch (k_step_overlap): 32 workgroups take the immersed-boundary
+chain (macros, interpolation, forcing, spreading, the collide of the cells
+that carry an immersed force, then the next step's skinning and tile binning)
+while the others stream the collide of every other cell; the "sequential"
+form runs every phase in its own launch (k_collide alone).
 
 Prints one JSON line: MLUPS (lattice updates per second / 1e6, every node
 counted), the main launch's achieved bandwidth (the collide's 216 B per cell
@@ -33,10 +34,10 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL = {"f32": 216, "f16": 108, "bf16": 108}
 METRIC = "MLUPS and % of HBM roofline per GPU; adjoint/forward time ratio"
-# The headline step runs the immersed-boundary phases after the tile binning
-# in this many workgroups beside the collide, in one launch (k_step_overlap);
-# 0 runs them in launches of their own before the collide (k_collide).
-HEADLINE_IB_WORKGROUPS = 48
+# The headline step runs the immersed-boundary phases in this many workgroups
+# beside the collide, in one launch (k_step_overlap); 0 runs them in launches
+# of their own before the collide (k_collide).
+HEADLINE_IB_WORKGROUPS = 32
 _CSRC = os.path.join(ROOT, "paper_2206_01683_amd", "csrc")
 # the sources each main kernel is compiled from, and its committed HBM traffic summary
 KERNEL_SOURCES = {

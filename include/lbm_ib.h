@@ -287,12 +287,13 @@ lbm_status lbm_macros(lbm_ctx *c, const lbm_frame *frame, float *rho, float *u);
  * device and reported by lbm_check.
  * Scheduling (lbm_params.ib_workgroups > 0): with direct forcing and a body
  * present, each step is one launch: ib_workgroups workgroups run the band
- * macros, interpolation and spreading, then skin and bin the next step's
- * markers, while the others run the collide (the collide blocks whose cells
- * lie in active tiles wait for the spreading), so the collide's streaming
- * overlaps them; the first step's skinning and binning run in launches of
- * their own. By default every phase runs in a launch of its own before the
- * collide. The results are the same bits either way. */
+ * macros, interpolation and spreading, collide the cells whose source node
+ * lies in an active tile (the only cells with an immersed force), then skin
+ * and bin the next step's markers, while the others collide every other cell
+ * without waiting, so the collide's streaming overlaps them; the first
+ * step's skinning and binning run in launches of their own. By default every
+ * phase runs in a launch of its own before the collide. The results are the
+ * same bits either way. */
 lbm_status lbm_ib_step(lbm_ctx *c, const lbm_markers *m, const float *poses, const lbm_frame *frames,
                        int32_t nsteps, float *wrench);
 

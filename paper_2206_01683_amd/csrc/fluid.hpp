@@ -108,19 +108,28 @@ struct CellAt {
   int x, y, z, xs, ys, zs;
 };
 
-// First half of collide_cell: locate the cell and pull its 27 populations
-// (for a boundary lane, those of its inward neighbour). False past the
-// lattice. YZ: y or z may have open faces (otherwise both are periodic).
+// Cell (x, y, z) and, on an open face, the inward neighbour whose
+// populations it reads (its source node). YZ: y or z may have open faces
+// (otherwise both are periodic).
+template <bool XPER, bool YZ = false>
+__device__ inline CellAt cell_at(const GridArgs &g, int x, int y, int z) {
+  CellAt c;
+  c.x = x;
+  c.y = y;
+  c.z = z;
+  c.xs = XPER ? x : (x == 0 ? 1 : (x == g.nx - 1 ? g.nx - 2 : x));
+  c.ys = (YZ && !g.yper) ? (y == 0 ? 1 : (y == g.ny - 1 ? g.ny - 2 : y)) : y;
+  c.zs = (YZ && !g.zper) ? (z == 0 ? 1 : (z == g.nz - 1 ? g.nz - 2 : z)) : z;
+  return c;
+}
+
+// The 27 populations pulled to the source node of c.
 template <class S, bool XPER, bool YZ = false>
-__device__ inline bool collide_load(const EnvView &e, int cur, int lb, int tx, int ty, CellAt &c, float f[Q]) {
+__device__ inline void collide_pull(const EnvView &e, int cur, const CellAt &c, float f[Q]) {
   using T = typename S::T;
   const gmem<T> *__restrict__ src = (const gmem<T> *)e.f[cur];
-  int x, y, z;
-  if (!cell_of(e, lb, tx, ty, x, y, z)) return false;
   const GridArgs &g = e.g;
-  const bool lo_face = !XPER && x == 0;
-  const bool hi_face = !XPER && x == g.nx - 1;
-  const int xs = lo_face ? 1 : (hi_face ? g.nx - 2 : x);
+  const int xs = c.xs, y = c.y, z = c.z;
   int xm, xp;
   if (XPER) {
     xm = xs == 0 ? g.nx - 1 : xs - 1;
@@ -131,7 +140,7 @@ __device__ inline bool collide_load(const EnvView &e, int cur, int lb, int tx, i
   }
   int ys = y, zs = z, ym, yp, zm, zp;
   if (YZ && !g.yper) {
-    ys = y == 0 ? 1 : (y == g.ny - 1 ? g.ny - 2 : y);
+    ys = c.ys;
     ym = ys - 1;
     yp = ys + 1;
   } else {
@@ -139,7 +148,7 @@ __device__ inline bool collide_load(const EnvView &e, int cur, int lb, int tx, i
     yp = y == g.ny - 1 ? 0 : y + 1;
   }
   if (YZ && !g.zper) {
-    zs = z == 0 ? 1 : (z == g.nz - 1 ? g.nz - 2 : z);
+    zs = c.zs;
     zm = zs - 1;
     zp = zs + 1;
   } else {
@@ -147,12 +156,17 @@ __device__ inline bool collide_load(const EnvView &e, int cur, int lb, int tx, i
     zp = z == g.nz - 1 ? 0 : z + 1;
   }
   pull27<S, true>(src, g, xm, xs, xp, ym, ys, yp, zm, zs, zp, f);
-  c.x = x;
-  c.y = y;
-  c.z = z;
-  c.xs = xs;
-  c.ys = ys;
-  c.zs = zs;
+}
+
+// First half of collide_cell: locate the cell and pull its 27 populations
+// (for a boundary lane, those of its inward neighbour). False past the
+// lattice.
+template <class S, bool XPER, bool YZ = false>
+__device__ inline bool collide_load(const EnvView &e, int cur, int lb, int tx, int ty, CellAt &c, float f[Q]) {
+  int x, y, z;
+  if (!cell_of(e, lb, tx, ty, x, y, z)) return false;
+  c = cell_at<XPER, YZ>(e.g, x, y, z);
+  collide_pull<S, XPER, YZ>(e, cur, c, f);
   return true;
 }
 

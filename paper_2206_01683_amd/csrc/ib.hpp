@@ -35,10 +35,9 @@ constexpr int kInterpMk = WG / 16;   // markers per interpolation (and CG apply)
 
 // Scheduling words of the overlapped step (step.hpp), each on its own
 // 128-byte line, in the workspace (EnvView::sched): the chain's barrier
-// arrival count and generation, and the count of chain workgroups that have
-// finished. active_item clears the arrival and done counts each step.
+// arrival count and generation. k_active clears the arrival count.
 constexpr int kSchedLine = 32;
-enum : int { SCHED_ARRIVE = 0, SCHED_GEN = kSchedLine, SCHED_DONE = 2 * kSchedLine, SCHED_WORDS = 3 * kSchedLine };
+enum : int { SCHED_ARRIVE = 0, SCHED_GEN = kSchedLine, SCHED_WORDS = 2 * kSchedLine };
 
 __device__ inline int stencil_base(float X) { return (int)floorf(X) - 1; }
 
@@ -215,8 +214,8 @@ __device__ __host__ inline int skin_items(int n) { return (n + WG - 1) / WG; }
 // Tiles 512*item .. 512*item+511: slots in workgroup order from one atomic per
 // workgroup. Slot numbering only decides storage locations, never results.
 // Clears the flags for the next step. slots: the tile map to write (null:
-// e.tile_slot). reset_sched: item 0 also clears the overlapped step's counts
-// (not when the overlapped step itself bins the next step's tiles).
+// e.tile_slot). reset_sched: item 0 also clears the overlapped step's barrier
+// count (not when the overlapped step itself bins the next step's tiles).
 __device__ inline void active_item(const EnvView &e, int item, int tid, bool reset_sched = true,
                                    int *slots = nullptr) {
   __shared__ int s_w[WG / 64];
@@ -225,7 +224,6 @@ __device__ inline void active_item(const EnvView &e, int item, int tid, bool res
   const int t = item * WG + tid;
   if (item == 0 && tid == 0 && e.sched != nullptr && reset_sched) {
     e.sched[SCHED_ARRIVE] = 0u;
-    e.sched[SCHED_DONE] = 0u;
   }
   int *tile_slot = slots != nullptr ? slots : e.tile_slot;
   int f = 0;

@@ -345,11 +345,10 @@ lbm_status launch_collide(lbm_ctx *c, const EnvView &e, const FrameF &fr, bool r
 
 template <class S, bool TRT>
 void step_overlap_kernels(const EnvView &e, const FrameF &fr, int cur, int grid, int nib, int passes, float *wrench,
-                          const float *next_pose, int *next_slots, unsigned target, hipStream_t s, bool xper, bool rot,
+                          const float *next_pose, int *next_slots, hipStream_t s, bool xper, bool rot,
                           bool yz) {
 #define LBM_STEP_OVERLAP(XP, RT, YZ_)                                                                           \
-  k_step_overlap<S, XP, RT, YZ_, TRT><<<grid, WG, 0, s>>>(e, fr, cur, nib, passes, wrench, next_pose, next_slots, \
-                                                         target)
+  k_step_overlap<S, XP, RT, YZ_, TRT><<<grid, WG, 0, s>>>(e, fr, cur, nib, passes, wrench, next_pose, next_slots)
   if (yz) {  // open y or z faces
     if (xper && rot)
       LBM_STEP_OVERLAP(true, true, true);
@@ -375,12 +374,12 @@ void step_overlap_kernels(const EnvView &e, const FrameF &fr, int cur, int grid,
 // step: on request only (ib_workgroups > 0 chain workgroups, direct forcing).
 // Under the collide's load the chain's dependent accesses slow several-fold,
 // so it pays only where the collide is long enough to hide it. On the
-// 384x192x192 fish at F32 with 32-64 chain workgroups a step takes 0.553 ms
-// against 0.583 ms in separate launches (one box; 96 and more take slots
-// from the collide, 16 and fewer leave the band blocks waiting); with 2-byte
-// storage (the collide takes 257 us), four forcing passes, or lattices small
-// for their markers (the 150x50x100 two-fish domain, the 128x64x64 fin) it
-// loses.
+// 384x192x192 fish at F32 with 24-40 chain workgroups a step takes
+// 0.532-0.543 ms against 0.570 ms in separate launches (fewer than 20 and the
+// chain outlasts the collide; more take slots from it); with 2-byte storage
+// (the collide takes 255 us, the chain longer), four forcing passes, or
+// lattices small for their markers (the 150x50x100 two-fish domain, the
+// 128x64x64 fin) it loses.
 bool overlap_chain(const lbm_ctx *c) { return c->p.ib_scheme == LBM_IB_DIRECT && c->p.ib_workgroups > 0; }
 
 // The band macros, interpolation and spreading beside the collide, and the
@@ -390,7 +389,7 @@ bool overlap_chain(const lbm_ctx *c) { return c->p.ib_scheme == LBM_IB_DIRECT &&
 // else 512 consecutive cells).
 template <class S>
 lbm_status launch_step_overlap(lbm_ctx *c, const EnvView &e0, const FrameF &fr, bool rot, float *wrench,
-                               const float *next_pose, int *next_slots, unsigned target) {
+                               const float *next_pose, int *next_slots) {
   EnvView e = e0;
   if (!(c->by > 0 && c->bx * c->by == WG)) {
     e.bx = WG;
@@ -402,11 +401,11 @@ lbm_status launch_step_overlap(lbm_ctx *c, const EnvView &e0, const FrameF &fr, 
   const int grid = nib + e.nblocks;
   const bool yz = !(e.g.yper && e.g.zper), xper = e.g.xper != 0;
   if (c->p.collision == LBM_COLLIDE_TRT)
-    step_overlap_kernels<S, true>(e, fr, c->cur, grid, nib, c->p.mdf_iters, wrench, next_pose, next_slots, target,
-                                  c->stream, xper, rot, yz);
+    step_overlap_kernels<S, true>(e, fr, c->cur, grid, nib, c->p.mdf_iters, wrench, next_pose, next_slots, c->stream,
+                                  xper, rot, yz);
   else
-    step_overlap_kernels<S, false>(e, fr, c->cur, grid, nib, c->p.mdf_iters, wrench, next_pose, next_slots, target,
-                                   c->stream, xper, rot, yz);
+    step_overlap_kernels<S, false>(e, fr, c->cur, grid, nib, c->p.mdf_iters, wrench, next_pose, next_slots, c->stream,
+                                   xper, rot, yz);
   return launched();
 }
 
@@ -539,10 +538,9 @@ lbm_status step_fused(lbm_ctx *c, const lbm_markers *m, const float *poses, cons
   e.tile_slot = maps[first];
   k_skin_mark<<<skin_items(e.n), WG, 0, c->stream>>>(e, poses);
   if ((st = launched()) != LBM_OK) return st;
-  k_active<<<(e.ntiles + WG - 1) / WG, WG, 0, c->stream>>>(e);  // also zeroes the done count
+  k_active<<<(e.ntiles + WG - 1) / WG, WG, 0, c->stream>>>(e);  // also zeroes the barrier count
   if ((st = launched()) != LBM_OK) return st;
   c->slots_dirty = true;
-  const unsigned nib = (unsigned)c->p.ib_workgroups;
   for (int s = 0; s < nsteps; ++s) {
     // one event per step after the first (each launch directly follows the
     // previous one, whose end event is its start): event packets between
@@ -552,8 +550,7 @@ lbm_status step_fused(lbm_ctx *c, const lbm_markers *m, const float *poses, cons
     e.tile_slot = maps[(first + s) & 1];
     const float *next_pose = s + 1 < nsteps ? poses + (size_t)(s + 1) * pose_stride : nullptr;
     st = launch_step_overlap<S>(c, e, frame_f(&frames[s]), rotating(&frames[s]),
-                                wrench ? wrench + (size_t)s * 8 : nullptr, next_pose, maps[(first + s + 1) & 1],
-                                nib * (unsigned)(s + 1));
+                                wrench ? wrench + (size_t)s * 8 : nullptr, next_pose, maps[(first + s + 1) & 1]);
     if (st != LBM_OK) return st;
     prof_mark(c, 2);
     prof_step(c, chained);

@@ -5,26 +5,24 @@
 //
 // Workgroups [0, nib) run the immersed-boundary chain, with barriers among
 // themselves: band macros, interpolation with direct forcing (and its
-// multi-direct passes), spreading into the fixed-point force; then they count
-// themselves done, skin the next step's markers and bin its tiles into the
-// other tile map (the two maps alternate between steps). The other workgroups
-// are the collide blocks, in launch order as in k_collide. A block none of
-// whose cells lies in an active tile needs no immersed force and collides at
-// once; a block with band cells waits for the chain first. Active tiles fill
-// a fraction of a percent of the lattice, so nearly all of the collide's
-// 216 B per cell stream while the latency-bound chain runs, instead of after
-// it, and a step is one launch.
+// multi-direct passes), spreading into the fixed-point force, then the
+// collide of the band cells (those whose source node lies in an active tile,
+// the only cells with an immersed force); then they skin the next step's
+// markers and bin its tiles into the other tile map (the two maps alternate
+// between steps). The other workgroups are the collide blocks, in launch
+// order as in k_collide: each collides its cells outside the band at once and
+// leaves the band cells to the chain. Active tiles fill a fraction of a
+// percent of the lattice, so nearly all of the collide's 216 B per cell
+// stream while the latency-bound chain runs, no collide block waits for it,
+// and a step is one launch.
 //
 // Correctness does not depend on timing: the chain reads the source buffer
-// (cur) and writes its own band arrays, the next step's marker data and the
-// other tile map, none of which the collide reads; the collide writes the
-// other population buffer, reads this step's tile map (complete before the
-// launch) and reads the immersed force only after the done count, by an
-// acquire. The done count grows over the launches of a call (the host passes
-// each launch's target). The chain's workgroups are the lowest-numbered, so
-// they are resident before any collide block can wait for them. The
-// arithmetic is the same inline code as the separate kernels', so results
-// agree bit for bit.
+// (cur) and writes its own band arrays, the band cells of the other buffer,
+// the next step's marker data and the other tile map; the collide blocks read
+// the source buffer and this step's tile map (complete before the launch) and
+// write the other buffer outside the band. The two never touch the same
+// words. The arithmetic is the same inline code as the separate kernels', so
+// results agree bit for bit.
 #pragma once
 
 #include "ib.hpp"
@@ -53,10 +51,36 @@ __device__ inline void chain_sync(unsigned *sched, int nib) {
 
 // The chain of workgroup blk of nib: the same phases and order as the
 // separate launches of step_one (macro; per pass: spread of the force so far
-// after the first, interpolation; final spread with the wrench sum), then,
-// when next_pose is not null, the next step's skinning and binning into
-// next_slots.
-template <class S, bool ROT>
+// after the first, interpolation; final spread with the wrench sum), the
+// collide of the band cells, then, when next_pose is not null, the next
+// step's skinning and binning into next_slots.
+// The band cells of active slot `slot`: the cells whose source node lies in
+// its tile, that is the tile's own cells, and on an open face whose last tile
+// is one node wide (a dimension of 8k + 1) also the face nodes beyond it
+// (the source node of a face node is its inward neighbour). A cell of the
+// box whose source lies in another tile is that tile's.
+template <class S, bool XPER, bool ROT, bool YZ, bool TRT>
+__device__ inline void band_collide_item(const EnvView &e, const FrameF &fr, int cur, int slot, int tid) {
+  const GridArgs &g = e.g;
+  const int t = ((const gmem<int> *)e.active)[slot];
+  const int tx = t % g.tnx, rest = t / g.tnx, ty = rest % g.tny, tz = rest / g.tny;
+  const int x0 = tx << 3, y0 = ty << 3, z0 = tz << 3;
+  int x1 = min(x0 + 8, g.nx), y1 = min(y0 + 8, g.ny), z1 = min(z0 + 8, g.nz);
+  if (!XPER && x1 == g.nx - 1) ++x1;
+  if (YZ && !g.yper && y1 == g.ny - 1) ++y1;
+  if (YZ && !g.zper && z1 == g.nz - 1) ++z1;
+  const int ex = x1 - x0, ey = y1 - y0, cnt = ex * ey * (z1 - z0);
+  for (int lc = tid; lc < cnt; lc += WG) {
+    const int x = x0 + lc % ex, r = lc / ex, y = y0 + r % ey, z = z0 + r / ey;
+    const CellAt c = cell_at<XPER, YZ>(g, x, y, z);
+    if (((c.xs >> 3) != tx) | ((c.ys >> 3) != ty) | ((c.zs >> 3) != tz)) continue;
+    float f[Q];
+    collide_pull<S, XPER, YZ>(e, cur, c, f);
+    collide_finish<S, XPER, ROT, YZ, TRT>(e, fr, cur, c, f);
+  }
+}
+
+template <class S, bool XPER, bool ROT, bool YZ, bool TRT>
 __device__ inline void ib_chain(const EnvView &e, const FrameF &fr, int cur, int blk, int nib, int passes,
                                 float *wrench, const float *next_pose, int *next_slots, int tid) {
   unsigned *sched = e.sched;
@@ -80,11 +104,11 @@ __device__ inline void ib_chain(const EnvView &e, const FrameF &fr, int cur, int
   }
   if (blk == 0 && wrench != nullptr) wrench_sum(e.partials, ninterp, wrench, tid);
   for (int item = blk; item < nspread; item += nib) spread_item(e, item, tid);
-  __syncthreads();
-  if (tid == 0) __hip_atomic_fetch_add(&sched[SCHED_DONE], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  chain_sync(sched, nib);
+  for (int slot = blk; slot < na; slot += nib) band_collide_item<S, XPER, ROT, YZ, TRT>(e, fr, cur, slot, tid);
   if (next_pose == nullptr) return;
-  // the next step, once every chain workgroup has finished spreading (which
-  // reads this step's marker data, chunk boxes and active list)
+  // the next step, once every chain workgroup has finished with this step's
+  // marker data, chunk boxes, active list and tile map
   chain_sync(sched, nib);
   for (int item = blk; item < skin_items(e.n); item += nib) skin_item(e, next_pose, item, tid);
   chain_sync(sched, nib);
@@ -93,38 +117,26 @@ __device__ inline void ib_chain(const EnvView &e, const FrameF &fr, int cur, int
 
 // Grid: nib + e.nblocks workgroups of WG threads; the collide shape of e is
 // linear (e.by == 0, e.bx == WG) or 2-D with e.bx * e.by == WG. e.tile_slot:
-// this step's tile map; done_target: the done count once this launch's chain
-// has finished its spreading.
+// this step's tile map.
 template <class S, bool XPER, bool ROT, bool YZ, bool TRT>
 __global__ void __launch_bounds__(WG) k_step_overlap(EnvView e, FrameF fr, int cur, int nib, int passes,
-                                                      float *wrench, const float *next_pose, int *next_slots,
-                                                      unsigned done_target) {
+                                                      float *wrench, const float *next_pose, int *next_slots) {
   const int tid = threadIdx.x;
   if ((int)blockIdx.x < nib) {
-    ib_chain<S, ROT>(e, fr, cur, blockIdx.x, nib, passes, wrench, next_pose, next_slots, tid);
+    ib_chain<S, XPER, ROT, YZ, TRT>(e, fr, cur, blockIdx.x, nib, passes, wrench, next_pose, next_slots, tid);
     return;
   }
   const int lb = (int)blockIdx.x - nib;
   if (lb >= e.nblocks) return;
   const int tx = e.by == 0 ? tid : tid % e.bx, ty = e.by == 0 ? 0 : tid / e.bx;
-  CellAt c;
+  int x, y, z;
+  if (!cell_of(e, lb, tx, ty, x, y, z)) return;
+  const CellAt c = cell_at<XPER, YZ>(e.g, x, y, z);
+  // a band cell (source node in an active tile) is the chain's
+  if (((const gmem<int> *)e.tile_slot)[(c.xs >> 3) + e.g.tnx * ((c.ys >> 3) + e.g.tny * (c.zs >> 3))] >= 0) return;
   float f[Q];
-  const bool have = collide_load<S, XPER, YZ>(e, cur, lb, tx, ty, c, f);
-  // a band cell reads the immersed force at its source node (xs, ys, zs)
-  int band = 0;
-  if (have) {
-    const int ys = YZ ? c.ys : c.y, zs = YZ ? c.zs : c.z;
-    band = e.tile_slot[(c.xs >> 3) + e.g.tnx * ((ys >> 3) + e.g.tny * (zs >> 3))] >= 0;
-  }
-  if (__syncthreads_or(band)) {
-    if (tid == 0) {
-      while (__hip_atomic_load(&e.sched[SCHED_DONE], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < done_target)
-        __builtin_amdgcn_s_sleep(2);
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    }
-    __syncthreads();
-  }
-  if (have) collide_finish<S, XPER, ROT, YZ, TRT>(e, fr, cur, c, f);
+  collide_pull<S, XPER, YZ>(e, cur, c, f);
+  collide_finish<S, XPER, ROT, YZ, TRT>(e, fr, cur, c, f);
 }
 
 }  // namespace lbmib

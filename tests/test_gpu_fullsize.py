@@ -15,12 +15,12 @@ from gpu_helpers import gpu_run, interior, oracle_run, random_state, rel_l2, say
 pytestmark = pytest.mark.gpu
 
 
-HEADLINE_IB_WORKGROUPS = 48  # bench.py's headline launch configuration
+HEADLINE_IB_WORKGROUPS = 32  # bench.py's headline launch configuration
 
 
 def test_full_size_fish_one_step():
     """Also the headline's launch configuration (the immersed-boundary chain
-    in 48 workgroups beside the collide, one launch): bit for bit the step
+    in 32 workgroups beside the collide, one launch): bit for bit the step
     with every phase in its own launch."""
     w = I.fish_workload(nsteps=1, start=123)
     say("full size: generating state")
@@ -55,6 +55,24 @@ def test_full_size_fish_one_step():
     np.testing.assert_allclose(U, ref["U"], atol=1e-6)
     np.testing.assert_allclose(F, ref["F"], atol=2e-5 * np.abs(ref["F"]).max())
     np.testing.assert_allclose(wr[0, :7], ref["wrench"][0, :7], atol=2e-4 * np.abs(ref["wrench"][0, :7]).max())
+
+
+def test_full_size_fish_three_fused_steps_match_separate_launches():
+    """Three steps in the headline's launch configuration, where each launch
+    also skins and bins the next step and collides the band cells: bit for
+    bit the same steps with every phase in its own launch."""
+    w = I.fish_workload(nsteps=3, start=123)
+    f0 = random_state(w, 13, du=0.02, noise=5e-5)
+    out = []
+    for nib in (0, HEADLINE_IB_WORKGROUPS):
+        say(f"full size: three steps, ib_workgroups {nib}")
+        sim, dm, wr = gpu_run(w, nsteps=3, f0=f0, ib_workgroups=nib)
+        assert sim.check() == 0
+        out.append((sim.read_populations().cpu().numpy(), dm.F.cpu().numpy(), wr))
+        del sim
+        torch.cuda.empty_cache()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
 
 
 @pytest.mark.parametrize("storage,bound", [("f16", 2.0 ** -11), ("bf16", 2.0 ** -8)])

@@ -4,8 +4,9 @@ configuration) against the same phases in launches of their own before the
 collide (ib_workgroups = 0 or -1):
 the arithmetic is the same inline code, so every result must agree bit for
 bit, for any number of chain workgroups, with multi-direct forcing passes,
-2-byte storage, TRT, open y/z faces, a rotating frame and a body across the
-periodic corner of a ragged lattice."""
+2-byte storage, TRT, open y/z faces, a rotating frame, a body across the
+periodic corner of a ragged lattice, and band cells on open faces beyond
+their source tile."""
 import numpy as np
 import pytest
 import torch
@@ -56,6 +57,22 @@ def _open_yz_rotating():
     return w
 
 
+def _hi_faces():
+    """Every face open, each dimension 8k + 1 (the last tile one node wide),
+    and a body whose stencils reach node n - 2 on each axis: the face nodes
+    n - 1 take their populations and force from the tile before theirs."""
+    nx, ny, nz = 41, 25, 17
+    u_in = np.array([0.03, 0.01, 0.0])
+    n = 6
+    w = I.Workload("hi-faces", nx, ny, nz, 0.6, I.BC_VELOCITY, I.BC_OUTFLOW, n,
+                   I.perturbed_velocity((nz, ny, nx), u_in, 1e-3, 5), I.fibonacci_sphere(400, 3.0, (34.4, 18.4, 10.4)),
+                   I.identity_poses(n), I.make_frames(n, origin=(34.4, 18.4, 10.4), u_lo=u_in, u_hi=u_in),
+                   np.array([-1.0, 0, 0]))
+    w.bc_y = (I.BC_VELOCITY, I.BC_OUTFLOW)
+    w.bc_z = (I.BC_VELOCITY, I.BC_OUTFLOW)
+    return w
+
+
 def _fin():
     return I.fin_workload(I.C5_BASE, nsteps=10, nx=48, ny=32, nz=32, length=16.0, n=600, head=(12.0, 16.0, 16.0))
 
@@ -68,6 +85,8 @@ CASES = {
     "sphere-2d-blocks": (lambda: I.sphere_workload(nsteps=6), 6, dict(block=(64, 8))),
     "ragged-37x21x13": (_ragged, 6, dict()),
     "open-yz-rotating": (_open_yz_rotating, 8, dict()),
+    "hi-faces-41x25x17": (_hi_faces, 6, dict()),
+    "hi-faces-f16-trt": (_hi_faces, 6, dict(storage="f16", collision=lbm.COLLIDE_TRT)),
     "fin-48x32x32": (_fin, 10, dict()),
 }
 
