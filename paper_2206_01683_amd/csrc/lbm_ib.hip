@@ -309,37 +309,56 @@ EnvView env_view(lbm_ctx *c, const lbm_markers *m) {
 
 // -------------------------------------------------------------- dispatch --
 template <class S, bool TRT>
-void collide_kernels(const EnvView &e, const FrameF &fr, int cur, int grid, dim3 blk, hipStream_t s, bool xper,
-                     bool rot, bool yz) {
+void collide_kernels(const EnvView &e, const FrameF &fr, int cur, int grid, dim3 blk, size_t lds, hipStream_t s,
+                     bool xper, bool rot, bool yz) {
   if (yz) {  // open y or z faces
     if (xper && rot)
-      k_collide<S, true, true, true, TRT><<<grid, blk, 0, s>>>(e, fr, cur);
+      k_collide<S, true, true, true, TRT><<<grid, blk, lds, s>>>(e, fr, cur);
     else if (xper)
-      k_collide<S, true, false, true, TRT><<<grid, blk, 0, s>>>(e, fr, cur);
+      k_collide<S, true, false, true, TRT><<<grid, blk, lds, s>>>(e, fr, cur);
     else if (rot)
-      k_collide<S, false, true, true, TRT><<<grid, blk, 0, s>>>(e, fr, cur);
+      k_collide<S, false, true, true, TRT><<<grid, blk, lds, s>>>(e, fr, cur);
     else
-      k_collide<S, false, false, true, TRT><<<grid, blk, 0, s>>>(e, fr, cur);
+      k_collide<S, false, false, true, TRT><<<grid, blk, lds, s>>>(e, fr, cur);
   } else if (xper && rot) {
-    k_collide<S, true, true, false, TRT><<<grid, blk, 0, s>>>(e, fr, cur);
+    k_collide<S, true, true, false, TRT><<<grid, blk, lds, s>>>(e, fr, cur);
   } else if (xper) {
-    k_collide<S, true, false, false, TRT><<<grid, blk, 0, s>>>(e, fr, cur);
+    k_collide<S, true, false, false, TRT><<<grid, blk, lds, s>>>(e, fr, cur);
   } else if (rot) {
-    k_collide<S, false, true, false, TRT><<<grid, blk, 0, s>>>(e, fr, cur);
+    k_collide<S, false, true, false, TRT><<<grid, blk, lds, s>>>(e, fr, cur);
   } else {
-    k_collide<S, false, false, false, TRT><<<grid, blk, 0, s>>>(e, fr, cur);
+    k_collide<S, false, false, false, TRT><<<grid, blk, lds, s>>>(e, fr, cur);
   }
+}
+
+// LDS a collide launch reserves (and never uses) so that about twelve waves,
+// three per SIMD, share a compute unit: each lane issues its 27 loads at
+// once, so few waves keep enough bytes in flight, and the F32 collide streams
+// faster so than at the eight waves per SIMD its registers allow (fish,
+// 384x192x192, 256-cell blocks: 508 us with three blocks per compute unit,
+// against 538 at four, 534 at two and 527-532 uncapped). The size sits
+// between the bounds for per_cu and per_cu + 1 blocks, in whole KiB. The
+// 2-byte forms move half the bytes per load and run best at full occupancy
+// (256 us, 258-260 us capped).
+template <class S>
+size_t collide_lds(dim3 blk) {
+  if (S::kind != StoreF32::kind) return 0;
+  constexpr int kLdsPerCu = 160 * 1024, kWavesPerCu = 12;
+  const int waves = (int)((blk.x * blk.y + 63) / 64);
+  const int per_cu = std::max(1, (kWavesPerCu + waves / 2) / waves);
+  return (size_t)(2 * kLdsPerCu / (2 * per_cu + 1)) & ~(size_t)1023;
 }
 
 template <class S>
 lbm_status launch_collide(lbm_ctx *c, const EnvView &e, const FrameF &fr, bool rot) {
   const int grid = e.nblocks;
   const dim3 blk = collide_block(c);
+  const size_t lds = collide_lds<S>(blk);
   const bool yz = !(e.g.yper && e.g.zper), xper = e.g.xper != 0;
   if (c->p.collision == LBM_COLLIDE_TRT)
-    collide_kernels<S, true>(e, fr, c->cur, grid, blk, c->stream, xper, rot, yz);
+    collide_kernels<S, true>(e, fr, c->cur, grid, blk, lds, c->stream, xper, rot, yz);
   else
-    collide_kernels<S, false>(e, fr, c->cur, grid, blk, c->stream, xper, rot, yz);
+    collide_kernels<S, false>(e, fr, c->cur, grid, blk, lds, c->stream, xper, rot, yz);
   return launched();
 }
 
