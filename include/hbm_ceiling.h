@@ -41,10 +41,13 @@ int hbm_read(const void *src, size_t bytes, float *sink, void *hip_stream);
  * lbm_ib.h: planes ps >= nx ny nz, rs = nx; rows ps = nx, rs = 27 nx), so each
  * buffer holds at least (nz ny - 1) rs + 26 ps + nx floats.
  * 256 consecutive cells of the x-fastest order per block, non-temporal
- * stores. -1 if a size is < 1 or the strides do not give every element its
- * own place. */
+ * stores. blocks_per_cu > 0 reserves unused LDS so that at most that many
+ * blocks share a compute unit (the cap the library's F32 collide runs
+ * under); 0 leaves occupancy to the registers. -1 if a size is < 1, the
+ * strides do not give every element its own place, or blocks_per_cu is
+ * outside 0..32. */
 int hbm_pull27(const float *src, float *dst, int32_t nx, int32_t ny, int32_t nz, int64_t ps, int64_t rs,
-               void *hip_stream);
+               int32_t blocks_per_cu, void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -74,15 +74,19 @@ int hbm_read(const void *src, size_t bytes, float *sink, void *hip_stream) {
 }
 
 int hbm_pull27(const float *src, float *dst, int32_t nx, int32_t ny, int32_t nz, int64_t ps, int64_t rs,
-               void *hip_stream) {
+               int32_t blocks_per_cu, void *hip_stream) {
   if (!src || !dst || src == dst || nx < 1 || ny < 1 || nz < 1 || ps < 1 || rs < 1) return -1;
+  if (blocks_per_cu < 0 || blocks_per_cu > 32) return -1;
   const uint64_t cells = (uint64_t)nx * ny * nz;
   const bool planes = rs == nx && (uint64_t)ps >= cells;
   const bool rows = ps == nx && rs == 27 * (int64_t)nx;
   if (!planes && !rows) return -1;
   const uint64_t blocks = (cells + 255) / 256;
   if (blocks > 0x7fffffffull) return -1;
-  k_pull27<<<(unsigned)blocks, 256, 0, static_cast<hipStream_t>(hip_stream)>>>(
+  // reserved, unused LDS: a size between the bounds for blocks_per_cu and
+  // blocks_per_cu + 1 blocks of a 160 KiB compute unit, in whole KiB
+  const size_t lds = blocks_per_cu > 0 ? (size_t)(2 * 160 * 1024 / (2 * blocks_per_cu + 1)) & ~(size_t)1023 : 0;
+  k_pull27<<<(unsigned)blocks, 256, lds, static_cast<hipStream_t>(hip_stream)>>>(
       src, dst, Dims{nx, ny, nz, (uint64_t)ps, (uint64_t)rs});
   return launched();
 }

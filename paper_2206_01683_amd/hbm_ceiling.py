@@ -33,7 +33,7 @@ def lib():
         L.hbm_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
         L.hbm_read.argtypes = [vp, ctypes.c_size_t, vp, vp]
         L.hbm_pull27.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
-                                 ctypes.c_int64, vp]
+                                 ctypes.c_int64, ctypes.c_int32, vp]
         for f in (L.hbm_copy, L.hbm_read, L.hbm_pull27):
             f.restype = ctypes.c_int
         _lib = L
@@ -77,8 +77,9 @@ def measure(nx: int = 384, ny: int = 192, nz: int = 192, reps: int = 20) -> dict
     out["copy"] = {"us": round(ms * 1e3, 2), "GBps": round(2 * nbytes / ms / 1e6, 1)}
     ms = _time(lambda: _ok(L.hbm_read(pa, nbytes, ps_, s), "hbm_read"), reps)
     out["read"] = {"us": round(ms * 1e3, 2), "GBps": round(nbytes / ms / 1e6, 1)}
-    for name, (ps, rs) in (("pull27_rows", (nx, 27 * nx)), ("pull27_planes", (plane, nx))):
-        ms = _time(lambda: _ok(L.hbm_pull27(pa, pb, nx, ny, nz, ps, rs, s), "hbm_pull27"), reps)
+    for name, (ps, rs, cap) in (("pull27_rows", (nx, 27 * nx, 0)), ("pull27_planes", (plane, nx, 0)),
+                                ("pull27_rows_3_blocks_per_cu", (nx, 27 * nx, 3))):
+        ms = _time(lambda: _ok(L.hbm_pull27(pa, pb, nx, ny, nz, ps, rs, cap, s), "hbm_pull27"), reps)
         out[name] = {"us": round(ms * 1e3, 2), "GBps": round(2 * nbytes / ms / 1e6, 1)}
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0.record()

@@ -218,10 +218,12 @@ def test_ceiling_library_exports_and_validates():
     assert C.hbm_copy(ctypes.c_void_p(4100), q, 160, None) == -1  # misaligned
     assert C.hbm_copy(None, q, 160, None) == -1
     assert C.hbm_read(p, 0, q, None) == -1
-    assert C.hbm_pull27(p, p, 8, 8, 8, 8, 216, None) == -1      # aliased
-    assert C.hbm_pull27(p, q, 8, 8, 8, 8, 64, None) == -1       # rows need rs = 27 nx
-    assert C.hbm_pull27(p, q, 8, 8, 8, 100, 8, None) == -1      # planes need ps >= cells
-    assert C.hbm_pull27(p, q, 0, 8, 8, 8, 216, None) == -1
+    assert C.hbm_pull27(p, p, 8, 8, 8, 8, 216, 0, None) == -1      # aliased
+    assert C.hbm_pull27(p, q, 8, 8, 8, 8, 64, 0, None) == -1       # rows need rs = 27 nx
+    assert C.hbm_pull27(p, q, 8, 8, 8, 100, 8, 0, None) == -1      # planes need ps >= cells
+    assert C.hbm_pull27(p, q, 0, 8, 8, 8, 216, 0, None) == -1
+    assert C.hbm_pull27(p, q, 8, 8, 8, 8, 216, -1, None) == -1     # blocks per compute unit
+    assert C.hbm_pull27(p, q, 8, 8, 8, 8, 216, 33, None) == -1
 
 
 def test_ib_workgroups_parameter_is_validated(L):
