@@ -123,6 +123,47 @@ def run_gpu(storage: str, steps: int, warmup: int, block=(0, 0), collision: int 
     return res
 
 
+def run_graph(storage: str, steps: int, warmup: int, block=(0, 0), ib_workgroups: int = 0):
+    """The headline step loop captured into one HIP graph (through torch):
+    `steps` steps per replay after an eager warm-up, then one warm-up replay
+    and one timed replay, wall clock between synchronizations. An even step
+    count keeps each replay on the same buffers."""
+    import numpy as np
+    import torch
+
+    from paper_2206_01683_amd import inputs as I
+    from paper_2206_01683_amd import lbm
+
+    steps += steps & 1
+    w = I.fish_workload(nsteps=warmup + steps)
+    sim = lbm.Simulation(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi, storage=storage, max_markers=w.markers.n,
+                         max_bones=w.markers.nbones, block=block, ib_workgroups=ib_workgroups)
+    dm = lbm.DeviceMarkers(w.markers)
+    poses = torch.as_tensor(np.ascontiguousarray(w.poses, np.float32), device="cuda")
+    wrench = torch.zeros((warmup + steps, 8), dtype=torch.float32, device="cuda")
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    sim.set_stream(side)
+    with torch.cuda.stream(side):
+        if warmup:
+            sim.step(w.frames[:warmup], dm, poses[:warmup], wrench[:warmup])
+    side.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        sim.step(w.frames[warmup:], dm, poses[warmup:], wrench[warmup:])
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.replay()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    status = sim.check()
+    del g, sim
+    torch.cuda.empty_cache()
+    return {"mlups": round(w.ncell * steps / wall / 1e6, 1), "ms_per_step": round(wall * 1e3 / steps, 4),
+            "steps_per_replay": steps, "status": status}
+
+
 BATCH_GROUPS = 2  # concurrent groups of the per-phase driver
 
 
@@ -399,10 +440,10 @@ def main():
     ap.add_argument("--storage", default="f32", choices=sorted(BYTES_PER_CELL))
     ap.add_argument("--cpu-steps", type=int, default=24, help="oracle sample length (0: skip)")
     ap.add_argument("--forms",
-                    default="sequential,ceiling,f16,bf16,trt,faces_frames,batched,adjoint,two_fish,free_swimmer,"
-                            "ib_schemes",
-                    help="comma-separated extra forms to measure: sequential, ceiling, f16, bf16, trt, faces_frames, "
-                         "batched, adjoint, two_fish, free_swimmer, ib_schemes")
+                    default="graph,sequential,ceiling,f16,bf16,trt,faces_frames,batched,adjoint,two_fish,"
+                            "free_swimmer,ib_schemes",
+                    help="comma-separated extra forms to measure: graph, sequential, ceiling, f16, bf16, trt, "
+                         "faces_frames, batched, adjoint, two_fish, free_swimmer, ib_schemes")
     ap.add_argument("--no-forms", action="store_true", help="measure no extra form")
     ap.add_argument("--block", type=int, nargs=2, default=(0, 0))
     ap.add_argument("--batch-envs", type=int, default=64, help="batched form: environments (0: skip)")
@@ -423,6 +464,9 @@ def main():
     w = main_run["workload"]
     want = set() if args.no_forms else {f.strip() for f in args.forms.split(",") if f.strip()}
     forms = {}
+    if "graph" in want:
+        # the headline step loop as one captured graph, replayed
+        forms["graph"] = run_graph(args.storage, args.steps, args.warmup, tuple(args.block), ib_workgroups=nib)
     seq = main_run if nib == 0 else None
     if nib > 0 and want & {"sequential", "ceiling"}:
         # the same step with the immersed-boundary phases in launches of their own before the collide: the

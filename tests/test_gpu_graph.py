@@ -13,17 +13,20 @@ from gpu_helpers import gpu_sim, say
 pytestmark = pytest.mark.gpu
 
 
-def test_captured_steps_replay_like_eager_steps():
+@pytest.mark.parametrize("ib_workgroups", [0, 32])
+def test_captured_steps_replay_like_eager_steps(ib_workgroups):
+    """ib_workgroups = 32: one launch per step with the chain beside the
+    collide, whose barrier counts carry over from replay to replay."""
     w = I.sphere_workload(nsteps=2)  # fixed sphere, fixed frames: the same two steps repeat
     dm = lbm.DeviceMarkers(w.markers)
     poses = torch.as_tensor(np.ascontiguousarray(w.poses[:2], np.float32), device="cuda")
-    eager = gpu_sim(w)
+    eager = gpu_sim(w, ib_workgroups=ib_workgroups)
     wr_e = torch.zeros((2, 8), device="cuda")
     for _ in range(5):
         eager.step(w.frames[:2], dm, poses, wr_e)
     torch.cuda.synchronize()
 
-    sim = gpu_sim(w)
+    sim = gpu_sim(w, ib_workgroups=ib_workgroups)
     torch.cuda.synchronize()
     side = torch.cuda.Stream()
     sim.set_stream(side)
