@@ -107,9 +107,11 @@ __device__ inline void ib_chain(const EnvView &e, const FrameF &fr, int cur, int
   chain_sync(sched, nib);
   for (int slot = blk; slot < na; slot += nib) band_collide_item<S, XPER, ROT, YZ, TRT>(e, fr, cur, slot, tid);
   if (next_pose == nullptr) return;
-  // the next step, once every chain workgroup has finished with this step's
-  // marker data, chunk boxes, active list and tile map
-  chain_sync(sched, nib);
+  // The next step's skinning needs no barrier after the band collide: it
+  // writes the marker data, chunk boxes and tile flags, which only the
+  // phases before the last barrier read, and the active count (na was read
+  // at the start). The binning rewrites the active list the band collide
+  // reads, so it waits for every workgroup.
   for (int item = blk; item < skin_items(e.n); item += nib) skin_item(e, next_pose, item, tid);
   chain_sync(sched, nib);
   for (int item = blk; item < active_items(e); item += nib) active_item(e, item, tid, false, next_slots);
