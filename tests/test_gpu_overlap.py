@@ -18,16 +18,17 @@ from gpu_helpers import say
 pytestmark = pytest.mark.gpu
 
 
-def _run(w, nsteps, ib_workgroups, storage="f32", collision=0, mdf=None, block=(0, 0)):
+def _run(w, nsteps, ib_workgroups, storage="f32", collision=0, mdf=None, block=(0, 0), max_active_tiles=0,
+         status=lbm.OK):
     sim = lbm.Simulation(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi, storage=storage, max_markers=w.markers.n,
                          max_bones=w.markers.nbones, u0=w.u0.astype(np.float32), bc_y=w.bc_y, bc_z=w.bc_z,
                          collision=collision, mdf_iters=mdf or w.mdf_iters, ib_workgroups=ib_workgroups,
-                         block=block)
+                         block=block, max_active_tiles=max_active_tiles)
     dm = lbm.DeviceMarkers(w.markers)
     poses = torch.as_tensor(np.ascontiguousarray(w.poses[:nsteps], np.float32), device="cuda")
     wrench = torch.zeros((nsteps, 8), dtype=torch.float32, device="cuda")
     sim.step(w.frames[:nsteps], dm, poses, wrench)
-    assert sim.check() == lbm.OK
+    assert sim.check() == status
     rho, u = sim.macros(w.frames[nsteps - 1])
     out = dict(f=sim.read_populations().cpu().numpy(), rho=rho.cpu().numpy(), u=u.cpu().numpy(),
                F=dm.F.cpu().numpy(), X=dm.X.cpu().numpy(), wrench=wrench.cpu().numpy())
@@ -88,6 +89,11 @@ CASES = {
     "hi-faces-41x25x17": (_hi_faces, 6, dict()),
     "hi-faces-f16-trt": (_hi_faces, 6, dict(storage="f16", collision=lbm.COLLIDE_TRT)),
     "fin-48x32x32": (_fin, 10, dict()),
+    # more active tiles than the capacity: the tiles past it get no slot, no
+    # force and no band cells, the same way in either schedule, and the
+    # capacity guard is raised
+    "sphere-capacity-8-tiles": (lambda: I.sphere_workload(nsteps=4), 4,
+                                dict(max_active_tiles=8, status=lbm.ERR_CAPACITY)),
 }
 
 
