@@ -168,7 +168,8 @@ typedef struct {
   int32_t wall_mode;         /* LBM_WALL_*; 0 = no-slip */
   int32_t layout;            /* LBM_LAYOUT_*; 0 = automatic */
   int32_t ib_workgroups;     /* direct forcing: > 0 runs the immersed-boundary phases in that many
-                                workgroups beside the collide, one launch per step (see lbm_ib_step);
+                                workgroups beside the collide, one launch per step (see lbm_ib_step),
+                                held to what the device runs at once (about two per compute unit);
                                 0 or -1 runs them before the collide in launches of their own */
 } lbm_params;
 
@@ -462,7 +463,11 @@ lbm_status lbm_swimmer_advance(const lbm_swimmer *s, lbm_swimmer_state *st, cons
 lbm_status lbm_body_forces(lbm_ctx *c, const lbm_markers *m, const double *center, float *out);
 
 /* Synchronize the stream and report device-side guards: LBM_ERR_UNSTABLE,
- * LBM_ERR_MARKER_RANGE, LBM_ERR_CAPACITY, or LBM_OK. Clears the guards. */
+ * LBM_ERR_MARKER_RANGE, LBM_ERR_CAPACITY, LBM_ERR_ARG (a bone index out of
+ * range), LBM_ERR_DEVICE (a barrier of the one-launch step waited past its
+ * limit, which only a device shared with work that never yields can cause;
+ * the steps since the last check are then void), or LBM_OK. Clears the
+ * guards. */
 lbm_status lbm_check(lbm_ctx *c);
 
 /* Measurement hook. enable != 0: every later step brackets its two phases

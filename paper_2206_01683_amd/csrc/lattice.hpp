@@ -155,6 +155,6 @@ __device__ inline int wrap_idx(int j, int n) {
 }
 
 // Device guard bits
-enum : int { GUARD_UNSTABLE = 1, GUARD_MARKER_RANGE = 2, GUARD_CAPACITY = 4, GUARD_BONE = 8 };
+enum : int { GUARD_UNSTABLE = 1, GUARD_MARKER_RANGE = 2, GUARD_CAPACITY = 4, GUARD_BONE = 8, GUARD_SCHEDULE = 16 };
 
 }  // namespace lbmib

@@ -362,12 +362,33 @@ lbm_status launch_collide(lbm_ctx *c, const EnvView &e, const FrameF &fr, bool r
   return launched();
 }
 
+// Workgroups of `kernel` (WG threads) that the current device holds at once,
+// or 0 if the runtime cannot tell.
+template <class K>
+int coresident_workgroups(K kernel) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                              hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, WG, 0) != hipSuccess)
+    return 0;
+  return per_cu * cus;
+}
+
+// The chain's barrier needs all its workgroups resident together: nib is
+// held to what the device holds at once of this kernel (queried once per
+// form; the results do not depend on nib).
 template <class S, bool TRT>
-void step_overlap_kernels(const EnvView &e, const FrameF &fr, int cur, int grid, int nib, int passes, float *wrench,
-                          const float *next_pose, int *next_slots, hipStream_t s, bool xper, bool rot,
-                          bool yz) {
+lbm_status step_overlap_kernels(const EnvView &e, const FrameF &fr, int cur, int nib, int passes, float *wrench,
+                                const float *next_pose, int *next_slots, hipStream_t s, bool xper, bool rot,
+                                bool yz) {
 #define LBM_STEP_OVERLAP(XP, RT, YZ_)                                                                           \
-  k_step_overlap<S, XP, RT, YZ_, TRT><<<grid, WG, 0, s>>>(e, fr, cur, nib, passes, wrench, next_pose, next_slots)
+  do {                                                                                                          \
+    static const int cap = coresident_workgroups(k_step_overlap<S, XP, RT, YZ_, TRT>);                          \
+    const int n = std::min(nib, cap);                                                                           \
+    if (n < 1) return LBM_ERR_DEVICE;                                                                           \
+    k_step_overlap<S, XP, RT, YZ_, TRT><<<n + e.nblocks, WG, 0, s>>>(e, fr, cur, n, passes, wrench, next_pose,  \
+                                                                    next_slots);                                \
+  } while (0)
   if (yz) {  // open y or z faces
     if (xper && rot)
       LBM_STEP_OVERLAP(true, true, true);
@@ -387,6 +408,7 @@ void step_overlap_kernels(const EnvView &e, const FrameF &fr, int cur, int grid,
     LBM_STEP_OVERLAP(false, false, false);
   }
 #undef LBM_STEP_OVERLAP
+  return launched();
 }
 
 // Whether the immersed-boundary chain runs beside the collide, one launch per
@@ -417,15 +439,12 @@ lbm_status launch_step_overlap(lbm_ctx *c, const EnvView &e0, const FrameF &fr, 
     e.nblocks = (int)(((size_t)c->p.nx * c->p.ny * c->p.nz + WG - 1) / WG);
   }
   const int nib = c->p.ib_workgroups;
-  const int grid = nib + e.nblocks;
   const bool yz = !(e.g.yper && e.g.zper), xper = e.g.xper != 0;
   if (c->p.collision == LBM_COLLIDE_TRT)
-    step_overlap_kernels<S, true>(e, fr, c->cur, grid, nib, c->p.mdf_iters, wrench, next_pose, next_slots, c->stream,
-                                  xper, rot, yz);
-  else
-    step_overlap_kernels<S, false>(e, fr, c->cur, grid, nib, c->p.mdf_iters, wrench, next_pose, next_slots, c->stream,
-                                   xper, rot, yz);
-  return launched();
+    return step_overlap_kernels<S, true>(e, fr, c->cur, nib, c->p.mdf_iters, wrench, next_pose, next_slots,
+                                         c->stream, xper, rot, yz);
+  return step_overlap_kernels<S, false>(e, fr, c->cur, nib, c->p.mdf_iters, wrench, next_pose, next_slots, c->stream,
+                                        xper, rot, yz);
 }
 
 template <class S>
@@ -1227,6 +1246,7 @@ lbm_status lbm_check(lbm_ctx *c) {
   if (guard & GUARD_MARKER_RANGE) return LBM_ERR_MARKER_RANGE;
   if (guard & GUARD_CAPACITY) return LBM_ERR_CAPACITY;
   if (guard & GUARD_BONE) return LBM_ERR_ARG;
+  if (guard & GUARD_SCHEDULE) return LBM_ERR_DEVICE;
   return LBM_OK;
 }
 

@@ -29,10 +29,17 @@
 
 namespace lbmib {
 
+// Polls of a chain barrier before a waiter gives up (well over a second):
+// the host keeps the chain within what the device holds at once, so only a
+// device shared with work that never yields its slots can reach it.
+constexpr long kChainSpins = 1L << 22;
+
 // Barrier among the nib chain workgroups (co-resident: dispatched first).
 // Arrival is an acquire-release read-modify-write at device scope; waiters
-// poll with relaxed loads and acquire once.
-__device__ inline void chain_sync(unsigned *sched, int nib) {
+// poll with relaxed loads and acquire once. A waiter that gives up raises
+// the schedule guard and goes on (its results are then void), so that the
+// launch always ends.
+__device__ inline void chain_sync(unsigned *sched, int nib, int *guard) {
   __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned gen = __hip_atomic_load(&sched[SCHED_GEN], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -41,8 +48,14 @@ __device__ inline void chain_sync(unsigned *sched, int nib) {
       __hip_atomic_store(&sched[SCHED_ARRIVE], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_fetch_add(&sched[SCHED_GEN], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
-      while (__hip_atomic_load(&sched[SCHED_GEN], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen)
+      long spins = 0;
+      while (__hip_atomic_load(&sched[SCHED_GEN], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
         __builtin_amdgcn_s_sleep(2);
+        if (++spins > kChainSpins) {
+          atomicOr(guard, (int)GUARD_SCHEDULE);
+          break;
+        }
+      }
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
   }
@@ -86,12 +99,12 @@ __device__ inline void ib_chain(const EnvView &e, const FrameF &fr, int cur, int
   unsigned *sched = e.sched;
   const int na = n_active_of(e);
   for (int slot = blk; slot < na; slot += nib) macro_item<S, ROT>(e, fr, cur, slot, tid);
-  chain_sync(sched, nib);
+  chain_sync(sched, nib, e.guard);
   const int nspread = na * kSpreadSplit, ninterp = interp_items(e.n);
   for (int it = 0; it < passes; ++it) {
     if (it > 0) {
       for (int item = blk; item < nspread; item += nib) spread_item(e, item, tid);
-      chain_sync(sched, nib);
+      chain_sync(sched, nib, e.guard);
     }
     float *part = (wrench != nullptr && it == passes - 1) ? e.partials : nullptr;
     for (int item = blk; item < ninterp; item += nib) {
@@ -100,11 +113,11 @@ __device__ inline void ib_chain(const EnvView &e, const FrameF &fr, int cur, int
       else
         interp_item<ROT, false>(e, fr, item, tid, part);
     }
-    chain_sync(sched, nib);
+    chain_sync(sched, nib, e.guard);
   }
   if (blk == 0 && wrench != nullptr) wrench_sum(e.partials, ninterp, wrench, tid);
   for (int item = blk; item < nspread; item += nib) spread_item(e, item, tid);
-  chain_sync(sched, nib);
+  chain_sync(sched, nib, e.guard);
   for (int slot = blk; slot < na; slot += nib) band_collide_item<S, XPER, ROT, YZ, TRT>(e, fr, cur, slot, tid);
   if (next_pose == nullptr) return;
   // The next step's skinning needs no barrier after the band collide: it
@@ -113,7 +126,7 @@ __device__ inline void ib_chain(const EnvView &e, const FrameF &fr, int cur, int
   // at the start). The binning rewrites the active list the band collide
   // reads, so it waits for every workgroup.
   for (int item = blk; item < skin_items(e.n); item += nib) skin_item(e, next_pose, item, tid);
-  chain_sync(sched, nib);
+  chain_sync(sched, nib, e.guard);
   for (int item = blk; item < active_items(e); item += nib) active_item(e, item, tid, false, next_slots);
 }
 

@@ -108,3 +108,15 @@ def test_overlapped_step_matches_separate_launches_bitwise(case):
         for k in ref:
             assert np.array_equal(ref[k], got[k]), (nib, k)
     assert np.abs(ref["wrench"][:, 0]).max() > 0
+
+
+def test_chain_beyond_what_the_device_holds_is_held_to_it():
+    """ib_workgroups = 1024, more workgroups than the device runs at once:
+    the library holds the chain to what the device holds, so its barriers
+    complete, and every result is the separate launches' bits."""
+    w = I.sphere_workload(nsteps=4)
+    say("overlap: 1024 chain workgroups requested")
+    ref = _run(w, 4, -1)
+    got = _run(w, 4, 1024)
+    for k in ref:
+        assert np.array_equal(ref[k], got[k]), k
