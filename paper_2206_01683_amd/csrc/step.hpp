@@ -62,11 +62,6 @@ __device__ inline void chain_sync(unsigned *sched, int nib, int *guard) {
   __syncthreads();
 }
 
-// The chain of workgroup blk of nib: the same phases and order as the
-// separate launches of step_one (macro; per pass: spread of the force so far
-// after the first, interpolation; final spread with the wrench sum), the
-// collide of the band cells, then, when next_pose is not null, the next
-// step's skinning and binning into next_slots.
 // The band cells of active slot `slot`: the cells whose source node lies in
 // its tile, that is the tile's own cells, and on an open face whose last tile
 // is one node wide (a dimension of 8k + 1) also the face nodes beyond it
@@ -93,6 +88,11 @@ __device__ inline void band_collide_item(const EnvView &e, const FrameF &fr, int
   }
 }
 
+// The chain of workgroup blk of nib: the same phases and order as the
+// separate launches of step_one (macro; per pass: spread of the force so far
+// after the first, interpolation; final spread with the wrench sum), the
+// collide of the band cells, then, when next_pose is not null, the next
+// step's skinning and binning into next_slots.
 template <class S, bool XPER, bool ROT, bool YZ, bool TRT>
 __device__ inline void ib_chain(const EnvView &e, const FrameF &fr, int cur, int blk, int nib, int passes,
                                 float *wrench, const float *next_pose, int *next_slots, int tid) {
