@@ -19,11 +19,11 @@ pytestmark = pytest.mark.gpu
 
 
 def _run(w, nsteps, ib_workgroups, storage="f32", collision=0, mdf=None, block=(0, 0), max_active_tiles=0,
-         status=lbm.OK):
+         status=lbm.OK, ib_scheme=lbm.IB_DIRECT):
     sim = lbm.Simulation(w.nx, w.ny, w.nz, w.tau, w.bc_lo, w.bc_hi, storage=storage, max_markers=w.markers.n,
                          max_bones=w.markers.nbones, u0=w.u0.astype(np.float32), bc_y=w.bc_y, bc_z=w.bc_z,
                          collision=collision, mdf_iters=mdf or w.mdf_iters, ib_workgroups=ib_workgroups,
-                         block=block, max_active_tiles=max_active_tiles)
+                         block=block, max_active_tiles=max_active_tiles, ib_scheme=ib_scheme)
     dm = lbm.DeviceMarkers(w.markers)
     poses = torch.as_tensor(np.ascontiguousarray(w.poses[:nsteps], np.float32), device="cuda")
     wrench = torch.zeros((nsteps, 8), dtype=torch.float32, device="cuda")
@@ -94,6 +94,9 @@ CASES = {
     # capacity guard is raised
     "sphere-capacity-8-tiles": (lambda: I.sphere_workload(nsteps=4), 4,
                                 dict(max_active_tiles=8, status=lbm.ERR_CAPACITY)),
+    # the implicit correction keeps its phases in launches of their own
+    # whatever ib_workgroups asks
+    "sphere-implicit-2": (lambda: I.sphere_workload(nsteps=4), 4, dict(ib_scheme=lbm.IB_IMPLICIT, mdf=2)),
 }
 
 
